@@ -1,0 +1,373 @@
+"""CPU oracle of the colocation suite.
+
+TEST INFRASTRUCTURE ONLY: plain, slow and obviously correct.  Only the tests,
+``__graft_entry__.smoke()`` and the benchmark's CPU-baseline leg may import
+this package.  It shares no code with the device library
+(``paper_2501_16909_amd``) and never imports it.
+
+Bit-level steps (two-rounding triad, FMA chains, pointer walk, quantizers,
+exact summation) live in ``coloc_oracle.c`` and are loaded with ctypes;
+dense products use numpy in FP64 as a library step.  Each function names
+the passage of the paper (Elvinger et al., SoCC'25) or the workload
+definition it follows.
+
+Parity status per function (pins are in tests/test_oracle_pins.py):
+  triad_f32, bitsum_u32, sum_f32_exact .......... pinned
+  fma_chain_f32 / valu_outputs .................. pinned
+  chase_u32, is_single_cycle .................... pinned
+  cache_wg_expected, lds_wave_pass_sum .......... pinned
+  f32_to_bf16, f32_to_e4m3, quantize_fp8 ........ pinned
+  gemm_f64, gemv_f64, mfma_tile_expected ........ pinned
+  slowdown, pct_of_peak ......................... pinned (paper Table 1 values)
+  admit / simulate_admission .................... pinned
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "coloc_oracle.c")
+_SO = os.path.join(_HERE, "libcoloc_oracle.so")
+_LIB = None
+
+_F32P = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
+_U32P = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+_U64P = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
+_U16P = np.ctypeslib.ndpointer(dtype=np.uint16, flags="C_CONTIGUOUS")
+_U8P = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+
+
+def build_oracle(force: bool = False) -> str:
+    """Compile coloc_oracle.c with gcc (no fused multiply-add contraction)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
+                               "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        lib = ctypes.CDLL(build_oracle())
+        lib.or_triad_f32.argtypes = [_F32P, _F32P, _F32P, ctypes.c_uint64]
+        lib.or_bitsum_u32.argtypes = [_U32P, ctypes.c_uint64]
+        lib.or_bitsum_u32.restype = ctypes.c_uint64
+        lib.or_sum_u32_mod32.argtypes = [_U32P, ctypes.c_uint64, ctypes.c_uint64]
+        lib.or_sum_u32_mod32.restype = ctypes.c_uint32
+        lib.or_sum_f32_exact.argtypes = [_F32P, ctypes.c_uint64]
+        lib.or_sum_f32_exact.restype = ctypes.c_double
+        lib.or_fma_chain_f32.argtypes = [_F32P, ctypes.c_uint64, ctypes.c_float, ctypes.c_float,
+                                         ctypes.c_uint64, _F32P]
+        lib.or_chase_u32.argtypes = [_U32P, ctypes.c_uint64, _U64P, ctypes.c_uint64,
+                                     ctypes.c_uint64, _U32P]
+        lib.or_is_single_cycle.argtypes = [_U32P, ctypes.c_uint64]
+        lib.or_is_single_cycle.restype = ctypes.c_int
+        lib.or_lds_wave_pass_sum.argtypes = [_U32P, ctypes.c_uint32, ctypes.c_uint32,
+                                             ctypes.c_uint32]
+        lib.or_lds_wave_pass_sum.restype = ctypes.c_uint32
+        lib.or_f32_to_bf16.argtypes = [_F32P, ctypes.c_uint64, _U16P]
+        lib.or_e4m3_decode.argtypes = [ctypes.c_uint8]
+        lib.or_e4m3_decode.restype = ctypes.c_double
+        lib.or_f32_to_e4m3.argtypes = [_F32P, ctypes.c_uint64, _U8P]
+        _LIB = lib
+    return _LIB
+
+
+def _f32(x):
+    return np.ascontiguousarray(x, dtype=np.float32)
+
+
+# --------------------------------------------------------------------------
+# Triad: copy-style bandwidth kernel.  The paper's copy kernel repeatedly
+# copies an input array to an output array (Section 3, Pitfall 2; Section
+# 4.3); the workload here is the STREAM triad a = b + 3c in FP32, which moves
+# two input streams and one output stream.  Repeated passes rewrite the same
+# values, so the output does not depend on how many passes ran.
+# --------------------------------------------------------------------------
+def triad_f32(b, c) -> np.ndarray:
+    b, c = _f32(b), _f32(c)
+    if b.shape != c.shape:
+        raise ValueError("b and c must have the same shape")
+    a = np.empty_like(b)
+    _lib().or_triad_f32(b.ravel(), c.ravel(), a.ravel(), b.size)
+    return a
+
+
+def bitsum_u32(x) -> int:
+    """Sum of the 32-bit patterns of x modulo 2**64 (order independent)."""
+    w = np.ascontiguousarray(x).view(np.uint32).ravel()
+    return int(_lib().or_bitsum_u32(w, w.size))
+
+
+def sum_f32_exact(x) -> float:
+    """Exact sum of FP32 values rounded to FP64."""
+    x = _f32(x).ravel()
+    return float(_lib().or_sum_f32_exact(x, x.size))
+
+
+def rel_err_sum(device_sum: float, x) -> float:
+    """Relative error of a device FP sum of x against the exact sum; falls
+    back to a normwise error (divide by sum |x|) when the sum nearly cancels
+    (|sum| < 1e-3 * sum|x|)."""
+    exact = sum_f32_exact(x)
+    absum = sum_f32_exact(np.abs(_f32(x)))
+    denom = abs(exact) if abs(exact) >= 1e-3 * absum else absum
+    if denom == 0.0:
+        return abs(device_sum - exact)
+    return abs(device_sum - exact) / denom
+
+
+# --------------------------------------------------------------------------
+# Cache working-set loops (vL1D, L2, Infinity Cache).  Every work-group sums
+# the 32-bit words of its region once per pass; the region is the same for
+# all work-groups.  Expected per-work-group checksum after P passes:
+# P * sum(region) mod 2**32.  Pass counts are run-until-stop on the device,
+# so the check uses the pass count each work-group reports.
+# --------------------------------------------------------------------------
+def region_sum_u32(words, lo: int = 0, hi: int | None = None) -> int:
+    w = np.ascontiguousarray(words, dtype=np.uint32).ravel()
+    hi = w.size if hi is None else hi
+    return int(_lib().or_sum_u32_mod32(w, lo, hi))
+
+
+def cache_wg_expected(region_words, passes) -> np.ndarray:
+    s = region_sum_u32(region_words)
+    p = np.asarray(passes, dtype=np.uint64)
+    return ((p * np.uint64(s)) & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+
+
+# --------------------------------------------------------------------------
+# LDS loop (shared-memory bandwidth / bank-conflict kernel, Section 4.4.1).
+# The window holds `nvec` vectors of `vw` words; at step k lane l reads
+# vector (l*stride + k) mod nvec (and writes it back to the twin window).
+# --------------------------------------------------------------------------
+def lds_wave_pass_sum(window_words, vw: int, stride: int) -> int:
+    w = np.ascontiguousarray(window_words, dtype=np.uint32).ravel()
+    if w.size % vw:
+        raise ValueError("window size must be a multiple of the vector width")
+    return int(_lib().or_lds_wave_pass_sum(w, w.size // vw, vw, stride))
+
+
+def lds_wg_expected(window_words, vw: int, stride: int, waves: int, passes) -> np.ndarray:
+    s = lds_wave_pass_sum(window_words, vw, stride)
+    p = np.asarray(passes, dtype=np.uint64)
+    return ((p * np.uint64(waves) * np.uint64(s)) & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+
+
+# --------------------------------------------------------------------------
+# VALU chain (compute kernel, Section 3 and Sections 4.4.2-4.4.3): each lane
+# runs `ilp` independent chains x <- fma(x, a, b).  Start values:
+# x0(t, c) = ((t mod 1024) + c + 1) * 2**-10 for global thread t, chain c.
+# --------------------------------------------------------------------------
+def fma_chain_f32(x0, a: float, b: float, steps: int) -> np.ndarray:
+    x0 = _f32(x0).ravel()
+    out = np.empty_like(x0)
+    _lib().or_fma_chain_f32(x0, x0.size, np.float32(a), np.float32(b), int(steps), out)
+    return out
+
+
+def valu_start_values(threads, ilp: int) -> np.ndarray:
+    t = np.asarray(threads, dtype=np.uint64)
+    c = np.arange(ilp, dtype=np.uint64)
+    k = (t[:, None] % np.uint64(1024)) + c[None, :] + np.uint64(1)
+    return (k.astype(np.float64) * 2.0 ** -10).astype(np.float32)
+
+
+def valu_outputs(threads, ilp: int, a: float, b: float, steps: int) -> np.ndarray:
+    """Final chain values, shape (len(threads), ilp)."""
+    x0 = valu_start_values(threads, ilp)
+    return fma_chain_f32(x0.ravel(), a, b, steps).reshape(x0.shape)
+
+
+# --------------------------------------------------------------------------
+# Pointer chase: i <- next[i], `hops` times from each start.
+# --------------------------------------------------------------------------
+def chase_u32(nxt, starts, hops: int) -> np.ndarray:
+    nxt = np.ascontiguousarray(nxt, dtype=np.uint32)
+    st = np.ascontiguousarray(starts, dtype=np.uint64)
+    end = np.empty(st.size, dtype=np.uint32)
+    _lib().or_chase_u32(nxt, nxt.size, st, st.size, int(hops), end)
+    return end
+
+
+def is_single_cycle(nxt) -> bool:
+    nxt = np.ascontiguousarray(nxt, dtype=np.uint32)
+    r = _lib().or_is_single_cycle(nxt, nxt.size)
+    if r < 0:
+        raise MemoryError("oracle could not allocate the visit map")
+    return bool(r)
+
+
+# --------------------------------------------------------------------------
+# Quantizers (precision extension).
+# --------------------------------------------------------------------------
+def f32_to_bf16(x) -> np.ndarray:
+    """Round-to-nearest-even FP32 -> BF16 codes (uint16)."""
+    x = _f32(x)
+    out = np.empty(x.shape, dtype=np.uint16)
+    _lib().or_f32_to_bf16(x.ravel(), x.size, out.reshape(-1))
+    return out
+
+
+def bf16_to_f64(codes) -> np.ndarray:
+    c = np.ascontiguousarray(codes, dtype=np.uint16)
+    return (c.astype(np.uint32) << np.uint32(16)).view(np.float32).astype(np.float64)
+
+
+def e4m3_decode(code: int) -> float:
+    return float(_lib().or_e4m3_decode(int(code) & 0xFF))
+
+
+def e4m3_table() -> np.ndarray:
+    return np.array([e4m3_decode(c) for c in range(256)], dtype=np.float64)
+
+
+def f32_to_e4m3(x) -> np.ndarray:
+    """OCP E4M3FN codes with round-to-nearest-even and saturation to +-448."""
+    x = _f32(x)
+    out = np.empty(x.shape, dtype=np.uint8)
+    _lib().or_f32_to_e4m3(x.ravel(), x.size, out.reshape(-1))
+    return out
+
+
+def e4m3_to_f64(codes) -> np.ndarray:
+    return e4m3_table()[np.asarray(codes, dtype=np.uint8)]
+
+
+def fp8_scale(x) -> tuple:
+    """Per-tensor scaling for FP8 (reading of the precision workload):
+    amax = max |x| (FP32), inv = 448 / amax and scale = amax / 448, both
+    single FP32 divisions; codes = E4M3(x * inv) with the product rounded to
+    FP32 first.  Returns (inv, scale) as FP32; amax == 0 gives (1, 1)."""
+    x = _f32(x)
+    amax = np.float32(np.max(np.abs(x))) if x.size else np.float32(0)
+    if amax == 0 or not np.isfinite(amax):
+        return np.float32(1.0), np.float32(1.0)
+    inv = np.float32(np.float32(448.0) / amax)
+    scale = np.float32(amax / np.float32(448.0))
+    return inv, scale
+
+
+def quantize_fp8(x) -> tuple:
+    """(codes, scale): codes = E4M3(fl32(x * inv)); dequantised x ~ code * scale."""
+    x = _f32(x)
+    inv, scale = fp8_scale(x)
+    y = (x * inv).astype(np.float32)
+    return f32_to_e4m3(y), scale
+
+
+# --------------------------------------------------------------------------
+# Dense victims (Section 4.4.1 uses a GEMM as the shared-memory-sensitive
+# victim; decode-phase LLM kernels (Sections 4.2, 4.3) are matrix-vector
+# products).  Plain definitions in FP64 on the already-quantised inputs.
+# --------------------------------------------------------------------------
+def gemm_f64(a, b) -> np.ndarray:
+    """C = A @ B^T with A (M x K) and B (N x K), both row-major, in FP64."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return a @ b.T
+
+
+def gemm_abs_f64(a, b) -> np.ndarray:
+    """|A| @ |B|^T: the scale of the rounding-error bound per entry."""
+    return np.abs(np.asarray(a, dtype=np.float64)) @ np.abs(np.asarray(b, dtype=np.float64)).T
+
+
+def gemm_entries_f64(a, b, rows, cols) -> np.ndarray:
+    """C[rows[k], cols[k]] of A @ B^T, one dot product per sampled entry."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    out = np.empty(len(rows), dtype=np.float64)
+    for k, (i, j) in enumerate(zip(rows, cols)):
+        out[k] = float(np.dot(a[i].astype(np.float64), b[j].astype(np.float64)))
+    return out
+
+
+def gemv_f64(w, x) -> np.ndarray:
+    """y = W @ x in FP64, W (N x K) row-major."""
+    return np.asarray(w, dtype=np.float64) @ np.asarray(x, dtype=np.float64)
+
+
+def accumulation_bound(k: int, abs_prod, unit_roundoff: float = 2.0 ** -24):
+    """Elementwise bound gamma_k * (|A||B|^T) with gamma_k = k u / (1 - k u)
+    (Higham, Accuracy and Stability of Numerical Algorithms, Lemma 3.1), for
+    FP32 accumulation of k products that are exact in FP32."""
+    ku = k * unit_roundoff
+    return (ku / (1.0 - ku)) * np.asarray(abs_prod, dtype=np.float64)
+
+
+def mfma_tile_expected(a_tile, b_tile, iterations: int) -> np.ndarray:
+    """Matrix-core stressor: acc <- A B + acc repeated `iterations` times from
+    acc = 0, for fixed fragments A (m x k) and B (k x n); exact value
+    iterations * (A @ B) in FP64."""
+    return float(iterations) * (np.asarray(a_tile, np.float64) @ np.asarray(b_tile, np.float64))
+
+
+# --------------------------------------------------------------------------
+# Slowdown and utilisation (Section 4.1: victim latency colocated versus in
+# isolation; Section 2.2: utilisation as a percentage of peak).
+# --------------------------------------------------------------------------
+def slowdown(t_alone, t_coloc) -> float:
+    """median(T_colocated) / median(T_alone)."""
+    return float(np.median(np.asarray(t_coloc, np.float64)) /
+                 np.median(np.asarray(t_alone, np.float64)))
+
+
+def pct_of_peak(achieved: float, peak: float) -> float:
+    return 100.0 * float(achieved) / float(peak)
+
+
+# --------------------------------------------------------------------------
+# Admission rule of the serving loop (reading of Section 5.1: predict each
+# kernel's slowdown from its per-resource sensitivity and the co-runners'
+# pressure, admit only when every prediction stays within the bound).
+# --------------------------------------------------------------------------
+def predicted_slowdown(sens, pressure) -> float:
+    """sens[r] = (s0, s1): victim slowdown curve on resource r, linear in the
+    stressor intensity x: s(x) = s0 + (s1 - s0) * x; pressure[r] = summed
+    co-runner pressure on r, clipped to [0, 1].  Product over resources."""
+    out = 1.0
+    for r, (s0, s1) in enumerate(sens):
+        x = min(max(float(pressure[r]), 0.0), 1.0)
+        out *= max(1.0, s0 + (s1 - s0) * x) / max(1.0, s0)
+    return out
+
+
+def admit(policy: str, running: list, cand: dict, free_bytes: int, bound: float,
+          slots: int) -> bool:
+    """running / cand: dicts with 'sens' (per-resource (s0, s1)), 'press'
+    (per-resource pressure it exerts), 'bytes' and 'occ' (fraction of wave
+    slots).  Policies: 'naive' (memory and slot only), 'usher' (summed
+    occupancy below 1, Section 3 Pitfall 1), 'sensitivity' (predicted
+    slowdown of every job within `bound`)."""
+    if cand["bytes"] > free_bytes or len(running) >= slots:
+        return False
+    if policy == "naive":
+        return True
+    if policy == "usher":
+        return sum(j["occ"] for j in running) + cand["occ"] < 1.0
+    if policy != "sensitivity":
+        raise ValueError(policy)
+    group = running + [cand]
+    nres = len(cand["sens"])
+    for j in group:
+        press = [0.0] * nres
+        for o in group:
+            if o is j:
+                continue
+            for r in range(nres):
+                press[r] += o["press"][r]
+        if predicted_slowdown(j["sens"], press) > bound:
+            return False
+    return True
+
+
+def _median(xs):
+    return float(np.median(np.asarray(xs, np.float64))) if len(xs) else math.nan

@@ -1,0 +1,348 @@
+"""Pins of the CPU oracle against facts fixed outside the oracle itself:
+published test vectors, closed forms, library routines that compute the
+same definition independently, brute force on tiny inputs and numbers the
+paper prints.  Each pin is chosen so that a plausible slip in the oracle (a
+fused multiply-add where two roundings are meant, a wrong stride or index,
+a transposed operand, an off-by-one in a walk) fails it."""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ----------------------------------------------------------------- inputs
+def test_splitmix64_published_vector():
+    with open(os.path.join(GOLDEN, "splitmix64_seed1234567.txt")) as f:
+        want = [int(l) for l in f if l.strip() and not l.startswith("#")]
+    assert synth.splitmix64_sequence(1234567, len(want)) == want
+
+
+def test_uniform_is_exact_grid_and_in_range():
+    u = synth.uniform_f32(7, 1 << 16)
+    assert u.dtype == np.float32
+    assert u.min() >= -1.0 and u.max() < 1.0
+    k = (u.astype(np.float64) + 1.0) * 2.0 ** 23
+    assert np.all(k == np.round(k))            # multiples of 2**-23
+    assert abs(u.mean()) < 4 * math.sqrt(1 / 3 / u.size)
+    assert abs(u.var() - 1 / 3) < 0.01
+    # counter form: regenerating any index alone gives the same value
+    idx = np.array([0, 5, 65535])
+    assert np.array_equal(synth.uniform_f32_at(7, idx), u[idx])
+    assert np.array_equal(synth.uniform_f32(7, 10, start=100), u[100:110])
+
+
+def test_normal_moments():
+    z = synth.normal_f32(11, 1 << 18, sigma=0.02)
+    n = z.size
+    assert abs(z.mean()) < 4 * 0.02 / math.sqrt(n)
+    assert abs(z.std() / 0.02 - 1.0) < 4 * math.sqrt(0.5 / n)
+
+
+def test_random_cycle_is_one_cycle():
+    for n in (1, 2, 3, 17, 1000):
+        nxt = synth.random_cycle_u32(5, n)
+        seen, i = set(), 0
+        for _ in range(n):
+            seen.add(i)
+            i = int(nxt[i])
+        assert i == 0 and len(seen) == n
+        assert oracle.is_single_cycle(nxt)
+
+
+def test_is_single_cycle_rejects_two_cycles_and_bad_tables():
+    assert not oracle.is_single_cycle(np.array([1, 0, 3, 2], np.uint32))   # two 2-cycles
+    assert not oracle.is_single_cycle(np.array([0, 1], np.uint32))         # fixed points
+    assert not oracle.is_single_cycle(np.array([1, 5, 0], np.uint32))      # out of range
+    assert oracle.is_single_cycle(np.array([1, 2, 0], np.uint32))
+
+
+# ------------------------------------------------------------------ triad
+def test_triad_closed_forms():
+    n = 4096
+    b = synth.uniform_f32(1, n)
+    assert np.array_equal(oracle.triad_f32(b, np.zeros(n, np.float32)), b)
+    for k in (-20, 0, 7):
+        c = np.full(n, 2.0 ** k, np.float32)
+        assert np.all(oracle.triad_f32(np.zeros(n, np.float32), c) == np.float32(3 * 2.0 ** k))
+
+
+def test_triad_has_two_roundings_not_one():
+    """a = fl(b + fl(3c)).  In FP64, 3c is exact (26 bits) and so is b + fl(3c)
+    for these inputs, so rounding each step once to FP32 gives the definition
+    independently of the oracle's own FP32 code path.  A fused version
+    (one rounding) must differ somewhere on these inputs."""
+    n = 1 << 18
+    b, c = synth.uniform_f32(2, n), synth.uniform_f32(3, n)
+    t = (3.0 * c.astype(np.float64)).astype(np.float32)
+    want = (b.astype(np.float64) + t.astype(np.float64)).astype(np.float32)
+    got = oracle.triad_f32(b, c)
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+    fused = (b.astype(np.float64) + 3.0 * c.astype(np.float64)).astype(np.float32)
+    assert np.count_nonzero(fused != want) > 0
+
+
+def test_triad_sum_identity():
+    """|sum a - (sum b + 3 sum c)| <= u * sum(3|c| + |a|), u = 2**-24."""
+    n = 1 << 16
+    b, c = synth.uniform_f32(4, n), synth.uniform_f32(5, n)
+    a = oracle.triad_f32(b, c)
+    lhs = abs(oracle.sum_f32_exact(a) - (math.fsum(b.astype(float)) + 3 * math.fsum(c.astype(float))))
+    assert lhs <= 2.0 ** -24 * float(np.sum(3 * np.abs(c.astype(np.float64)) + np.abs(a)))
+
+
+# --------------------------------------------------------------- checksums
+def test_bitsum_brute_force_and_wrap():
+    x = np.array([1.0, -2.5, 0.0], np.float32)
+    assert oracle.bitsum_u32(x) == sum(int(v) for v in x.view(np.uint32)) % 2 ** 64
+    w = np.full(5, 0xFFFFFFFF, np.uint32)
+    assert oracle.bitsum_u32(w) == 5 * 0xFFFFFFFF
+    big = np.full(1 << 20, 0xFFFFFFFF, np.uint32)
+    assert oracle.bitsum_u32(big) == ((1 << 20) * 0xFFFFFFFF) % 2 ** 64
+
+
+def test_exact_sum_against_fsum_and_cancellation():
+    x = synth.uniform_f32(9, 100000) * np.float32(1e3)
+    assert oracle.sum_f32_exact(x) == math.fsum(x.astype(float))
+    y = np.array([3e38, 1.0, -3e38, 2.0 ** -149, -1.0], np.float32)
+    assert oracle.sum_f32_exact(y) == 2.0 ** -149
+    z = np.array([-1.5, -2.25], np.float32)
+    assert oracle.sum_f32_exact(z) == -3.75
+    assert math.isnan(oracle.sum_f32_exact(np.array([1.0, np.inf], np.float32)))
+
+
+def test_rel_err_sum_switches_to_normwise_on_cancellation():
+    x = np.array([1.0, -1.0, 1e-6], np.float32)
+    # sum ~ 1e-6 << 1e-3 * sum|x| ~ 2e-3 -> normwise, denominator ~ 2
+    assert oracle.rel_err_sum(0.0, x) == pytest.approx(float(np.float32(1e-6)) / 2.000001, rel=1e-6)
+
+
+def test_cache_sums_closed_form():
+    for n in (1, 7, 4096, 1 << 20):
+        w = np.arange(n, dtype=np.uint32)
+        assert oracle.region_sum_u32(w) == (n * (n - 1) // 2) % 2 ** 32
+    w = np.arange(1 << 20, dtype=np.uint32)
+    exp = oracle.cache_wg_expected(w, [0, 1, 3, 1000003])
+    s = ((1 << 20) * ((1 << 20) - 1) // 2) % 2 ** 32
+    assert list(exp) == [0, s, (3 * s) % 2 ** 32, (1000003 * s) % 2 ** 32]
+
+
+def test_lds_pass_visits_every_vector_once_per_lane():
+    """Each lane walks all nvec vectors once per pass, for any stride, so a
+    wave's pass sum is 64 * sum(window); brute force on a tiny window also
+    pins the stride and index arithmetic."""
+    w = synth.u32(21, 8192)
+    total = int(w.astype(np.uint64).sum()) % 2 ** 32
+    for vw in (1, 2, 4):
+        for stride in (1, 2, 3, 32, 64):
+            assert oracle.lds_wave_pass_sum(w, vw, stride) == (64 * total) % 2 ** 32
+    tiny = np.arange(12, dtype=np.uint32) * np.uint32(7) + np.uint32(1)
+    for vw, stride in ((1, 5), (2, 4), (4, 3)):
+        nvec = 12 // vw
+        s = 0
+        for lane in range(64):
+            for k in range(nvec):
+                v = (lane * stride + k) % nvec
+                s += int(tiny[v * vw:(v + 1) * vw].sum())
+        assert oracle.lds_wave_pass_sum(tiny, vw, stride) == s % 2 ** 32
+
+
+# ------------------------------------------------------------- VALU chain
+def test_fma_chain_closed_forms():
+    z = np.zeros(3, np.float32)
+    assert np.all(oracle.fma_chain_f32(z, 1.0, 1.0, 1000) == 1000.0)
+    out = oracle.fma_chain_f32(z, 0.5, 1.0, 10)
+    assert np.all(out == np.float32(2 - 2.0 ** -9))
+    assert np.all(oracle.fma_chain_f32(z, 0.5, 1.0, 30) == 2.0)
+
+
+def test_fma_chain_rounds_once():
+    """x*a = 1 + 2**-11 + 2**-24 exactly; fma(x, a, -1) keeps the 2**-24
+    term, whereas rounding the product first would lose it."""
+    x = np.array([1 + 2.0 ** -12], np.float32)
+    out = oracle.fma_chain_f32(x, 1 + 2.0 ** -12, -1.0, 1)
+    assert out[0] == np.float32(2.0 ** -11 + 2.0 ** -24)
+
+
+def test_valu_start_values_and_fixed_point():
+    th = np.array([0, 1, 1023, 1024, 5000])
+    x0 = oracle.valu_start_values(th, 4)
+    assert x0[0, 0] == np.float32(2.0 ** -10) and x0[3, 0] == x0[0, 0]
+    assert x0[2, 3] == np.float32((1023 + 3 + 1) * 2.0 ** -10)
+    # x_{k} - 1 = a^k (x0 - 1) with a = 1 - 2**-12, b = 2**-12: converges to 1
+    out = oracle.valu_outputs(th, 4, 1 - 2.0 ** -12, 2.0 ** -12, 4096)
+    exact = 1 + (1 - 2.0 ** -12) ** 4096 * (x0.astype(np.float64) - 1)
+    assert np.max(np.abs(out - exact)) < 4096 * 2.0 ** -23
+
+
+# ----------------------------------------------------------- pointer chase
+def test_chase_brute_force_and_full_cycle():
+    n = 1 << 12
+    nxt = synth.random_cycle_u32(13, n)
+    starts = np.array([0, 1, 4095, 77], np.uint64)
+    for hops in (0, 1, 5, 1000):
+        want = []
+        for s in starts:
+            i = int(s)
+            for _ in range(hops):
+                i = int(nxt[i])
+            want.append(i)
+        assert list(oracle.chase_u32(nxt, starts, hops)) == want
+    assert np.array_equal(oracle.chase_u32(nxt, starts, n), starts.astype(np.uint32))
+    assert not np.array_equal(oracle.chase_u32(nxt, starts, n - 1), starts.astype(np.uint32))
+
+
+# ----------------------------------------------------------------- BF16
+def test_bf16_ties_overflow_nan():
+    f = lambda bits: np.array([bits], np.uint32).view(np.float32)
+    # halfway between 1.0 (0x3F80) and 1 + 2**-7 (0x3F81): even code wins
+    assert oracle.f32_to_bf16(f(0x3F808000))[0] == 0x3F80
+    # halfway between 0x3F81 and 0x3F82: even code wins (0x3F82)
+    assert oracle.f32_to_bf16(f(0x3F818000))[0] == 0x3F82
+    assert oracle.f32_to_bf16(f(0x3F808001))[0] == 0x3F81
+    assert oracle.f32_to_bf16(f(0x3F807FFF))[0] == 0x3F80
+    assert oracle.f32_to_bf16(f(0xBF808001))[0] == 0xBF81
+    # largest finite FP32 rounds to +inf in BF16 (beyond the overflow midpoint)
+    assert oracle.f32_to_bf16(f(0x7F7FFFFF))[0] == 0x7F80
+    assert oracle.f32_to_bf16(f(0x7F7F7FFF))[0] == 0x7F7F
+    assert oracle.f32_to_bf16(np.array([np.inf, -np.inf], np.float32)).tolist() == [0x7F80, 0xFF80]
+    assert oracle.f32_to_bf16(np.array([np.nan], np.float32))[0] & 0x7FC0 == 0x7FC0
+
+
+def test_bf16_nearest_by_brute_force():
+    x = synth.normal_f32(17, 5000)
+    codes = oracle.f32_to_bf16(x)
+    for v, c in zip(x[:500], codes[:500]):
+        t = int(np.array([v], np.float32).view(np.uint32)[0]) >> 16
+        cands = [t, t + 1]
+        vals = [Fraction(float(oracle.bf16_to_f64(np.array([cc], np.uint16))[0])) for cc in cands]
+        err = [abs(Fraction(float(v)) - q) for q in vals]
+        best = cands[0] if err[0] < err[1] else cands[1] if err[1] < err[0] else \
+            (cands[0] if cands[0] % 2 == 0 else cands[1])
+        assert c == best
+
+
+# ------------------------------------------------------------------- FP8
+def test_e4m3_named_values():
+    with open(os.path.join(GOLDEN, "e4m3_points.txt")) as f:
+        rows = [l.split() for l in f if l.strip() and not l.startswith("#")]
+    for code, val in rows:
+        got = oracle.e4m3_decode(int(code, 16))
+        assert got == float(val) and math.copysign(1, got) == math.copysign(1, float(val))
+    assert math.isnan(oracle.e4m3_decode(0x7F)) and math.isnan(oracle.e4m3_decode(0xFF))
+    t = oracle.e4m3_table()
+    finite = t[np.isfinite(t)]
+    assert finite.size == 254 and np.max(finite) == 448.0
+
+
+def test_e4m3_round_trip_ties_and_saturation():
+    t = oracle.e4m3_table()
+    codes = np.array([c for c in range(256) if np.isfinite(t[c])], np.uint8)
+    vals = t[codes].astype(np.float32)
+    back = oracle.f32_to_e4m3(vals)
+    # +0 and -0 keep their own codes; every finite code round-trips
+    assert np.array_equal(back, codes)
+    # midpoint between 1.0 (0x38, even) and 1.125 (0x39) -> 0x38;
+    # midpoint between 1.125 and 1.25 (0x3A, even) -> 0x3A
+    assert oracle.f32_to_e4m3(np.array([1.0625, 1.1875], np.float32)).tolist() == [0x38, 0x3A]
+    # saturation: beyond 448, infinities -> +-448; NaN -> NaN code
+    assert oracle.f32_to_e4m3(np.array([464.0, 1e9, np.inf, -np.inf], np.float32)).tolist() == \
+        [0x7E, 0x7E, 0x7E, 0xFE]
+    assert oracle.f32_to_e4m3(np.array([np.nan], np.float32))[0] & 0x7F == 0x7F
+    # below half the smallest subnormal -> zero; at exactly half -> zero (even)
+    assert oracle.f32_to_e4m3(np.array([2.0 ** -11, 2.0 ** -10, 2.0 ** -10 * 1.01], np.float32)).tolist() \
+        == [0, 0, 1]
+
+
+def test_fp8_scale_and_quantize():
+    x = np.array([0.5, -2.0, 1.0], np.float32)
+    inv, scale = oracle.fp8_scale(x)
+    assert inv == np.float32(224.0) and scale == np.float32(2.0 / 448.0)
+    codes, s = oracle.quantize_fp8(x)
+    assert oracle.e4m3_decode(codes[1]) == -448.0
+    assert np.allclose(oracle.e4m3_to_f64(codes) * s, x, rtol=2 ** -4)
+    assert oracle.fp8_scale(np.zeros(4, np.float32)) == (1.0, 1.0)
+
+
+# ---------------------------------------------------------------- GEMM/V
+def test_gemm_oracle_against_loops_and_identity():
+    rng_a = synth.normal_f32(31, 5 * 7).reshape(5, 7)
+    rng_b = synth.normal_f32(32, 3 * 7).reshape(3, 7)
+    c = oracle.gemm_f64(rng_a, rng_b)
+    for i in range(5):
+        for j in range(3):
+            s = math.fsum(float(rng_a[i, k]) * float(rng_b[j, k]) for k in range(7))
+            assert abs(c[i, j] - s) < 1e-12
+    eye = np.eye(7, dtype=np.float32)
+    assert np.array_equal(oracle.gemm_f64(rng_a, eye), rng_a.astype(np.float64))
+    # B^T convention: a non-symmetric B must not be used untransposed
+    b = np.arange(49, dtype=np.float32).reshape(7, 7)
+    assert np.array_equal(oracle.gemm_f64(eye, b), b.T.astype(np.float64))
+    ent = oracle.gemm_entries_f64(rng_a, rng_b, [0, 4, 2], [2, 0, 1])
+    assert np.allclose(ent, [c[0, 2], c[4, 0], c[2, 1]], rtol=0, atol=1e-12)
+
+
+def test_gemv_row_sums():
+    w = synth.normal_f32(33, 6 * 9, sigma=0.02).reshape(6, 9)
+    y = oracle.gemv_f64(w, np.ones(9, np.float32))
+    for i in range(6):
+        assert abs(y[i] - math.fsum(float(v) for v in w[i])) < 1e-15
+
+
+def test_accumulation_bound_and_mfma_closed_form():
+    b = oracle.accumulation_bound(4096, np.ones((2, 2)))
+    assert np.allclose(b, 4096 * 2.0 ** -24 / (1 - 4096 * 2.0 ** -24))
+    a = np.ones((32, 16))
+    bb = np.ones((16, 32))
+    assert np.all(oracle.mfma_tile_expected(a, bb, 1000) == 16000.0)
+    a2 = np.arange(6, dtype=float).reshape(2, 3)
+    b2 = np.arange(6, dtype=float).reshape(3, 2)
+    assert np.array_equal(oracle.mfma_tile_expected(a2, b2, 2), 2 * np.array([[10, 13], [28, 40]]))
+
+
+# ------------------------------------------------------ paper's own numbers
+def test_slowdown_definition_against_paper_table1():
+    with open(os.path.join(GOLDEN, "paper_numbers.json")) as f:
+        p = json.load(f)
+    t = p["table1_membw"]
+    s = oracle.slowdown([t["p90_tbt_ms"][0]], [t["p90_tbt_ms"][-1]])
+    assert round(s, 2) == t["max_slowdown_stated"]
+    fv = p["full_vs_partition"]
+    assert round(oracle.slowdown([fv["full_ms"]], [fv["partition_ms"]]), 2) == fv["slowdown_stated"]
+    bs = p["block_scheduler"]
+    assert oracle.slowdown([bs["alone_ms"]] * 3, [bs["coloc_ms"]] * 3) > 2.0
+    # median, not mean: one outlier does not move it
+    assert oracle.slowdown([1.0, 1.0, 1.0], [1.0, 1.0, 100.0]) == 1.0
+    occ = p["occupancy"]
+    assert oracle.pct_of_peak(occ["warps_per_block"], occ["max_warps_per_sm"]) == occ["occupancy_pct"]
+
+
+# ------------------------------------------------------------- admission
+def _job(sens1, press, nbytes=1, occ=0.1):
+    return {"sens": [(1.0, s) for s in sens1], "press": press, "bytes": nbytes, "occ": occ}
+
+
+def test_admission_rules():
+    quiet = _job([1.0, 1.0], [0.0, 0.0])
+    hog = _job([1.0, 1.0], [1.0, 0.0], occ=0.6)
+    fragile = _job([3.0, 1.0], [0.0, 0.0], occ=0.6)
+    # memory and slots bind every policy
+    for pol in ("naive", "usher", "sensitivity"):
+        assert not oracle.admit(pol, [], _job([1, 1], [0, 0], nbytes=10), 5, 1.5, 4)
+        assert not oracle.admit(pol, [quiet] * 4, quiet, 10, 1.5, 4)
+    assert oracle.admit("naive", [hog], fragile, 10, 1.5, 4)
+    assert not oracle.admit("usher", [hog], fragile, 10, 1.5, 4)     # occupancy 1.2
+    assert not oracle.admit("sensitivity", [hog], fragile, 10, 1.5, 4)  # predicts 3x
+    assert oracle.admit("sensitivity", [hog], fragile, 10, 3.0, 4)
+    assert oracle.admit("sensitivity", [quiet], fragile, 10, 1.5, 4)
+    # unbounded: sensitivity == naive
+    assert oracle.admit("sensitivity", [hog, hog], fragile, 10, math.inf, 4)
+    # linear interpolation of the curve at half pressure: 1 + (3-1)*0.5 = 2
+    assert oracle.predicted_slowdown([(1.0, 3.0)], [0.5]) == 2.0
