@@ -1,0 +1,382 @@
+/*
+ * coloc.h -- C ABI of libcoloc.so, the MI355X (gfx950) resource-stressor
+ * suite and victim-colocation harness.
+ *
+ * What it measures follows Elvinger et al., "Understanding GPU Resource
+ * Interference One Level Deeper" (SoCC'25):
+ *   - one microbenchmark per shared GPU resource, each holding a constant
+ *     level of interference for the whole life of the colocated workload
+ *     (Section 4.1);
+ *   - the workload's slowdown colocated versus in isolation (Section 4.3,
+ *     cache-pollution experiment), per resource and per intensity, as the
+ *     sensitivity profile a kernel-level interference estimator consumes
+ *     (Section 5.1);
+ *   - the stressor's own utilisation as a fraction of the resource's peak
+ *     (Section 2.2 metrics; Tables 1-3).
+ * Intra-CU colocation is two HIP streams; the CU-partitioned (inter-CU)
+ * mode, the paper's green-context setting (Section 4.1), uses CU-masked
+ * streams.
+ *
+ * Conventions for every call:
+ *   - Returns ci_status_t; never throws, never exits.  On error,
+ *     ci_last_error() returns a thread-local message (valid until the next
+ *     call on the same thread).
+ *   - "device pointer" = memory of the context's GPU, allocated by the caller
+ *     (e.g. torch) unless stated; the library never frees it.
+ *   - `stream` arguments are hipStream_t values passed as void*.  The call's
+ *     work is ordered after work already queued on `stream`, and `stream`
+ *     waits for the call's results.  NULL means "no ordering": the caller
+ *     must have finished its own prior work (the legacy null stream is never
+ *     used, because it would serialise against the CU-masked streams).
+ *   - Device timestamps are the GPU's constant-rate wall clock
+ *     (ci_device_info_t.wall_clock_khz ticks per millisecond).
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef COLOC_H
+#define COLOC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ci_status {
+  CI_OK = 0,
+  CI_ERR_INVALID_ARG = 1,  /* bad pointer, size, enum, intensity or option */
+  CI_ERR_HIP = 2,          /* a HIP runtime call failed (message names it)  */
+  CI_ERR_OOM = 3,          /* device or host allocation failed / budget    */
+  CI_ERR_TIMEOUT = 4,      /* a stressor hit its in-kernel deadline, or did
+                              not start within the start timeout           */
+  CI_ERR_UNSUPPORTED = 5,  /* combination not implemented on this device   */
+  CI_ERR_BUSY = 6          /* context already has a stressor on that slot  */
+} ci_status_t;
+
+/* Shared resources with one stressor each (paper Section 4: block scheduler
+ * 4.2; L2 capacity and memory bandwidth 4.3; shared memory 4.4.1; issue
+ * (IPC) 4.4.2; compute pipelines 4.4.3), mapped to CDNA4 units. */
+typedef enum ci_resource {
+  CI_RES_HBM = 0,        /* triad a = b + 3c streaming over FP32 arrays       */
+  CI_RES_L2 = 1,         /* every WG re-reads one region sized for each XCD's L2 */
+  CI_RES_MALL = 2,       /* ... a region that misses L2 and fits Infinity Cache */
+  CI_RES_VL1D = 3,       /* ... a region that fits the per-CU vector L1        */
+  CI_RES_LDS = 4,        /* LDS copy loop with a stride (bank-conflict) knob   */
+  CI_RES_VALU_F32 = 5,   /* FP32 FMA chains with an ILP knob                   */
+  CI_RES_MFMA_F32 = 6,   /* matrix-core loops, FP32 inputs                     */
+  CI_RES_MFMA_BF16 = 7,  /* ... BF16 inputs                                    */
+  CI_RES_MFMA_FP8 = 8,   /* ... FP8 E4M3 inputs                                */
+  CI_RES_PTRCHASE = 9,   /* dependent loads through a random cycle             */
+  CI_RES_DISPATCH = 10,  /* stream of empty 64-thread work-groups              */
+  CI_RES_OCCUPANCY = 11, /* sleeping WGs that hold LDS / wave slots (Sec. 4.2)  */
+  CI_RES_COUNT = 12
+} ci_resource_t;
+
+typedef enum ci_dtype { CI_DT_F32 = 0, CI_DT_BF16 = 1, CI_DT_FP8E4M3 = 2 } ci_dtype_t;
+
+typedef enum ci_victim_kind {
+  CI_VICTIM_TRIAD_F32 = 0, /* a = b + 3c (FP32), `passes` sweeps per launch    */
+  CI_VICTIM_GEMM = 1,      /* C = s_a s_b A B^T, FP32 accumulate and output    */
+  CI_VICTIM_GEMV = 2       /* y = W x, BF16 in, FP32 accumulate and output     */
+} ci_victim_kind_t;
+
+typedef enum ci_placement {
+  CI_PLACE_SHARED = 0,     /* victim may use every CU (intra-CU colocation)    */
+  CI_PLACE_DISJOINT = 1    /* victim confined to the CUs the stressor lacks    */
+} ci_placement_t;
+
+typedef struct ci_ctx ci_ctx_t;
+typedef struct ci_stressor ci_stressor_t;
+
+/* ---------------------------------------------------------------- device */
+typedef struct ci_device_info {
+  int device;
+  int num_cus;              /* compute units visible (256 on MI355X)        */
+  int num_xcds;             /* accelerator complex dies (8)                  */
+  int wave_size;            /* 64                                            */
+  int clock_khz;            /* peak engine clock reported by the runtime     */
+  int wall_clock_khz;       /* device timestamp rate                          */
+  uint64_t lds_bytes_per_cu;
+  uint64_t l2_bytes_per_xcd;
+  uint64_t hbm_bytes;
+  char arch[64];            /* gcnArchName, e.g. "gfx950:sramecc+:xnack-"    */
+  /* peak denominators used for %-of-peak (published figures for MI355X,
+   * or, where none is published, per-clock derivations: see
+   * ci_peak_for()).                                                          */
+  double peak[CI_RES_COUNT];
+} ci_device_info_t;
+
+/* Create a context on HIP device `device`: reads device properties, builds
+ * the CU-mask layout and allocates the small internal scratch (checksum
+ * partials, pinned control block).  *out owned by the library. */
+ci_status_t ci_init(int device, ci_ctx_t** out);
+/* Destroy a context; stops nothing: every stressor must be stopped first
+ * (CI_ERR_BUSY otherwise).  NULL is a no-op. */
+ci_status_t ci_shutdown(ci_ctx_t* ctx);
+const char* ci_last_error(void);
+ci_status_t ci_device_info(ci_ctx_t* ctx, ci_device_info_t* out);
+
+/* Peak of resource r in its own unit: bytes/s for HBM, L2, MALL, VL1D and
+ * LDS; flop/s for VALU and MFMA; work-groups/s for DISPATCH; hops/s for the
+ * chase (no peak: 0); OCCUPANCY has no rate (0). */
+ci_status_t ci_peak_for(ci_ctx_t* ctx, ci_resource_t r, double* peak);
+
+/* ------------------------------------------------------------ CU masks */
+/* Intensity x in [0, 1] -> k = 8 * round(32 * x) CUs (num_xcds *
+ * round(num_cus / num_xcds * x) in general): whole steps of one CU on every
+ * XCD, since work-groups are dealt to the XCDs round-robin and a queue whose
+ * mask leaves an XCD empty cannot be created.  CU-mask bit b selects CU b/8
+ * of XCD b mod 8, so the mask is bits 0..k-1.  mask: 8 uint32 words as
+ * hipExtStreamCreateWithCUMask reads them.  complement != 0 returns the other
+ * num_cus - k CUs (the disjoint-placement victim mask).  *ncu receives the
+ * number of CUs in the returned mask. */
+ci_status_t ci_cu_mask(ci_ctx_t* ctx, float intensity, int complement, uint32_t mask[8],
+                       int* ncu);
+
+/* Placement probe (the AMD analog of the paper's per-block SM-ID print,
+ * Section 4.2 footnote): launches `nwg` 64-thread work-groups on a stream
+ * restricted to `mask` (NULL = all CUs; CI_ERR_INVALID_ARG if the mask
+ * leaves an XCD without CUs); work-group i writes its hardware
+ * location to out_loc[i] (device pointer, nwg uint32):
+ *   bits 0-3 CU id, bit 4 shader array, bits 5-6 shader engine, bits 8-11 XCD.
+ * Synchronous. */
+ci_status_t ci_probe_placement(ci_ctx_t* ctx, const uint32_t* mask, uint32_t nwg,
+                               uint32_t* out_loc);
+
+/* ----------------------------------------------------------- stressors */
+/* Per-work-group record written by every stressor work-group at exit
+ * (device memory inside the caller's workspace). */
+typedef struct ci_wg_record {
+  uint64_t t_start;  /* device wall clock at WG start                      */
+  uint64_t t_end;    /* device wall clock at WG exit                       */
+  uint64_t work;     /* passes completed (per resource unit, see below)    */
+  uint64_t check;    /* checksum accumulated by the WG (resource specific) */
+  uint32_t loc;      /* hardware location, encoded as in ci_probe_placement */
+  uint32_t flags;    /* bit 0: exited on its deadline; bit 1: saw stop     */
+  uint64_t pad;
+} ci_wg_record_t;    /* 48 bytes */
+
+typedef struct ci_stressor_opts {
+  /* Resource-specific operands (device pointers, caller-owned):
+   *   HBM:        src0 = b, src1 = c, dst = a   (FP32, n elements)
+   *   L2/MALL/VL1D: src0 = region (uint32, n words)
+   *   LDS:        src0 = window words (uint32, 8192 = 32 KiB)
+   *   VALU_F32:   dst  = final chain values (FP32, grid*threads*knob)
+   *   MFMA_*:     src0 = A tile (32 x K), src1 = B tile (K x 32), row-major,
+   *               element type F32 / BF16 / E4M3 with K = 2 / 16 / 64;
+   *               dst = per-wave accumulator tiles (FP32, waves*knob*32*32)
+   *   PTRCHASE:   src0 = next[] (uint32, n entries, one cycle),
+   *               dst = end index per chain (uint32, grid*threads*knob)
+   *   DISPATCH:   dst = uint64 counter of work-groups executed (may be NULL
+   *               for the empty-kernel timing form)
+   *   OCCUPANCY:  none                                                       */
+  const void* src0;
+  const void* src1;
+  void* dst;
+  uint64_t n;
+  uint32_t wg_per_cu;    /* work-groups per masked CU; 0 = resource default  */
+  uint32_t threads;      /* threads per work-group; 0 = resource default     */
+  uint32_t knob;         /* VALU: ILP chains per lane (1,2,4,8); LDS: stride
+                            in vectors; MFMA: independent accumulators (1-4);
+                            PTRCHASE: chains per lane (1-8); OCCUPANCY: LDS
+                            KiB held per WG; 0 = default                     */
+  uint32_t vec;          /* LDS: vector width in 32-bit words (1, 2, 4)      */
+  uint64_t passes;       /* 0 = run until stressor_stop; > 0 = exactly this
+                            many passes per work-group, then exit            */
+  uint64_t iters;        /* VALU: FMA steps per pass (default 4096); MFMA:
+                            MFMAs per accumulator per pass (default 1024);
+                            PTRCHASE: hops per pass (default 65536);
+                            DISPATCH: work-groups per launch (default 1e6)   */
+  float fa, fb;          /* VALU chain x <- fma(x, fa, fb)                   */
+  uint32_t deadline_ms;  /* in-kernel safety deadline, 0 = 2000 ms           */
+  uint32_t reserved;
+} ci_stressor_opts_t;
+
+typedef struct ci_stressor_report {
+  int resource;
+  int ncu;                  /* CUs in the stressor's mask                    */
+  uint32_t grid;            /* work-groups launched                          */
+  uint32_t wg_reported;     /* records with t_end != 0                       */
+  uint64_t t_first_start;   /* min record t_start                            */
+  uint64_t t_last_start;    /* max record t_start                            */
+  uint64_t t_first_end;     /* min record t_end                              */
+  uint64_t t_last_end;      /* max record t_end                              */
+  double window_ns;         /* t_last_end - t_first_start in ns              */
+  double kernel_ns;         /* event time of the launch(es)                  */
+  uint64_t work;            /* sum of record work                            */
+  double units;             /* algorithmic bytes / flops / WGs / hops        */
+  double achieved;          /* units / window seconds                        */
+  double pct_of_peak;       /* 100 * achieved / peak (0 if no peak)          */
+  uint64_t checksum;        /* sum of record checks mod 2^64                 */
+  int timed_out;            /* some WG exited on its deadline                */
+  int distinct_cus;         /* distinct hardware CUs seen in the records     */
+} ci_stressor_report_t;
+
+/* Device bytes of workspace a stressor needs for `ncu` CUs (its records and
+ * control words).  intensity-independent upper bound: pass ncu = num_cus. */
+ci_status_t ci_workspace_size(ci_resource_t r, const ci_stressor_opts_t* opts, int ncu,
+                              size_t* bytes);
+
+/* Start stressor r at CU fraction `intensity` (0..1, rounded as in
+ * ci_cu_mask).  The kernel runs on a
+ * library-owned CU-masked stream that first waits for work already queued on
+ * `stream` (which is not blocked).  With opts->passes == 0 the call returns
+ * once the stressor is observed running on the device (all its work-groups
+ * resident, or 50 ms elapsed), and it keeps running until stressor_stop or
+ * its deadline.  With passes > 0 it returns right after the launch.
+ * intensity == 0 returns a valid handle that launches nothing.  ws: device
+ * workspace of ws_bytes >= ci_workspace_size(); must stay allocated until
+ * stressor_stop returns.  One running stressor per context at a time:
+ * CI_ERR_BUSY otherwise. */
+ci_status_t stressor_launch(ci_ctx_t* ctx, ci_resource_t r, float intensity, void* stream,
+                            const ci_stressor_opts_t* opts, void* ws, size_t ws_bytes,
+                            ci_stressor_t** h);
+
+/* Signal stop, wait for the kernel(s) to drain (bounded by the deadline),
+ * make `stream` of the launch wait for completion, read the records and fill
+ * *rep (may be NULL).  Frees h.  Returns CI_ERR_TIMEOUT (after filling rep)
+ * if a work-group hit its deadline. */
+ci_status_t stressor_stop(ci_stressor_t* h, ci_stressor_report_t* rep);
+
+/* Copy the stressor's records (grid entries) to host memory; valid only
+ * between the end of stressor_stop's drain and the next launch: call with
+ * the same ws after stressor_stop. */
+ci_status_t ci_read_records(ci_ctx_t* ctx, const void* ws, uint32_t grid, ci_wg_record_t* out);
+
+/* -------------------------------------------------------------- victims */
+typedef struct ci_victim_desc {
+  int kind;              /* ci_victim_kind_t                                  */
+  int dtype;             /* GEMM: F32 / BF16 / FP8E4M3; GEMV: BF16; TRIAD: F32 */
+  uint64_t m, n, k;      /* TRIAD: n elements; GEMM: M, N, K; GEMV: n rows, k cols */
+  const void* a;         /* TRIAD: b; GEMM: A (M x K row-major); GEMV: W (copies x n x k) */
+  const void* b;         /* TRIAD: c; GEMM: B (N x K row-major); GEMV: x (k)  */
+  void* out;             /* TRIAD: a (n FP32); GEMM: C (M x N FP32); GEMV: y (n FP32) */
+  float scale_a, scale_b;/* FP8 dequantisation scales (ignored otherwise)     */
+  uint32_t passes;       /* TRIAD sweeps per launch (>= 1)                     */
+  uint32_t copies;       /* GEMV weight copies rotated over runs (>= 1)        */
+} ci_victim_desc_t;
+
+typedef struct ci_victim_result {
+  double time_ns;          /* launch time from HIP events                      */
+  uint64_t checksum_bits;  /* sum of the output's 32-bit patterns mod 2^64     */
+  double sum_f64;          /* FP64 sum of the output (fixed reduction order)   */
+  uint64_t t_begin;        /* device clock just before / after the victim      */
+  uint64_t t_end;
+} ci_victim_result_t;
+
+/* Run the victim once on `stream` and wait for it: one kernel launch timed
+ * with HIP events, bracketed by device timestamps, followed by the output
+ * checksum.  Victim constraints: TRIAD n >= 0; GEMM K a multiple of 16 / 8 /
+ * 4 elements for FP8 / BF16 / F32 (any M, N); GEMV k a multiple of 8. */
+ci_status_t victim_run(ci_ctx_t* ctx, const ci_victim_desc_t* d, void* stream,
+                       ci_victim_result_t* out);
+
+/* Checksums of n FP32 values at device pointer x (stream-ordered on
+ * `stream`, synchronous): bit-pattern sum mod 2^64 and FP64 sum. */
+ci_status_t ci_checksum_f32(ci_ctx_t* ctx, const void* x, uint64_t n, void* stream,
+                            uint64_t* bits, double* sum);
+
+/* Per-tensor quantisation on the device (precision extension):
+ *   dtype BF16: dst (uint16 codes) = round-to-nearest-even of src;
+ *   dtype FP8E4M3: amax = max|src|, inv = 448/amax, scale = amax/448 (FP32),
+ *     dst (uint8 codes) = E4M3FN(fl32(src * inv)), nearest-even, saturating
+ *     at +-448; *scale_out = scale (1 when amax == 0).
+ * Synchronous on `stream`. */
+ci_status_t ci_quantize(ci_ctx_t* ctx, const void* src, uint64_t n, int dtype, void* dst,
+                        float* scale_out, void* stream);
+
+/* ------------------------------------------------------- sensitivity */
+typedef struct ci_measure_opts {
+  uint32_t reps;         /* alone/colocated pairs per cell (default 20)       */
+  uint32_t warmups;      /* victim warm-up runs per cell (default 3)          */
+  int placement;         /* ci_placement_t                                    */
+  uint32_t deadline_ms;  /* stressor deadline per colocated run (default 2000) */
+} ci_measure_opts_t;
+
+typedef struct ci_cell {
+  int resource;
+  float intensity;
+  int ncu;
+  double slowdown;            /* median(T_col) / median(T_alone)             */
+  double slowdown_p10, slowdown_p90;  /* of the per-rep ratios               */
+  double t_alone_ns;          /* medians                                      */
+  double t_col_ns;
+  double stressor_achieved;   /* mean over reps, resource units / s          */
+  double stressor_pct_peak;
+  int window_covered;         /* every colocated run inside the stressor window */
+  int output_equal;           /* every colocated output checksum == alone      */
+  int timed_out;
+  int reps;
+} ci_cell_t;
+
+/* For every resource rs[i] (operands in sopts[i]) and intensity xs[j]:
+ * warm the victim up, then `reps` times run it alone and colocated with the
+ * stressor (persistent mode), checking the window and output of each
+ * colocated run; cells[i * nx + j] receives the result.  ws: workspace large
+ * enough for every listed stressor at full intensity.  Synchronous. */
+ci_status_t measure_sensitivity(ci_ctx_t* ctx, const ci_victim_desc_t* d,
+                                const ci_resource_t* rs, const ci_stressor_opts_t* sopts, int nr,
+                                const float* xs, int nx, const ci_measure_opts_t* o, void* ws,
+                                size_t ws_bytes, void* stream, ci_cell_t* cells);
+
+/* ------------------------------------------------------------- serving */
+typedef enum ci_policy_kind {
+  CI_POLICY_NAIVE = 0,       /* admit when memory and a slot are free          */
+  CI_POLICY_USHER = 1,       /* ... and summed occupancy stays below 1         */
+  CI_POLICY_SENSITIVITY = 2  /* ... and every predicted slowdown <= bound      */
+} ci_policy_kind_t;
+
+#define CI_NPOINTS 5  /* intensities 0, .25, .5, .75, 1 */
+
+typedef struct ci_profile {
+  int kind;                             /* victim kind this profile covers    */
+  float sens[CI_RES_COUNT][CI_NPOINTS]; /* measured slowdown curve per resource */
+  float press[CI_RES_COUNT];            /* pressure it exerts (0..1)           */
+  float occ;                            /* fraction of wave slots it fills     */
+} ci_profile_t;
+
+typedef struct ci_request {
+  double arrival_s;       /* seconds after the loop starts                   */
+  int kind;               /* ci_victim_kind_t                                 */
+  int dtype;              /* as in ci_victim_desc_t                           */
+  uint64_t m, n, k;       /* sizes as in ci_victim_desc_t                     */
+  uint64_t seed;          /* input stream seed (uniform [-1, 1) inputs)       */
+} ci_request_t;
+
+typedef struct ci_policy {
+  int kind;               /* ci_policy_kind_t                                 */
+  double bound;           /* SENSITIVITY: max predicted slowdown              */
+  uint64_t hbm_budget;    /* bytes of device memory the loop may hold         */
+  int slots;              /* max requests on the device at once (1..8)        */
+  const ci_profile_t* profiles;
+  int nprofiles;
+} ci_policy_t;
+
+typedef struct ci_served {
+  double arrival_s, admit_s, end_s;  /* host clock, seconds after start       */
+  double service_ns;                 /* device time of the request's kernel   */
+  uint64_t checksum_bits;
+  double sum_f64;
+  int slot;
+  int status;                        /* ci_status_t of this request           */
+} ci_served_t;
+
+/* Continuous-batching colocation loop: requests (sorted by arrival_s)
+ * arrive in real time; each is admitted FIFO (no bypass) when the policy
+ * allows, its inputs are generated and its kernel launched on a free slot
+ * stream, and it retires when its completion is observed.  The loop owns
+ * one device arena of hbm_budget bytes for all request buffers.  out[i]
+ * receives request i's record.  Synchronous; returns when all are done. */
+ci_status_t serve_run(ci_ctx_t* ctx, const ci_request_t* trace, int n, const ci_policy_t* p,
+                      ci_served_t* out);
+
+/* Pure admission decision used by serve_run, exposed for testing:
+ * running[0..nrun) and cand index profiles; bytes in use / free; returns 1
+ * (admit) or 0 in *admit. */
+ci_status_t ci_admit(const ci_policy_t* p, const int* running_kinds, int nrun, int cand_kind,
+                     uint64_t cand_bytes, uint64_t free_bytes, int* admit);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COLOC_H */

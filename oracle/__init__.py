@@ -197,6 +197,12 @@ def chase_u32(nxt, starts, hops: int) -> np.ndarray:
     return end
 
 
+def chase_starts(nchains: int, n: int) -> np.ndarray:
+    """Evenly spaced starts: chain q of Q begins at floor(q * n / Q)."""
+    q = np.arange(nchains, dtype=np.uint64)
+    return (q * np.uint64(n)) // np.uint64(nchains)
+
+
 def is_single_cycle(nxt) -> bool:
     nxt = np.ascontiguousarray(nxt, dtype=np.uint32)
     r = _lib().or_is_single_cycle(nxt, nxt.size)
@@ -329,21 +335,29 @@ def pct_of_peak(achieved: float, peak: float) -> float:
 # kernel's slowdown from its per-resource sensitivity and the co-runners'
 # pressure, admit only when every prediction stays within the bound).
 # --------------------------------------------------------------------------
+SENS_POINTS = (0.0, 0.25, 0.5, 0.75, 1.0)
+
+
+def curve_at(curve, x: float) -> float:
+    """Piecewise-linear slowdown curve measured at intensities SENS_POINTS."""
+    x = min(max(float(x), 0.0), 1.0)
+    return float(np.interp(x, SENS_POINTS, np.asarray(curve, np.float64)))
+
+
 def predicted_slowdown(sens, pressure) -> float:
-    """sens[r] = (s0, s1): victim slowdown curve on resource r, linear in the
-    stressor intensity x: s(x) = s0 + (s1 - s0) * x; pressure[r] = summed
-    co-runner pressure on r, clipped to [0, 1].  Product over resources."""
+    """sens[r]: the victim's slowdown curve on resource r (five points);
+    pressure[r]: summed co-runner pressure on r.  Product over resources of
+    max(1, curve_r(pressure_r)) (a conservative combination)."""
     out = 1.0
-    for r, (s0, s1) in enumerate(sens):
-        x = min(max(float(pressure[r]), 0.0), 1.0)
-        out *= max(1.0, s0 + (s1 - s0) * x) / max(1.0, s0)
+    for r, curve in enumerate(sens):
+        out *= max(1.0, curve_at(curve, pressure[r]))
     return out
 
 
 def admit(policy: str, running: list, cand: dict, free_bytes: int, bound: float,
           slots: int) -> bool:
-    """running / cand: dicts with 'sens' (per-resource (s0, s1)), 'press'
-    (per-resource pressure it exerts), 'bytes' and 'occ' (fraction of wave
+    """running / cand: dicts with 'sens' (per-resource five-point curves),
+    'press' (per-resource pressure it exerts), 'bytes' and 'occ' (fraction of wave
     slots).  Policies: 'naive' (memory and slot only), 'usher' (summed
     occupancy below 1, Section 3 Pitfall 1), 'sensitivity' (predicted
     slowdown of every job within `bound`)."""

@@ -1,0 +1,469 @@
+"""Python binding of libcoloc.so (include/coloc.h): argument marshalling only.
+
+Every step runs in the library's HIP kernels; torch supplies device memory
+and streams.  Loading fails loudly when the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcoloc.so")
+
+RESOURCES = ["hbm", "l2", "mall", "vl1d", "lds", "valu_f32", "mfma_f32", "mfma_bf16",
+             "mfma_fp8", "ptrchase", "dispatch", "occupancy"]
+RES = {name: i for i, name in enumerate(RESOURCES)}
+DTYPES = {"f32": 0, "bf16": 1, "fp8": 2}
+VICTIMS = {"triad": 0, "gemm": 1, "gemv": 2}
+POLICIES = {"naive": 0, "usher": 1, "sensitivity": 2}
+STATUS = {0: "CI_OK", 1: "CI_ERR_INVALID_ARG", 2: "CI_ERR_HIP", 3: "CI_ERR_OOM",
+          4: "CI_ERR_TIMEOUT", 5: "CI_ERR_UNSUPPORTED", 6: "CI_ERR_BUSY"}
+NPOINTS = 5
+NRES = len(RESOURCES)
+
+
+class CiError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class DeviceInfo(C.Structure):
+    _fields_ = [("device", C.c_int), ("num_cus", C.c_int), ("num_xcds", C.c_int),
+                ("wave_size", C.c_int), ("clock_khz", C.c_int), ("wall_clock_khz", C.c_int),
+                ("lds_bytes_per_cu", C.c_uint64), ("l2_bytes_per_xcd", C.c_uint64),
+                ("hbm_bytes", C.c_uint64), ("arch", C.c_char * 64),
+                ("peak", C.c_double * NRES)]
+
+
+class WgRecord(C.Structure):
+    _fields_ = [("t_start", C.c_uint64), ("t_end", C.c_uint64), ("work", C.c_uint64),
+                ("check", C.c_uint64), ("loc", C.c_uint32), ("flags", C.c_uint32),
+                ("pad", C.c_uint64)]
+
+
+class StressorOpts(C.Structure):
+    _fields_ = [("src0", C.c_void_p), ("src1", C.c_void_p), ("dst", C.c_void_p),
+                ("n", C.c_uint64), ("wg_per_cu", C.c_uint32), ("threads", C.c_uint32),
+                ("knob", C.c_uint32), ("vec", C.c_uint32), ("passes", C.c_uint64),
+                ("iters", C.c_uint64), ("fa", C.c_float), ("fb", C.c_float),
+                ("deadline_ms", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class StressorReport(C.Structure):
+    _fields_ = [("resource", C.c_int), ("ncu", C.c_int), ("grid", C.c_uint32),
+                ("wg_reported", C.c_uint32), ("t_first_start", C.c_uint64),
+                ("t_last_start", C.c_uint64), ("t_first_end", C.c_uint64),
+                ("t_last_end", C.c_uint64), ("window_ns", C.c_double), ("kernel_ns", C.c_double),
+                ("work", C.c_uint64), ("units", C.c_double), ("achieved", C.c_double),
+                ("pct_of_peak", C.c_double), ("checksum", C.c_uint64), ("timed_out", C.c_int),
+                ("distinct_cus", C.c_int)]
+
+
+class VictimDesc(C.Structure):
+    _fields_ = [("kind", C.c_int), ("dtype", C.c_int), ("m", C.c_uint64), ("n", C.c_uint64),
+                ("k", C.c_uint64), ("a", C.c_void_p), ("b", C.c_void_p), ("out", C.c_void_p),
+                ("scale_a", C.c_float), ("scale_b", C.c_float), ("passes", C.c_uint32),
+                ("copies", C.c_uint32)]
+
+
+class VictimResult(C.Structure):
+    _fields_ = [("time_ns", C.c_double), ("checksum_bits", C.c_uint64), ("sum_f64", C.c_double),
+                ("t_begin", C.c_uint64), ("t_end", C.c_uint64)]
+
+
+class MeasureOpts(C.Structure):
+    _fields_ = [("reps", C.c_uint32), ("warmups", C.c_uint32), ("placement", C.c_int),
+                ("deadline_ms", C.c_uint32)]
+
+
+class Cell(C.Structure):
+    _fields_ = [("resource", C.c_int), ("intensity", C.c_float), ("ncu", C.c_int),
+                ("slowdown", C.c_double), ("slowdown_p10", C.c_double),
+                ("slowdown_p90", C.c_double), ("t_alone_ns", C.c_double),
+                ("t_col_ns", C.c_double), ("stressor_achieved", C.c_double),
+                ("stressor_pct_peak", C.c_double), ("window_covered", C.c_int),
+                ("output_equal", C.c_int), ("timed_out", C.c_int), ("reps", C.c_int)]
+
+
+class Profile(C.Structure):
+    _fields_ = [("kind", C.c_int), ("sens", (C.c_float * NPOINTS) * NRES),
+                ("press", C.c_float * NRES), ("occ", C.c_float)]
+
+
+class Request(C.Structure):
+    _fields_ = [("arrival_s", C.c_double), ("kind", C.c_int), ("dtype", C.c_int),
+                ("m", C.c_uint64), ("n", C.c_uint64), ("k", C.c_uint64), ("seed", C.c_uint64)]
+
+
+class Policy(C.Structure):
+    _fields_ = [("kind", C.c_int), ("bound", C.c_double), ("hbm_budget", C.c_uint64),
+                ("slots", C.c_int), ("profiles", C.POINTER(Profile)), ("nprofiles", C.c_int)]
+
+
+class Served(C.Structure):
+    _fields_ = [("arrival_s", C.c_double), ("admit_s", C.c_double), ("end_s", C.c_double),
+                ("service_ns", C.c_double), ("checksum_bits", C.c_uint64), ("sum_f64", C.c_double),
+                ("slot", C.c_int), ("status", C.c_int)]
+
+
+EXPORTS = {
+    "ci_init": ([C.c_int, C.POINTER(C.c_void_p)], C.c_int),
+    "ci_shutdown": ([C.c_void_p], C.c_int),
+    "ci_last_error": ([], C.c_char_p),
+    "ci_device_info": ([C.c_void_p, C.POINTER(DeviceInfo)], C.c_int),
+    "ci_peak_for": ([C.c_void_p, C.c_int, C.POINTER(C.c_double)], C.c_int),
+    "ci_cu_mask": ([C.c_void_p, C.c_float, C.c_int, C.POINTER(C.c_uint32), C.POINTER(C.c_int)], C.c_int),
+    "ci_probe_placement": ([C.c_void_p, C.POINTER(C.c_uint32), C.c_uint32, C.c_void_p], C.c_int),
+    "ci_workspace_size": ([C.c_int, C.POINTER(StressorOpts), C.c_int, C.POINTER(C.c_size_t)], C.c_int),
+    "stressor_launch": ([C.c_void_p, C.c_int, C.c_float, C.c_void_p, C.POINTER(StressorOpts),
+                         C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)], C.c_int),
+    "stressor_stop": ([C.c_void_p, C.POINTER(StressorReport)], C.c_int),
+    "ci_read_records": ([C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(WgRecord)], C.c_int),
+    "victim_run": ([C.c_void_p, C.POINTER(VictimDesc), C.c_void_p, C.POINTER(VictimResult)], C.c_int),
+    "ci_checksum_f32": ([C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.POINTER(C.c_uint64),
+                         C.POINTER(C.c_double)], C.c_int),
+    "ci_quantize": ([C.c_void_p, C.c_void_p, C.c_uint64, C.c_int, C.c_void_p, C.POINTER(C.c_float),
+                     C.c_void_p], C.c_int),
+    "measure_sensitivity": ([C.c_void_p, C.POINTER(VictimDesc), C.POINTER(C.c_int),
+                             C.POINTER(StressorOpts), C.c_int, C.POINTER(C.c_float), C.c_int,
+                             C.POINTER(MeasureOpts), C.c_void_p, C.c_size_t, C.c_void_p,
+                             C.POINTER(Cell)], C.c_int),
+    "serve_run": ([C.c_void_p, C.POINTER(Request), C.c_int, C.POINTER(Policy), C.POINTER(Served)], C.c_int),
+    "ci_admit": ([C.POINTER(Policy), C.POINTER(C.c_int), C.c_int, C.c_int, C.c_uint64, C.c_uint64,
+                  C.POINTER(C.c_int)], C.c_int),
+}
+
+_LIB = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libcoloc.so and declare every exported entry point."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built: run python -m paper_2501_16909_amd.build "
+                               "(the device library has no fallback)")
+        lib = C.CDLL(path)
+        for name, (args, res) in EXPORTS.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _LIB = lib
+    return _LIB
+
+
+def _check(st: int):
+    if st != 0:
+        msg = load_library().ci_last_error()
+        raise CiError(st, msg.decode() if msg else "")
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream_handle(stream) -> int | None:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+@dataclass
+class Report:
+    resource: str
+    ncu: int
+    grid: int
+    wg_reported: int
+    t_first_start: int
+    t_last_start: int
+    t_first_end: int
+    t_last_end: int
+    window_ns: float
+    kernel_ns: float
+    work: int
+    units: float
+    achieved: float
+    pct_of_peak: float
+    checksum: int
+    timed_out: bool
+    distinct_cus: int
+    status: int = 0
+
+
+def _report(r: StressorReport, st: int) -> Report:
+    return Report(RESOURCES[r.resource], r.ncu, r.grid, r.wg_reported, r.t_first_start,
+                  r.t_last_start, r.t_first_end, r.t_last_end, r.window_ns, r.kernel_ns, r.work,
+                  r.units, r.achieved, r.pct_of_peak, r.checksum, bool(r.timed_out), r.distinct_cus,
+                  st)
+
+
+def make_opts(**kw) -> StressorOpts:
+    o = StressorOpts()
+    for k, v in kw.items():
+        if k in ("src0", "src1", "dst"):
+            setattr(o, k, _ptr(v))
+        else:
+            setattr(o, k, v)
+    return o
+
+
+class Stressor:
+    """A running stressor; use as a context manager or call stop()."""
+
+    def __init__(self, ctx: "Context", resource: str, intensity: float, stream=None,
+                 ws=None, keep=(), **opts):
+        import torch
+        self.ctx = ctx
+        self.resource = resource
+        self.opts = make_opts(**opts)
+        self._keep = keep  # tensors that must outlive the kernel
+        lib = load_library()
+        need = C.c_size_t()
+        _check(lib.ci_workspace_size(RES[resource], C.byref(self.opts), ctx.info.num_cus, C.byref(need)))
+        if ws is None:
+            ws = torch.empty(max(int(need.value), 256), dtype=torch.uint8, device=ctx.device)
+        self.ws = ws
+        self.stream = stream
+        h = C.c_void_p()
+        _check(lib.stressor_launch(ctx.handle, RES[resource], float(intensity),
+                                   _stream_handle(stream), C.byref(self.opts), _ptr(ws),
+                                   ws.numel(), C.byref(h)))
+        self.h = h
+        self.report: Report | None = None
+
+    def stop(self, raise_on_timeout: bool = True) -> Report:
+        if self.h is None:
+            return self.report
+        rep = StressorReport()
+        st = load_library().stressor_stop(self.h, C.byref(rep))
+        self.h = None
+        self.report = _report(rep, st)
+        if st != 0 and not (st == 4 and not raise_on_timeout):
+            _check(st)
+        return self.report
+
+    def records(self) -> np.ndarray:
+        """Per-work-group records (valid after stop())."""
+        g = self.report.grid if self.report else 0
+        arr = (WgRecord * max(g, 1))()
+        _check(load_library().ci_read_records(self.ctx.handle, _ptr(self.ws), g, arr))
+        dt = np.dtype([("t_start", "<u8"), ("t_end", "<u8"), ("work", "<u8"), ("check", "<u8"),
+                       ("loc", "<u4"), ("flags", "<u4"), ("pad", "<u8")])
+        return np.frombuffer(bytes(arr), dtype=dt, count=g).copy()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.stop(raise_on_timeout=exc[0] is None)
+        return False
+
+
+@dataclass
+class VictimOutcome:
+    time_ns: float
+    checksum_bits: int
+    sum_f64: float
+    t_begin: int
+    t_end: int
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        import torch
+        lib = load_library()
+        h = C.c_void_p()
+        _check(lib.ci_init(int(device), C.byref(h)))
+        self.handle = h
+        self.device = torch.device("cuda", device)
+        info = DeviceInfo()
+        _check(lib.ci_device_info(h, C.byref(info)))
+        self.info = info
+        self.stream = torch.cuda.Stream(device=self.device)
+
+    def close(self):
+        if self.handle:
+            _check(load_library().ci_shutdown(self.handle))
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
+    # -------------------------------------------------------------- info
+    def peak(self, resource: str) -> float:
+        v = C.c_double()
+        _check(load_library().ci_peak_for(self.handle, RES[resource], C.byref(v)))
+        return v.value
+
+    def cu_mask(self, intensity: float, complement: bool = False):
+        m = (C.c_uint32 * 8)()
+        n = C.c_int()
+        _check(load_library().ci_cu_mask(self.handle, float(intensity), int(complement), m, C.byref(n)))
+        return list(m), n.value
+
+    def probe_placement(self, mask, nwg: int) -> np.ndarray:
+        import torch
+        out = torch.zeros(nwg, dtype=torch.int32, device=self.device)
+        torch.cuda.synchronize(self.device)
+        mp = (C.c_uint32 * 8)(*mask) if mask is not None else None
+        _check(load_library().ci_probe_placement(self.handle, mp, nwg, _ptr(out)))
+        return out.cpu().numpy().view(np.uint32)
+
+    # ---------------------------------------------------------- stressors
+    def _sync_torch(self):
+        import torch
+        torch.cuda.current_stream(self.device).synchronize()
+
+    def stressor(self, resource: str, intensity: float, stream=None, ws=None, **opts) -> Stressor:
+        self._sync_torch()
+        keep = tuple(v for k, v in opts.items() if k in ("src0", "src1", "dst") and v is not None)
+        return Stressor(self, resource, intensity, stream if stream is not None else self.stream,
+                        ws=ws, keep=keep, **opts)
+
+    # ------------------------------------------------------------ victims
+    def victim_run(self, desc: VictimDesc, stream=None) -> VictimOutcome:
+        self._sync_torch()
+        r = VictimResult()
+        s = stream if stream is not None else self.stream
+        _check(load_library().victim_run(self.handle, C.byref(desc), _stream_handle(s), C.byref(r)))
+        return VictimOutcome(r.time_ns, r.checksum_bits, r.sum_f64, r.t_begin, r.t_end)
+
+    @staticmethod
+    def triad_desc(b, c, a, passes: int = 1) -> VictimDesc:
+        d = VictimDesc()
+        d.kind, d.dtype, d.n = 0, 0, b.numel()
+        d.a, d.b, d.out = _ptr(b), _ptr(c), _ptr(a)
+        d.passes, d.copies, d.scale_a, d.scale_b = passes, 1, 1.0, 1.0
+        return d
+
+    @staticmethod
+    def gemm_desc(A, B, Cm, dtype: str, m: int, n: int, k: int, scale_a=1.0, scale_b=1.0) -> VictimDesc:
+        d = VictimDesc()
+        d.kind, d.dtype, d.m, d.n, d.k = 1, DTYPES[dtype], m, n, k
+        d.a, d.b, d.out = _ptr(A), _ptr(B), _ptr(Cm)
+        d.scale_a, d.scale_b, d.passes, d.copies = float(scale_a), float(scale_b), 1, 1
+        return d
+
+    @staticmethod
+    def gemv_desc(W, x, y, n: int, k: int, copies: int = 1) -> VictimDesc:
+        d = VictimDesc()
+        d.kind, d.dtype, d.n, d.k = 2, 1, n, k
+        d.a, d.b, d.out = _ptr(W), _ptr(x), _ptr(y)
+        d.copies, d.passes, d.scale_a, d.scale_b = copies, 1, 1.0, 1.0
+        return d
+
+    def victim_triad(self, b, c, a, passes: int = 1, stream=None) -> VictimOutcome:
+        return self.victim_run(self.triad_desc(b, c, a, passes), stream)
+
+    def checksum(self, x) -> tuple:
+        self._sync_torch()
+        bits, s = C.c_uint64(), C.c_double()
+        _check(load_library().ci_checksum_f32(self.handle, _ptr(x), x.numel(),
+                                              _stream_handle(self.stream), C.byref(bits), C.byref(s)))
+        return bits.value, s.value
+
+    def quantize(self, x, dtype: str):
+        """(codes tensor, scale): BF16 (uint16 codes viewed as int16) or FP8 (uint8)."""
+        import torch
+        self._sync_torch()
+        if dtype == "bf16":
+            out = torch.empty(x.shape, dtype=torch.int16, device=x.device)
+        elif dtype == "fp8":
+            out = torch.empty(x.shape, dtype=torch.uint8, device=x.device)
+        else:
+            raise ValueError(dtype)
+        sc = C.c_float()
+        _check(load_library().ci_quantize(self.handle, _ptr(x), x.numel(), DTYPES[dtype], _ptr(out),
+                                          C.byref(sc), _stream_handle(self.stream)))
+        return out, sc.value
+
+    # -------------------------------------------------------- sensitivity
+    def measure_sensitivity(self, desc: VictimDesc, resources, opts_list, intensities,
+                            reps: int = 20, warmups: int = 3, placement: str = "shared",
+                            deadline_ms: int = 2000, ws=None):
+        import torch
+        self._sync_torch()
+        nr, nx = len(resources), len(intensities)
+        rs = (C.c_int * nr)(*[RES[r] for r in resources])
+        so = (StressorOpts * nr)(*[make_opts(**o) for o in opts_list])
+        xs = (C.c_float * nx)(*[float(x) for x in intensities])
+        mo = MeasureOpts(reps, warmups, 1 if placement == "disjoint" else 0, deadline_ms)
+        need = 256
+        for i in range(nr):
+            b = C.c_size_t()
+            _check(load_library().ci_workspace_size(rs[i], C.byref(so[i]), self.info.num_cus, C.byref(b)))
+            need = max(need, int(b.value))
+        if ws is None:
+            ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        cells = (Cell * (nr * nx))()
+        _check(load_library().measure_sensitivity(self.handle, C.byref(desc), rs, so, nr, xs, nx,
+                                                  C.byref(mo), _ptr(ws), ws.numel(),
+                                                  _stream_handle(self.stream), cells))
+        out = []
+        for c in cells:
+            out.append({f: getattr(c, f) for f, _ in Cell._fields_})
+            out[-1]["resource"] = RESOURCES[c.resource]
+        return out
+
+    # ------------------------------------------------------------ serving
+    def serve(self, requests, policy: str = "naive", bound: float = 1.5, hbm_budget: int = 8 << 30,
+              slots: int = 4, profiles=None):
+        self._sync_torch()
+        n = len(requests)
+        tr = (Request * max(n, 1))()
+        for i, q in enumerate(requests):
+            tr[i] = Request(q["arrival_s"], VICTIMS[q["kind"]], DTYPES[q.get("dtype", "f32")],
+                            q.get("m", 0), q.get("n", 0), q.get("k", 0), q["seed"])
+        profs = make_profiles(profiles or {})
+        pol = Policy(POLICIES[policy], bound, hbm_budget, slots,
+                     C.cast(profs, C.POINTER(Profile)) if len(profs) else None, len(profs))
+        out = (Served * max(n, 1))()
+        _check(load_library().serve_run(self.handle, tr, n, C.byref(pol), out))
+        return [{f: getattr(out[i], f) for f, _ in Served._fields_} for i in range(n)]
+
+
+def make_profiles(profiles: dict):
+    """profiles: {kind name: {"sens": {res: [5 slowdowns]}, "press": {res: p}, "occ": o}}."""
+    arr = (Profile * max(len(profiles), 1))()
+    for i, (kind, p) in enumerate(profiles.items()):
+        arr[i].kind = VICTIMS[kind]
+        for r in range(NRES):
+            for j in range(NPOINTS):
+                arr[i].sens[r][j] = 1.0
+            arr[i].press[r] = 0.0
+        for rname, curve in p.get("sens", {}).items():
+            for j, v in enumerate(curve):
+                arr[i].sens[RES[rname]][j] = float(v)
+        for rname, v in p.get("press", {}).items():
+            arr[i].press[RES[rname]] = float(v)
+        arr[i].occ = float(p.get("occ", 0.0))
+    if not profiles:
+        return (Profile * 0)()
+    return arr
+
+
+def admit(policy: str, profiles: dict, running_kinds, cand_kind: str, cand_bytes: int,
+          free_bytes: int, bound: float = 1.5, slots: int = 4) -> bool:
+    profs = make_profiles(profiles)
+    pol = Policy(POLICIES[policy], bound, 1 << 40, slots,
+                 C.cast(profs, C.POINTER(Profile)) if len(profs) else None, len(profs))
+    rk = (C.c_int * max(len(running_kinds), 1))(*[VICTIMS[k] for k in running_kinds])
+    out = C.c_int()
+    _check(load_library().ci_admit(C.byref(pol), rk, len(running_kinds), VICTIMS[cand_kind],
+                                   cand_bytes, free_bytes, C.byref(out)))
+    return bool(out.value)

@@ -1,0 +1,276 @@
+// Memory-side kernels: the triad (bandwidth stressor and victim) and the
+// cache working-set loop used for the vL1D, L2 and Infinity-Cache stressors.
+//
+// The paper's bandwidth microbenchmark is a copy kernel that keeps copying a
+// large input array to an output array with vectorised loads (Section 3,
+// Pitfall 2; Section 4.3, Table 1); its cache-pollution variant sweeps the
+// per-instance data size to move the working set in and out of L2 (Section
+// 4.3, Figure 3).  Here the streaming form is the triad a = b + 3c (two FP32
+// input streams, one output stream); the cache forms re-read a region sized
+// to one level of the CDNA4 hierarchy.
+#include "internal.h"
+
+namespace ci {
+namespace {
+
+constexpr uint32_t kChunk = 1024;  // floats per wave-chunk: 64 lanes x 4 x 4
+
+__device__ __forceinline__ float triad1(float b, float c) {
+  // two roundings: fl(b + fl(3c)); contraction into a fused multiply-add is
+  // switched off for this expression
+#pragma clang fp contract(off)
+  const float t = 3.0f * c;
+  return b + t;
+}
+
+__device__ __forceinline__ float4 triad4(float4 b, float4 c) {
+  return make_float4(triad1(b.x, c.x), triad1(b.y, c.y), triad1(b.z, c.z), triad1(b.w, c.w));
+}
+
+// One wave-chunk of 1024 elements starting at `base`: four 16-byte loads of
+// each input per lane, all issued before the first store.  Streaming
+// (non-temporal) hints: the stressor's data is never reused.
+typedef float vf4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ vf4 triad_v(vf4 b, vf4 c) {
+  vf4 r;
+  r.x = triad1(b.x, c.x);
+  r.y = triad1(b.y, c.y);
+  r.z = triad1(b.z, c.z);
+  r.w = triad1(b.w, c.w);
+  return r;
+}
+
+__device__ __forceinline__ void triad_chunk(const float* __restrict__ b, const float* __restrict__ c,
+                                            float* __restrict__ a, uint64_t base, uint64_t n,
+                                            uint32_t lane) {
+  if (base + kChunk <= n) {
+    const vf4* b4 = reinterpret_cast<const vf4*>(b + base);
+    const vf4* c4 = reinterpret_cast<const vf4*>(c + base);
+    vf4* a4 = reinterpret_cast<vf4*>(a + base);
+    vf4 vb[4], vc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      vb[u] = __builtin_nontemporal_load(b4 + u * 64 + lane);
+      vc[u] = __builtin_nontemporal_load(c4 + u * 64 + lane);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) __builtin_nontemporal_store(triad_v(vb[u], vc[u]), a4 + u * 64 + lane);
+  } else {
+    for (uint64_t i = base + lane; i < n && i < base + kChunk; i += 64) a[i] = triad1(b[i], c[i]);
+  }
+}
+
+// Persistent / fixed-pass triad.  Wave w of the grid owns wave-chunks
+// w, w + W, w + 2W, ... (W = waves in the grid); record.work counts the
+// wave-chunks the work-group processed.
+__global__ void __launch_bounds__(1024) triad_stressor(KCtrl c, const float* __restrict__ b,
+                                                       const float* __restrict__ cc,
+                                                       float* __restrict__ a, uint64_t n) {
+  __shared__ uint64_t s_t0;
+  __shared__ uint64_t s_work[16];
+  __shared__ uint32_t s_flags[16];
+  const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
+  const uint32_t wpg = blockDim.x >> 6;
+  if (threadIdx.x == 0) {
+    uint64_t t0;
+    wg_begin(c, t0);
+    s_t0 = t0;
+    if (blockIdx.x == 0) poller_announce(c, t0);
+  }
+  __syncthreads();
+  const uint64_t t0 = s_t0;
+  const uint64_t gw = (uint64_t)blockIdx.x * wpg + wid;
+  const uint64_t nw = (uint64_t)gridDim.x * wpg;
+  const uint64_t nchunks = (n + kChunk - 1) / kChunk;
+  uint64_t done = 0;
+  StopState st;
+  stop_init(st, c, t0, blockIdx.x == 0 && wid == 0);
+  if (c.passes) {
+    for (uint64_t p = 0; p < c.passes; ++p)
+      for (uint64_t ch = gw; ch < nchunks; ch += nw) {
+        triad_chunk(b, cc, a, ch * kChunk, n, lane);
+        ++done;
+      }
+  } else if (gw < nchunks) {
+    uint64_t ch = gw;
+    for (;;) {
+      triad_chunk(b, cc, a, ch * kChunk, n, lane);
+      ++done;
+      ch += nw;
+      if (ch >= nchunks) ch = gw;
+      if (should_stop(st, c)) break;
+    }
+  } else {
+    while (!should_stop(st, c)) __builtin_amdgcn_s_sleep(32);
+  }
+  if (lane == 0) {
+    s_work[wid] = done;
+    s_flags[wid] = st.flags;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t w = 0;
+    uint32_t f = 0;
+    for (uint32_t i = 0; i < wpg; ++i) { w += s_work[i]; f |= s_flags[i]; }
+    write_record(c, blockIdx.x, t0, w, 0, f);
+  }
+}
+
+// Victim triad: `passes` sweeps of the whole array (grid-stride over
+// wave-chunks); every sweep rewrites the same values.
+__global__ void __launch_bounds__(256) triad_victim(const float* __restrict__ b,
+                                                    const float* __restrict__ c,
+                                                    float* __restrict__ a, uint64_t n,
+                                                    uint32_t passes) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint64_t gw = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
+  const uint64_t nchunks = (n + kChunk - 1) / kChunk;
+  for (uint32_t p = 0; p < passes; ++p)
+    for (uint64_t ch = gw; ch < nchunks; ch += nw) {
+      const uint64_t base = ch * kChunk;
+      if (base + kChunk <= n) {
+        const float4* b4 = reinterpret_cast<const float4*>(b + base);
+        const float4* c4 = reinterpret_cast<const float4*>(c + base);
+        float4* a4 = reinterpret_cast<float4*>(a + base);
+        float4 vb[4], vc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) { vb[u] = b4[u * 64 + lane]; vc[u] = c4[u * 64 + lane]; }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a4[u * 64 + lane] = triad4(vb[u], vc[u]);
+      } else {
+        for (uint64_t i = base + lane; i < n && i < base + kChunk; i += 64) a[i] = triad1(b[i], c[i]);
+      }
+    }
+}
+
+// Cache working-set loop.  Work-group g reads its span of `len` words once per
+// pass: the whole region (slice_words == 0; each work-group starts at its own
+// phase so that concurrent groups do not walk in lock-step) or its own slice
+// [g * slice, (g + 1) * slice) mod region.  Threads read 16 bytes at a time,
+// four loads in flight; every word of the span is read exactly once per pass.
+// record.work = passes, record.check = sum of the words read, mod 2^32.
+// Span length must be a multiple of 4 * blockDim.x words (checked on the host).
+__global__ void __launch_bounds__(1024) cache_stressor(KCtrl c, const uint32_t* __restrict__ region,
+                                                       uint64_t region_words, uint64_t slice_words,
+                                                       uint32_t batch) {
+  __shared__ uint64_t s_t0;
+  __shared__ uint32_t s_stop;
+  __shared__ uint32_t s_part[16];
+  const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6, wpg = blockDim.x >> 6;
+  if (threadIdx.x == 0) {
+    uint64_t t0;
+    wg_begin(c, t0);
+    s_t0 = t0;
+    s_stop = 0;
+    if (blockIdx.x == 0) poller_announce(c, t0);
+  }
+  __syncthreads();
+  const uint64_t t0 = s_t0;
+  const uint64_t len = slice_words ? slice_words : region_words;
+  const uint64_t lo = slice_words ? ((uint64_t)blockIdx.x * slice_words) % region_words : 0;
+  const uint64_t round_words = 4ull * blockDim.x;           // one 16-byte load per thread
+  const uint64_t rounds = len / round_words;
+  const uint64_t phase = slice_words ? 0 : ((uint64_t)blockIdx.x * 7u) % rounds;
+  const uint4* base = reinterpret_cast<const uint4*>(region + lo);
+  StopState st;
+  stop_init(st, c, t0, blockIdx.x == 0 && threadIdx.x == 0);
+  uint32_t acc = 0;
+  uint64_t passes = 0;
+  for (;;) {
+    for (uint32_t bt = 0; bt < batch; ++bt) {
+      uint64_t r = phase;
+      uint64_t left = rounds;
+      while (left >= 4) {
+        uint4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          uint64_t rr = r + u;
+          if (rr >= rounds) rr -= rounds;
+          v[u] = base[rr * blockDim.x + threadIdx.x];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += v[u].x + v[u].y + v[u].z + v[u].w;
+        r += 4;
+        if (r >= rounds) r -= rounds;
+        left -= 4;
+      }
+      while (left > 0) {
+        const uint4 v = base[r * blockDim.x + threadIdx.x];
+        acc += v.x + v.y + v.z + v.w;
+        if (++r >= rounds) r = 0;
+        --left;
+      }
+    }
+    passes += batch;
+    if (c.passes) {
+      if (passes >= c.passes) break;
+      continue;
+    }
+    if (threadIdx.x == 0 && should_stop(st, c)) s_stop = 1;
+    __syncthreads();
+    if (s_stop) break;
+  }
+  const uint32_t ws = wave_sum_u32(acc);
+  if (lane == 0) s_part[wid] = ws;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t tot = 0;
+    for (uint32_t i = 0; i < wpg; ++i) tot += s_part[i];
+    write_record(c, blockIdx.x, t0, passes, tot, st.flags);
+  }
+}
+
+__global__ void zero_kernel(uint4* p, uint64_t n16, uint8_t* tail, uint32_t ntail) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+    p[i] = make_uint4(0, 0, 0, 0);
+  if (blockIdx.x == 0 && threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
+__global__ void stamp_kernel(uint64_t* slot) {
+  if (threadIdx.x == 0) *slot = dev_now();
+}
+
+}  // namespace
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  const uint64_t n16 = bytes / 16;
+  const uint32_t ntail = (uint32_t)(bytes % 16);
+  uint64_t g = (n16 + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g == 0) g = 1;
+  hipLaunchKernelGGL(zero_kernel, dim3((uint32_t)g), dim3(256), 0, s, (uint4*)p, n16,
+                     (uint8_t*)p + n16 * 16, ntail);
+  return hipGetLastError();
+}
+
+hipError_t launch_stamp(uint64_t* slot, hipStream_t s) {
+  hipLaunchKernelGGL(stamp_kernel, dim3(1), dim3(64), 0, s, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_triad_stressor(const KCtrl& c, const float* b, const float* cc, float* a,
+                                 uint64_t n, uint32_t threads, hipStream_t s, hipEvent_t e0,
+                                 hipEvent_t e1) {
+  return xlaunch(triad_stressor, dim3(c.grid), dim3(threads), 0, s, e0, e1, c, b,
+                               cc, a, n);
+}
+
+hipError_t launch_triad_victim(const float* b, const float* c, float* a, uint64_t n,
+                               uint32_t passes, uint32_t grid, hipStream_t s, hipEvent_t e0,
+                               hipEvent_t e1) {
+  return xlaunch(triad_victim, dim3(grid), dim3(kTriadThreads), 0, s, e0, e1, b,
+                               c, a, n, passes);
+}
+
+hipError_t launch_cache_stressor(const KCtrl& c, const uint32_t* region, uint64_t region_words,
+                                 uint64_t slice_words, uint32_t batch, uint32_t threads,
+                                 hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  return xlaunch(cache_stressor, dim3(c.grid), dim3(threads), 0, s, e0, e1, c,
+                               region, region_words, slice_words, batch);
+}
+
+}  // namespace ci

@@ -1,0 +1,60 @@
+// Host-side state of libcoloc (not part of the C ABI).
+#pragma once
+
+#include <array>
+#include <atomic>
+#include <map>
+#include <thread>
+
+#include "internal.h"
+
+struct ci_ctx {
+  int device = 0;
+  ci_device_info_t info{};
+  ci::HostCtrl* host = nullptr;        // pinned: stop / started words
+  volatile uint64_t* hres = nullptr;   // pinned: stamps and checksums written by kernels
+  uint64_t* part_bits = nullptr;       // device scratch for reductions
+  double* part_sum = nullptr;
+  float* amax_part = nullptr;
+  float* amax_out = nullptr;
+  uint32_t* probe_buf = nullptr;
+  uint32_t nparts = 0;
+  std::map<std::array<uint32_t, 8>, hipStream_t> masked;  // CU-masked streams by mask
+  hipStream_t vstream = nullptr;       // non-blocking stream for shared-placement victims
+  hipEvent_t ev[12] = {};
+  struct ci_stressor* active = nullptr;
+  uint64_t rot = 0;                    // GEMV weight-copy rotation
+};
+
+struct ci_stressor {
+  ci_ctx* ctx = nullptr;
+  ci_resource_t r = CI_RES_HBM;
+  float intensity = 0.0f;
+  int ncu = 0;
+  uint32_t grid = 0;
+  hipStream_t ms = nullptr;            // masked stream the kernel runs on
+  hipStream_t caller = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  ci_stressor_opts_t o{};
+  bool noop = false;
+  bool persistent = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  std::thread feeder;                  // DISPATCH only
+  std::atomic<int> feeder_stop{0};
+  std::atomic<uint64_t> launched{0};
+  hipError_t feeder_err = hipSuccess;
+};
+
+namespace ci {
+constexpr size_t kMaxMaskedStreams = 6;
+int cus_for(const ci_ctx* ctx, double intensity);
+bool mask_covers_all_xcds(const ci_ctx* ctx, const uint32_t mask[8]);
+ci_status_t set_err(ci_status_t st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+hipStream_t masked_stream(ci_ctx* ctx, const uint32_t mask[8]);
+void mask_for(const ci_ctx* ctx, int k, int complement, uint32_t mask[8]);
+ci_status_t launch_victim(ci_ctx* ctx, const ci_victim_desc_t* d, hipStream_t s, hipEvent_t e0,
+                          hipEvent_t e1);
+ci_status_t run_victim(ci_ctx* ctx, const ci_victim_desc_t* d, hipStream_t caller, hipStream_t xs,
+                       ci_victim_result_t* out);
+}  // namespace ci

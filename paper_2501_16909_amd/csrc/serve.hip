@@ -1,0 +1,390 @@
+// Continuous-batching colocation loop and its admission rule.
+//
+// The paper asks a colocation scheduler to decide per kernel, to predict
+// each kernel's slowdown from its per-resource sensitivity and the
+// co-runners' pressure, and to trade a bounded slowdown for utilisation
+// (Section 5.1); it shows single-metric rules (summed achieved occupancy,
+// Section 3 Pitfall 1) mispredicting.  serve_run admits arriving requests
+// FIFO under one of three rules (memory only, summed occupancy, predicted
+// slowdown) and runs admitted requests concurrently on slot streams.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <thread>
+#include <vector>
+
+#include "internal.h"
+#include "runtime.h"
+
+using namespace ci;
+
+namespace {
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+const ci_profile_t* profile_of(const ci_policy_t* p, int kind) {
+  for (int i = 0; i < p->nprofiles; ++i)
+    if (p->profiles[i].kind == kind) return &p->profiles[i];
+  return nullptr;
+}
+
+// Piecewise-linear slowdown curve at intensity x (points at 0, .25, .5, .75, 1).
+double curve_at(const float* s, double x) {
+  x = std::min(1.0, std::max(0.0, x));
+  const double pos = x * (CI_NPOINTS - 1);
+  int i = (int)std::floor(pos);
+  if (i >= CI_NPOINTS - 1) return s[CI_NPOINTS - 1];
+  const double t = pos - i;
+  return s[i] + (s[i + 1] - s[i]) * t;
+}
+
+// Predicted slowdown of job `j` among `group`: product over resources of
+// max(1, curve_r(summed pressure of the others on r)).
+double predict(const std::vector<const ci_profile_t*>& group, size_t j) {
+  double out = 1.0;
+  for (int r = 0; r < CI_RES_COUNT; ++r) {
+    double press = 0.0;
+    for (size_t o = 0; o < group.size(); ++o)
+      if (o != j) press += group[o]->press[r];
+    out *= std::max(1.0, curve_at(group[j]->sens[r], press));
+  }
+  return out;
+}
+
+// First-fit allocator over one device arena (offsets in bytes, 256-aligned).
+class Arena {
+ public:
+  explicit Arena(uint64_t size) : size_(size) { free_[0] = size; }
+  bool alloc(uint64_t bytes, uint64_t* off) {
+    bytes = (bytes + 255) & ~255ull;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const uint64_t rest = it->second - bytes, at = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[at] = rest;
+        used_ += bytes;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(uint64_t off, uint64_t bytes) {
+    bytes = (bytes + 255) & ~255ull;
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  uint64_t largest_free() const {
+    uint64_t m = 0;
+    for (auto& kv : free_) m = std::max(m, kv.second);
+    return m;
+  }
+  uint64_t used() const { return used_; }
+
+ private:
+  uint64_t size_;
+  uint64_t used_ = 0;
+  std::map<uint64_t, uint64_t> free_;
+};
+
+uint64_t elem_bytes(int dt) { return dt == CI_DT_F32 ? 4 : dt == CI_DT_BF16 ? 2 : 1; }
+
+// Bytes a request holds while it runs: operands, output and one FP32
+// staging buffer its inputs are drawn into before conversion.
+uint64_t footprint(const ci_request_t& q) {
+  auto al = [](uint64_t b) { return (b + 255) & ~255ull; };
+  switch (q.kind) {
+    case CI_VICTIM_TRIAD_F32: return 3 * al(q.n * 4);
+    case CI_VICTIM_GEMM: {
+      const uint64_t e = elem_bytes(q.dtype);
+      uint64_t stage = std::max(q.m, q.n) * q.k * 4;
+      if (q.dtype == CI_DT_F32) stage = 0;
+      return al(q.m * q.k * e) + al(q.n * q.k * e) + al(q.m * q.n * 4) + al(stage);
+    }
+    case CI_VICTIM_GEMV: return al(q.n * q.k * 2) + al(q.k * 2) + al(q.n * 4) + al(std::max(q.n * q.k, q.k) * 4);
+    default: return 0;
+  }
+}
+
+struct Running {
+  int idx = -1;
+  uint64_t off = 0, bytes = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, done = nullptr;
+  ci_victim_desc_t d{};
+};
+
+}  // namespace
+
+extern "C" ci_status_t ci_admit(const ci_policy_t* p, const int* running_kinds, int nrun,
+                                int cand_kind, uint64_t cand_bytes, uint64_t free_bytes,
+                                int* admit) {
+  if (!p || !admit || nrun < 0 || (nrun && !running_kinds))
+    return set_err(CI_ERR_INVALID_ARG, "ci_admit: bad argument");
+  *admit = 0;
+  if (cand_bytes > free_bytes || nrun >= p->slots) return CI_OK;
+  if (p->kind == CI_POLICY_NAIVE) {
+    *admit = 1;
+    return CI_OK;
+  }
+  std::vector<const ci_profile_t*> group;
+  for (int i = 0; i < nrun; ++i) {
+    const ci_profile_t* pr = profile_of(p, running_kinds[i]);
+    if (!pr) return set_err(CI_ERR_INVALID_ARG, "ci_admit: no profile for kind %d", running_kinds[i]);
+    group.push_back(pr);
+  }
+  const ci_profile_t* cp = profile_of(p, cand_kind);
+  if (!cp) return set_err(CI_ERR_INVALID_ARG, "ci_admit: no profile for kind %d", cand_kind);
+  group.push_back(cp);
+  if (p->kind == CI_POLICY_USHER) {
+    double occ = 0.0;
+    for (auto* g : group) occ += g->occ;
+    *admit = occ < 1.0;
+    return CI_OK;
+  }
+  if (p->kind != CI_POLICY_SENSITIVITY) return set_err(CI_ERR_INVALID_ARG, "ci_admit: policy %d", p->kind);
+  for (size_t j = 0; j < group.size(); ++j)
+    if (predict(group, j) > p->bound) return CI_OK;
+  *admit = 1;
+  return CI_OK;
+}
+
+#define HIPCHK(call)                                                                            \
+  do {                                                                                          \
+    hipError_t e_ = (call);                                                                     \
+    if (e_ != hipSuccess) return set_err(CI_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+namespace {
+
+// Draw the request's inputs into the arena and launch it on `s`.
+ci_status_t start_request(ci_ctx* ctx, const ci_request_t& q, uint8_t* base, hipStream_t s,
+                          Running& run) {
+  auto al = [](uint64_t b) { return (b + 255) & ~255ull; };
+  ci_victim_desc_t& d = run.d;
+  memset(&d, 0, sizeof(d));
+  d.kind = q.kind;
+  d.dtype = q.dtype;
+  d.m = q.m;
+  d.n = q.n;
+  d.k = q.k;
+  d.passes = 1;
+  d.copies = 1;
+  d.scale_a = d.scale_b = 1.0f;
+  uint8_t* p = base;
+  switch (q.kind) {
+    case CI_VICTIM_TRIAD_F32: {
+      float* b = (float*)p;
+      float* c = (float*)(p + al(q.n * 4));
+      float* a = (float*)(p + 2 * al(q.n * 4));
+      HIPCHK(launch_fill_uniform(b, q.n, q.seed, s));
+      HIPCHK(launch_fill_uniform(c, q.n, q.seed + 1, s));
+      d.a = b;
+      d.b = c;
+      d.out = a;
+      break;
+    }
+    case CI_VICTIM_GEMM: {
+      const uint64_t e = elem_bytes(q.dtype);
+      uint8_t* A = p;
+      uint8_t* B = A + al(q.m * q.k * e);
+      float* C = (float*)(B + al(q.n * q.k * e));
+      float* stage = (float*)((uint8_t*)C + al(q.m * q.n * 4));
+      if (q.dtype == CI_DT_F32) {
+        HIPCHK(launch_fill_uniform((float*)A, q.m * q.k, q.seed, s));
+        HIPCHK(launch_fill_uniform((float*)B, q.n * q.k, q.seed + 1, s));
+      } else if (q.dtype == CI_DT_BF16) {
+        HIPCHK(launch_fill_uniform(stage, q.m * q.k, q.seed, s));
+        HIPCHK(launch_to_bf16(stage, q.m * q.k, (uint16_t*)A, s));
+        HIPCHK(launch_fill_uniform(stage, q.n * q.k, q.seed + 1, s));
+        HIPCHK(launch_to_bf16(stage, q.n * q.k, (uint16_t*)B, s));
+      } else {
+        return set_err(CI_ERR_UNSUPPORTED, "serve: FP8 GEMM requests are not served");
+      }
+      d.a = A;
+      d.b = B;
+      d.out = C;
+      break;
+    }
+    case CI_VICTIM_GEMV: {
+      uint16_t* W = (uint16_t*)p;
+      uint16_t* x = (uint16_t*)(p + al(q.n * q.k * 2));
+      float* y = (float*)((uint8_t*)x + al(q.k * 2));
+      float* stage = (float*)((uint8_t*)y + al(q.n * 4));
+      HIPCHK(launch_fill_uniform(stage, q.n * q.k, q.seed, s));
+      HIPCHK(launch_to_bf16(stage, q.n * q.k, W, s));
+      HIPCHK(launch_fill_uniform(stage, q.k, q.seed + 1, s));
+      HIPCHK(launch_to_bf16(stage, q.k, x, s));
+      d.a = W;
+      d.b = x;
+      d.out = y;
+      break;
+    }
+    default: return set_err(CI_ERR_INVALID_ARG, "serve: request kind %d", q.kind);
+  }
+  ci_status_t st = launch_victim(ctx, &d, s, run.ev0, run.ev1);
+  if (st != CI_OK) return st;
+  HIPCHK(hipEventRecord(run.done, s));
+  return CI_OK;
+}
+
+}  // namespace
+
+extern "C" ci_status_t serve_run(ci_ctx_t* ctx, const ci_request_t* trace, int n,
+                                 const ci_policy_t* p, ci_served_t* out) {
+  if (!ctx || !p || n < 0 || (n && (!trace || !out)))
+    return set_err(CI_ERR_INVALID_ARG, "serve_run: bad argument");
+  if (p->slots < 1 || p->slots > 8) return set_err(CI_ERR_INVALID_ARG, "serve_run: slots must be in [1, 8]");
+  if (p->hbm_budget < 4096) return set_err(CI_ERR_INVALID_ARG, "serve_run: HBM budget too small");
+  for (int i = 0; i < n; ++i) {
+    const ci_request_t& q = trace[i];
+    if (i && q.arrival_s < trace[i - 1].arrival_s)
+      return set_err(CI_ERR_INVALID_ARG, "serve_run: trace not sorted by arrival");
+    if (q.kind == CI_VICTIM_GEMM && (q.dtype != CI_DT_BF16 && q.dtype != CI_DT_F32))
+      return set_err(CI_ERR_INVALID_ARG, "serve_run: request %d dtype", i);
+    if (q.kind == CI_VICTIM_GEMM && ((q.k * elem_bytes(q.dtype)) % 16 || !q.m || !q.n || !q.k))
+      return set_err(CI_ERR_INVALID_ARG, "serve_run: request %d GEMM shape", i);
+    if (q.kind == CI_VICTIM_GEMV && (q.k % 8 || !q.n || !q.k))
+      return set_err(CI_ERR_INVALID_ARG, "serve_run: request %d GEMV shape", i);
+    if (q.kind == CI_VICTIM_TRIAD_F32 && !q.n)
+      return set_err(CI_ERR_INVALID_ARG, "serve_run: request %d empty triad", i);
+    if (q.kind < 0 || q.kind > CI_VICTIM_GEMV) return set_err(CI_ERR_INVALID_ARG, "serve_run: request %d kind", i);
+    if (footprint(q) > p->hbm_budget)
+      return set_err(CI_ERR_OOM, "serve_run: request %d needs %llu bytes > budget", i,
+                     (unsigned long long)footprint(q));
+    if (p->kind != CI_POLICY_NAIVE && !profile_of(p, q.kind))
+      return set_err(CI_ERR_INVALID_ARG, "serve_run: no profile for request %d kind %d", i, q.kind);
+  }
+  if (ctx->active) return set_err(CI_ERR_BUSY, "serve_run: a stressor is running");
+  HIPCHK(hipSetDevice(ctx->device));
+  uint8_t* arena_base = nullptr;
+  HIPCHK(hipMalloc((void**)&arena_base, p->hbm_budget));
+  // per-slot streams, events and checksum scratch
+  const int S = p->slots;
+  std::vector<hipStream_t> streams(S, nullptr);
+  std::vector<Running> slot(S);
+  uint64_t* part_bits = nullptr;
+  double* part_sum = nullptr;
+  uint64_t* res = nullptr;  // pinned: [slot][2]
+  const uint32_t nparts = 256;
+  ci_status_t st = CI_OK;
+  auto fail = [&](ci_status_t s2) { if (st == CI_OK) st = s2; };
+  if (hipMalloc((void**)&part_bits, (size_t)S * nparts * 8) != hipSuccess ||
+      hipMalloc((void**)&part_sum, (size_t)S * nparts * 8) != hipSuccess ||
+      hipHostMalloc((void**)&res, (size_t)S * 2 * 8, hipHostMallocCoherent) != hipSuccess)
+    fail(set_err(CI_ERR_OOM, "serve_run: scratch"));
+  for (int s = 0; s < S && st == CI_OK; ++s) {
+    if (hipStreamCreateWithFlags(&streams[s], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreate(&slot[s].ev0) != hipSuccess || hipEventCreate(&slot[s].ev1) != hipSuccess ||
+        hipEventCreateWithFlags(&slot[s].done, hipEventDisableTiming) != hipSuccess)
+      fail(set_err(CI_ERR_HIP, "serve_run: stream/event creation"));
+  }
+  Arena arena(p->hbm_budget);
+  std::deque<int> queue;
+  std::vector<int> run_kinds;
+  int next_arrival = 0, done = 0;
+  const double t0 = now_s();
+  for (int i = 0; i < n; ++i) {
+    memset(&out[i], 0, sizeof(out[i]));
+    out[i].arrival_s = trace[i].arrival_s;
+    out[i].slot = -1;
+  }
+  while (st == CI_OK && done < n) {
+    const double t = now_s() - t0;
+    while (next_arrival < n && trace[next_arrival].arrival_s <= t) queue.push_back(next_arrival++);
+    bool progressed = false;
+    // retire finished requests
+    for (int s = 0; s < S; ++s) {
+      Running& r = slot[s];
+      if (r.idx < 0) continue;
+      hipError_t q = hipEventQuery(r.done);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess) {
+        fail(set_err(CI_ERR_HIP, "serve_run: request %d: %s", r.idx, hipGetErrorString(q)));
+        break;
+      }
+      ci_served_t& o = out[r.idx];
+      o.end_s = now_s() - t0;
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, r.ev0, r.ev1);
+      o.service_ns = (double)ms * 1e6;
+      o.checksum_bits = res[2 * s];
+      memcpy(&o.sum_f64, (const void*)&res[2 * s + 1], 8);
+      o.status = CI_OK;
+      arena.release(r.off, r.bytes);
+      r.idx = -1;
+      ++done;
+      progressed = true;
+    }
+    if (st != CI_OK) break;
+    // admit FIFO, no bypass
+    while (!queue.empty()) {
+      int s = -1;
+      run_kinds.clear();
+      for (int k = 0; k < S; ++k) {
+        if (slot[k].idx < 0) { if (s < 0) s = k; }
+        else run_kinds.push_back(trace[slot[k].idx].kind);
+      }
+      if (s < 0) break;
+      const ci_request_t& q = trace[queue.front()];
+      const uint64_t bytes = (footprint(q) + 255) & ~255ull;
+      int ok = 0;
+      ci_status_t a = ci_admit(p, run_kinds.data(), (int)run_kinds.size(), q.kind, bytes,
+                               arena.largest_free(), &ok);
+      if (a != CI_OK) { fail(a); break; }
+      if (!ok) break;
+      uint64_t off = 0;
+      if (!arena.alloc(bytes, &off)) break;
+      Running& r = slot[s];
+      r.idx = queue.front();
+      r.off = off;
+      r.bytes = bytes;
+      queue.pop_front();
+      out[r.idx].admit_s = now_s() - t0;
+      out[r.idx].slot = s;
+      ci_status_t ls = start_request(ctx, q, arena_base + off, streams[s], r);
+      if (ls == CI_OK) {
+        hipError_t e = launch_checksum_f32((const float*)r.d.out,
+                                           q.kind == CI_VICTIM_GEMM ? q.m * q.n : q.n,
+                                           part_bits + (size_t)s * nparts, part_sum + (size_t)s * nparts,
+                                           nparts, &res[2 * s], (double*)&res[2 * s + 1], streams[s]);
+        if (e == hipSuccess) e = hipEventRecord(r.done, streams[s]);
+        if (e != hipSuccess) ls = set_err(CI_ERR_HIP, "serve_run: checksum: %s", hipGetErrorString(e));
+      }
+      if (ls != CI_OK) { fail(ls); break; }
+      progressed = true;
+    }
+    if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
+  // drain whatever is still on the device before freeing
+  for (int s = 0; s < S; ++s)
+    if (streams[s]) (void)hipStreamSynchronize(streams[s]);
+  for (int s = 0; s < S; ++s) {
+    if (slot[s].ev0) (void)hipEventDestroy(slot[s].ev0);
+    if (slot[s].ev1) (void)hipEventDestroy(slot[s].ev1);
+    if (slot[s].done) (void)hipEventDestroy(slot[s].done);
+    if (streams[s]) (void)hipStreamDestroy(streams[s]);
+  }
+  if (res) (void)hipHostFree(res);
+  if (part_bits) (void)hipFree(part_bits);
+  if (part_sum) (void)hipFree(part_sum);
+  (void)hipFree(arena_base);
+  return st;
+}

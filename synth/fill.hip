@@ -15,13 +15,19 @@ __device__ __forceinline__ uint64_t splitmix_word(uint64_t seed, uint64_t i) {
   return z ^ (z >> 31);
 }
 
+__device__ __forceinline__ float uniform_of(uint64_t w) {
+#pragma clang fp contract(off)
+  const float k = (float)(uint32_t)(w >> 40);  // 24-bit integer: exact
+  const float scaled = k * 0x1.0p-23f;          // exact
+  return scaled - 1.0f;                         // exact
+}
+
 __global__ void __launch_bounds__(256) fill_uniform_f32(float* __restrict__ dst, uint64_t n,
                                                         uint64_t seed, uint64_t start) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     const uint64_t w = splitmix_word(seed, start + i);
-    const float k = (float)(uint32_t)(w >> 40);  // 24-bit integer: exact
-    dst[i] = __fadd_rn(__fmul_rn(k, 0x1.0p-23f), -1.0f);
+    dst[i] = uniform_of(w);
   }
 }
 

@@ -1,0 +1,196 @@
+"""GPU parity of the core path: placement under CU masks, the device input
+fill, the triad victim, the HBM (triad) stressor, colocation and the
+zero-intensity invariant.  Every comparison is against the CPU oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(dev):
+    from paper_2501_16909_amd import coloc
+    c = coloc.Context(0)
+    yield c
+    c.close()
+
+
+def _t(x, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+def test_device_info(ctx):
+    info = ctx.info
+    assert info.num_cus == 256, info.num_cus
+    assert info.arch.decode().startswith("gfx950")
+    assert info.wave_size == 64
+    assert info.wall_clock_khz > 0
+    assert ctx.peak("hbm") == 8.0e12
+
+
+def test_placement_full_and_single_bits(ctx):
+    locs = ctx.probe_placement(None, 8192)
+    xcc = (locs >> 8) & 0xF
+    assert set(xcc.tolist()) == set(range(8))
+    assert len(set(locs.tolist())) == 256
+    # eight consecutive CU-mask bits 8j..8j+7 select one CU on every XCD:
+    # bit b lands on XCD b mod 8
+    seen = set()
+    for j in (0, 1, 5, 31):
+        mask = [0] * 8
+        for b in range(8 * j, 8 * j + 8):
+            mask[b // 32] |= 1 << (b % 32)
+        l = ctx.probe_placement(mask, 512)
+        cus = set(l.tolist())
+        assert len(cus) == 8, (j, sorted(cus))
+        assert sorted((c >> 8) & 0xF for c in cus) == list(range(8))
+        assert not (cus & seen)
+        seen |= cus
+    # a mask that leaves an XCD without CUs is refused
+    from paper_2501_16909_amd import coloc
+    with pytest.raises(coloc.CiError) as ei:
+        ctx.probe_placement([1, 0, 0, 0, 0, 0, 0, 0], 64)
+    assert ei.value.status == 1
+
+
+@pytest.mark.parametrize("x", [1 / 32, 0.25, 0.5, 0.75, 0.3])
+def test_intensity_masks_are_balanced(ctx, x):
+    mask, ncu = ctx.cu_mask(x)
+    assert ncu == 8 * round(32 * x)
+    l = ctx.probe_placement(mask, 16384)
+    cus = set(l.tolist())
+    assert len(cus) == ncu
+    per_xcd = np.bincount([(c >> 8) & 0xF for c in cus], minlength=8)
+    assert per_xcd.max() == per_xcd.min() == ncu // 8
+    comp, nc = ctx.cu_mask(x, complement=True)
+    lc = set(ctx.probe_placement(comp, 16384).tolist())
+    assert len(lc) == nc and not (lc & cus)
+
+
+def test_device_fill_matches_host_generator(ctx, dev):
+    import torch
+    n = (1 << 20) + 77
+    t = torch.empty(n, dtype=torch.float32, device=dev)
+    synth.device_fill_uniform_f32(t.data_ptr(), n, 12345, start=5)
+    torch.cuda.synchronize()
+    assert np.array_equal(t.cpu().numpy().view(np.uint32),
+                          synth.uniform_f32(12345, n, start=5).view(np.uint32))
+    w = torch.empty(n, dtype=torch.int32, device=dev)
+    synth.device_fill_u32(w.data_ptr(), n, 999)
+    torch.cuda.synchronize()
+    assert np.array_equal(w.cpu().numpy().view(np.uint32), synth.u32(999, n))
+
+
+@pytest.mark.parametrize("n,passes", [(0, 1), (1, 1), (1023, 1), (1024, 2), ((1 << 20) + 333, 3),
+                                      (1 << 22, 1)])
+def test_triad_victim_matches_oracle(ctx, dev, n, passes):
+    import torch
+    b = synth.uniform_f32(synth.seed_for(0, synth.BUF_B), n)
+    c = synth.uniform_f32(synth.seed_for(0, synth.BUF_C), n)
+    tb, tc = _t(b, dev), _t(c, dev)
+    ta = torch.full((max(n, 1),), float("nan"), device=dev)[:n]
+    r = ctx.victim_triad(tb, tc, ta, passes=passes)
+    want = oracle.triad_f32(b, c)
+    got = ta.cpu().numpy()
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+    assert r.checksum_bits == oracle.bitsum_u32(want)
+    assert oracle.rel_err_sum(r.sum_f64, want) <= 1e-6
+    assert r.time_ns > 0 or n == 0
+    assert r.t_end >= r.t_begin
+
+
+def test_triad_sum_relative_error_full_size(ctx, dev):
+    """N = 2^30 (4 GiB per array): outputs checked on sampled indices
+    regenerated from the counter-form generator; the FP64 checksum against
+    the closed-form identity sum a ~ sum b + 3 sum c."""
+    import torch
+    n = 1 << 30
+    sb, sc = synth.seed_for(1, synth.BUF_B), synth.seed_for(1, synth.BUF_C)
+    tb = torch.empty(n, dtype=torch.float32, device=dev)
+    tc = torch.empty(n, dtype=torch.float32, device=dev)
+    synth.device_fill_uniform_f32(tb.data_ptr(), n, sb)
+    synth.device_fill_uniform_f32(tc.data_ptr(), n, sc)
+    torch.cuda.synchronize()
+    ta = torch.empty_like(tb)
+    r = ctx.victim_triad(tb, tc, ta, passes=1)
+    idx = np.unique(np.concatenate([np.arange(64), n - 1 - np.arange(64),
+                                    (synth.words(77, 4096) % np.uint64(n)).astype(np.int64)]))
+    want = oracle.triad_f32(synth.uniform_f32_at(sb, idx), synth.uniform_f32_at(sc, idx))
+    got = ta[torch.from_numpy(idx).to(dev)].cpu().numpy()
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+    # device sums of the inputs and the output obey the triad identity
+    bits_b, sum_b = ctx.checksum(tb)
+    bits_c, sum_c = ctx.checksum(tc)
+    absum = float((3 * tc.abs().double().sum() + ta.abs().double().sum()).item())
+    assert abs(r.sum_f64 - (sum_b + 3 * sum_c)) <= 2.0 ** -24 * absum * 1.01 + 1e-6 * abs(r.sum_f64)
+    del tb, tc, ta
+    torch.cuda.empty_cache()
+
+
+def _hbm_buffers(dev, n, cfg=0):
+    b = synth.uniform_f32(synth.seed_for(cfg, synth.BUF_B2), n)
+    c = synth.uniform_f32(synth.seed_for(cfg, synth.BUF_C2), n)
+    import torch
+    return b, c, _t(b, dev), _t(c, dev), torch.empty(n, dtype=torch.float32, device=dev)
+
+
+@pytest.mark.parametrize("x,passes,n", [(1.0, 1, (1 << 22) + 5), (0.5, 3, 1 << 20), (1 / 32, 2, 5000)])
+def test_hbm_stressor_fixed_passes(ctx, dev, x, passes, n):
+    b, c, tb, tc, ta = _hbm_buffers(dev, n)
+    st = ctx.stressor("hbm", x, src0=tb, src1=tc, dst=ta, n=n, passes=passes)
+    rep = st.stop()
+    want = oracle.triad_f32(b, c)
+    assert np.array_equal(ta.cpu().numpy().view(np.uint32), want.view(np.uint32))
+    ncu = 8 * round(32 * x)
+    assert rep.grid == ncu * 4 and rep.wg_reported == rep.grid
+    chunks = (n + 1023) // 1024
+    assert rep.work == passes * chunks
+    assert rep.units == 12.0 * n * passes
+    assert rep.distinct_cus == ncu
+
+
+def test_hbm_stressor_persistent_colocated(ctx, dev):
+    n_v = 1 << 22
+    b = synth.uniform_f32(synth.seed_for(0, synth.BUF_B), n_v)
+    c = synth.uniform_f32(synth.seed_for(0, synth.BUF_C), n_v)
+    tb, tc = _t(b, dev), _t(c, dev)
+    import torch
+    ta = torch.empty_like(tb)
+    alone = ctx.victim_triad(tb, tc, ta, passes=20)
+    sb, sc, tsb, tsc, tsa = _hbm_buffers(dev, 1 << 24)
+    with ctx.stressor("hbm", 1.0, src0=tsb, src1=tsc, dst=tsa, n=1 << 24) as st:
+        col = ctx.victim_triad(tb, tc, ta, passes=20)
+    rep = st.report
+    assert not rep.timed_out
+    assert col.checksum_bits == alone.checksum_bits
+    assert rep.wg_reported == rep.grid
+    assert rep.t_last_start <= col.t_begin and rep.t_first_end >= col.t_end, "stressor window"
+    assert col.time_ns > 1.05 * alone.time_ns, (alone.time_ns, col.time_ns)
+    want = oracle.triad_f32(sb, sc)
+    assert np.array_equal(tsa.cpu().numpy().view(np.uint32), want.view(np.uint32))
+    print(f"triad alone {alone.time_ns/1e3:.1f} us colocated {col.time_ns/1e3:.1f} us; "
+          f"stressor {rep.achieved/1e9:.0f} GB/s")
+
+
+def test_zero_intensity_invariant(ctx, dev):
+    """A stressor at intensity 0 launches nothing: slowdown 1.00 +- 0.02."""
+    import torch
+    n = 1 << 22
+    b = synth.uniform_f32(synth.seed_for(0, synth.BUF_B), n)
+    c = synth.uniform_f32(synth.seed_for(0, synth.BUF_C), n)
+    tb, tc = _t(b, dev), _t(c, dev)
+    ta = torch.empty_like(tb)
+    _, _, tsb, tsc, tsa = _hbm_buffers(dev, 1 << 22)
+    d = ctx.triad_desc(tb, tc, ta, passes=10)
+    cells = ctx.measure_sensitivity(d, ["hbm"], [dict(src0=tsb, src1=tsc, dst=tsa, n=1 << 22)], [0.0, 1.0],
+                                    reps=15, warmups=3)
+    z, full = cells
+    assert abs(z["slowdown"] - 1.0) <= 0.02, z
+    assert z["output_equal"] and full["output_equal"]
+    assert full["window_covered"], full
+    assert full["slowdown"] > 1.1, full
+    print("cells:", cells)

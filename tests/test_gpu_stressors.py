@@ -1,0 +1,255 @@
+"""GPU parity of every stressor kernel against the oracle, in the fixed-pass
+form (exact work) and in the persistent form (work as reported)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(dev):
+    from paper_2501_16909_amd import coloc
+    c = coloc.Context(0)
+    yield c
+    c.close()
+
+
+def _t(x, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+# ------------------------------------------------------------ cache loops
+@pytest.mark.parametrize("res,words,x,passes", [
+    ("vl1d", 4096, 1.0, 7),            # 16 KiB
+    ("l2", 1 << 19, 0.25, 2),          # 2 MiB
+    ("mall", 1 << 25, 1.0, 1),         # 128 MiB, per-WG slices
+    ("mall", 1 << 22, 0.5, 3),
+])
+def test_cache_stressor_fixed(ctx, dev, res, words, x, passes):
+    w = synth.u32(synth.seed_for(1, synth.BUF_CACHE), words)
+    tw = _t(w.view(np.int32), dev)
+    st = ctx.stressor(res, x, src0=tw, n=words, passes=passes)
+    rep = st.stop()
+    rec = st.records()
+    assert rep.wg_reported == rep.grid and np.all(rec["work"] == passes)
+    if res == "mall":
+        span = words // rep.grid
+        span -= span % 1024
+        for g in range(rep.grid):
+            lo = (g * span) % words
+            s = oracle.region_sum_u32(w, lo, lo + span)
+            assert rec["check"][g] == (passes * s) % 2 ** 32, g
+        assert rep.units == 4.0 * span * passes * rep.grid
+    else:
+        exp = oracle.cache_wg_expected(w, rec["work"])
+        assert np.array_equal(rec["check"].astype(np.uint32), exp)
+        assert rep.units == 4.0 * words * passes * rep.grid
+
+
+@pytest.mark.parametrize("res,words", [("vl1d", 4096), ("l2", 1 << 19), ("mall", 1 << 25)])
+def test_cache_stressor_persistent(ctx, dev, res, words):
+    import time
+    w = synth.u32(synth.seed_for(1, synth.BUF_CACHE), words)
+    tw = _t(w.view(np.int32), dev)
+    with ctx.stressor(res, 1.0, src0=tw, n=words) as st:
+        time.sleep(0.02)
+    rep = st.report
+    rec = st.records()
+    assert not rep.timed_out and rep.wg_reported == rep.grid
+    assert np.all(rec["work"] > 0)
+    assert np.all(rec["flags"] & 2)          # every group saw the stop flag
+    if res != "mall":
+        exp = oracle.cache_wg_expected(w, rec["work"])
+        assert np.array_equal(rec["check"].astype(np.uint32), exp)
+    print(f"{res}: {rep.achieved/1e12:.2f} TB/s ({rep.pct_of_peak:.1f}% of peak) over "
+          f"{rep.window_ns/1e6:.2f} ms")
+
+
+# -------------------------------------------------------------------- LDS
+@pytest.mark.parametrize("vec,stride", [(1, 1), (1, 2), (1, 32), (2, 1), (4, 1), (4, 3)])
+def test_lds_stressor_fixed(ctx, dev, vec, stride):
+    w = synth.u32(synth.seed_for(1, synth.BUF_LDS), 8192)
+    st = ctx.stressor("lds", 0.25, src0=_t(w.view(np.int32), dev), vec=vec, knob=stride, passes=3)
+    rep = st.stop()
+    rec = st.records()
+    exp = oracle.lds_wg_expected(w, vec, stride, waves=4, passes=rec["work"])
+    assert np.all(rec["work"] == 3)
+    assert np.array_equal(rec["check"].astype(np.uint32), exp)
+    assert rep.units == 3 * rep.grid * 4 * 64 * 8192 * 4 * 2
+
+
+# ------------------------------------------------------------------- VALU
+@pytest.mark.parametrize("ilp,iters,passes,x", [(1, 4096, 1, 0.125), (2, 100, 3, 0.25), (4, 4096, 2, 0.5),
+                                                 (8, 4096, 1, 1.0), (8, 13, 1, 1 / 32)])
+def test_valu_stressor_fixed(ctx, dev, ilp, iters, passes, x):
+    import torch
+    ncu = 8 * round(32 * x)
+    threads = ncu * 4 * 256
+    out = torch.empty(threads * ilp, dtype=torch.float32, device=dev)
+    a, b = 1 - 2.0 ** -12, 2.0 ** -12
+    st = ctx.stressor("valu_f32", x, dst=out, knob=ilp, iters=iters, passes=passes, fa=a, fb=b)
+    rep = st.stop()
+    got = out.cpu().numpy().reshape(threads, ilp)
+    sel = np.unique(np.concatenate([np.arange(0, threads, 97), [threads - 1]]))
+    want = oracle.valu_outputs(sel, ilp, a, b, iters * passes)
+    assert np.array_equal(got[sel].view(np.uint32), want.view(np.uint32))
+    assert rep.units == 2.0 * threads * ilp * iters * passes
+
+
+def test_valu_closed_form_counts(ctx, dev):
+    """fa = 1, fb = 1 from x0: each chain adds exactly one per step."""
+    import torch
+    threads = 8 * 4 * 256
+    out = torch.empty(threads * 4, dtype=torch.float32, device=dev)
+    st = ctx.stressor("valu_f32", 1 / 32, dst=out, knob=4, iters=1000, passes=2, fa=1.0, fb=1.0)
+    st.stop()
+    x0 = oracle.valu_start_values(np.arange(threads), 4)
+    assert np.array_equal(out.cpu().numpy().reshape(threads, 4), x0 + np.float32(2000))
+
+
+# ------------------------------------------------------------------- MFMA
+def _mfma_operands(dtype, kind):
+    k = {"f32": 2, "bf16": 16, "fp8": 64}[dtype]
+    if kind == "ones":
+        a = np.ones((32, k), np.float32)
+        b = np.ones((k, 32), np.float32)
+    else:
+        a = synth.normal_f32(synth.seed_for(3, synth.BUF_MFMA), 32 * k).reshape(32, k)
+        b = synth.normal_f32(synth.seed_for(3, synth.BUF_MFMA) + 1, k * 32).reshape(k, 32)
+    if dtype == "f32":
+        return a, b, a, b
+    if dtype == "bf16":
+        qa, qb = oracle.f32_to_bf16(a), oracle.f32_to_bf16(b)
+        return qa.view(np.int16), qb.view(np.int16), oracle.bf16_to_f64(qa), oracle.bf16_to_f64(qb)
+    qa = oracle.f32_to_e4m3(np.clip(a, -448, 448))
+    qb = oracle.f32_to_e4m3(np.clip(b, -448, 448))
+    return qa, qb, oracle.e4m3_to_f64(qa), oracle.e4m3_to_f64(qb)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+@pytest.mark.parametrize("kind", ["ones", "normal"])
+def test_mfma_stressor_fixed(ctx, dev, dtype, kind):
+    import torch
+    da, db, fa, fb = _mfma_operands(dtype, kind)
+    iters, passes, x, accs = 100, 2, 0.125, 4
+    ncu = 8 * round(32 * x)
+    waves = ncu * 2 * 4
+    out = torch.empty(waves * accs * 1024, dtype=torch.float32, device=dev)
+    st = ctx.stressor(f"mfma_{dtype}", x, src0=_t(da, dev), src1=_t(db, dev), dst=out,
+                      knob=accs, iters=iters, passes=passes)
+    rep = st.stop()
+    tiles = out.cpu().numpy().reshape(waves * accs, 32, 32)
+    total = iters * passes
+    want = oracle.mfma_tile_expected(fa, fb, total)
+    if kind == "ones":
+        assert np.all(tiles == want), (dtype, np.unique(tiles)[:5])
+    else:
+        absprod = total * (np.abs(fa) @ np.abs(fb))
+        k = fa.shape[1]
+        # each step: k exact products summed in FP32, then added to |acc| <= absprod.
+        # The matrix core's internal rounding is not specified: the bound takes
+        # faithful rounding (error below one ulp, u = 2^-23), which covers
+        # round-to-nearest (2^-24) as well.
+        bound = oracle.accumulation_bound(k + total, absprod, unit_roundoff=2.0 ** -23)
+        err = np.abs(tiles - want[None])
+        print(f"{dtype}: max err/bound = {float((err / bound[None]).max()):.3f}")
+        assert np.all(err <= bound[None]), (dtype, float(err.max()), float(bound.max()))
+        assert np.all(tiles == tiles[0:1])   # every wave and accumulator agree bit for bit
+    assert rep.units == waves * accs * total * 2.0 * 32 * 32 * fa.shape[1]
+
+
+# ---------------------------------------------------------- pointer chase
+@pytest.mark.parametrize("n,chains,hops,passes,x", [(1 << 12, 1, 4096, 1, 1 / 32),
+                                                    (1 << 20, 4, 100, 3, 0.25),
+                                                    (1 << 24, 8, 64, 1, 1.0)])
+def test_chase_stressor_fixed(ctx, dev, n, chains, hops, passes, x):
+    import torch
+    nxt = synth.random_cycle_u32(synth.seed_for(1, synth.BUF_CHASE), n)
+    ncu = 8 * round(32 * x)
+    q = ncu * 4 * 256 * chains
+    end = torch.empty(q, dtype=torch.int32, device=dev)
+    st = ctx.stressor("ptrchase", x, src0=_t(nxt.view(np.int32), dev), n=n, dst=end, knob=chains,
+                      iters=hops, passes=passes)
+    rep = st.stop()
+    starts = oracle.chase_starts(q, n)
+    sel = np.unique(np.concatenate([np.arange(0, q, max(1, q // 2000)), [q - 1]]))
+    want = oracle.chase_u32(nxt, starts[sel], hops * passes)
+    got = end.cpu().numpy().view(np.uint32)[sel]
+    assert np.array_equal(got, want)
+    if n == 4096 and hops * passes == n:
+        assert np.array_equal(got, starts[sel].astype(np.uint32))   # a full cycle returns
+    assert rep.units == q // chains * chains * hops * passes
+
+
+# --------------------------------------------------------- dispatch / hog
+def test_dispatch_counts_every_workgroup(ctx, dev):
+    import torch
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    st = ctx.stressor("dispatch", 1.0, dst=cnt, iters=1000000, passes=2)
+    rep = st.stop()
+    assert int(cnt.item()) == 2000000
+    assert rep.units == 2e6
+    st = ctx.stressor("dispatch", 0.5, iters=1000000, passes=1)   # empty kernel, timing form
+    rep = st.stop()
+    assert rep.kernel_ns > 0
+
+
+def test_dispatch_persistent_feeder(ctx, dev):
+    import time
+    import torch
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    with ctx.stressor("dispatch", 1.0, dst=cnt, iters=100000) as st:
+        time.sleep(0.05)
+    rep = st.report
+    assert int(cnt.item()) == rep.units and rep.units >= 100000
+    print(f"dispatch: {rep.units/ (rep.kernel_ns*1e-9) / 1e6:.0f} M WG/s")
+
+
+def test_occupancy_hog_holds_cus(ctx, dev):
+    import time
+    with ctx.stressor("occupancy", 0.5, knob=64) as st:
+        time.sleep(0.01)
+    rep = st.report
+    rec = st.records()
+    assert rep.wg_reported == rep.grid == 128 and rep.distinct_cus >= 64
+    assert np.all(rec["flags"] & 2) and np.all(rec["work"] > 0)
+    assert np.all(rec["check"] == 64 * 1024 // 4 - 1)
+
+
+def test_stressor_deadline_fires_without_stop(ctx, dev):
+    """The host never raises the flag before the deadline: every work-group
+    exits on its own deadline and the report says so."""
+    import time
+    w = synth.u32(5, 4096)
+    st = ctx.stressor("vl1d", 0.125, src0=_t(w.view(np.int32), dev), n=4096, deadline_ms=30)
+    time.sleep(0.2)
+    rep = st.stop(raise_on_timeout=False)
+    assert rep.timed_out and rep.status == 4
+    rec = st.records()
+    assert np.all(rec["flags"] & 1)
+    exp = oracle.cache_wg_expected(w, rec["work"])
+    assert np.array_equal(rec["check"].astype(np.uint32), exp)
+
+
+def test_invalid_arguments_rejected(ctx, dev):
+    from paper_2501_16909_amd import coloc
+    w = _t(synth.u32(5, 4096).view(np.int32), dev)
+    for bad in (dict(resource="hbm", x=0.5),                        # missing operands
+                dict(resource="l2", x=0.5, src0=w, n=1000),         # span not a multiple
+                dict(resource="valu_f32", x=0.5, dst=w, knob=3),    # bad ILP
+                dict(resource="lds", x=0.5, src0=w, vec=3)):
+        r, x = bad.pop("resource"), bad.pop("x")
+        with pytest.raises(coloc.CiError) as ei:
+            ctx.stressor(r, x, **bad)
+        assert ei.value.status == 1
+    with pytest.raises(coloc.CiError):
+        ctx.stressor("hbm", 1.5)
+    with pytest.raises(coloc.CiError):
+        ctx.stressor("hbm", float("nan"))
+    # a zero-intensity stressor is a valid no-op
+    rep = ctx.stressor("hbm", 0.0).stop()
+    assert rep.grid == 0 and rep.ncu == 0

@@ -326,7 +326,8 @@ def test_slowdown_definition_against_paper_table1():
 
 # ------------------------------------------------------------- admission
 def _job(sens1, press, nbytes=1, occ=0.1):
-    return {"sens": [(1.0, s) for s in sens1], "press": press, "bytes": nbytes, "occ": occ}
+    curves = [[1.0 + (s - 1.0) * t for t in oracle.SENS_POINTS] for s in sens1]
+    return {"sens": curves, "press": press, "bytes": nbytes, "occ": occ}
 
 
 def test_admission_rules():
@@ -344,5 +345,10 @@ def test_admission_rules():
     assert oracle.admit("sensitivity", [quiet], fragile, 10, 1.5, 4)
     # unbounded: sensitivity == naive
     assert oracle.admit("sensitivity", [hog, hog], fragile, 10, math.inf, 4)
-    # linear interpolation of the curve at half pressure: 1 + (3-1)*0.5 = 2
-    assert oracle.predicted_slowdown([(1.0, 3.0)], [0.5]) == 2.0
+    # piecewise-linear interpolation between the measured points
+    assert oracle.predicted_slowdown([[1.0, 1.5, 2.0, 2.5, 3.0]], [0.5]) == 2.0
+    assert oracle.predicted_slowdown([[1.0, 1.0, 1.0, 2.0, 4.0]], [0.875]) == 3.0
+    # pressure is clipped to [0, 1]; slowdowns below 1 count as 1; product over resources
+    assert oracle.predicted_slowdown([[1.0, 1.0, 1.0, 1.0, 2.0]], [5.0]) == 2.0
+    assert oracle.predicted_slowdown([[0.9] * 5, [2.0] * 5], [0.3, 0.3]) == 2.0
+    assert oracle.predicted_slowdown([[1.5] * 5, [2.0] * 5], [0.3, 0.3]) == 3.0
