@@ -180,7 +180,9 @@ typedef struct ci_stressor_opts {
                             in vectors; MFMA: independent accumulators (1-4);
                             PTRCHASE: chains per lane (1-8); OCCUPANCY: LDS
                             KiB held per WG; 0 = default                     */
-  uint32_t vec;          /* LDS: vector width in 32-bit words (1, 2, 4)      */
+  uint32_t vec;          /* LDS: vector width in 32-bit words (1, 2, 4);
+                            HBM: 0 = streaming (non-temporal) accesses,
+                            1 = ordinary cached accesses                     */
   uint64_t passes;       /* 0 = run until stressor_stop; > 0 = exactly this
                             many passes per work-group, then exit            */
   uint64_t iters;        /* VALU: FMA steps per pass (default 4096); MFMA:

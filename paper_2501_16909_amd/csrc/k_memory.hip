@@ -41,6 +41,7 @@ __device__ __forceinline__ vf4 triad_v(vf4 b, vf4 c) {
   return r;
 }
 
+template <bool NT>
 __device__ __forceinline__ void triad_chunk(const float* __restrict__ b, const float* __restrict__ c,
                                             float* __restrict__ a, uint64_t base, uint64_t n,
                                             uint32_t lane) {
@@ -51,11 +52,19 @@ __device__ __forceinline__ void triad_chunk(const float* __restrict__ b, const f
     vf4 vb[4], vc[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      vb[u] = __builtin_nontemporal_load(b4 + u * 64 + lane);
-      vc[u] = __builtin_nontemporal_load(c4 + u * 64 + lane);
+      if constexpr (NT) {
+        vb[u] = __builtin_nontemporal_load(b4 + u * 64 + lane);
+        vc[u] = __builtin_nontemporal_load(c4 + u * 64 + lane);
+      } else {
+        vb[u] = b4[u * 64 + lane];
+        vc[u] = c4[u * 64 + lane];
+      }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) __builtin_nontemporal_store(triad_v(vb[u], vc[u]), a4 + u * 64 + lane);
+    for (int u = 0; u < 4; ++u) {
+      if constexpr (NT) __builtin_nontemporal_store(triad_v(vb[u], vc[u]), a4 + u * 64 + lane);
+      else a4[u * 64 + lane] = triad_v(vb[u], vc[u]);
+    }
   } else {
     for (uint64_t i = base + lane; i < n && i < base + kChunk; i += 64) a[i] = triad1(b[i], c[i]);
   }
@@ -63,7 +72,9 @@ __device__ __forceinline__ void triad_chunk(const float* __restrict__ b, const f
 
 // Persistent / fixed-pass triad.  Wave w of the grid owns wave-chunks
 // w, w + W, w + 2W, ... (W = waves in the grid); record.work counts the
-// wave-chunks the work-group processed.
+// wave-chunks the work-group processed.  NT selects streaming (non-temporal)
+// or ordinary cached accesses.
+template <bool NT>
 __global__ void __launch_bounds__(1024) triad_stressor(KCtrl c, const float* __restrict__ b,
                                                        const float* __restrict__ cc,
                                                        float* __restrict__ a, uint64_t n) {
@@ -89,13 +100,13 @@ __global__ void __launch_bounds__(1024) triad_stressor(KCtrl c, const float* __r
   if (c.passes) {
     for (uint64_t p = 0; p < c.passes; ++p)
       for (uint64_t ch = gw; ch < nchunks; ch += nw) {
-        triad_chunk(b, cc, a, ch * kChunk, n, lane);
+        triad_chunk<NT>(b, cc, a, ch * kChunk, n, lane);
         ++done;
       }
   } else if (gw < nchunks) {
     uint64_t ch = gw;
     for (;;) {
-      triad_chunk(b, cc, a, ch * kChunk, n, lane);
+      triad_chunk<NT>(b, cc, a, ch * kChunk, n, lane);
       ++done;
       ch += nw;
       if (ch >= nchunks) ch = gw;
@@ -253,10 +264,11 @@ hipError_t launch_stamp(uint64_t* slot, hipStream_t s) {
 }
 
 hipError_t launch_triad_stressor(const KCtrl& c, const float* b, const float* cc, float* a,
-                                 uint64_t n, uint32_t threads, hipStream_t s, hipEvent_t e0,
-                                 hipEvent_t e1) {
-  return xlaunch(triad_stressor, dim3(c.grid), dim3(threads), 0, s, e0, e1, c, b,
-                               cc, a, n);
+                                 uint64_t n, uint32_t threads, bool streaming, hipStream_t s,
+                                 hipEvent_t e0, hipEvent_t e1) {
+  if (streaming)
+    return xlaunch(triad_stressor<true>, dim3(c.grid), dim3(threads), 0, s, e0, e1, c, b, cc, a, n);
+  return xlaunch(triad_stressor<false>, dim3(c.grid), dim3(threads), 0, s, e0, e1, c, b, cc, a, n);
 }
 
 hipError_t launch_triad_victim(const float* b, const float* c, float* a, uint64_t n,

@@ -263,19 +263,20 @@ struct Defaults {
 };
 
 Defaults defaults_for(ci_resource_t r) {
+  // Chosen from standalone sweeps on MI355X (work-groups per CU x threads):
+  // the smallest occupancy within a few percent of the best rate, so that a
+  // colocated victim can still be dispatched beside the stressor.
   switch (r) {
-    // Work-groups per CU stay at or below half the wave slots so that a
-    // colocated victim can still be dispatched next to the stressor.
-    case CI_RES_HBM: return {256, 4, 0, 0, 0};
+    case CI_RES_HBM: return {256, 1, 0, 0, 0};
     case CI_RES_L2: return {256, 4, 0, 0, 0};
-    case CI_RES_MALL: return {256, 4, 0, 0, 0};
+    case CI_RES_MALL: return {256, 1, 0, 0, 0};
     case CI_RES_VL1D: return {256, 4, 0, 0, 0};
-    case CI_RES_LDS: return {256, 2, 1, 4, 0};
+    case CI_RES_LDS: return {1024, 1, 1, 4, 0};
     case CI_RES_VALU_F32: return {256, 4, 8, 0, 4096};
     case CI_RES_MFMA_F32:
     case CI_RES_MFMA_BF16:
     case CI_RES_MFMA_FP8: return {256, 2, 4, 0, 1024};
-    case CI_RES_PTRCHASE: return {256, 4, 4, 0, 1024};
+    case CI_RES_PTRCHASE: return {256, 1, 4, 0, 1024};
     case CI_RES_DISPATCH: return {64, 0, 0, 0, 1000000};
     case CI_RES_OCCUPANCY: return {256, 1, 64, 0, 0};
     default: return {256, 1, 0, 0, 0};
@@ -407,7 +408,7 @@ static ci_status_t launch_kernel(ci_stressor* h, const KCtrl& c) {
   switch (h->r) {
     case CI_RES_HBM:
       e = launch_triad_stressor(c, (const float*)o.src0, (const float*)o.src1, (float*)o.dst, o.n,
-                                o.threads, s, h->e0, h->e1);
+                                o.threads, o.vec == 0, s, h->e0, h->e1);
       break;
     case CI_RES_L2:
     case CI_RES_VL1D:

@@ -146,7 +146,7 @@ def test_hbm_stressor_fixed_passes(ctx, dev, x, passes, n):
     want = oracle.triad_f32(b, c)
     assert np.array_equal(ta.cpu().numpy().view(np.uint32), want.view(np.uint32))
     ncu = 8 * round(32 * x)
-    assert rep.grid == ncu * 4 and rep.wg_reported == rep.grid
+    assert rep.grid == ncu and rep.wg_reported == rep.grid
     chunks = (n + 1023) // 1024
     assert rep.work == passes * chunks
     assert rep.units == 12.0 * n * passes

@@ -73,13 +73,19 @@ def test_cache_stressor_persistent(ctx, dev, res, words):
 @pytest.mark.parametrize("vec,stride", [(1, 1), (1, 2), (1, 32), (2, 1), (4, 1), (4, 3)])
 def test_lds_stressor_fixed(ctx, dev, vec, stride):
     w = synth.u32(synth.seed_for(1, synth.BUF_LDS), 8192)
-    st = ctx.stressor("lds", 0.25, src0=_t(w.view(np.int32), dev), vec=vec, knob=stride, passes=3)
+    st = ctx.stressor("lds", 0.25, src0=_t(w.view(np.int32), dev), vec=vec, knob=stride, passes=3,
+                      threads=256, wg_per_cu=2)
     rep = st.stop()
     rec = st.records()
     exp = oracle.lds_wg_expected(w, vec, stride, waves=4, passes=rec["work"])
     assert np.all(rec["work"] == 3)
     assert np.array_equal(rec["check"].astype(np.uint32), exp)
     assert rep.units == 3 * rep.grid * 4 * 64 * 8192 * 4 * 2
+    st = ctx.stressor("lds", 0.25, src0=_t(w.view(np.int32), dev), vec=vec, knob=stride, passes=2)
+    rep = st.stop()   # default shape: 1024 threads (16 waves), one work-group per CU
+    rec = st.records()
+    assert np.array_equal(rec["check"].astype(np.uint32),
+                          oracle.lds_wg_expected(w, vec, stride, waves=16, passes=rec["work"]))
 
 
 # ------------------------------------------------------------------- VALU
@@ -88,7 +94,7 @@ def test_lds_stressor_fixed(ctx, dev, vec, stride):
 def test_valu_stressor_fixed(ctx, dev, ilp, iters, passes, x):
     import torch
     ncu = 8 * round(32 * x)
-    threads = ncu * 4 * 256
+    threads = ncu * 4 * 256          # default: four 256-thread work-groups per CU
     out = torch.empty(threads * ilp, dtype=torch.float32, device=dev)
     a, b = 1 - 2.0 ** -12, 2.0 ** -12
     st = ctx.stressor("valu_f32", x, dst=out, knob=ilp, iters=iters, passes=passes, fa=a, fb=b)
@@ -170,7 +176,7 @@ def test_chase_stressor_fixed(ctx, dev, n, chains, hops, passes, x):
     import torch
     nxt = synth.random_cycle_u32(synth.seed_for(1, synth.BUF_CHASE), n)
     ncu = 8 * round(32 * x)
-    q = ncu * 4 * 256 * chains
+    q = ncu * 256 * chains           # default: one 256-thread work-group per CU
     end = torch.empty(q, dtype=torch.int32, device=dev)
     st = ctx.stressor("ptrchase", x, src0=_t(nxt.view(np.int32), dev), n=n, dst=end, knob=chains,
                       iters=hops, passes=passes)
