@@ -66,7 +66,7 @@ def test_errors_are_reported_without_a_device():
     size = ctypes.c_size_t()
     assert lib.ci_workspace_size(99, None, 256, ctypes.byref(size)) == 1
     assert lib.ci_workspace_size(0, None, 256, ctypes.byref(size)) == 0
-    assert size.value == 256 + 256 * 4 * 48   # records for 4 work-groups per CU
+    assert size.value == 256 + 256 * 1 * 48   # records for one work-group per CU
 
 
 def _profiles():
