@@ -241,6 +241,7 @@ class Stressor:
                                    ws.numel(), C.byref(h)))
         self.h = h
         self.report: Report | None = None
+        ctx._active = self
 
     def stop(self, raise_on_timeout: bool = True) -> Report:
         if self.h is None:
@@ -248,6 +249,7 @@ class Stressor:
         rep = StressorReport()
         st = load_library().stressor_stop(self.h, C.byref(rep))
         self.h = None
+        self.ctx._active = None
         self.report = _report(rep, st)
         if st != 0 and not (st == 4 and not raise_on_timeout):
             _check(st)
@@ -291,6 +293,7 @@ class Context:
         _check(lib.ci_device_info(h, C.byref(info)))
         self.info = info
         self.stream = torch.cuda.Stream(device=self.device)
+        self._active = None
 
     def close(self):
         if self.handle:
@@ -326,8 +329,12 @@ class Context:
 
     # ---------------------------------------------------------- stressors
     def _sync_torch(self):
+        """Finish torch's queued work before a library call.  Skipped while a
+        stressor runs: torch's default stream is the legacy null stream, and
+        synchronising it would wait for the CU-masked stressor stream too."""
         import torch
-        torch.cuda.current_stream(self.device).synchronize()
+        if self._active is None:
+            torch.cuda.current_stream(self.device).synchronize()
 
     def stressor(self, resource: str, intensity: float, stream=None, ws=None, **opts) -> Stressor:
         self._sync_torch()
@@ -349,6 +356,7 @@ class Context:
         d.kind, d.dtype, d.n = 0, 0, b.numel()
         d.a, d.b, d.out = _ptr(b), _ptr(c), _ptr(a)
         d.passes, d.copies, d.scale_a, d.scale_b = passes, 1, 1.0, 1.0
+        d._keep = (b, c, a)   # the descriptor holds raw pointers: keep the tensors alive
         return d
 
     @staticmethod
@@ -357,6 +365,7 @@ class Context:
         d.kind, d.dtype, d.m, d.n, d.k = 1, DTYPES[dtype], m, n, k
         d.a, d.b, d.out = _ptr(A), _ptr(B), _ptr(Cm)
         d.scale_a, d.scale_b, d.passes, d.copies = float(scale_a), float(scale_b), 1, 1
+        d._keep = (A, B, Cm)
         return d
 
     @staticmethod
@@ -365,6 +374,7 @@ class Context:
         d.kind, d.dtype, d.n, d.k = 2, 1, n, k
         d.a, d.b, d.out = _ptr(W), _ptr(x), _ptr(y)
         d.copies, d.passes, d.scale_a, d.scale_b = copies, 1, 1.0, 1.0
+        d._keep = (W, x, y)
         return d
 
     def victim_triad(self, b, c, a, passes: int = 1, stream=None) -> VictimOutcome:
