@@ -1,0 +1,272 @@
+#!/usr/bin/env python3
+"""Benchmark of the stressor suite and colocation harness on one MI355X.
+
+Default (one JSON line on stdout): a step is one pass of the standalone
+stressor suite -- HBM triad over FP32 N = 2^30, L2 over 2 MiB, Infinity Cache
+over 128 MiB, vL1D over 16 KiB, LDS over 64 KiB per work-group, FP32 FMA
+chains of 4096 steps, FP32/BF16/FP8 matrix-core loops, a pointer chase over a
+random 2^24 cycle, 10^6 empty 64-thread work-groups -- plus one colocated
+triad pair (victim and stressor both a = b + 3c over N = 2^22).  `value` is
+the HBM stressor's bandwidth; every stressor's rate and fraction of peak and
+the pair's slowdown ride along in the same line.
+
+Other workloads (their own JSON lines): --config sweep | precision | serve.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("victim slowdown per resource vs intensity; stressor % of peak (HBM GB/s, TFLOPS)")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def sha_of(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+# --------------------------------------------------------------------------
+class Suite:
+    """Device buffers and the fixed-work form of every stressor."""
+
+    def __init__(self, ctx, dev):
+        import torch
+        import synth
+        self.ctx, self.dev = ctx, dev
+        T = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+        n = 1 << 30
+        self.n_hbm = n
+        self.hb = torch.empty(n, dtype=torch.float32, device=dev)
+        self.hc = torch.empty_like(self.hb)
+        self.ha = torch.empty_like(self.hb)
+        synth.device_fill_uniform_f32(self.hb.data_ptr(), n, synth.seed_for(1, synth.BUF_B))
+        synth.device_fill_uniform_f32(self.hc.data_ptr(), n, synth.seed_for(1, synth.BUF_C))
+        self.l2 = torch.empty(1 << 19, dtype=torch.int32, device=dev)
+        self.mall = torch.empty(1 << 25, dtype=torch.int32, device=dev)
+        self.l1 = torch.empty(1 << 12, dtype=torch.int32, device=dev)
+        synth.device_fill_u32(self.l2.data_ptr(), 1 << 19, synth.seed_for(1, synth.BUF_CACHE))
+        synth.device_fill_u32(self.mall.data_ptr(), 1 << 25, synth.seed_for(1, synth.BUF_CACHE) + 1)
+        synth.device_fill_u32(self.l1.data_ptr(), 1 << 12, synth.seed_for(1, synth.BUF_CACHE) + 2)
+        self.win = T(synth.u32(synth.seed_for(1, synth.BUF_LDS), 8192).view(np.int32))
+        self.valu_out = torch.empty(256 * 4 * 256 * 8, dtype=torch.float32, device=dev)
+        ones = {"f32": (np.ones((32, 2), np.float32), np.ones((2, 32), np.float32)),
+                "bf16": (np.full((32, 16), 0x3F80, np.int16), np.full((16, 32), 0x3F80, np.int16)),
+                "fp8": (np.full((32, 64), 0x38, np.uint8), np.full((64, 32), 0x38, np.uint8))}
+        self.mf = {k: (T(a), T(b)) for k, (a, b) in ones.items()}
+        self.mf_out = torch.empty(256 * 2 * 4 * 4 * 1024, dtype=torch.float32, device=dev)
+        self.chase = T(synth.random_cycle_u32(synth.seed_for(1, synth.BUF_CHASE), 1 << 24).view(np.int32))
+        self.chase_end = torch.empty(256 * 256 * 4, dtype=torch.int32, device=dev)
+        self.count = torch.zeros(1, dtype=torch.int64, device=dev)
+        # colocated triad pair (N = 2^22): victim and an identical stressor
+        m = 1 << 22
+        self.vb = torch.empty(m, dtype=torch.float32, device=dev)
+        self.vc, self.va = torch.empty_like(self.vb), torch.empty_like(self.vb)
+        self.sb, self.sc, self.sa = (torch.empty_like(self.vb) for _ in range(3))
+        for t, s in ((self.vb, synth.BUF_B), (self.vc, synth.BUF_C), (self.sb, synth.BUF_B2),
+                     (self.sc, synth.BUF_C2)):
+            synth.device_fill_uniform_f32(t.data_ptr(), m, synth.seed_for(0, s))
+        torch.cuda.synchronize()
+        self.ws = torch.empty(256 + 256 * 8 * 48, dtype=torch.uint8, device=dev)
+        self.items = [
+            ("hbm", dict(src0=self.hb, src1=self.hc, dst=self.ha, n=n, passes=1), "GB/s", 1e9),
+            ("l2", dict(src0=self.l2, n=1 << 19, passes=8), "TB/s", 1e12),
+            ("mall", dict(src0=self.mall, n=1 << 25, passes=20), "TB/s", 1e12),
+            ("vl1d", dict(src0=self.l1, n=1 << 12, passes=4000), "TB/s", 1e12),
+            ("lds", dict(src0=self.win, passes=10), "TB/s", 1e12),
+            ("valu_f32", dict(dst=self.valu_out, iters=4096, passes=4, fa=1 - 2 ** -12, fb=2 ** -12), "TFLOP/s", 1e12),
+            ("mfma_f32", dict(src0=self.mf["f32"][0], src1=self.mf["f32"][1], dst=self.mf_out, iters=2048, passes=2), "TFLOP/s", 1e12),
+            ("mfma_bf16", dict(src0=self.mf["bf16"][0], src1=self.mf["bf16"][1], dst=self.mf_out, iters=2048, passes=2), "TFLOP/s", 1e12),
+            ("mfma_fp8", dict(src0=self.mf["fp8"][0], src1=self.mf["fp8"][1], dst=self.mf_out, iters=2048, passes=2), "TFLOP/s", 1e12),
+            ("ptrchase", dict(src0=self.chase, n=1 << 24, dst=self.chase_end, iters=512, passes=1), "Ghop/s", 1e9),
+            ("dispatch", dict(iters=1000000, passes=1), "MWG/s", 1e6),
+        ]
+
+    def step(self, acc):
+        for name, opts, unit, scale in self.items:
+            st = self.ctx.stressor(name, 1.0, ws=self.ws, **opts)
+            rep = st.stop()
+            rate = rep.units / (rep.kernel_ns * 1e-9)
+            a = acc.setdefault(name, {"unit": unit, "scale": scale, "rates": [], "kernel_ns": [],
+                                      "pct": [], "units": rep.units})
+            a["rates"].append(rate)
+            a["kernel_ns"].append(rep.kernel_ns)
+            a["pct"].append(100.0 * rate / self.ctx.peak(name) if self.ctx.peak(name) > 0 else None)
+        # colocated triad pair (shared CUs and disjoint halves)
+        d = self.ctx.triad_desc(self.vb, self.vc, self.va, passes=10)
+        so = [dict(src0=self.sb, src1=self.sc, dst=self.sa, n=1 << 22)]
+        for placement, x in (("shared", 1.0), ("disjoint", 0.5)):
+            cell = self.ctx.measure_sensitivity(d, ["hbm"], so, [x], reps=3, warmups=1,
+                                                placement=placement, ws=self.ws)[0]
+            acc.setdefault("pair_" + placement, []).append(cell)
+
+
+def hbm_traffic(kernel_src):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "hbm_triad_n2e30_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        c = json.load(f)
+    if c.get("kernel_source_sha") != sha_of(kernel_src):
+        return None
+    return c.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline():
+    """The oracle's triad on a bounded sample, on the host (one thread)."""
+    import oracle
+    import synth
+    n = 1 << 26
+    b = synth.uniform_f32(synth.seed_for(1, synth.BUF_B), n)
+    c = synth.uniform_f32(synth.seed_for(1, synth.BUF_C), n)
+    oracle.triad_f32(b[:1024], c[:1024])
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.triad_f32(b, c)
+        reps += 1
+        if time.perf_counter() - t0 > 10.0 or reps >= 40:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": round(12.0 * n * reps / dt / 1e9, 3), "unit": "GB/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"C oracle triad a=b+3c (two FP32 roundings) over N=2^26 FP32, {reps} passes "
+                      f"({dt:.1f} s), host CPU, single thread"}
+
+
+def run_suite(args):
+    import torch
+    from paper_2501_16909_amd import coloc
+    dev = torch.device("cuda:0")
+    ctx = coloc.Context(0)
+    suite = Suite(ctx, dev)
+    log("setup done")
+    warm = {}
+    for i in range(args.warmup):
+        suite.step(warm)
+    acc = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        suite.step(acc)
+        log(f"step {i + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stress = {}
+    for name, _, unit, scale in suite.items:
+        a = acc[name]
+        rate = float(np.mean(a["rates"]))
+        pct = a["pct"][0]
+        stress[name] = {"achieved": round(rate / scale, 3), "unit": unit,
+                        "pct_of_peak": None if pct is None else round(float(np.mean(a["pct"])), 1),
+                        "kernel_ms": round(float(np.mean(a["kernel_ns"])) / 1e6, 4)}
+    pairs = {}
+    for placement in ("shared", "disjoint"):
+        cells = acc["pair_" + placement]
+        pairs[placement] = {"slowdown": round(float(np.median([c["slowdown"] for c in cells])), 3),
+                            "t_alone_us": round(float(np.median([c["t_alone_ns"] for c in cells])) / 1e3, 2),
+                            "t_coloc_us": round(float(np.median([c["t_col_ns"] for c in cells])) / 1e3, 2),
+                            "output_equal": all(c["output_equal"] for c in cells),
+                            "window_covered": all(c["window_covered"] for c in cells),
+                            "stressor_cus": cells[0]["ncu"]}
+    hbm = acc["hbm"]
+    t_ns = float(np.mean(hbm["kernel_ns"]))
+    achieved = hbm["units"] / t_ns  # GB/s (bytes per ns)
+    traffic = hbm_traffic(os.path.join(ROOT, "paper_2501_16909_amd", "csrc", "k_memory.hip"))
+    line = {
+        "metric": METRIC,
+        "value": round(achieved, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (SplitMix64 counter-form uniform [-1,1) / uint32 words / random cycle)",
+        "config": {"workload": "stressor suite standalone: HBM triad FP32 N=2^30; L2 2 MiB; "
+                               "Infinity Cache 128 MiB; vL1D 16 KiB; LDS 64 KiB/WG; FP32 FMA 4096; "
+                               "MFMA FP32/BF16/FP8; uint32 chase over 2^24 cycle; 10^6 empty "
+                               "64-thread WGs; plus colocated triad pair N=2^22",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+                     "frac": round(achieved / 8000.0, 4),
+                     "traffic": traffic,
+                     "kernel": "triad_stressor (12 B per element, N=2^30, one pass per launch)"},
+        "stressors": stress,
+        "colocated_triad_pair": pairs,
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+def run_counters(args):
+    """Short run for hardware-counter passes: the HBM stressor over N = 2^30
+    (one pass per launch) twice, then a plain 1 GiB device-to-device copy
+    twice as the calibration kernel of known traffic (1 GiB read, 1 GiB
+    written)."""
+    import torch
+    import synth
+    from paper_2501_16909_amd import coloc
+    dev = torch.device("cuda:0")
+    ctx = coloc.Context(0)
+    n = 1 << 30
+    b = torch.empty(n, dtype=torch.float32, device=dev)
+    c, a = torch.empty_like(b), torch.empty_like(b)
+    synth.device_fill_uniform_f32(b.data_ptr(), n, synth.seed_for(1, synth.BUF_B))
+    synth.device_fill_uniform_f32(c.data_ptr(), n, synth.seed_for(1, synth.BUF_C))
+    torch.cuda.synchronize()
+    for _ in range(2):
+        rep = ctx.stressor("hbm", 1.0, src0=b, src1=c, dst=a, n=n, passes=1).stop()
+        log(f"hbm stressor: {rep.units / rep.kernel_ns:.0f} GB/s")
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ctx.close()
+    print(json.dumps({"counters_run": "hbm_triad_n2e30 x2, copy 1GiB x2"}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="suite", choices=["suite", "sweep", "precision", "serve", "counters"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--out", default=None, help="also write the JSON line(s) to this file")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the colocation "
+                                   "harness measures interference inside a single device",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    if args.config == "suite":
+        run_suite(args)
+    elif args.config == "counters":
+        run_counters(args)
+    else:
+        raise SystemExit(f"--config {args.config}: not built yet")
+
+
+if __name__ == "__main__":
+    main()
