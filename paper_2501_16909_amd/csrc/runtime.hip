@@ -179,7 +179,7 @@ extern "C" ci_status_t ci_init(int device, ci_ctx_t** out) {
   in.peak[CI_RES_HBM] = 8.0e12;                         // HBM3E, published
   in.peak[CI_RES_L2] = 8.0 * 16 * 128 * f;              // 16 channels x 128 B/clk per XCD
   in.peak[CI_RES_MALL] = 17.2e12;                       // Infinity Fabric/MALL (CDNA3 figure)
-  in.peak[CI_RES_VL1D] = cus * 128.0 * f;               // 128 B/clk per CU
+  in.peak[CI_RES_VL1D] = cus * 64.0 * f;                // 64 B/clk per CU
   in.peak[CI_RES_LDS] = cus * 128.0 * f;                // 128 B/clk per CU
   in.peak[CI_RES_VALU_F32] = cus * 4 * 16 * 2.0 * f;    // unpacked FMA: 16 lanes/clk/SIMD
   in.peak[CI_RES_MFMA_F32] = 157.3e12;                  // published dense
