@@ -218,6 +218,263 @@ def run_suite(args):
     print(json.dumps(line), flush=True)
 
 
+
+# --------------------------------------------------------------------------
+# Sensitivity sweep, precision and serving workloads (their own JSON lines)
+# --------------------------------------------------------------------------
+INTENSITIES = [0.0, 0.25, 0.5, 0.75, 1.0]
+
+
+def stressor_operands(dev):
+    """Operands for every stressor at the sweep's sizes."""
+    import torch
+    import synth
+    T = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    n = 1 << 28
+    hb = torch.empty(n, dtype=torch.float32, device=dev)
+    hc, ha = torch.empty_like(hb), torch.empty_like(hb)
+    synth.device_fill_uniform_f32(hb.data_ptr(), n, synth.seed_for(2, synth.BUF_B))
+    synth.device_fill_uniform_f32(hc.data_ptr(), n, synth.seed_for(2, synth.BUF_C))
+    l2 = torch.empty(1 << 19, dtype=torch.int32, device=dev)
+    mall = torch.empty(1 << 25, dtype=torch.int32, device=dev)
+    l1 = torch.empty(1 << 12, dtype=torch.int32, device=dev)
+    for t, k in ((l2, 0), (mall, 1), (l1, 2)):
+        synth.device_fill_u32(t.data_ptr(), t.numel(), synth.seed_for(2, synth.BUF_CACHE) + k)
+    win = T(synth.u32(synth.seed_for(2, synth.BUF_LDS), 8192).view(np.int32))
+    valu = torch.empty(256 * 4 * 256 * 8, dtype=torch.float32, device=dev)
+    mf = {"f32": (np.ones((32, 2), np.float32), np.ones((2, 32), np.float32)),
+          "bf16": (np.full((32, 16), 0x3F80, np.int16), np.full((16, 32), 0x3F80, np.int16)),
+          "fp8": (np.full((32, 64), 0x38, np.uint8), np.full((64, 32), 0x38, np.uint8))}
+    mf = {k: (T(a), T(b)) for k, (a, b) in mf.items()}
+    mout = torch.empty(256 * 2 * 4 * 4 * 1024, dtype=torch.float32, device=dev)
+    chase = T(synth.random_cycle_u32(synth.seed_for(2, synth.BUF_CHASE), 1 << 24).view(np.int32))
+    cend = torch.empty(256 * 256 * 4, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    return {
+        "hbm": dict(src0=hb, src1=hc, dst=ha, n=n),
+        "l2": dict(src0=l2, n=1 << 19),
+        "mall": dict(src0=mall, n=1 << 25),
+        "vl1d": dict(src0=l1, n=1 << 12),
+        "lds": dict(src0=win),
+        "valu_f32": dict(dst=valu, fa=1 - 2 ** -12, fb=2 ** -12),
+        "mfma_f32": dict(src0=mf["f32"][0], src1=mf["f32"][1], dst=mout),
+        "mfma_bf16": dict(src0=mf["bf16"][0], src1=mf["bf16"][1], dst=mout),
+        "mfma_fp8": dict(src0=mf["fp8"][0], src1=mf["fp8"][1], dst=mout),
+        "ptrchase": dict(src0=chase, n=1 << 24, dst=cend),
+        "dispatch": dict(iters=100000),
+        "occupancy": dict(),
+    }
+
+
+def sweep_victims(ctx, dev):
+    import torch
+    import synth
+    m = 4096
+    a = torch.empty(m * m, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    a.copy_(torch.from_numpy(synth.normal_f32(synth.seed_for(2, synth.BUF_GEMM_A), m * m)))
+    b.copy_(torch.from_numpy(synth.normal_f32(synth.seed_for(2, synth.BUF_GEMM_B), m * m)))
+    qa, _ = ctx.quantize(a, "bf16")
+    qb, _ = ctx.quantize(b, "bf16")
+    c = torch.empty((m, m), dtype=torch.float32, device=dev)
+    gemm = ctx.gemm_desc(qa, qb, c, "bf16", m, m, m)
+    n = 8192
+    w = torch.from_numpy(synth.normal_f32(synth.seed_for(2, synth.BUF_GEMV_W), n * n, sigma=0.02)).to(dev)
+    x = torch.from_numpy(synth.normal_f32(synth.seed_for(2, synth.BUF_GEMV_X), n)).to(dev)
+    qw, _ = ctx.quantize(w, "bf16")
+    qx, _ = ctx.quantize(x, "bf16")
+    w3 = qw.repeat(3)          # three identical weight copies, rotated over runs (384 MiB)
+    y = torch.empty(n, dtype=torch.float32, device=dev)
+    gemv = ctx.gemv_desc(w3, qx, y, n, n, copies=3)
+    del a, b, w
+    return {"gemm_bf16_4096": gemm, "gemv_bf16_8192": gemv}
+
+
+def run_sweep(args):
+    import torch
+    from paper_2501_16909_amd import coloc
+    dev = torch.device("cuda:0")
+    ctx = coloc.Context(0)
+    ops = stressor_operands(dev)
+    victims = sweep_victims(ctx, dev)
+    res = list(ops)
+    ws = torch.empty(256 + 256 * 8 * 48, dtype=torch.uint8, device=dev)
+    out = {"metric": "victim slowdown per resource vs intensity", "config": {
+        "workload": "sensitivity sweep: BF16 GEMM 4096^3 and BF16 GEMV 8192^2 (3 rotating weight "
+                    "copies) x 12 stressors x CU intensity 0/25/50/75/100%", "reps": args.reps},
+        "intensities": INTENSITIES, "tables": {}}
+    t0 = time.perf_counter()
+    for placement in ("shared", "disjoint"):
+        for vname, d in victims.items():
+            cells = ctx.measure_sensitivity(d, res, [ops[r] for r in res], INTENSITIES, reps=args.reps,
+                                            warmups=2, placement=placement, ws=ws)
+            tab = {}
+            for i, r in enumerate(res):
+                row = cells[i * len(INTENSITIES):(i + 1) * len(INTENSITIES)]
+                tab[r] = {"slowdown": [None if c["slowdown"] != c["slowdown"] else round(c["slowdown"], 3) for c in row],
+                          "p90": [None if c["slowdown_p90"] != c["slowdown_p90"] else round(c["slowdown_p90"], 3) for c in row],
+                          "stressor_pct_peak": [round(c["stressor_pct_peak"], 1) for c in row],
+                          "valid": [bool(c["window_covered"] and c["output_equal"] and not c["timed_out"]) for c in row],
+                          "t_alone_us": round(row[0]["t_alone_ns"] / 1e3, 2)}
+            out["tables"][f"{vname}/{placement}"] = tab
+            log(f"{vname} {placement}: " + ", ".join(f"{r}={tab[r]['slowdown'][-1]}" for r in res))
+    out["seconds"] = round(time.perf_counter() - t0, 1)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(out, f)
+
+
+def run_precision(args):
+    """GEMM M = N = K = 8192 in FP32, BF16 and FP8 (per-tensor scale) from
+    N(0,1) inputs, FP32 accumulation.  Error against FP64 on 4096 sampled
+    entries: kernel error (FP64 product of the quantised inputs) and total
+    error (FP64 product of the FP32 inputs), each normalised by |A||B|^T and
+    normwise; plus the sensitivity row per dtype."""
+    import torch
+    import oracle
+    import synth
+    from paper_2501_16909_amd import coloc
+    dev = torch.device("cuda:0")
+    ctx = coloc.Context(0)
+    m = 8192
+    ha = synth.normal_f32(synth.seed_for(3, synth.BUF_GEMM_A), m * m).reshape(m, m)
+    hb = synth.normal_f32(synth.seed_for(3, synth.BUF_GEMM_B), m * m).reshape(m, m)
+    a = torch.from_numpy(ha).to(dev)
+    b = torch.from_numpy(hb).to(dev)
+    c = torch.empty((m, m), dtype=torch.float32, device=dev)
+    idx = synth.words(4242, 4096)
+    rows = (idx % np.uint64(m)).astype(np.int64)
+    cols = ((idx >> np.uint64(32)) % np.uint64(m)).astype(np.int64)
+    exact = oracle.gemm_entries_f64(ha, hb, rows, cols)
+    absx = oracle.gemm_entries_f64(np.abs(ha), np.abs(hb), rows, cols)
+    ops = stressor_operands(dev)
+    ws = torch.empty(256 + 256 * 8 * 48, dtype=torch.uint8, device=dev)
+    out = {"metric": "GEMM error vs FP64 and sensitivity per dtype",
+           "config": {"workload": "GEMM M=N=K=8192, inputs N(0,1), FP32 accumulate; FP8 e4m3 per-tensor scale",
+                      "sample": "4096 fixed-seed entries"}, "dtypes": {}}
+    for dt in ("f32", "bf16", "fp8"):
+        if dt == "f32":
+            qa, qb, sa, sb = a, b, 1.0, 1.0
+            fa, fb = ha.astype(np.float64), hb.astype(np.float64)
+        else:
+            qa, sa = ctx.quantize(a, dt)
+            qb, sb = ctx.quantize(b, dt)
+            if dt == "bf16":
+                fa, fb = oracle.bf16_to_f64(qa.cpu().numpy().view(np.uint16)), oracle.bf16_to_f64(qb.cpu().numpy().view(np.uint16))
+            else:
+                fa, fb = oracle.e4m3_to_f64(qa.cpu().numpy()), oracle.e4m3_to_f64(qb.cpu().numpy())
+        d = ctx.gemm_desc(qa, qb, c, dt, m, m, m, sa, sb)
+        times = [ctx.victim_run(d).time_ns for _ in range(5)]
+        got = c.cpu().numpy()[rows, cols].astype(np.float64)
+        kern = sa * sb * oracle.gemm_entries_f64(fa, fb, rows, cols)
+        kabs = sa * sb * oracle.gemm_entries_f64(np.abs(fa), np.abs(fb), rows, cols)
+        t = float(np.median(times))
+        entry = {"time_ms": round(t / 1e6, 3), "tflops": round(2.0 * m ** 3 / t / 1e3, 1),
+                 "pct_of_peak": round(100 * 2.0 * m ** 3 / (t * 1e-9) / ctx.peak("mfma_" + dt), 1),
+                 "kernel_err_max_rel_absprod": float(np.max(np.abs(got - kern) / kabs)),
+                 "kernel_err_normwise": float(np.linalg.norm(got - kern) / np.linalg.norm(kern)),
+                 "total_err_max_rel_absprod": float(np.max(np.abs(got - exact) / absx)),
+                 "total_err_normwise": float(np.linalg.norm(got - exact) / np.linalg.norm(exact))}
+        res = list(ops)
+        cells = ctx.measure_sensitivity(d, res, [ops[r] for r in res], [0.0, 0.5, 1.0], reps=args.reps,
+                                        warmups=1, ws=ws)
+        entry["sensitivity"] = {r: [round(cells[i * 3 + j]["slowdown"], 3) for j in range(3)]
+                                for i, r in enumerate(res)}
+        entry["sensitivity_intensities"] = [0.0, 0.5, 1.0]
+        out["dtypes"][dt] = entry
+        log(f"{dt}: {entry['time_ms']} ms {entry['tflops']} TF, total err normwise {entry['total_err_normwise']:.3g}")
+    ctx.close()
+    print(json.dumps(out), flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(out, f)
+
+
+def serve_trace(lam, seconds, seed):
+    """Poisson arrivals; a third each of BF16 GEMM (n ~ log-U[512, 8192],
+    multiple of 128), BF16 GEMV (n ~ log-U[4096, 16384], multiple of 8) and
+    FP32 triad (N ~ log-U[2^20, 2^28])."""
+    import synth
+    w = synth.words(seed, 4 * int(lam * seconds * 2 + 16))
+    u = ((w >> np.uint64(11)).astype(np.float64) + 0.5) * 2.0 ** -53
+    reqs, t, i = [], 0.0, 0
+    while True:
+        t += -np.log(u[i]) / lam
+        i += 1
+        if t > seconds:
+            break
+        kind = int(u[i] * 3)
+        i += 1
+        x = u[i]
+        i += 1
+        if kind == 0:
+            n = int(round(np.exp(np.log(512) + x * (np.log(8192) - np.log(512))) / 128)) * 128
+            reqs.append({"arrival_s": t, "kind": "gemm", "dtype": "bf16", "m": n, "n": n, "k": n})
+        elif kind == 1:
+            n = int(round(np.exp(np.log(4096) + x * (np.log(16384) - np.log(4096))) / 8)) * 8
+            reqs.append({"arrival_s": t, "kind": "gemv", "dtype": "bf16", "n": n, "k": n})
+        else:
+            n = int(np.exp(np.log(2.0 ** 20) + x * (np.log(2.0 ** 28) - np.log(2.0 ** 20))))
+            reqs.append({"arrival_s": t, "kind": "triad", "n": n})
+        reqs[-1]["seed"] = 900000 + 10 * len(reqs)
+    return reqs
+
+
+def run_serve(args):
+    """Serving loop at several arrival rates, naive versus sensitivity-aware
+    admission; latency p50/p99, throughput, and slowdown of service time
+    against the same request served alone (sampled)."""
+    import torch
+    from paper_2501_16909_amd import coloc
+    ctx = coloc.Context(0)
+    profiles = None
+    if args.profiles and os.path.exists(args.profiles):
+        with open(args.profiles) as f:
+            profiles = json.load(f)
+    out = {"metric": "serving latency p50/p99 and throughput, naive vs sensitivity-aware admission",
+           "config": {"workload": "Poisson arrivals, 1/3 each BF16 GEMM n~logU[512,8192], BF16 GEMV "
+                                  "n~logU[4096,16384], FP32 triad N~logU[2^20,2^28]",
+                      "seconds": args.seconds, "slots": 4, "hbm_budget_gib": 32},
+           "runs": []}
+    iso_cache = {}
+    for lam in args.rates:
+        reqs = serve_trace(lam, args.seconds, 31337 + int(lam))
+        for policy in (["naive", "sensitivity"] if profiles else ["naive"]):
+            t0 = time.perf_counter()
+            res = ctx.serve(reqs, policy=policy, bound=args.bound, hbm_budget=32 << 30, slots=4,
+                            profiles=profiles)
+            wall = time.perf_counter() - t0
+            lat = np.array([r["end_s"] - r["arrival_s"] for r in res])
+            svc = np.array([r["service_ns"] for r in res])
+            # isolated service time for a fixed sample of requests
+            sample = list(range(0, len(reqs), max(1, len(reqs) // 40)))
+            ratios = []
+            for i in sample:
+                key = json.dumps({k: v for k, v in reqs[i].items() if k != "arrival_s"}, sort_keys=True)
+                if key not in iso_cache:
+                    iso = ctx.serve([dict(reqs[i], arrival_s=0.0)], policy="naive", hbm_budget=32 << 30, slots=1)[0]
+                    iso_cache[key] = iso
+                iso = iso_cache[key]
+                assert iso["checksum_bits"] == res[i]["checksum_bits"], "result differs alone vs in the mix"
+                ratios.append(res[i]["service_ns"] / iso["service_ns"])
+            out["runs"].append({"rate_per_s": lam, "policy": policy, "requests": len(reqs),
+                                "latency_ms_p50": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                                "latency_ms_p99": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                                "throughput_req_s": round(len(reqs) / max(r["end_s"] for r in res), 1),
+                                "service_ms_mean": round(float(svc.mean()) / 1e6, 4),
+                                "slowdown_p50": round(float(np.percentile(ratios, 50)), 3),
+                                "slowdown_p99": round(float(np.percentile(ratios, 99)), 3),
+                                "results_equal_isolated": True, "wall_s": round(wall, 2)})
+            log(json.dumps(out["runs"][-1]))
+    ctx.close()
+    print(json.dumps(out), flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(out, f)
+
+
 def run_counters(args):
     """Short run for hardware-counter passes: the HBM stressor over N = 2^30
     (one pass per launch) twice, then a plain 1 GiB device-to-device copy
@@ -254,6 +511,12 @@ def main():
     ap.add_argument("--config", default="suite", choices=["suite", "sweep", "precision", "serve", "counters"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--out", default=None, help="also write the JSON line(s) to this file")
+    ap.add_argument("--reps", type=int, default=10, help="sweep / precision: repetitions per cell")
+    ap.add_argument("--rates", type=float, nargs="+", default=[200.0, 1000.0, 3000.0],
+                    help="serve: arrival rates per second")
+    ap.add_argument("--seconds", type=float, default=2.0, help="serve: trace length")
+    ap.add_argument("--bound", type=float, default=1.5, help="serve: p99 slowdown bound")
+    ap.add_argument("--profiles", default=None, help="serve: sensitivity profiles (JSON)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the colocation "
@@ -264,8 +527,12 @@ def main():
         run_suite(args)
     elif args.config == "counters":
         run_counters(args)
-    else:
-        raise SystemExit(f"--config {args.config}: not built yet")
+    elif args.config == "sweep":
+        run_sweep(args)
+    elif args.config == "precision":
+        run_precision(args)
+    elif args.config == "serve":
+        run_serve(args)
 
 
 if __name__ == "__main__":
