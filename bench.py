@@ -286,8 +286,14 @@ def sweep_victims(ctx, dev):
     w3 = qw.repeat(3)          # three identical weight copies, rotated over runs (384 MiB)
     y = torch.empty(n, dtype=torch.float32, device=dev)
     gemv = ctx.gemv_desc(w3, qx, y, n, n, copies=3)
+    t = 1 << 24
+    tb = torch.empty(t, dtype=torch.float32, device=dev)
+    tc, ta = torch.empty_like(tb), torch.empty_like(tb)
+    synth.device_fill_uniform_f32(tb.data_ptr(), t, synth.seed_for(2, synth.BUF_B2))
+    synth.device_fill_uniform_f32(tc.data_ptr(), t, synth.seed_for(2, synth.BUF_C2))
+    triad = ctx.triad_desc(tb, tc, ta, passes=2)
     del a, b, w
-    return {"gemm_bf16_4096": gemm, "gemv_bf16_8192": gemv}
+    return {"gemm_bf16_4096": gemm, "gemv_bf16_8192": gemv, "triad_f32_2e24": triad}
 
 
 def run_sweep(args):
@@ -307,15 +313,21 @@ def run_sweep(args):
     for placement in ("shared", "disjoint"):
         for vname, d in victims.items():
             cells = ctx.measure_sensitivity(d, res, [ops[r] for r in res], INTENSITIES, reps=args.reps,
-                                            warmups=2, placement=placement, ws=ws)
+                                            warmups=3, placement=placement, ws=ws,
+                                            deadline_ms=args.deadline_ms)
             tab = {}
             for i, r in enumerate(res):
                 row = cells[i * len(INTENSITIES):(i + 1) * len(INTENSITIES)]
-                tab[r] = {"slowdown": [None if c["slowdown"] != c["slowdown"] else round(c["slowdown"], 3) for c in row],
-                          "p90": [None if c["slowdown_p90"] != c["slowdown_p90"] else round(c["slowdown_p90"], 3) for c in row],
+                nan = lambda v: v != v
+                tab[r] = {"slowdown": [None if nan(c["slowdown"]) else round(c["slowdown"], 3) for c in row],
+                          "p90": [None if nan(c["slowdown_p90"]) else round(c["slowdown_p90"], 3) for c in row],
                           "stressor_pct_peak": [round(c["stressor_pct_peak"], 1) for c in row],
-                          "valid": [bool(c["window_covered"] and c["output_equal"] and not c["timed_out"]) for c in row],
-                          "t_alone_us": round(row[0]["t_alone_ns"] / 1e3, 2)}
+                          # a stressor that hit its deadline outlived the victim's
+                          # starvation: the slowdown is then a lower bound
+                          "starved": [bool(c["timed_out"]) for c in row],
+                          "valid": [bool(c["window_covered"] and c["output_equal"]) and not nan(c["slowdown"])
+                                    for c in row],
+                          "t_alone_us": [None if nan(c["t_alone_ns"]) else round(c["t_alone_ns"] / 1e3, 2) for c in row]}
             out["tables"][f"{vname}/{placement}"] = tab
             log(f"{vname} {placement}: " + ", ".join(f"{r}={tab[r]['slowdown'][-1]}" for r in res))
     out["seconds"] = round(time.perf_counter() - t0, 1)
@@ -379,7 +391,7 @@ def run_precision(args):
                  "total_err_normwise": float(np.linalg.norm(got - exact) / np.linalg.norm(exact))}
         res = list(ops)
         cells = ctx.measure_sensitivity(d, res, [ops[r] for r in res], [0.0, 0.5, 1.0], reps=args.reps,
-                                        warmups=1, ws=ws)
+                                        warmups=1, ws=ws, deadline_ms=args.deadline_ms)
         entry["sensitivity"] = {r: [round(cells[i * 3 + j]["slowdown"], 3) for j in range(3)]
                                 for i, r in enumerate(res)}
         entry["sensitivity_intensities"] = [0.0, 0.5, 1.0]
@@ -422,6 +434,59 @@ def serve_trace(lam, seconds, seed):
     return reqs
 
 
+def serve_profiles(ctx, args):
+    """Sensitivity profiles of the three request kinds at representative
+    sizes (GEMM BF16 2048^3, GEMV BF16 8192^2, triad N = 2^24): slowdown
+    curves (shared placement) on the resources the kinds themselves load --
+    HBM, BF16 matrix cores, LDS -- and the pressure each kind exerts there,
+    its standalone rate over the matching stressor's standalone rate."""
+    import torch
+    import synth
+    dev = ctx.device
+    ops = stressor_operands(dev)
+    ws = torch.empty(256 + 256 * 8 * 48, dtype=torch.uint8, device=dev)
+    rates = {}
+    for r, extra in (("hbm", dict(passes=1)), ("mfma_bf16", dict(iters=2048, passes=2)), ("lds", dict(passes=4))):
+        rep = ctx.stressor(r, 1.0, ws=ws, **ops[r], **extra).stop()
+        rates[r] = rep.units / (rep.kernel_ns * 1e-9)
+    g = 2048
+    A = torch.from_numpy(synth.uniform_f32(11, g * g)).to(dev)
+    B = torch.from_numpy(synth.uniform_f32(12, g * g)).to(dev)
+    qa, _ = ctx.quantize(A, "bf16")
+    qb, _ = ctx.quantize(B, "bf16")
+    C = torch.empty((g, g), dtype=torch.float32, device=dev)
+    n = 8192
+    W = torch.from_numpy(synth.uniform_f32(13, n * n)).to(dev)
+    X = torch.from_numpy(synth.uniform_f32(14, n)).to(dev)
+    qw, _ = ctx.quantize(W, "bf16")
+    qx, _ = ctx.quantize(X, "bf16")
+    Y = torch.empty(n, dtype=torch.float32, device=dev)
+    t = 1 << 24
+    tb = torch.from_numpy(synth.uniform_f32(15, t)).to(dev)
+    tc = torch.from_numpy(synth.uniform_f32(16, t)).to(dev)
+    ta = torch.empty_like(tb)
+    descs = {"gemm": ctx.gemm_desc(qa, qb, C, "bf16", g, g, g), "gemv": ctx.gemv_desc(qw, qx, Y, n, n),
+             "triad": ctx.triad_desc(tb, tc, ta, passes=1)}
+    # standalone use of each resource (algorithmic bytes / flops per run)
+    gemm_lds = (g // 128) ** 2 * (g * 2 // 128) * (4 * 16384 + 32768)   # per stage: reads + writes
+    use = {"gemm": {"mfma_bf16": 2.0 * g ** 3, "lds": gemm_lds, "hbm": 3.0 * 2 * g * g},
+           "gemv": {"hbm": 2.0 * n * n}, "triad": {"hbm": 12.0 * t}}
+    occ = {"gemm": min(1.0, (g // 128) ** 2 / (256 * 2)) * 8 / 32, "gemv": 1.0, "triad": 1.0}
+    res = ["hbm", "mfma_bf16", "lds"]
+    profiles = {}
+    for kind, d in descs.items():
+        t_alone = float(np.median([ctx.victim_run(d).time_ns for _ in range(5)])) * 1e-9
+        cells = ctx.measure_sensitivity(d, res, [ops[r] for r in res], INTENSITIES, reps=args.reps,
+                                        warmups=2, ws=ws, deadline_ms=args.deadline_ms)
+        sens = {}
+        for i, r in enumerate(res):
+            row = cells[i * len(INTENSITIES):(i + 1) * len(INTENSITIES)]
+            sens[r] = [float(c["slowdown"]) if c["slowdown"] == c["slowdown"] else 1.0 for c in row]
+        press = {r: min(1.0, use[kind].get(r, 0.0) / t_alone / rates[r]) for r in res}
+        profiles[kind] = {"sens": sens, "press": press, "occ": occ[kind]}
+    return profiles
+
+
 def run_serve(args):
     """Serving loop at several arrival rates, naive versus sensitivity-aware
     admission; latency p50/p99, throughput, and slowdown of service time
@@ -429,10 +494,12 @@ def run_serve(args):
     import torch
     from paper_2501_16909_amd import coloc
     ctx = coloc.Context(0)
-    profiles = None
     if args.profiles and os.path.exists(args.profiles):
         with open(args.profiles) as f:
             profiles = json.load(f)
+    else:
+        profiles = serve_profiles(ctx, args)
+        log("profiles: " + json.dumps(profiles))
     out = {"metric": "serving latency p50/p99 and throughput, naive vs sensitivity-aware admission",
            "config": {"workload": "Poisson arrivals, 1/3 each BF16 GEMM n~logU[512,8192], BF16 GEMV "
                                   "n~logU[4096,16384], FP32 triad N~logU[2^20,2^28]",
@@ -475,6 +542,21 @@ def run_serve(args):
             json.dump(out, f)
 
 
+def run_suite_counters(args):
+    """Each stressor of the suite once, fixed work, no colocation: the run
+    the per-stressor hardware-counter passes profile."""
+    import torch
+    from paper_2501_16909_amd import coloc
+    dev = torch.device("cuda:0")
+    ctx = coloc.Context(0)
+    suite = Suite(ctx, dev)
+    for name, opts, unit, scale in suite.items:
+        rep = ctx.stressor(name, 1.0, ws=suite.ws, **opts).stop()
+        log(f"{name}: {rep.units / (rep.kernel_ns * 1e-9) / scale:.2f} {unit}")
+    ctx.close()
+    print(json.dumps({"counters_run": "stressor suite, one fixed-work launch each"}), flush=True)
+
+
 def run_counters(args):
     """Short run for hardware-counter passes: the HBM stressor over N = 2^30
     (one pass per launch) twice, then a plain 1 GiB device-to-device copy
@@ -508,10 +590,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="suite", choices=["suite", "sweep", "precision", "serve", "counters"])
+    ap.add_argument("--config", default="suite", choices=["suite", "sweep", "precision", "serve", "counters", "suite-counters"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--out", default=None, help="also write the JSON line(s) to this file")
     ap.add_argument("--reps", type=int, default=10, help="sweep / precision: repetitions per cell")
+    ap.add_argument("--deadline-ms", type=int, default=200,
+                    help="sweep / precision / serve: stressor deadline per colocated run")
     ap.add_argument("--rates", type=float, nargs="+", default=[200.0, 1000.0, 3000.0],
                     help="serve: arrival rates per second")
     ap.add_argument("--seconds", type=float, default=2.0, help="serve: trace length")
@@ -527,6 +611,8 @@ def main():
         run_suite(args)
     elif args.config == "counters":
         run_counters(args)
+    elif args.config == "suite-counters":
+        run_suite_counters(args)
     elif args.config == "sweep":
         run_sweep(args)
     elif args.config == "precision":

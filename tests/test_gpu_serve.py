@@ -84,7 +84,7 @@ def test_serve_naive_overlaps_and_matches_isolated(ctx):
 
 def test_serve_budget_and_slots_bound_concurrency(ctx):
     reqs = [dict(r, arrival_s=0.0) for r in _trace()]
-    out = ctx.serve(reqs, policy="naive", hbm_budget=64 << 20, slots=2)
+    out = ctx.serve(reqs, policy="naive", hbm_budget=128 << 20, slots=2)
     assert all(o["status"] == 0 for o in out)
     ev = sorted([(o["admit_s"], 1) for o in out] + [(o["end_s"], -1) for o in out])
     live = peak = 0
