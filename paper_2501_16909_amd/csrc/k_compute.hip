@@ -109,7 +109,7 @@ __global__ void __launch_bounds__(1024) lds_stressor(KCtrl c, const uint32_t* __
 // pass.  Start value of chain j of global thread t: ((t mod 1024)+j+1)/1024.
 // The chains continue across passes; dst[t*ILP + j] = final value.
 template <int ILP>
-__global__ void __launch_bounds__(1024) valu_stressor(KCtrl c, float* __restrict__ out, uint64_t iters,
+__global__ void __launch_bounds__(1024) valu_stressor(KCtrl c, float* __restrict__ out, uint32_t iters,
                                                       float fa, float fb) {
   __shared__ uint64_t s_t0;
   __shared__ uint32_t s_stop;
@@ -118,23 +118,23 @@ __global__ void __launch_bounds__(1024) valu_stressor(KCtrl c, float* __restrict
   float x[ILP];
 #pragma unroll
   for (int j = 0; j < ILP; ++j) x[j] = (float)((uint32_t)(t & 1023u) + j + 1) * 0x1.0p-10f;
+  // An FMA may read only one scalar register: keep the addend in a vector
+  // register for the whole loop (a lane broadcast of the same value).
+  const float vb = __shfl(fb, 0, 64);
   WgStop ws;
   stop_init(ws.st, c, t0, blockIdx.x == 0 && threadIdx.x == 0);
+  const uint32_t blocks = iters >> 3, rem = iters & 7u;
   uint64_t passes = 0;
   for (;;) {
-    for (uint64_t it = 0; it < iters; it += 8) {
-      const uint64_t m = (iters - it) < 8 ? (iters - it) : 8;
-      if (m == 8) {
+    for (uint32_t blk = 0; blk < blocks; ++blk) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+      for (int u = 0; u < 8; ++u)
 #pragma unroll
-          for (int j = 0; j < ILP; ++j) x[j] = __builtin_fmaf(x[j], fa, fb);
-      } else {
-        for (uint64_t u = 0; u < m; ++u)
-#pragma unroll
-          for (int j = 0; j < ILP; ++j) x[j] = __builtin_fmaf(x[j], fa, fb);
-      }
+        for (int j = 0; j < ILP; ++j) x[j] = __builtin_fmaf(x[j], fa, vb);
     }
+    for (uint32_t r = 0; r < rem; ++r)
+#pragma unroll
+      for (int j = 0; j < ILP; ++j) x[j] = __builtin_fmaf(x[j], fa, vb);
     ++passes;
     if (c.passes) {
       if (passes >= c.passes) break;
@@ -375,9 +375,10 @@ hipError_t launch_lds_stressor(const KCtrl& c, const uint32_t* window, uint32_t 
   }
 }
 
-hipError_t launch_valu_stressor(const KCtrl& c, float* out, uint32_t ilp, uint64_t iters, float fa,
+hipError_t launch_valu_stressor(const KCtrl& c, float* out, uint32_t ilp, uint64_t iters64, float fa,
                                 float fb, uint32_t threads, hipStream_t s, hipEvent_t e0,
                                 hipEvent_t e1) {
+  const uint32_t iters = (uint32_t)iters64;  // range checked by the caller
   switch (ilp) {
     case 1: return xlaunch(valu_stressor<1>, dim3(c.grid), dim3(threads), 0, s, e0, e1, c, out, iters, fa, fb);
     case 2: return xlaunch(valu_stressor<2>, dim3(c.grid), dim3(threads), 0, s, e0, e1, c, out, iters, fa, fb);

@@ -181,37 +181,33 @@ __global__ void __launch_bounds__(1024) cache_stressor(KCtrl c, const uint32_t* 
   const uint64_t t0 = s_t0;
   const uint64_t len = slice_words ? slice_words : region_words;
   const uint64_t lo = slice_words ? ((uint64_t)blockIdx.x * slice_words) % region_words : 0;
-  const uint64_t round_words = 4ull * blockDim.x;           // one 16-byte load per thread
-  const uint64_t rounds = len / round_words;
-  const uint64_t phase = slice_words ? 0 : ((uint64_t)blockIdx.x * 7u) % rounds;
-  const uint4* base = reinterpret_cast<const uint4*>(region + lo);
+  // One round = one 16-byte load per thread; the span is `rounds` rounds.
+  // Counts fit 32 bits (checked on the host), so loop control stays scalar.
+  const uint32_t rounds = (uint32_t)(len / (4ull * blockDim.x));
+  const uint32_t phase = slice_words ? 0u : (uint32_t)(((uint64_t)blockIdx.x * 7u) % rounds);
+  const uint4* base = reinterpret_cast<const uint4*>(region + lo) + threadIdx.x;
+  const uint32_t stride = blockDim.x;
   StopState st;
   stop_init(st, c, t0, blockIdx.x == 0 && threadIdx.x == 0);
   uint32_t acc = 0;
   uint64_t passes = 0;
   for (;;) {
     for (uint32_t bt = 0; bt < batch; ++bt) {
-      uint64_t r = phase;
-      uint64_t left = rounds;
-      while (left >= 4) {
-        uint4 v[4];
+      // rounds [phase, rounds) then [0, phase): each word once per pass
+      for (int part = 0; part < 2; ++part) {
+        uint32_t r = part ? 0u : phase;
+        const uint32_t end = part ? phase : rounds;
+        for (; r + 4 <= end; r += 4) {
+          uint4 v[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          uint64_t rr = r + u;
-          if (rr >= rounds) rr -= rounds;
-          v[u] = base[rr * blockDim.x + threadIdx.x];
+          for (int u = 0; u < 4; ++u) v[u] = base[(uint64_t)(r + u) * stride];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc += v[u].x + v[u].y + v[u].z + v[u].w;
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc += v[u].x + v[u].y + v[u].z + v[u].w;
-        r += 4;
-        if (r >= rounds) r -= rounds;
-        left -= 4;
-      }
-      while (left > 0) {
-        const uint4 v = base[r * blockDim.x + threadIdx.x];
-        acc += v.x + v.y + v.z + v.w;
-        if (++r >= rounds) r = 0;
-        --left;
+        for (; r < end; ++r) {
+          const uint4 v = base[(uint64_t)r * stride];
+          acc += v.x + v.y + v.z + v.w;
+        }
       }
     }
     passes += batch;

@@ -330,6 +330,8 @@ ci_status_t check_opts(ci_ctx* ctx, ci_resource_t r, const ci_stressor_opts_t& o
       if (!o.src0) return set_err(CI_ERR_INVALID_ARG, "%s: region is required", kResName[r]);
       if ((uintptr_t)o.src0 & 15) return set_err(CI_ERR_INVALID_ARG, "%s: region must be 16-byte aligned", kResName[r]);
       const uint64_t span = cache_span_words(r, o, grid);
+      if (span / (4ull * o.threads) > 0xFFFFFFFFull)
+        return set_err(CI_ERR_INVALID_ARG, "%s: region too large", kResName[r]);
       if (span == 0 || span % (4ull * o.threads))
         return set_err(CI_ERR_INVALID_ARG,
                        "%s: region of %llu words gives a per-work-group span of %llu words, which "
@@ -346,6 +348,7 @@ ci_status_t check_opts(ci_ctx* ctx, ci_resource_t r, const ci_stressor_opts_t& o
       break;
     case CI_RES_VALU_F32:
       if (!o.dst) return set_err(CI_ERR_INVALID_ARG, "valu: dst is required");
+      if (o.iters == 0 || o.iters > 0xFFFFFFFFull) return set_err(CI_ERR_INVALID_ARG, "valu: iters must be in [1, 2^32)");
       if (o.knob != 1 && o.knob != 2 && o.knob != 4 && o.knob != 8)
         return set_err(CI_ERR_INVALID_ARG, "valu: ILP must be 1, 2, 4 or 8");
       break;
