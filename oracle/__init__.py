@@ -14,6 +14,7 @@ definition it follows.
 Parity status per function (pins are in tests/test_oracle_pins.py):
   triad_f32, bitsum_u32, sum_f32_exact .......... pinned
   fma_chain_f32 / valu_outputs .................. pinned
+  dmul_chain_f64 / valu64_outputs ............... pinned
   chase_u32, is_single_cycle .................... pinned
   cache_wg_expected, lds_wave_pass_sum .......... pinned
   f32_to_bf16, f32_to_e4m3, quantize_fp8 ........ pinned
@@ -65,6 +66,9 @@ def _lib():
         lib.or_sum_f32_exact.restype = ctypes.c_double
         lib.or_fma_chain_f32.argtypes = [_F32P, ctypes.c_uint64, ctypes.c_float, ctypes.c_float,
                                          ctypes.c_uint64, _F32P]
+        lib.or_dmul_chain.argtypes = [np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS"),
+                                      ctypes.c_uint64, ctypes.c_double, ctypes.c_uint64,
+                                      np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")]
         lib.or_chase_u32.argtypes = [_U32P, ctypes.c_uint64, _U64P, ctypes.c_uint64,
                                      ctypes.c_uint64, _U32P]
         lib.or_is_single_cycle.argtypes = [_U32P, ctypes.c_uint64]
@@ -184,6 +188,24 @@ def valu_outputs(threads, ilp: int, a: float, b: float, steps: int) -> np.ndarra
     """Final chain values, shape (len(threads), ilp)."""
     x0 = valu_start_values(threads, ilp)
     return fma_chain_f32(x0.ravel(), a, b, steps).reshape(x0.shape)
+
+
+def dmul_chain_f64(x0, a: float, steps: int) -> np.ndarray:
+    """FP64 pipeline chain (Section 4.4.3): x <- x * a, `steps` times."""
+    x0 = np.ascontiguousarray(x0, dtype=np.float64).ravel()
+    out = np.empty_like(x0)
+    _lib().or_dmul_chain(x0, x0.size, float(a), int(steps), out)
+    return out
+
+
+def valu64_outputs(threads, ilp: int, a: float, steps: int) -> np.ndarray:
+    """FP64 stressor outputs, shape (len(threads), ilp); start values as for
+    the FP32 chains, x0(t, c) = ((t mod 1024) + c + 1) * 2**-10."""
+    t = np.asarray(threads, dtype=np.uint64)
+    c = np.arange(ilp, dtype=np.uint64)
+    k = (t[:, None] % np.uint64(1024)) + c[None, :] + np.uint64(1)
+    x0 = k.astype(np.float64) * 2.0 ** -10
+    return dmul_chain_f64(x0.ravel(), a, steps).reshape(x0.shape)
 
 
 # --------------------------------------------------------------------------

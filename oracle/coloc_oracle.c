@@ -133,6 +133,16 @@ void or_fma_chain_f32(const float* x0, uint64_t n, float a, float b, uint64_t st
   }
 }
 
+/* FP64 pipeline chain (the paper's FP64 compute kernel, Section 4.4.3):
+ * x <- x * a, rounded to binary64 each step (one IEEE multiply). */
+void or_dmul_chain(const double* x0, uint64_t n, double a, uint64_t steps, double* out) {
+  for (uint64_t i = 0; i < n; ++i) {
+    double x = x0[i];
+    for (uint64_t k = 0; k < steps; ++k) x = x * a;
+    out[i] = x;
+  }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Pointer chase: follow next[] `hops` times from each start index. */
 void or_chase_u32(const uint32_t* next, uint64_t n, const uint64_t* starts, uint64_t nchains,

@@ -182,6 +182,22 @@ def test_valu_start_values_and_fixed_point():
     assert np.max(np.abs(out - exact)) < 4096 * 2.0 ** -23
 
 
+def test_dmul_chain_closed_forms_and_rounding():
+    x0 = np.array([0.75, 1.0, 3.0], np.float64)
+    assert np.array_equal(oracle.dmul_chain_f64(x0, 2.0, 100), x0 * 2.0 ** 100)
+    assert np.array_equal(oracle.dmul_chain_f64(x0, 0.5, 50), x0 * 2.0 ** -50)
+    # one correctly rounded binary64 multiply per step, checked with exact
+    # rational arithmetic on a product that needs rounding
+    a = 1 + 2.0 ** -30
+    x = 1 + 2.0 ** -29
+    got = oracle.dmul_chain_f64(np.array([x]), a, 1)[0]
+    exact = Fraction(x) * Fraction(a)          # 1 + 3*2^-30 + 2^-59: needs rounding
+    assert Fraction(got) != exact and abs(Fraction(got) - exact) <= Fraction(2.0 ** -53)
+    assert got == x * a
+    out = oracle.valu64_outputs(np.array([0, 1023, 1024]), 2, 0.5, 3)
+    assert out[0, 0] == 2.0 ** -10 / 8 and out[2, 1] == out[0, 1] == 2 * 2.0 ** -10 / 8
+
+
 # ----------------------------------------------------------- pointer chase
 def test_chase_brute_force_and_full_cycle():
     n = 1 << 12
