@@ -542,6 +542,232 @@ def run_serve(args):
             json.dump(out, f)
 
 
+
+# --------------------------------------------------------------------------
+# The paper's individual experiments, on MI355X
+# --------------------------------------------------------------------------
+def _gemv_victim(ctx, dev, n=8192, copies=3):
+    import torch
+    import synth
+    w = torch.from_numpy(synth.normal_f32(synth.seed_for(2, synth.BUF_GEMV_W), n * n, sigma=0.02)).to(dev)
+    x = torch.from_numpy(synth.normal_f32(synth.seed_for(2, synth.BUF_GEMV_X), n)).to(dev)
+    qw, _ = ctx.quantize(w, "bf16")
+    qx, _ = ctx.quantize(x, "bf16")
+    y = torch.empty(n, dtype=torch.float32, device=dev)
+    return ctx.gemv_desc(qw.repeat(copies), qx, y, n, n, copies=copies)
+
+
+def _gemm_victim(ctx, dev, n):
+    import torch
+    import synth
+    a = torch.from_numpy(synth.normal_f32(synth.seed_for(2, synth.BUF_GEMM_A), n * n)).to(dev)
+    b = torch.from_numpy(synth.normal_f32(synth.seed_for(2, synth.BUF_GEMM_B), n * n)).to(dev)
+    qa, _ = ctx.quantize(a, "bf16")
+    qb, _ = ctx.quantize(b, "bf16")
+    c = torch.empty((n, n), dtype=torch.float32, device=dev)
+    return ctx.gemm_desc(qa, qb, c, "bf16", n, n, n)
+
+
+def _cell(c):
+    nan = lambda v: v != v
+    return {"slowdown": None if nan(c["slowdown"]) else round(c["slowdown"], 3),
+            "p10": None if nan(c["slowdown_p10"]) else round(c["slowdown_p10"], 3),
+            "p90": None if nan(c["slowdown_p90"]) else round(c["slowdown_p90"], 3),
+            "t_alone_us": None if nan(c["t_alone_ns"]) else round(c["t_alone_ns"] / 1e3, 2),
+            "stressor_pct_peak": round(c["stressor_pct_peak"], 1),
+            "valid": bool(c["window_covered"] and c["output_equal"]), "starved": bool(c["timed_out"])}
+
+
+def run_pollution(args):
+    """Cache pollution (Section 4.3, Figure 3 analog): two triad instances on
+    disjoint halves of the CUs, data size per instance swept across the
+    per-XCD L2 (4 MB) and the Infinity Cache (256 MB); slowdown of one."""
+    import torch
+    import synth
+    from paper_2501_16909_amd import coloc
+    ctx = coloc.Context(0)
+    dev = ctx.device
+    ws = torch.empty(256 + 256 * 8 * 48, dtype=torch.uint8, device=dev)
+    rows = []
+    for mib in (0.75, 1.5, 3, 6, 12, 24, 48, 96, 192, 384, 768, 1536):
+        n = int(mib * (1 << 20) / 12) // 1024 * 1024
+        bufs = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(6)]
+        for i, t in enumerate(bufs):
+            synth.device_fill_uniform_f32(t.data_ptr(), n, synth.seed_for(5, i))
+        torch.cuda.synchronize()
+        passes = max(1, int(300e-6 * 4e12 / (12 * n)))    # >= ~0.3 ms per victim run
+        d = ctx.triad_desc(bufs[0], bufs[1], bufs[2], passes=passes)
+        so = [dict(src0=bufs[3], src1=bufs[4], dst=bufs[5], n=n, vec=1)]   # cached accesses, as the victim
+        cell = ctx.measure_sensitivity(d, ["hbm"], so, [0.5], reps=args.reps, warmups=2, placement="disjoint",
+                                       ws=ws, deadline_ms=args.deadline_ms)[0]
+        r = _cell(cell)
+        r.update({"mib_per_instance": mib, "n": n, "victim_passes": passes,
+                  "victim_gbs_alone": round(12.0 * n * passes / cell["t_alone_ns"], 1)})
+        rows.append(r)
+        log(json.dumps(r))
+        del bufs
+        torch.cuda.empty_cache()
+    out = {"metric": "slowdown vs data size per instance (cache pollution)",
+           "config": {"workload": "two FP32 triads on disjoint CU halves (128 + 128 CUs), per-instance data "
+                                  "= 3 arrays; victim timed, stressor persistent"}, "rows": rows}
+    ctx.close()
+    _emit(out, args)
+
+
+def run_bandwidth(args):
+    """L2/memory-bandwidth partition (Section 4.3, Table 1 analog): GEMV
+    victim (BF16 8192^2, three rotated weight copies) on half the CUs, HBM
+    stressor on the other half with 0..4 work-groups per CU."""
+    import torch
+    from paper_2501_16909_amd import coloc
+    ctx = coloc.Context(0)
+    dev = ctx.device
+    ops = stressor_operands(dev)
+    d = _gemv_victim(ctx, dev)
+    ws = torch.empty(256 + 256 * 8 * 48, dtype=torch.uint8, device=dev)
+    rows = []
+    for wg in (0, 1, 2, 3, 4):
+        if wg == 0:
+            cell = ctx.measure_sensitivity(d, ["hbm"], [ops["hbm"]], [0.0], reps=args.reps, warmups=2,
+                                           placement="disjoint", ws=ws)[0]
+            cell_half = ctx.measure_sensitivity(d, ["hbm"], [ops["hbm"]], [0.5], reps=1, warmups=1,
+                                                placement="disjoint", ws=ws)[0]
+            r = _cell(cell)
+            r["t_alone_half_us"] = round(cell_half["t_alone_ns"] / 1e3, 2)
+        else:
+            o = dict(ops["hbm"], wg_per_cu=wg)
+            r = _cell(ctx.measure_sensitivity(d, ["hbm"], [o], [0.5], reps=args.reps, warmups=2,
+                                              placement="disjoint", ws=ws, deadline_ms=args.deadline_ms)[0])
+        r["stressor_wg_per_cu"] = wg
+        r["stressor_workgroups"] = wg * 128
+        rows.append(r)
+        log(json.dumps(r))
+    out = {"metric": "GEMV slowdown vs stressor work-groups on disjoint CUs (bandwidth partition)",
+           "config": {"workload": "BF16 GEMV 8192^2 x 3 copies on 128 CUs; HBM triad stressor (N=2^28) on "
+                                  "the other 128 CUs"}, "rows": rows}
+    ctx.close()
+    _emit(out, args)
+
+
+def run_ilp(args):
+    """Issue pressure (Section 4.4.2, Table 2 analog): FP32 FMA stressor with
+    one 256-thread work-group per CU (one wave per SIMD) and ILP 1/2/4/8,
+    on the same CUs as a GEMV and a triad victim."""
+    import torch
+    from paper_2501_16909_amd import coloc
+    ctx = coloc.Context(0)
+    dev = ctx.device
+    ops = stressor_operands(dev)
+    ws = torch.empty(256 + 256 * 8 * 48, dtype=torch.uint8, device=dev)
+    victims = {"gemv_bf16_8192": _gemv_victim(ctx, dev)}
+    import synth
+    n = 1 << 24
+    tb = torch.empty(n, dtype=torch.float32, device=dev)
+    tc, ta = torch.empty_like(tb), torch.empty_like(tb)
+    synth.device_fill_uniform_f32(tb.data_ptr(), n, 1)
+    synth.device_fill_uniform_f32(tc.data_ptr(), n, 2)
+    victims["triad_f32_2e24"] = ctx.triad_desc(tb, tc, ta, passes=2)
+    out = {"metric": "victim slowdown vs VALU stressor ILP (issue pressure)",
+           "config": {"workload": "FP32 FMA chains, 256 WGs x 256 threads (one wave per SIMD), ILP S1..S4 = "
+                                  "1/2/4/8, same CUs as the victim"}, "rows": []}
+    for ilp in (1, 2, 4, 8):
+        o = dict(ops["valu_f32"], knob=ilp, wg_per_cu=1)
+        rep = ctx.stressor("valu_f32", 1.0, ws=ws, iters=4096, passes=8, **o).stop()
+        rate = rep.units / (rep.kernel_ns * 1e-9)
+        # wave instructions per cycle per CU: FMAs / 64 lanes / (CUs x clock)
+        ipc = rate / 2 / 64 / (256 * ctx.info.clock_khz * 1e3)
+        row = {"ilp": ilp, "stressor_tflops": round(rate / 1e12, 2), "stressor_valu_ipc_per_cu": round(ipc, 3)}
+        for vname, d in victims.items():
+            c = ctx.measure_sensitivity(d, ["valu_f32"], [o], [1.0], reps=args.reps, warmups=2, ws=ws,
+                                        deadline_ms=args.deadline_ms)[0]
+            row[vname] = _cell(c)
+        out["rows"].append(row)
+        log(json.dumps(row))
+    ctx.close()
+    _emit(out, args)
+
+
+def run_pairs(args):
+    """Pipeline interference (Section 4.4.3, Table 3 analog) with two FP64
+    multiply kernels of ILP 1/2/4/8, and the Pitfall-1 analog (Section 3):
+    two FP32 FMA kernels with one wave per SIMD each."""
+    import torch
+    from paper_2501_16909_amd import coloc
+    ctx1, ctx2 = coloc.Context(0), coloc.Context(0)
+    dev = ctx1.device
+    ws1 = torch.empty(256 + 256 * 8 * 48, dtype=torch.uint8, device=dev)
+    ws2 = torch.empty_like(ws1)
+    out64 = [torch.empty(256 * 256 * 8, dtype=torch.float64, device=dev) for _ in range(2)]
+    out = {"metric": "seq/col speedup of two identical compute kernels",
+           "config": {"workload": "each kernel 256 WGs x 256 threads (one wave per SIMD), all CUs, "
+                                  "two hardware queues"}, "fp64_mul": [], "fp32_fma": []}
+    for ilp in (1, 2, 4, 8):
+        # both kernels write their own output buffer
+        o = dict(knob=ilp, wg_per_cu=1, iters=4096, passes=16, fa=1 - 2 ** -20)
+        r1 = ctx1.stressor("valu_f64", 1.0, ws=ws1, dst=out64[0], **o).stop()
+        r2 = ctx2.stressor("valu_f64", 1.0, ws=ws2, dst=out64[1], **o).stop()
+        seq = r1.window_ns + r2.window_ns
+        s1 = ctx1.stressor("valu_f64", 1.0, ws=ws1, dst=out64[0], **o)
+        s2 = ctx2.stressor("valu_f64", 1.0, ws=ws2, dst=out64[1], **o)
+        a, b = s1.stop(), s2.stop()
+        col_ns = (max(a.t_last_end, b.t_last_end) - min(a.t_first_start, b.t_first_start)) * 1e6 / ctx1.info.wall_clock_khz
+        row = {"ilp": ilp, "fp64_pipe_util_alone_pct": round(r1.pct_of_peak, 1),
+               "seq_ms": round(seq / 1e6, 4), "col_ms": round(col_ns / 1e6, 4),
+               "speedup_seq_over_col": round(seq / col_ns, 3)}
+        out["fp64_mul"].append(row)
+        log(json.dumps(row))
+    out32 = [torch.empty(256 * 256 * 8, dtype=torch.float32, device=dev) for _ in range(2)]
+    for ilp in (1, 8):
+        o = dict(knob=ilp, wg_per_cu=1, iters=4096, passes=16, fa=1 - 2 ** -12, fb=2 ** -12)
+        r1 = ctx1.stressor("valu_f32", 1.0, ws=ws1, dst=out32[0], **o).stop()
+        s1 = ctx1.stressor("valu_f32", 1.0, ws=ws1, dst=out32[0], **o)
+        s2 = ctx2.stressor("valu_f32", 1.0, ws=ws2, dst=out32[1], **o)
+        a, b = s1.stop(), s2.stop()
+        row = {"ilp": ilp, "alone_ms": round(r1.window_ns / 1e6, 4),
+               "colocated_ms_each": round((a.window_ns + b.window_ns) / 2 / 1e6, 4),
+               "slowdown_each": round((a.window_ns + b.window_ns) / 2 / r1.window_ns, 3),
+               "alone_pct_peak": round(r1.pct_of_peak, 1)}
+        out["fp32_fma"].append(row)
+        log(json.dumps(row))
+    ctx1.close()
+    ctx2.close()
+    _emit(out, args)
+
+
+def run_ldsstride(args):
+    """Shared-memory interference (Section 4.4.1, Figure 4 analog): GEMM
+    victims (BF16, dims 1024 and 2048) against the LDS stressor with 32-bit
+    accesses at stride 1..64 words (bank-conflict degree), same CUs."""
+    import torch
+    from paper_2501_16909_amd import coloc
+    ctx = coloc.Context(0)
+    dev = ctx.device
+    ops = stressor_operands(dev)
+    ws = torch.empty(256 + 256 * 8 * 48, dtype=torch.uint8, device=dev)
+    out = {"metric": "GEMM slowdown vs LDS stressor bank-conflict stride",
+           "config": {"workload": "BF16 GEMM n = 1024 and 2048 (own MFMA kernel); LDS stressor 64 KiB per WG, "
+                                  "256 threads, one WG per CU, 32-bit accesses at stride s words"}, "rows": []}
+    victims = {n: _gemm_victim(ctx, dev, n) for n in (1024, 2048)}
+    for stride in (1, 2, 4, 8, 16, 32, 64):
+        o = dict(ops["lds"], vec=1, knob=stride, threads=256, wg_per_cu=1)
+        rep = ctx.stressor("lds", 1.0, ws=ws, passes=2, **o).stop()
+        row = {"stride": stride, "lds_tbs_alone": round(rep.units / rep.kernel_ns / 1e3, 2)}
+        for n, d in victims.items():
+            row[f"gemm_{n}"] = _cell(ctx.measure_sensitivity(d, ["lds"], [o], [1.0], reps=args.reps, warmups=2,
+                                                             ws=ws, deadline_ms=args.deadline_ms)[0])
+        out["rows"].append(row)
+        log(json.dumps(row))
+    ctx.close()
+    _emit(out, args)
+
+
+def _emit(out, args):
+    print(json.dumps(out), flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(out, f)
+
+
 def run_suite_counters(args):
     """Each stressor of the suite once, fixed work, no colocation: the run
     the per-stressor hardware-counter passes profile."""
@@ -590,7 +816,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="suite", choices=["suite", "sweep", "precision", "serve", "counters", "suite-counters"])
+    ap.add_argument("--config", default="suite", choices=["suite", "sweep", "precision", "serve", "counters", "suite-counters",
+                             "pollution", "bandwidth", "ilp", "pairs", "ldsstride"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--out", default=None, help="also write the JSON line(s) to this file")
     ap.add_argument("--reps", type=int, default=10, help="sweep / precision: repetitions per cell")
@@ -619,6 +846,16 @@ def main():
         run_precision(args)
     elif args.config == "serve":
         run_serve(args)
+    elif args.config == "pollution":
+        run_pollution(args)
+    elif args.config == "bandwidth":
+        run_bandwidth(args)
+    elif args.config == "ilp":
+        run_ilp(args)
+    elif args.config == "pairs":
+        run_pairs(args)
+    elif args.config == "ldsstride":
+        run_ldsstride(args)
 
 
 if __name__ == "__main__":

@@ -69,7 +69,8 @@ typedef enum ci_resource {
   CI_RES_PTRCHASE = 9,   /* dependent loads through a random cycle             */
   CI_RES_DISPATCH = 10,  /* stream of empty 64-thread work-groups              */
   CI_RES_OCCUPANCY = 11, /* sleeping WGs that hold LDS / wave slots (Sec. 4.2)  */
-  CI_RES_COUNT = 12
+  CI_RES_VALU_F64 = 12,  /* FP64 multiply chains with an ILP knob (Sec. 4.4.3) */
+  CI_RES_COUNT = 13
 } ci_resource_t;
 
 typedef enum ci_dtype { CI_DT_F32 = 0, CI_DT_BF16 = 1, CI_DT_FP8E4M3 = 2 } ci_dtype_t;
@@ -117,7 +118,8 @@ const char* ci_last_error(void);
 ci_status_t ci_device_info(ci_ctx_t* ctx, ci_device_info_t* out);
 
 /* Peak of resource r in its own unit: bytes/s for HBM, L2, MALL, VL1D and
- * LDS; flop/s for VALU and MFMA; work-groups/s for DISPATCH; hops/s for the
+ * LDS; flop/s for VALU and MFMA (for VALU_F64 one multiply = one flop, so its
+ * peak is half the FP64 FMA rate); work-groups/s for DISPATCH; hops/s for the
  * chase (no peak: 0); OCCUPANCY has no rate (0). */
 ci_status_t ci_peak_for(ci_ctx_t* ctx, ci_resource_t r, double* peak);
 
@@ -162,6 +164,8 @@ typedef struct ci_stressor_opts {
    *   L2/MALL/VL1D: src0 = region (uint32, n words)
    *   LDS:        src0 = window words (uint32, 8192 = 32 KiB)
    *   VALU_F32:   dst  = final chain values (FP32, grid*threads*knob)
+   *   VALU_F64:   dst  = final chain values (FP64, grid*threads*knob); the
+   *               multiplier is (double)fa
    *   MFMA_*:     src0 = A tile (32 x K), src1 = B tile (K x 32), row-major,
    *               element type F32 / BF16 / E4M3 with K = 2 / 16 / 64;
    *               dst = per-wave accumulator tiles (FP32, waves*knob*32*32)
@@ -176,7 +180,7 @@ typedef struct ci_stressor_opts {
   uint64_t n;
   uint32_t wg_per_cu;    /* work-groups per masked CU; 0 = resource default  */
   uint32_t threads;      /* threads per work-group; 0 = resource default     */
-  uint32_t knob;         /* VALU: ILP chains per lane (1,2,4,8); LDS: stride
+  uint32_t knob;         /* VALU_F32/F64: ILP chains per lane (1,2,4,8); LDS: stride
                             in vectors; MFMA: independent accumulators (1-4);
                             PTRCHASE: chains per lane (1-8); OCCUPANCY: LDS
                             KiB held per WG; 0 = default                     */

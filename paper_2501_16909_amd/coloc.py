@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcoloc.so")
 
 RESOURCES = ["hbm", "l2", "mall", "vl1d", "lds", "valu_f32", "mfma_f32", "mfma_bf16",
-             "mfma_fp8", "ptrchase", "dispatch", "occupancy"]
+             "mfma_fp8", "ptrchase", "dispatch", "occupancy", "valu_f64"]
 RES = {name: i for i, name in enumerate(RESOURCES)}
 DTYPES = {"f32": 0, "bf16": 1, "fp8": 2}
 VICTIMS = {"triad": 0, "gemm": 1, "gemv": 2}
@@ -139,6 +139,9 @@ EXPORTS = {
 }
 
 _LIB = None
+# Stressors running anywhere in this process (any context): while one runs,
+# nothing here touches torch's legacy null stream (see Context._sync_torch).
+_RUNNING: set = set()
 
 
 def load_library(path: str = LIB_PATH):
@@ -242,6 +245,7 @@ class Stressor:
         self.h = h
         self.report: Report | None = None
         ctx._active = self
+        _RUNNING.add(id(self))
 
     def stop(self, raise_on_timeout: bool = True) -> Report:
         if self.h is None:
@@ -250,6 +254,7 @@ class Stressor:
         st = load_library().stressor_stop(self.h, C.byref(rep))
         self.h = None
         self.ctx._active = None
+        _RUNNING.discard(id(self))
         self.report = _report(rep, st)
         if st != 0 and not (st == 4 and not raise_on_timeout):
             _check(st)
@@ -329,11 +334,12 @@ class Context:
 
     # ---------------------------------------------------------- stressors
     def _sync_torch(self):
-        """Finish torch's queued work before a library call.  Skipped while a
-        stressor runs: torch's default stream is the legacy null stream, and
-        synchronising it would wait for the CU-masked stressor stream too."""
+        """Finish torch's queued work before a library call.  Skipped while any
+        stressor runs in this process: torch's default stream is the legacy
+        null stream, and synchronising it would also wait for every CU-masked
+        stressor stream."""
         import torch
-        if self._active is None:
+        if not _RUNNING:
             torch.cuda.current_stream(self.device).synchronize()
 
     def stressor(self, resource: str, intensity: float, stream=None, ws=None, **opts) -> Stressor:

@@ -189,6 +189,9 @@ hipError_t launch_lds_stressor(const KCtrl& c, const uint32_t* window, uint32_t 
 hipError_t launch_valu_stressor(const KCtrl& c, float* out, uint32_t ilp, uint64_t iters,
                                 float fa, float fb, uint32_t threads, hipStream_t s,
     hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_valu64_stressor(const KCtrl& c, double* out, uint32_t ilp, uint64_t iters,
+                                  double fa, uint32_t threads, hipStream_t s, hipEvent_t e0,
+                                  hipEvent_t e1);
 hipError_t launch_mfma_stressor(const KCtrl& c, int dtype, const void* a, const void* b,
                                 float* out, uint32_t accs, uint64_t iters, uint32_t threads,
                                 hipStream_t s,

@@ -148,6 +148,47 @@ __global__ void __launch_bounds__(1024) valu_stressor(KCtrl c, float* __restrict
   if (threadIdx.x == 0) write_record(c, blockIdx.x, t0, passes, 0, ws.st.flags);
 }
 
+// ------------------------------------------------------------ VALU FP64
+// The paper's FP64 pipeline kernel (Section 4.4.3): ILP independent chains of
+// x <- x * a per lane, one rounded binary64 multiply per step; same start
+// values and pass structure as the FP32 chains; dst[t*ILP + j] = final x.
+template <int ILP>
+__global__ void __launch_bounds__(1024) valu64_stressor(KCtrl c, double* __restrict__ out,
+                                                        uint32_t iters, double fa) {
+  __shared__ uint64_t s_t0;
+  __shared__ uint32_t s_stop;
+  const uint64_t t0 = wg_enter(c, &s_t0, &s_stop);
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double x[ILP];
+#pragma unroll
+  for (int j = 0; j < ILP; ++j) x[j] = (double)((uint32_t)(t & 1023u) + j + 1) * 0x1.0p-10;
+  WgStop ws;
+  stop_init(ws.st, c, t0, blockIdx.x == 0 && threadIdx.x == 0);
+  const uint32_t blocks = iters >> 3, rem = iters & 7u;
+  uint64_t passes = 0;
+  for (;;) {
+    for (uint32_t blk = 0; blk < blocks; ++blk) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int j = 0; j < ILP; ++j) x[j] = __dmul_rn(x[j], fa);
+    }
+    for (uint32_t r = 0; r < rem; ++r)
+#pragma unroll
+      for (int j = 0; j < ILP; ++j) x[j] = __dmul_rn(x[j], fa);
+    ++passes;
+    if (c.passes) {
+      if (passes >= c.passes) break;
+      continue;
+    }
+    if (ws.check(c, &s_stop)) break;
+  }
+#pragma unroll
+  for (int j = 0; j < ILP; ++j) out[t * ILP + j] = x[j];
+  __syncthreads();
+  if (threadIdx.x == 0) write_record(c, blockIdx.x, t0, passes, 0, ws.st.flags);
+}
+
 // ------------------------------------------------------------------ MFMA
 // Every wave keeps NACC accumulators of one 32x32 output tile and adds the
 // same product A (32 x K) * B (K x 32) to each, `iters` times per pass, with
@@ -384,6 +425,19 @@ hipError_t launch_valu_stressor(const KCtrl& c, float* out, uint32_t ilp, uint64
     case 2: return xlaunch(valu_stressor<2>, dim3(c.grid), dim3(threads), 0, s, e0, e1, c, out, iters, fa, fb);
     case 4: return xlaunch(valu_stressor<4>, dim3(c.grid), dim3(threads), 0, s, e0, e1, c, out, iters, fa, fb);
     case 8: return xlaunch(valu_stressor<8>, dim3(c.grid), dim3(threads), 0, s, e0, e1, c, out, iters, fa, fb);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_valu64_stressor(const KCtrl& c, double* out, uint32_t ilp, uint64_t iters64,
+                                  double fa, uint32_t threads, hipStream_t s, hipEvent_t e0,
+                                  hipEvent_t e1) {
+  const uint32_t iters = (uint32_t)iters64;  // range checked by the caller
+  switch (ilp) {
+    case 1: return xlaunch(valu64_stressor<1>, dim3(c.grid), dim3(threads), 0, s, e0, e1, c, out, iters, fa);
+    case 2: return xlaunch(valu64_stressor<2>, dim3(c.grid), dim3(threads), 0, s, e0, e1, c, out, iters, fa);
+    case 4: return xlaunch(valu64_stressor<4>, dim3(c.grid), dim3(threads), 0, s, e0, e1, c, out, iters, fa);
+    case 8: return xlaunch(valu64_stressor<8>, dim3(c.grid), dim3(threads), 0, s, e0, e1, c, out, iters, fa);
     default: return hipErrorInvalidValue;
   }
 }

@@ -52,7 +52,7 @@ double now_s() {
 
 const char* kResName[CI_RES_COUNT] = {"hbm", "l2", "mall", "vl1d", "lds", "valu_f32",
                                       "mfma_f32", "mfma_bf16", "mfma_fp8", "ptrchase",
-                                      "dispatch", "occupancy"};
+                                      "dispatch", "occupancy", "valu_f64"};
 
 }  // namespace
 
@@ -188,6 +188,7 @@ extern "C" ci_status_t ci_init(int device, ci_ctx_t** out) {
   in.peak[CI_RES_PTRCHASE] = 0.0;
   in.peak[CI_RES_DISPATCH] = 0.0;
   in.peak[CI_RES_OCCUPANCY] = 0.0;
+  in.peak[CI_RES_VALU_F64] = cus * 4 * 16 * f;          // FP64 multiplies: 16 lanes/clk/SIMD
   *out = ctx;
   return CI_OK;
 }
@@ -268,7 +269,7 @@ Defaults defaults_for(ci_resource_t r) {
   // colocated victim can still be dispatched beside the stressor.
   switch (r) {
     case CI_RES_HBM: return {256, 1, 0, 0, 0};
-    case CI_RES_L2: return {256, 4, 0, 0, 0};
+    case CI_RES_L2: return {512, 3, 0, 0, 0};
     case CI_RES_MALL: return {256, 1, 0, 0, 0};
     case CI_RES_VL1D: return {256, 4, 0, 0, 0};
     case CI_RES_LDS: return {1024, 1, 1, 4, 0};
@@ -279,6 +280,7 @@ Defaults defaults_for(ci_resource_t r) {
     case CI_RES_PTRCHASE: return {256, 1, 4, 0, 1024};
     case CI_RES_DISPATCH: return {64, 0, 0, 0, 1000000};
     case CI_RES_OCCUPANCY: return {256, 1, 64, 0, 0};
+    case CI_RES_VALU_F64: return {256, 4, 4, 0, 4096};
     default: return {256, 1, 0, 0, 0};
   }
 }
@@ -351,6 +353,12 @@ ci_status_t check_opts(ci_ctx* ctx, ci_resource_t r, const ci_stressor_opts_t& o
       if (o.iters == 0 || o.iters > 0xFFFFFFFFull) return set_err(CI_ERR_INVALID_ARG, "valu: iters must be in [1, 2^32)");
       if (o.knob != 1 && o.knob != 2 && o.knob != 4 && o.knob != 8)
         return set_err(CI_ERR_INVALID_ARG, "valu: ILP must be 1, 2, 4 or 8");
+      break;
+    case CI_RES_VALU_F64:
+      if (!o.dst) return set_err(CI_ERR_INVALID_ARG, "valu_f64: dst is required");
+      if (o.knob != 1 && o.knob != 2 && o.knob != 4 && o.knob != 8)
+        return set_err(CI_ERR_INVALID_ARG, "valu_f64: ILP must be 1, 2, 4 or 8");
+      if (o.iters == 0 || o.iters > 0xFFFFFFFFull) return set_err(CI_ERR_INVALID_ARG, "valu_f64: iters must be in [1, 2^32)");
       break;
     case CI_RES_MFMA_F32:
     case CI_RES_MFMA_BF16:
@@ -433,6 +441,10 @@ static ci_status_t launch_kernel(ci_stressor* h, const KCtrl& c) {
     case CI_RES_VALU_F32:
       e = launch_valu_stressor(c, (float*)o.dst, o.knob, o.iters, o.fa, o.fb, o.threads, s, h->e0,
                                h->e1);
+      break;
+    case CI_RES_VALU_F64:
+      e = launch_valu64_stressor(c, (double*)o.dst, o.knob, o.iters, (double)o.fa, o.threads, s,
+                                 h->e0, h->e1);
       break;
     case CI_RES_MFMA_F32:
     case CI_RES_MFMA_BF16:
@@ -637,6 +649,7 @@ static double units_of(const ci_stressor* h, const std::vector<ci_wg_record_t>& 
     case CI_RES_MFMA_FP8:
       return (double)work * waves * o.knob * (double)o.iters * 2.0 * 32 * 32 * mfma_k(mfma_dtype(h->r));
     case CI_RES_PTRCHASE: return (double)work * o.threads * o.knob * (double)o.iters;
+    case CI_RES_VALU_F64: return (double)work * o.threads * o.knob * (double)o.iters;
     case CI_RES_DISPATCH: return (double)h->launched.load() * (double)o.iters;
     default: return 0.0;
   }

@@ -72,9 +72,12 @@ def test_serve_naive_overlaps_and_matches_isolated(ctx):
     for q, o in zip(reqs, out):
         assert o["admit_s"] >= q["arrival_s"] - 1e-9 and o["end_s"] > o["admit_s"]
         assert 0 <= o["slot"] < 4 and o["service_ns"] > 0
-    # overlap happened: some request was admitted before an earlier one ended
-    ends = sorted((o["admit_s"], o["end_s"]) for o in out)
-    assert any(ends[i + 1][0] < ends[i][1] for i in range(len(ends) - 1))
+    # requests that arrive together run together: four are admitted before
+    # the first completion is observed
+    burst = ctx.serve([dict(r, arrival_s=0.0) for r in reqs], policy="naive", hbm_budget=1 << 30, slots=4)
+    spans = sorted((o["admit_s"], o["end_s"]) for o in burst)
+    assert any(spans[i + 1][0] < spans[i][1] for i in range(len(spans) - 1))
+    assert [o["checksum_bits"] for o in burst] == [o["checksum_bits"] for o in out]
     # same result alone and in the mix (bit for bit), and against the oracle
     for q, o in zip(reqs, out):
         alone = ctx.serve([dict(q, arrival_s=0.0)], policy="naive", hbm_budget=1 << 30, slots=1)[0]

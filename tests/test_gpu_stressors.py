@@ -260,3 +260,21 @@ def test_invalid_arguments_rejected(ctx, dev):
     # a zero-intensity stressor is a valid no-op
     rep = ctx.stressor("hbm", 0.0).stop()
     assert rep.grid == 0 and rep.ncu == 0
+
+
+# ------------------------------------------------------------ VALU FP64
+@pytest.mark.parametrize("ilp,iters,passes,x,a", [(1, 4096, 1, 0.125, 1 - 2.0 ** -20),
+                                                  (4, 1000, 3, 0.5, 1 + 2.0 ** -20),
+                                                  (8, 13, 2, 1 / 32, 0.5), (2, 100, 1, 1.0, 2.0)])
+def test_valu64_stressor_fixed(ctx, dev, ilp, iters, passes, x, a):
+    import torch
+    ncu = 8 * round(32 * x)
+    threads = ncu * 4 * 256
+    out = torch.empty(threads * ilp, dtype=torch.float64, device=dev)
+    st = ctx.stressor("valu_f64", x, dst=out, knob=ilp, iters=iters, passes=passes, fa=a)
+    rep = st.stop()
+    got = out.cpu().numpy().reshape(threads, ilp)
+    sel = np.unique(np.concatenate([np.arange(0, threads, 89), [threads - 1]]))
+    want = oracle.valu64_outputs(sel, ilp, a, iters * passes)
+    assert np.array_equal(got[sel].view(np.uint64), want.view(np.uint64))
+    assert rep.units == float(threads) * ilp * iters * passes
