@@ -768,6 +768,88 @@ def _emit(out, args):
             json.dump(out, f)
 
 
+
+def predicted_pair_slowdown(profiles, a, b):
+    """Product over resources of max(1, curve_A(pressure of B))."""
+    out = 1.0
+    pts = np.array(INTENSITIES)
+    for r, curve in profiles[a]["sens"].items():
+        x = min(1.0, max(0.0, profiles[b]["press"].get(r, 0.0)))
+        out *= max(1.0, float(np.interp(x, pts, curve)))
+    return out
+
+
+def run_estimator(args):
+    """Kernel-level interference estimator (Section 5.1), validated on
+    workload pairs: predict the slowdown of victim A while victim B runs
+    beside it (B enqueued back to back on a second stream for longer than A
+    runs), from A's sensitivity curves and B's standalone pressure, and
+    compare with the measured slowdown (medians of alternating runs)."""
+    import torch
+    import synth
+    from paper_2501_16909_amd import coloc
+    ctx = coloc.Context(0)
+    dev = ctx.device
+    profiles = serve_profiles(ctx, args)
+    log("profiles: " + json.dumps(profiles))
+    # two independent instances of each kind (A's buffers and B's buffers)
+    def make(kind, seed):
+        if kind == "gemm":
+            g = 2048
+            A = torch.from_numpy(synth.uniform_f32(seed, g * g)).to(dev)
+            B = torch.from_numpy(synth.uniform_f32(seed + 1, g * g)).to(dev)
+            qa, _ = ctx.quantize(A, "bf16")
+            qb, _ = ctx.quantize(B, "bf16")
+            return ctx.gemm_desc(qa, qb, torch.empty((g, g), dtype=torch.float32, device=dev), "bf16", g, g, g)
+        if kind == "gemv":
+            n = 8192
+            W = torch.from_numpy(synth.uniform_f32(seed, n * n)).to(dev)
+            X = torch.from_numpy(synth.uniform_f32(seed + 1, n)).to(dev)
+            qw, _ = ctx.quantize(W, "bf16")
+            qx, _ = ctx.quantize(X, "bf16")
+            return ctx.gemv_desc(qw, qx, torch.empty(n, dtype=torch.float32, device=dev), n, n)
+        t = 1 << 24
+        tb = torch.from_numpy(synth.uniform_f32(seed, t)).to(dev)
+        tc = torch.from_numpy(synth.uniform_f32(seed + 1, t)).to(dev)
+        return ctx.triad_desc(tb, tc, torch.empty_like(tb), passes=1)
+    kinds = ["gemm", "gemv", "triad"]
+    A = {k: make(k, 7000 + 10 * i) for i, k in enumerate(kinds)}
+    B = {k: make(k, 8000 + 10 * i) for i, k in enumerate(kinds)}
+    side = torch.cuda.Stream(device=dev)
+    rows = []
+    for a in kinds:
+        t_a = float(np.median([ctx.victim_run(A[a]).time_ns for _ in range(5)]))
+        for b in kinds:
+            tb_alone = float(np.median([ctx.victim_run(B[b]).time_ns for _ in range(3)]))
+            count = int(min(4000, max(20, 6.0 * t_a / tb_alone)))
+            alone, col = [], []
+            for _ in range(args.reps):
+                alone.append(ctx.victim_run(A[a]).time_ns)
+                side.synchronize()
+                ctx.victim_enqueue(B[b], side, count)
+                col.append(ctx.victim_run(A[a]).time_ns)
+                side.synchronize()
+            meas = float(np.median(col) / np.median(alone))
+            pred = predicted_pair_slowdown(profiles, a, b)
+            rows.append({"victim": a, "corunner": b, "measured": round(meas, 3), "predicted": round(pred, 3),
+                         "abs_err": round(abs(pred - meas), 3), "rel_err": round(abs(pred - meas) / meas, 3)})
+            log(json.dumps(rows[-1]))
+    err = np.array([r["rel_err"] for r in rows])
+    m = np.array([r["measured"] for r in rows])
+    p = np.array([r["predicted"] for r in rows])
+    rank = lambda v: np.argsort(np.argsort(v))
+    spearman = float(np.corrcoef(rank(m), rank(p))[0, 1]) if len(rows) > 2 else None
+    out = {"metric": "estimator error on workload pairs",
+           "config": {"workload": "victims BF16 GEMM 2048^3, BF16 GEMV 8192^2, FP32 triad 2^24; co-runner "
+                                  "enqueued back to back on a second stream; shared CUs",
+                      "model": "product over HBM / BF16-MFMA / LDS of max(1, sensitivity curve at the "
+                               "co-runner's standalone pressure)"},
+           "pairs": rows, "mean_rel_err": round(float(err.mean()), 3),
+           "max_rel_err": round(float(err.max()), 3), "spearman": spearman, "profiles": profiles}
+    ctx.close()
+    _emit(out, args)
+
+
 def run_suite_counters(args):
     """Each stressor of the suite once, fixed work, no colocation: the run
     the per-stressor hardware-counter passes profile."""
@@ -817,7 +899,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="suite", choices=["suite", "sweep", "precision", "serve", "counters", "suite-counters",
-                             "pollution", "bandwidth", "ilp", "pairs", "ldsstride"])
+                             "pollution", "bandwidth", "ilp", "pairs", "ldsstride", "estimator"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--out", default=None, help="also write the JSON line(s) to this file")
     ap.add_argument("--reps", type=int, default=10, help="sweep / precision: repetitions per cell")
@@ -856,6 +938,8 @@ def main():
         run_pairs(args)
     elif args.config == "ldsstride":
         run_ldsstride(args)
+    elif args.config == "estimator":
+        run_estimator(args)
 
 
 if __name__ == "__main__":

@@ -277,6 +277,13 @@ typedef struct ci_victim_result {
 ci_status_t victim_run(ci_ctx_t* ctx, const ci_victim_desc_t* d, void* stream,
                        ci_victim_result_t* out);
 
+/* Enqueue `count` back-to-back launches of the victim's kernel on `stream`
+ * (non-NULL) and return without waiting: no events, stamps or checksums.
+ * Used to keep a second workload running beside a timed victim, the way the
+ * paper's estimator is validated on workload pairs (Section 5.1).  The
+ * caller synchronises `stream` before reusing the buffers. */
+ci_status_t victim_enqueue(ci_ctx_t* ctx, const ci_victim_desc_t* d, void* stream, uint32_t count);
+
 /* Checksums of n FP32 values at device pointer x (stream-ordered on
  * `stream`, synchronous): bit-pattern sum mod 2^64 and FP64 sum. */
 ci_status_t ci_checksum_f32(ci_ctx_t* ctx, const void* x, uint64_t n, void* stream,

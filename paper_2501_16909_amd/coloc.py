@@ -125,6 +125,7 @@ EXPORTS = {
     "stressor_stop": ([C.c_void_p, C.POINTER(StressorReport)], C.c_int),
     "ci_read_records": ([C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(WgRecord)], C.c_int),
     "victim_run": ([C.c_void_p, C.POINTER(VictimDesc), C.c_void_p, C.POINTER(VictimResult)], C.c_int),
+    "victim_enqueue": ([C.c_void_p, C.POINTER(VictimDesc), C.c_void_p, C.c_uint32], C.c_int),
     "ci_checksum_f32": ([C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.POINTER(C.c_uint64),
                          C.POINTER(C.c_double)], C.c_int),
     "ci_quantize": ([C.c_void_p, C.c_void_p, C.c_uint64, C.c_int, C.c_void_p, C.POINTER(C.c_float),
@@ -355,6 +356,11 @@ class Context:
         s = stream if stream is not None else self.stream
         _check(load_library().victim_run(self.handle, C.byref(desc), _stream_handle(s), C.byref(r)))
         return VictimOutcome(r.time_ns, r.checksum_bits, r.sum_f64, r.t_begin, r.t_end)
+
+    def victim_enqueue(self, desc: VictimDesc, stream, count: int):
+        """Queue `count` launches of the victim on `stream` without waiting."""
+        self._sync_torch()
+        _check(load_library().victim_enqueue(self.handle, C.byref(desc), _stream_handle(stream), int(count)))
 
     @staticmethod
     def triad_desc(b, c, a, passes: int = 1) -> VictimDesc:

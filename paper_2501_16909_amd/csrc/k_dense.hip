@@ -162,6 +162,94 @@ __global__ void __launch_bounds__(256, 2) gemm_kernel(const uint8_t* __restrict_
     }
 }
 
+// Large-tile GEMM: one 256-thread work-group per CU owns a 256 x 256 tile of
+// C; each of its four waves owns 128 x 128 (4 x 4 MFMA tiles of 32 x 32, 16
+// accumulators), so every LDS fragment read feeds four MFMAs instead of two.
+// Two 72 KiB K-stages of A and B are double-buffered in LDS (144 KiB of the
+// CU's 160 KiB), filled through registers while the other stage computes.
+constexpr int kBig = 256;
+constexpr int kBigTileLds = kBig * kRowPitch;    // one operand, one stage
+
+template <int DT>
+__global__ void __launch_bounds__(256, 1) gemm256_kernel(const uint8_t* __restrict__ A,
+                                                         const uint8_t* __restrict__ B,
+                                                         float* __restrict__ C, uint32_t M,
+                                                         uint32_t N, uint32_t K, float scale) {
+  using G = Gemm<DT>;
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  uint8_t* sA = smem;                     // [2][256][kRowPitch]
+  uint8_t* sB = smem + 2 * kBigTileLds;   // [2][256][kRowPitch]
+  const uint32_t nbm = (M + kBig - 1) / kBig, nbn = (N + kBig - 1) / kBig;
+  uint32_t tm, tn;
+  tile_of(blockIdx.x, nbm, nbn, tm, tn);
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wid = tid >> 6;
+  const uint32_t wm = wid >> 1, wn = wid & 1u;   // wave's 128x128 sub-tile
+  const uint64_t rowBytes = (uint64_t)K * G::kElem;
+  const uint32_t nstages = (uint32_t)((rowBytes + kStageBytes - 1) / kStageBytes);
+  // global -> register staging: thread loads 16 B at (row = tid/8 + 32 j, chunk = tid%8)
+  const uint32_t lrow = tid >> 3, lchunk = tid & 7u;
+  i32x4 ra[8], rb[8];
+  auto gload = [&](uint32_t st) {
+    const uint64_t kb = (uint64_t)st * kStageBytes + lchunk * 16u;
+    const bool kin = kb + 16 <= rowBytes;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t r = lrow + 32u * j;
+      const uint32_t gm = tm * kBig + r, gn = tn * kBig + r;
+      ra[j] = (kin && gm < M) ? *reinterpret_cast<const i32x4*>(A + gm * rowBytes + kb) : i32x4{0, 0, 0, 0};
+      rb[j] = (kin && gn < N) ? *reinterpret_cast<const i32x4*>(B + gn * rowBytes + kb) : i32x4{0, 0, 0, 0};
+    }
+  };
+  auto sstore = [&](uint32_t buf) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t r = lrow + 32u * j;
+      *reinterpret_cast<i32x4*>(sA + buf * kBigTileLds + r * kRowPitch + lchunk * 16u) = ra[j];
+      *reinterpret_cast<i32x4*>(sB + buf * kBigTileLds + r * kRowPitch + lchunk * 16u) = rb[j];
+    }
+  };
+  f32x16 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  const uint32_t frow = lane & 31u, fk = (lane >> 5) * G::kFragBytes;
+  for (uint32_t st = 0; st < nstages; ++st) {
+    const uint32_t buf = st & 1u;
+    if (st + 1 < nstages) gload(st + 1);
+    const uint8_t* a0 = sA + buf * kBigTileLds + (wm * 128 + frow) * kRowPitch + fk;
+    const uint8_t* b0 = sB + buf * kBigTileLds + (wn * 128 + frow) * kRowPitch + fk;
+#pragma unroll
+    for (int s = 0; s < G::kSub; ++s) {
+      const uint32_t ko = s * 2 * G::kFragBytes;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = G::mma(a0 + i * 32 * kRowPitch + ko, b0 + j * 32 * kRowPitch + ko, acc[i][j]);
+    }
+    if (st + 1 < nstages) sstore(buf ^ 1u);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t col = tn * kBig + wn * 128 + j * 32 + (lane & 31u);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const uint32_t row = tm * kBig + wm * 128 + i * 32 + 8u * (v / 4) + 4u * (lane >> 5) + (v % 4);
+        if (row < M && col < N) C[(uint64_t)row * N + col] = acc[i][j][v] * scale;
+      }
+    }
+}
+
 // GEMV: wave w handles rows w, w + W, ...; lane l reads 16-byte chunks
 // l, l + 64, ... of the row (8 BF16 each), four chunks in flight, and keeps
 // an FP32 running sum; the 64 partial sums are combined by a fixed butterfly.
@@ -212,6 +300,25 @@ __global__ void __launch_bounds__(256) gemv_bf16_kernel(const uint16_t* __restri
 
 hipError_t launch_gemm(int dtype, const void* a, const void* b, float* c, uint64_t m, uint64_t n,
                        uint64_t k, float scale, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  // Large tiles once they fill the chip (>= one 256x256 tile per CU).
+  const uint64_t nbig = ((m + kBig - 1) / kBig) * ((n + kBig - 1) / kBig);
+  if (nbig >= 256) {
+    const uint32_t shm = 4 * kBigTileLds;
+    const uint8_t* A = (const uint8_t*)a;
+    const uint8_t* B = (const uint8_t*)b;
+    switch (dtype) {
+      case CI_DT_F32:
+        return xlaunch(gemm256_kernel<CI_DT_F32>, dim3((uint32_t)nbig), dim3(256), shm, s, e0, e1, A, B,
+                       c, (uint32_t)m, (uint32_t)n, (uint32_t)k, scale);
+      case CI_DT_BF16:
+        return xlaunch(gemm256_kernel<CI_DT_BF16>, dim3((uint32_t)nbig), dim3(256), shm, s, e0, e1, A, B,
+                       c, (uint32_t)m, (uint32_t)n, (uint32_t)k, scale);
+      case CI_DT_FP8E4M3:
+        return xlaunch(gemm256_kernel<CI_DT_FP8E4M3>, dim3((uint32_t)nbig), dim3(256), shm, s, e0, e1, A,
+                       B, c, (uint32_t)m, (uint32_t)n, (uint32_t)k, scale);
+      default: return hipErrorInvalidValue;
+    }
+  }
   const uint64_t nb = ((m + kBM - 1) / kBM) * ((n + kBN - 1) / kBN);
   const uint32_t shm = 4 * kTileLds;
   const uint8_t* A = (const uint8_t*)a;

@@ -799,8 +799,8 @@ ci_status_t ci::launch_victim(ci_ctx* ctx, const ci_victim_desc_t* d, hipStream_
   switch (d->kind) {
     case CI_VICTIM_TRIAD_F32: {
       if (d->n == 0) {
-        e = hipEventRecord(e0, s);
-        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e0) e = hipEventRecord(e0, s);
+        if (e == hipSuccess && e1) e = hipEventRecord(e1, s);
         break;
       }
       uint64_t g = (d->n + 4095) / 4096;
@@ -865,6 +865,19 @@ extern "C" ci_status_t victim_run(ci_ctx_t* ctx, const ci_victim_desc_t* d, void
   if (st != CI_OK) return st;
   HIPCHK(hipSetDevice(ctx->device));
   return run_victim(ctx, d, (hipStream_t)stream, ctx->vstream, out);
+}
+
+extern "C" ci_status_t victim_enqueue(ci_ctx_t* ctx, const ci_victim_desc_t* d, void* stream,
+                                      uint32_t count) {
+  if (!ctx || !stream) return set_err(CI_ERR_INVALID_ARG, "victim_enqueue: NULL ctx or stream");
+  ci_status_t st = check_victim(d);
+  if (st != CI_OK) return st;
+  HIPCHK(hipSetDevice(ctx->device));
+  for (uint32_t i = 0; i < count; ++i) {
+    st = launch_victim(ctx, d, (hipStream_t)stream, nullptr, nullptr);
+    if (st != CI_OK) return st;
+  }
+  return CI_OK;
 }
 
 extern "C" ci_status_t ci_checksum_f32(ci_ctx_t* ctx, const void* x, uint64_t n, void* stream,

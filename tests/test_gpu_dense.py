@@ -84,7 +84,8 @@ def _quantise_host(x, dtype):
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
 @pytest.mark.parametrize("m,n,k", [(128, 128, 128), (256, 384, 512), (200, 130, 64), (1, 1, 16),
-                                   (512, 512, 1040), (1000, 777, 336)])
+                                   (512, 512, 1040), (1000, 777, 336),
+                                   (4100, 4000, 336)])   # large-tile path, ragged edges
 def test_gemm_matches_oracle(ctx, dev, dtype, m, n, k):
     import torch
     a, b = _gemm_inputs(dtype, m, n, k, 1000 + m + n + k)
@@ -194,3 +195,20 @@ def test_victims_identical_alone_and_colocated(ctx, dev):
         assert c["window_covered"], c
         print(f"gemm1024 vs {c['resource']}@{c['intensity']}: slowdown {c['slowdown']:.2f}")
     assert ctx.victim_run(d).checksum_bits == base
+
+
+def test_victim_enqueue_runs_back_to_back(ctx, dev):
+    import torch
+    n = (1 << 20) + 9
+    b = synth.uniform_f32(61, n)
+    c = synth.uniform_f32(62, n)
+    tb, tc = _t(b, dev), _t(c, dev)
+    ta = torch.zeros(n, dtype=torch.float32, device=dev)
+    s = torch.cuda.Stream(device=dev)
+    d = ctx.triad_desc(tb, tc, ta, passes=1)
+    ctx.victim_enqueue(d, s, 5)
+    s.synchronize()
+    assert np.array_equal(ta.cpu().numpy().view(np.uint32), oracle.triad_f32(b, c).view(np.uint32))
+    from paper_2501_16909_amd import coloc
+    with pytest.raises(coloc.CiError):
+        ctx.victim_enqueue(d, None, 1)
