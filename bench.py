@@ -33,9 +33,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def sha_of(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def sha_of(*paths):
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+# sources the HBM stressor's machine code is built from
+HBM_KERNEL_SOURCES = [os.path.join("paper_2501_16909_amd", "csrc", f) for f in ("k_memory.hip", "internal.h")]
 
 
 # --------------------------------------------------------------------------
@@ -113,15 +120,15 @@ class Suite:
             acc.setdefault("pair_" + placement, []).append(cell)
 
 
-def hbm_traffic(kernel_src):
+def hbm_traffic():
     """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source; else None."""
+    taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "hbm_triad_n2e30_counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         c = json.load(f)
-    if c.get("kernel_source_sha") != sha_of(kernel_src):
+    if c.get("kernel_source_sha") != sha_of(*[os.path.join(ROOT, p) for p in HBM_KERNEL_SOURCES]):
         return None
     return c.get("traffic_bytes_per_launch")
 
@@ -186,7 +193,7 @@ def run_suite(args):
     hbm = acc["hbm"]
     t_ns = float(np.mean(hbm["kernel_ns"]))
     achieved = hbm["units"] / t_ns  # GB/s (bytes per ns)
-    traffic = hbm_traffic(os.path.join(ROOT, "paper_2501_16909_amd", "csrc", "k_memory.hip"))
+    traffic = hbm_traffic()
     line = {
         "metric": METRIC,
         "value": round(achieved, 1),
@@ -434,21 +441,37 @@ def serve_trace(lam, seconds, seed):
     return reqs
 
 
-def serve_profiles(ctx, args):
+DUTIES = (10, 25, 50, 75, 100)
+
+
+def serve_profiles(ctx, args, axis="cu"):
     """Sensitivity profiles of the three request kinds at representative
     sizes (GEMM BF16 2048^3, GEMV BF16 8192^2, triad N = 2^24): slowdown
     curves (shared placement) on the resources the kinds themselves load --
     HBM, BF16 matrix cores, LDS -- and the pressure each kind exerts there,
-    its standalone rate over the matching stressor's standalone rate."""
+    its standalone rate over the matching stressor's standalone rate.
+
+    axis "cu": the stressor runs at full rate on a fraction x of the CUs.
+    axis "duty": the stressor runs on every CU, active a fraction of the
+    time; each duty level's standalone rate over the full rate is the curve's
+    abscissa, resampled onto the same five points."""
     import torch
     import synth
     dev = ctx.device
     ops = stressor_operands(dev)
     ws = torch.empty(256 + 256 * 8 * 48, dtype=torch.uint8, device=dev)
     rates = {}
+    duty_rates = {}
     for r, extra in (("hbm", dict(passes=1)), ("mfma_bf16", dict(iters=2048, passes=2)), ("lds", dict(passes=4))):
         rep = ctx.stressor(r, 1.0, ws=ws, **ops[r], **extra).stop()
         rates[r] = rep.units / (rep.kernel_ns * 1e-9)
+        if axis == "duty":
+            duty_rates[r] = {}
+            for duty in DUTIES:
+                rep = ctx.stressor(r, 1.0, ws=ws, duty=duty, **ops[r], **extra).stop()
+                duty_rates[r][duty] = rep.units / (rep.kernel_ns * 1e-9)
+            log(f"{r} duty rates (fraction of full): "
+                + ", ".join(f"{k}%: {v / rates[r]:.3f}" for k, v in duty_rates[r].items()))
     g = 2048
     A = torch.from_numpy(synth.uniform_f32(11, g * g)).to(dev)
     B = torch.from_numpy(synth.uniform_f32(12, g * g)).to(dev)
@@ -476,12 +499,27 @@ def serve_profiles(ctx, args):
     profiles = {}
     for kind, d in descs.items():
         t_alone = float(np.median([ctx.victim_run(d).time_ns for _ in range(5)])) * 1e-9
-        cells = ctx.measure_sensitivity(d, res, [ops[r] for r in res], INTENSITIES, reps=args.reps,
-                                        warmups=2, ws=ws, deadline_ms=args.deadline_ms)
         sens = {}
-        for i, r in enumerate(res):
-            row = cells[i * len(INTENSITIES):(i + 1) * len(INTENSITIES)]
-            sens[r] = [float(c["slowdown"]) if c["slowdown"] == c["slowdown"] else 1.0 for c in row]
+        if axis == "cu":
+            cells = ctx.measure_sensitivity(d, res, [ops[r] for r in res], INTENSITIES, reps=args.reps,
+                                            warmups=2, ws=ws, deadline_ms=args.deadline_ms)
+            for i, r in enumerate(res):
+                row = cells[i * len(INTENSITIES):(i + 1) * len(INTENSITIES)]
+                sens[r] = [float(c["slowdown"]) if c["slowdown"] == c["slowdown"] else 1.0 for c in row]
+        else:
+            xs = {r: [0.0] for r in res}
+            ys = {r: [1.0] for r in res}
+            for duty in DUTIES:
+                cells = ctx.measure_sensitivity(d, res, [dict(ops[r], duty=duty) for r in res], [1.0],
+                                                reps=args.reps, warmups=2, ws=ws,
+                                                deadline_ms=args.deadline_ms)
+                for i, r in enumerate(res):
+                    xs[r].append(duty_rates[r][duty] / rates[r])
+                    ys[r].append(float(cells[i]["slowdown"]))
+            for r in res:
+                order = np.argsort(xs[r], kind="stable")
+                sens[r] = [float(v) for v in np.interp(INTENSITIES, np.asarray(xs[r])[order],
+                                                       np.asarray(ys[r])[order])]
         press = {r: min(1.0, use[kind].get(r, 0.0) / t_alone / rates[r]) for r in res}
         profiles[kind] = {"sens": sens, "press": press, "occ": occ[kind]}
     return profiles
@@ -498,7 +536,7 @@ def run_serve(args):
         with open(args.profiles) as f:
             profiles = json.load(f)
     else:
-        profiles = serve_profiles(ctx, args)
+        profiles = serve_profiles(ctx, args, axis=args.profile_axis)
         log("profiles: " + json.dumps(profiles))
     out = {"metric": "serving latency p50/p99 and throughput, naive vs sensitivity-aware admission",
            "config": {"workload": "Poisson arrivals, 1/3 each BF16 GEMM n~logU[512,8192], BF16 GEMV "
@@ -790,8 +828,8 @@ def run_estimator(args):
     from paper_2501_16909_amd import coloc
     ctx = coloc.Context(0)
     dev = ctx.device
-    profiles = serve_profiles(ctx, args)
-    log("profiles: " + json.dumps(profiles))
+    axes = {"cu": serve_profiles(ctx, args, axis="cu"), "duty": serve_profiles(ctx, args, axis="duty")}
+    log("profiles: " + json.dumps(axes))
     # two independent instances of each kind (A's buffers and B's buffers)
     def make(kind, seed):
         if kind == "gemm":
@@ -830,22 +868,28 @@ def run_estimator(args):
                 col.append(ctx.victim_run(A[a]).time_ns)
                 side.synchronize()
             meas = float(np.median(col) / np.median(alone))
-            pred = predicted_pair_slowdown(profiles, a, b)
-            rows.append({"victim": a, "corunner": b, "measured": round(meas, 3), "predicted": round(pred, 3),
-                         "abs_err": round(abs(pred - meas), 3), "rel_err": round(abs(pred - meas) / meas, 3)})
-            log(json.dumps(rows[-1]))
-    err = np.array([r["rel_err"] for r in rows])
-    m = np.array([r["measured"] for r in rows])
-    p = np.array([r["predicted"] for r in rows])
+            row = {"victim": a, "corunner": b, "measured": round(meas, 3)}
+            for ax, prof in axes.items():
+                pred = predicted_pair_slowdown(prof, a, b)
+                row[f"predicted_{ax}"] = round(pred, 3)
+                row[f"rel_err_{ax}"] = round(abs(pred - meas) / meas, 3)
+            rows.append(row)
+            log(json.dumps(row))
     rank = lambda v: np.argsort(np.argsort(v))
-    spearman = float(np.corrcoef(rank(m), rank(p))[0, 1]) if len(rows) > 2 else None
+    m = np.array([r["measured"] for r in rows])
+    summary = {}
+    for ax in axes:
+        err = np.array([r[f"rel_err_{ax}"] for r in rows])
+        p = np.array([r[f"predicted_{ax}"] for r in rows])
+        summary[ax] = {"mean_rel_err": round(float(err.mean()), 3), "max_rel_err": round(float(err.max()), 3),
+                       "spearman": float(np.corrcoef(rank(m), rank(p))[0, 1]) if len(rows) > 2 else None}
     out = {"metric": "estimator error on workload pairs",
            "config": {"workload": "victims BF16 GEMM 2048^3, BF16 GEMV 8192^2, FP32 triad 2^24; co-runner "
                                   "enqueued back to back on a second stream; shared CUs",
                       "model": "product over HBM / BF16-MFMA / LDS of max(1, sensitivity curve at the "
-                               "co-runner's standalone pressure)"},
-           "pairs": rows, "mean_rel_err": round(float(err.mean()), 3),
-           "max_rel_err": round(float(err.max()), 3), "spearman": spearman, "profiles": profiles}
+                               "co-runner's standalone pressure); curves on two intensity axes: CU "
+                               "fraction at full rate ('cu') and duty cycle on every CU ('duty')"},
+           "pairs": rows, "axes": summary, "profiles": axes}
     ctx.close()
     _emit(out, args)
 
@@ -910,6 +954,8 @@ def main():
     ap.add_argument("--seconds", type=float, default=2.0, help="serve: trace length")
     ap.add_argument("--bound", type=float, default=1.5, help="serve: p99 slowdown bound")
     ap.add_argument("--profiles", default=None, help="serve: sensitivity profiles (JSON)")
+    ap.add_argument("--profile-axis", default="cu", choices=["cu", "duty"],
+                    help="serve: intensity axis of measured profiles (CU fraction or duty cycle)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the colocation "

@@ -195,7 +195,11 @@ typedef struct ci_stressor_opts {
                             DISPATCH: work-groups per launch (default 1e6)   */
   float fa, fb;          /* VALU chain x <- fma(x, fa, fb)                   */
   uint32_t deadline_ms;  /* in-kernel safety deadline, 0 = 2000 ms           */
-  uint32_t reserved;
+  uint32_t duty;         /* percent of time the stressor is active (1..100;
+                            0 = 100): after each pass (HBM: each chunk) a
+                            wave idles for (100/duty - 1) times the time the
+                            pass took, so the unit sees duty% of the load on
+                            every masked CU.  Ignored by DISPATCH / OCCUPANCY */
 } ci_stressor_opts_t;
 
 typedef struct ci_stressor_report {

@@ -51,7 +51,7 @@ class StressorOpts(C.Structure):
                 ("n", C.c_uint64), ("wg_per_cu", C.c_uint32), ("threads", C.c_uint32),
                 ("knob", C.c_uint32), ("vec", C.c_uint32), ("passes", C.c_uint64),
                 ("iters", C.c_uint64), ("fa", C.c_float), ("fb", C.c_float),
-                ("deadline_ms", C.c_uint32), ("reserved", C.c_uint32)]
+                ("deadline_ms", C.c_uint32), ("duty", C.c_uint32)]
 
 
 class StressorReport(C.Structure):

@@ -46,7 +46,7 @@ struct KCtrl {              // by-value kernel argument
   uint64_t announce_ticks;  // poller waits at most this long for the grid
   uint64_t passes;          // 0 = persistent
   uint32_t grid;
-  uint32_t pad;
+  uint32_t duty;            // percent active, 1..100
 };
 
 constexpr uint32_t kRecFlagDeadline = 1u;
@@ -126,6 +126,28 @@ __device__ __forceinline__ bool should_stop(StopState& s, const KCtrl& c) {
   }
   if (v) s.flags |= kRecFlagStop;
   return v != 0;
+}
+
+// Duty cycle (intensity along time instead of CUs).  A wave marks the start
+// of a busy stretch; at each duty point it idles for (100/duty - 1) times the
+// stretch it just worked, then marks again.  Duty points sit every few
+// microseconds of work, so a victim sees the load interleaved finely rather
+// than in long bursts.  With several stressor waves per SIMD the unit's load
+// is not linear in duty (a wave that works while others idle runs faster), so
+// callers take the measured rate, not duty, as the load.
+__device__ __forceinline__ uint64_t duty_mark(const KCtrl& c) {
+  return (c.duty >= 100u || c.duty == 0u) ? 0 : dev_now();
+}
+__device__ __forceinline__ void duty_point(const KCtrl& c, uint64_t& t_busy0) {
+  if (c.duty >= 100u || c.duty == 0u) return;
+  const uint64_t now = dev_now();
+  const uint64_t until = now + (now - t_busy0) * (100u - c.duty) / c.duty;
+  uint64_t t = now;
+  while (t < until) {
+    __builtin_amdgcn_s_sleep(2);
+    t = dev_now();
+  }
+  t_busy0 = t;
 }
 
 __device__ __forceinline__ void write_record(const KCtrl& c, uint32_t wg, uint64_t t0,

@@ -65,26 +65,30 @@ __global__ void __launch_bounds__(1024) lds_stressor(KCtrl c, const uint32_t* __
   stop_init(ws.st, c, t0, blockIdx.x == 0 && threadIdx.x == 0);
   uint32_t acc = 0;
   uint64_t passes = 0;
+  uint64_t tp = duty_mark(c);
   for (;;) {
     uint32_t* src = (passes & 1) ? lds + kWords : lds;
     uint32_t* dst = (passes & 1) ? lds : lds + kWords;
     uint32_t v = v0;
+    for (uint32_t kg = 0; kg < kVec; kg += 256) {
+      duty_point(c, tp);
 #pragma unroll 8
-    for (uint32_t k = 0; k < kVec; ++k) {
-      if constexpr (VW == 4) {
-        const uint4 x = *reinterpret_cast<const uint4*>(src + v * 4);
-        *reinterpret_cast<uint4*>(dst + v * 4) = x;
-        acc += x.x + x.y + x.z + x.w;
-      } else if constexpr (VW == 2) {
-        const uint2 x = *reinterpret_cast<const uint2*>(src + v * 2);
-        *reinterpret_cast<uint2*>(dst + v * 2) = x;
-        acc += x.x + x.y;
-      } else {
-        const uint32_t x = src[v];
-        dst[v] = x;
-        acc += x;
+      for (uint32_t k = 0; k < 256; ++k) {
+        if constexpr (VW == 4) {
+          const uint4 x = *reinterpret_cast<const uint4*>(src + v * 4);
+          *reinterpret_cast<uint4*>(dst + v * 4) = x;
+          acc += x.x + x.y + x.z + x.w;
+        } else if constexpr (VW == 2) {
+          const uint2 x = *reinterpret_cast<const uint2*>(src + v * 2);
+          *reinterpret_cast<uint2*>(dst + v * 2) = x;
+          acc += x.x + x.y;
+        } else {
+          const uint32_t x = src[v];
+          dst[v] = x;
+          acc += x;
+        }
+        v = (v + 1) & (kVec - 1);
       }
-      v = (v + 1) & (kVec - 1);
     }
     ++passes;
     if (c.passes) {
@@ -125,16 +129,29 @@ __global__ void __launch_bounds__(1024) valu_stressor(KCtrl c, float* __restrict
   stop_init(ws.st, c, t0, blockIdx.x == 0 && threadIdx.x == 0);
   const uint32_t blocks = iters >> 3, rem = iters & 7u;
   uint64_t passes = 0;
+  uint64_t tp = duty_mark(c);
   for (;;) {
-    for (uint32_t blk = 0; blk < blocks; ++blk) {
+    // groups of 64 blocks of 8 steps, a duty point after each group
+    uint32_t blk = 0;
+    for (; blk + 64 <= blocks; blk += 64) {
+#pragma nounroll
+      for (uint32_t g = 0; g < 64; ++g)
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int j = 0; j < ILP; ++j) x[j] = __builtin_fmaf(x[j], fa, vb);
+      duty_point(c, tp);
+    }
+#pragma nounroll
+    for (; blk < blocks; ++blk)
 #pragma unroll
       for (int u = 0; u < 8; ++u)
 #pragma unroll
         for (int j = 0; j < ILP; ++j) x[j] = __builtin_fmaf(x[j], fa, vb);
-    }
     for (uint32_t r = 0; r < rem; ++r)
 #pragma unroll
       for (int j = 0; j < ILP; ++j) x[j] = __builtin_fmaf(x[j], fa, vb);
+    duty_point(c, tp);
     ++passes;
     if (c.passes) {
       if (passes >= c.passes) break;
@@ -166,16 +183,29 @@ __global__ void __launch_bounds__(1024) valu64_stressor(KCtrl c, double* __restr
   stop_init(ws.st, c, t0, blockIdx.x == 0 && threadIdx.x == 0);
   const uint32_t blocks = iters >> 3, rem = iters & 7u;
   uint64_t passes = 0;
+  uint64_t tp = duty_mark(c);
   for (;;) {
-    for (uint32_t blk = 0; blk < blocks; ++blk) {
+    // groups of 64 blocks of 8 steps, a duty point after each group
+    uint32_t blk = 0;
+    for (; blk + 64 <= blocks; blk += 64) {
+#pragma nounroll
+      for (uint32_t g = 0; g < 64; ++g)
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int j = 0; j < ILP; ++j) x[j] = __dmul_rn(x[j], fa);
+      duty_point(c, tp);
+    }
+#pragma nounroll
+    for (; blk < blocks; ++blk)
 #pragma unroll
       for (int u = 0; u < 8; ++u)
 #pragma unroll
         for (int j = 0; j < ILP; ++j) x[j] = __dmul_rn(x[j], fa);
-    }
     for (uint32_t r = 0; r < rem; ++r)
 #pragma unroll
       for (int j = 0; j < ILP; ++j) x[j] = __dmul_rn(x[j], fa);
+    duty_point(c, tp);
     ++passes;
     if (c.passes) {
       if (passes >= c.passes) break;
@@ -293,11 +323,20 @@ __global__ void __launch_bounds__(1024) mfma_stressor(KCtrl c, const void* __res
   WgStop ws;
   stop_init(ws.st, c, t0, blockIdx.x == 0 && threadIdx.x == 0);
   uint64_t passes = 0;
+  uint64_t tp = duty_mark(c);
   for (;;) {
-    for (uint64_t it = 0; it < iters; ++it) {
+    // groups of 32 steps, a duty point after each group
+    uint64_t it = 0;
+    for (; it + 32 <= iters; it += 32) {
+      for (int g = 0; g < 32; ++g)
+#pragma unroll
+        for (int q = 0; q < NACC; ++q) acc[q] = Op::mma(fa, fb, acc[q]);
+      duty_point(c, tp);
+    }
+    for (; it < iters; ++it)
 #pragma unroll
       for (int q = 0; q < NACC; ++q) acc[q] = Op::mma(fa, fb, acc[q]);
-    }
+    duty_point(c, tp);
     ++passes;
     if (c.passes) {
       if (passes >= c.passes) break;
@@ -342,11 +381,14 @@ __global__ void __launch_bounds__(1024) chase_stressor(KCtrl c, const uint32_t* 
   WgStop ws;
   stop_init(ws.st, c, t0, blockIdx.x == 0 && threadIdx.x == 0);
   uint64_t passes = 0;
+  uint64_t tp = duty_mark(c);
   for (;;) {
     for (uint64_t h = 0; h < hops; ++h) {
+      if ((h & 15u) == 15u) duty_point(c, tp);
 #pragma unroll
       for (int j = 0; j < CH; ++j) idx[j] = min(next[idx[j]], nmax);  // clamp: a bad table cannot read out of bounds
     }
+    duty_point(c, tp);
     ++passes;
     if (c.passes) {
       if (passes >= c.passes) break;

@@ -97,16 +97,19 @@ __global__ void __launch_bounds__(1024) triad_stressor(KCtrl c, const float* __r
   uint64_t done = 0;
   StopState st;
   stop_init(st, c, t0, blockIdx.x == 0 && wid == 0);
+  uint64_t tp = duty_mark(c);
   if (c.passes) {
     for (uint64_t p = 0; p < c.passes; ++p)
       for (uint64_t ch = gw; ch < nchunks; ch += nw) {
         triad_chunk<NT>(b, cc, a, ch * kChunk, n, lane);
+        duty_point(c, tp);
         ++done;
       }
   } else if (gw < nchunks) {
     uint64_t ch = gw;
     for (;;) {
       triad_chunk<NT>(b, cc, a, ch * kChunk, n, lane);
+      duty_point(c, tp);
       ++done;
       ch += nw;
       if (ch >= nchunks) ch = gw;
@@ -191,8 +194,10 @@ __global__ void __launch_bounds__(1024) cache_stressor(KCtrl c, const uint32_t* 
   stop_init(st, c, t0, blockIdx.x == 0 && threadIdx.x == 0);
   uint32_t acc = 0;
   uint64_t passes = 0;
+  uint64_t tp = duty_mark(c);
   for (;;) {
     for (uint32_t bt = 0; bt < batch; ++bt) {
+      duty_point(c, tp);
       // rounds [phase, rounds) then [0, phase): each word once per pass
       for (int part = 0; part < 2; ++part) {
         uint32_t r = part ? 0u : phase;

@@ -316,6 +316,7 @@ uint64_t cache_span_words(ci_resource_t r, const ci_stressor_opts_t& o, uint32_t
 }
 
 ci_status_t check_opts(ci_ctx* ctx, ci_resource_t r, const ci_stressor_opts_t& o, uint32_t grid) {
+  if (o.duty > 100) return set_err(CI_ERR_INVALID_ARG, "%s: duty %u%% > 100", kResName[r], o.duty);
   if (o.threads == 0 || o.threads > 1024 || o.threads % 64)
     return set_err(CI_ERR_INVALID_ARG, "%s: threads %u must be a multiple of 64 in [64, 1024]",
                    kResName[r], o.threads);
@@ -598,6 +599,7 @@ extern "C" ci_status_t stressor_launch(ci_ctx_t* ctx, ci_resource_t r, float int
   c.announce_ticks = 50 * khz;                        // 50 ms
   c.passes = h->o.passes;
   c.grid = h->grid;
+  c.duty = h->o.duty == 0 ? 100u : h->o.duty;
   st = launch_kernel(h, c);
   if (st != CI_OK) {
     delete h;

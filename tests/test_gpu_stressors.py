@@ -278,3 +278,63 @@ def test_valu64_stressor_fixed(ctx, dev, ilp, iters, passes, x, a):
     want = oracle.valu64_outputs(sel, ilp, a, iters * passes)
     assert np.array_equal(got[sel].view(np.uint64), want.view(np.uint64))
     assert rep.units == float(threads) * ilp * iters * passes
+
+
+# ------------------------------------------------------------ duty cycle
+def test_duty_cycle_keeps_results_and_scales_time(ctx, dev):
+    """A duty-cycled stressor does the same work with the same results; it
+    only idles between stretches of work.  With one wave per SIMD nothing
+    else fills the idle issue slots, so at a fixed clock the launch takes
+    100/duty times as long; with several waves per SIMD the rate still falls
+    with duty."""
+    import torch
+    a, b = 1 - 2.0 ** -12, 2.0 ** -12
+
+    def run(duty, wg, iters, passes):
+        threads = 256 * wg * 256
+        out = torch.empty(threads * 4, dtype=torch.float32, device=dev)
+        rep = ctx.stressor("valu_f32", 1.0, dst=out, knob=4, iters=iters, passes=passes, fa=a, fb=b,
+                           wg_per_cu=wg, threads=256, duty=duty).stop()
+        assert rep.units == 2.0 * threads * 4 * iters * passes
+        return out.cpu().numpy(), rep.kernel_ns
+
+    outs, times = {}, {}
+    for duty in (100, 50, 25):
+        outs[duty], times[duty] = run(duty, 1, 40000, 8)
+    assert np.array_equal(outs[100].view(np.uint32), outs[50].view(np.uint32))
+    assert np.array_equal(outs[100].view(np.uint32), outs[25].view(np.uint32))
+    threads = 256 * 256
+    sel = np.arange(0, threads, 1013)
+    want = oracle.valu_outputs(sel, 4, a, b, 40000 * 8)
+    assert np.array_equal(outs[25].reshape(threads, 4)[sel].view(np.uint32), want.view(np.uint32))
+    # the wave idles as long as it worked at 50% and three times as long at
+    # 25%: twice the launch time.  Against 100% the ratio is smaller: with the
+    # VALUs of every CU busy the chip lowers its clock, at half duty it does not.
+    assert 1.8 < times[25] / times[50] < 2.2, times
+    assert 1.15 < times[50] / times[100] < 2.2, times
+    # default shape: four work-groups per CU share each SIMD
+    t4 = {d: run(d, 4, 20000, 4)[1] for d in (100, 50, 25)}
+    assert t4[100] < t4[50] < t4[25], t4
+    # the MFMA and LDS loops keep their results under a duty cycle too
+    da, db, fa, fb = _mfma_operands("bf16", "ones")
+    waves = 256 * 2 * 4
+    out = torch.empty(waves * 4 * 1024, dtype=torch.float32, device=dev)
+    ctx.stressor("mfma_bf16", 1.0, src0=_t(da, dev), src1=_t(db, dev), dst=out, knob=4, iters=100,
+                 passes=3, duty=40).stop()
+    assert np.all(out.cpu().numpy().reshape(-1, 32, 32) == oracle.mfma_tile_expected(fa, fb, 300))
+    w = synth.u32(synth.seed_for(1, synth.BUF_LDS), 8192)
+    for vec in (1, 4):
+        st = ctx.stressor("lds", 0.25, src0=_t(w.view(np.int32), dev), vec=vec, knob=3, passes=3, duty=30)
+        st.stop()
+        rec = st.records()
+        assert np.array_equal(rec["check"].astype(np.uint32),
+                              oracle.lds_wg_expected(w, vec, 3, waves=16, passes=rec["work"]))
+
+
+def test_duty_out_of_range_rejected(ctx, dev):
+    from paper_2501_16909_amd import coloc
+    import torch
+    out = torch.empty(1 << 16, dtype=torch.float32, device=dev)
+    with pytest.raises(coloc.CiError) as ei:
+        ctx.stressor("valu_f32", 0.25, dst=out, duty=101)
+    assert ei.value.status == 1
