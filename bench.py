@@ -541,7 +541,8 @@ def run_serve(args):
     out = {"metric": "serving latency p50/p99 and throughput, naive vs sensitivity-aware admission",
            "config": {"workload": "Poisson arrivals, 1/3 each BF16 GEMM n~logU[512,8192], BF16 GEMV "
                                   "n~logU[4096,16384], FP32 triad N~logU[2^20,2^28]",
-                      "seconds": args.seconds, "slots": 4, "hbm_budget_gib": 32},
+                      "seconds": args.seconds, "slots": 4, "hbm_budget_gib": 32,
+                      "profile_axis": args.profile_axis},
            "runs": []}
     iso_cache = {}
     for lam in args.rates:
@@ -954,7 +955,7 @@ def main():
     ap.add_argument("--seconds", type=float, default=2.0, help="serve: trace length")
     ap.add_argument("--bound", type=float, default=1.5, help="serve: p99 slowdown bound")
     ap.add_argument("--profiles", default=None, help="serve: sensitivity profiles (JSON)")
-    ap.add_argument("--profile-axis", default="cu", choices=["cu", "duty"],
+    ap.add_argument("--profile-axis", default="duty", choices=["cu", "duty"],
                     help="serve: intensity axis of measured profiles (CU fraction or duty cycle)")
     args = ap.parse_args()
     if args.gpus != 1:
