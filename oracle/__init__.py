@@ -21,6 +21,7 @@ Parity status per function (pins are in tests/test_oracle_pins.py):
   gemm_f64, gemv_f64, mfma_tile_expected ........ pinned
   slowdown, pct_of_peak ......................... pinned (paper Table 1 values)
   admit / simulate_admission .................... pinned
+  decode (submodule: synthetic decode step) ..... pinned
 """
 from __future__ import annotations
 
