@@ -336,6 +336,141 @@ ci_status_t measure_sensitivity(ci_ctx_t* ctx, const ci_victim_desc_t* d,
                                 const float* xs, int nx, const ci_measure_opts_t* o, void* ws,
                                 size_t ws_bytes, void* stream, ci_cell_t* cells);
 
+/* -------------------------------------------------------- decode victim */
+/* One decode step of a Llama-style decoder with random weights: the
+ * stand-in for the paper's LLM decode victims (Sections 4.2-4.4), whose
+ * weights and serving stack are not available.  Fig. 5 breaks one decode
+ * step into its kernels; the step here is timed kernel by kernel too.
+ * Per layer: RMS norm -> QKV GEMV -> rotary embedding and KV-cache append ->
+ * grouped-query attention (chunked over the context, then merged) -> output
+ * GEMV + residual -> RMS norm -> gate/up GEMV -> SiLU(gate) * up -> down
+ * GEMV + residual; after the last layer a final RMS norm and the
+ * vocabulary GEMV.  BF16 weights, cache and GEMV inputs; FP32 accumulation,
+ * residual stream and GEMV outputs. */
+typedef enum ci_decode_kernel {
+  CI_DK_ATTN_NORM = 0, CI_DK_QKV = 1, CI_DK_ROPE = 2, CI_DK_ATTN = 3, CI_DK_ATTN_COMBINE = 4,
+  CI_DK_OPROJ = 5, CI_DK_MLP_NORM = 6, CI_DK_GATE_UP = 7, CI_DK_SILU = 8, CI_DK_DOWN = 9,
+  CI_DK_FINAL_NORM = 10, CI_DK_LM_HEAD = 11, CI_DK_COUNT = 12
+} ci_decode_kernel_t;
+
+typedef struct ci_decode_config {
+  uint32_t hidden;     /* model width; multiple of 8                          */
+  uint32_t n_q;        /* query heads                                          */
+  uint32_t n_kv;       /* key/value heads; n_q / n_kv in 1..16                 */
+  uint32_t head_dim;   /* 128 or 256                                           */
+  uint32_t ffn;        /* MLP width; multiple of 8                             */
+  uint32_t vocab;      /* output rows; 0 = no vocabulary projection            */
+  uint32_t layers;     /* >= 1                                                 */
+  uint32_t batch;      /* sequences per step, 1..8                             */
+  uint32_t max_ctx;    /* cache positions per sequence                         */
+  float eps;           /* RMS-norm epsilon                                     */
+  float rope_base;     /* rotary base (pair i turns by pos * base^(-2i/head_dim)) */
+} ci_decode_config_t;
+
+/* Element offsets (BF16 elements) into the weight arena, and sizes.  Layer
+ * l's tensors sit at the layer-0 offset + l * layer_stride.  Every offset is
+ * a multiple of 64 elements (128 bytes).
+ *   g_attn, g_mlp, g_final: hidden gains
+ *   w_qkv: (n_q + 2 n_kv) * head_dim rows x hidden (query heads, key heads,
+ *          value heads; head h at rows h * head_dim ..)
+ *   w_o: hidden x (n_q * head_dim)     w_gu: 2 ffn x hidden (gate, then up)
+ *   w_down: hidden x ffn               w_lm: vocab x hidden              */
+typedef struct ci_decode_layout {
+  uint64_t g_attn, w_qkv, w_o, g_mlp, w_gu, w_down;
+  uint64_t layer_stride;
+  uint64_t g_final, w_lm;
+  uint64_t weight_elems;    /* arena size in BF16 elements                     */
+  uint64_t cache_elems;     /* per cache tensor: layers x batch x n_kv x max_ctx x head_dim */
+  uint64_t workspace_bytes; /* device workspace decode_step needs              */
+  uint64_t attn_part_bytes; /* workspace ci_attention_decode needs             */
+} ci_decode_layout_t;
+
+/* Validates cfg and fills the layout.  CI_ERR_INVALID_ARG on a bad config. */
+ci_status_t decode_layout(const ci_decode_config_t* cfg, ci_decode_layout_t* out);
+
+typedef struct ci_decode_desc {
+  ci_decode_config_t cfg;
+  const void* weights;  /* device BF16 arena laid out by decode_layout          */
+  void* k_cache;        /* device BF16 [layers][batch][n_kv][max_ctx][head_dim] */
+  void* v_cache;        /* same shape                                            */
+  const int32_t* pos;   /* HOST int32[batch]: position of the new token, in
+                           [0, max_ctx); it attends to positions 0 .. pos     */
+  const float* x_in;    /* device FP32 [batch][hidden]                          */
+  float* x_out;         /* device FP32 [batch][hidden]                          */
+  float* logits;        /* device FP32 [batch][vocab]; may be NULL if vocab 0   */
+  void* work;           /* device workspace of layout.workspace_bytes           */
+} ci_decode_desc_t;
+
+typedef struct ci_decode_result {
+  double step_ns;                /* first kernel's start to last kernel's end */
+  double kernel_ns[CI_DK_COUNT]; /* per kernel kind, summed over layers       */
+  uint64_t checksum_bits;        /* bit-pattern sum of logits (x_out if vocab 0) */
+  double sum_f64;                /* FP64 sum of the same                       */
+  uint64_t t_begin, t_end;       /* device clock around the step               */
+} ci_decode_result_t;
+
+/* Run one decode step on `stream` and wait for it.  The step reads x_in and
+ * the cache, writes entry pos[b] of every layer's cache, x_out and logits;
+ * with unchanged inputs, repeated steps give bit-identical outputs.  Every
+ * kernel launch carries its own start/stop events. */
+ci_status_t decode_step(ci_ctx_t* ctx, const ci_decode_desc_t* d, void* stream,
+                        ci_decode_result_t* out);
+
+typedef struct ci_decode_cell {
+  int resource;
+  float intensity;
+  uint32_t duty;
+  int ncu;
+  double step_alone_p50, step_alone_p90;  /* ns, over the reps               */
+  double step_col_p50, step_col_p90;
+  double kernel_alone_ns[CI_DK_COUNT];    /* medians over the reps           */
+  double kernel_col_ns[CI_DK_COUNT];
+  double stressor_achieved, stressor_pct_peak;  /* means over the reps        */
+  int window_covered, output_equal, timed_out, reps;
+} ci_decode_cell_t;
+
+/* measure_sensitivity for the decode step: for every resource rs[i] and
+ * intensity xs[j], warm up, then `reps` times run a step alone and one
+ * colocated with the stressor (persistent mode, shared or disjoint
+ * placement), checking stressor window and output of each colocated step.
+ * Reports p50/p90 step times and per-kernel medians (Fig. 5 breakdown). */
+ci_status_t measure_decode(ci_ctx_t* ctx, const ci_decode_desc_t* d, const ci_resource_t* rs,
+                           const ci_stressor_opts_t* sopts, int nr, const float* xs, int nx,
+                           const ci_measure_opts_t* o, void* ws, size_t ws_bytes, void* stream,
+                           ci_decode_cell_t* cells);
+
+/* The step's kernels one at a time (device pointers, synchronous on
+ * `stream`), for parity tests and for callers composing their own step.
+ *   ci_rmsnorm_bf16: y[r] = bf16(x[r] / sqrt(mean(x[r]^2) + eps) * g),
+ *     rows x n, n a multiple of 4.
+ *   ci_gemv_bf16_rows: out[b][i] = res[b][i] (res may be NULL or alias out)
+ *     + sum_j w[i][j] v[b][j]; w rows x k, v batch x k (batch 1..8), k a
+ *     multiple of 8, w and v 16-byte aligned.
+ *   ci_rope_append: rotates the query and key heads of qkv (batch x
+ *     (n_q + 2 n_kv) x head_dim FP32) at position pos[b] (HOST array), writes
+ *     the queries to q_out (batch x n_q x head_dim FP32) and the BF16 keys
+ *     and values to entry pos[b] of k_cache / v_cache (one layer:
+ *     batch x n_kv x max_ctx x head_dim).
+ *   ci_attention_decode: out (batch x n_q*head_dim BF16) = softmax(q K^T /
+ *     sqrt(head_dim)) V over positions 0 .. pos[b]; part: device scratch of
+ *     layout.attn_part_bytes for this batch, n_q, head_dim and max_ctx.
+ *   ci_silu_mul_bf16: h[b][j] = bf16(g / (1 + exp(-g)) * u) with
+ *     g = gu[b][j], u = gu[b][ffn + j]. */
+ci_status_t ci_rmsnorm_bf16(ci_ctx_t* ctx, const float* x, const uint16_t* g, uint32_t rows,
+                            uint32_t n, float eps, uint16_t* y, void* stream);
+ci_status_t ci_gemv_bf16_rows(ci_ctx_t* ctx, const uint16_t* w, const uint16_t* v, const float* res,
+                              float* out, uint32_t rows, uint32_t k, uint32_t batch, void* stream);
+ci_status_t ci_rope_append(ci_ctx_t* ctx, const float* qkv, const int32_t* pos, uint32_t batch,
+                           uint32_t n_q, uint32_t n_kv, uint32_t head_dim, uint32_t max_ctx,
+                           float rope_base, float* q_out, uint16_t* k_cache, uint16_t* v_cache,
+                           void* stream);
+ci_status_t ci_attention_decode(ci_ctx_t* ctx, const float* q, const uint16_t* k_cache,
+                                const uint16_t* v_cache, const int32_t* pos, uint32_t batch,
+                                uint32_t n_q, uint32_t n_kv, uint32_t head_dim, uint32_t max_ctx,
+                                void* part, size_t part_bytes, uint16_t* out, void* stream);
+ci_status_t ci_silu_mul_bf16(ci_ctx_t* ctx, const float* gu, uint32_t batch, uint32_t ffn,
+                             uint16_t* h, void* stream);
+
 /* ------------------------------------------------------------- serving */
 typedef enum ci_policy_kind {
   CI_POLICY_NAIVE = 0,       /* admit when memory and a slot are free          */

@@ -18,8 +18,8 @@ ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["k_memory.hip", "k_compute.hip", "k_dense.hip", "k_util.hip", "runtime.hip",
-           "serve.hip"]
+SOURCES = ["k_memory.hip", "k_compute.hip", "k_dense.hip", "k_util.hip", "k_decode.hip", "runtime.hip",
+           "serve.hip", "decode.hip"]
 LIB = os.path.join(HERE, "libcoloc.so")
 SYNTH_SRC = os.path.join(ROOT, "synth", "fill.hip")
 SYNTH_LIB = os.path.join(ROOT, "synth", "libsynth.so")

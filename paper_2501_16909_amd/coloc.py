@@ -111,6 +111,48 @@ class Served(C.Structure):
                 ("slot", C.c_int), ("status", C.c_int)]
 
 
+DECODE_KERNELS = ["attn_norm", "qkv", "rope", "attn", "attn_combine", "oproj", "mlp_norm", "gate_up",
+                  "silu", "down", "final_norm", "lm_head"]
+NDK = len(DECODE_KERNELS)
+
+
+class DecodeConfig(C.Structure):
+    _fields_ = [("hidden", C.c_uint32), ("n_q", C.c_uint32), ("n_kv", C.c_uint32),
+                ("head_dim", C.c_uint32), ("ffn", C.c_uint32), ("vocab", C.c_uint32),
+                ("layers", C.c_uint32), ("batch", C.c_uint32), ("max_ctx", C.c_uint32),
+                ("eps", C.c_float), ("rope_base", C.c_float)]
+
+
+class DecodeLayout(C.Structure):
+    _fields_ = [("g_attn", C.c_uint64), ("w_qkv", C.c_uint64), ("w_o", C.c_uint64),
+                ("g_mlp", C.c_uint64), ("w_gu", C.c_uint64), ("w_down", C.c_uint64),
+                ("layer_stride", C.c_uint64), ("g_final", C.c_uint64), ("w_lm", C.c_uint64),
+                ("weight_elems", C.c_uint64), ("cache_elems", C.c_uint64),
+                ("workspace_bytes", C.c_uint64), ("attn_part_bytes", C.c_uint64)]
+
+
+class DecodeDesc(C.Structure):
+    _fields_ = [("cfg", DecodeConfig), ("weights", C.c_void_p), ("k_cache", C.c_void_p),
+                ("v_cache", C.c_void_p), ("pos", C.POINTER(C.c_int32)), ("x_in", C.c_void_p),
+                ("x_out", C.c_void_p), ("logits", C.c_void_p), ("work", C.c_void_p)]
+
+
+class DecodeResult(C.Structure):
+    _fields_ = [("step_ns", C.c_double), ("kernel_ns", C.c_double * NDK),
+                ("checksum_bits", C.c_uint64), ("sum_f64", C.c_double),
+                ("t_begin", C.c_uint64), ("t_end", C.c_uint64)]
+
+
+class DecodeCell(C.Structure):
+    _fields_ = [("resource", C.c_int), ("intensity", C.c_float), ("duty", C.c_uint32),
+                ("ncu", C.c_int), ("step_alone_p50", C.c_double), ("step_alone_p90", C.c_double),
+                ("step_col_p50", C.c_double), ("step_col_p90", C.c_double),
+                ("kernel_alone_ns", C.c_double * NDK), ("kernel_col_ns", C.c_double * NDK),
+                ("stressor_achieved", C.c_double), ("stressor_pct_peak", C.c_double),
+                ("window_covered", C.c_int), ("output_equal", C.c_int), ("timed_out", C.c_int),
+                ("reps", C.c_int)]
+
+
 EXPORTS = {
     "ci_init": ([C.c_int, C.POINTER(C.c_void_p)], C.c_int),
     "ci_shutdown": ([C.c_void_p], C.c_int),
@@ -137,6 +179,22 @@ EXPORTS = {
     "serve_run": ([C.c_void_p, C.POINTER(Request), C.c_int, C.POINTER(Policy), C.POINTER(Served)], C.c_int),
     "ci_admit": ([C.POINTER(Policy), C.POINTER(C.c_int), C.c_int, C.c_int, C.c_uint64, C.c_uint64,
                   C.POINTER(C.c_int)], C.c_int),
+    "decode_layout": ([C.POINTER(DecodeConfig), C.POINTER(DecodeLayout)], C.c_int),
+    "decode_step": ([C.c_void_p, C.POINTER(DecodeDesc), C.c_void_p, C.POINTER(DecodeResult)], C.c_int),
+    "measure_decode": ([C.c_void_p, C.POINTER(DecodeDesc), C.POINTER(C.c_int), C.POINTER(StressorOpts),
+                        C.c_int, C.POINTER(C.c_float), C.c_int, C.POINTER(MeasureOpts), C.c_void_p,
+                        C.c_size_t, C.c_void_p, C.POINTER(DecodeCell)], C.c_int),
+    "ci_rmsnorm_bf16": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_float,
+                         C.c_void_p, C.c_void_p], C.c_int),
+    "ci_gemv_bf16_rows": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32,
+                           C.c_uint32, C.c_uint32, C.c_void_p], C.c_int),
+    "ci_rope_append": ([C.c_void_p, C.c_void_p, C.POINTER(C.c_int32), C.c_uint32, C.c_uint32, C.c_uint32,
+                        C.c_uint32, C.c_uint32, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p,
+                        C.c_void_p], C.c_int),
+    "ci_attention_decode": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32),
+                             C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_void_p,
+                             C.c_size_t, C.c_void_p, C.c_void_p], C.c_int),
+    "ci_silu_mul_bf16": ([C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p], C.c_int),
 }
 
 _LIB = None
@@ -442,6 +500,109 @@ class Context:
             out[-1]["resource"] = RESOURCES[c.resource]
         return out
 
+    # ------------------------------------------------------------- decode
+    @staticmethod
+    def decode_layout(cfg: dict) -> DecodeLayout:
+        c = DecodeConfig(**{f: cfg[f] for f, _ in DecodeConfig._fields_})
+        out = DecodeLayout()
+        _check(load_library().decode_layout(C.byref(c), C.byref(out)))
+        return out
+
+    def decode_step(self, model: "DecodeModel") -> dict:
+        self._sync_torch()
+        r = DecodeResult()
+        _check(load_library().decode_step(self.handle, C.byref(model.desc), _stream_handle(self.stream),
+                                          C.byref(r)))
+        return {"step_ns": r.step_ns, "kernel_ns": dict(zip(DECODE_KERNELS, list(r.kernel_ns))),
+                "checksum_bits": r.checksum_bits, "sum_f64": r.sum_f64, "t_begin": r.t_begin,
+                "t_end": r.t_end}
+
+    def measure_decode(self, model: "DecodeModel", resources, opts_list, intensities, reps: int = 10,
+                       warmups: int = 2, placement: str = "shared", deadline_ms: int = 2000, ws=None):
+        import torch
+        self._sync_torch()
+        nr, nx = len(resources), len(intensities)
+        rs = (C.c_int * nr)(*[RES[r] for r in resources])
+        so = (StressorOpts * nr)(*[make_opts(**o) for o in opts_list])
+        xs = (C.c_float * nx)(*[float(x) for x in intensities])
+        mo = MeasureOpts(reps, warmups, 1 if placement == "disjoint" else 0, deadline_ms)
+        if ws is None:
+            need = 256
+            for i in range(nr):
+                b = C.c_size_t()
+                _check(load_library().ci_workspace_size(rs[i], C.byref(so[i]), self.info.num_cus, C.byref(b)))
+                need = max(need, int(b.value))
+            ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        cells = (DecodeCell * (nr * nx))()
+        _check(load_library().measure_decode(self.handle, C.byref(model.desc), rs, so, nr, xs, nx,
+                                             C.byref(mo), _ptr(ws), ws.numel(),
+                                             _stream_handle(self.stream), cells))
+        out = []
+        for c in cells:
+            d = {f: getattr(c, f) for f, _ in DecodeCell._fields_ if not f.startswith("kernel_")}
+            d["resource"] = RESOURCES[c.resource]
+            d["kernel_alone_ns"] = dict(zip(DECODE_KERNELS, list(c.kernel_alone_ns)))
+            d["kernel_col_ns"] = dict(zip(DECODE_KERNELS, list(c.kernel_col_ns)))
+            out.append(d)
+        return out
+
+    def rmsnorm_bf16(self, x, g, eps: float, y=None):
+        import torch
+        self._sync_torch()
+        rows, n = x.shape
+        if y is None:
+            y = torch.empty((rows, n), dtype=torch.int16, device=x.device)
+        _check(load_library().ci_rmsnorm_bf16(self.handle, _ptr(x), _ptr(g), rows, n, float(eps), _ptr(y),
+                                              _stream_handle(self.stream)))
+        return y
+
+    def gemv_bf16_rows(self, w, v, res=None, out=None):
+        """out[b] = res[b] + w @ v[b]; w rows x k BF16 codes, v batch x k."""
+        import torch
+        self._sync_torch()
+        rows, k = w.shape
+        batch = v.shape[0]
+        if out is None:
+            out = torch.empty((batch, rows), dtype=torch.float32, device=w.device)
+        _check(load_library().ci_gemv_bf16_rows(self.handle, _ptr(w), _ptr(v), _ptr(res), _ptr(out), rows, k,
+                                                batch, _stream_handle(self.stream)))
+        return out
+
+    def rope_append(self, qkv, pos, n_q: int, n_kv: int, head_dim: int, max_ctx: int, rope_base: float,
+                    q_out, k_cache, v_cache):
+        self._sync_torch()
+        batch = len(pos)
+        p = (C.c_int32 * batch)(*[int(v) for v in pos])
+        _check(load_library().ci_rope_append(self.handle, _ptr(qkv), p, batch, n_q, n_kv, head_dim, max_ctx,
+                                             float(rope_base), _ptr(q_out), _ptr(k_cache), _ptr(v_cache),
+                                             _stream_handle(self.stream)))
+
+    def attention_decode(self, q, k_cache, v_cache, pos, n_q: int, n_kv: int, head_dim: int, max_ctx: int,
+                         out=None):
+        import torch
+        self._sync_torch()
+        batch = len(pos)
+        lay = self.decode_layout(dict(hidden=8, n_q=n_q, n_kv=n_kv, head_dim=head_dim, ffn=8, vocab=0,
+                                      layers=1, batch=batch, max_ctx=max_ctx, eps=0.0, rope_base=1.0))
+        part = torch.empty(max(int(lay.attn_part_bytes), 16), dtype=torch.uint8, device=q.device)
+        if out is None:
+            out = torch.empty((batch, n_q * head_dim), dtype=torch.int16, device=q.device)
+        p = (C.c_int32 * batch)(*[int(v) for v in pos])
+        _check(load_library().ci_attention_decode(self.handle, _ptr(q), _ptr(k_cache), _ptr(v_cache), p, batch,
+                                                  n_q, n_kv, head_dim, max_ctx, _ptr(part), part.numel(),
+                                                  _ptr(out), _stream_handle(self.stream)))
+        return out
+
+    def silu_mul_bf16(self, gu, ffn: int, h=None):
+        import torch
+        self._sync_torch()
+        batch = gu.shape[0]
+        if h is None:
+            h = torch.empty((batch, ffn), dtype=torch.int16, device=gu.device)
+        _check(load_library().ci_silu_mul_bf16(self.handle, _ptr(gu), batch, ffn, _ptr(h),
+                                               _stream_handle(self.stream)))
+        return h
+
     # ------------------------------------------------------------ serving
     def serve(self, requests, policy: str = "naive", bound: float = 1.5, hbm_budget: int = 8 << 30,
               slots: int = 4, profiles=None):
@@ -457,6 +618,68 @@ class Context:
         out = (Served * max(n, 1))()
         _check(load_library().serve_run(self.handle, tr, n, C.byref(pol), out))
         return [{f: getattr(out[i], f) for f, _ in Served._fields_} for i in range(n)]
+
+
+class DecodeModel:
+    """Device buffers of one synthetic decode step: BF16 weight arena and
+    KV caches drawn from the seeded streams of synth.decode_tensor_specs,
+    the FP32 residual-stream input, outputs and workspace."""
+
+    def __init__(self, ctx: Context, cfg: dict, pos, seed: int):
+        import torch
+        import synth
+        self.cfg = dict(cfg)
+        self.layout = lay = ctx.decode_layout(self.cfg)
+        dev = ctx.device
+        lib = load_library()
+        self.weights = torch.empty(int(lay.weight_elems), dtype=torch.int16, device=dev)
+        self.k_cache = torch.empty(int(lay.cache_elems), dtype=torch.int16, device=dev)
+        self.v_cache = torch.empty(int(lay.cache_elems), dtype=torch.int16, device=dev)
+        b, hid = cfg["batch"], cfg["hidden"]
+        self.x_in = torch.empty((b, hid), dtype=torch.float32, device=dev)
+        self.x_out = torch.empty((b, hid), dtype=torch.float32, device=dev)
+        self.logits = torch.empty((b, max(cfg["vocab"], 1)), dtype=torch.float32, device=dev)
+        self.work = torch.empty(max(int(lay.workspace_bytes), 256), dtype=torch.uint8, device=dev)
+        specs = synth.decode_tensor_specs(self.cfg, seed)
+        biggest = max(n for _, _, _, n, _, _ in specs)
+        stage = torch.empty(max(biggest, 1), dtype=torch.float32, device=dev)
+        torch.cuda.synchronize(dev)
+        stream = _stream_handle(ctx.stream)
+        for name, layer, sd, n, scale, offset in specs:
+            if n == 0:
+                continue
+            if name == "x_in":
+                synth.device_fill_affine_f32(_ptr(self.x_in), n, sd, scale, offset, stream=stream)
+                continue
+            if name in ("k_cache", "v_cache"):
+                dst = _ptr(getattr(self, name))
+            else:
+                off = getattr(lay, name) + (layer * lay.layer_stride if layer >= 0 else 0)
+                dst = _ptr(self.weights) + 2 * int(off)
+            synth.device_fill_affine_f32(_ptr(stage), n, sd, scale, offset, stream=stream)
+            sc = C.c_float()
+            _check(lib.ci_quantize(ctx.handle, _ptr(stage), n, DTYPES["bf16"], dst, C.byref(sc), stream))
+        ctx.stream.synchronize()
+        del stage
+        self.set_positions(pos)
+
+    def set_positions(self, pos):
+        self.pos = (C.c_int32 * self.cfg["batch"])(*[int(p) for p in pos])
+        d = DecodeDesc()
+        d.cfg = DecodeConfig(**{f: self.cfg[f] for f, _ in DecodeConfig._fields_})
+        d.weights, d.k_cache, d.v_cache = _ptr(self.weights), _ptr(self.k_cache), _ptr(self.v_cache)
+        d.pos = C.cast(self.pos, C.POINTER(C.c_int32))
+        d.x_in, d.x_out = _ptr(self.x_in), _ptr(self.x_out)
+        d.logits = _ptr(self.logits) if self.cfg["vocab"] else None
+        d.work = _ptr(self.work)
+        self.desc = d
+
+    def tensor(self, name: str, layer: int = -1):
+        """View of one weight tensor of the arena (BF16 codes as int16)."""
+        lay = self.layout
+        spec = {s[0]: s[3] for s in __import__("synth").decode_tensor_specs(self.cfg, 0) if s[1] in (0, -1)}
+        off = getattr(lay, name) + (layer * lay.layer_stride if layer >= 0 else 0)
+        return self.weights[int(off):int(off) + spec[name]]
 
 
 def make_profiles(profiles: dict):

@@ -241,6 +241,25 @@ hipError_t launch_gemm(int dtype, const void* a, const void* b, float* c, uint64
 hipError_t launch_gemv_bf16(const uint16_t* w, const uint16_t* x, float* y, uint64_t n,
                             uint64_t k, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_fill_uniform(float* dst, uint64_t n, uint64_t seed, hipStream_t s);
+// decode step
+hipError_t launch_rmsnorm_bf16(const float* x, const uint16_t* g, uint16_t* y, uint32_t rows,
+                               uint32_t n, float eps, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_gemv_rows(const uint16_t* w, const uint16_t* v, const float* res, float* out,
+                            uint32_t rows, uint32_t k, uint32_t batch, hipStream_t s, hipEvent_t e0,
+                            hipEvent_t e1);
+hipError_t launch_rope_append(const float* qkv, const int32_t* pos, float* q_out, uint16_t* kc,
+                              uint16_t* vc, uint32_t batch, uint32_t nq, uint32_t nkv, uint32_t d,
+                              uint32_t max_ctx, float base, hipStream_t s, hipEvent_t e0,
+                              hipEvent_t e1);
+hipError_t launch_attn_partial(const float* q, const uint16_t* kc, const uint16_t* vc,
+                               const int32_t* pos, float* part, uint32_t batch, uint32_t nq,
+                               uint32_t nkv, uint32_t d, uint32_t max_ctx, uint32_t nchunks,
+                               uint32_t used_chunks, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_attn_combine(const float* part, const int32_t* pos, uint16_t* out, uint32_t batch,
+                               uint32_t nq, uint32_t d, uint32_t nchunks, hipStream_t s, hipEvent_t e0,
+                               hipEvent_t e1);
+hipError_t launch_silu_mul(const float* gu, uint16_t* h, uint32_t f, uint32_t batch, hipStream_t s,
+                           hipEvent_t e0, hipEvent_t e1);
 
 // Victim constraints checked on the host before any launch.
 constexpr uint32_t kTriadThreads = 256;

@@ -5,6 +5,7 @@
 #include <atomic>
 #include <map>
 #include <thread>
+#include <vector>
 
 #include "internal.h"
 
@@ -24,6 +25,10 @@ struct ci_ctx {
   hipEvent_t ev[12] = {};
   struct ci_stressor* active = nullptr;
   uint64_t rot = 0;                    // GEMV weight-copy rotation
+  // decode step: positions staged host -> device, events per kernel launch
+  int32_t* dec_pos_host = nullptr;     // pinned, kDecodeMaxBatch entries
+  int32_t* dec_pos_dev = nullptr;
+  std::vector<hipEvent_t> dec_ev;
 };
 
 struct ci_stressor {
@@ -46,8 +51,17 @@ struct ci_stressor {
   hipError_t feeder_err = hipSuccess;
 };
 
+#define HIPCHK(call)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) return ci::set_err(CI_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
 namespace ci {
 constexpr size_t kMaxMaskedStreams = 6;
+constexpr uint32_t kDecodeMaxBatch = 8;
+double median(std::vector<double> v);
+double quantile(std::vector<double> v, double q);
 int cus_for(const ci_ctx* ctx, double intensity);
 bool mask_covers_all_xcds(const ci_ctx* ctx, const uint32_t mask[8]);
 ci_status_t set_err(ci_status_t st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));

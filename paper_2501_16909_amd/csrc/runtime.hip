@@ -36,11 +36,6 @@ ci_status_t ci::set_err(ci_status_t st, const char* fmt, ...) {
 
 extern "C" const char* ci_last_error(void) { return g_err.c_str(); }
 
-#define HIPCHK(call)                                                                      \
-  do {                                                                                    \
-    hipError_t e_ = (call);                                                               \
-    if (e_ != hipSuccess) return set_err(CI_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
-  } while (0)
 
 // ----------------------------------------------------------------- context
 namespace {
@@ -209,6 +204,10 @@ extern "C" ci_status_t ci_shutdown(ci_ctx_t* ctx) {
   if (ctx->amax_part) (void)hipFree(ctx->amax_part);
   if (ctx->amax_out) (void)hipFree(ctx->amax_out);
   if (ctx->probe_buf) (void)hipFree(ctx->probe_buf);
+  for (auto& ev : ctx->dec_ev)
+    if (ev) (void)hipEventDestroy(ev);
+  if (ctx->dec_pos_host) (void)hipHostFree(ctx->dec_pos_host);
+  if (ctx->dec_pos_dev) (void)hipFree(ctx->dec_pos_dev);
   delete ctx;
   return CI_OK;
 }
@@ -922,16 +921,14 @@ extern "C" ci_status_t ci_quantize(ci_ctx_t* ctx, const void* src, uint64_t n, i
 }
 
 // -------------------------------------------------------------- sensitivity
-namespace {
-
-double median(std::vector<double> v) {
+double ci::median(std::vector<double> v) {
   if (v.empty()) return NAN;
   std::sort(v.begin(), v.end());
   const size_t n = v.size();
   return n % 2 ? v[n / 2] : 0.5 * (v[n / 2 - 1] + v[n / 2]);
 }
 
-double quantile(std::vector<double> v, double q) {
+double ci::quantile(std::vector<double> v, double q) {
   if (v.empty()) return NAN;
   std::sort(v.begin(), v.end());
   const double pos = q * (double)(v.size() - 1);
@@ -939,7 +936,6 @@ double quantile(std::vector<double> v, double q) {
   return v[lo] + (v[hi] - v[lo]) * (pos - (double)lo);
 }
 
-}  // namespace
 
 extern "C" ci_status_t measure_sensitivity(ci_ctx_t* ctx, const ci_victim_desc_t* d,
                                            const ci_resource_t* rs, const ci_stressor_opts_t* sopts,

@@ -166,11 +166,6 @@ extern "C" ci_status_t ci_admit(const ci_policy_t* p, const int* running_kinds, 
   return CI_OK;
 }
 
-#define HIPCHK(call)                                                                            \
-  do {                                                                                          \
-    hipError_t e_ = (call);                                                                     \
-    if (e_ != hipSuccess) return set_err(CI_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
-  } while (0)
 
 namespace {
 

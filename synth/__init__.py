@@ -86,6 +86,14 @@ def uniform_f32(seed: int, n: int, start: int = 0) -> np.ndarray:
     return out
 
 
+def uniform_affine_f32(seed: int, n: int, scale: float, offset: float = 0.0, start: int = 0) -> np.ndarray:
+    """uniform_f32(seed, n, start) * scale + offset, each operation rounded
+    to FP32 (the device fill does the same two roundings)."""
+    u = uniform_f32(seed, n, start)
+    t = u * np.float32(scale)
+    return (t + np.float32(offset)).astype(np.float32)
+
+
 def uniform_f32_at(seed: int, idx) -> np.ndarray:
     return _uniform_from_words(words_at(seed, idx))
 
@@ -150,6 +158,10 @@ def _lib():
             fn.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64,
                            ctypes.c_uint64, ctypes.c_void_p]
             fn.restype = ctypes.c_int
+        lib.synth_fill_affine_f32.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64,
+                                              ctypes.c_uint64, ctypes.c_float, ctypes.c_float,
+                                              ctypes.c_void_p]
+        lib.synth_fill_affine_f32.restype = ctypes.c_int
         _LIB = lib
     return _LIB
 
@@ -164,3 +176,40 @@ def device_fill_u32(ptr: int, n: int, seed: int, start: int = 0, stream: int = 0
     rc = _lib().synth_fill_u32(ptr, n, seed, start, stream)
     if rc != 0:
         raise RuntimeError(f"synth_fill_u32 failed: hip error {rc}")
+
+
+def device_fill_affine_f32(ptr: int, n: int, seed: int, scale: float, offset: float = 0.0,
+                           start: int = 0, stream: int = 0) -> None:
+    rc = _lib().synth_fill_affine_f32(ptr, n, seed, start, scale, offset, stream)
+    if rc != 0:
+        raise RuntimeError(f"synth_fill_affine_f32 failed: hip error {rc}")
+
+
+# --------------------------------------------------------------------------
+# Decode-step inputs: which stream fills which tensor, and its value range.
+# Weight matrices are uniform on [-1, 1) scaled by 1/sqrt(fan-in); RMS-norm
+# gains uniform on [0.75, 1.25); cache entries and the residual-stream
+# input uniform on [-1, 1).  Every tensor is drawn in FP32 and rounded to
+# BF16 where the model stores BF16.
+def decode_tensor_specs(cfg: dict, seed: int) -> list:
+    """[(name, layer, stream seed, count, scale, offset)] for the weights
+    (layer -1 = after the last layer), then the caches ("k_cache",
+    "v_cache", count per cache tensor) and "x_in"."""
+    hid, nq, nkv, d, ffn = cfg["hidden"], cfg["n_q"], cfg["n_kv"], cfg["head_dim"], cfg["ffn"]
+    L, vocab, batch, ctx = cfg["layers"], cfg["vocab"], cfg["batch"], cfg["max_ctx"]
+    inv = lambda k: float(np.float32(1.0) / np.sqrt(np.float32(k)))
+    out = []
+    for l in range(L):
+        b = seed + 16 * l
+        out += [("g_attn", l, b + 0, hid, 0.25, 1.0),
+                ("w_qkv", l, b + 1, (nq + 2 * nkv) * d * hid, inv(hid), 0.0),
+                ("w_o", l, b + 2, hid * nq * d, inv(nq * d), 0.0),
+                ("g_mlp", l, b + 3, hid, 0.25, 1.0),
+                ("w_gu", l, b + 4, 2 * ffn * hid, inv(hid), 0.0),
+                ("w_down", l, b + 5, hid * ffn, inv(ffn), 0.0)]
+    b = seed + 16 * L
+    out += [("g_final", -1, b + 0, hid, 0.25, 1.0), ("w_lm", -1, b + 1, vocab * hid, inv(hid), 0.0)]
+    n_cache = L * batch * nkv * ctx * d
+    out += [("k_cache", -1, b + 2, n_cache, 1.0, 0.0), ("v_cache", -1, b + 3, n_cache, 1.0, 0.0),
+            ("x_in", -1, b + 4, batch * hid, 1.0, 0.0)]
+    return out

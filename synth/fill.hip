@@ -1,8 +1,10 @@
 // Device fill of the SplitMix64 counter-form streams drawn in synth/__init__.py.
 // Word i of stream `seed` is mix(seed + (i + 1) * GAMMA) (Steele, Lea and
-// Flood, OOPSLA 2014).  Only the uniform and uint32 draws are offered here;
-// both are integer work plus exact conversions, so host and device agree bit
-// for bit.  Draws only: no arithmetic of the measured method lives here.
+// Flood, OOPSLA 2014).  Only the uniform, scaled-uniform and uint32 draws
+// are offered here; they are integer work, exact conversions and (for the
+// scaled draw) two individually rounded FP32 operations, so host and device
+// agree bit for bit.  Draws only: no arithmetic of the measured method
+// lives here.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -29,6 +31,21 @@ __global__ void __launch_bounds__(256) fill_uniform_f32(float* __restrict__ dst,
     const uint64_t w = splitmix_word(seed, start + i);
     dst[i] = uniform_of(w);
   }
+}
+
+// u * scale + offset with two FP32 roundings (no fused multiply-add).
+__device__ __forceinline__ float affine_of(float u, float scale, float offset) {
+#pragma clang fp contract(off)
+  const float t = u * scale;
+  return t + offset;
+}
+
+__global__ void __launch_bounds__(256) fill_affine_f32(float* __restrict__ dst, uint64_t n,
+                                                       uint64_t seed, uint64_t start, float scale,
+                                                       float offset) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    dst[i] = affine_of(uniform_of(splitmix_word(seed, start + i)), scale, offset);
 }
 
 __global__ void __launch_bounds__(256) fill_u32(uint32_t* __restrict__ dst, uint64_t n,
@@ -61,5 +78,14 @@ extern "C" int synth_fill_u32(void* dst, uint64_t n, uint64_t seed, uint64_t sta
   if (!dst) return (int)hipErrorInvalidValue;
   hipLaunchKernelGGL(fill_u32, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream,
                      (uint32_t*)dst, n, seed, start);
+  return (int)hipGetLastError();
+}
+
+extern "C" int synth_fill_affine_f32(void* dst, uint64_t n, uint64_t seed, uint64_t start, float scale,
+                                     float offset, void* stream) {
+  if (n == 0) return 0;
+  if (!dst) return (int)hipErrorInvalidValue;
+  hipLaunchKernelGGL(fill_affine_f32, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream,
+                     (float*)dst, n, seed, start, scale, offset);
   return (int)hipGetLastError();
 }

@@ -38,7 +38,10 @@ def test_struct_layouts_match_header(tmp_path):
                "ci_victim_desc_t": coloc.VictimDesc, "ci_victim_result_t": coloc.VictimResult,
                "ci_measure_opts_t": coloc.MeasureOpts, "ci_cell_t": coloc.Cell,
                "ci_profile_t": coloc.Profile, "ci_request_t": coloc.Request,
-               "ci_policy_t": coloc.Policy, "ci_served_t": coloc.Served}
+               "ci_policy_t": coloc.Policy, "ci_served_t": coloc.Served,
+               "ci_decode_config_t": coloc.DecodeConfig, "ci_decode_layout_t": coloc.DecodeLayout,
+               "ci_decode_desc_t": coloc.DecodeDesc, "ci_decode_result_t": coloc.DecodeResult,
+               "ci_decode_cell_t": coloc.DecodeCell}
     src = tmp_path / "sz.c"
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
     for cname, py in structs.items():
@@ -101,3 +104,38 @@ def test_admission_matches_oracle(policy, bound):
                 assert got == want, (policy, bound, running, cand)
     assert not coloc.admit("naive", profs, [], "gemv", 101, 100)
     assert not coloc.admit("naive", profs, ["gemv"] * 4, "gemv", 1, 100, slots=4)
+
+
+LLAMA8B = dict(hidden=4096, n_q=32, n_kv=8, head_dim=128, ffn=14336, vocab=128256, layers=32, batch=1,
+               max_ctx=4096, eps=1e-5, rope_base=500000.0)
+
+
+def test_decode_layout_sizes_and_alignment():
+    """The weight arena holds every tensor once, each 128-byte aligned (Llama
+    3.1 8B: 8.03 B parameters, less the 0.53 B input-embedding table the
+    step does not read)."""
+    lay = coloc.Context.decode_layout(LLAMA8B)
+    per_layer = 4096 + 6144 * 4096 + 4096 * 4096 + 4096 + 2 * 14336 * 4096 + 4096 * 14336
+    assert lay.layer_stride == per_layer                 # every size already a multiple of 64
+    assert lay.weight_elems == 32 * per_layer + 4096 + 128256 * 4096
+    assert abs(lay.weight_elems + 128256 * 4096 - 8.03e9) < 0.01e9
+    for f in ("g_attn", "w_qkv", "w_o", "g_mlp", "w_gu", "w_down", "layer_stride", "g_final", "w_lm"):
+        assert getattr(lay, f) % 64 == 0, f
+    assert (lay.g_attn, lay.w_qkv) == (0, 4096)
+    assert lay.w_o == lay.w_qkv + 6144 * 4096 and lay.g_mlp == lay.w_o + 4096 * 4096
+    assert lay.cache_elems == 32 * 1 * 8 * 4096 * 128
+    assert lay.attn_part_bytes == 1 * 32 * 64 * 130 * 4
+    small = dict(LLAMA8B, hidden=520, ffn=72, n_q=3, n_kv=1, vocab=7, layers=2, max_ctx=65, batch=3)
+    lay = coloc.Context.decode_layout(small)
+    assert lay.g_attn == 0 and lay.w_qkv == 576            # 520 rounded up to 64
+    assert lay.layer_stride % 64 == 0 and lay.w_lm % 64 == 0
+    assert lay.attn_part_bytes == 3 * 3 * 2 * 130 * 4
+
+
+@pytest.mark.parametrize("bad", [dict(hidden=4100), dict(ffn=0), dict(head_dim=64), dict(n_q=12, n_kv=5),
+                                 dict(n_q=34, n_kv=2), dict(layers=0), dict(batch=9), dict(batch=0),
+                                 dict(max_ctx=0), dict(rope_base=0.0), dict(eps=-1.0)])
+def test_decode_layout_rejects_bad_configs(bad):
+    with pytest.raises(coloc.CiError) as ei:
+        coloc.Context.decode_layout(dict(LLAMA8B, **bad))
+    assert ei.value.status == 1
