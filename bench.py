@@ -800,6 +800,89 @@ def run_ldsstride(args):
     _emit(out, args)
 
 
+LLAMA31_8B = dict(hidden=4096, n_q=32, n_kv=8, head_dim=128, ffn=14336, vocab=128256, layers=32,
+                 eps=1e-5, rope_base=500000.0)
+
+
+def run_decode(args):
+    """Synthetic decode step as the victim (the LLM decode victims of
+    Sections 4.2-4.4 with random weights; per-kernel breakdown as in
+    Fig. 5): Llama-3.1-8B shapes, BF16 weights and KV cache, 4096-entry
+    cache per sequence.  Alone: step p50/p90 (replayed as a HIP graph, and
+    as plain launches), HBM bytes per step and the achieved rate, per-kernel
+    medians (launches with their own events).  Then the step beside each
+    stressor (shared CUs, CU fraction 0.25 / 0.5 / 1.0; duty 25 / 50 % on
+    every CU): p50/p90 step slowdown (graph) and the kernels that lose most
+    (per-kernel events)."""
+    import torch
+    import synth
+    from paper_2501_16909_amd import coloc
+    ctx = coloc.Context(0)
+    dev = ctx.device
+    batch = args.batch
+    cfg = dict(LLAMA31_8B, batch=batch, max_ctx=4096)
+    pos = [4095 - 1024 * (b % 4) for b in range(batch)]     # ragged contexts
+    model = coloc.DecodeModel(ctx, cfg, pos, synth.seed_for(5, 0))
+    lay = model.layout
+    nsteps = max(args.steps, 20)
+
+    def steps_in(flags):
+        model.set_flags(flags)
+        for _ in range(args.warmup + 3):
+            ctx.decode_step(model)
+        return [ctx.decode_step(model) for _ in range(nsteps)]
+
+    graph = np.array([r["step_ns"] for r in steps_in(coloc.DECODE_GRAPH)])
+    plain = np.array([r["step_ns"] for r in steps_in(0)])
+    timed = steps_in(coloc.DECODE_KERNEL_TIMES)
+    kern = {k: float(np.median([r["kernel_ns"][k] for r in timed])) for k in coloc.DECODE_KERNELS}
+    kv_read = sum((p + 1) for p in pos) * cfg["n_kv"] * cfg["head_dim"] * 2 * 2 * cfg["layers"]
+    weight_bytes = 2 * int(lay.weight_elems)
+    step_bytes = weight_bytes + kv_read
+    p50 = float(np.median(graph))
+    gemv_ns = sum(kern[k] for k in ("qkv", "oproj", "gate_up", "down", "lm_head"))
+    alone = {"step_us_p50": round(p50 / 1e3, 1), "step_us_p90": round(float(np.quantile(graph, 0.9)) / 1e3, 1),
+             "step_us_p50_plain_launches": round(float(np.median(plain)) / 1e3, 1),
+             "step_us_p50_timed_launches": round(float(np.median([r["step_ns"] for r in timed])) / 1e3, 1),
+             "hbm_bytes_per_step": step_bytes, "achieved_gb_s": round(step_bytes / p50, 1),
+             "pct_of_hbm_peak": round(100 * step_bytes / p50 / 8000.0, 1),
+             "gemv_gb_s": round(weight_bytes / gemv_ns, 1),
+             "kernel_us": {k: round(v / 1e3, 1) for k, v in kern.items()}}
+    log("decode alone: " + json.dumps(alone))
+    ops = stressor_operands(dev)
+    ws = torch.empty(256 + 256 * 16 * 48, dtype=torch.uint8, device=dev)
+    res = ["hbm", "l2", "mall", "lds", "valu_f32", "mfma_bf16", "ptrchase"]
+    rows = []
+    for axis, levels in (("cu", [0.25, 0.5, 1.0]), ("duty", [25, 50])):
+        for lv in levels:
+            xs = [lv] if axis == "cu" else [1.0]
+            opts = [dict(ops[r], duty=(lv if axis == "duty" else 100)) for r in res]
+            model.set_flags(coloc.DECODE_GRAPH)
+            steps = ctx.measure_decode(model, res, opts, xs, reps=args.reps, warmups=2, ws=ws,
+                                       deadline_ms=max(args.deadline_ms, 500))
+            model.set_flags(coloc.DECODE_KERNEL_TIMES)
+            kcells = ctx.measure_decode(model, res, opts, xs, reps=max(3, args.reps // 2), warmups=1, ws=ws,
+                                        deadline_ms=max(args.deadline_ms, 500))
+            for c, kcell in zip(steps, kcells):
+                ka, kc = kcell["kernel_alone_ns"], kcell["kernel_col_ns"]
+                worst = sorted(((kc[k] / ka[k], k) for k in ka if ka[k] > 0), reverse=True)[:3]
+                rows.append({"resource": c["resource"], "axis": axis, "level": lv,
+                             "slowdown_p50": round(c["step_col_p50"] / c["step_alone_p50"], 3),
+                             "slowdown_p90": round(c["step_col_p90"] / c["step_alone_p90"], 3),
+                             "stressor_pct_peak": round(c["stressor_pct_peak"], 1),
+                             "worst_kernels": [[k, round(v, 2)] for v, k in worst],
+                             "window_covered": bool(c["window_covered"] and kcell["window_covered"]),
+                             "output_equal": bool(c["output_equal"] and kcell["output_equal"])})
+                log(json.dumps(rows[-1]))
+    out = {"metric": "decode-step victim: step time alone and p50/p90 slowdown per stressor",
+           "config": {"workload": f"synthetic decode step, Llama-3.1-8B shapes (32 layers, 4096 hidden, 32/8 "
+                                  f"heads x 128, FFN 14336, vocab 128256), BF16 weights, batch {batch}, "
+                                  f"cache positions {pos}", "model": "Llama-3.1-8B shapes, random weights"},
+           "alone": alone, "cells": rows}
+    ctx.close()
+    _emit(out, args)
+
+
 def _emit(out, args):
     print(json.dumps(out), flush=True)
     if args.out:
@@ -944,7 +1027,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="suite", choices=["suite", "sweep", "precision", "serve", "counters", "suite-counters",
-                             "pollution", "bandwidth", "ilp", "pairs", "ldsstride", "estimator"])
+                             "pollution", "bandwidth", "ilp", "pairs", "ldsstride", "estimator", "decode"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--out", default=None, help="also write the JSON line(s) to this file")
     ap.add_argument("--reps", type=int, default=10, help="sweep / precision: repetitions per cell")
@@ -955,6 +1038,7 @@ def main():
     ap.add_argument("--seconds", type=float, default=2.0, help="serve: trace length")
     ap.add_argument("--bound", type=float, default=1.5, help="serve: p99 slowdown bound")
     ap.add_argument("--profiles", default=None, help="serve: sensitivity profiles (JSON)")
+    ap.add_argument("--batch", type=int, default=1, help="decode: sequences per step (1..8)")
     ap.add_argument("--profile-axis", default="duty", choices=["cu", "duty"],
                     help="serve: intensity axis of measured profiles (CU fraction or duty cycle)")
     args = ap.parse_args()
@@ -987,6 +1071,8 @@ def main():
         run_ldsstride(args)
     elif args.config == "estimator":
         run_estimator(args)
+    elif args.config == "decode":
+        run_decode(args)
 
 
 if __name__ == "__main__":

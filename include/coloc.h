@@ -340,18 +340,28 @@ ci_status_t measure_sensitivity(ci_ctx_t* ctx, const ci_victim_desc_t* d,
 /* One decode step of a Llama-style decoder with random weights: the
  * stand-in for the paper's LLM decode victims (Sections 4.2-4.4), whose
  * weights and serving stack are not available.  Fig. 5 breaks one decode
- * step into its kernels; the step here is timed kernel by kernel too.
- * Per layer: RMS norm -> QKV GEMV -> rotary embedding and KV-cache append ->
- * grouped-query attention (chunked over the context, then merged) -> output
- * GEMV + residual -> RMS norm -> gate/up GEMV -> SiLU(gate) * up -> down
- * GEMV + residual; after the last layer a final RMS norm and the
- * vocabulary GEMV.  BF16 weights, cache and GEMV inputs; FP32 accumulation,
- * residual stream and GEMV outputs. */
+ * step into its kernels; the step here can be timed kernel by kernel too.
+ * Per layer, as launched:
+ *   QKV      RMS norm of the residual stream, QKV GEMV, rotary embedding of
+ *            queries and keys, keys and values appended to the cache;
+ *   ATTN     grouped-query attention over 64-position chunks of the cache;
+ *   COMBINE  merge of the chunks (softmax normalisation), BF16 out;
+ *   OPROJ    output GEMV + residual;
+ *   GATE_UP  RMS norm, gate/up GEMV, SiLU(gate) * up, BF16 out;
+ *   DOWN     down GEMV + residual;
+ * after the last layer LM_HEAD: final RMS norm and the vocabulary GEMV.
+ * BF16 weights, cache and GEMV inputs; FP32 accumulation, residual stream
+ * and GEMV outputs. */
 typedef enum ci_decode_kernel {
-  CI_DK_ATTN_NORM = 0, CI_DK_QKV = 1, CI_DK_ROPE = 2, CI_DK_ATTN = 3, CI_DK_ATTN_COMBINE = 4,
-  CI_DK_OPROJ = 5, CI_DK_MLP_NORM = 6, CI_DK_GATE_UP = 7, CI_DK_SILU = 8, CI_DK_DOWN = 9,
-  CI_DK_FINAL_NORM = 10, CI_DK_LM_HEAD = 11, CI_DK_COUNT = 12
+  CI_DK_QKV = 0, CI_DK_ATTN = 1, CI_DK_ATTN_COMBINE = 2, CI_DK_OPROJ = 3, CI_DK_GATE_UP = 4,
+  CI_DK_DOWN = 5, CI_DK_LM_HEAD = 6, CI_DK_COUNT = 7
 } ci_decode_kernel_t;
+
+/* ci_decode_desc_t.flags */
+#define CI_DECODE_KERNEL_TIMES 1u  /* start/stop events on every launch      */
+#define CI_DECODE_GRAPH 2u         /* replay the launches as a HIP graph,
+                                      captured on first use per descriptor
+                                      contents and context length bucket    */
 
 typedef struct ci_decode_config {
   uint32_t hidden;     /* model width; multiple of 8                          */
@@ -399,11 +409,14 @@ typedef struct ci_decode_desc {
   float* x_out;         /* device FP32 [batch][hidden]                          */
   float* logits;        /* device FP32 [batch][vocab]; may be NULL if vocab 0   */
   void* work;           /* device workspace of layout.workspace_bytes           */
+  uint32_t flags;       /* CI_DECODE_KERNEL_TIMES or CI_DECODE_GRAPH (not both) or 0 */
+  uint32_t reserved;
 } ci_decode_desc_t;
 
 typedef struct ci_decode_result {
-  double step_ns;                /* first kernel's start to last kernel's end */
-  double kernel_ns[CI_DK_COUNT]; /* per kernel kind, summed over layers       */
+  double step_ns;                /* the step's launches, from HIP events       */
+  double kernel_ns[CI_DK_COUNT]; /* per kernel kind, summed over layers (only
+                                    with CI_DECODE_KERNEL_TIMES, else 0)       */
   uint64_t checksum_bits;        /* bit-pattern sum of logits (x_out if vocab 0) */
   double sum_f64;                /* FP64 sum of the same                       */
   uint64_t t_begin, t_end;       /* device clock around the step               */
@@ -411,8 +424,10 @@ typedef struct ci_decode_result {
 
 /* Run one decode step on `stream` and wait for it.  The step reads x_in and
  * the cache, writes entry pos[b] of every layer's cache, x_out and logits;
- * with unchanged inputs, repeated steps give bit-identical outputs.  Every
- * kernel launch carries its own start/stop events. */
+ * with unchanged inputs, repeated steps give bit-identical outputs, in every
+ * mode (flags).  Step time: first kernel start to last kernel end with
+ * CI_DECODE_KERNEL_TIMES, else events recorded around the launches (or the
+ * graph launch). */
 ci_status_t decode_step(ci_ctx_t* ctx, const ci_decode_desc_t* d, void* stream,
                         ci_decode_result_t* out);
 
@@ -439,8 +454,45 @@ ci_status_t measure_decode(ci_ctx_t* ctx, const ci_decode_desc_t* d, const ci_re
                            const ci_measure_opts_t* o, void* ws, size_t ws_bytes, void* stream,
                            ci_decode_cell_t* cells);
 
-/* The step's kernels one at a time (device pointers, synchronous on
- * `stream`), for parity tests and for callers composing their own step.
+/* The step's GEMV with its fused prologue and epilogue (device pointers,
+ * synchronous on `stream`):
+ *   input: v (BF16, batch x k) or, when v is NULL, x (FP32, batch x k)
+ *     normalised as ci_rmsnorm_bf16 does with gain g and eps, bit for bit;
+ *   PLAIN: out[b][i] = res[b][i] (res may be NULL or alias out) + sum_j
+ *     w[i][j] in[b][j];
+ *   SILU: rows = 2 ffn (gate rows, then up rows); h[b][j] =
+ *     bf16(g / (1 + exp(-g)) * u), g and u rows j and ffn + j, as
+ *     ci_silu_mul_bf16 computes them;
+ *   ROPE: rows = (n_q + 2 n_kv) * head_dim; the outputs go through
+ *     ci_rope_append's arithmetic at host positions pos[b]: rotated queries
+ *     to q_out, keys and values to entry pos[b] of k_cache / v_cache.
+ * w, v, x, g 16-byte aligned; k a multiple of 8; batch 1..8. */
+typedef enum ci_gemv_epilogue { CI_GEMV_PLAIN = 0, CI_GEMV_SILU = 1, CI_GEMV_ROPE = 2 } ci_gemv_epilogue_t;
+
+typedef struct ci_gemv_args {
+  const void* w;
+  uint32_t rows, k, batch;
+  int epilogue;               /* ci_gemv_epilogue_t                            */
+  const void* v;              /* BF16 input, or NULL                           */
+  const float* x;             /* FP32 input to normalise when v is NULL        */
+  const void* g;              /* BF16 gain (k)                                 */
+  float eps;
+  const float* res;           /* PLAIN                                         */
+  float* out;
+  void* h;                    /* SILU                                          */
+  const int32_t* pos;         /* ROPE: HOST int32[batch], each in [0, max_ctx) */
+  uint32_t n_q, n_kv, head_dim, max_ctx;
+  float rope_base;
+  float* q_out;
+  void* k_cache;
+  void* v_cache;
+} ci_gemv_args_t;
+
+ci_status_t ci_fused_gemv(ci_ctx_t* ctx, const ci_gemv_args_t* a, void* stream);
+
+/* The step's stages as separate kernels (device pointers, synchronous on
+ * `stream`): the unfused composition the fused GEMV reproduces, for parity
+ * tests and for callers composing their own step.
  *   ci_rmsnorm_bf16: y[r] = bf16(x[r] / sqrt(mean(x[r]^2) + eps) * g),
  *     rows x n, n a multiple of 4.
  *   ci_gemv_bf16_rows: out[b][i] = res[b][i] (res may be NULL or alias out)

@@ -111,9 +111,10 @@ class Served(C.Structure):
                 ("slot", C.c_int), ("status", C.c_int)]
 
 
-DECODE_KERNELS = ["attn_norm", "qkv", "rope", "attn", "attn_combine", "oproj", "mlp_norm", "gate_up",
-                  "silu", "down", "final_norm", "lm_head"]
+DECODE_KERNELS = ["qkv", "attn", "attn_combine", "oproj", "gate_up", "down", "lm_head"]
 NDK = len(DECODE_KERNELS)
+DECODE_KERNEL_TIMES, DECODE_GRAPH = 1, 2
+GEMV_EPILOGUES = {"plain": 0, "silu": 1, "rope": 2}
 
 
 class DecodeConfig(C.Structure):
@@ -134,7 +135,17 @@ class DecodeLayout(C.Structure):
 class DecodeDesc(C.Structure):
     _fields_ = [("cfg", DecodeConfig), ("weights", C.c_void_p), ("k_cache", C.c_void_p),
                 ("v_cache", C.c_void_p), ("pos", C.POINTER(C.c_int32)), ("x_in", C.c_void_p),
-                ("x_out", C.c_void_p), ("logits", C.c_void_p), ("work", C.c_void_p)]
+                ("x_out", C.c_void_p), ("logits", C.c_void_p), ("work", C.c_void_p),
+                ("flags", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class GemvArgs(C.Structure):
+    _fields_ = [("w", C.c_void_p), ("rows", C.c_uint32), ("k", C.c_uint32), ("batch", C.c_uint32),
+                ("epilogue", C.c_int), ("v", C.c_void_p), ("x", C.c_void_p), ("g", C.c_void_p),
+                ("eps", C.c_float), ("res", C.c_void_p), ("out", C.c_void_p), ("h", C.c_void_p),
+                ("pos", C.POINTER(C.c_int32)), ("n_q", C.c_uint32), ("n_kv", C.c_uint32),
+                ("head_dim", C.c_uint32), ("max_ctx", C.c_uint32), ("rope_base", C.c_float),
+                ("q_out", C.c_void_p), ("k_cache", C.c_void_p), ("v_cache", C.c_void_p)]
 
 
 class DecodeResult(C.Structure):
@@ -195,6 +206,7 @@ EXPORTS = {
                              C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_void_p,
                              C.c_size_t, C.c_void_p, C.c_void_p], C.c_int),
     "ci_silu_mul_bf16": ([C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p], C.c_int),
+    "ci_fused_gemv": ([C.c_void_p, C.POINTER(GemvArgs), C.c_void_p], C.c_int),
 }
 
 _LIB = None
@@ -593,6 +605,26 @@ class Context:
                                                   _ptr(out), _stream_handle(self.stream)))
         return out
 
+    def fused_gemv(self, w, epilogue: str = "plain", v=None, x=None, g=None, eps: float = 0.0, res=None,
+                   out=None, h=None, pos=None, n_q: int = 0, n_kv: int = 0, head_dim: int = 0,
+                   max_ctx: int = 0, rope_base: float = 1.0, q_out=None, k_cache=None, v_cache=None):
+        """The decode step's GEMV with its fused prologue (RMS norm of x when
+        v is None) and epilogue ("plain", "silu", "rope")."""
+        self._sync_torch()
+        rows, k = w.shape
+        batch = (v if v is not None else x).shape[0]
+        a = GemvArgs()
+        a.w, a.rows, a.k, a.batch, a.epilogue = _ptr(w), rows, k, batch, GEMV_EPILOGUES[epilogue]
+        a.v, a.x, a.g, a.eps = _ptr(v), _ptr(x), _ptr(g), float(eps)
+        a.res, a.out, a.h = _ptr(res), _ptr(out), _ptr(h)
+        keep = None
+        if pos is not None:
+            keep = (C.c_int32 * batch)(*[int(p) for p in pos])
+            a.pos = C.cast(keep, C.POINTER(C.c_int32))
+        a.n_q, a.n_kv, a.head_dim, a.max_ctx, a.rope_base = n_q, n_kv, head_dim, max_ctx, float(rope_base)
+        a.q_out, a.k_cache, a.v_cache = _ptr(q_out), _ptr(k_cache), _ptr(v_cache)
+        _check(load_library().ci_fused_gemv(self.handle, C.byref(a), _stream_handle(self.stream)))
+
     def silu_mul_bf16(self, gu, ffn: int, h=None):
         import torch
         self._sync_torch()
@@ -625,7 +657,7 @@ class DecodeModel:
     KV caches drawn from the seeded streams of synth.decode_tensor_specs,
     the FP32 residual-stream input, outputs and workspace."""
 
-    def __init__(self, ctx: Context, cfg: dict, pos, seed: int):
+    def __init__(self, ctx: Context, cfg: dict, pos, seed: int, flags: int = DECODE_KERNEL_TIMES):
         import torch
         import synth
         self.cfg = dict(cfg)
@@ -661,6 +693,7 @@ class DecodeModel:
             _check(lib.ci_quantize(ctx.handle, _ptr(stage), n, DTYPES["bf16"], dst, C.byref(sc), stream))
         ctx.stream.synchronize()
         del stage
+        self.flags = flags
         self.set_positions(pos)
 
     def set_positions(self, pos):
@@ -672,7 +705,12 @@ class DecodeModel:
         d.x_in, d.x_out = _ptr(self.x_in), _ptr(self.x_out)
         d.logits = _ptr(self.logits) if self.cfg["vocab"] else None
         d.work = _ptr(self.work)
+        d.flags = self.flags
         self.desc = d
+
+    def set_flags(self, flags: int):
+        self.flags = flags
+        self.desc.flags = flags
 
     def tensor(self, name: str, layer: int = -1):
         """View of one weight tensor of the arena (BF16 codes as int16)."""

@@ -3,7 +3,9 @@
 // and the step's sensitivity measurement beside a stressor.
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "internal.h"
@@ -19,7 +21,7 @@ uint64_t al64(uint64_t x) { return (x + 63) & ~63ull; }
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Work {
-  size_t x, xn, qkv, qrot, part, attn, gu, h, total;
+  size_t x, qrot, part, attn, h, total;
   uint32_t nchunks;
 };
 
@@ -50,12 +52,9 @@ Work work_of(const ci_decode_config_t& c) {
   const size_t B = c.batch, d = c.head_dim;
   w.nchunks = (c.max_ctx + kChunk - 1) / kChunk;
   w.x = take(B * c.hidden * 4);
-  w.xn = take(B * c.hidden * 2);
-  w.qkv = take(B * (c.n_q + 2 * c.n_kv) * d * 4);
   w.qrot = take(B * c.n_q * d * 4);
   w.part = take(B * c.n_q * w.nchunks * (d + 2) * 4);
   w.attn = take(B * c.n_q * d * 2);
-  w.gu = take(B * 2 * (size_t)c.ffn * 4);
   w.h = take(B * c.ffn * 2);
   w.total = o;
   return w;
@@ -132,6 +131,9 @@ ci_status_t check_desc(const ci_decode_desc_t* d) {
   if (!aligned16(d->weights) || !aligned16(d->x_in) || !aligned16(d->x_out) || !aligned16(d->work) ||
       !aligned16(d->k_cache) || !aligned16(d->v_cache))
     return set_err(CI_ERR_INVALID_ARG, "decode: device buffers must be 16-byte aligned");
+  if (d->flags & ~(CI_DECODE_KERNEL_TIMES | CI_DECODE_GRAPH) ||
+      (d->flags & CI_DECODE_KERNEL_TIMES && d->flags & CI_DECODE_GRAPH))
+    return set_err(CI_ERR_INVALID_ARG, "decode: flags 0x%x", d->flags);
   return CI_OK;
 }
 
@@ -151,89 +153,203 @@ ci_status_t exec_end(ci_ctx* ctx, hipStream_t caller, hipStream_t xs) {
   return CI_OK;
 }
 
+// Queue the step's kernels on `xs`.  ev(kind) gives the event pair of the
+// next launch (both null for untimed launches).
+template <class EvFn>
+ci_status_t enqueue_step(const ci_decode_desc_t* d, const int32_t* pos, uint32_t used, hipStream_t xs,
+                         EvFn ev) {
+  const ci_decode_config_t& c = d->cfg;
+  const ci_decode_layout_t L = layout_of(c);
+  const Work W = work_of(c);
+  uint8_t* w8 = (uint8_t*)d->work;
+  float* x = (float*)(w8 + W.x);
+  float* qrot = (float*)(w8 + W.qrot);
+  float* part = (float*)(w8 + W.part);
+  uint16_t* attn = (uint16_t*)(w8 + W.attn);
+  uint16_t* h = (uint16_t*)(w8 + W.h);
+  const uint32_t B = c.batch, hid = c.hidden, dh = c.head_dim, f = c.ffn;
+  const uint64_t cache_layer = (uint64_t)B * c.n_kv * c.max_ctx * dh;
+  const uint16_t* wts = (const uint16_t*)d->weights;
+#define STEP(kind, call)                                                                       \
+  do {                                                                                         \
+    hipEvent_t e0_, e1_;                                                                       \
+    ev(kind, &e0_, &e1_);                                                                      \
+    hipError_t r_ = (call);                                                                    \
+    if (r_ != hipSuccess) return set_err(CI_ERR_HIP, "decode %s: %s", #kind, hipGetErrorString(r_)); \
+  } while (0)
+  for (uint32_t l = 0; l < c.layers; ++l) {
+    const uint16_t* wl = wts + (uint64_t)l * L.layer_stride;
+    const float* xres = l == 0 ? d->x_in : x;
+    float* xo = l + 1 == c.layers ? d->x_out : x;
+    GemvArgs q{};
+    q.w = wl + L.w_qkv;
+    q.x = xres;
+    q.g = wl + L.g_attn;
+    q.eps = c.eps;
+    q.pos = pos;
+    q.q_out = qrot;
+    q.kc = (uint16_t*)d->k_cache + l * cache_layer;
+    q.vc = (uint16_t*)d->v_cache + l * cache_layer;
+    q.rows = (c.n_q + 2 * c.n_kv) * dh;
+    q.k = hid;
+    q.batch = B;
+    q.nq = c.n_q;
+    q.nkv = c.n_kv;
+    q.d = dh;
+    q.max_ctx = c.max_ctx;
+    q.base = c.rope_base;
+    STEP(CI_DK_QKV, launch_gemv_fused(q, 1, kEpiRope, xs, e0_, e1_));
+    STEP(CI_DK_ATTN, launch_attn_partial(qrot, q.kc, q.vc, pos, part, B, c.n_q, c.n_kv, dh, c.max_ctx,
+                                         W.nchunks, used, xs, e0_, e1_));
+    STEP(CI_DK_ATTN_COMBINE, launch_attn_combine(part, pos, attn, B, c.n_q, dh, W.nchunks, xs, e0_, e1_));
+    GemvArgs o{};
+    o.w = wl + L.w_o;
+    o.v = attn;
+    o.res = xres;
+    o.out = x;
+    o.rows = hid;
+    o.k = c.n_q * dh;
+    o.batch = B;
+    STEP(CI_DK_OPROJ, launch_gemv_fused(o, 0, kEpiPlain, xs, e0_, e1_));
+    GemvArgs g{};
+    g.w = wl + L.w_gu;
+    g.x = x;
+    g.g = wl + L.g_mlp;
+    g.eps = c.eps;
+    g.h = h;
+    g.rows = 2 * f;
+    g.k = hid;
+    g.batch = B;
+    STEP(CI_DK_GATE_UP, launch_gemv_fused(g, 1, kEpiSilu, xs, e0_, e1_));
+    GemvArgs dn{};
+    dn.w = wl + L.w_down;
+    dn.v = h;
+    dn.res = x;
+    dn.out = xo;
+    dn.rows = hid;
+    dn.k = f;
+    dn.batch = B;
+    STEP(CI_DK_DOWN, launch_gemv_fused(dn, 0, kEpiPlain, xs, e0_, e1_));
+  }
+  if (c.vocab) {
+    GemvArgs lm{};
+    lm.w = wts + L.w_lm;
+    lm.x = d->x_out;
+    lm.g = wts + L.g_final;
+    lm.eps = c.eps;
+    lm.out = d->logits;
+    lm.rows = c.vocab;
+    lm.k = hid;
+    lm.batch = B;
+    STEP(CI_DK_LM_HEAD, launch_gemv_fused(lm, 1, kEpiPlain, xs, e0_, e1_));
+  }
+#undef STEP
+  return CI_OK;
+}
+
+uint32_t launches_of(const ci_decode_config_t& c) { return c.layers * 6 + (c.vocab ? 1 : 0); }
+
+// Graph of the step's launches for this descriptor (everything but the
+// host positions) and context bucket, captured on first use.
+ci_status_t step_graph(ci_ctx* ctx, const ci_decode_desc_t* d, uint32_t used, hipStream_t xs,
+                       hipGraphExec_t* out) {
+  std::string key((const char*)d, offsetof(ci_decode_desc_t, pos));
+  key.append((const char*)&d->x_in, offsetof(ci_decode_desc_t, flags) - offsetof(ci_decode_desc_t, x_in));
+  key.append((const char*)&used, sizeof(used));
+  key.append((const char*)&xs, sizeof(xs));
+  auto it = ctx->dec_graphs.find(key);
+  if (it != ctx->dec_graphs.end()) {
+    *out = it->second;
+    return CI_OK;
+  }
+  if (ctx->dec_graphs.size() >= kDecodeMaxGraphs) {
+    (void)hipGraphExecDestroy(ctx->dec_graphs.begin()->second);
+    ctx->dec_graphs.erase(ctx->dec_graphs.begin());
+  }
+  HIPCHK(hipStreamBeginCapture(xs, hipStreamCaptureModeRelaxed));
+  ci_status_t st = enqueue_step(d, ctx->dec_pos_dev, used, xs, [](int, hipEvent_t* a, hipEvent_t* b) {
+    *a = *b = nullptr;
+  });
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(xs, &g);
+  if (st != CI_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (ec != hipSuccess) return set_err(CI_ERR_HIP, "decode graph capture: %s", hipGetErrorString(ec));
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) return set_err(CI_ERR_HIP, "decode graph instantiate: %s", hipGetErrorString(ei));
+  ctx->dec_graphs.emplace(key, ex);
+  *out = ex;
+  return CI_OK;
+}
+
 // One step on exec stream `xs`; blocks until done.
 ci_status_t run_decode(ci_ctx* ctx, const ci_decode_desc_t* d, hipStream_t caller, hipStream_t xs,
                        ci_decode_result_t* out) {
   const ci_decode_config_t& c = d->cfg;
-  const ci_decode_layout_t L = layout_of(c);
-  const Work W = work_of(c);
-  const uint32_t nk = c.layers * 10 + (c.vocab ? 2 : 0);
-  ci_status_t st = ensure_decode_state(ctx, 2 * (size_t)nk);
-  if (st != CI_OK) return st;
-  st = exec_begin(ctx, caller, xs);
+  const uint32_t nk = launches_of(c);
+  const bool timed = d->flags & CI_DECODE_KERNEL_TIMES;
+  ci_status_t st = ensure_decode_state(ctx, timed ? 2 * (size_t)nk : 0);
   if (st != CI_OK) return st;
   uint32_t max_pos = 0;
+  for (uint32_t b = 0; b < c.batch; ++b) {   // validated again when staged
+    if (d->pos && d->pos[b] >= 0) max_pos = std::max(max_pos, (uint32_t)d->pos[b]);
+  }
+  const uint32_t used = max_pos / kChunk + 1;
+  hipGraphExec_t graph = nullptr;
+  if (d->flags & CI_DECODE_GRAPH) {
+    st = step_graph(ctx, d, used, xs, &graph);
+    if (st != CI_OK) return st;
+  }
+  st = exec_begin(ctx, caller, xs);
+  if (st != CI_OK) return st;
   st = stage_positions(ctx, d->pos, c.batch, c.max_ctx, xs, &max_pos);
   if (st != CI_OK) return st;
-  uint8_t* w8 = (uint8_t*)d->work;
-  float* x = (float*)(w8 + W.x);
-  uint16_t* xn = (uint16_t*)(w8 + W.xn);
-  float* qkv = (float*)(w8 + W.qkv);
-  float* qrot = (float*)(w8 + W.qrot);
-  float* part = (float*)(w8 + W.part);
-  uint16_t* attn = (uint16_t*)(w8 + W.attn);
-  float* gu = (float*)(w8 + W.gu);
-  uint16_t* h = (uint16_t*)(w8 + W.h);
-  const int32_t* pos = ctx->dec_pos_dev;
-  const uint32_t B = c.batch, hid = c.hidden, dh = c.head_dim, f = c.ffn;
-  const uint32_t qkv_rows = (c.n_q + 2 * c.n_kv) * dh, qd = c.n_q * dh;
-  const uint32_t used = max_pos / kChunk + 1;
-  const uint64_t cache_layer = (uint64_t)B * c.n_kv * c.max_ctx * dh;
-  std::vector<int> kinds;
-  kinds.reserve(nk);
   volatile uint64_t* hr = ctx->hres;
   hr[0] = hr[1] = hr[2] = hr[3] = 0;
   HIPCHK(launch_stamp((uint64_t*)&hr[0], xs));
-  auto ev = [&](int kind, int which) {
-    if (which == 0) kinds.push_back(kind);
-    return ctx->dec_ev[2 * (kinds.size() - 1) + which];
-  };
-#define STEP(kind, call)                                                                       \
-  do {                                                                                         \
-    hipEvent_t e0_ = ev(kind, 0), e1_ = ev(kind, 1);                                           \
-    hipError_t r_ = (call);                                                                    \
-    if (r_ != hipSuccess) return set_err(CI_ERR_HIP, "decode %s: %s", #kind, hipGetErrorString(r_)); \
-  } while (0)
-  const uint16_t* wts = (const uint16_t*)d->weights;
-  for (uint32_t l = 0; l < c.layers; ++l) {
-    const uint16_t* wl = wts + (uint64_t)l * L.layer_stride;
-    uint16_t* kc = (uint16_t*)d->k_cache + l * cache_layer;
-    uint16_t* vc = (uint16_t*)d->v_cache + l * cache_layer;
-    const float* xres = l == 0 ? d->x_in : x;
-    float* xo = l + 1 == c.layers ? d->x_out : x;
-    STEP(CI_DK_ATTN_NORM, launch_rmsnorm_bf16(xres, wl + L.g_attn, xn, B, hid, c.eps, xs, e0_, e1_));
-    STEP(CI_DK_QKV, launch_gemv_rows(wl + L.w_qkv, xn, nullptr, qkv, qkv_rows, hid, B, xs, e0_, e1_));
-    STEP(CI_DK_ROPE, launch_rope_append(qkv, pos, qrot, kc, vc, B, c.n_q, c.n_kv, dh, c.max_ctx,
-                                        c.rope_base, xs, e0_, e1_));
-    STEP(CI_DK_ATTN, launch_attn_partial(qrot, kc, vc, pos, part, B, c.n_q, c.n_kv, dh, c.max_ctx,
-                                         W.nchunks, used, xs, e0_, e1_));
-    STEP(CI_DK_ATTN_COMBINE, launch_attn_combine(part, pos, attn, B, c.n_q, dh, W.nchunks, xs, e0_, e1_));
-    STEP(CI_DK_OPROJ, launch_gemv_rows(wl + L.w_o, attn, xres, x, hid, qd, B, xs, e0_, e1_));
-    STEP(CI_DK_MLP_NORM, launch_rmsnorm_bf16(x, wl + L.g_mlp, xn, B, hid, c.eps, xs, e0_, e1_));
-    STEP(CI_DK_GATE_UP, launch_gemv_rows(wl + L.w_gu, xn, nullptr, gu, 2 * f, hid, B, xs, e0_, e1_));
-    STEP(CI_DK_SILU, launch_silu_mul(gu, h, f, B, xs, e0_, e1_));
-    STEP(CI_DK_DOWN, launch_gemv_rows(wl + L.w_down, h, x, xo, hid, f, B, xs, e0_, e1_));
+  std::vector<int> kinds;
+  if (graph) {
+    HIPCHK(hipEventRecord(ctx->ev[7], xs));
+    HIPCHK(hipGraphLaunch(graph, xs));
+    HIPCHK(hipEventRecord(ctx->ev[8], xs));
+  } else if (timed) {
+    kinds.reserve(nk);
+    st = enqueue_step(d, ctx->dec_pos_dev, used, xs, [&](int kind, hipEvent_t* a, hipEvent_t* b) {
+      kinds.push_back(kind);
+      *a = ctx->dec_ev[2 * (kinds.size() - 1)];
+      *b = ctx->dec_ev[2 * (kinds.size() - 1) + 1];
+    });
+    if (st != CI_OK) return st;
+  } else {
+    HIPCHK(hipEventRecord(ctx->ev[7], xs));
+    st = enqueue_step(d, ctx->dec_pos_dev, used, xs, [](int, hipEvent_t* a, hipEvent_t* b) {
+      *a = *b = nullptr;
+    });
+    if (st != CI_OK) return st;
+    HIPCHK(hipEventRecord(ctx->ev[8], xs));
   }
-  if (c.vocab) {
-    STEP(CI_DK_FINAL_NORM, launch_rmsnorm_bf16(d->x_out, wts + L.g_final, xn, B, hid, c.eps, xs, e0_, e1_));
-    STEP(CI_DK_LM_HEAD, launch_gemv_rows(wts + L.w_lm, xn, nullptr, d->logits, c.vocab, hid, B, xs, e0_, e1_));
-  }
-#undef STEP
   HIPCHK(launch_stamp((uint64_t*)&hr[1], xs));
   const float* res = c.vocab ? d->logits : d->x_out;
-  const uint64_t len = (uint64_t)B * (c.vocab ? c.vocab : hid);
+  const uint64_t len = (uint64_t)c.batch * (c.vocab ? c.vocab : c.hidden);
   HIPCHK(launch_checksum_f32(res, len, ctx->part_bits, ctx->part_sum, ctx->nparts, (uint64_t*)&hr[2],
                              (double*)&hr[3], xs));
   st = exec_end(ctx, caller, xs);
   if (st != CI_OK) return st;
   memset(out, 0, sizeof(*out));
-  for (size_t i = 0; i < kinds.size(); ++i) {
-    float ms = 0.0f;
-    HIPCHK(hipEventElapsedTime(&ms, ctx->dec_ev[2 * i], ctx->dec_ev[2 * i + 1]));
-    out->kernel_ns[kinds[i]] += (double)ms * 1e6;
-  }
   float ms = 0.0f;
-  HIPCHK(hipEventElapsedTime(&ms, ctx->dec_ev[0], ctx->dec_ev[2 * kinds.size() - 1]));
+  if (timed) {
+    for (size_t i = 0; i < kinds.size(); ++i) {
+      HIPCHK(hipEventElapsedTime(&ms, ctx->dec_ev[2 * i], ctx->dec_ev[2 * i + 1]));
+      out->kernel_ns[kinds[i]] += (double)ms * 1e6;
+    }
+    HIPCHK(hipEventElapsedTime(&ms, ctx->dec_ev[0], ctx->dec_ev[2 * kinds.size() - 1]));
+  } else {
+    HIPCHK(hipEventElapsedTime(&ms, ctx->ev[7], ctx->ev[8]));
+  }
   out->step_ns = (double)ms * 1e6;
   out->t_begin = hr[0];
   out->t_end = hr[1];
@@ -392,7 +508,70 @@ extern "C" ci_status_t ci_gemv_bf16_rows(ci_ctx_t* ctx, const uint16_t* w, const
   hipStream_t caller = (hipStream_t)stream, xs = ctx->vstream;
   ci_status_t st = exec_begin(ctx, caller, xs);
   if (st != CI_OK) return st;
-  HIPCHK(launch_gemv_rows(w, v, res, out, rows, k, batch, xs, nullptr, nullptr));
+  GemvArgs a{};
+  a.w = w;
+  a.v = v;
+  a.res = res;
+  a.out = out;
+  a.rows = rows;
+  a.k = k;
+  a.batch = batch;
+  HIPCHK(launch_gemv_fused(a, 0, kEpiPlain, xs, nullptr, nullptr));
+  return exec_end(ctx, caller, xs);
+}
+
+extern "C" ci_status_t ci_fused_gemv(ci_ctx_t* ctx, const ci_gemv_args_t* in, void* stream) {
+  if (!ctx || !in || !in->w) return set_err(CI_ERR_INVALID_ARG, "ci_fused_gemv: NULL argument");
+  const ci_gemv_args_t& a = *in;
+  if (a.rows == 0 || a.k == 0 || a.k % 8) return set_err(CI_ERR_INVALID_ARG, "ci_fused_gemv: k must be a positive multiple of 8");
+  if (a.batch == 0 || a.batch > kDecodeMaxBatch) return set_err(CI_ERR_INVALID_ARG, "ci_fused_gemv: batch %u not in 1..8", a.batch);
+  if (!aligned16(a.w) || (a.v && !aligned16(a.v)) || (!a.v && (!a.x || !a.g || !aligned16(a.x) || !aligned16(a.g))))
+    return set_err(CI_ERR_INVALID_ARG, "ci_fused_gemv: input missing or not 16-byte aligned");
+  GemvArgs g{};
+  g.w = (const uint16_t*)a.w;
+  g.v = (const uint16_t*)a.v;
+  g.x = a.x;
+  g.g = (const uint16_t*)a.g;
+  g.eps = a.eps;
+  g.rows = a.rows;
+  g.k = a.k;
+  g.batch = a.batch;
+  if (a.epilogue == CI_GEMV_PLAIN) {
+    if (!a.out) return set_err(CI_ERR_INVALID_ARG, "ci_fused_gemv: NULL out");
+    g.res = a.res;
+    g.out = a.out;
+  } else if (a.epilogue == CI_GEMV_SILU) {
+    if (!a.h || a.rows % 2) return set_err(CI_ERR_INVALID_ARG, "ci_fused_gemv: SILU needs h and an even row count");
+    g.h = (uint16_t*)a.h;
+  } else if (a.epilogue == CI_GEMV_ROPE) {
+    ci_decode_config_t c{8, a.n_q, a.n_kv, a.head_dim, 8, 0, 1, a.batch, a.max_ctx, 0.0f, a.rope_base};
+    ci_status_t st = check_cfg(&c);
+    if (st != CI_OK) return st;
+    if ((uint64_t)(a.n_q + 2 * a.n_kv) * a.head_dim != a.rows)
+      return set_err(CI_ERR_INVALID_ARG, "ci_fused_gemv: ROPE rows %u != (n_q + 2 n_kv) * head_dim", a.rows);
+    if (!a.q_out || !a.k_cache || !a.v_cache) return set_err(CI_ERR_INVALID_ARG, "ci_fused_gemv: NULL ROPE output");
+    g.q_out = a.q_out;
+    g.kc = (uint16_t*)a.k_cache;
+    g.vc = (uint16_t*)a.v_cache;
+    g.nq = a.n_q;
+    g.nkv = a.n_kv;
+    g.d = a.head_dim;
+    g.max_ctx = a.max_ctx;
+    g.base = a.rope_base;
+  } else {
+    return set_err(CI_ERR_INVALID_ARG, "ci_fused_gemv: epilogue %d", a.epilogue);
+  }
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t caller = (hipStream_t)stream, xs = ctx->vstream;
+  ci_status_t st = exec_begin(ctx, caller, xs);
+  if (st != CI_OK) return st;
+  if (a.epilogue == CI_GEMV_ROPE) {
+    uint32_t mp = 0;
+    st = stage_positions(ctx, a.pos, a.batch, a.max_ctx, xs, &mp);
+    if (st != CI_OK) return st;
+    g.pos = ctx->dec_pos_dev;
+  }
+  HIPCHK(launch_gemv_fused(g, a.v ? 0 : 1, a.epilogue, xs, nullptr, nullptr));
   return exec_end(ctx, caller, xs);
 }
 

@@ -189,6 +189,8 @@ inline hipError_t xlaunch(void (*kernel)(KArgs...), dim3 grid, dim3 block, uint3
   void* argv[sizeof...(Args) + 1];
   std::tuple<KArgs...> tup{static_cast<KArgs>(args)...};
   fill_args(tup, argv, std::index_sequence_for<KArgs...>{});
+  if (!e0 && !e1)   // plain launch: capturable into a HIP graph
+    return hipLaunchKernel(reinterpret_cast<const void*>(kernel), grid, block, argv, shmem, s);
   return hipExtLaunchKernel(reinterpret_cast<const void*>(kernel), grid, block, argv, shmem, s,
                             e0, e1, 0);
 }
@@ -244,9 +246,27 @@ hipError_t launch_fill_uniform(float* dst, uint64_t n, uint64_t seed, hipStream_
 // decode step
 hipError_t launch_rmsnorm_bf16(const float* x, const uint16_t* g, uint16_t* y, uint32_t rows,
                                uint32_t n, float eps, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
-hipError_t launch_gemv_rows(const uint16_t* w, const uint16_t* v, const float* res, float* out,
-                            uint32_t rows, uint32_t k, uint32_t batch, hipStream_t s, hipEvent_t e0,
-                            hipEvent_t e1);
+// Fused decode GEMV (see k_decode.hip): out / h / (q_out, kc, vc) from rows
+// of w times batch vectors, given as BF16 v or as FP32 x normalised with g.
+struct GemvArgs {
+  const uint16_t* w;
+  const uint16_t* v;      // BF16 input: batch x k
+  const float* x;         // normalised input: batch x k FP32, gain g, eps
+  const uint16_t* g;
+  const float* res;       // PLAIN: optional residual (may alias out)
+  float* out;             // PLAIN: batch x rows FP32
+  uint16_t* h;            // SILU: batch x rows/2 BF16
+  const int32_t* pos;     // ROPE: device positions; q_out FP32, caches BF16
+  float* q_out;
+  uint16_t* kc;
+  uint16_t* vc;
+  uint32_t rows, k, batch;
+  uint32_t nq, nkv, d, max_ctx;
+  float eps, base;
+};
+constexpr int kEpiPlain = 0, kEpiSilu = 1, kEpiRope = 2;
+hipError_t launch_gemv_fused(const GemvArgs& a, int input_norm, int epilogue, hipStream_t s,
+                             hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_rope_append(const float* qkv, const int32_t* pos, float* q_out, uint16_t* kc,
                               uint16_t* vc, uint32_t batch, uint32_t nq, uint32_t nkv, uint32_t d,
                               uint32_t max_ctx, float base, hipStream_t s, hipEvent_t e0,

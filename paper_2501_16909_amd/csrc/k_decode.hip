@@ -1,23 +1,29 @@
 // Kernels of the synthetic decode step: the stand-in for the paper's LLM
 // decode victims (Sections 4.2-4.4; per-kernel latencies of one step as in
-// Fig. 5).  A Llama-style decoder layer with random weights, batch <= 8:
-//
-//   rmsnorm_kernel       RMS normalisation with gain, BF16 out
-//   gemv_rows_kernel     BF16 weight rows x NB BF16 vectors, FP32 out, with
-//                        an optional FP32 residual added in the epilogue
-//   rope_append_kernel   rotary embedding (rotate-half) of queries and keys;
-//                        keys and values appended to the BF16 cache
-//   attn_partial_kernel  grouped-query attention over 64-position chunks of
-//                        the cache: per chunk max, exp-sum and unnormalised
-//                        output (split over the context so that one
-//                        sequence fills the chip)
-//   attn_combine_kernel  merges the chunks, BF16 out
-//   silu_mul_kernel      SiLU(gate) * up, BF16 out
+// Fig. 5).  A Llama-style decoder layer with random weights, batch <= 8.
 //
 // Weight streaming dominates a decode step, so the GEMV is the kernel that
-// matters: one wave per R rows, 16-byte coalesced weight loads, the NB
-// input vectors staged in LDS per K tile and shared by every wave of the
-// work-group, FP32 accumulation and a butterfly reduction.
+// matters, and the step is built around it: the small element-wise stages
+// ride inside the GEMVs instead of paying a launch (and a pipeline drain)
+// each.
+//
+//   gemv_fused_kernel   BF16 weight rows x NB vectors, FP32 accumulation.
+//     input  BF16: the vectors as given;
+//            NORM: FP32 vectors RMS-normalised with a BF16 gain and rounded
+//                  to BF16 while they are staged (every work-group computes
+//                  the norms itself, in the same order as rmsnorm_kernel);
+//     output PLAIN: FP32 rows, plus an optional residual (may alias);
+//            SILU:  rows j and j + rows/2 of one wave are gate and up, the
+//                   epilogue writes BF16 SiLU(gate) * up;
+//            ROPE:  rows i and i + head_dim/2 of a head share a wave, the
+//                   epilogue applies the rotary embedding and writes the
+//                   query (FP32) or appends key and value (BF16) to the cache.
+//   attn_partial_kernel  grouped-query attention over 64-position chunks:
+//                        per chunk max, exp-sum and unnormalised output.
+//   attn_combine_kernel  merges the chunks of one head, BF16 out.
+//   rmsnorm_kernel, rope_append_kernel, silu_mul_kernel: the same stages as
+//     stand-alone kernels (the unfused composition the fused path must
+//     reproduce bit for bit; they share the arithmetic helpers below).
 #include "internal.h"
 
 #include <math.h>
@@ -27,13 +33,16 @@ namespace {
 
 __device__ __forceinline__ float bf_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
-__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // FP32 -> BF16 bits, round to nearest even; NaN -> quiet NaN of the same sign.
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
   const uint32_t u = __float_as_uint(f);
   if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)(((u >> 16) & 0x8000u) | 0x7FC0u);
   return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ uint32_t pack2(uint16_t lo, uint16_t hi) {
+  return (uint32_t)lo | ((uint32_t)hi << 16);
 }
 
 __device__ __forceinline__ float wave_sum_f(float v) {
@@ -60,120 +69,270 @@ __device__ __forceinline__ float dot8(uint4 w, uint4 x, float acc) {
   return acc;
 }
 
-// ---------------------------------------------------------------- RMSNorm
-// One work-group of 256 threads per row; n a multiple of 4.
-__global__ void __launch_bounds__(256) rmsnorm_kernel(const float* __restrict__ x,
-                                                      const uint16_t* __restrict__ g,
-                                                      uint16_t* __restrict__ y, uint32_t n,
-                                                      float eps) {
-  __shared__ float part[4];
-  const float4* xr = reinterpret_cast<const float4*>(x + (size_t)blockIdx.x * n);
-  const uint2* gr = reinterpret_cast<const uint2*>(g);
-  uint2* yr = reinterpret_cast<uint2*>(y + (size_t)blockIdx.x * n);
-  const uint32_t n4 = n / 4;
+// ---------------------------------------------- arithmetic shared by paths
+// Sum of squares of x[0..n) by a 256-thread work-group: thread t takes the
+// float4s t, t + 256, ..., then the waves' sums are added in a fixed order.
+// Uniform control flow required (barriers).
+__device__ float block_sumsq_256(const float* __restrict__ x, uint32_t n, float* s_part) {
+  const float4* x4 = reinterpret_cast<const float4*>(x);
   float ss = 0.0f;
-  for (uint32_t i = threadIdx.x; i < n4; i += 256) {
-    const float4 v = xr[i];
+  for (uint32_t i = threadIdx.x; i < n / 4; i += 256) {
+    const float4 v = x4[i];
     ss = fmaf(v.x, v.x, ss);
     ss = fmaf(v.y, v.y, ss);
     ss = fmaf(v.z, v.z, ss);
     ss = fmaf(v.w, v.w, ss);
   }
   ss = wave_sum_f(ss);
-  if ((threadIdx.x & 63u) == 0) part[threadIdx.x >> 6] = ss;
+  if ((threadIdx.x & 63u) == 0) s_part[threadIdx.x >> 6] = ss;
   __syncthreads();
-  const float tot = (part[0] + part[1]) + (part[2] + part[3]);
-  const float r = 1.0f / sqrtf(tot / (float)n + eps);
-  for (uint32_t i = threadIdx.x; i < n4; i += 256) {
-    const float4 v = xr[i];
-    const uint2 gw = gr[i];
-    const uint16_t a = f32_to_bf16_rne(v.x * r * bf_lo(gw.x));
-    const uint16_t b = f32_to_bf16_rne(v.y * r * bf_hi(gw.x));
-    const uint16_t c = f32_to_bf16_rne(v.z * r * bf_lo(gw.y));
-    const uint16_t d = f32_to_bf16_rne(v.w * r * bf_hi(gw.y));
-    yr[i] = make_uint2((uint32_t)a | ((uint32_t)b << 16), (uint32_t)c | ((uint32_t)d << 16));
+  const float tot = (s_part[0] + s_part[1]) + (s_part[2] + s_part[3]);
+  __syncthreads();
+  return tot;
+}
+
+__device__ __forceinline__ float rms_factor(float sumsq, uint32_t n, float eps) {
+  return 1.0f / sqrtf(sumsq / (float)n + eps);
+}
+
+__device__ __forceinline__ uint16_t norm_bf16(float x, float r, float g) {
+#pragma clang fp contract(off)
+  return f32_to_bf16_rne((x * r) * g);
+}
+
+// Pair i of a head turns by pos * base^(-2i/d): angle, cosine and sine in
+// FP64, rounded to FP32; the rotation in FP32 without contraction.
+__device__ __forceinline__ void rope_cos_sin(uint32_t pos, uint32_t i, uint32_t d, float base, float* cs,
+                                             float* sn) {
+  const double ang = (double)pos * pow((double)base, -2.0 * (double)i / (double)d);
+  *cs = (float)cos(ang);
+  *sn = (float)sin(ang);
+}
+
+__device__ __forceinline__ void rope_apply(float x1, float x2, float cs, float sn, float* y1, float* y2) {
+#pragma clang fp contract(off)
+  *y1 = x1 * cs - x2 * sn;
+  *y2 = x2 * cs + x1 * sn;
+}
+
+__device__ __forceinline__ float silu_mul_f(float g, float u) {
+#pragma clang fp contract(off)
+  return g / (1.0f + expf(-g)) * u;
+}
+
+// ---------------------------------------------------------------- RMSNorm
+// One 256-thread work-group per row; n a multiple of 4.
+__global__ void __launch_bounds__(256) rmsnorm_kernel(const float* __restrict__ x,
+                                                      const uint16_t* __restrict__ g,
+                                                      uint16_t* __restrict__ y, uint32_t n,
+                                                      float eps) {
+  __shared__ float s_part[4];
+  const float* xr = x + (size_t)blockIdx.x * n;
+  const float r = rms_factor(block_sumsq_256(xr, n, s_part), n, eps);
+  const float4* x4 = reinterpret_cast<const float4*>(xr);
+  const uint2* g2 = reinterpret_cast<const uint2*>(g);
+  uint2* y2 = reinterpret_cast<uint2*>(y + (size_t)blockIdx.x * n);
+  for (uint32_t i = threadIdx.x; i < n / 4; i += 256) {
+    const float4 v = x4[i];
+    const uint2 gw = g2[i];
+    y2[i] = make_uint2(pack2(norm_bf16(v.x, r, bf_lo(gw.x)), norm_bf16(v.y, r, bf_hi(gw.x))),
+                       pack2(norm_bf16(v.z, r, bf_lo(gw.y)), norm_bf16(v.w, r, bf_hi(gw.y))));
   }
 }
 
 // ------------------------------------------------------------------- GEMV
-// out[b][row] = res[b][row] (if res) + sum_j W[row][j] * v[b][j]
-// W: rows x k BF16 row-major; v: NB x k BF16; res, out: NB x rows FP32 (they
-// may alias: each element is read and then written by the same lane).
-// Work-group: 4 waves, wave w owns rows (4 * blockIdx.x + w) * R .. + R - 1.
-// K is walked in tiles of TK elements; each tile of the NB vectors is staged
-// in LDS (32 KiB) and read by every wave.  Lane l covers 16-byte chunks
-// l, l + 64, l + 128, l + 192 of each 256-chunk step, so a wave's loads of a
-// row are 1 KiB contiguous.
-template <int NB, int R>
-__global__ void __launch_bounds__(256) gemv_rows_kernel(const uint16_t* __restrict__ W,
-                                                        const uint16_t* __restrict__ v,
-                                                        const float* res, float* out,
-                                                        uint32_t rows, uint32_t k) {
-  constexpr uint32_t TK = 16384 / NB;   // elements per vector per tile
-  constexpr uint32_t TC = TK / 8;       // 16-byte chunks per vector per tile
+constexpr int IN_BF16 = 0, IN_NORM = 1;
+constexpr int EPI_PLAIN = 0, EPI_SILU = 1, EPI_ROPE = 2;
+
+// Work-group: 4 waves; wave w (global index gw = 4 * blockIdx.x + w) owns R
+// rows: PLAIN rows gw*R .. gw*R + R-1; SILU / ROPE R/2 row pairs.  K is
+// walked in tiles of TK elements; each tile of the NB vectors is staged in
+// LDS (32 KiB) once per work-group and read by all four waves.  Lane l
+// covers 16-byte chunks l, l+64, l+128, l+192 of each 256-chunk step, so a
+// wave's loads of a row are 1 KiB contiguous.  Vectors b >= batch are zero.
+template <int NB, int R, int IN, int EPI>
+__global__ void __launch_bounds__(256) gemv_fused_kernel(GemvArgs a) {
+  constexpr uint32_t TK = 16384 / NB;
+  constexpr uint32_t TC = TK / 8;
+  constexpr int P = R / 2;
   __shared__ uint4 xs[NB * TC];
-  const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
-  const uint32_t row0 = (blockIdx.x * 4u + wid) * R;
+  __shared__ float s_part[4];
+  __shared__ float s_r[NB];
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t gw = blockIdx.x * 4u + (threadIdx.x >> 6);
+  uint32_t row[R], jp[P > 0 ? P : 1];
   bool live[R];
+  if constexpr (EPI == EPI_PLAIN) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      row[r] = gw * R + r;
+      live[r] = row[r] < a.rows;
+    }
+  } else {
+    const uint32_t npairs = a.rows / 2;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      jp[p] = gw * P + p;
+      const bool ok = jp[p] < npairs;
+      uint32_t ra, rb;
+      if constexpr (EPI == EPI_SILU) {
+        ra = jp[p];
+        rb = jp[p] + npairs;
+      } else {
+        const uint32_t half = a.d / 2, head = jp[p] / half, i = jp[p] - head * half;
+        ra = head * a.d + i;
+        rb = ra + half;
+      }
+      row[2 * p] = ra;
+      row[2 * p + 1] = rb;
+      live[2 * p] = live[2 * p + 1] = ok;
+    }
+  }
   const uint4* wr[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    live[r] = row0 + r < rows;
-    wr[r] = reinterpret_cast<const uint4*>(W + (size_t)(live[r] ? row0 + r : 0) * k);
-  }
+  for (int r = 0; r < R; ++r) wr[r] = reinterpret_cast<const uint4*>(a.w + (size_t)(live[r] ? row[r] : 0) * a.k);
   float acc[R][NB];
 #pragma unroll
   for (int r = 0; r < R; ++r)
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[r][b] = 0.0f;
-  const uint32_t kc = k / 8;            // chunks per row
-  for (uint32_t c0 = 0; c0 < kc; c0 += TC) {
-    const uint32_t nch = min(TC, kc - c0);
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < NB * nch; i += 256) {
-      const uint32_t b = i / nch, c = i - b * nch;
-      xs[b * TC + c] = reinterpret_cast<const uint4*>(v + (size_t)b * k)[c0 + c];
-    }
-    __syncthreads();
-    for (uint32_t c = lane; c < nch; c += 256) {
-      uint4 w[R][4];
+  // Rounds of 256 chunks: round j covers chunks 256 j .. 256 j + 255, lane
+  // l the chunks 256 j + l + 64 u (u < 4).  TC is a multiple of 256, so a
+  // round never straddles two tiles.  The next round's weights are loaded
+  // before the current round's products, and round 0's before the vectors
+  // are normalised and staged.
+  const uint32_t kc = a.k / 8;
+  const uint32_t nrounds = (kc + 255) / 256;
+  uint4 wcur[R][4], wnext[R][4];
+  auto load_round = [&](uint32_t j, uint4 (&wv)[R][4]) {
 #pragma unroll
-      for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          w[r][u] = (live[r] && c + 64u * u < nch) ? wr[r][c0 + c + 64u * u] : make_uint4(0, 0, 0, 0);
+    for (int r = 0; r < R; ++r)
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        if (c + 64u * u >= nch) break;
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          const uint4 xv = xs[b * TC + c + 64u * u];
-#pragma unroll
-          for (int r = 0; r < R; ++r) acc[r][b] = dot8(w[r][u], xv, acc[r][b]);
+        const uint32_t c = 256u * j + lane + 64u * u;
+        wv[r][u] = (live[r] && c < kc) ? wr[r][c] : make_uint4(0, 0, 0, 0);
+      }
+  };
+  load_round(0, wcur);
+  // ROPE: the lane that writes pair p of vector b (lane p * NB + b) takes
+  // its cosine and sine now, while round 0's weights are in flight.
+  float rcs = 1.0f, rsn = 0.0f;
+  if constexpr (EPI == EPI_ROPE) {
+    const uint32_t p = lane / NB, b = lane % NB;
+    const uint32_t half = a.d / 2, jpl = gw * P + p;
+    if (lane < (uint32_t)(P * NB) && b < a.batch && jpl < a.rows / 2) {
+      const uint32_t head = jpl / half;
+      if (head < a.nq + a.nkv) rope_cos_sin((uint32_t)a.pos[b], jpl - head * half, a.d, a.base, &rcs, &rsn);
+    }
+  }
+  if constexpr (IN == IN_NORM) {
+#pragma unroll 1
+    for (uint32_t b = 0; b < (uint32_t)NB; ++b) {
+      float tot = 0.0f;
+      if (b < a.batch) tot = block_sumsq_256(a.x + (size_t)b * a.k, a.k, s_part);
+      if (threadIdx.x == 0) s_r[b] = b < a.batch ? rms_factor(tot, a.k, a.eps) : 0.0f;
+    }
+  }
+  for (uint32_t j = 0; j < nrounds; ++j) {
+    const uint32_t cr = 256u * j;          // first chunk of the round
+    const uint32_t c0 = cr - cr % TC;      // first chunk of its tile
+    if (cr == c0) {
+      const uint32_t nch = min(TC, kc - c0);
+      __syncthreads();
+      for (uint32_t i = threadIdx.x; i < NB * nch; i += 256) {
+        const uint32_t b = i / nch, c = i - b * nch;
+        uint4 val = make_uint4(0, 0, 0, 0);
+        if (b < a.batch) {
+          if constexpr (IN == IN_BF16) {
+            val = reinterpret_cast<const uint4*>(a.v + (size_t)b * a.k)[c0 + c];
+          } else {
+            const float4* xp = reinterpret_cast<const float4*>(a.x + (size_t)b * a.k) + 2 * (c0 + c);
+            const float4 x0 = xp[0], x1 = xp[1];
+            const uint4 gg = reinterpret_cast<const uint4*>(a.g)[c0 + c];
+            const float r = s_r[b];
+            val.x = pack2(norm_bf16(x0.x, r, bf_lo(gg.x)), norm_bf16(x0.y, r, bf_hi(gg.x)));
+            val.y = pack2(norm_bf16(x0.z, r, bf_lo(gg.y)), norm_bf16(x0.w, r, bf_hi(gg.y)));
+            val.z = pack2(norm_bf16(x1.x, r, bf_lo(gg.z)), norm_bf16(x1.y, r, bf_hi(gg.z)));
+            val.w = pack2(norm_bf16(x1.z, r, bf_lo(gg.w)), norm_bf16(x1.w, r, bf_hi(gg.w)));
+          }
         }
+        xs[b * TC + c] = val;
+      }
+      __syncthreads();
+    }
+    if (j + 1 < nrounds) load_round(j + 1, wnext);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t c = cr + lane + 64u * u;
+      if (c >= kc) break;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const uint4 xv = xs[b * TC + (c - c0)];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r][b] = dot8(wcur[r][u], xv, acc[r][b]);
       }
     }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) wcur[r][u] = wnext[r][u];
   }
 #pragma unroll
   for (int r = 0; r < R; ++r)
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[r][b] = wave_sum_f(acc[r][b]);
+  if constexpr (EPI == EPI_PLAIN) {
 #pragma unroll
-  for (int r = 0; r < R; ++r)
+    for (int r = 0; r < R; ++r)
 #pragma unroll
-    for (int b = 0; b < NB; ++b)
-      if (lane == (uint32_t)(r * NB + b) && live[r]) {
-        const size_t o = (size_t)b * rows + row0 + r;
-        out[o] = (res ? res[o] : 0.0f) + acc[r][b];
-      }
+      for (int b = 0; b < NB; ++b)
+        if (lane == (uint32_t)(r * NB + b) && live[r] && (uint32_t)b < a.batch) {
+          const size_t o = (size_t)b * a.rows + row[r];
+          a.out[o] = (a.res ? a.res[o] : 0.0f) + acc[r][b];
+        }
+  } else if constexpr (EPI == EPI_SILU) {
+    const uint32_t f = a.rows / 2;
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+        if (lane == (uint32_t)(p * NB + b) && live[2 * p] && (uint32_t)b < a.batch)
+          a.h[(size_t)b * f + jp[p]] = f32_to_bf16_rne(silu_mul_f(acc[2 * p][b], acc[2 * p + 1][b]));
+  } else {
+    const uint32_t half = a.d / 2;
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+        if (lane == (uint32_t)(p * NB + b) && live[2 * p] && (uint32_t)b < a.batch) {
+          const uint32_t head = jp[p] / half, i = jp[p] - head * half;
+          const uint32_t pp = (uint32_t)a.pos[b];
+          const float x1 = acc[2 * p][b], x2 = acc[2 * p + 1][b];
+          if (head < a.nq) {
+            float y1, y2;
+            rope_apply(x1, x2, rcs, rsn, &y1, &y2);
+            float* dst = a.q_out + ((size_t)b * a.nq + head) * a.d;
+            dst[i] = y1;
+            dst[i + half] = y2;
+          } else if (head < a.nq + a.nkv) {
+            float y1, y2;
+            rope_apply(x1, x2, rcs, rsn, &y1, &y2);
+            uint16_t* dst = a.kc + (((size_t)b * a.nkv + (head - a.nq)) * a.max_ctx + pp) * a.d;
+            dst[i] = f32_to_bf16_rne(y1);
+            dst[i + half] = f32_to_bf16_rne(y2);
+          } else {
+            uint16_t* dst = a.vc + (((size_t)b * a.nkv + (head - a.nq - a.nkv)) * a.max_ctx + pp) * a.d;
+            dst[i] = f32_to_bf16_rne(x1);
+            dst[i + half] = f32_to_bf16_rne(x2);
+          }
+        }
+  }
 }
 
 // ------------------------------------------------------------- RoPE + cache
-// grid (batch, n_q + 2 n_kv), block head_dim / 2.  qkv: batch x (n_q + 2 n_kv)
-// heads x head_dim FP32 (query heads, key heads, value heads).  Pair i of a
-// head is (i, i + head_dim/2), turned by pos * base^(-2i/head_dim); the angle
-// and its cosine and sine are taken in FP64 and rounded to FP32.  Cache
-// (this layer): batch x n_kv x max_ctx x head_dim BF16.
+// Stand-alone form.  grid (batch, n_q + 2 n_kv), block head_dim / 2.
+// qkv: batch x (n_q + 2 n_kv) heads x head_dim FP32 (query heads, key heads,
+// value heads).  Cache (one layer): batch x n_kv x max_ctx x head_dim BF16.
 __global__ void __launch_bounds__(128) rope_append_kernel(const float* __restrict__ qkv,
                                                           const int32_t* __restrict__ pos,
                                                           float* __restrict__ q_out,
@@ -191,10 +350,9 @@ __global__ void __launch_bounds__(128) rope_append_kernel(const float* __restric
     dst[i + half] = f32_to_bf16_rne(x2);
     return;
   }
-  const double ang = (double)p * pow((double)base, -2.0 * (double)i / (double)d);
-  const float cs = (float)cos(ang), sn = (float)sin(ang);
-  const float y1 = x1 * cs - x2 * sn;
-  const float y2 = x2 * cs + x1 * sn;
+  float cs, sn, y1, y2;
+  rope_cos_sin(p, i, d, base, &cs, &sn);
+  rope_apply(x1, x2, cs, sn, &y1, &y2);
   if (h < nq) {
     float* dst = q_out + ((size_t)b * nq + h) * d;
     dst[i] = y1;
@@ -209,10 +367,10 @@ __global__ void __launch_bounds__(128) rope_append_kernel(const float* __restric
 // -------------------------------------------------------------- attention
 // grid (chunks, n_kv, batch), block group * 64 (group = n_q / n_kv <= 16):
 // wave w handles query head kvh * group + w over positions t0 .. t0 + 63
-// of key/value head kvh.  Keys and values of the chunk are staged in LDS
-// with an odd row pitch (D/2 + 1 words), so lane-per-position score reads
-// hit distinct banks.  Output per (batch, head, chunk): {max, exp-sum,
-// D unnormalised outputs}; an empty chunk (t0 > pos) writes {-inf, 0, 0...}.
+// of key/value head kvh.  The chunk's keys and values are staged in LDS
+// with 16-byte loads (rows padded to D/2 + 4 words); lane t scores position
+// t0 + t.  Output per (batch, head, chunk): {max, exp-sum, D unnormalised
+// outputs}; an empty chunk (t0 > pos) writes {-inf, 0, 0...}.
 template <int D>
 __global__ void __launch_bounds__(1024) attn_partial_kernel(const float* __restrict__ q,
                                                             const uint16_t* __restrict__ kc,
@@ -221,12 +379,13 @@ __global__ void __launch_bounds__(1024) attn_partial_kernel(const float* __restr
                                                             float* __restrict__ part, uint32_t nq,
                                                             uint32_t nkv, uint32_t max_ctx,
                                                             uint32_t nchunks, float scale) {
-  constexpr uint32_t kW = D / 2;        // 32-bit words per row
-  constexpr uint32_t kPitch = kW + 1;
-  constexpr uint32_t kWPL = D / 128;    // value words per lane
-  __shared__ uint32_t ks[64 * kPitch];
-  __shared__ uint32_t vs[64 * kPitch];
-  __shared__ float qs[16 * D];
+  constexpr uint32_t kRow4 = D / 8;            // uint4 per cached row
+  constexpr uint32_t kPitch4 = kRow4 + 1;      // padded, in uint4
+  constexpr uint32_t kPitchW = 4 * kPitch4;    // in 32-bit words
+  constexpr uint32_t kWPL = D / 128;           // value words per lane
+  __shared__ uint4 ks[64 * kPitch4];
+  __shared__ uint4 vs[64 * kPitch4];
+  __shared__ float4 qs[16 * D / 4];
   __shared__ float ps[16 * 64];
   const uint32_t chunk = blockIdx.x, kvh = blockIdx.y, b = blockIdx.z;
   const uint32_t group = blockDim.x >> 6, lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
@@ -243,26 +402,34 @@ __global__ void __launch_bounds__(1024) attn_partial_kernel(const float* __restr
     return;
   }
   const size_t base = (((size_t)b * nkv + kvh) * max_ctx + t0) * D;
-  const uint32_t* k32 = reinterpret_cast<const uint32_t*>(kc + base);
-  const uint32_t* v32 = reinterpret_cast<const uint32_t*>(vc + base);
-  for (uint32_t i = threadIdx.x; i < 64 * kW; i += blockDim.x) {
-    const uint32_t t = i / kW, c = i - t * kW;
+  const uint4* k4 = reinterpret_cast<const uint4*>(kc + base);
+  const uint4* v4 = reinterpret_cast<const uint4*>(vc + base);
+  for (uint32_t i = threadIdx.x; i < 64 * kRow4; i += blockDim.x) {
+    const uint32_t t = i / kRow4, c = i - t * kRow4;
     const bool ok = (int32_t)(t0 + t) < T;
-    ks[t * kPitch + c] = ok ? k32[i] : 0u;
-    vs[t * kPitch + c] = ok ? v32[i] : 0u;
+    const uint4 kk = ok ? k4[i] : make_uint4(0, 0, 0, 0);
+    const uint4 vv = ok ? v4[i] : make_uint4(0, 0, 0, 0);
+    ks[t * kPitch4 + c] = kk;
+    vs[t * kPitch4 + c] = vv;
   }
-  const float* qh = q + ((size_t)b * nq + h) * D;
-  for (uint32_t j = lane; j < D; j += 64) qs[w * D + j] = qh[j];
+  const float4* qh = reinterpret_cast<const float4*>(q + ((size_t)b * nq + h) * D);
+  for (uint32_t j = lane; j < D / 4; j += 64) qs[w * (D / 4) + j] = qh[j];
   __syncthreads();
   float s = 0.0f;
-  const uint32_t* kr = ks + lane * kPitch;
-  const float2* q2 = reinterpret_cast<const float2*>(qs + w * D);
-#pragma unroll 8
-  for (uint32_t c = 0; c < kW; ++c) {
-    const uint32_t kw = kr[c];
-    const float2 qq = q2[c];
-    s = fmaf(qq.x, bf_lo(kw), s);
-    s = fmaf(qq.y, bf_hi(kw), s);
+  const uint4* kr = ks + lane * kPitch4;
+  const float4* qw = qs + w * (D / 4);
+#pragma unroll 4
+  for (uint32_t c = 0; c < kRow4; ++c) {
+    const uint4 kw = kr[c];
+    const float4 qa = qw[2 * c], qb = qw[2 * c + 1];
+    s = fmaf(qa.x, bf_lo(kw.x), s);
+    s = fmaf(qa.y, bf_hi(kw.x), s);
+    s = fmaf(qa.z, bf_lo(kw.y), s);
+    s = fmaf(qa.w, bf_hi(kw.y), s);
+    s = fmaf(qb.x, bf_lo(kw.z), s);
+    s = fmaf(qb.y, bf_hi(kw.z), s);
+    s = fmaf(qb.z, bf_lo(kw.w), s);
+    s = fmaf(qb.w, bf_hi(kw.w), s);
   }
   const bool valid = (int32_t)(t0 + lane) < T;
   s = valid ? s * scale : -INFINITY;
@@ -274,12 +441,13 @@ __global__ void __launch_bounds__(1024) attn_partial_kernel(const float* __restr
   float o[2 * kWPL];
 #pragma unroll
   for (uint32_t j = 0; j < 2 * kWPL; ++j) o[j] = 0.0f;
+  const uint32_t* vw32 = reinterpret_cast<const uint32_t*>(vs);
+#pragma unroll 4
   for (uint32_t t = 0; t < 64; ++t) {
     const float pt = ps[w * 64 + t];
-    const uint32_t* vr = vs + t * kPitch;
 #pragma unroll
     for (uint32_t u = 0; u < kWPL; ++u) {
-      const uint32_t vw = vr[lane + 64 * u];
+      const uint32_t vw = vw32[t * kPitchW + lane + 64 * u];
       o[2 * u] = fmaf(pt, bf_lo(vw), o[2 * u]);
       o[2 * u + 1] = fmaf(pt, bf_hi(vw), o[2 * u + 1]);
     }
@@ -288,93 +456,129 @@ __global__ void __launch_bounds__(1024) attn_partial_kernel(const float* __restr
     dst[0] = m;
     dst[1] = l;
   }
+  float2* d2 = reinterpret_cast<float2*>(dst + 2);
 #pragma unroll
-  for (uint32_t u = 0; u < kWPL; ++u) {
-    const uint32_t j = 2 * (lane + 64 * u);
-    dst[2 + j] = o[2 * u];
-    dst[2 + j + 1] = o[2 * u + 1];
-  }
+  for (uint32_t u = 0; u < kWPL; ++u) d2[lane + 64 * u] = make_float2(o[2 * u], o[2 * u + 1]);
 }
 
-// grid (n_q, batch), block 64: merge the chunks of one head.  out: batch x
-// (n_q * D) BF16, head h at columns h * D.
+// grid (n_q, batch), block 256: merge the chunks of one head.  Thread t
+// takes chunk maxima t, t+256, ... (block maximum M), then per tile of 256
+// chunks the weights e_c = exp(m_c - M) go to LDS and thread t accumulates
+// dimension pair t mod (D/2) over chunks t / (D/2), + 256/(D/2), ...; the
+// partial sums of the chunk groups are added in a fixed order.
 template <int D>
-__global__ void __launch_bounds__(64) attn_combine_kernel(const float* __restrict__ part,
-                                                          const int32_t* __restrict__ pos,
-                                                          uint16_t* __restrict__ out, uint32_t nq,
-                                                          uint32_t nchunks) {
-  constexpr uint32_t kWPL = D / 128;
-  const uint32_t h = blockIdx.x, b = blockIdx.y, lane = threadIdx.x;
-  const uint32_t nc = ((uint32_t)pos[b] + 64u) / 64u;
+__global__ void __launch_bounds__(256) attn_combine_kernel(const float* __restrict__ part,
+                                                           const int32_t* __restrict__ pos,
+                                                           uint16_t* __restrict__ out, uint32_t nq,
+                                                           uint32_t nchunks) {
+  constexpr uint32_t kPairs = D / 2;            // dimension pairs
+  constexpr uint32_t kGroups = 256 / kPairs;    // chunk groups (4 for D=128, 2 for D=256)
+  __shared__ float s_e[256];
+  __shared__ float s_red[4];
+  __shared__ float2 s_o[kGroups][kPairs];
+  const uint32_t h = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
+  const uint32_t nc = (uint32_t)pos[b] / 64u + 1u;
   const float* src = part + ((size_t)b * nq + h) * nchunks * (D + 2);
-  float M = -INFINITY;
-  for (uint32_t c = 0; c < nc; ++c) M = fmaxf(M, src[c * (D + 2)]);
-  float L = 0.0f;
-  float o[2 * kWPL];
-#pragma unroll
-  for (uint32_t j = 0; j < 2 * kWPL; ++j) o[j] = 0.0f;
-  for (uint32_t c = 0; c < nc; ++c) {
-    const float* pc = src + c * (D + 2);
-    const float e = expf(pc[0] - M);
-    L = fmaf(pc[1], e, L);
-#pragma unroll
-    for (uint32_t u = 0; u < kWPL; ++u) {
-      const uint32_t j = 2 * (lane + 64 * u);
-      o[2 * u] = fmaf(pc[2 + j], e, o[2 * u]);
-      o[2 * u + 1] = fmaf(pc[3 + j], e, o[2 * u + 1]);
+  float mx = -INFINITY;
+  for (uint32_t c = t; c < nc; c += 256) mx = fmaxf(mx, src[(size_t)c * (D + 2)]);
+  mx = wave_max_f(mx);
+  if ((t & 63u) == 0) s_red[t >> 6] = mx;
+  __syncthreads();
+  const float M = fmaxf(fmaxf(s_red[0], s_red[1]), fmaxf(s_red[2], s_red[3]));
+  __syncthreads();
+  const uint32_t dp = t % kPairs, grp = t / kPairs;
+  float lsum = 0.0f;
+  float2 o = make_float2(0.0f, 0.0f);
+  for (uint32_t c0 = 0; c0 < nc; c0 += 256) {
+    const uint32_t n = min(256u, nc - c0);
+    float e = 0.0f;
+    if (t < n) {
+      const float* pc = src + (size_t)(c0 + t) * (D + 2);
+      e = expf(pc[0] - M);
+      lsum = fmaf(pc[1], e, lsum);
     }
+    s_e[t] = e;
+    __syncthreads();
+#pragma unroll 4
+    for (uint32_t c = grp; c < n; c += kGroups) {
+      const float ec = s_e[c];
+      const float2 v = reinterpret_cast<const float2*>(src + (size_t)(c0 + c) * (D + 2) + 2)[dp];
+      o.x = fmaf(v.x, ec, o.x);
+      o.y = fmaf(v.y, ec, o.y);
+    }
+    __syncthreads();
   }
-  uint32_t* dst = reinterpret_cast<uint32_t*>(out + ((size_t)b * nq + h) * D);
+  lsum = wave_sum_f(lsum);
+  if ((t & 63u) == 0) s_red[t >> 6] = lsum;
+  s_o[grp][dp] = o;
+  __syncthreads();
+  const float L = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+  if (t < kPairs) {
+    float2 acc = s_o[0][t];
 #pragma unroll
-  for (uint32_t u = 0; u < kWPL; ++u) {
-    const uint16_t lo = f32_to_bf16_rne(o[2 * u] / L);
-    const uint16_t hi = f32_to_bf16_rne(o[2 * u + 1] / L);
-    dst[lane + 64 * u] = (uint32_t)lo | ((uint32_t)hi << 16);
+    for (uint32_t g = 1; g < kGroups; ++g) {
+      acc.x += s_o[g][t].x;
+      acc.y += s_o[g][t].y;
+    }
+    uint32_t* dst = reinterpret_cast<uint32_t*>(out + ((size_t)b * nq + h) * D);
+    dst[t] = pack2(f32_to_bf16_rne(acc.x / L), f32_to_bf16_rne(acc.y / L));
   }
 }
 
 // ------------------------------------------------------------------- SiLU
-// gu: batch x 2f FP32 (gate columns, then up columns); h: batch x f BF16.
+// Stand-alone form.  gu: batch x 2f FP32 (gate columns, then up columns);
+// h: batch x f BF16.
 __global__ void __launch_bounds__(256) silu_mul_kernel(const float* __restrict__ gu,
                                                        uint16_t* __restrict__ h, uint32_t f,
                                                        uint32_t batch) {
   const uint64_t n = (uint64_t)batch * f;
   for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
     const uint64_t b = i / f, j = i - b * f;
-    const float g = gu[b * 2 * f + j], u = gu[b * 2 * f + f + j];
-    h[i] = f32_to_bf16_rne(g / (1.0f + expf(-g)) * u);
+    h[i] = f32_to_bf16_rne(silu_mul_f(gu[b * 2 * f + j], gu[b * 2 * f + f + j]));
   }
 }
 
-template <int NB>
-hipError_t gemv_nb(const uint16_t* w, const uint16_t* v, const float* res, float* out, uint32_t rows,
-                   uint32_t k, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  constexpr int R = NB <= 2 ? 2 : 4;
-  const uint32_t grid = (rows + 4 * R - 1) / (4 * R);
-  return xlaunch(gemv_rows_kernel<NB, R>, dim3(grid), dim3(256), 0, s, e0, e1, w, v, res, out, rows, k);
+template <int NB, int IN, int EPI>
+hipError_t gemv_launch(const GemvArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  constexpr int R = 2;
+  const uint32_t units = EPI == EPI_PLAIN ? a.rows : a.rows / 2;   // rows or row pairs
+  const uint32_t per_wave = EPI == EPI_PLAIN ? R : R / 2;
+  const uint32_t grid = (units + 4 * per_wave - 1) / (4 * per_wave);
+  return xlaunch(gemv_fused_kernel<NB, R, IN, EPI>, dim3(grid), dim3(256), 0, s, e0, e1, a);
+}
+
+template <int IN, int EPI>
+hipError_t gemv_nb(const GemvArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (a.batch <= 1) return gemv_launch<1, IN, EPI>(a, s, e0, e1);
+  if (a.batch <= 2) return gemv_launch<2, IN, EPI>(a, s, e0, e1);
+  if (a.batch <= 4) return gemv_launch<4, IN, EPI>(a, s, e0, e1);
+  return gemv_launch<8, IN, EPI>(a, s, e0, e1);
 }
 
 }  // namespace
 
+hipError_t launch_gemv_fused(const GemvArgs& a, int input_norm, int epilogue, hipStream_t s, hipEvent_t e0,
+                             hipEvent_t e1) {
+  if (a.batch == 0 || a.batch > 8 || a.rows == 0 || a.k == 0 || a.k % 8) return hipErrorInvalidValue;
+  if (input_norm) {
+    switch (epilogue) {
+      case EPI_PLAIN: return gemv_nb<IN_NORM, EPI_PLAIN>(a, s, e0, e1);
+      case EPI_SILU: return gemv_nb<IN_NORM, EPI_SILU>(a, s, e0, e1);
+      case EPI_ROPE: return gemv_nb<IN_NORM, EPI_ROPE>(a, s, e0, e1);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (epilogue) {
+    case EPI_PLAIN: return gemv_nb<IN_BF16, EPI_PLAIN>(a, s, e0, e1);
+    case EPI_SILU: return gemv_nb<IN_BF16, EPI_SILU>(a, s, e0, e1);
+    case EPI_ROPE: return gemv_nb<IN_BF16, EPI_ROPE>(a, s, e0, e1);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_rmsnorm_bf16(const float* x, const uint16_t* g, uint16_t* y, uint32_t rows,
                                uint32_t n, float eps, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   return xlaunch(rmsnorm_kernel, dim3(rows), dim3(256), 0, s, e0, e1, x, g, y, n, eps);
-}
-
-hipError_t launch_gemv_rows(const uint16_t* w, const uint16_t* v, const float* res, float* out,
-                            uint32_t rows, uint32_t k, uint32_t batch, hipStream_t s, hipEvent_t e0,
-                            hipEvent_t e1) {
-  switch (batch) {
-    case 1: return gemv_nb<1>(w, v, res, out, rows, k, s, e0, e1);
-    case 2: return gemv_nb<2>(w, v, res, out, rows, k, s, e0, e1);
-    case 3: return gemv_nb<3>(w, v, res, out, rows, k, s, e0, e1);
-    case 4: return gemv_nb<4>(w, v, res, out, rows, k, s, e0, e1);
-    case 5: return gemv_nb<5>(w, v, res, out, rows, k, s, e0, e1);
-    case 6: return gemv_nb<6>(w, v, res, out, rows, k, s, e0, e1);
-    case 7: return gemv_nb<7>(w, v, res, out, rows, k, s, e0, e1);
-    case 8: return gemv_nb<8>(w, v, res, out, rows, k, s, e0, e1);
-    default: return hipErrorInvalidValue;
-  }
 }
 
 hipError_t launch_rope_append(const float* qkv, const int32_t* pos, float* q_out, uint16_t* kc,
@@ -404,10 +608,10 @@ hipError_t launch_attn_combine(const float* part, const int32_t* pos, uint16_t* 
                                uint32_t nq, uint32_t d, uint32_t nchunks, hipStream_t s, hipEvent_t e0,
                                hipEvent_t e1) {
   if (d == 128)
-    return xlaunch(attn_combine_kernel<128>, dim3(nq, batch), dim3(64), 0, s, e0, e1, part, pos, out, nq,
+    return xlaunch(attn_combine_kernel<128>, dim3(nq, batch), dim3(256), 0, s, e0, e1, part, pos, out, nq,
                    nchunks);
   if (d == 256)
-    return xlaunch(attn_combine_kernel<256>, dim3(nq, batch), dim3(64), 0, s, e0, e1, part, pos, out, nq,
+    return xlaunch(attn_combine_kernel<256>, dim3(nq, batch), dim3(256), 0, s, e0, e1, part, pos, out, nq,
                    nchunks);
   return hipErrorInvalidValue;
 }

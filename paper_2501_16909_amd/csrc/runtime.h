@@ -4,6 +4,7 @@
 #include <array>
 #include <atomic>
 #include <map>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -29,6 +30,7 @@ struct ci_ctx {
   int32_t* dec_pos_host = nullptr;     // pinned, kDecodeMaxBatch entries
   int32_t* dec_pos_dev = nullptr;
   std::vector<hipEvent_t> dec_ev;
+  std::map<std::string, hipGraphExec_t> dec_graphs;   // captured decode steps
 };
 
 struct ci_stressor {
@@ -60,6 +62,7 @@ struct ci_stressor {
 namespace ci {
 constexpr size_t kMaxMaskedStreams = 6;
 constexpr uint32_t kDecodeMaxBatch = 8;
+constexpr size_t kDecodeMaxGraphs = 8;
 double median(std::vector<double> v);
 double quantile(std::vector<double> v, double q);
 int cus_for(const ci_ctx* ctx, double intensity);

@@ -204,6 +204,8 @@ extern "C" ci_status_t ci_shutdown(ci_ctx_t* ctx) {
   if (ctx->amax_part) (void)hipFree(ctx->amax_part);
   if (ctx->amax_out) (void)hipFree(ctx->amax_out);
   if (ctx->probe_buf) (void)hipFree(ctx->probe_buf);
+  for (auto& kv : ctx->dec_graphs) (void)hipGraphExecDestroy(kv.second);
+  ctx->dec_graphs.clear();
   for (auto& ev : ctx->dec_ev)
     if (ev) (void)hipEventDestroy(ev);
   if (ctx->dec_pos_host) (void)hipHostFree(ctx->dec_pos_host);

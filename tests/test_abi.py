@@ -41,7 +41,7 @@ def test_struct_layouts_match_header(tmp_path):
                "ci_policy_t": coloc.Policy, "ci_served_t": coloc.Served,
                "ci_decode_config_t": coloc.DecodeConfig, "ci_decode_layout_t": coloc.DecodeLayout,
                "ci_decode_desc_t": coloc.DecodeDesc, "ci_decode_result_t": coloc.DecodeResult,
-               "ci_decode_cell_t": coloc.DecodeCell}
+               "ci_decode_cell_t": coloc.DecodeCell, "ci_gemv_args_t": coloc.GemvArgs}
     src = tmp_path / "sz.c"
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
     for cname, py in structs.items():
