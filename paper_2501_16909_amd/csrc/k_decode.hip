@@ -28,6 +28,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace ci {
 namespace {
 
@@ -144,139 +146,68 @@ __global__ void __launch_bounds__(256) rmsnorm_kernel(const float* __restrict__ 
 constexpr int IN_BF16 = 0, IN_NORM = 1;
 constexpr int EPI_PLAIN = 0, EPI_SILU = 1, EPI_ROPE = 2;
 
-// Work-group: 4 waves; wave w (global index gw = 4 * blockIdx.x + w) owns R
-// rows: PLAIN rows gw*R .. gw*R + R-1; SILU / ROPE R/2 row pairs.  K is
-// walked in tiles of TK elements; each tile of the NB vectors is staged in
-// LDS (32 KiB) once per work-group and read by all four waves.  Lane l
-// covers 16-byte chunks l, l+64, l+128, l+192 of each 256-chunk step, so a
-// wave's loads of a row are 1 KiB contiguous.  Vectors b >= batch are zero.
-template <int NB, int R, int IN, int EPI>
-__global__ void __launch_bounds__(256) gemv_fused_kernel(GemvArgs a) {
-  constexpr uint32_t TK = 16384 / NB;
-  constexpr uint32_t TC = TK / 8;
-  constexpr int P = R / 2;
-  __shared__ uint4 xs[NB * TC];
-  __shared__ float s_part[4];
-  __shared__ float s_r[NB];
-  const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t gw = blockIdx.x * 4u + (threadIdx.x >> 6);
-  uint32_t row[R], jp[P > 0 ? P : 1];
+// The rows one wave computes at a time (a "unit"): PLAIN R consecutive rows;
+// SILU / ROPE one row pair (R = 2).  For ROPE the lane that writes vector b
+// (lane b) also carries the pair's cosine and sine.
+template <int R, int EPI>
+struct Unit {
+  uint32_t row[R];
   bool live[R];
+  uint32_t jp;             // pair index (SILU / ROPE)
+  const uint4* wr[R];
+  float cs, sn;
+};
+
+template <int NB, int R, int EPI, bool kRope = true>
+__device__ __forceinline__ void map_unit(const GemvArgs& a, uint32_t unit, uint32_t lane, Unit<R, EPI>& u) {
   if constexpr (EPI == EPI_PLAIN) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      row[r] = gw * R + r;
-      live[r] = row[r] < a.rows;
+      u.row[r] = unit * R + r;
+      u.live[r] = u.row[r] < a.rows;
     }
   } else {
     const uint32_t npairs = a.rows / 2;
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      jp[p] = gw * P + p;
-      const bool ok = jp[p] < npairs;
-      uint32_t ra, rb;
-      if constexpr (EPI == EPI_SILU) {
-        ra = jp[p];
-        rb = jp[p] + npairs;
-      } else {
-        const uint32_t half = a.d / 2, head = jp[p] / half, i = jp[p] - head * half;
-        ra = head * a.d + i;
-        rb = ra + half;
-      }
-      row[2 * p] = ra;
-      row[2 * p + 1] = rb;
-      live[2 * p] = live[2 * p + 1] = ok;
+    u.jp = unit;
+    const bool ok = unit < npairs;
+    if constexpr (EPI == EPI_SILU) {
+      u.row[0] = unit;
+      u.row[1] = unit + npairs;
+    } else {
+      const uint32_t half = a.d / 2, head = unit / half, i = unit - head * half;
+      u.row[0] = head * a.d + i;
+      u.row[1] = u.row[0] + half;
     }
+    u.live[0] = u.live[1] = ok;
   }
-  const uint4* wr[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) wr[r] = reinterpret_cast<const uint4*>(a.w + (size_t)(live[r] ? row[r] : 0) * a.k);
-  float acc[R][NB];
+  for (int r = 0; r < R; ++r)
+    u.wr[r] = reinterpret_cast<const uint4*>(a.w + (size_t)(u.live[r] ? u.row[r] : 0) * a.k);
+  u.cs = 1.0f;
+  u.sn = 0.0f;
+  if constexpr (EPI == EPI_ROPE && kRope) {
+    const uint32_t half = a.d / 2, head = u.jp / half;
+    if (u.live[0] && lane < a.batch && head < a.nq + a.nkv)
+      rope_cos_sin((uint32_t)a.pos[lane], u.jp - head * half, a.d, a.base, &u.cs, &u.sn);
+  }
+}
+
+// 16-byte chunks c = 256 j + lane + 64 v (v < 4) of round j of the unit's rows.
+template <int R, int EPI>
+__device__ __forceinline__ void load_round(const Unit<R, EPI>& u, uint32_t j, uint32_t lane, uint32_t kc,
+                                           uint4 (&wv)[R][4]) {
 #pragma unroll
   for (int r = 0; r < R; ++r)
 #pragma unroll
-    for (int b = 0; b < NB; ++b) acc[r][b] = 0.0f;
-  // Rounds of 256 chunks: round j covers chunks 256 j .. 256 j + 255, lane
-  // l the chunks 256 j + l + 64 u (u < 4).  TC is a multiple of 256, so a
-  // round never straddles two tiles.  The next round's weights are loaded
-  // before the current round's products, and round 0's before the vectors
-  // are normalised and staged.
-  const uint32_t kc = a.k / 8;
-  const uint32_t nrounds = (kc + 255) / 256;
-  uint4 wcur[R][4], wnext[R][4];
-  auto load_round = [&](uint32_t j, uint4 (&wv)[R][4]) {
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const uint32_t c = 256u * j + lane + 64u * u;
-        wv[r][u] = (live[r] && c < kc) ? wr[r][c] : make_uint4(0, 0, 0, 0);
-      }
-  };
-  load_round(0, wcur);
-  // ROPE: the lane that writes pair p of vector b (lane p * NB + b) takes
-  // its cosine and sine now, while round 0's weights are in flight.
-  float rcs = 1.0f, rsn = 0.0f;
-  if constexpr (EPI == EPI_ROPE) {
-    const uint32_t p = lane / NB, b = lane % NB;
-    const uint32_t half = a.d / 2, jpl = gw * P + p;
-    if (lane < (uint32_t)(P * NB) && b < a.batch && jpl < a.rows / 2) {
-      const uint32_t head = jpl / half;
-      if (head < a.nq + a.nkv) rope_cos_sin((uint32_t)a.pos[b], jpl - head * half, a.d, a.base, &rcs, &rsn);
+    for (int v = 0; v < 4; ++v) {
+      const uint32_t c = 256u * j + lane + 64u * v;
+      wv[r][v] = (u.live[r] && c < kc) ? u.wr[r][c] : make_uint4(0, 0, 0, 0);
     }
-  }
-  if constexpr (IN == IN_NORM) {
-#pragma unroll 1
-    for (uint32_t b = 0; b < (uint32_t)NB; ++b) {
-      float tot = 0.0f;
-      if (b < a.batch) tot = block_sumsq_256(a.x + (size_t)b * a.k, a.k, s_part);
-      if (threadIdx.x == 0) s_r[b] = b < a.batch ? rms_factor(tot, a.k, a.eps) : 0.0f;
-    }
-  }
-  for (uint32_t j = 0; j < nrounds; ++j) {
-    const uint32_t cr = 256u * j;          // first chunk of the round
-    const uint32_t c0 = cr - cr % TC;      // first chunk of its tile
-    if (cr == c0) {
-      const uint32_t nch = min(TC, kc - c0);
-      __syncthreads();
-      for (uint32_t i = threadIdx.x; i < NB * nch; i += 256) {
-        const uint32_t b = i / nch, c = i - b * nch;
-        uint4 val = make_uint4(0, 0, 0, 0);
-        if (b < a.batch) {
-          if constexpr (IN == IN_BF16) {
-            val = reinterpret_cast<const uint4*>(a.v + (size_t)b * a.k)[c0 + c];
-          } else {
-            const float4* xp = reinterpret_cast<const float4*>(a.x + (size_t)b * a.k) + 2 * (c0 + c);
-            const float4 x0 = xp[0], x1 = xp[1];
-            const uint4 gg = reinterpret_cast<const uint4*>(a.g)[c0 + c];
-            const float r = s_r[b];
-            val.x = pack2(norm_bf16(x0.x, r, bf_lo(gg.x)), norm_bf16(x0.y, r, bf_hi(gg.x)));
-            val.y = pack2(norm_bf16(x0.z, r, bf_lo(gg.y)), norm_bf16(x0.w, r, bf_hi(gg.y)));
-            val.z = pack2(norm_bf16(x1.x, r, bf_lo(gg.z)), norm_bf16(x1.y, r, bf_hi(gg.z)));
-            val.w = pack2(norm_bf16(x1.z, r, bf_lo(gg.w)), norm_bf16(x1.w, r, bf_hi(gg.w)));
-          }
-        }
-        xs[b * TC + c] = val;
-      }
-      __syncthreads();
-    }
-    if (j + 1 < nrounds) load_round(j + 1, wnext);
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const uint32_t c = cr + lane + 64u * u;
-      if (c >= kc) break;
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const uint4 xv = xs[b * TC + (c - c0)];
-#pragma unroll
-        for (int r = 0; r < R; ++r) acc[r][b] = dot8(wcur[r][u], xv, acc[r][b]);
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) wcur[r][u] = wnext[r][u];
-  }
+}
+
+template <int NB, int R, int EPI>
+__device__ __forceinline__ void epilogue(const GemvArgs& a, const Unit<R, EPI>& u, uint32_t lane,
+                                         float (&acc)[R][NB]) {
 #pragma unroll
   for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -286,47 +217,182 @@ __global__ void __launch_bounds__(256) gemv_fused_kernel(GemvArgs a) {
     for (int r = 0; r < R; ++r)
 #pragma unroll
       for (int b = 0; b < NB; ++b)
-        if (lane == (uint32_t)(r * NB + b) && live[r] && (uint32_t)b < a.batch) {
-          const size_t o = (size_t)b * a.rows + row[r];
+        if (lane == (uint32_t)(r * NB + b) && u.live[r] && (uint32_t)b < a.batch) {
+          const size_t o = (size_t)b * a.rows + u.row[r];
           a.out[o] = (a.res ? a.res[o] : 0.0f) + acc[r][b];
         }
   } else if constexpr (EPI == EPI_SILU) {
     const uint32_t f = a.rows / 2;
 #pragma unroll
-    for (int p = 0; p < P; ++p)
-#pragma unroll
-      for (int b = 0; b < NB; ++b)
-        if (lane == (uint32_t)(p * NB + b) && live[2 * p] && (uint32_t)b < a.batch)
-          a.h[(size_t)b * f + jp[p]] = f32_to_bf16_rne(silu_mul_f(acc[2 * p][b], acc[2 * p + 1][b]));
+    for (int b = 0; b < NB; ++b)
+      if (lane == (uint32_t)b && u.live[0] && (uint32_t)b < a.batch)
+        a.h[(size_t)b * f + u.jp] = f32_to_bf16_rne(silu_mul_f(acc[0][b], acc[1][b]));
   } else {
-    const uint32_t half = a.d / 2;
+    const uint32_t half = a.d / 2, head = u.jp / half, i = u.jp - head * half;
 #pragma unroll
-    for (int p = 0; p < P; ++p)
-#pragma unroll
-      for (int b = 0; b < NB; ++b)
-        if (lane == (uint32_t)(p * NB + b) && live[2 * p] && (uint32_t)b < a.batch) {
-          const uint32_t head = jp[p] / half, i = jp[p] - head * half;
-          const uint32_t pp = (uint32_t)a.pos[b];
-          const float x1 = acc[2 * p][b], x2 = acc[2 * p + 1][b];
-          if (head < a.nq) {
-            float y1, y2;
-            rope_apply(x1, x2, rcs, rsn, &y1, &y2);
-            float* dst = a.q_out + ((size_t)b * a.nq + head) * a.d;
-            dst[i] = y1;
-            dst[i + half] = y2;
-          } else if (head < a.nq + a.nkv) {
-            float y1, y2;
-            rope_apply(x1, x2, rcs, rsn, &y1, &y2);
-            uint16_t* dst = a.kc + (((size_t)b * a.nkv + (head - a.nq)) * a.max_ctx + pp) * a.d;
-            dst[i] = f32_to_bf16_rne(y1);
-            dst[i + half] = f32_to_bf16_rne(y2);
-          } else {
-            uint16_t* dst = a.vc + (((size_t)b * a.nkv + (head - a.nq - a.nkv)) * a.max_ctx + pp) * a.d;
-            dst[i] = f32_to_bf16_rne(x1);
-            dst[i + half] = f32_to_bf16_rne(x2);
-          }
+    for (int b = 0; b < NB; ++b)
+      if (lane == (uint32_t)b && u.live[0] && (uint32_t)b < a.batch) {
+        const uint32_t pp = (uint32_t)a.pos[b];
+        const float x1 = acc[0][b], x2 = acc[1][b];
+        if (head < a.nq) {
+          float y1, y2;
+          rope_apply(x1, x2, u.cs, u.sn, &y1, &y2);
+          float* dst = a.q_out + ((size_t)b * a.nq + head) * a.d;
+          dst[i] = y1;
+          dst[i + half] = y2;
+        } else if (head < a.nq + a.nkv) {
+          float y1, y2;
+          rope_apply(x1, x2, u.cs, u.sn, &y1, &y2);
+          uint16_t* dst = a.kc + (((size_t)b * a.nkv + (head - a.nq)) * a.max_ctx + pp) * a.d;
+          dst[i] = f32_to_bf16_rne(y1);
+          dst[i + half] = f32_to_bf16_rne(y2);
+        } else {
+          uint16_t* dst = a.vc + (((size_t)b * a.nkv + (head - a.nq - a.nkv)) * a.max_ctx + pp) * a.d;
+          dst[i] = f32_to_bf16_rne(x1);
+          dst[i + half] = f32_to_bf16_rne(x2);
         }
+      }
   }
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[r][b] = 0.0f;
+}
+
+// Stage chunks c0 .. c0 + nch - 1 of the NB vectors into LDS (BF16 input,
+// or FP32 input normalised with factors s_r and gain g); zeros for b >= batch.
+template <int NB, int IN>
+__device__ __forceinline__ void stage_tile(const GemvArgs& a, uint32_t c0, uint32_t nch, uint32_t tc,
+                                           const float* s_r, uint4* xs) {
+  for (uint32_t i = threadIdx.x; i < NB * nch; i += 256) {
+    const uint32_t b = i / nch, c = i - b * nch;
+    uint4 val = make_uint4(0, 0, 0, 0);
+    if (b < a.batch) {
+      if constexpr (IN == IN_BF16) {
+        val = reinterpret_cast<const uint4*>(a.v + (size_t)b * a.k)[c0 + c];
+      } else {
+        const float4* xp = reinterpret_cast<const float4*>(a.x + (size_t)b * a.k) + 2 * (c0 + c);
+        const float4 x0 = xp[0], x1 = xp[1];
+        const uint4 gg = reinterpret_cast<const uint4*>(a.g)[c0 + c];
+        const float r = s_r[b];
+        val.x = pack2(norm_bf16(x0.x, r, bf_lo(gg.x)), norm_bf16(x0.y, r, bf_hi(gg.x)));
+        val.y = pack2(norm_bf16(x0.z, r, bf_lo(gg.y)), norm_bf16(x0.w, r, bf_hi(gg.y)));
+        val.z = pack2(norm_bf16(x1.x, r, bf_lo(gg.z)), norm_bf16(x1.y, r, bf_hi(gg.z)));
+        val.w = pack2(norm_bf16(x1.z, r, bf_lo(gg.w)), norm_bf16(x1.w, r, bf_hi(gg.w)));
+      }
+    }
+    xs[b * tc + c] = val;
+  }
+}
+
+// out = W x (rows of BF16 weights times NB vectors), FP32 accumulation.
+// Work-group: 4 waves.  K is walked in rounds of 256 16-byte chunks (lane l
+// takes chunks l, l+64, l+128, l+192 of a round: 1 KiB contiguous per row
+// per wave); the vectors are staged in LDS in tiles of TK elements (32 KiB),
+// once per work-group, read by all four waves.  TC is a multiple of 256, so
+// a round never straddles two tiles.  Each lane's products are summed in
+// increasing chunk order, then over the 64 lanes by a butterfly: the result
+// does not depend on NB, R or the grid.
+//   One tile (k <= TK): the grid is persistent; wave gw takes units gw,
+//     gw + 4 gridDim.x, ...; the next step's weights (next round, or round 0
+//     of the next unit) are loaded before the current step's products.
+//   Several tiles: one unit per wave, tiles staged in turn.
+template <int NB, int R, int IN, int EPI>
+__global__ void __launch_bounds__(256) gemv_fused_kernel(GemvArgs a, uint32_t units) {
+  constexpr uint32_t TK = 16384 / NB;
+  constexpr uint32_t TC = TK / 8;
+  __shared__ uint4 xs[NB * TC];
+  __shared__ float s_part[4];
+  __shared__ float s_r[NB];
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t gw = blockIdx.x * 4u + (threadIdx.x >> 6);
+  const uint32_t nwaves = gridDim.x * 4u;
+  const uint32_t kc = a.k / 8;
+  const uint32_t nrounds = (kc + 255) / 256;
+  float acc[R][NB];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[r][b] = 0.0f;
+  Unit<R, EPI> cur;
+  uint4 wcur[R][4], wnext[R][4];
+  map_unit<NB, R, EPI>(a, gw, lane, cur);
+  load_round(cur, 0, lane, kc, wcur);
+  if constexpr (IN == IN_NORM) {
+#pragma unroll 1
+    for (uint32_t b = 0; b < (uint32_t)NB; ++b) {
+      float tot = 0.0f;
+      if (b < a.batch) tot = block_sumsq_256(a.x + (size_t)b * a.k, a.k, s_part);
+      if (threadIdx.x == 0) s_r[b] = b < a.batch ? rms_factor(tot, a.k, a.eps) : 0.0f;
+    }
+  }
+  if (kc <= TC) {
+    __syncthreads();
+    stage_tile<NB, IN>(a, 0, kc, TC, s_r, xs);
+    __syncthreads();
+    uint32_t unit = gw, j = 0;
+    while (unit < units) {
+      const bool wrap = j + 1 == nrounds;
+      const uint32_t nunit = wrap ? unit + nwaves : unit;
+      if (nunit < units) {
+        if (wrap) {
+          Unit<R, EPI> t;      // weights only: the rotary factors come with the unit itself
+          map_unit<NB, R, EPI, false>(a, nunit, lane, t);
+          load_round(t, 0, lane, kc, wnext);
+        } else {
+          load_round(cur, j + 1, lane, kc, wnext);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const uint32_t c = 256u * j + lane + 64u * v;
+        if (c >= kc) break;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const uint4 xv = xs[b * TC + c];
+#pragma unroll
+          for (int r = 0; r < R; ++r) acc[r][b] = dot8(wcur[r][v], xv, acc[r][b]);
+        }
+      }
+      if (wrap) {
+        epilogue<NB, R, EPI>(a, cur, lane, acc);
+        map_unit<NB, R, EPI>(a, nunit, lane, cur);
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) wcur[r][v] = wnext[r][v];
+      unit = nunit;
+      j = wrap ? 0 : j + 1;
+    }
+    return;
+  }
+  for (uint32_t j = 0; j < nrounds; ++j) {
+    const uint32_t cr = 256u * j;          // first chunk of the round
+    const uint32_t c0 = cr - cr % TC;      // first chunk of its tile
+    if (cr == c0) {
+      __syncthreads();
+      stage_tile<NB, IN>(a, c0, min(TC, kc - c0), TC, s_r, xs);
+      __syncthreads();
+    }
+    if (j + 1 < nrounds) load_round(cur, j + 1, lane, kc, wnext);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const uint32_t c = cr + lane + 64u * v;
+      if (c >= kc) break;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const uint4 xv = xs[b * TC + (c - c0)];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r][b] = dot8(wcur[r][v], xv, acc[r][b]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) wcur[r][v] = wnext[r][v];
+  }
+  if (gw < units) epilogue<NB, R, EPI>(a, cur, lane, acc);
 }
 
 // ------------------------------------------------------------- RoPE + cache
@@ -538,21 +604,49 @@ __global__ void __launch_bounds__(256) silu_mul_kernel(const float* __restrict__
   }
 }
 
-template <int NB, int IN, int EPI>
+// Work-groups of `kernel` (256 threads) that fit on the device at once:
+// the size of a persistent grid.
+uint32_t resident_wgs(const void* kernel) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, 0) != hipSuccess)
+    return 256;
+  return (uint32_t)std::max(1, cus * std::max(per, 1));
+}
+
+template <int NB, int R, int IN, int EPI>
+uint32_t resident_of() {
+  static const uint32_t n = resident_wgs(reinterpret_cast<const void*>(gemv_fused_kernel<NB, R, IN, EPI>));
+  return n;
+}
+
+template <int NB, int R, int IN, int EPI>
 hipError_t gemv_launch(const GemvArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  constexpr int R = 2;
-  const uint32_t units = EPI == EPI_PLAIN ? a.rows : a.rows / 2;   // rows or row pairs
-  const uint32_t per_wave = EPI == EPI_PLAIN ? R : R / 2;
-  const uint32_t grid = (units + 4 * per_wave - 1) / (4 * per_wave);
-  return xlaunch(gemv_fused_kernel<NB, R, IN, EPI>, dim3(grid), dim3(256), 0, s, e0, e1, a);
+  const uint32_t units = EPI == EPI_PLAIN ? (a.rows + R - 1) / R : a.rows / 2;
+  uint32_t grid = (units + 3) / 4;
+  const uint32_t tc = 2048 / NB;
+  if (a.k / 8 <= tc) grid = std::min(grid, resident_of<NB, R, IN, EPI>());
+  if (grid == 0) grid = 1;
+  return xlaunch(gemv_fused_kernel<NB, R, IN, EPI>, dim3(grid), dim3(256), 0, s, e0, e1, a, units);
+}
+
+template <int NB, int IN, int EPI>
+hipError_t gemv_rows_r(const GemvArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  // plain rows: one row per wave while the resident grid still has a wave
+  // for every row, two rows otherwise
+  if constexpr (EPI == EPI_PLAIN) {
+    if (a.rows <= 4 * resident_of<NB, 1, IN, EPI>()) return gemv_launch<NB, 1, IN, EPI>(a, s, e0, e1);
+  }
+  return gemv_launch<NB, 2, IN, EPI>(a, s, e0, e1);
 }
 
 template <int IN, int EPI>
 hipError_t gemv_nb(const GemvArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  if (a.batch <= 1) return gemv_launch<1, IN, EPI>(a, s, e0, e1);
-  if (a.batch <= 2) return gemv_launch<2, IN, EPI>(a, s, e0, e1);
-  if (a.batch <= 4) return gemv_launch<4, IN, EPI>(a, s, e0, e1);
-  return gemv_launch<8, IN, EPI>(a, s, e0, e1);
+  if (a.batch <= 1) return gemv_rows_r<1, IN, EPI>(a, s, e0, e1);
+  if (a.batch <= 2) return gemv_rows_r<2, IN, EPI>(a, s, e0, e1);
+  if (a.batch <= 4) return gemv_rows_r<4, IN, EPI>(a, s, e0, e1);
+  return gemv_rows_r<8, IN, EPI>(a, s, e0, e1);
 }
 
 }  // namespace
