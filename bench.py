@@ -42,7 +42,7 @@ def sha_of(*paths):
 
 
 # sources the HBM stressor's machine code is built from
-HBM_KERNEL_SOURCES = [os.path.join("paper_2501_16909_amd", "csrc", f) for f in ("k_memory.hip", "internal.h")]
+HBM_KERNEL_SOURCES = [os.path.join("paper_2501_16909_amd", "csrc", f) for f in ("k_memory.hip", "stressor_dev.h")]
 
 
 # --------------------------------------------------------------------------
