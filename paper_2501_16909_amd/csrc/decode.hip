@@ -294,9 +294,13 @@ ci_status_t run_decode(ci_ctx* ctx, const ci_decode_desc_t* d, hipStream_t calle
   const bool timed = d->flags & CI_DECODE_KERNEL_TIMES;
   ci_status_t st = ensure_decode_state(ctx, timed ? 2 * (size_t)nk : 0);
   if (st != CI_OK) return st;
+  if (!d->pos) return set_err(CI_ERR_INVALID_ARG, "decode: NULL positions");
   uint32_t max_pos = 0;
-  for (uint32_t b = 0; b < c.batch; ++b) {   // validated again when staged
-    if (d->pos && d->pos[b] >= 0) max_pos = std::max(max_pos, (uint32_t)d->pos[b]);
+  for (uint32_t b = 0; b < c.batch; ++b) {   // before any capture or launch
+    if (d->pos[b] < 0 || (uint32_t)d->pos[b] >= c.max_ctx)
+      return set_err(CI_ERR_INVALID_ARG, "decode: position %d of sequence %u not in [0, %u)", d->pos[b], b,
+                     c.max_ctx);
+    max_pos = std::max(max_pos, (uint32_t)d->pos[b]);
   }
   const uint32_t used = max_pos / kChunk + 1;
   hipGraphExec_t graph = nullptr;

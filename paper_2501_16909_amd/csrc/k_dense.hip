@@ -162,20 +162,27 @@ __global__ void __launch_bounds__(256, 2) gemm_kernel(const uint8_t* __restrict_
     }
 }
 
-// Large-tile GEMM: one 256-thread work-group per CU owns a 256 x 256 tile of
-// C; each of its four waves owns 128 x 128 (4 x 4 MFMA tiles of 32 x 32, 16
-// accumulators), so every LDS fragment read feeds four MFMAs instead of two.
-// Two 72 KiB K-stages of A and B are double-buffered in LDS (144 KiB of the
-// CU's 160 KiB), filled through registers while the other stage computes.
+// Large-tile GEMM: one work-group per CU owns a 256 x 256 tile of C, with
+// WAVES waves in a 2 x WAVES/2 grid: each wave owns 128 x (512/WAVES)
+// (4 x 1024/(32 WAVES) MFMA tiles of 32 x 32), so every A fragment read from
+// LDS feeds several MFMAs.  With 8 waves two share each SIMD, so one wave's
+// LDS reads and barrier waits overlap the other's MFMAs.  Two 72 KiB
+// K-stages of A and B are double-buffered in LDS (144 KiB of the CU's
+// 160 KiB), filled through registers while the other stage computes.
 constexpr int kBig = 256;
 constexpr int kBigTileLds = kBig * kRowPitch;    // one operand, one stage
+constexpr int kBigWaves = 8;
 
-template <int DT>
-__global__ void __launch_bounds__(256, 1) gemm256_kernel(const uint8_t* __restrict__ A,
-                                                         const uint8_t* __restrict__ B,
-                                                         float* __restrict__ C, uint32_t M,
-                                                         uint32_t N, uint32_t K, float scale) {
+template <int DT, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES, 1) gemm256_kernel(const uint8_t* __restrict__ A,
+                                                                const uint8_t* __restrict__ B,
+                                                                float* __restrict__ C, uint32_t M,
+                                                                uint32_t N, uint32_t K, float scale) {
   using G = Gemm<DT>;
+  constexpr int NT = 64 * WAVES;          // threads
+  constexpr int WN = WAVES / 2;           // waves along N
+  constexpr int JN = kBig / WN / 32;      // 32-wide MFMA tiles per wave along N
+  constexpr int LR = kBig / (NT / 8);     // rows each thread stages per operand
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   uint8_t* sA = smem;                     // [2][256][kRowPitch]
   uint8_t* sB = smem + 2 * kBigTileLds;   // [2][256][kRowPitch]
@@ -183,18 +190,18 @@ __global__ void __launch_bounds__(256, 1) gemm256_kernel(const uint8_t* __restri
   uint32_t tm, tn;
   tile_of(blockIdx.x, nbm, nbn, tm, tn);
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wid = tid >> 6;
-  const uint32_t wm = wid >> 1, wn = wid & 1u;   // wave's 128x128 sub-tile
+  const uint32_t wm = wid / WN, wn = wid % WN;   // wave's 128 x (256/WN) sub-tile
   const uint64_t rowBytes = (uint64_t)K * G::kElem;
   const uint32_t nstages = (uint32_t)((rowBytes + kStageBytes - 1) / kStageBytes);
-  // global -> register staging: thread loads 16 B at (row = tid/8 + 32 j, chunk = tid%8)
+  // global -> register staging: thread loads 16 B at (row = tid/8 + NT/8 j, chunk = tid%8)
   const uint32_t lrow = tid >> 3, lchunk = tid & 7u;
-  i32x4 ra[8], rb[8];
+  i32x4 ra[LR], rb[LR];
   auto gload = [&](uint32_t st) {
     const uint64_t kb = (uint64_t)st * kStageBytes + lchunk * 16u;
     const bool kin = kb + 16 <= rowBytes;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const uint32_t r = lrow + 32u * j;
+    for (int j = 0; j < LR; ++j) {
+      const uint32_t r = lrow + (NT / 8) * j;
       const uint32_t gm = tm * kBig + r, gn = tn * kBig + r;
       ra[j] = (kin && gm < M) ? *reinterpret_cast<const i32x4*>(A + gm * rowBytes + kb) : i32x4{0, 0, 0, 0};
       rb[j] = (kin && gn < N) ? *reinterpret_cast<const i32x4*>(B + gn * rowBytes + kb) : i32x4{0, 0, 0, 0};
@@ -202,17 +209,17 @@ __global__ void __launch_bounds__(256, 1) gemm256_kernel(const uint8_t* __restri
   };
   auto sstore = [&](uint32_t buf) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const uint32_t r = lrow + 32u * j;
+    for (int j = 0; j < LR; ++j) {
+      const uint32_t r = lrow + (NT / 8) * j;
       *reinterpret_cast<i32x4*>(sA + buf * kBigTileLds + r * kRowPitch + lchunk * 16u) = ra[j];
       *reinterpret_cast<i32x4*>(sB + buf * kBigTileLds + r * kRowPitch + lchunk * 16u) = rb[j];
     }
   };
-  f32x16 acc[4][4];
+  f32x16 acc[4][JN];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < JN; ++j)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
 
@@ -224,14 +231,14 @@ __global__ void __launch_bounds__(256, 1) gemm256_kernel(const uint8_t* __restri
     const uint32_t buf = st & 1u;
     if (st + 1 < nstages) gload(st + 1);
     const uint8_t* a0 = sA + buf * kBigTileLds + (wm * 128 + frow) * kRowPitch + fk;
-    const uint8_t* b0 = sB + buf * kBigTileLds + (wn * 128 + frow) * kRowPitch + fk;
+    const uint8_t* b0 = sB + buf * kBigTileLds + (wn * (kBig / WN) + frow) * kRowPitch + fk;
 #pragma unroll
     for (int s = 0; s < G::kSub; ++s) {
       const uint32_t ko = s * 2 * G::kFragBytes;
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < JN; ++j)
           acc[i][j] = G::mma(a0 + i * 32 * kRowPitch + ko, b0 + j * 32 * kRowPitch + ko, acc[i][j]);
     }
     if (st + 1 < nstages) sstore(buf ^ 1u);
@@ -240,8 +247,8 @@ __global__ void __launch_bounds__(256, 1) gemm256_kernel(const uint8_t* __restri
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const uint32_t col = tn * kBig + wn * 128 + j * 32 + (lane & 31u);
+    for (int j = 0; j < JN; ++j) {
+      const uint32_t col = tn * kBig + wn * (kBig / WN) + j * 32 + (lane & 31u);
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const uint32_t row = tm * kBig + wm * 128 + i * 32 + 8u * (v / 4) + 4u * (lane >> 5) + (v % 4);
@@ -306,16 +313,17 @@ hipError_t launch_gemm(int dtype, const void* a, const void* b, float* c, uint64
     const uint32_t shm = 4 * kBigTileLds;
     const uint8_t* A = (const uint8_t*)a;
     const uint8_t* B = (const uint8_t*)b;
+    constexpr int W = kBigWaves;
     switch (dtype) {
       case CI_DT_F32:
-        return xlaunch(gemm256_kernel<CI_DT_F32>, dim3((uint32_t)nbig), dim3(256), shm, s, e0, e1, A, B,
-                       c, (uint32_t)m, (uint32_t)n, (uint32_t)k, scale);
-      case CI_DT_BF16:
-        return xlaunch(gemm256_kernel<CI_DT_BF16>, dim3((uint32_t)nbig), dim3(256), shm, s, e0, e1, A, B,
-                       c, (uint32_t)m, (uint32_t)n, (uint32_t)k, scale);
-      case CI_DT_FP8E4M3:
-        return xlaunch(gemm256_kernel<CI_DT_FP8E4M3>, dim3((uint32_t)nbig), dim3(256), shm, s, e0, e1, A,
+        return xlaunch(gemm256_kernel<CI_DT_F32, W>, dim3((uint32_t)nbig), dim3(64 * W), shm, s, e0, e1, A,
                        B, c, (uint32_t)m, (uint32_t)n, (uint32_t)k, scale);
+      case CI_DT_BF16:
+        return xlaunch(gemm256_kernel<CI_DT_BF16, W>, dim3((uint32_t)nbig), dim3(64 * W), shm, s, e0, e1, A,
+                       B, c, (uint32_t)m, (uint32_t)n, (uint32_t)k, scale);
+      case CI_DT_FP8E4M3:
+        return xlaunch(gemm256_kernel<CI_DT_FP8E4M3, W>, dim3((uint32_t)nbig), dim3(64 * W), shm, s, e0, e1,
+                       A, B, c, (uint32_t)m, (uint32_t)n, (uint32_t)k, scale);
       default: return hipErrorInvalidValue;
     }
   }
