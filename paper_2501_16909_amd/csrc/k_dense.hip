@@ -4,12 +4,20 @@
 // matrix-vector products that stream weights from memory (Sections 4.2-4.3).
 //
 // GEMM layout: A is M x K and B is N x K, both row-major (K contiguous), C is
-// M x N FP32 row-major.  A 256-thread work-group owns a 128 x 128 tile of C;
-// its four waves each own 64 x 64 (2 x 2 MFMA tiles of 32 x 32).  K is
-// consumed in stages of 128 bytes per row, double-buffered in LDS through
-// registers: the next stage's global loads are in flight while the current
-// stage feeds the MFMAs.  Rows and K chunks past the matrix edges read as
-// zero, so any M and N work; K * element size must be a multiple of 16.
+// M x N FP32 row-major.  Three kernels, one summation order (each output is
+// the MFMA chain over K in increasing order, so they agree bit for bit):
+//   gemm256d_kernel  256 x 256 tiles, direct global -> LDS loads into a
+//                    4-stage ring; shapes with >= 256 tiles and K * element
+//                    size a multiple of 64 bytes;
+//   gemm256_kernel   256 x 256 tiles staged through registers, other
+//                    shapes with >= 256 tiles;
+//   gemm_kernel      128 x 128 tiles for smaller shapes: a 256-thread
+//                    work-group, four waves of 64 x 64 (2 x 2 MFMA tiles of
+//                    32 x 32), K in stages of 128 bytes per row
+//                    double-buffered in LDS through registers.
+// Rows and K chunks past the matrix edges read as zero (register-staged
+// kernels) or only feed outputs that are not stored (ring kernel), so any M
+// and N work; K * element size must be a multiple of 16.
 #include "internal.h"
 
 namespace ci {
@@ -68,15 +76,22 @@ struct Gemm<CI_DT_FP8E4M3> {
   }
 };
 
-// Map the work-group index to a C tile so that the tiles one XCD works on
-// are contiguous (work-groups are dealt to the 8 XCDs round-robin).
+// Map the work-group index to a C tile.  Work-groups are dealt to the 8
+// XCDs round-robin, so first each XCD gets a contiguous range of tile
+// numbers t; then t runs down bands of 4 tile rows (column by column within
+// a band), so the tiles an XCD computes at one time form a 4 x 8 block that
+// shares 4 A panels and 8 B panels in that XCD's L2 (a 2 x 16 row-major
+// block would need 18).
 __device__ __forceinline__ void tile_of(uint32_t bid, uint32_t nbm, uint32_t nbn, uint32_t& tm,
                                         uint32_t& tn) {
   const uint32_t nb = nbm * nbn;
   uint32_t t = bid;
   if ((nb & 7u) == 0) t = (bid & 7u) * (nb >> 3) + (bid >> 3);
-  tm = t / nbn;
-  tn = t % nbn;
+  constexpr uint32_t kBand = 4;
+  const uint32_t band = kBand * nbn, group = t / band;
+  const uint32_t first = group * kBand, rows = min(nbm - first, kBand), r = t - group * band;
+  tm = first + r % rows;
+  tn = r / rows;
 }
 
 template <int DT>
@@ -257,6 +272,148 @@ __global__ void __launch_bounds__(64 * WAVES, 1) gemm256_kernel(const uint8_t* _
     }
 }
 
+
+// Large-tile GEMM with direct global -> LDS loads (16 bytes per lane,
+// lane l of a wave instruction filling bytes 16 l of a 1 KiB block) into a
+// 4-deep ring of K-stages of 64 bytes per row: stages st + 1 .. st + 3 are in
+// flight while stage st computes, without staging registers.  Rows are
+// stored unpadded; the 16-byte chunk c of row r sits at chunk
+// c ^ ((r >> 2) & 3), so the 32 rows a fragment read touches fall on
+// distinct banks.  Eight waves (2 x 4, each 128 x 64; two per SIMD) read
+// their stage's fragments into registers, then issue its MFMAs.  One bare
+// barrier per stage: each wave first waits for its own loads of the stage
+// (s_waitcnt on the vector-memory counter), so after the barrier the whole
+// stage is in LDS and the slot of stage st - 1 may be refilled; a fence
+// there would also wait for the later stages' loads.  Needs K * element
+// size to be a multiple of 64 bytes; the register-staged kernel above takes
+// the rest.
+constexpr int kRingStages = 4;
+constexpr int kDStage = 64;                         // K bytes per stage per row
+constexpr int kDOperand = kBig * kDStage;           // one operand, one stage (16 KiB)
+constexpr int kDSlot = 2 * kDOperand;               // A and B of one stage
+
+__device__ __forceinline__ uint32_t dswz(uint32_t row, uint32_t byte) {
+  return row * kDStage + ((((byte >> 4) ^ (row >> 2)) & 3u) << 4) + (byte & 15u);
+}
+
+// One MFMA operand fragment per lane, read from a swizzled LDS stage.
+template <int DT> struct Frag;
+template <> struct Frag<CI_DT_F32> {
+  using T = float;
+  __device__ static T ld(const uint8_t* p, uint32_t row, uint32_t kb) {
+    return *reinterpret_cast<const float*>(p + dswz(row, kb));
+  }
+  __device__ static f32x16 mma(T a, T b, f32x16 c) { return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0); }
+};
+template <> struct Frag<CI_DT_BF16> {
+  using T = bf16x8;
+  __device__ static T ld(const uint8_t* p, uint32_t row, uint32_t kb) {
+    return *reinterpret_cast<const bf16x8*>(p + dswz(row, kb));
+  }
+  __device__ static f32x16 mma(T a, T b, f32x16 c) { return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0); }
+};
+template <> struct Frag<CI_DT_FP8E4M3> {
+  using T = i32x8;
+  __device__ static T ld(const uint8_t* p, uint32_t row, uint32_t kb) {
+    const i32x4 a0 = *reinterpret_cast<const i32x4*>(p + dswz(row, kb));
+    const i32x4 a1 = *reinterpret_cast<const i32x4*>(p + dswz(row, kb + 16));
+    return i32x8{a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+  }
+  __device__ static f32x16 mma(T a, T b, f32x16 c) {
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 0, 0, 0);
+  }
+};
+
+template <int DT>
+__global__ void __launch_bounds__(512, 1) gemm256d_kernel(const uint8_t* __restrict__ A,
+                                                          const uint8_t* __restrict__ B,
+                                                          float* __restrict__ C, uint32_t M,
+                                                          uint32_t N, uint32_t K, float scale) {
+  using G = Gemm<DT>;
+  constexpr int WN = 4, JN = 2;           // 8 waves: 2 x 4, each 128 x 64
+  extern __shared__ __attribute__((aligned(1024))) uint8_t smem[];
+  const uint32_t nbm = (M + kBig - 1) / kBig, nbn = (N + kBig - 1) / kBig;
+  uint32_t tm, tn;
+  tile_of(blockIdx.x, nbm, nbn, tm, tn);
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wid = tid >> 6;
+  const uint32_t wm = wid / WN, wn = wid % WN;
+  const uint64_t rowBytes = (uint64_t)K * G::kElem;
+  const uint32_t nstages = (uint32_t)(rowBytes / kDStage);
+  // Wave w fills 1 KiB blocks w and w + 8 of each operand (16 blocks of 16
+  // rows); lane l lands on row 16 q + l / 4, physical chunk l % 4.
+  uint32_t lrow[2], lchunk[2];
+  const uint8_t* srcA[2];
+  const uint8_t* srcB[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const uint32_t q = wid + 8u * h;
+    lrow[h] = 16u * q + (lane >> 2);
+    lchunk[h] = ((lane & 3u) ^ (lrow[h] >> 2)) & 3u;    // logical chunk for this slot
+    const uint32_t gm = min(tm * kBig + lrow[h], M - 1), gn = min(tn * kBig + lrow[h], N - 1);
+    srcA[h] = A + (uint64_t)gm * rowBytes + lchunk[h] * 16u;
+    srcB[h] = B + (uint64_t)gn * rowBytes + lchunk[h] * 16u;
+  }
+  auto issue = [&](uint32_t st) {
+    uint8_t* slot = smem + (st % kRingStages) * kDSlot;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t blk = (wid + 8u * h) * 1024u;
+      __builtin_amdgcn_global_load_lds(srcA[h] + (uint64_t)st * kDStage, slot + blk, 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(srcB[h] + (uint64_t)st * kDStage, slot + kDOperand + blk, 16, 0, 0);
+    }
+  };
+  f32x16 acc[4][JN];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < JN; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+  for (uint32_t st = 0; st < kRingStages - 1 && st < nstages; ++st) issue(st);
+  const uint32_t frow = lane & 31u, fk = (lane >> 5) * G::kFragBytes;
+  for (uint32_t st = 0; st < nstages; ++st) {
+    // this wave's loads of stage st are done when at most the loads of the
+    // stages issued after it (up to 2 stages x 4 instructions) are pending
+    const uint32_t after = min(nstages - 1 - st, (uint32_t)kRingStages - 2);
+    if (after >= 2) __builtin_amdgcn_s_waitcnt(0x0F78);        // vmcnt(8)
+    else if (after == 1) __builtin_amdgcn_s_waitcnt(0x0F74);   // vmcnt(4)
+    else __builtin_amdgcn_s_waitcnt(0x0F70);                   // vmcnt(0)
+    // every wave's part of stage st is in LDS and stage st - 1 is consumed;
+    // a bare barrier: a fence here would wait for the later stages' loads too
+    __builtin_amdgcn_s_barrier();
+    if (st + kRingStages - 1 < nstages) issue(st + kRingStages - 1);
+    const uint8_t* slot = smem + (st % kRingStages) * kDSlot;
+    constexpr int NS = kDStage / (2 * G::kFragBytes);
+    using F = Frag<DT>;
+    typename F::T fa[NS][4], fb[NS][JN];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const uint32_t kb = fk + s * 2 * G::kFragBytes;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) fa[s][i] = F::ld(slot, wm * 128 + i * 32 + frow, kb);
+#pragma unroll
+      for (int j = 0; j < JN; ++j) fb[s][j] = F::ld(slot + kDOperand, wn * 64 + j * 32 + frow, kb);
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < JN; ++j) acc[i][j] = F::mma(fa[s][i], fb[s][j], acc[i][j]);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < JN; ++j) {
+      const uint32_t col = tn * kBig + wn * 64 + j * 32 + (lane & 31u);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const uint32_t row = tm * kBig + wm * 128 + i * 32 + 8u * (v / 4) + 4u * (lane >> 5) + (v % 4);
+        if (row < M && col < N) C[(uint64_t)row * N + col] = acc[i][j][v] * scale;
+      }
+    }
+}
+
 // GEMV: wave w handles rows w, w + W, ...; lane l reads 16-byte chunks
 // l, l + 64, ... of the row (8 BF16 each), four chunks in flight, and keeps
 // an FP32 running sum; the 64 partial sums are combined by a fixed butterfly.
@@ -309,6 +466,23 @@ hipError_t launch_gemm(int dtype, const void* a, const void* b, float* c, uint64
                        uint64_t k, float scale, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   // Large tiles once they fill the chip (>= one 256x256 tile per CU).
   const uint64_t nbig = ((m + kBig - 1) / kBig) * ((n + kBig - 1) / kBig);
+  if (nbig >= 256 && (k * (dtype == CI_DT_F32 ? 4 : dtype == CI_DT_BF16 ? 2 : 1)) % kDStage == 0) {
+    const uint32_t shm = kRingStages * kDSlot;
+    const uint8_t* A = (const uint8_t*)a;
+    const uint8_t* B = (const uint8_t*)b;
+    switch (dtype) {
+      case CI_DT_F32:
+        return xlaunch(gemm256d_kernel<CI_DT_F32>, dim3((uint32_t)nbig), dim3(512), shm, s, e0, e1, A, B, c,
+                       (uint32_t)m, (uint32_t)n, (uint32_t)k, scale);
+      case CI_DT_BF16:
+        return xlaunch(gemm256d_kernel<CI_DT_BF16>, dim3((uint32_t)nbig), dim3(512), shm, s, e0, e1, A, B, c,
+                       (uint32_t)m, (uint32_t)n, (uint32_t)k, scale);
+      case CI_DT_FP8E4M3:
+        return xlaunch(gemm256d_kernel<CI_DT_FP8E4M3>, dim3((uint32_t)nbig), dim3(512), shm, s, e0, e1, A, B,
+                       c, (uint32_t)m, (uint32_t)n, (uint32_t)k, scale);
+      default: return hipErrorInvalidValue;
+    }
+  }
   if (nbig >= 256) {
     const uint32_t shm = 4 * kBigTileLds;
     const uint8_t* A = (const uint8_t*)a;

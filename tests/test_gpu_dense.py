@@ -85,7 +85,9 @@ def _quantise_host(x, dtype):
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
 @pytest.mark.parametrize("m,n,k", [(128, 128, 128), (256, 384, 512), (200, 130, 64), (1, 1, 16),
                                    (512, 512, 1040), (1000, 777, 336),
-                                   (4100, 4000, 336)])   # large-tile path, ragged edges
+                                   (4100, 4000, 336),     # large tiles, ragged edges
+                                   (4100, 4000, 64),      # LDS ring: 4 / 2 / 1 stages (f32 / bf16 / fp8)
+                                   (4100, 4000, 192)])    # LDS ring: 12 / 6 / 3 stages
 def test_gemm_matches_oracle(ctx, dev, dtype, m, n, k):
     import torch
     a, b = _gemm_inputs(dtype, m, n, k, 1000 + m + n + k)
