@@ -310,7 +310,13 @@ def run_sweep(args):
     ctx = coloc.Context(0)
     ops = stressor_operands(dev)
     victims = sweep_victims(ctx, dev)
-    res = list(ops)
+    # rows: every stressor in its default shape, plus the pipe stressors
+    # with one wave per SIMD (a 256-thread work-group per CU), which leave
+    # issue slots to co-resident victims
+    rows = [(r, r, ops[r]) for r in ops]
+    for r in ("valu_f32", "mfma_bf16"):
+        rows.append((r + "_1wave", r, dict(ops[r], wg_per_cu=1, threads=256)))
+    res = [r for _, r, _ in rows]
     ws = torch.empty(256 + 256 * 8 * 48, dtype=torch.uint8, device=dev)
     out = {"metric": "victim slowdown per resource vs intensity", "config": {
         "workload": "sensitivity sweep: BF16 GEMM 4096^3 and BF16 GEMV 8192^2 (3 rotating weight "
@@ -319,11 +325,11 @@ def run_sweep(args):
     t0 = time.perf_counter()
     for placement in ("shared", "disjoint"):
         for vname, d in victims.items():
-            cells = ctx.measure_sensitivity(d, res, [ops[r] for r in res], INTENSITIES, reps=args.reps,
+            cells = ctx.measure_sensitivity(d, res, [o for _, _, o in rows], INTENSITIES, reps=args.reps,
                                             warmups=3, placement=placement, ws=ws,
                                             deadline_ms=args.deadline_ms)
             tab = {}
-            for i, r in enumerate(res):
+            for i, (r, _, _) in enumerate(rows):
                 row = cells[i * len(INTENSITIES):(i + 1) * len(INTENSITIES)]
                 nan = lambda v: v != v
                 tab[r] = {"slowdown": [None if nan(c["slowdown"]) else round(c["slowdown"], 3) for c in row],
@@ -336,7 +342,7 @@ def run_sweep(args):
                                     for c in row],
                           "t_alone_us": [None if nan(c["t_alone_ns"]) else round(c["t_alone_ns"] / 1e3, 2) for c in row]}
             out["tables"][f"{vname}/{placement}"] = tab
-            log(f"{vname} {placement}: " + ", ".join(f"{r}={tab[r]['slowdown'][-1]}" for r in res))
+            log(f"{vname} {placement}: " + ", ".join(f"{r}={tab[r]['slowdown'][-2]}" for r in tab))
     out["seconds"] = round(time.perf_counter() - t0, 1)
     ctx.close()
     print(json.dumps(out), flush=True)
