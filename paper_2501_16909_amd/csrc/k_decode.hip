@@ -467,19 +467,36 @@ __global__ void __launch_bounds__(1024) attn_partial_kernel(const float* __restr
     for (uint32_t j = lane; j < D; j += 64) dst[2 + j] = 0.0f;
     return;
   }
+  // the query first (D/4 <= 64 float4: one per lane), so its load overlaps
+  // the chunk's
+  const float4* qh = reinterpret_cast<const float4*>(q + ((size_t)b * nq + h) * D);
+  const float4 qv = lane < D / 4 ? qh[lane] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   const size_t base = (((size_t)b * nkv + kvh) * max_ctx + t0) * D;
   const uint4* k4 = reinterpret_cast<const uint4*>(kc + base);
   const uint4* v4 = reinterpret_cast<const uint4*>(vc + base);
-  for (uint32_t i = threadIdx.x; i < 64 * kRow4; i += blockDim.x) {
-    const uint32_t t = i / kRow4, c = i - t * kRow4;
-    const bool ok = (int32_t)(t0 + t) < T;
-    const uint4 kk = ok ? k4[i] : make_uint4(0, 0, 0, 0);
-    const uint4 vv = ok ? v4[i] : make_uint4(0, 0, 0, 0);
-    ks[t * kPitch4 + c] = kk;
-    vs[t * kPitch4 + c] = vv;
+  // rounds of four 16-byte loads per tensor per thread, all in flight
+  // before any is stored
+  constexpr uint32_t kTotal = 64 * kRow4;      // uint4 per tensor per chunk
+  for (uint32_t i0 = threadIdx.x; i0 < kTotal; i0 += 4 * blockDim.x) {
+    uint4 kk[4], vv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t i = i0 + u * blockDim.x;
+      const bool ok = i < kTotal && (int32_t)(t0 + i / kRow4) < T;
+      kk[u] = ok ? k4[i] : make_uint4(0, 0, 0, 0);
+      vv[u] = ok ? v4[i] : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t i = i0 + u * blockDim.x;
+      if (i < kTotal) {
+        const uint32_t t = i / kRow4, c = i - t * kRow4;
+        ks[t * kPitch4 + c] = kk[u];
+        vs[t * kPitch4 + c] = vv[u];
+      }
+    }
   }
-  const float4* qh = reinterpret_cast<const float4*>(q + ((size_t)b * nq + h) * D);
-  for (uint32_t j = lane; j < D / 4; j += 64) qs[w * (D / 4) + j] = qh[j];
+  if (lane < D / 4) qs[w * (D / 4) + lane] = qv;
   __syncthreads();
   float s = 0.0f;
   const uint4* kr = ks + lane * kPitch4;

@@ -400,3 +400,7 @@ def test_measure_decode_alone_and_colocated(ctx, dev):
     assert full["window_covered"] and full["ncu"] == 256
     assert full["step_col_p50"] > 1.05 * full["step_alone_p50"], full
     assert abs(z["step_col_p50"] / z["step_alone_p50"] - 1.0) < 0.1, z
+    # disjoint halves: the graph replays on the victim's CU-masked queue
+    half, = ctx.measure_decode(model, ["hbm"], hbm, [0.5], reps=5, warmups=2, placement="disjoint")
+    assert half["output_equal"] and half["window_covered"] and half["ncu"] == 128, half
+    assert half["step_alone_p50"] > 0 and half["step_col_p50"] > 0
