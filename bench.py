@@ -89,8 +89,8 @@ class Suite:
         self.ws = torch.empty(256 + 256 * 8 * 48, dtype=torch.uint8, device=dev)
         self.items = [
             ("hbm", dict(src0=self.hb, src1=self.hc, dst=self.ha, n=n, passes=1), "GB/s", 1e9),
-            ("l2", dict(src0=self.l2, n=1 << 19, passes=8), "TB/s", 1e12),
-            ("mall", dict(src0=self.mall, n=1 << 25, passes=20), "TB/s", 1e12),
+            ("l2", dict(src0=self.l2, n=1 << 19, passes=32), "TB/s", 1e12),
+            ("mall", dict(src0=self.mall, n=1 << 25, passes=60), "TB/s", 1e12),
             ("vl1d", dict(src0=self.l1, n=1 << 12, passes=4000), "TB/s", 1e12),
             ("lds", dict(src0=self.win, passes=10), "TB/s", 1e12),
             ("valu_f32", dict(dst=self.valu_out, iters=4096, passes=4, fa=1 - 2 ** -12, fb=2 ** -12), "TFLOP/s", 1e12),
@@ -344,6 +344,7 @@ def run_sweep(args):
             out["tables"][f"{vname}/{placement}"] = tab
             log(f"{vname} {placement}: " + ", ".join(f"{r}={tab[r]['slowdown'][-2]}" for r in tab))
     out["seconds"] = round(time.perf_counter() - t0, 1)
+    out["queue_pair_check"] = ctx.queue_stats()
     ctx.close()
     print(json.dumps(out), flush=True)
     if args.out:

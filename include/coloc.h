@@ -145,6 +145,21 @@ ci_status_t ci_cu_mask(ci_ctx_t* ctx, float intensity, int complement, uint32_t 
 ci_status_t ci_probe_placement(ci_ctx_t* ctx, const uint32_t* mask, uint32_t nwg,
                                uint32_t* out_loc);
 
+/* Queue-pair check counters.  Two hardware queues can slow each other's
+ * kernels although the kernels share no CU (the command-processor side of
+ * the paper's block-scheduler interference, Section 4.2), and on MI355X
+ * whether two queues do so depends on where the driver placed them.  Before
+ * the first colocated measurement of a (victim queue, stressor queue) pair in
+ * each call, measure_sensitivity and measure_decode run the victim alone and beside an
+ * idle kernel (one sleeping 64-thread work-group per CU of the stressor's
+ * mask) on the stressor's queue; if the idle kernel slows the victim by more
+ * than 5 %, a queue is replaced (the stressor's and the victim's in turn, at
+ * most 7 times).
+ *   *checks: pairs checked; *replaced: queues replaced; *unresolved: pairs
+ *   still above 5 % after the last replacement (measured as placed). */
+ci_status_t ci_queue_stats(ci_ctx_t* ctx, uint32_t* checks, uint32_t* replaced,
+                           uint32_t* unresolved);
+
 /* ----------------------------------------------------------- stressors */
 /* Per-work-group record written by every stressor work-group at exit
  * (device memory inside the caller's workspace). */
@@ -329,7 +344,8 @@ typedef struct ci_cell {
 /* For every resource rs[i] (operands in sopts[i]) and intensity xs[j]:
  * warm the victim up, then `reps` times run it alone and colocated with the
  * stressor (persistent mode), checking the window and output of each
- * colocated run; cells[i * nx + j] receives the result.  ws: workspace large
+ * colocated run; cells[i * nx + j] receives the result.  Even repetitions
+ * run alone first, odd ones colocated first (counterbalanced order).  ws: workspace large
  * enough for every listed stressor at full intensity.  Synchronous. */
 ci_status_t measure_sensitivity(ci_ctx_t* ctx, const ci_victim_desc_t* d,
                                 const ci_resource_t* rs, const ci_stressor_opts_t* sopts, int nr,

@@ -172,6 +172,8 @@ EXPORTS = {
     "ci_peak_for": ([C.c_void_p, C.c_int, C.POINTER(C.c_double)], C.c_int),
     "ci_cu_mask": ([C.c_void_p, C.c_float, C.c_int, C.POINTER(C.c_uint32), C.POINTER(C.c_int)], C.c_int),
     "ci_probe_placement": ([C.c_void_p, C.POINTER(C.c_uint32), C.c_uint32, C.c_void_p], C.c_int),
+    "ci_queue_stats": ([C.c_void_p, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)],
+                       C.c_int),
     "ci_workspace_size": ([C.c_int, C.POINTER(StressorOpts), C.c_int, C.POINTER(C.c_size_t)], C.c_int),
     "stressor_launch": ([C.c_void_p, C.c_int, C.c_float, C.c_void_p, C.POINTER(StressorOpts),
                          C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)], C.c_int),
@@ -402,6 +404,12 @@ class Context:
         mp = (C.c_uint32 * 8)(*mask) if mask is not None else None
         _check(load_library().ci_probe_placement(self.handle, mp, nwg, _ptr(out)))
         return out.cpu().numpy().view(np.uint32)
+
+    def queue_stats(self) -> dict:
+        """Queue-pair check counters (see ci_queue_stats in coloc.h)."""
+        v = [C.c_uint32() for _ in range(3)]
+        _check(load_library().ci_queue_stats(self.handle, *[C.byref(x) for x in v]))
+        return {"checks": v[0].value, "replaced": v[1].value, "unresolved": v[2].value}
 
     # ---------------------------------------------------------- stressors
     def _sync_torch(self):

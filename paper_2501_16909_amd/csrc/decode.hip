@@ -286,6 +286,22 @@ ci_status_t step_graph(ci_ctx* ctx, const ci_decode_desc_t* d, uint32_t used, hi
   return CI_OK;
 }
 
+ci_status_t run_decode(ci_ctx* ctx, const ci_decode_desc_t* d, hipStream_t caller, hipStream_t xs,
+                       ci_decode_result_t* out);
+
+struct DecodeRun {
+  ci_ctx* ctx;
+  const ci_decode_desc_t* d;
+  hipStream_t caller;
+  static ci_status_t call(void* p, hipStream_t vs, double* ns) {
+    DecodeRun* v = static_cast<DecodeRun*>(p);
+    ci_decode_result_t r;
+    const ci_status_t st = run_decode(v->ctx, v->d, v->caller, vs, &r);
+    *ns = r.step_ns;
+    return st;
+  }
+};
+
 // One step on exec stream `xs`; blocks until done.
 ci_status_t run_decode(ci_ctx* ctx, const ci_decode_desc_t* d, hipStream_t caller, hipStream_t xs,
                        ci_decode_result_t* out) {
@@ -402,6 +418,7 @@ extern "C" ci_status_t measure_decode(ci_ctx_t* ctx, const ci_decode_desc_t* d,
       return set_err(CI_ERR_INVALID_ARG, "measure_decode: intensity %g", xs[j]);
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t caller = (hipStream_t)stream;
+  ctx->queue_checked.clear();  // queue pairs are checked per victim
   for (int i = 0; i < nr; ++i) {
     for (int j = 0; j < nx; ++j) {
       ci_decode_cell_t& cell = cells[i * nx + j];
@@ -412,14 +429,15 @@ extern "C" ci_status_t measure_decode(ci_ctx_t* ctx, const ci_decode_desc_t* d,
       const int k = cus_for(ctx, xs[j]);
       cell.ncu = k;
       hipStream_t vs = ctx->vstream;
-      if (mo.placement == CI_PLACE_DISJOINT) {
+      uint32_t vmask[8];
+      const bool masked = mo.placement == CI_PLACE_DISJOINT && k > 0;  // k == 0: whole GPU, unmasked
+      if (masked) {
         if (k >= ctx->info.num_cus) {
           cell.step_alone_p50 = cell.step_col_p50 = NAN;
           continue;
         }
-        uint32_t mask[8];
-        mask_for(ctx, k, 1, mask);
-        vs = masked_stream(ctx, mask);
+        mask_for(ctx, k, 1, vmask);
+        vs = masked_stream(ctx, vmask);
         if (!vs) return set_err(CI_ERR_HIP, "hipExtStreamCreateWithCUMask failed");
       }
       ci_stressor_opts_t so{};
@@ -427,6 +445,10 @@ extern "C" ci_status_t measure_decode(ci_ctx_t* ctx, const ci_decode_desc_t* d,
       so.passes = 0;
       so.deadline_ms = mo.deadline_ms;
       ci_decode_result_t r;
+      DecodeRun dr{ctx, d, caller};
+      st = check_queue_pair(ctx, xs[j], caller, &vs, masked ? vmask : nullptr, ws, ws_bytes,
+                            &DecodeRun::call, &dr);
+      if (st != CI_OK) return st;
       for (uint32_t w = 0; w < mo.warmups; ++w) {
         st = run_decode(ctx, d, caller, vs, &r);
         if (st != CI_OK) return st;
@@ -436,9 +458,13 @@ extern "C" ci_status_t measure_decode(ci_ctx_t* ctx, const ci_decode_desc_t* d,
       double ach = 0.0, pct = 0.0;
       int covered = 1, equal = 1, timed = 0, nrep = 0;
       for (uint32_t rep = 0; rep < mo.reps; ++rep) {
+        // counterbalanced order, as in measure_sensitivity
+        const bool col_first = rep & 1u;
         ci_decode_result_t ra, rc;
-        st = run_decode(ctx, d, caller, vs, &ra);
-        if (st != CI_OK) return st;
+        if (!col_first) {
+          st = run_decode(ctx, d, caller, vs, &ra);
+          if (st != CI_OK) return st;
+        }
         ci_stressor_t* h = nullptr;
         st = stressor_launch(ctx, rs[i], xs[j], caller, &so, ws, ws_bytes, &h);
         if (st != CI_OK) return st;
@@ -451,6 +477,10 @@ extern "C" ci_status_t measure_decode(ci_ctx_t* ctx, const ci_decode_desc_t* d,
           timed = 1;
         } else if (st != CI_OK) {
           return st;
+        }
+        if (col_first) {
+          st = run_decode(ctx, d, caller, vs, &ra);
+          if (st != CI_OK) return st;
         }
         if (!noop && rs[i] != CI_RES_DISPATCH) {
           if (!(sr.t_last_start <= rc.t_begin && sr.t_first_end >= rc.t_end) || sr.wg_reported != sr.grid)

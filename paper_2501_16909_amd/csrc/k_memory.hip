@@ -254,14 +254,12 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
   uint64_t g = (n16 + 255) / 256;
   if (g > 4096) g = 4096;
   if (g == 0) g = 1;
-  hipLaunchKernelGGL(zero_kernel, dim3((uint32_t)g), dim3(256), 0, s, (uint4*)p, n16,
-                     (uint8_t*)p + n16 * 16, ntail);
-  return hipGetLastError();
+  return xlaunch(zero_kernel, dim3((uint32_t)g), dim3(256), 0, s, nullptr, nullptr, (uint4*)p, n16,
+                 (uint8_t*)p + n16 * 16, ntail);
 }
 
 hipError_t launch_stamp(uint64_t* slot, hipStream_t s) {
-  hipLaunchKernelGGL(stamp_kernel, dim3(1), dim3(64), 0, s, slot);
-  return hipGetLastError();
+  return xlaunch(stamp_kernel, dim3(1), dim3(64), 0, s, nullptr, nullptr, slot);
 }
 
 hipError_t launch_triad_stressor(const KCtrl& c, const float* b, const float* cc, float* a,

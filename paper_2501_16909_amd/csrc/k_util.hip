@@ -174,41 +174,35 @@ hipError_t launch_checksum_f32(const float* x, uint64_t n, uint64_t* part_bits, 
                                uint32_t nparts, uint64_t* out_bits, double* out_sum,
                                hipStream_t s) {
   const uint64_t len = n ? (n + nparts - 1) / nparts : 1;
-  hipLaunchKernelGGL(checksum_stage1, dim3(nparts), dim3(256), 0, s, x, n, len, part_bits, part_sum);
-  hipError_t e = hipGetLastError();
+  hipError_t e = xlaunch(checksum_stage1, dim3(nparts), dim3(256), 0, s, nullptr, nullptr, x, n, len,
+                         part_bits, part_sum);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(checksum_stage2, dim3(1), dim3(256), 0, s, part_bits, part_sum, nparts,
-                     out_bits, out_sum);
-  return hipGetLastError();
+  return xlaunch(checksum_stage2, dim3(1), dim3(256), 0, s, nullptr, nullptr, part_bits, part_sum, nparts,
+                 out_bits, out_sum);
 }
 
 hipError_t launch_amax_f32(const float* x, uint64_t n, float* part, uint32_t nparts, float* out,
                            hipStream_t s) {
   const uint64_t len = n ? (n + nparts - 1) / nparts : 1;
-  hipLaunchKernelGGL(amax_stage1, dim3(nparts), dim3(256), 0, s, x, n, len, part);
-  hipError_t e = hipGetLastError();
+  hipError_t e = xlaunch(amax_stage1, dim3(nparts), dim3(256), 0, s, nullptr, nullptr, x, n, len, part);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(amax_stage2, dim3(1), dim3(256), 0, s, part, nparts, out);
-  return hipGetLastError();
+  return xlaunch(amax_stage2, dim3(1), dim3(256), 0, s, nullptr, nullptr, part, nparts, out);
 }
 
 hipError_t launch_to_bf16(const float* x, uint64_t n, uint16_t* out, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(to_bf16_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, n, out);
-  return hipGetLastError();
+  return xlaunch(to_bf16_kernel, dim3(grid_for(n)), dim3(256), 0, s, nullptr, nullptr, x, n, out);
 }
 
 hipError_t launch_to_fp8(const float* x, uint64_t n, const float* amax, uint8_t* out,
                          hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(to_fp8_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, n, amax, out);
-  return hipGetLastError();
+  return xlaunch(to_fp8_kernel, dim3(grid_for(n)), dim3(256), 0, s, nullptr, nullptr, x, n, amax, out);
 }
 
 hipError_t launch_fill_uniform(float* dst, uint64_t n, uint64_t seed, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(fill_uniform_kernel, dim3(grid_for(n)), dim3(256), 0, s, dst, n, seed);
-  return hipGetLastError();
+  return xlaunch(fill_uniform_kernel, dim3(grid_for(n)), dim3(256), 0, s, nullptr, nullptr, dst, n, seed);
 }
 
 }  // namespace ci

@@ -23,6 +23,9 @@ struct ci_ctx {
   uint32_t nparts = 0;
   std::map<std::array<uint32_t, 8>, hipStream_t> masked;  // CU-masked streams by mask
   hipStream_t vstream = nullptr;       // non-blocking stream for shared-placement victims
+  // (victim stream, stressor stream) pairs that passed the queue-pair check
+  std::vector<std::pair<hipStream_t, hipStream_t>> queue_checked;
+  uint32_t queue_checks = 0, queue_replaced = 0, queue_unresolved = 0;
   hipEvent_t ev[12] = {};
   struct ci_stressor* active = nullptr;
   uint64_t rot = 0;                    // GEMV weight-copy rotation
@@ -60,7 +63,7 @@ struct ci_stressor {
   } while (0)
 
 namespace ci {
-constexpr size_t kMaxMaskedStreams = 6;
+constexpr size_t kMaxMaskedStreams = 8;
 constexpr uint32_t kDecodeMaxBatch = 8;
 constexpr size_t kDecodeMaxGraphs = 8;
 double median(std::vector<double> v);
@@ -69,6 +72,14 @@ int cus_for(const ci_ctx* ctx, double intensity);
 bool mask_covers_all_xcds(const ci_ctx* ctx, const uint32_t mask[8]);
 ci_status_t set_err(ci_status_t st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 hipStream_t masked_stream(ci_ctx* ctx, const uint32_t mask[8]);
+hipStream_t replace_masked_stream(ci_ctx* ctx, const uint32_t mask[8]);
+// Queue-pair check before a colocated measurement: see runtime.hip.
+// run(arg, s, &ns) runs the victim once alone on stream s and returns its
+// time.  *vs may be replaced: vmask is the victim stream's CU mask, or NULL
+// for the unmasked victim stream.
+ci_status_t check_queue_pair(ci_ctx* ctx, float intensity, hipStream_t caller, hipStream_t* vs,
+                             const uint32_t* vmask, void* ws, size_t ws_bytes,
+                             ci_status_t (*run)(void*, hipStream_t, double*), void* arg);
 void mask_for(const ci_ctx* ctx, int k, int complement, uint32_t mask[8]);
 ci_status_t launch_victim(ci_ctx* ctx, const ci_victim_desc_t* d, hipStream_t s, hipEvent_t e0,
                           hipEvent_t e1);

@@ -67,6 +67,24 @@ bool ci::mask_covers_all_xcds(const ci_ctx* ctx, const uint32_t mask[8]) {
   return true;
 }
 
+static void forget_stream(ci_ctx* ctx, hipStream_t s) {
+  auto& v = ctx->queue_checked;
+  v.erase(std::remove_if(v.begin(), v.end(),
+                         [s](const std::pair<hipStream_t, hipStream_t>& p) {
+                           return p.first == s || p.second == s;
+                         }),
+          v.end());
+}
+
+static hipStream_t new_masked_stream(const std::array<uint32_t, 8>& key) {
+  hipStream_t s = nullptr;
+  if (hipExtStreamCreateWithCUMask(&s, 8, key.data()) != hipSuccess) {
+    (void)hipGetLastError();  // do not leave the failure for the next call to find
+    return nullptr;
+  }
+  return s;
+}
+
 hipStream_t ci::masked_stream(ci_ctx* ctx, const uint32_t mask[8]) {
   std::array<uint32_t, 8> key{};
   for (int i = 0; i < 8; ++i) key[i] = mask[i];
@@ -79,14 +97,28 @@ hipStream_t ci::masked_stream(ci_ctx* ctx, const uint32_t mask[8]) {
       if (ctx->active && ctx->active->ms == jt->second) continue;
       (void)hipStreamSynchronize(jt->second);
       (void)hipStreamDestroy(jt->second);
+      forget_stream(ctx, jt->second);
       ctx->masked.erase(jt);
       break;
     }
   }
-  hipStream_t s = nullptr;
-  if (hipExtStreamCreateWithCUMask(&s, 8, key.data()) != hipSuccess) {
-    (void)hipGetLastError();  // do not leave the failure for the next call to find
-    return nullptr;
+  hipStream_t s = new_masked_stream(key);
+  if (s) ctx->masked[key] = s;
+  return s;
+}
+
+// A new hardware queue for `mask`: the replacement is created while the old
+// queue still exists, so that it cannot be handed the same queue slot.
+hipStream_t ci::replace_masked_stream(ci_ctx* ctx, const uint32_t mask[8]) {
+  std::array<uint32_t, 8> key{};
+  for (int i = 0; i < 8; ++i) key[i] = mask[i];
+  hipStream_t s = new_masked_stream(key);
+  if (!s) return nullptr;
+  auto it = ctx->masked.find(key);
+  if (it != ctx->masked.end()) {
+    (void)hipStreamSynchronize(it->second);
+    (void)hipStreamDestroy(it->second);
+    forget_stream(ctx, it->second);
   }
   ctx->masked[key] = s;
   return s;
@@ -194,6 +226,7 @@ extern "C" ci_status_t ci_shutdown(ci_ctx_t* ctx) {
   (void)hipSetDevice(ctx->device);
   for (auto& kv : ctx->masked) (void)hipStreamDestroy(kv.second);
   ctx->masked.clear();
+  ctx->queue_checked.clear();
   if (ctx->vstream) (void)hipStreamDestroy(ctx->vstream);
   for (auto& ev : ctx->ev)
     if (ev) (void)hipEventDestroy(ev);
@@ -408,20 +441,23 @@ extern "C" ci_status_t ci_workspace_size(ci_resource_t r, const ci_stressor_opts
 static void wait_started(ci_stressor* h, double timeout_s) {
   const double t_end = now_s() + timeout_s;
   while (!h->ctx->host->started) {
-    if (hipEventQuery(h->e1) == hipSuccess) return;  // already finished (or failed to start)
     if (now_s() > t_end) return;
     std::this_thread::yield();
   }
 }
 
+// A persistent kernel is launched with its start event only: the end event
+// is recorded when the stressor is stopped, so that while it runs nothing
+// waits in its queue behind it.
 static ci_status_t launch_kernel(ci_stressor* h, const KCtrl& c) {
   const ci_stressor_opts_t& o = h->o;
   hipStream_t s = h->ms;
   hipError_t e = hipSuccess;
+  hipEvent_t e0 = h->e0, e1 = h->persistent ? nullptr : h->e1;
   switch (h->r) {
     case CI_RES_HBM:
       e = launch_triad_stressor(c, (const float*)o.src0, (const float*)o.src1, (float*)o.dst, o.n,
-                                o.threads, o.vec == 0, s, h->e0, h->e1);
+                                o.threads, o.vec == 0, s, e0, e1);
       break;
     case CI_RES_L2:
     case CI_RES_VL1D:
@@ -433,33 +469,33 @@ static ci_status_t launch_kernel(ci_stressor* h, const KCtrl& c) {
         const uint64_t b = (65536 + span - 1) / span;
         batch = (uint32_t)std::max<uint64_t>(1, b);
       }
-      e = launch_cache_stressor(c, (const uint32_t*)o.src0, o.n, slice, batch, o.threads, s, h->e0,
-                                h->e1);
+      e = launch_cache_stressor(c, (const uint32_t*)o.src0, o.n, slice, batch, o.threads, s, e0,
+                                e1);
       break;
     }
     case CI_RES_LDS:
-      e = launch_lds_stressor(c, (const uint32_t*)o.src0, o.vec, o.knob, o.threads, s, h->e0, h->e1);
+      e = launch_lds_stressor(c, (const uint32_t*)o.src0, o.vec, o.knob, o.threads, s, e0, e1);
       break;
     case CI_RES_VALU_F32:
-      e = launch_valu_stressor(c, (float*)o.dst, o.knob, o.iters, o.fa, o.fb, o.threads, s, h->e0,
-                               h->e1);
+      e = launch_valu_stressor(c, (float*)o.dst, o.knob, o.iters, o.fa, o.fb, o.threads, s, e0,
+                               e1);
       break;
     case CI_RES_VALU_F64:
       e = launch_valu64_stressor(c, (double*)o.dst, o.knob, o.iters, (double)o.fa, o.threads, s,
-                                 h->e0, h->e1);
+                                 e0, e1);
       break;
     case CI_RES_MFMA_F32:
     case CI_RES_MFMA_BF16:
     case CI_RES_MFMA_FP8:
       e = launch_mfma_stressor(c, mfma_dtype(h->r), o.src0, o.src1, (float*)o.dst, o.knob, o.iters,
-                               o.threads, s, h->e0, h->e1);
+                               o.threads, s, e0, e1);
       break;
     case CI_RES_PTRCHASE:
       e = launch_chase_stressor(c, (const uint32_t*)o.src0, o.n, (uint32_t*)o.dst, o.knob, o.iters,
-                                o.threads, s, h->e0, h->e1);
+                                o.threads, s, e0, e1);
       break;
     case CI_RES_OCCUPANCY:
-      e = launch_hog(c, o.knob * 1024u, o.threads, s, h->e0, h->e1);
+      e = launch_hog(c, o.knob * 1024u, o.threads, s, e0, e1);
       break;
     default: return set_err(CI_ERR_INVALID_ARG, "launch_kernel: resource %d", (int)h->r);
   }
@@ -678,6 +714,15 @@ extern "C" ci_status_t stressor_stop(ci_stressor_t* h, ci_stressor_report_t* rep
   if (h->feeder.joinable()) {
     h->feeder_stop.store(1, std::memory_order_release);
     h->feeder.join();
+  } else if (h->persistent) {
+    // the end event of a persistent kernel is queued only now
+    hipError_t er = hipEventRecord(h->e1, h->ms);
+    if (er != hipSuccess) {
+      (void)hipStreamSynchronize(h->ms);
+      ctx->active = nullptr;
+      delete h;
+      return set_err(CI_ERR_HIP, "stressor_stop: end event: %s", hipGetErrorString(er));
+    }
   }
   // Drain: every wave exits on the flag or on its own deadline.
   const double limit = now_s() + h->o.deadline_ms * 1e-3 + 5.0;
@@ -747,6 +792,106 @@ extern "C" ci_status_t stressor_stop(ci_stressor_t* h, ci_stressor_report_t* rep
   ctx->active = nullptr;
   delete h;
   return st;
+}
+
+// ------------------------------------------------------- queue-pair check
+// Kernels on two hardware queues can slow each other although they share no
+// CU and no memory traffic: on MI355X a victim beside a sleeping kernel (one
+// 64-thread work-group per CU) on another queue ran either at its alone speed
+// or 1.3-1.5x slower, depending only on the order in which the process had
+// created its queues, and by how much depended on the victim.  Before the
+// first colocated measurement of a (victim queue, stressor queue) pair in a
+// measurement call (one victim), the victim therefore runs alone and beside
+// such an idle kernel on the stressor's queue, in counterbalanced order; if
+// the idle kernel alone slows it by more than kQueueTol, a queue is replaced
+// (the stressor's and the victim's in turn) and the check repeated,
+// kQueueAttempts times at most.
+namespace {
+constexpr double kQueueTol = 1.05;
+constexpr int kQueueAttempts = 8;
+constexpr int kQueuePairs = 6;
+
+// Replaces the shared-placement victim stream (a plain stream: the runtime
+// deals plain streams round-robin over its hardware queues).
+hipStream_t replace_vstream(ci_ctx* ctx) {
+  hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  (void)hipStreamSynchronize(ctx->vstream);
+  (void)hipStreamDestroy(ctx->vstream);
+  forget_stream(ctx, ctx->vstream);
+  ctx->vstream = s;
+  return s;
+}
+}  // namespace
+
+ci_status_t ci::check_queue_pair(ci_ctx* ctx, float intensity, hipStream_t caller, hipStream_t* vs,
+                                 const uint32_t* vmask, void* ws, size_t ws_bytes,
+                                 ci_status_t (*run)(void*, hipStream_t, double*), void* arg) {
+  const int k = cus_for(ctx, intensity);
+  if (k == 0) return CI_OK;
+  uint32_t mask[8];
+  mask_for(ctx, k, 0, mask);
+  hipStream_t ss = masked_stream(ctx, mask);
+  if (!ss) return set_err(CI_ERR_HIP, "hipExtStreamCreateWithCUMask failed");
+  for (const auto& p : ctx->queue_checked)
+    if (p.first == *vs && p.second == ss) return CI_OK;
+  ci_stressor_opts_t o{};
+  o.threads = 64;
+  o.wg_per_cu = 1;
+  o.knob = 1;  // 1 KiB of LDS
+  o.deadline_ms = 1000;
+  size_t need = 0;
+  if (ci_workspace_size(CI_RES_OCCUPANCY, &o, k, &need) != CI_OK || !ws || ws_bytes < need)
+    return CI_OK;  // no room for the idle kernel: the pair stays unchecked
+  ++ctx->queue_checks;
+  for (int attempt = 0;; ++attempt) {
+    ci_status_t st = CI_OK;
+    double t = 0.0;
+    for (int w = 0; w < 2 && st == CI_OK; ++w) st = run(arg, *vs, &t);
+    if (st != CI_OK) return st;
+    std::vector<double> ta, ti;
+    for (int rep = 0; rep < kQueuePairs; ++rep) {
+      const bool idle_first = rep & 1;
+      double t_alone = 0.0, t_idle = 0.0;
+      if (!idle_first && (st = run(arg, *vs, &t_alone)) != CI_OK) return st;
+      ci_stressor_t* h = nullptr;
+      st = stressor_launch(ctx, CI_RES_OCCUPANCY, intensity, caller, &o, ws, ws_bytes, &h);
+      if (st != CI_OK) return st;
+      const ci_status_t vst = run(arg, *vs, &t_idle);
+      st = stressor_stop(h, nullptr);
+      if (vst != CI_OK) return vst;
+      if (st != CI_OK) return st;
+      if (idle_first && (st = run(arg, *vs, &t_alone)) != CI_OK) return st;
+      ta.push_back(t_alone);
+      ti.push_back(t_idle);
+    }
+    if (median(ti) <= kQueueTol * median(ta)) break;
+    if (attempt + 1 >= kQueueAttempts) {  // measured as placed; not retried
+      ++ctx->queue_unresolved;
+      break;
+    }
+    ++ctx->queue_replaced;
+    if (attempt % 2 == 0) {
+      ss = replace_masked_stream(ctx, mask);
+      if (!ss) return set_err(CI_ERR_HIP, "hipExtStreamCreateWithCUMask failed");
+    } else {
+      hipStream_t nv = vmask ? replace_masked_stream(ctx, vmask) : replace_vstream(ctx);
+      if (!nv) return set_err(CI_ERR_HIP, "victim stream replacement failed");
+      *vs = nv;
+    }
+  }
+  ctx->queue_checked.push_back({*vs, ss});
+  return CI_OK;
+}
+
+extern "C" ci_status_t ci_queue_stats(ci_ctx_t* ctx, uint32_t* checks, uint32_t* replaced,
+                                      uint32_t* unresolved) {
+  if (!ctx || !checks || !replaced || !unresolved)
+    return set_err(CI_ERR_INVALID_ARG, "ci_queue_stats: NULL argument");
+  *checks = ctx->queue_checks;
+  *replaced = ctx->queue_replaced;
+  *unresolved = ctx->queue_unresolved;
+  return CI_OK;
 }
 
 // ------------------------------------------------------------------ victims
@@ -939,6 +1084,21 @@ double ci::quantile(std::vector<double> v, double q) {
 }
 
 
+namespace {
+struct VictimRun {
+  ci_ctx* ctx;
+  const ci_victim_desc_t* d;
+  hipStream_t caller;
+  static ci_status_t call(void* p, hipStream_t vs, double* ns) {
+    VictimRun* v = static_cast<VictimRun*>(p);
+    ci_victim_result_t r;
+    const ci_status_t st = run_victim(v->ctx, v->d, v->caller, vs, &r);
+    *ns = r.time_ns;
+    return st;
+  }
+};
+}  // namespace
+
 extern "C" ci_status_t measure_sensitivity(ci_ctx_t* ctx, const ci_victim_desc_t* d,
                                            const ci_resource_t* rs, const ci_stressor_opts_t* sopts,
                                            int nr, const float* xs, int nx,
@@ -959,6 +1119,7 @@ extern "C" ci_status_t measure_sensitivity(ci_ctx_t* ctx, const ci_victim_desc_t
       return set_err(CI_ERR_INVALID_ARG, "measure_sensitivity: intensity %g", xs[j]);
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t caller = (hipStream_t)stream;
+  ctx->queue_checked.clear();  // queue pairs are checked per victim
   for (int i = 0; i < nr; ++i) {
     for (int j = 0; j < nx; ++j) {
       ci_cell_t& cell = cells[i * nx + j];
@@ -968,14 +1129,15 @@ extern "C" ci_status_t measure_sensitivity(ci_ctx_t* ctx, const ci_victim_desc_t
       const int k = cus_for(ctx, xs[j]);
       cell.ncu = k;
       hipStream_t vs = ctx->vstream;
-      if (mo.placement == CI_PLACE_DISJOINT) {
+      uint32_t vmask[8];
+      const bool masked = mo.placement == CI_PLACE_DISJOINT && k > 0;  // k == 0: whole GPU, unmasked
+      if (masked) {
         if (k >= ctx->info.num_cus) {  // no CUs left for the victim
           cell.slowdown = cell.slowdown_p10 = cell.slowdown_p90 = NAN;
           continue;
         }
-        uint32_t mask[8];
-        mask_for(ctx, k, 1, mask);
-        vs = masked_stream(ctx, mask);
+        mask_for(ctx, k, 1, vmask);
+        vs = masked_stream(ctx, vmask);
         if (!vs) return set_err(CI_ERR_HIP, "hipExtStreamCreateWithCUMask failed");
       }
       ci_stressor_opts_t so{};
@@ -983,6 +1145,10 @@ extern "C" ci_status_t measure_sensitivity(ci_ctx_t* ctx, const ci_victim_desc_t
       so.passes = 0;
       so.deadline_ms = mo.deadline_ms;
       ci_victim_result_t r;
+      VictimRun vr{ctx, d, caller};
+      st = check_queue_pair(ctx, xs[j], caller, &vs, masked ? vmask : nullptr, ws, ws_bytes,
+                            &VictimRun::call, &vr);
+      if (st != CI_OK) return st;
       for (uint32_t w = 0; w < mo.warmups; ++w) {
         st = run_victim(ctx, d, caller, vs, &r);
         if (st != CI_OK) return st;
@@ -991,9 +1157,15 @@ extern "C" ci_status_t measure_sensitivity(ci_ctx_t* ctx, const ci_victim_desc_t
       double ach = 0.0, pct = 0.0;
       int covered = 1, equal = 1, timed = 0, nrep = 0;
       for (uint32_t rep = 0; rep < mo.reps; ++rep) {
+        // counterbalanced order (alone, colocated, colocated, alone, ...):
+        // drift and carry-over from the previous run (clock, caches the
+        // stressor left cold) fall on both sides equally
+        const bool col_first = rep & 1u;
         ci_victim_result_t ra, rc;
-        st = run_victim(ctx, d, caller, vs, &ra);
-        if (st != CI_OK) return st;
+        if (!col_first) {
+          st = run_victim(ctx, d, caller, vs, &ra);
+          if (st != CI_OK) return st;
+        }
         ci_stressor_t* h = nullptr;
         st = stressor_launch(ctx, rs[i], xs[j], caller, &so, ws, ws_bytes, &h);
         if (st != CI_OK) return st;
@@ -1006,6 +1178,10 @@ extern "C" ci_status_t measure_sensitivity(ci_ctx_t* ctx, const ci_victim_desc_t
           timed = 1;
         } else if (st != CI_OK) {
           return st;
+        }
+        if (col_first) {
+          st = run_victim(ctx, d, caller, vs, &ra);
+          if (st != CI_OK) return st;
         }
         if (!noop && rs[i] != CI_RES_DISPATCH) {
           if (!(sr.t_last_start <= rc.t_begin && sr.t_first_end >= rc.t_end) ||

@@ -68,24 +68,27 @@ extern "C" int synth_fill_uniform_f32(void* dst, uint64_t n, uint64_t seed, uint
                                       void* stream) {
   if (n == 0) return 0;
   if (!dst) return (int)hipErrorInvalidValue;
-  hipLaunchKernelGGL(fill_uniform_f32, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream,
-                     (float*)dst, n, seed, start);
-  return (int)hipGetLastError();
+  float* d = (float*)dst;
+  void* argv[] = {&d, &n, &seed, &start};
+  return (int)hipLaunchKernel((const void*)fill_uniform_f32, dim3(grid_for(n)), dim3(256), argv, 0,
+                              (hipStream_t)stream);
 }
 
 extern "C" int synth_fill_u32(void* dst, uint64_t n, uint64_t seed, uint64_t start, void* stream) {
   if (n == 0) return 0;
   if (!dst) return (int)hipErrorInvalidValue;
-  hipLaunchKernelGGL(fill_u32, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream,
-                     (uint32_t*)dst, n, seed, start);
-  return (int)hipGetLastError();
+  uint32_t* d = (uint32_t*)dst;
+  void* argv[] = {&d, &n, &seed, &start};
+  return (int)hipLaunchKernel((const void*)fill_u32, dim3(grid_for(n)), dim3(256), argv, 0,
+                              (hipStream_t)stream);
 }
 
 extern "C" int synth_fill_affine_f32(void* dst, uint64_t n, uint64_t seed, uint64_t start, float scale,
                                      float offset, void* stream) {
   if (n == 0) return 0;
   if (!dst) return (int)hipErrorInvalidValue;
-  hipLaunchKernelGGL(fill_affine_f32, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream,
-                     (float*)dst, n, seed, start, scale, offset);
-  return (int)hipGetLastError();
+  float* d = (float*)dst;
+  void* argv[] = {&d, &n, &seed, &start, &scale, &offset};
+  return (int)hipLaunchKernel((const void*)fill_affine_f32, dim3(grid_for(n)), dim3(256), argv, 0,
+                              (hipStream_t)stream);
 }
