@@ -885,7 +885,7 @@ def run_decode(args):
            "config": {"workload": f"synthetic decode step, Llama-3.1-8B shapes (32 layers, 4096 hidden, 32/8 "
                                   f"heads x 128, FFN 14336, vocab 128256), BF16 weights, batch {batch}, "
                                   f"cache positions {pos}", "model": "Llama-3.1-8B shapes, random weights"},
-           "alone": alone, "cells": rows}
+           "alone": alone, "cells": rows, "queue_pair_check": ctx.queue_stats()}
     ctx.close()
     _emit(out, args)
 
