@@ -146,7 +146,7 @@ def cpu_baseline():
     while True:
         oracle.triad_f32(b, c)
         reps += 1
-        if time.perf_counter() - t0 > 10.0 or reps >= 40:
+        if time.perf_counter() - t0 > 10.0:
             break
     dt = time.perf_counter() - t0
     return {"value": round(12.0 * n * reps / dt / 1e9, 3), "unit": "GB/s", "cores": 1,
