@@ -119,6 +119,73 @@ def test_serve_sensitivity_policy_serialises_fragile_mix(ctx):
         assert a["checksum_bits"] == b["checksum_bits"]
 
 
+def _replay_job(p):
+    # the library stores curves and pressures as FP32: the oracle sees the
+    # same rounded values
+    from paper_2501_16909_amd import coloc
+    f32 = lambda v: float(np.float32(v))
+    return {"sens": [[f32(v) for v in p["sens"].get(r, [1.0] * 5)] for r in coloc.RESOURCES],
+            "press": [f32(p["press"].get(r, 0.0)) for r in coloc.RESOURCES],
+            "bytes": 1, "occ": f32(p["occ"])}
+
+
+def test_serve_admissions_replay_against_oracle(ctx):
+    """Discrete-event replay of the loop's own log: given the completion
+    order the loop observed, every admission is one the oracle's admission
+    rule allows, and no request waited through a completion after which the
+    rule would already have allowed it (FIFO, no bypass)."""
+    profiles = {"gemv": {"sens": {"hbm": [1.0, 1.5, 2.0, 2.5, 3.0]}, "press": {"hbm": 0.2}, "occ": 0.6},
+                "triad": {"sens": {"hbm": [1.0, 1.1, 1.2, 1.3, 1.4]}, "press": {"hbm": 1.0}, "occ": 0.6},
+                "gemm": {"sens": {"lds": [1.0] * 5}, "press": {"mfma_bf16": 0.9}, "occ": 0.3}}
+    # requests of 0.1-0.5 ms each, so that completions are spaced out
+    sizes = [("gemv", dict(n=16384, k=16384, dtype="bf16")), ("triad", dict(n=1 << 27)),
+             ("gemm", dict(m=4096, n=4096, k=4096, dtype="bf16")), ("gemv", dict(n=8192, k=16384, dtype="bf16")),
+             ("triad", dict(n=3 << 25)), ("gemm", dict(m=2048, n=4096, k=4096, dtype="bf16"))]
+    reqs = []
+    for i, (kind, kw) in enumerate(sizes * 3):
+        reqs.append(dict(kw, arrival_s=0.0, kind=kind, seed=7000 + 10 * i))
+    slots, bound = 3, 1.5
+    out = ctx.serve(reqs, policy="sensitivity", bound=bound, hbm_budget=16 << 30, slots=slots,
+                    profiles=profiles)
+    assert all(o["status"] == 0 for o in out)
+    jobs = [_replay_job(profiles[q["kind"]]) for q in reqs]
+
+    def running(t, i):
+        return frozenset(j for j, o in enumerate(out) if j != i and o["admit_s"] <= t < o["end_s"])
+
+    order = [i for i, _ in sorted(enumerate(out), key=lambda kv: kv[1]["admit_s"])]
+    assert order == sorted(order)                       # FIFO, no bypass
+    events = sorted([o["end_s"] for o in out] + [o["admit_s"] for o in out])
+    delta = 2e-4   # far longer than one pass of the loop (retire, then admit)
+    checked = 0
+    for i, o in enumerate(out):
+        now = running(o["admit_s"], i)
+        assert oracle.admit("sensitivity", [jobs[j] for j in now], jobs[i], 1 << 40, bound, slots), (i, now)
+        lo = max(o["arrival_s"], out[i - 1]["admit_s"] if i else 0.0)
+        for k, ok in enumerate(out):      # completions while i waited at the front of the queue
+            tau = ok["end_s"]
+            if not (lo < tau < o["admit_s"]):
+                continue
+            # only instants after which nothing happened for delta: the loop
+            # evaluated exactly this state and left i waiting
+            if any(tau < e < tau + delta for e in events):
+                continue
+            state = running(tau, i)
+            assert not oracle.admit("sensitivity", [jobs[j] for j in state], jobs[i], 1 << 40, bound,
+                                    slots), (i, k, state)
+            checked += 1
+    print(f"admissions replayed: {len(out)}, waiting states checked: {checked}")
+    # the rule's consequence here: a fragile GEMV never runs beside a triad
+    spans = {i: (o["admit_s"], o["end_s"]) for i, o in enumerate(out)}
+    for i, qi in enumerate(reqs):
+        for j, qj in enumerate(reqs):
+            if qi["kind"] == "gemv" and qj["kind"] == "triad":
+                a, b = spans[i], spans[j]
+                assert a[1] <= b[0] + 1e-9 or b[1] <= a[0] + 1e-9, (i, j)
+    starts = sorted(spans.values())
+    assert any(starts[i + 1][0] < starts[i][1] for i in range(len(starts) - 1))
+
+
 def test_serve_rejects_bad_traces(ctx):
     from paper_2501_16909_amd import coloc
     with pytest.raises(coloc.CiError):
