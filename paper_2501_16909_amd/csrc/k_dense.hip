@@ -18,6 +18,8 @@
 // Rows and K chunks past the matrix edges read as zero (register-staged
 // kernels) or only feed outputs that are not stored (ring kernel), so any M
 // and N work; K * element size must be a multiple of 16.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace ci {
@@ -275,18 +277,18 @@ __global__ void __launch_bounds__(64 * WAVES, 1) gemm256_kernel(const uint8_t* _
 
 // Large-tile GEMM with direct global -> LDS loads (16 bytes per lane,
 // lane l of a wave instruction filling bytes 16 l of a 1 KiB block) into a
-// 4-deep ring of K-stages of 64 bytes per row: stages st + 1 .. st + 3 are in
-// flight while stage st computes, without staging registers.  Rows are
+// 4-deep ring of K-stages of 64 bytes per row: two or three later stages
+// are in flight while a stage computes, without staging registers.  Rows are
 // stored unpadded; the 16-byte chunk c of row r sits at chunk
 // c ^ ((r >> 2) & 3), so the 32 rows a fragment read touches fall on
 // distinct banks.  Eight waves (2 x 4, each 128 x 64; two per SIMD) read
-// their stage's fragments into registers, then issue its MFMAs.  One bare
-// barrier per stage: each wave first waits for its own loads of the stage
-// (s_waitcnt on the vector-memory counter), so after the barrier the whole
-// stage is in LDS and the slot of stage st - 1 may be refilled; a fence
-// there would also wait for the later stages' loads.  Needs K * element
-// size to be a multiple of 64 bytes; the register-staged kernel above takes
-// the rest.
+// fragments into registers and issue the MFMAs; with two MFMA k-steps per
+// stage or more (FP32, BF16) the reads of the next k-step overlap the
+// current one's MFMAs.  One bare barrier per stage: each wave first waits
+// for its own loads of the stage (s_waitcnt on the vector-memory counter),
+// so after the barrier the whole stage is in LDS; a fence there would also
+// wait for the later stages' loads.  Needs K * element size to be a
+// multiple of 64 bytes; the register-staged kernel above takes the rest.
 constexpr int kRingStages = 4;
 constexpr int kDStage = 64;                         // K bytes per stage per row
 constexpr int kDOperand = kBig * kDStage;           // one operand, one stage (16 KiB)
@@ -369,37 +371,96 @@ __global__ void __launch_bounds__(512, 1) gemm256d_kernel(const uint8_t* __restr
     for (int j = 0; j < JN; ++j)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
-  for (uint32_t st = 0; st < kRingStages - 1 && st < nstages; ++st) issue(st);
   const uint32_t frow = lane & 31u, fk = (lane >> 5) * G::kFragBytes;
-  for (uint32_t st = 0; st < nstages; ++st) {
-    // this wave's loads of stage st are done when at most the loads of the
-    // stages issued after it (up to 2 stages x 4 instructions) are pending
-    const uint32_t after = min(nstages - 1 - st, (uint32_t)kRingStages - 2);
+  constexpr int NS = kDStage / (2 * G::kFragBytes);   // MFMA k-steps per stage
+  using F = Frag<DT>;
+  // Wait until this wave's loads of stage t are done (at most `ahead`
+  // later stages of 4 instructions each may be pending), then a bare
+  // barrier: every wave's part of stage t is in LDS.  A fence would also
+  // wait for the later stages' loads.
+  auto wait_stage = [&](uint32_t t, uint32_t ahead) {
+    const uint32_t after = min(nstages - 1, t + ahead) - t;
     if (after >= 2) __builtin_amdgcn_s_waitcnt(0x0F78);        // vmcnt(8)
     else if (after == 1) __builtin_amdgcn_s_waitcnt(0x0F74);   // vmcnt(4)
     else __builtin_amdgcn_s_waitcnt(0x0F70);                   // vmcnt(0)
-    // every wave's part of stage st is in LDS and stage st - 1 is consumed;
-    // a bare barrier: a fence here would wait for the later stages' loads too
     __builtin_amdgcn_s_barrier();
-    if (st + kRingStages - 1 < nstages) issue(st + kRingStages - 1);
-    const uint8_t* slot = smem + (st % kRingStages) * kDSlot;
-    constexpr int NS = kDStage / (2 * G::kFragBytes);
-    using F = Frag<DT>;
-    typename F::T fa[NS][4], fb[NS][JN];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
+  };
+  if constexpr (NS % 2 == 0) {
+    // Two fragment buffers of one k-step each: k-step g + 1 is read from LDS
+    // while the MFMAs of k-step g run, across stage boundaries too.  The
+    // reads of a stage's last k-step are waited for after the next stage's
+    // barrier, so that barrier frees the slot of the stage before: stage
+    // t + P is issued at the barrier of stage t into the slot of t - 2.
+    constexpr uint32_t P = kRingStages - 2;
+    for (uint32_t st = 0; st < P && st < nstages; ++st) issue(st);
+    typename F::T fa[2][4], fb[2][JN];
+    auto read_ks = [&](uint32_t t, int s, auto buf) {
+      constexpr int b = decltype(buf)::value;
+      const uint8_t* slot = smem + (t % kRingStages) * kDSlot;
       const uint32_t kb = fk + s * 2 * G::kFragBytes;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) fa[s][i] = F::ld(slot, wm * 128 + i * 32 + frow, kb);
+      for (int i = 0; i < 4; ++i) fa[b][i] = F::ld(slot, wm * 128 + i * 32 + frow, kb);
 #pragma unroll
-      for (int j = 0; j < JN; ++j) fb[s][j] = F::ld(slot + kDOperand, wn * 64 + j * 32 + frow, kb);
-    }
-#pragma unroll
-    for (int s = 0; s < NS; ++s)
+      for (int j = 0; j < JN; ++j) fb[b][j] = F::ld(slot + kDOperand, wn * 64 + j * 32 + frow, kb);
+    };
+    auto mma_ks = [&](auto buf) {
+      constexpr int b = decltype(buf)::value;
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < JN; ++j) acc[i][j] = F::mma(fa[s][i], fb[s][j], acc[i][j]);
+        for (int j = 0; j < JN; ++j) acc[i][j] = F::mma(fa[b][i], fb[b][j], acc[i][j]);
+    };
+    using B0 = std::integral_constant<int, 0>;
+    using B1 = std::integral_constant<int, 1>;
+    // stage t, its first k-step already in buffer 0; with `more`, the last
+    // k-step's MFMAs overlap the next stage's barrier and first reads
+    auto stage_body = [&](uint32_t t, bool more) {
+#pragma unroll
+      for (int s = 0; s < NS; s += 2) {
+        read_ks(t, s + 1, B1{});
+        mma_ks(B0{});
+        if (s + 2 < NS) {
+          read_ks(t, s + 2, B0{});
+        } else if (more) {
+          wait_stage(t + 1, P - 1);
+          if (t + 1 + P < nstages) issue(t + 1 + P);
+          read_ks(t + 1, 0, B0{});
+        }
+        mma_ks(B1{});
+      }
+    };
+    wait_stage(0, P - 1);
+    if (P < nstages) issue(P);
+    read_ks(0, 0, B0{});
+    // no branch around the reads in the steady state, so that each MFMA
+    // block waits only for its own buffer's reads
+    uint32_t st = 0;
+    for (; st + 1 < nstages; ++st) stage_body(st, true);
+    stage_body(st, false);
+  } else {
+    // One k-step per stage (FP8): a single buffer, read then multiplied;
+    // the barrier of stage st frees the slot of st - 1.
+    for (uint32_t st = 0; st < kRingStages - 1 && st < nstages; ++st) issue(st);
+    for (uint32_t st = 0; st < nstages; ++st) {
+      wait_stage(st, kRingStages - 2);
+      if (st + kRingStages - 1 < nstages) issue(st + kRingStages - 1);
+      const uint8_t* slot = smem + (st % kRingStages) * kDSlot;
+      typename F::T fa[NS][4], fb[NS][JN];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const uint32_t kb = fk + s * 2 * G::kFragBytes;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) fa[s][i] = F::ld(slot, wm * 128 + i * 32 + frow, kb);
+#pragma unroll
+        for (int j = 0; j < JN; ++j) fb[s][j] = F::ld(slot + kDOperand, wn * 64 + j * 32 + frow, kb);
+      }
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < JN; ++j) acc[i][j] = F::mma(fa[s][i], fb[s][j], acc[i][j]);
+    }
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
