@@ -151,11 +151,15 @@ ci_status_t ci_probe_placement(ci_ctx_t* ctx, const uint32_t* mask, uint32_t nwg
  * whether two queues do so depends on where the driver placed them.  Before
  * the first colocated measurement of a (victim queue, stressor queue) pair in
  * each call, measure_sensitivity and measure_decode run the victim alone and beside an
- * idle kernel (one sleeping 64-thread work-group per CU of the stressor's
- * mask) on the stressor's queue; if the idle kernel slows the victim by more
+ * idle kernel on the stressor's queue (sleeping work-groups on the
+ * stressor's CUs: one of 64 threads per CU on shared CUs, the stressor's own
+ * launch shape on disjoint CUs); if the idle kernel slows the victim by more
  * than 5 %, a queue is replaced (the stressor's and the victim's in turn, at
- * most 7 times).
- *   *checks: pairs checked; *replaced: queues replaced; *unresolved: pairs
+ * most 7 times).  A victim queue is first qualified: measured alone against
+ * two fresh queues with the same mask, the fastest kept (a queue can also be
+ * slow on its own).
+ *   *checks: pairs checked; *replaced: queues replaced (by either step);
+ *   *unresolved: pairs
  *   still above 5 % after the last replacement (measured as placed). */
 ci_status_t ci_queue_stats(ci_ctx_t* ctx, uint32_t* checks, uint32_t* replaced,
                            uint32_t* unresolved);

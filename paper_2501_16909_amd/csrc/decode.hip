@@ -419,6 +419,7 @@ extern "C" ci_status_t measure_decode(ci_ctx_t* ctx, const ci_decode_desc_t* d,
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t caller = (hipStream_t)stream;
   ctx->queue_checked.clear();  // queue pairs are checked per victim
+  ctx->queue_qualified.clear();
   for (int i = 0; i < nr; ++i) {
     for (int j = 0; j < nx; ++j) {
       ci_decode_cell_t& cell = cells[i * nx + j];
@@ -446,8 +447,8 @@ extern "C" ci_status_t measure_decode(ci_ctx_t* ctx, const ci_decode_desc_t* d,
       so.deadline_ms = mo.deadline_ms;
       ci_decode_result_t r;
       DecodeRun dr{ctx, d, caller};
-      st = check_queue_pair(ctx, xs[j], caller, &vs, masked ? vmask : nullptr, ws, ws_bytes,
-                            &DecodeRun::call, &dr);
+      st = check_queue_pair(ctx, rs[i], sopts ? &sopts[i] : nullptr, xs[j], caller, &vs,
+                            masked ? vmask : nullptr, ws, ws_bytes, &DecodeRun::call, &dr);
       if (st != CI_OK) return st;
       for (uint32_t w = 0; w < mo.warmups; ++w) {
         st = run_decode(ctx, d, caller, vs, &r);

@@ -23,8 +23,13 @@ struct ci_ctx {
   uint32_t nparts = 0;
   std::map<std::array<uint32_t, 8>, hipStream_t> masked;  // CU-masked streams by mask
   hipStream_t vstream = nullptr;       // non-blocking stream for shared-placement victims
-  // (victim stream, stressor stream) pairs that passed the queue-pair check
-  std::vector<std::pair<hipStream_t, hipStream_t>> queue_checked;
+  // queue pairs that passed the queue-pair check, with the idle kernel's shape
+  struct QueuePair {
+    hipStream_t victim, stressor;
+    uint32_t threads, wg_per_cu;
+  };
+  std::vector<QueuePair> queue_checked;
+  std::vector<hipStream_t> queue_qualified;   // victim streams kept after qualification
   uint32_t queue_checks = 0, queue_replaced = 0, queue_unresolved = 0;
   hipEvent_t ev[12] = {};
   struct ci_stressor* active = nullptr;
@@ -76,8 +81,10 @@ hipStream_t replace_masked_stream(ci_ctx* ctx, const uint32_t mask[8]);
 // Queue-pair check before a colocated measurement: see runtime.hip.
 // run(arg, s, &ns) runs the victim once alone on stream s and returns its
 // time.  *vs may be replaced: vmask is the victim stream's CU mask, or NULL
-// for the unmasked victim stream.
-ci_status_t check_queue_pair(ci_ctx* ctx, float intensity, hipStream_t caller, hipStream_t* vs,
+// for the unmasked victim stream.  With a victim mask (disjoint CUs) the
+// idle kernel takes the launch shape of stressor r with options so.
+ci_status_t check_queue_pair(ci_ctx* ctx, ci_resource_t r, const ci_stressor_opts_t* so,
+                             float intensity, hipStream_t caller, hipStream_t* vs,
                              const uint32_t* vmask, void* ws, size_t ws_bytes,
                              ci_status_t (*run)(void*, hipStream_t, double*), void* arg);
 void mask_for(const ci_ctx* ctx, int k, int complement, uint32_t mask[8]);

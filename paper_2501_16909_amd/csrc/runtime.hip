@@ -70,9 +70,7 @@ bool ci::mask_covers_all_xcds(const ci_ctx* ctx, const uint32_t mask[8]) {
 static void forget_stream(ci_ctx* ctx, hipStream_t s) {
   auto& v = ctx->queue_checked;
   v.erase(std::remove_if(v.begin(), v.end(),
-                         [s](const std::pair<hipStream_t, hipStream_t>& p) {
-                           return p.first == s || p.second == s;
-                         }),
+                         [s](const ci_ctx::QueuePair& p) { return p.victim == s || p.stressor == s; }),
           v.end());
 }
 
@@ -227,6 +225,7 @@ extern "C" ci_status_t ci_shutdown(ci_ctx_t* ctx) {
   for (auto& kv : ctx->masked) (void)hipStreamDestroy(kv.second);
   ctx->masked.clear();
   ctx->queue_checked.clear();
+  ctx->queue_qualified.clear();
   if (ctx->vstream) (void)hipStreamDestroy(ctx->vstream);
   for (auto& ev : ctx->ev)
     if (ev) (void)hipEventDestroy(ev);
@@ -799,13 +798,16 @@ extern "C" ci_status_t stressor_stop(ci_stressor_t* h, ci_stressor_report_t* rep
 // CU and no memory traffic: on MI355X a victim beside a sleeping kernel (one
 // 64-thread work-group per CU) on another queue ran either at its alone speed
 // or 1.3-1.5x slower, depending only on the order in which the process had
-// created its queues, and by how much depended on the victim.  Before the
-// first colocated measurement of a (victim queue, stressor queue) pair in a
+// created its queues, and by how much depended on the victim and, on
+// disjoint CUs, on the other kernel's launch shape.  Before the first
+// colocated measurement of a (victim queue, stressor queue) pair in a
 // measurement call (one victim), the victim therefore runs alone and beside
-// such an idle kernel on the stressor's queue, in counterbalanced order; if
-// the idle kernel alone slows it by more than kQueueTol, a queue is replaced
+// an idle kernel on the stressor's queue, in counterbalanced order; if the
+// idle kernel alone slows it by more than kQueueTol, a queue is replaced
 // (the stressor's and the victim's in turn) and the check repeated,
-// kQueueAttempts times at most.
+// kQueueAttempts times at most.  On shared CUs the idle kernel is one
+// 64-thread work-group per CU (wave slots the victim needs stay free); on
+// disjoint CUs it takes the stressor's shape (threads, work-groups per CU).
 namespace {
 constexpr double kQueueTol = 1.05;
 constexpr int kQueueAttempts = 8;
@@ -822,9 +824,77 @@ hipStream_t replace_vstream(ci_ctx* ctx) {
   ctx->vstream = s;
   return s;
 }
+
+ci_status_t median_alone(hipStream_t s, ci_status_t (*run)(void*, hipStream_t, double*), void* arg,
+                         double* out) {
+  std::vector<double> t;
+  for (int i = 0; i < 2 + kQueuePairs; ++i) {
+    double ns = 0.0;
+    const ci_status_t st = run(arg, s, &ns);
+    if (st != CI_OK) return st;
+    if (i >= 2) t.push_back(ns);
+  }
+  *out = median(t);
+  return CI_OK;
+}
+
+// A victim queue can also be slow on its own: the same kernel alone on two
+// queues with the same CU mask has run 1.5x apart.  Before its first pair
+// check in a measurement call, the victim's queue is measured against
+// kQualifyCandidates freshly created queues with the same mask (created
+// while the others exist, so they land elsewhere), and the fastest is kept.
+constexpr int kQualifyCandidates = 2;
+constexpr double kQualifyGain = 0.97;
+
+ci_status_t qualify_victim_queue(ci_ctx* ctx, hipStream_t* vs, const uint32_t* vmask,
+                                 ci_status_t (*run)(void*, hipStream_t, double*), void* arg) {
+  for (hipStream_t q : ctx->queue_qualified)
+    if (q == *vs) return CI_OK;
+  std::array<uint32_t, 8> key{};
+  if (vmask)
+    for (int i = 0; i < 8; ++i) key[i] = vmask[i];
+  hipStream_t best = *vs;
+  double t_best = 0.0;
+  ci_status_t st = median_alone(best, run, arg, &t_best);
+  if (st != CI_OK) return st;
+  for (int c = 0; c < kQualifyCandidates; ++c) {
+    hipStream_t cand = nullptr;
+    if (vmask) {
+      cand = new_masked_stream(key);
+    } else if (hipStreamCreateWithFlags(&cand, hipStreamNonBlocking) != hipSuccess) {
+      cand = nullptr;
+    }
+    if (!cand) return set_err(CI_ERR_HIP, "victim queue qualification: stream creation failed");
+    double t = 0.0;
+    st = median_alone(cand, run, arg, &t);
+    hipStream_t loser = cand;
+    if (st == CI_OK && t < kQualifyGain * t_best) {
+      loser = best;
+      best = cand;
+      t_best = t;
+    }
+    (void)hipStreamSynchronize(loser);
+    if (loser != *vs) {
+      (void)hipStreamDestroy(loser);
+    }
+    if (st != CI_OK) return st;
+  }
+  if (best != *vs) {  // install the winner where the old victim queue was kept
+    ++ctx->queue_replaced;
+    (void)hipStreamSynchronize(*vs);
+    (void)hipStreamDestroy(*vs);
+    forget_stream(ctx, *vs);
+    if (vmask) ctx->masked[key] = best;
+    else ctx->vstream = best;
+    *vs = best;
+  }
+  ctx->queue_qualified.push_back(best);
+  return CI_OK;
+}
 }  // namespace
 
-ci_status_t ci::check_queue_pair(ci_ctx* ctx, float intensity, hipStream_t caller, hipStream_t* vs,
+ci_status_t ci::check_queue_pair(ci_ctx* ctx, ci_resource_t r, const ci_stressor_opts_t* so,
+                                 float intensity, hipStream_t caller, hipStream_t* vs,
                                  const uint32_t* vmask, void* ws, size_t ws_bytes,
                                  ci_status_t (*run)(void*, hipStream_t, double*), void* arg) {
   const int k = cus_for(ctx, intensity);
@@ -833,13 +903,23 @@ ci_status_t ci::check_queue_pair(ci_ctx* ctx, float intensity, hipStream_t calle
   mask_for(ctx, k, 0, mask);
   hipStream_t ss = masked_stream(ctx, mask);
   if (!ss) return set_err(CI_ERR_HIP, "hipExtStreamCreateWithCUMask failed");
-  for (const auto& p : ctx->queue_checked)
-    if (p.first == *vs && p.second == ss) return CI_OK;
   ci_stressor_opts_t o{};
   o.threads = 64;
   o.wg_per_cu = 1;
+  if (vmask) {  // disjoint CUs: the stressor's own launch shape
+    ci_stressor_opts_t ro;
+    resolve(r, so, &ro);
+    o.threads = ro.threads ? ro.threads : 64;
+    o.wg_per_cu = ro.wg_per_cu ? ro.wg_per_cu : 1;
+    if ((uint64_t)o.wg_per_cu * o.threads > 2048) o.wg_per_cu = 2048 / o.threads;
+  }
   o.knob = 1;  // 1 KiB of LDS
   o.deadline_ms = 1000;
+  ci_status_t qs = qualify_victim_queue(ctx, vs, vmask, run, arg);
+  if (qs != CI_OK) return qs;
+  for (const auto& p : ctx->queue_checked)
+    if (p.victim == *vs && p.stressor == ss && p.threads == o.threads && p.wg_per_cu == o.wg_per_cu)
+      return CI_OK;
   size_t need = 0;
   if (ci_workspace_size(CI_RES_OCCUPANCY, &o, k, &need) != CI_OK || !ws || ws_bytes < need)
     return CI_OK;  // no room for the idle kernel: the pair stays unchecked
@@ -878,9 +958,11 @@ ci_status_t ci::check_queue_pair(ci_ctx* ctx, float intensity, hipStream_t calle
       hipStream_t nv = vmask ? replace_masked_stream(ctx, vmask) : replace_vstream(ctx);
       if (!nv) return set_err(CI_ERR_HIP, "victim stream replacement failed");
       *vs = nv;
+      qs = qualify_victim_queue(ctx, vs, vmask, run, arg);
+      if (qs != CI_OK) return qs;
     }
   }
-  ctx->queue_checked.push_back({*vs, ss});
+  ctx->queue_checked.push_back({*vs, ss, o.threads, o.wg_per_cu});
   return CI_OK;
 }
 
@@ -1120,6 +1202,7 @@ extern "C" ci_status_t measure_sensitivity(ci_ctx_t* ctx, const ci_victim_desc_t
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t caller = (hipStream_t)stream;
   ctx->queue_checked.clear();  // queue pairs are checked per victim
+  ctx->queue_qualified.clear();
   for (int i = 0; i < nr; ++i) {
     for (int j = 0; j < nx; ++j) {
       ci_cell_t& cell = cells[i * nx + j];
@@ -1146,8 +1229,8 @@ extern "C" ci_status_t measure_sensitivity(ci_ctx_t* ctx, const ci_victim_desc_t
       so.deadline_ms = mo.deadline_ms;
       ci_victim_result_t r;
       VictimRun vr{ctx, d, caller};
-      st = check_queue_pair(ctx, xs[j], caller, &vs, masked ? vmask : nullptr, ws, ws_bytes,
-                            &VictimRun::call, &vr);
+      st = check_queue_pair(ctx, rs[i], sopts ? &sopts[i] : nullptr, xs[j], caller, &vs,
+                            masked ? vmask : nullptr, ws, ws_bytes, &VictimRun::call, &vr);
       if (st != CI_OK) return st;
       for (uint32_t w = 0; w < mo.warmups; ++w) {
         st = run_victim(ctx, d, caller, vs, &r);
