@@ -152,7 +152,7 @@ ci_status_t ci_probe_placement(ci_ctx_t* ctx, const uint32_t* mask, uint32_t nwg
  * the first colocated measurement of a (victim queue, stressor queue) pair in
  * each call, measure_sensitivity and measure_decode run the victim alone and beside an
  * idle kernel on the stressor's queue (sleeping work-groups on the
- * stressor's CUs: one of 64 threads per CU on shared CUs, the stressor's own
+ * stressor's CUs: one of 256 threads per CU on shared CUs, the stressor's own
  * launch shape on disjoint CUs); if the idle kernel slows the victim by more
  * than 5 %, a queue is replaced (the stressor's and the victim's in turn, at
  * most 7 times).  A victim queue is first qualified: measured alone against
@@ -306,6 +306,14 @@ ci_status_t victim_run(ci_ctx_t* ctx, const ci_victim_desc_t* d, void* stream,
  * paper's estimator is validated on workload pairs (Section 5.1).  The
  * caller synchronises `stream` before reusing the buffers. */
 ci_status_t victim_enqueue(ci_ctx_t* ctx, const ci_victim_desc_t* d, void* stream, uint32_t count);
+
+/* Enqueue on `stream` (non-NULL) a one-wave kernel that writes the device
+ * wall clock (ticks at ci_device_info_t.wall_clock_khz, the clock of the
+ * victim and stressor stamps) to *slot, a device address.  Bracketing
+ * enqueued work with two stamps shows whether it covered a timed victim's
+ * window [t_begin, t_end] (Section 4.1: interference constant over the
+ * victim's lifetime).  Returns without waiting. */
+ci_status_t ci_stamp(ci_ctx_t* ctx, uint64_t* slot, void* stream);
 
 /* Checksums of n FP32 values at device pointer x (stream-ordered on
  * `stream`, synchronous): bit-pattern sum mod 2^64 and FP64 sum. */

@@ -181,6 +181,7 @@ EXPORTS = {
     "ci_read_records": ([C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(WgRecord)], C.c_int),
     "victim_run": ([C.c_void_p, C.POINTER(VictimDesc), C.c_void_p, C.POINTER(VictimResult)], C.c_int),
     "victim_enqueue": ([C.c_void_p, C.POINTER(VictimDesc), C.c_void_p, C.c_uint32], C.c_int),
+    "ci_stamp": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "ci_checksum_f32": ([C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.POINTER(C.c_uint64),
                          C.POINTER(C.c_double)], C.c_int),
     "ci_quantize": ([C.c_void_p, C.c_void_p, C.c_uint64, C.c_int, C.c_void_p, C.POINTER(C.c_float),
@@ -439,6 +440,11 @@ class Context:
         """Queue `count` launches of the victim on `stream` without waiting."""
         self._sync_torch()
         _check(load_library().victim_enqueue(self.handle, C.byref(desc), _stream_handle(stream), int(count)))
+
+    def stamp(self, slot, stream):
+        """Enqueue a device wall-clock stamp into slot (a one-element int64
+        device tensor, or a view of one) on stream; returns at once."""
+        _check(load_library().ci_stamp(self.handle, _ptr(slot), _stream_handle(stream)))
 
     @staticmethod
     def triad_desc(b, c, a, passes: int = 1) -> VictimDesc:

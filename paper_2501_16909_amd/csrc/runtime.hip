@@ -806,8 +806,10 @@ extern "C" ci_status_t stressor_stop(ci_stressor_t* h, ci_stressor_report_t* rep
 // idle kernel alone slows it by more than kQueueTol, a queue is replaced
 // (the stressor's and the victim's in turn) and the check repeated,
 // kQueueAttempts times at most.  On shared CUs the idle kernel is one
-// 64-thread work-group per CU (wave slots the victim needs stay free); on
-// disjoint CUs it takes the stressor's shape (threads, work-groups per CU).
+// 256-thread work-group per CU (most wave slots stay free for the victim;
+// a 64-thread one missed the effect that 256-thread kernels then caused);
+// on disjoint CUs it takes the stressor's shape (threads, work-groups per
+// CU).
 namespace {
 constexpr double kQueueTol = 1.05;
 constexpr int kQueueAttempts = 8;
@@ -904,7 +906,7 @@ ci_status_t ci::check_queue_pair(ci_ctx* ctx, ci_resource_t r, const ci_stressor
   hipStream_t ss = masked_stream(ctx, mask);
   if (!ss) return set_err(CI_ERR_HIP, "hipExtStreamCreateWithCUMask failed");
   ci_stressor_opts_t o{};
-  o.threads = 64;
+  o.threads = 256;  // shared CUs: one 256-thread work-group per CU
   o.wg_per_cu = 1;
   if (vmask) {  // disjoint CUs: the stressor's own launch shape
     ci_stressor_opts_t ro;
@@ -1107,6 +1109,13 @@ extern "C" ci_status_t victim_enqueue(ci_ctx_t* ctx, const ci_victim_desc_t* d, 
     st = launch_victim(ctx, d, (hipStream_t)stream, nullptr, nullptr);
     if (st != CI_OK) return st;
   }
+  return CI_OK;
+}
+
+extern "C" ci_status_t ci_stamp(ci_ctx_t* ctx, uint64_t* slot, void* stream) {
+  if (!ctx || !slot || !stream) return set_err(CI_ERR_INVALID_ARG, "ci_stamp: NULL argument");
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(launch_stamp(slot, (hipStream_t)stream));
   return CI_OK;
 }
 

@@ -217,3 +217,30 @@ def test_disjoint_idle_stressor_costs_nothing(ctx, dev):
     st = ctx.queue_stats()
     assert st["checks"] >= 1, st
     print("queue-pair check:", st, [round(c["slowdown"], 3) for c in cells])
+
+
+def test_stamps_bracket_enqueued_work(ctx, dev):
+    """ci_stamp writes the device clock that victim_run's stamps use: two
+    stamps around enqueued work are ordered and precede a later victim."""
+    import torch
+    n = 1 << 22
+    tb = _t(synth.uniform_f32(synth.seed_for(0, synth.BUF_B), n), dev)
+    tc = _t(synth.uniform_f32(synth.seed_for(0, synth.BUF_C), n), dev)
+    ta = torch.empty_like(tb)
+    d = ctx.triad_desc(tb, tc, ta, passes=4)
+    side = torch.cuda.Stream(device=dev)
+    slots = torch.zeros(2, dtype=torch.int64, device=dev)
+    ctx.stamp(slots[0:1], side)
+    ctx.victim_enqueue(d, side, 8)
+    ctx.stamp(slots[1:2], side)
+    side.synchronize()
+    s0, s1 = (int(v) for v in slots.cpu().tolist())
+    assert 0 < s0 < s1
+    # 8 launches of 4 passes over 48 MiB take well over 10 us
+    ticks_us = ctx.info.wall_clock_khz / 1e3
+    assert (s1 - s0) / ticks_us > 10.0
+    out = ctx.victim_run(d)
+    assert out.t_begin > s1 and out.t_end > out.t_begin
+    from paper_2501_16909_amd import coloc
+    with pytest.raises(coloc.CiError):
+        ctx.stamp(slots[0:1], None)
