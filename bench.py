@@ -898,6 +898,66 @@ def _emit(out, args):
 
 
 
+def run_queues(args):
+    """Hardware-queue interference: a victim beside an idle kernel (the
+    occupancy hog sleeping on the stressor's CUs, 1 KiB of LDS per
+    work-group) in several launch shapes, with and without the queue-pair
+    check, over fresh contexts whose CU-masked queues are created in seeded
+    random orders.  Without the check the slowdown measures the queues
+    alone; with it, what remains after the harness picks its queues."""
+    import torch
+    import synth
+    from paper_2501_16909_amd import coloc
+    dev = torch.device("cuda:0")
+    n = 8192
+    w = torch.from_numpy(synth.normal_f32(synth.seed_for(2, synth.BUF_GEMV_W), n * n, sigma=0.02)).to(dev)
+    x = torch.from_numpy(synth.normal_f32(synth.seed_for(2, synth.BUF_GEMV_X), n)).to(dev)
+    shapes = [(64, 1), (256, 1), (256, 4), (1024, 1)]
+    rng = np.random.default_rng(16909)
+    runs = []
+    t0 = time.perf_counter()
+    for c in range(args.contexts):
+        ctx = coloc.Context(0)
+        qw, _ = ctx.quantize(w, "bf16")
+        qx, _ = ctx.quantize(x, "bf16")
+        w3 = qw.repeat(3)
+        y = torch.empty(n, dtype=torch.float32, device=dev)
+        d = ctx.gemv_desc(w3, qx, y, n, n, copies=3)
+        masks = [(xx, comp) for xx in (0.25, 0.5, 0.75) for comp in (False, True)] + [(1.0, False)]
+        order = [masks[i] for i in rng.permutation(len(masks))]
+        for xx, comp in order:
+            ctx.probe_placement(ctx.cu_mask(xx, comp)[0], 64)
+        run = {"context": c, "queue_order": [f"{'complement ' if comp else ''}{xx:g}" for xx, comp in order],
+               "raw": {}, "checked": {}}
+        for placement in ("disjoint", "shared"):
+            for th, wg in shapes:
+                o = dict(threads=th, wg_per_cu=wg, knob=1)
+                cell = ctx.measure_sensitivity(d, ["occupancy"], [o], [0.5], reps=args.reps, warmups=3,
+                                               placement=placement, queue_check=False)[0]
+                run["raw"][f"{placement} {th}x{wg}"] = round(cell["slowdown"], 3)
+            cell = ctx.measure_sensitivity(d, ["occupancy"], [dict(threads=256, wg_per_cu=1, knob=1)], [0.5],
+                                           reps=args.reps, warmups=3, placement=placement)[0]
+            run["checked"][f"{placement} 256x1"] = round(cell["slowdown"], 3)
+        run["queue_pair_check"] = ctx.queue_stats()
+        log(json.dumps(run))
+        runs.append(run)
+        del w3, qw, qx, y
+        ctx.close()
+    summary = {}
+    for key in runs[0]["raw"]:
+        v = [r["raw"][key] for r in runs]
+        summary["raw " + key] = {"min": min(v), "median": float(np.median(v)), "max": max(v)}
+    for key in runs[0]["checked"]:
+        v = [r["checked"][key] for r in runs]
+        summary["checked " + key] = {"min": min(v), "median": float(np.median(v)), "max": max(v)}
+    out = {"metric": "victim slowdown beside an idle kernel on another hardware queue",
+           "config": {"workload": "BF16 GEMV 8192^2 (3 rotating copies) victim; sleeping occupancy hog on the "
+                                  "other half of the CUs (disjoint) or on half the CUs (shared); intensity 0.5",
+                      "contexts": args.contexts, "reps": args.reps},
+           "runs": runs, "summary": summary, "seconds": round(time.perf_counter() - t0, 1)}
+    _emit(out, args)
+
+
 def predicted_pair_slowdown(profiles, a, b):
     """Product over resources of max(1, curve_A(pressure of B))."""
     out = 1.0
@@ -1066,7 +1126,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="suite", choices=["suite", "sweep", "precision", "serve", "counters", "suite-counters",
-                             "pollution", "bandwidth", "ilp", "pairs", "ldsstride", "estimator", "decode"])
+                             "pollution", "bandwidth", "ilp", "pairs", "ldsstride", "estimator", "decode",
+                             "queues"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--out", default=None, help="also write the JSON line(s) to this file")
     ap.add_argument("--reps", type=int, default=10, help="sweep / precision: repetitions per cell")
@@ -1078,6 +1139,7 @@ def main():
     ap.add_argument("--bound", type=float, default=1.5, help="serve: p99 slowdown bound")
     ap.add_argument("--profiles", default=None, help="serve: sensitivity profiles (JSON)")
     ap.add_argument("--batch", type=int, default=1, help="decode: sequences per step (1..8)")
+    ap.add_argument("--contexts", type=int, default=6, help="queues: fresh contexts (queue orders) to try")
     ap.add_argument("--profile-axis", default="duty", choices=["cu", "duty"],
                     help="serve: intensity axis of measured profiles (CU fraction or duty cycle)")
     args = ap.parse_args()
@@ -1112,6 +1174,8 @@ def main():
         run_estimator(args)
     elif args.config == "decode":
         run_decode(args)
+    elif args.config == "queues":
+        run_queues(args)
 
 
 if __name__ == "__main__":

@@ -330,11 +330,15 @@ ci_status_t ci_quantize(ci_ctx_t* ctx, const void* src, uint64_t n, int dtype, v
                         float* scale_out, void* stream);
 
 /* ------------------------------------------------------- sensitivity */
+/* ci_measure_opts_t.flags */
+#define CI_MEASURE_NO_QUEUE_CHECK 1u  /* skip the queue-pair check (raw placement) */
+
 typedef struct ci_measure_opts {
   uint32_t reps;         /* alone/colocated pairs per cell (default 20)       */
   uint32_t warmups;      /* victim warm-up runs per cell (default 3)          */
   int placement;         /* ci_placement_t                                    */
   uint32_t deadline_ms;  /* stressor deadline per colocated run (default 2000) */
+  uint32_t flags;        /* CI_MEASURE_* bits                                 */
 } ci_measure_opts_t;
 
 typedef struct ci_cell {

@@ -76,9 +76,12 @@ class VictimResult(C.Structure):
                 ("t_begin", C.c_uint64), ("t_end", C.c_uint64)]
 
 
+MEASURE_NO_QUEUE_CHECK = 1
+
+
 class MeasureOpts(C.Structure):
     _fields_ = [("reps", C.c_uint32), ("warmups", C.c_uint32), ("placement", C.c_int),
-                ("deadline_ms", C.c_uint32)]
+                ("deadline_ms", C.c_uint32), ("flags", C.c_uint32)]
 
 
 class Cell(C.Structure):
@@ -501,14 +504,15 @@ class Context:
     # -------------------------------------------------------- sensitivity
     def measure_sensitivity(self, desc: VictimDesc, resources, opts_list, intensities,
                             reps: int = 20, warmups: int = 3, placement: str = "shared",
-                            deadline_ms: int = 2000, ws=None):
+                            deadline_ms: int = 2000, ws=None, queue_check: bool = True):
         import torch
         self._sync_torch()
         nr, nx = len(resources), len(intensities)
         rs = (C.c_int * nr)(*[RES[r] for r in resources])
         so = (StressorOpts * nr)(*[make_opts(**o) for o in opts_list])
         xs = (C.c_float * nx)(*[float(x) for x in intensities])
-        mo = MeasureOpts(reps, warmups, 1 if placement == "disjoint" else 0, deadline_ms)
+        mo = MeasureOpts(reps, warmups, 1 if placement == "disjoint" else 0, deadline_ms,
+                         0 if queue_check else MEASURE_NO_QUEUE_CHECK)
         need = 256
         for i in range(nr):
             b = C.c_size_t()
@@ -544,14 +548,16 @@ class Context:
                 "t_end": r.t_end}
 
     def measure_decode(self, model: "DecodeModel", resources, opts_list, intensities, reps: int = 10,
-                       warmups: int = 2, placement: str = "shared", deadline_ms: int = 2000, ws=None):
+                       warmups: int = 2, placement: str = "shared", deadline_ms: int = 2000, ws=None,
+                       queue_check: bool = True):
         import torch
         self._sync_torch()
         nr, nx = len(resources), len(intensities)
         rs = (C.c_int * nr)(*[RES[r] for r in resources])
         so = (StressorOpts * nr)(*[make_opts(**o) for o in opts_list])
         xs = (C.c_float * nx)(*[float(x) for x in intensities])
-        mo = MeasureOpts(reps, warmups, 1 if placement == "disjoint" else 0, deadline_ms)
+        mo = MeasureOpts(reps, warmups, 1 if placement == "disjoint" else 0, deadline_ms,
+                         0 if queue_check else MEASURE_NO_QUEUE_CHECK)
         if ws is None:
             need = 256
             for i in range(nr):

@@ -1199,7 +1199,7 @@ extern "C" ci_status_t measure_sensitivity(ci_ctx_t* ctx, const ci_victim_desc_t
     return set_err(CI_ERR_INVALID_ARG, "measure_sensitivity: bad argument");
   ci_status_t st = check_victim(d);
   if (st != CI_OK) return st;
-  ci_measure_opts_t mo{20, 3, CI_PLACE_SHARED, 2000};
+  ci_measure_opts_t mo{20, 3, CI_PLACE_SHARED, 2000, 0};
   if (o) {
     mo = *o;
     if (!mo.reps) mo.reps = 20;
@@ -1238,9 +1238,11 @@ extern "C" ci_status_t measure_sensitivity(ci_ctx_t* ctx, const ci_victim_desc_t
       so.deadline_ms = mo.deadline_ms;
       ci_victim_result_t r;
       VictimRun vr{ctx, d, caller};
-      st = check_queue_pair(ctx, rs[i], sopts ? &sopts[i] : nullptr, xs[j], caller, &vs,
-                            masked ? vmask : nullptr, ws, ws_bytes, &VictimRun::call, &vr);
-      if (st != CI_OK) return st;
+      if (!(mo.flags & CI_MEASURE_NO_QUEUE_CHECK)) {
+        st = check_queue_pair(ctx, rs[i], sopts ? &sopts[i] : nullptr, xs[j], caller, &vs,
+                              masked ? vmask : nullptr, ws, ws_bytes, &VictimRun::call, &vr);
+        if (st != CI_OK) return st;
+      }
       for (uint32_t w = 0; w < mo.warmups; ++w) {
         st = run_victim(ctx, d, caller, vs, &r);
         if (st != CI_OK) return st;
