@@ -244,3 +244,20 @@ def test_stamps_bracket_enqueued_work(ctx, dev):
     from paper_2501_16909_amd import coloc
     with pytest.raises(coloc.CiError):
         ctx.stamp(slots[0:1], None)
+
+
+def test_raw_placement_flag_skips_the_queue_check(ctx, dev):
+    import torch
+    n = 1 << 22
+    tb = _t(synth.uniform_f32(synth.seed_for(0, synth.BUF_B), n), dev)
+    tc = _t(synth.uniform_f32(synth.seed_for(0, synth.BUF_C), n), dev)
+    ta = torch.empty_like(tb)
+    d = ctx.triad_desc(tb, tc, ta, passes=4)
+    before = ctx.queue_stats()["checks"]
+    cell, = ctx.measure_sensitivity(d, ["occupancy"], [dict()], [0.5], reps=4, warmups=1,
+                                    placement="disjoint", queue_check=False)
+    assert cell["output_equal"] and cell["window_covered"] and cell["reps"] == 4
+    assert ctx.queue_stats()["checks"] == before
+    cell, = ctx.measure_sensitivity(d, ["occupancy"], [dict()], [0.5], reps=4, warmups=1,
+                                    placement="disjoint")
+    assert ctx.queue_stats()["checks"] == before + 1
