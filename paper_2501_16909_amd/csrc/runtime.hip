@@ -795,21 +795,19 @@ extern "C" ci_status_t stressor_stop(ci_stressor_t* h, ci_stressor_report_t* rep
 
 // ------------------------------------------------------- queue-pair check
 // Kernels on two hardware queues can slow each other although they share no
-// CU and no memory traffic: on MI355X a victim beside a sleeping kernel (one
-// 64-thread work-group per CU) on another queue ran either at its alone speed
-// or 1.3-1.5x slower, depending only on the order in which the process had
-// created its queues, and by how much depended on the victim and, on
-// disjoint CUs, on the other kernel's launch shape.  Before the first
-// colocated measurement of a (victim queue, stressor queue) pair in a
-// measurement call (one victim), the victim therefore runs alone and beside
-// an idle kernel on the stressor's queue, in counterbalanced order; if the
-// idle kernel alone slows it by more than kQueueTol, a queue is replaced
-// (the stressor's and the victim's in turn) and the check repeated,
-// kQueueAttempts times at most.  On shared CUs the idle kernel is one
-// 256-thread work-group per CU (most wave slots stay free for the victim;
-// a 64-thread one missed the effect that 256-thread kernels then caused);
-// on disjoint CUs it takes the stressor's shape (threads, work-groups per
-// CU).
+// CU and no memory traffic: on MI355X a victim beside a sleeping kernel on
+// another queue ran either at its alone speed or 1.4-1.6x slower, depending
+// only on the order in which the process had created its queues (in three
+// of six random orders; the sleeping kernel's shape made no difference).
+// Before the first colocated measurement of a (victim queue, stressor
+// queue) pair in a measurement call (one victim), the victim therefore runs
+// alone and beside an idle kernel on the stressor's queue, in
+// counterbalanced order; if the idle kernel alone slows it by more than
+// kQueueTol, a queue is replaced (the stressor's and the victim's in turn)
+// and the check repeated, kQueueAttempts times at most.  The idle kernel is
+// one 256-thread work-group per stressed CU on shared CUs (most wave slots
+// stay free for the victim) and takes the stressor's shape (threads,
+// work-groups per CU) on disjoint CUs.
 namespace {
 constexpr double kQueueTol = 1.05;
 constexpr int kQueueAttempts = 8;
