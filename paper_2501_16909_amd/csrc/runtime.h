@@ -23,13 +23,19 @@ struct ci_ctx {
   uint32_t nparts = 0;
   std::map<std::array<uint32_t, 8>, hipStream_t> masked;  // CU-masked streams by mask
   hipStream_t vstream = nullptr;       // non-blocking stream for shared-placement victims
-  // queue pairs that passed the queue-pair check, with the idle kernel's shape
+  // Queue pairs that passed the queue-pair check (with the idle kernel's
+  // shape) and victim streams kept after qualification, each valid only at
+  // the queue generation it was verified in: every stream this library
+  // creates or destroys starts a new generation, since the runtime may then
+  // place the existing queues differently.
   struct QueuePair {
     hipStream_t victim, stressor;
     uint32_t threads, wg_per_cu;
+    uint64_t gen;
   };
   std::vector<QueuePair> queue_checked;
-  std::vector<hipStream_t> queue_qualified;   // victim streams kept after qualification
+  std::vector<std::pair<hipStream_t, uint64_t>> queue_qualified;
+  uint64_t queue_gen = 0;
   uint32_t queue_checks = 0, queue_replaced = 0, queue_unresolved = 0;
   hipEvent_t ev[12] = {};
   struct ci_stressor* active = nullptr;

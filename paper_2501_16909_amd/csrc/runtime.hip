@@ -74,13 +74,21 @@ static void forget_stream(ci_ctx* ctx, hipStream_t s) {
           v.end());
 }
 
-static hipStream_t new_masked_stream(const std::array<uint32_t, 8>& key) {
+static hipStream_t new_masked_stream(ci_ctx* ctx, const std::array<uint32_t, 8>& key) {
   hipStream_t s = nullptr;
   if (hipExtStreamCreateWithCUMask(&s, 8, key.data()) != hipSuccess) {
     (void)hipGetLastError();  // do not leave the failure for the next call to find
     return nullptr;
   }
+  ++ctx->queue_gen;
   return s;
+}
+
+static void destroy_stream(ci_ctx* ctx, hipStream_t s) {
+  (void)hipStreamSynchronize(s);
+  (void)hipStreamDestroy(s);
+  forget_stream(ctx, s);
+  ++ctx->queue_gen;
 }
 
 hipStream_t ci::masked_stream(ci_ctx* ctx, const uint32_t mask[8]) {
@@ -93,14 +101,12 @@ hipStream_t ci::masked_stream(ci_ctx* ctx, const uint32_t mask[8]) {
   if (ctx->masked.size() >= kMaxMaskedStreams) {
     for (auto jt = ctx->masked.begin(); jt != ctx->masked.end(); ++jt) {
       if (ctx->active && ctx->active->ms == jt->second) continue;
-      (void)hipStreamSynchronize(jt->second);
-      (void)hipStreamDestroy(jt->second);
-      forget_stream(ctx, jt->second);
+      destroy_stream(ctx, jt->second);
       ctx->masked.erase(jt);
       break;
     }
   }
-  hipStream_t s = new_masked_stream(key);
+  hipStream_t s = new_masked_stream(ctx, key);
   if (s) ctx->masked[key] = s;
   return s;
 }
@@ -110,14 +116,10 @@ hipStream_t ci::masked_stream(ci_ctx* ctx, const uint32_t mask[8]) {
 hipStream_t ci::replace_masked_stream(ci_ctx* ctx, const uint32_t mask[8]) {
   std::array<uint32_t, 8> key{};
   for (int i = 0; i < 8; ++i) key[i] = mask[i];
-  hipStream_t s = new_masked_stream(key);
+  hipStream_t s = new_masked_stream(ctx, key);
   if (!s) return nullptr;
   auto it = ctx->masked.find(key);
-  if (it != ctx->masked.end()) {
-    (void)hipStreamSynchronize(it->second);
-    (void)hipStreamDestroy(it->second);
-    forget_stream(ctx, it->second);
-  }
+  if (it != ctx->masked.end()) destroy_stream(ctx, it->second);
   ctx->masked[key] = s;
   return s;
 }
@@ -815,12 +817,17 @@ constexpr int kQueuePairs = 6;
 
 // Replaces the shared-placement victim stream (a plain stream: the runtime
 // deals plain streams round-robin over its hardware queues).
-hipStream_t replace_vstream(ci_ctx* ctx) {
+hipStream_t new_plain_stream(ci_ctx* ctx) {
   hipStream_t s = nullptr;
   if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
-  (void)hipStreamSynchronize(ctx->vstream);
-  (void)hipStreamDestroy(ctx->vstream);
-  forget_stream(ctx, ctx->vstream);
+  ++ctx->queue_gen;
+  return s;
+}
+
+hipStream_t replace_vstream(ci_ctx* ctx) {
+  hipStream_t s = new_plain_stream(ctx);
+  if (!s) return nullptr;
+  destroy_stream(ctx, ctx->vstream);
   ctx->vstream = s;
   return s;
 }
@@ -848,8 +855,8 @@ constexpr double kQualifyGain = 0.97;
 
 ci_status_t qualify_victim_queue(ci_ctx* ctx, hipStream_t* vs, const uint32_t* vmask,
                                  ci_status_t (*run)(void*, hipStream_t, double*), void* arg) {
-  for (hipStream_t q : ctx->queue_qualified)
-    if (q == *vs) return CI_OK;
+  for (const auto& q : ctx->queue_qualified)
+    if (q.first == *vs && q.second == ctx->queue_gen) return CI_OK;
   std::array<uint32_t, 8> key{};
   if (vmask)
     for (int i = 0; i < 8; ++i) key[i] = vmask[i];
@@ -858,12 +865,7 @@ ci_status_t qualify_victim_queue(ci_ctx* ctx, hipStream_t* vs, const uint32_t* v
   ci_status_t st = median_alone(best, run, arg, &t_best);
   if (st != CI_OK) return st;
   for (int c = 0; c < kQualifyCandidates; ++c) {
-    hipStream_t cand = nullptr;
-    if (vmask) {
-      cand = new_masked_stream(key);
-    } else if (hipStreamCreateWithFlags(&cand, hipStreamNonBlocking) != hipSuccess) {
-      cand = nullptr;
-    }
+    hipStream_t cand = vmask ? new_masked_stream(ctx, key) : new_plain_stream(ctx);
     if (!cand) return set_err(CI_ERR_HIP, "victim queue qualification: stream creation failed");
     double t = 0.0;
     st = median_alone(cand, run, arg, &t);
@@ -873,22 +875,17 @@ ci_status_t qualify_victim_queue(ci_ctx* ctx, hipStream_t* vs, const uint32_t* v
       best = cand;
       t_best = t;
     }
-    (void)hipStreamSynchronize(loser);
-    if (loser != *vs) {
-      (void)hipStreamDestroy(loser);
-    }
+    if (loser != *vs) destroy_stream(ctx, loser);
     if (st != CI_OK) return st;
   }
   if (best != *vs) {  // install the winner where the old victim queue was kept
     ++ctx->queue_replaced;
-    (void)hipStreamSynchronize(*vs);
-    (void)hipStreamDestroy(*vs);
-    forget_stream(ctx, *vs);
+    destroy_stream(ctx, *vs);
     if (vmask) ctx->masked[key] = best;
     else ctx->vstream = best;
     *vs = best;
   }
-  ctx->queue_qualified.push_back(best);
+  ctx->queue_qualified.push_back({best, ctx->queue_gen});
   return CI_OK;
 }
 }  // namespace
@@ -918,7 +915,8 @@ ci_status_t ci::check_queue_pair(ci_ctx* ctx, ci_resource_t r, const ci_stressor
   ci_status_t qs = qualify_victim_queue(ctx, vs, vmask, run, arg);
   if (qs != CI_OK) return qs;
   for (const auto& p : ctx->queue_checked)
-    if (p.victim == *vs && p.stressor == ss && p.threads == o.threads && p.wg_per_cu == o.wg_per_cu)
+    if (p.victim == *vs && p.stressor == ss && p.threads == o.threads && p.wg_per_cu == o.wg_per_cu &&
+        p.gen == ctx->queue_gen)
       return CI_OK;
   size_t need = 0;
   if (ci_workspace_size(CI_RES_OCCUPANCY, &o, k, &need) != CI_OK || !ws || ws_bytes < need)
@@ -962,7 +960,7 @@ ci_status_t ci::check_queue_pair(ci_ctx* ctx, ci_resource_t r, const ci_stressor
       if (qs != CI_OK) return qs;
     }
   }
-  ctx->queue_checked.push_back({*vs, ss, o.threads, o.wg_per_cu});
+  ctx->queue_checked.push_back({*vs, ss, o.threads, o.wg_per_cu, ctx->queue_gen});
   return CI_OK;
 }
 
