@@ -87,8 +87,12 @@ class Suite:
             synth.device_fill_uniform_f32(t.data_ptr(), m, synth.seed_for(0, s))
         torch.cuda.synchronize()
         self.ws = torch.empty(256 + 256 * 8 * 48, dtype=torch.uint8, device=dev)
+        from paper_2501_16909_amd.coloc import HBM_MIX as mix
         self.items = [
             ("hbm", dict(src0=self.hb, src1=self.hc, dst=self.ha, n=n, passes=1), "GB/s", 1e9),
+            ("hbm_read", dict(src0=self.hb, src1=self.hc, n=n, passes=1, knob=mix["read"]), "GB/s", 1e9),
+            ("hbm_copy", dict(src0=self.hb, dst=self.ha, n=n, passes=1, knob=mix["copy"]), "GB/s", 1e9),
+            ("hbm_write", dict(dst=self.ha, n=n, passes=1, knob=mix["write"]), "GB/s", 1e9),
             ("l2", dict(src0=self.l2, n=1 << 19, passes=32), "TB/s", 1e12),
             ("mall", dict(src0=self.mall, n=1 << 25, passes=60), "TB/s", 1e12),
             ("vl1d", dict(src0=self.l1, n=1 << 12, passes=4000), "TB/s", 1e12),
@@ -103,14 +107,15 @@ class Suite:
 
     def step(self, acc):
         for name, opts, unit, scale in self.items:
-            st = self.ctx.stressor(name, 1.0, ws=self.ws, **opts)
+            res = name.split("_")[0] if name.startswith("hbm_") else name
+            st = self.ctx.stressor(res, 1.0, ws=self.ws, **opts)
             rep = st.stop()
             rate = rep.units / (rep.kernel_ns * 1e-9)
             a = acc.setdefault(name, {"unit": unit, "scale": scale, "rates": [], "kernel_ns": [],
                                       "pct": [], "units": rep.units})
             a["rates"].append(rate)
             a["kernel_ns"].append(rep.kernel_ns)
-            a["pct"].append(100.0 * rate / self.ctx.peak(name) if self.ctx.peak(name) > 0 else None)
+            a["pct"].append(100.0 * rate / self.ctx.peak(res) if self.ctx.peak(res) > 0 else None)
         # colocated triad pair (shared CUs and disjoint halves)
         d = self.ctx.triad_desc(self.vb, self.vc, self.va, passes=10)
         so = [dict(src0=self.sb, src1=self.sc, dst=self.sa, n=1 << 22)]
@@ -207,7 +212,8 @@ def run_suite(args):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (SplitMix64 counter-form uniform [-1,1) / uint32 words / random cycle)",
-        "config": {"workload": "stressor suite standalone: HBM triad FP32 N=2^30; L2 2 MiB; "
+        "config": {"workload": "stressor suite standalone: HBM triad FP32 N=2^30 (and its "
+                               "read-only, copy and write-only mixes); L2 2 MiB; "
                                "Infinity Cache 128 MiB; vL1D 16 KiB; LDS 64 KiB/WG; FP32 FMA 4096; "
                                "MFMA FP32/BF16/FP8; uint32 chase over 2^24 cycle; 10^6 empty "
                                "64-thread WGs; plus colocated triad pair N=2^22",
@@ -215,7 +221,7 @@ def run_suite(args):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
                      "frac": round(achieved / 8000.0, 4),
                      "traffic": traffic,
-                     "kernel": "triad_stressor (12 B per element, N=2^30, one pass per launch)"},
+                     "kernel": "hbm_stressor, triad mix (12 B per element, N=2^30, one pass per launch)"},
         "stressors": stress,
         "colocated_triad_pair": pairs,
     }
@@ -1094,7 +1100,8 @@ def run_suite_counters(args):
 
 def run_counters(args):
     """Short run for hardware-counter passes: the HBM stressor over N = 2^30
-    (one pass per launch) twice, then a plain 1 GiB device-to-device copy
+    (one pass per launch) twice, its read-only, copy and write-only mixes
+    once each, then a plain 1 GiB device-to-device copy
     twice as the calibration kernel of known traffic (1 GiB read, 1 GiB
     written)."""
     import torch
@@ -1111,13 +1118,16 @@ def run_counters(args):
     for _ in range(2):
         rep = ctx.stressor("hbm", 1.0, src0=b, src1=c, dst=a, n=n, passes=1).stop()
         log(f"hbm stressor: {rep.units / rep.kernel_ns:.0f} GB/s")
+    for mix, ops in (("read", dict(src0=b, src1=c)), ("copy", dict(src0=b, dst=a)), ("write", dict(dst=a))):
+        rep = ctx.stressor("hbm", 1.0, n=n, passes=1, knob=coloc.HBM_MIX[mix], **ops).stop()
+        log(f"hbm stressor, {mix} mix: {rep.units / rep.kernel_ns:.0f} GB/s")
     src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
     for _ in range(2):
         dst.copy_(src)
     torch.cuda.synchronize()
     ctx.close()
-    print(json.dumps({"counters_run": "hbm_triad_n2e30 x2, copy 1GiB x2"}), flush=True)
+    print(json.dumps({"counters_run": "hbm_triad_n2e30 x2, read/copy/write mixes x1, copy 1GiB x2"}), flush=True)
 
 
 def main():

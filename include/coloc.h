@@ -57,7 +57,7 @@ typedef enum ci_status {
  * 4.2; L2 capacity and memory bandwidth 4.3; shared memory 4.4.1; issue
  * (IPC) 4.4.2; compute pipelines 4.4.3), mapped to CDNA4 units. */
 typedef enum ci_resource {
-  CI_RES_HBM = 0,        /* triad a = b + 3c streaming over FP32 arrays       */
+  CI_RES_HBM = 0,        /* array streaming: triad a = b + 3c, or a CI_HBM_* mix */
   CI_RES_L2 = 1,         /* every WG re-reads one region sized for each XCD's L2 */
   CI_RES_MALL = 2,       /* ... a region that misses L2 and fits Infinity Cache */
   CI_RES_VL1D = 3,       /* ... a region that fits the per-CU vector L1        */
@@ -177,9 +177,28 @@ typedef struct ci_wg_record {
   uint64_t pad;
 } ci_wg_record_t;    /* 48 bytes */
 
+/* HBM traffic mixes (the HBM stressor's knob).  The paper's bandwidth
+ * stressor streams large arrays through HBM (Section 3, Pitfall 2; Section
+ * 4.3, Table 1); the mix sets the read/write proportion of that stream, since
+ * DRAM bandwidth and a co-runner's slowdown both depend on it.  Per element
+ * i < n (4-byte words, every element once per pass):
+ *   CI_HBM_TRIAD  a[i] = b[i] + 3 c[i] in FP32, rounded after the product
+ *                 and after the sum; 2 reads : 1 write, 12 B (default)
+ *   CI_HBM_READ   reads b[i] and c[i]; nothing is stored; each work-group's
+ *                 record.check is the sum of the words it read mod 2^32, so
+ *                 the checksum over all records, mod 2^32, is passes x
+ *                 sum_i (b[i] + c[i]) as uint32 words; 8 B
+ *   CI_HBM_COPY   a[i] = b[i] (bit copy); 1 : 1, 8 B
+ *   CI_HBM_WRITE  a[i] = the bits of lo32(i) * 0x9E3779B1 mod 2^32; 4 B    */
+#define CI_HBM_TRIAD 1u
+#define CI_HBM_READ 2u
+#define CI_HBM_COPY 3u
+#define CI_HBM_WRITE 4u
+
 typedef struct ci_stressor_opts {
   /* Resource-specific operands (device pointers, caller-owned):
-   *   HBM:        src0 = b, src1 = c, dst = a   (FP32, n elements)
+   *   HBM:        src0 = b, src1 = c, dst = a   (FP32, n elements; only the
+   *               arrays the traffic mix touches are required)
    *   L2/MALL/VL1D: src0 = region (uint32, n words)
    *   LDS:        src0 = window words (uint32, 8192 = 32 KiB)
    *   VALU_F32:   dst  = final chain values (FP32, grid*threads*knob)
@@ -201,6 +220,7 @@ typedef struct ci_stressor_opts {
   uint32_t threads;      /* threads per work-group; 0 = resource default     */
   uint32_t knob;         /* VALU_F32/F64: ILP chains per lane (1,2,4,8); LDS: stride
                             in vectors; MFMA: independent accumulators (1-4);
+                            HBM: traffic mix CI_HBM_* (0 = triad);
                             PTRCHASE: chains per lane (1-8); OCCUPANCY: LDS
                             KiB held per WG; 0 = default                     */
   uint32_t vec;          /* LDS: vector width in 32-bit words (1, 2, 4);

@@ -13,6 +13,7 @@ definition it follows.
 
 Parity status per function (pins are in tests/test_oracle_pins.py):
   triad_f32, bitsum_u32, sum_f32_exact .......... pinned
+  hbm_read_checksum, hbm_copy, hbm_write_pattern  pinned
   fma_chain_f32 / valu_outputs .................. pinned
   dmul_chain_f64 / valu64_outputs ............... pinned
   chase_u32, is_single_cycle .................... pinned
@@ -127,6 +128,42 @@ def rel_err_sum(device_sum: float, x) -> float:
     if denom == 0.0:
         return abs(device_sum - exact)
     return abs(device_sum - exact) / denom
+
+
+# --------------------------------------------------------------------------
+# HBM traffic mixes.  The bandwidth stressor of Section 3 (Pitfall 2) and
+# Section 4.3 streams large arrays; besides the triad it can read only, copy,
+# or write only, which sets the read/write proportion of the DRAM traffic.
+# Per element (4-byte words): read-only folds b[i] + c[i] into a checksum
+# mod 2**32 (once per pass), copy stores b's bits, write-only stores
+# lo32(i) * 0x9E3779B1 mod 2**32.
+# --------------------------------------------------------------------------
+HBM_MIXES = {"triad": 1, "read": 2, "copy": 3, "write": 4}
+WRITE_MULTIPLIER = 0x9E3779B1
+
+
+def hbm_bytes_per_element(mix: str) -> int:
+    """Bytes a mix moves per element: triad 2 reads + 1 write, read-only and
+    copy two streams, write-only one."""
+    return {"triad": 12, "read": 8, "copy": 8, "write": 4}[mix]
+
+
+def hbm_read_checksum(b, c, passes: int) -> int:
+    """passes x sum over i of (b[i] + c[i]) as uint32 words, mod 2**32."""
+    s = (region_sum_u32(np.ascontiguousarray(b).view(np.uint32))
+         + region_sum_u32(np.ascontiguousarray(c).view(np.uint32))) % (1 << 32)
+    return (int(passes) * s) % (1 << 32)
+
+
+def hbm_copy(b) -> np.ndarray:
+    """The copy mix's output: b's 32-bit words, NaN payloads included."""
+    return np.ascontiguousarray(b).view(np.uint32).copy()
+
+
+def hbm_write_pattern(n: int, first: int = 0) -> np.ndarray:
+    """Words the write-only mix stores at indices first .. first + n - 1."""
+    i = (np.arange(first, first + n, dtype=np.uint64) & np.uint64(0xFFFFFFFF))
+    return ((i * np.uint64(WRITE_MULTIPLIER)) & np.uint64(0xFFFFFFFF)).astype(np.uint32)
 
 
 # --------------------------------------------------------------------------

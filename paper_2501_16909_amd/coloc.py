@@ -18,6 +18,8 @@ RESOURCES = ["hbm", "l2", "mall", "vl1d", "lds", "valu_f32", "mfma_f32", "mfma_b
              "mfma_fp8", "ptrchase", "dispatch", "occupancy", "valu_f64"]
 RES = {name: i for i, name in enumerate(RESOURCES)}
 DTYPES = {"f32": 0, "bf16": 1, "fp8": 2}
+# HBM stressor traffic mixes (its `knob`): CI_HBM_TRIAD / READ / COPY / WRITE
+HBM_MIX = {"triad": 1, "read": 2, "copy": 3, "write": 4}
 VICTIMS = {"triad": 0, "gemm": 1, "gemv": 2}
 POLICIES = {"naive": 0, "usher": 1, "sensitivity": 2}
 STATUS = {0: "CI_OK", 1: "CI_ERR_INVALID_ARG", 2: "CI_ERR_HIP", 3: "CI_ERR_OOM",

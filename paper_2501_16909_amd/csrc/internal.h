@@ -39,9 +39,10 @@ inline hipError_t xlaunch(void (*kernel)(KArgs...), dim3 grid, dim3 block, uint3
 // Each returns hipSuccess or the launch error.  `grid` work-groups.
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_stamp(uint64_t* slot, hipStream_t s);
-hipError_t launch_triad_stressor(const KCtrl& c, const float* b, const float* cc, float* a,
-                                 uint64_t n, uint32_t threads, bool streaming, hipStream_t s,
-                                 hipEvent_t e0, hipEvent_t e1);
+// mix: CI_HBM_TRIAD / READ / COPY / WRITE (anything else: triad)
+hipError_t launch_hbm_stressor(const KCtrl& c, uint32_t mix, const float* b, const float* cc,
+                               float* a, uint64_t n, uint32_t threads, bool streaming,
+                               hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_triad_victim(const float* b, const float* c, float* a, uint64_t n,
                                uint32_t passes, uint32_t grid, hipStream_t s, hipEvent_t e0,
                                hipEvent_t e1);

@@ -5,9 +5,11 @@
 // large input array to an output array with vectorised loads (Section 3,
 // Pitfall 2; Section 4.3, Table 1); its cache-pollution variant sweeps the
 // per-instance data size to move the working set in and out of L2 (Section
-// 4.3, Figure 3).  Here the streaming form is the triad a = b + 3c (two FP32
-// input streams, one output stream); the cache forms re-read a region sized
-// to one level of the CDNA4 hierarchy.
+// 4.3, Figure 3).  Here the default streaming form is the triad a = b + 3c
+// (two FP32 input streams, one output stream); read-only, copy and
+// write-only forms move the same arrays in other read/write proportions.
+// The cache forms re-read a region sized to one level of the CDNA4
+// hierarchy.
 #include "internal.h"
 
 namespace ci {
@@ -27,9 +29,6 @@ __device__ __forceinline__ float4 triad4(float4 b, float4 c) {
   return make_float4(triad1(b.x, c.x), triad1(b.y, c.y), triad1(b.z, c.z), triad1(b.w, c.w));
 }
 
-// One wave-chunk of 1024 elements starting at `base`: four 16-byte loads of
-// each input per lane, all issued before the first store.  Streaming
-// (non-temporal) hints: the stressor's data is never reused.
 typedef float vf4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ vf4 triad_v(vf4 b, vf4 c) {
@@ -41,46 +40,107 @@ __device__ __forceinline__ vf4 triad_v(vf4 b, vf4 c) {
   return r;
 }
 
-template <bool NT>
-__device__ __forceinline__ void triad_chunk(const float* __restrict__ b, const float* __restrict__ c,
-                                            float* __restrict__ a, uint64_t base, uint64_t n,
-                                            uint32_t lane) {
+typedef uint32_t vu4 __attribute__((ext_vector_type(4)));
+
+// HBM traffic mixes (the stressor's knob; the values are the public CI_HBM_*
+// constants): bytes moved per element are 12, 8, 8 and 4.
+enum HbmMix : uint32_t { kMixTriad = 1, kMixRead = 2, kMixCopy = 3, kMixWrite = 4 };
+
+// Stored by the write-only mix: element i holds the bits of lo32(i) times an
+// odd constant (so distinct i < 2^32 give distinct words).
+constexpr uint32_t kWriteMul = 0x9E3779B1u;
+
+template <bool NT, typename V>
+__device__ __forceinline__ V ld(const V* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
+template <bool NT, typename V>
+__device__ __forceinline__ void st(V* p, V v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+// One wave-chunk of 1024 elements starting at `base`: four 16-byte accesses
+// per lane and stream, all loads issued before the first store.  Streaming
+// (non-temporal) hints: the stressor's data is never reused.  The read-only
+// mix adds the 32-bit words it reads into `acc` (mod 2^32).
+template <uint32_t MIX, bool NT>
+__device__ __forceinline__ void hbm_chunk(const float* __restrict__ b, const float* __restrict__ c,
+                                          float* __restrict__ a, uint64_t base, uint64_t n,
+                                          uint32_t lane, uint32_t& acc) {
   if (base + kChunk <= n) {
-    const vf4* b4 = reinterpret_cast<const vf4*>(b + base);
-    const vf4* c4 = reinterpret_cast<const vf4*>(c + base);
-    vf4* a4 = reinterpret_cast<vf4*>(a + base);
-    vf4 vb[4], vc[4];
+    if constexpr (MIX == kMixTriad) {
+      const vf4* b4 = reinterpret_cast<const vf4*>(b + base);
+      const vf4* c4 = reinterpret_cast<const vf4*>(c + base);
+      vf4* a4 = reinterpret_cast<vf4*>(a + base);
+      vf4 vb[4], vc[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if constexpr (NT) {
-        vb[u] = __builtin_nontemporal_load(b4 + u * 64 + lane);
-        vc[u] = __builtin_nontemporal_load(c4 + u * 64 + lane);
-      } else {
-        vb[u] = b4[u * 64 + lane];
-        vc[u] = c4[u * 64 + lane];
+      for (int u = 0; u < 4; ++u) {
+        vb[u] = ld<NT>(b4 + u * 64 + lane);
+        vc[u] = ld<NT>(c4 + u * 64 + lane);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) st<NT>(a4 + u * 64 + lane, triad_v(vb[u], vc[u]));
+    } else if constexpr (MIX == kMixRead) {
+      const vu4* b4 = reinterpret_cast<const vu4*>(b + base);
+      const vu4* c4 = reinterpret_cast<const vu4*>(c + base);
+      vu4 vb[4], vc[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        vb[u] = ld<NT>(b4 + u * 64 + lane);
+        vc[u] = ld<NT>(c4 + u * 64 + lane);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const vu4 t = vb[u] + vc[u];
+        acc += t.x + t.y + t.z + t.w;
+      }
+    } else if constexpr (MIX == kMixCopy) {
+      const vu4* b4 = reinterpret_cast<const vu4*>(b + base);
+      vu4* a4 = reinterpret_cast<vu4*>(a + base);
+      vu4 vb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) vb[u] = ld<NT>(b4 + u * 64 + lane);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) st<NT>(a4 + u * 64 + lane, vb[u]);
+    } else {
+      vu4* a4 = reinterpret_cast<vu4*>(a + base);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t i0 = (uint32_t)base + (uint32_t)(u * 256) + lane * 4u;
+        const vu4 v = {i0 * kWriteMul, (i0 + 1u) * kWriteMul, (i0 + 2u) * kWriteMul,
+                       (i0 + 3u) * kWriteMul};
+        st<NT>(a4 + u * 64 + lane, v);
       }
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if constexpr (NT) __builtin_nontemporal_store(triad_v(vb[u], vc[u]), a4 + u * 64 + lane);
-      else a4[u * 64 + lane] = triad_v(vb[u], vc[u]);
-    }
   } else {
-    for (uint64_t i = base + lane; i < n && i < base + kChunk; i += 64) a[i] = triad1(b[i], c[i]);
+    const uint32_t* bu = reinterpret_cast<const uint32_t*>(b);
+    const uint32_t* cu = reinterpret_cast<const uint32_t*>(c);
+    uint32_t* au = reinterpret_cast<uint32_t*>(a);
+    for (uint64_t i = base + lane; i < n && i < base + kChunk; i += 64) {
+      if constexpr (MIX == kMixTriad) a[i] = triad1(b[i], c[i]);
+      else if constexpr (MIX == kMixRead) acc += bu[i] + cu[i];
+      else if constexpr (MIX == kMixCopy) au[i] = bu[i];
+      else au[i] = (uint32_t)i * kWriteMul;
+    }
   }
 }
 
-// Persistent / fixed-pass triad.  Wave w of the grid owns wave-chunks
+// Persistent / fixed-pass HBM stressor.  Wave w of the grid owns wave-chunks
 // w, w + W, w + 2W, ... (W = waves in the grid); record.work counts the
-// wave-chunks the work-group processed.  NT selects streaming (non-temporal)
-// or ordinary cached accesses.
-template <bool NT>
-__global__ void __launch_bounds__(1024) triad_stressor(KCtrl c, const float* __restrict__ b,
-                                                       const float* __restrict__ cc,
-                                                       float* __restrict__ a, uint64_t n) {
+// wave-chunks the work-group processed and, for the read-only mix,
+// record.check is the sum of the words it read mod 2^32.  NT selects
+// streaming (non-temporal) or ordinary cached accesses.
+template <uint32_t MIX, bool NT>
+__global__ void __launch_bounds__(1024) hbm_stressor(KCtrl c, const float* __restrict__ b,
+                                                     const float* __restrict__ cc,
+                                                     float* __restrict__ a, uint64_t n) {
   __shared__ uint64_t s_t0;
   __shared__ uint64_t s_work[16];
   __shared__ uint32_t s_flags[16];
+  __shared__ uint32_t s_acc[16];
   const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
   const uint32_t wpg = blockDim.x >> 6;
   if (threadIdx.x == 0) {
@@ -95,39 +155,42 @@ __global__ void __launch_bounds__(1024) triad_stressor(KCtrl c, const float* __r
   const uint64_t nw = (uint64_t)gridDim.x * wpg;
   const uint64_t nchunks = (n + kChunk - 1) / kChunk;
   uint64_t done = 0;
-  StopState st;
-  stop_init(st, c, t0, blockIdx.x == 0 && wid == 0);
+  uint32_t acc = 0;
+  StopState sst;
+  stop_init(sst, c, t0, blockIdx.x == 0 && wid == 0);
   uint64_t tp = duty_mark(c);
   if (c.passes) {
     for (uint64_t p = 0; p < c.passes; ++p)
       for (uint64_t ch = gw; ch < nchunks; ch += nw) {
-        triad_chunk<NT>(b, cc, a, ch * kChunk, n, lane);
+        hbm_chunk<MIX, NT>(b, cc, a, ch * kChunk, n, lane, acc);
         duty_point(c, tp);
         ++done;
       }
   } else if (gw < nchunks) {
     uint64_t ch = gw;
     for (;;) {
-      triad_chunk<NT>(b, cc, a, ch * kChunk, n, lane);
+      hbm_chunk<MIX, NT>(b, cc, a, ch * kChunk, n, lane, acc);
       duty_point(c, tp);
       ++done;
       ch += nw;
       if (ch >= nchunks) ch = gw;
-      if (should_stop(st, c)) break;
+      if (should_stop(sst, c)) break;
     }
   } else {
-    while (!should_stop(st, c)) __builtin_amdgcn_s_sleep(32);
+    while (!should_stop(sst, c)) __builtin_amdgcn_s_sleep(32);
   }
+  const uint32_t wacc = wave_sum_u32(acc);
   if (lane == 0) {
     s_work[wid] = done;
-    s_flags[wid] = st.flags;
+    s_flags[wid] = sst.flags;
+    s_acc[wid] = wacc;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     uint64_t w = 0;
-    uint32_t f = 0;
-    for (uint32_t i = 0; i < wpg; ++i) { w += s_work[i]; f |= s_flags[i]; }
-    write_record(c, blockIdx.x, t0, w, 0, f);
+    uint32_t f = 0, sum = 0;
+    for (uint32_t i = 0; i < wpg; ++i) { w += s_work[i]; f |= s_flags[i]; sum += s_acc[i]; }
+    write_record(c, blockIdx.x, t0, w, sum, f);
   }
 }
 
@@ -262,12 +325,20 @@ hipError_t launch_stamp(uint64_t* slot, hipStream_t s) {
   return xlaunch(stamp_kernel, dim3(1), dim3(64), 0, s, nullptr, nullptr, slot);
 }
 
-hipError_t launch_triad_stressor(const KCtrl& c, const float* b, const float* cc, float* a,
-                                 uint64_t n, uint32_t threads, bool streaming, hipStream_t s,
-                                 hipEvent_t e0, hipEvent_t e1) {
-  if (streaming)
-    return xlaunch(triad_stressor<true>, dim3(c.grid), dim3(threads), 0, s, e0, e1, c, b, cc, a, n);
-  return xlaunch(triad_stressor<false>, dim3(c.grid), dim3(threads), 0, s, e0, e1, c, b, cc, a, n);
+hipError_t launch_hbm_stressor(const KCtrl& c, uint32_t mix, const float* b, const float* cc,
+                               float* a, uint64_t n, uint32_t threads, bool streaming,
+                               hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  const dim3 g(c.grid), t(threads);
+#define CI_HBM_LAUNCH(M)                                                                    \
+  return streaming ? xlaunch(hbm_stressor<M, true>, g, t, 0, s, e0, e1, c, b, cc, a, n)     \
+                   : xlaunch(hbm_stressor<M, false>, g, t, 0, s, e0, e1, c, b, cc, a, n)
+  switch (mix) {
+    case kMixRead: CI_HBM_LAUNCH(kMixRead);
+    case kMixCopy: CI_HBM_LAUNCH(kMixCopy);
+    case kMixWrite: CI_HBM_LAUNCH(kMixWrite);
+    default: CI_HBM_LAUNCH(kMixTriad);
+  }
+#undef CI_HBM_LAUNCH
 }
 
 hipError_t launch_triad_victim(const float* b, const float* c, float* a, uint64_t n,

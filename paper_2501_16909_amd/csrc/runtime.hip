@@ -303,7 +303,7 @@ Defaults defaults_for(ci_resource_t r) {
   // the smallest occupancy within a few percent of the best rate, so that a
   // colocated victim can still be dispatched beside the stressor.
   switch (r) {
-    case CI_RES_HBM: return {256, 1, 0, 0, 0};
+    case CI_RES_HBM: return {256, 1, CI_HBM_TRIAD, 0, 0};
     case CI_RES_L2: return {512, 3, 0, 0, 0};
     case CI_RES_MALL: return {256, 1, 0, 0, 0};
     case CI_RES_VL1D: return {256, 4, 0, 0, 0};
@@ -332,6 +332,16 @@ void resolve(ci_resource_t r, const ci_stressor_opts_t* in, ci_stressor_opts_t* 
   if (!o->deadline_ms) o->deadline_ms = 2000;
 }
 
+// Bytes moved per element by each HBM traffic mix (4-byte words).
+double hbm_bytes_per_element(uint32_t mix) {
+  switch (mix) {
+    case CI_HBM_READ:
+    case CI_HBM_COPY: return 8.0;
+    case CI_HBM_WRITE: return 4.0;
+    default: return 12.0;
+  }
+}
+
 int mfma_dtype(ci_resource_t r) {
   return r == CI_RES_MFMA_F32 ? CI_DT_F32 : r == CI_RES_MFMA_BF16 ? CI_DT_BF16 : CI_DT_FP8E4M3;
 }
@@ -356,12 +366,22 @@ ci_status_t check_opts(ci_ctx* ctx, ci_resource_t r, const ci_stressor_opts_t& o
     return set_err(CI_ERR_INVALID_ARG, "%s: threads %u must be a multiple of 64 in [64, 1024]",
                    kResName[r], o.threads);
   switch (r) {
-    case CI_RES_HBM:
-      if (!o.src0 || !o.src1 || !o.dst) return set_err(CI_ERR_INVALID_ARG, "hbm: b, c and a are required");
+    case CI_RES_HBM: {
+      if (o.knob < CI_HBM_TRIAD || o.knob > CI_HBM_WRITE)
+        return set_err(CI_ERR_INVALID_ARG, "hbm: traffic mix %u is not one of CI_HBM_*", o.knob);
+      // arrays each mix touches: triad b, c, a; read b, c; copy b, a; write a
+      const bool need_b = o.knob != CI_HBM_WRITE;
+      const bool need_c = o.knob == CI_HBM_TRIAD || o.knob == CI_HBM_READ;
+      const bool need_a = o.knob != CI_HBM_READ;
+      static const char* const kNeed[] = {"", "b, c and a", "b and c", "b and a", "a"};
+      if ((need_b && !o.src0) || (need_c && !o.src1) || (need_a && !o.dst))
+        return set_err(CI_ERR_INVALID_ARG, "hbm: %s required", kNeed[o.knob]);
       if (o.n == 0) return set_err(CI_ERR_INVALID_ARG, "hbm: n must be > 0");
-      if (((uintptr_t)o.src0 | (uintptr_t)o.src1 | (uintptr_t)o.dst) & 15)
+      if (((need_b ? (uintptr_t)o.src0 : 0) | (need_c ? (uintptr_t)o.src1 : 0) |
+           (need_a ? (uintptr_t)o.dst : 0)) & 15)
         return set_err(CI_ERR_INVALID_ARG, "hbm: arrays must be 16-byte aligned");
       break;
+    }
     case CI_RES_L2:
     case CI_RES_MALL:
     case CI_RES_VL1D: {
@@ -457,8 +477,8 @@ static ci_status_t launch_kernel(ci_stressor* h, const KCtrl& c) {
   hipEvent_t e0 = h->e0, e1 = h->persistent ? nullptr : h->e1;
   switch (h->r) {
     case CI_RES_HBM:
-      e = launch_triad_stressor(c, (const float*)o.src0, (const float*)o.src1, (float*)o.dst, o.n,
-                                o.threads, o.vec == 0, s, e0, e1);
+      e = launch_hbm_stressor(c, o.knob, (const float*)o.src0, (const float*)o.src1,
+                              (float*)o.dst, o.n, o.threads, o.vec == 0, s, e0, e1);
       break;
     case CI_RES_L2:
     case CI_RES_VL1D:
@@ -675,9 +695,11 @@ static double units_of(const ci_stressor* h, const std::vector<ci_wg_record_t>& 
   const ci_stressor_opts_t& o = h->o;
   const double waves = o.threads / 64.0;
   switch (h->r) {
-    case CI_RES_HBM:
-      if (!h->persistent) return 12.0 * (double)o.n * (double)o.passes;
-      return 12.0 * 1024.0 * (double)work;
+    case CI_RES_HBM: {
+      const double per = hbm_bytes_per_element(o.knob);
+      if (!h->persistent) return per * (double)o.n * (double)o.passes;
+      return per * 1024.0 * (double)work;
+    }
     case CI_RES_L2:
     case CI_RES_VL1D:
     case CI_RES_MALL:

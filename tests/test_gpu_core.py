@@ -176,6 +176,71 @@ def test_hbm_stressor_persistent_colocated(ctx, dev):
           f"stressor {rep.achieved/1e9:.0f} GB/s")
 
 
+@pytest.mark.parametrize("mix", ["read", "copy", "write"])
+@pytest.mark.parametrize("x,passes,n,vec", [(1.0, 1, (1 << 22) + 5, 0), (0.5, 3, 1 << 20, 1),
+                                           (1 / 32, 2, 5000, 0), (0.25, 1, 333, 1)])
+def test_hbm_mixes_fixed_passes(ctx, dev, mix, x, passes, n, vec):
+    """Read-only, copy and write-only mixes: outputs bit-exact, the read
+    checksum mod 2^32 exact, and nothing stored where the mix stores nothing."""
+    import torch
+    from paper_2501_16909_amd import coloc
+    b, c, tb, tc, _ = _hbm_buffers(dev, n, cfg=3)
+    sentinel = np.full(n, 0x7FC0DEAD, np.uint32)
+    ta = _t(sentinel.view(np.float32), dev)
+    ops = {"read": dict(src0=tb, src1=tc), "copy": dict(src0=tb, dst=ta), "write": dict(dst=ta)}[mix]
+    rep = ctx.stressor("hbm", x, n=n, passes=passes, vec=vec, knob=coloc.HBM_MIX[mix], **ops).stop()
+    got = ta.cpu().numpy().view(np.uint32)
+    if mix == "read":
+        assert np.array_equal(got, sentinel)
+        assert rep.checksum % 2 ** 32 == oracle.hbm_read_checksum(b, c, passes)
+    elif mix == "copy":
+        assert np.array_equal(got, oracle.hbm_copy(b))
+    else:
+        assert np.array_equal(got, oracle.hbm_write_pattern(n))
+    ncu = 8 * round(32 * x)
+    assert rep.grid == ncu and rep.wg_reported == rep.grid and not rep.timed_out
+    assert rep.work == passes * ((n + 1023) // 1024)
+    assert rep.units == oracle.hbm_bytes_per_element(mix) * n * passes
+    # the inputs are left as they were
+    assert np.array_equal(tb.cpu().numpy().view(np.uint32), b.view(np.uint32))
+
+
+def test_hbm_mix_options_are_checked(ctx, dev):
+    import torch
+    from paper_2501_16909_amd import coloc
+    t = torch.empty(1024, dtype=torch.float32, device=dev)
+    for bad in (dict(knob=5, src0=t, src1=t, dst=t), dict(knob=coloc.HBM_MIX["read"], src0=t),
+                dict(knob=coloc.HBM_MIX["copy"], src0=t), dict(knob=coloc.HBM_MIX["write"]),
+                dict(knob=coloc.HBM_MIX["copy"], src0=t[1:], dst=t)):
+        with pytest.raises(coloc.CiError) as ei:
+            ctx.stressor("hbm", 0.25, n=512, passes=1, **bad)
+        assert ei.value.status == 1, bad
+
+
+def test_hbm_read_mix_full_size_closed_form(ctx, dev):
+    """N = 2^30 words per array: b holds the words 0..N-1 and c zeros, so the
+    read checksum is passes * N(N-1)/2 mod 2^32; the persistent form reports
+    8 bytes per element of every chunk it read."""
+    import torch
+    from paper_2501_16909_amd import coloc
+    n = 1 << 30
+    tb = torch.arange(n, dtype=torch.int32, device=dev).view(torch.float32)
+    tc = torch.zeros(n, dtype=torch.float32, device=dev)
+    rep = ctx.stressor("hbm", 1.0, src0=tb, src1=tc, n=n, passes=2, knob=coloc.HBM_MIX["read"]).stop()
+    assert rep.checksum % 2 ** 32 == (2 * (n * (n - 1) // 2)) % 2 ** 32
+    assert rep.units == 16.0 * n and rep.wg_reported == rep.grid
+    import time
+    with ctx.stressor("hbm", 1.0, src0=tb, src1=tc, n=n, knob=coloc.HBM_MIX["read"]) as st:
+        time.sleep(0.02)
+    r = st.report
+    assert not r.timed_out and r.wg_reported == r.grid
+    assert r.units == 8.0 * 1024 * r.work and r.work > 0
+    print(f"read mix: fixed {rep.achieved / 1e9:.0f} GB/s ({rep.pct_of_peak:.1f} %), "
+          f"persistent {r.achieved / 1e9:.0f} GB/s")
+    del tb, tc
+    torch.cuda.empty_cache()
+
+
 def test_zero_intensity_invariant(ctx, dev):
     """A stressor at intensity 0 launches nothing: slowdown 1.00 +- 0.02."""
     import torch

@@ -134,6 +134,27 @@ def test_cache_sums_closed_form():
     assert list(exp) == [0, s, (3 * s) % 2 ** 32, (1000003 * s) % 2 ** 32]
 
 
+def test_hbm_mix_closed_forms():
+    # read-only: b holds the words 0..n-1, c a constant K -> passes * (n(n-1)/2 + nK) mod 2^32
+    for n, k, p in ((1, 5, 1), (1000, 0xFFFFFFFF, 3), ((1 << 20) + 77, 0x9E3779B1, 7)):
+        b = np.arange(n, dtype=np.uint32).view(np.float32)
+        c = np.full(n, k, np.uint32).view(np.float32)
+        assert oracle.hbm_read_checksum(b, c, p) == (p * (n * (n - 1) // 2 + n * k)) % 2 ** 32
+    # copy keeps every bit, signalling-NaN payloads included
+    w = np.array([0x7F800001, 0xFFC00123, 0x80000000, 0x3F800000], np.uint32)
+    assert np.array_equal(oracle.hbm_copy(w.view(np.float32)), w)
+    # write-only: an odd multiplier is a bijection mod 2^32, indices wrap at 2^32,
+    # and the words sum to K n(n-1)/2 mod 2^32
+    k = oracle.WRITE_MULTIPLIER
+    assert k % 2 == 1
+    pat = oracle.hbm_write_pattern(1 << 16)
+    assert pat[0] == 0 and pat[1] == k and len(np.unique(pat)) == 1 << 16
+    n = (1 << 20) + 13
+    assert oracle.region_sum_u32(oracle.hbm_write_pattern(n)) == (k * (n * (n - 1) // 2)) % 2 ** 32
+    assert np.array_equal(oracle.hbm_write_pattern(5, first=(1 << 32) + 9), oracle.hbm_write_pattern(5, first=9))
+    assert [oracle.hbm_bytes_per_element(m) for m in ("triad", "read", "copy", "write")] == [12, 8, 8, 4]
+
+
 def test_lds_pass_visits_every_vector_once_per_lane():
     """Each lane walks all nvec vectors once per pass, for any stride, so a
     wave's pass sum is 64 * sum(window); brute force on a tiny window also
