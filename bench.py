@@ -46,6 +46,12 @@ HBM_KERNEL_SOURCES = [os.path.join("paper_2501_16909_amd", "csrc", f) for f in (
 
 
 # --------------------------------------------------------------------------
+def suite_resource(name: str) -> str:
+    """Resource of a suite entry: the HBM mixes (hbm_read, ...) are the HBM
+    stressor with another knob."""
+    return "hbm" if name.startswith("hbm_") else name
+
+
 class Suite:
     """Device buffers and the fixed-work form of every stressor."""
 
@@ -107,7 +113,7 @@ class Suite:
 
     def step(self, acc):
         for name, opts, unit, scale in self.items:
-            res = name.split("_")[0] if name.startswith("hbm_") else name
+            res = suite_resource(name)
             st = self.ctx.stressor(res, 1.0, ws=self.ws, **opts)
             rep = st.stop()
             rate = rep.units / (rep.kernel_ns * 1e-9)
@@ -358,6 +364,49 @@ def run_sweep(args):
             json.dump(out, f)
 
 
+def run_hbm_mix(args):
+    """Victim slowdown against the HBM stressor in each traffic mix (triad,
+    read-only, copy, write-only) at CU intensity 0/25/50/75/100 %, with the
+    stressor's own bandwidth in each cell: how much of a memory-bound
+    co-runner's harm depends on its read/write proportion."""
+    import torch
+    from paper_2501_16909_amd import coloc
+    dev = torch.device("cuda:0")
+    ctx = coloc.Context(0)
+    h = stressor_operands(dev)["hbm"]
+    victims = sweep_victims(ctx, dev)
+    mixes = {"triad": dict(src0=h["src0"], src1=h["src1"], dst=h["dst"]),
+             "read": dict(src0=h["src0"], src1=h["src1"]),
+             "copy": dict(src0=h["src0"], dst=h["dst"]),
+             "write": dict(dst=h["dst"])}
+    opts = [dict(o, n=h["n"], knob=coloc.HBM_MIX[m]) for m, o in mixes.items()]
+    ws = torch.empty(256 + 256 * 8 * 48, dtype=torch.uint8, device=dev)
+    out = {"metric": "victim slowdown vs HBM traffic mix and intensity", "config": {
+        "workload": "victims of the sensitivity sweep x HBM stressor over 2^28-element FP32 arrays "
+                    "in four read/write mixes x CU intensity 0/25/50/75/100%", "reps": args.reps},
+        "intensities": INTENSITIES, "tables": {}}
+    t0 = time.perf_counter()
+    for placement in ("shared", "disjoint"):
+        for vname, d in victims.items():
+            cells = ctx.measure_sensitivity(d, ["hbm"] * len(mixes), opts, INTENSITIES, reps=args.reps,
+                                            warmups=3, placement=placement, ws=ws,
+                                            deadline_ms=args.deadline_ms)
+            tab = {}
+            for i, m in enumerate(mixes):
+                row = cells[i * len(INTENSITIES):(i + 1) * len(INTENSITIES)]
+                nan = lambda v: v != v
+                tab[m] = {"slowdown": [None if nan(c["slowdown"]) else round(c["slowdown"], 3) for c in row],
+                          "stressor_gbs": [round(c["stressor_achieved"] / 1e9, 1) for c in row],
+                          "valid": [bool(c["window_covered"] and c["output_equal"]) and not nan(c["slowdown"])
+                                    for c in row]}
+            out["tables"][f"{vname}/{placement}"] = tab
+            log(f"{vname} {placement}: " + ", ".join(f"{m}={tab[m]['slowdown'][-1]}" for m in tab))
+    out["seconds"] = round(time.perf_counter() - t0, 1)
+    out["queue_pair_check"] = ctx.queue_stats()
+    ctx.close()
+    _emit(out, args)
+
+
 def run_precision(args):
     """GEMM M = N = K = 8192 in FP32, BF16 and FP8 (per-tensor scale) from
     N(0,1) inputs, FP32 accumulation.  Error against FP64 on 4096 sampled
@@ -455,9 +504,13 @@ def serve_trace(lam, seconds, seed):
 
 
 DUTIES = (10, 25, 50, 75, 100)
+# Write share of each request kind's compulsory HBM bytes: the GEMV reads its
+# weights and writes one short vector, the triad writes one stream of three,
+# the GEMM writes an FP32 C as large as its BF16 A and B together.
+HBM_WRITE_FRAC = {"gemm": 0.5, "gemv": 0.0, "triad": 1.0 / 3.0}
 
 
-def serve_profiles(ctx, args, axis="cu"):
+def serve_profiles(ctx, args, axis="cu", hbm_mix="triad", res=("hbm", "mfma_bf16", "lds")):
     """Sensitivity profiles of the three request kinds at representative
     sizes (GEMM BF16 2048^3, GEMV BF16 8192^2, triad N = 2^24): slowdown
     curves (shared placement) on the resources the kinds themselves load --
@@ -467,15 +520,25 @@ def serve_profiles(ctx, args, axis="cu"):
     axis "cu": the stressor runs at full rate on a fraction x of the CUs.
     axis "duty": the stressor runs on every CU, active a fraction of the
     time; each duty level's standalone rate over the full rate is the curve's
-    abscissa, resampled onto the same five points."""
+    abscissa, resampled onto the same five points.
+
+    hbm_mix picks the HBM stressor's traffic mix ("triad" or "read"); res
+    limits the resources profiled."""
     import torch
     import synth
+    from paper_2501_16909_amd.coloc import HBM_MIX
     dev = ctx.device
     ops = stressor_operands(dev)
+    if hbm_mix == "read":
+        h = ops["hbm"]
+        ops["hbm"] = dict(src0=h["src0"], src1=h["src1"], n=h["n"], knob=HBM_MIX["read"])
+    res = list(res)
     ws = torch.empty(256 + 256 * 8 * 48, dtype=torch.uint8, device=dev)
     rates = {}
     duty_rates = {}
-    for r, extra in (("hbm", dict(passes=1)), ("mfma_bf16", dict(iters=2048, passes=2)), ("lds", dict(passes=4))):
+    fixed = {"hbm": dict(passes=1), "mfma_bf16": dict(iters=2048, passes=2), "lds": dict(passes=4)}
+    for r in res:
+        extra = fixed[r]
         rep = ctx.stressor(r, 1.0, ws=ws, **ops[r], **extra).stop()
         rates[r] = rep.units / (rep.kernel_ns * 1e-9)
         if axis == "duty":
@@ -508,7 +571,6 @@ def serve_profiles(ctx, args, axis="cu"):
     use = {"gemm": {"mfma_bf16": 2.0 * g ** 3, "lds": gemm_lds, "hbm": 3.0 * 2 * g * g},
            "gemv": {"hbm": 2.0 * n * n}, "triad": {"hbm": 12.0 * t}}
     occ = {"gemm": min(1.0, (g // 128) ** 2 / (256 * 2)) * 8 / 32, "gemv": 1.0, "triad": 1.0}
-    res = ["hbm", "mfma_bf16", "lds"]
     profiles = {}
     for kind, d in descs.items():
         t_alone = float(np.median([ctx.victim_run(d).time_ns for _ in range(5)])) * 1e-9
@@ -534,7 +596,8 @@ def serve_profiles(ctx, args, axis="cu"):
                 sens[r] = [float(v) for v in np.interp(INTENSITIES, np.asarray(xs[r])[order],
                                                        np.asarray(ys[r])[order])]
         press = {r: min(1.0, use[kind].get(r, 0.0) / t_alone / rates[r]) for r in res}
-        profiles[kind] = {"sens": sens, "press": press, "occ": occ[kind]}
+        profiles[kind] = {"sens": sens, "press": press, "occ": occ[kind],
+                          "hbm_write_frac": HBM_WRITE_FRAC[kind]}
     return profiles
 
 
@@ -964,12 +1027,18 @@ def run_queues(args):
     _emit(out, args)
 
 
-def predicted_pair_slowdown(profiles, a, b):
-    """Product over resources of max(1, curve_A(pressure of B))."""
+def predicted_pair_slowdown(profiles, a, b, read_profiles=None):
+    """Product over resources of max(1, curve_A(pressure of B)).  With
+    read_profiles (HBM curves and pressures against the read-only mix), a
+    co-runner whose HBM traffic is mostly reads (write fraction below 1/6)
+    is priced on the read-only curve instead of the triad's."""
     out = 1.0
     pts = np.array(INTENSITIES)
     for r, curve in profiles[a]["sens"].items():
-        x = min(1.0, max(0.0, profiles[b]["press"].get(r, 0.0)))
+        x = profiles[b]["press"].get(r, 0.0)
+        if r == "hbm" and read_profiles is not None and profiles[b]["hbm_write_frac"] < 1 / 6:
+            curve, x = read_profiles[a]["sens"]["hbm"], read_profiles[b]["press"]["hbm"]
+        x = min(1.0, max(0.0, x))
         out *= max(1.0, float(np.interp(x, pts, curve)))
     return out
 
@@ -987,7 +1056,10 @@ def run_estimator(args):
     ctx = coloc.Context(0)
     dev = ctx.device
     axes = {"cu": serve_profiles(ctx, args, axis="cu"), "duty": serve_profiles(ctx, args, axis="duty")}
+    # HBM curves against the read-only mix, for read-mostly co-runners
+    read_axes = {ax: serve_profiles(ctx, args, axis=ax, hbm_mix="read", res=("hbm",)) for ax in axes}
     log("profiles: " + json.dumps(axes))
+    log("read-mix HBM profiles: " + json.dumps(read_axes))
     # two independent instances of each kind (A's buffers and B's buffers)
     def make(kind, seed):
         if kind == "gemm":
@@ -1059,15 +1131,16 @@ def run_estimator(args):
             row = {"victim": a, "corunner": b, "measured": round(meas, 3),
                    "measured_trials": [round(t, 3) for t in trials], "stream_attempts": attempts}
             for ax, prof in axes.items():
-                pred = predicted_pair_slowdown(prof, a, b)
-                row[f"predicted_{ax}"] = round(pred, 3)
-                row[f"rel_err_{ax}"] = round(abs(pred - meas) / meas, 3)
+                for name, rp in ((ax, None), (ax + "_mix", read_axes[ax])):
+                    pred = predicted_pair_slowdown(prof, a, b, rp)
+                    row[f"predicted_{name}"] = round(pred, 3)
+                    row[f"rel_err_{name}"] = round(abs(pred - meas) / meas, 3)
             rows.append(row)
             log(json.dumps(row))
     rank = lambda v: np.argsort(np.argsort(v))
     m = np.array([r["measured"] for r in rows])
     summary = {}
-    for ax in axes:
+    for ax in [a for x in axes for a in (x, x + "_mix")]:
         err = np.array([r[f"rel_err_{ax}"] for r in rows])
         p = np.array([r[f"predicted_{ax}"] for r in rows])
         summary[ax] = {"mean_rel_err": round(float(err.mean()), 3), "max_rel_err": round(float(err.max()), 3),
@@ -1077,8 +1150,9 @@ def run_estimator(args):
                                   "enqueued back to back on a second stream; shared CUs",
                       "model": "product over HBM / BF16-MFMA / LDS of max(1, sensitivity curve at the "
                                "co-runner's standalone pressure); curves on two intensity axes: CU "
-                               "fraction at full rate ('cu') and duty cycle on every CU ('duty')"},
-           "pairs": rows, "axes": summary, "profiles": axes}
+                               "fraction at full rate ('cu') and duty cycle on every CU ('duty'); "
+                               "'_mix': read-mostly co-runners priced on the read-only HBM curve"},
+           "pairs": rows, "axes": summary, "profiles": axes, "read_mix_profiles": read_axes}
     ctx.close()
     _emit(out, args)
 
@@ -1092,7 +1166,7 @@ def run_suite_counters(args):
     ctx = coloc.Context(0)
     suite = Suite(ctx, dev)
     for name, opts, unit, scale in suite.items:
-        rep = ctx.stressor(name, 1.0, ws=suite.ws, **opts).stop()
+        rep = ctx.stressor(suite_resource(name), 1.0, ws=suite.ws, **opts).stop()
         log(f"{name}: {rep.units / (rep.kernel_ns * 1e-9) / scale:.2f} {unit}")
     ctx.close()
     print(json.dumps({"counters_run": "stressor suite, one fixed-work launch each"}), flush=True)
@@ -1137,7 +1211,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="suite", choices=["suite", "sweep", "precision", "serve", "counters", "suite-counters",
                              "pollution", "bandwidth", "ilp", "pairs", "ldsstride", "estimator", "decode",
-                             "queues"])
+                             "queues", "hbm_mix"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--out", default=None, help="also write the JSON line(s) to this file")
     ap.add_argument("--reps", type=int, default=10, help="sweep / precision: repetitions per cell")
@@ -1186,6 +1260,8 @@ def main():
         run_decode(args)
     elif args.config == "queues":
         run_queues(args)
+    elif args.config == "hbm_mix":
+        run_hbm_mix(args)
 
 
 if __name__ == "__main__":
