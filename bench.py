@@ -48,8 +48,11 @@ HBM_KERNEL_SOURCES = [os.path.join("paper_2501_16909_amd", "csrc", f) for f in (
 # --------------------------------------------------------------------------
 def suite_resource(name: str) -> str:
     """Resource of a suite entry: the HBM mixes (hbm_read, ...) are the HBM
-    stressor with another knob."""
-    return "hbm" if name.startswith("hbm_") else name
+    stressor with another knob; *_32w entries are a stressor in its
+    32-waves-per-CU shape instead of its colocation default."""
+    if name.startswith("hbm_"):
+        return "hbm"
+    return name[:-4] if name.endswith("_32w") else name
 
 
 class Suite:
@@ -100,9 +103,11 @@ class Suite:
             ("hbm_copy", dict(src0=self.hb, dst=self.ha, n=n, passes=1, knob=mix["copy"]), "GB/s", 1e9),
             ("hbm_write", dict(dst=self.ha, n=n, passes=1, knob=mix["write"]), "GB/s", 1e9),
             ("l2", dict(src0=self.l2, n=1 << 19, passes=32), "TB/s", 1e12),
+            ("l2_32w", dict(src0=self.l2, n=1 << 19, passes=32, wg_per_cu=2, threads=1024), "TB/s", 1e12),
             ("mall", dict(src0=self.mall, n=1 << 25, passes=60), "TB/s", 1e12),
             ("vl1d", dict(src0=self.l1, n=1 << 12, passes=4000), "TB/s", 1e12),
             ("lds", dict(src0=self.win, passes=10), "TB/s", 1e12),
+            ("lds_32w", dict(src0=self.win, passes=10, wg_per_cu=2), "TB/s", 1e12),
             ("valu_f32", dict(dst=self.valu_out, iters=4096, passes=4, fa=1 - 2 ** -12, fb=2 ** -12), "TFLOP/s", 1e12),
             ("mfma_f32", dict(src0=self.mf["f32"][0], src1=self.mf["f32"][1], dst=self.mf_out, iters=2048, passes=2), "TFLOP/s", 1e12),
             ("mfma_bf16", dict(src0=self.mf["bf16"][0], src1=self.mf["bf16"][1], dst=self.mf_out, iters=2048, passes=2), "TFLOP/s", 1e12),
@@ -220,7 +225,8 @@ def run_suite(args):
         "data": "synthetic (SplitMix64 counter-form uniform [-1,1) / uint32 words / random cycle)",
         "config": {"workload": "stressor suite standalone: HBM triad FP32 N=2^30 (and its "
                                "read-only, copy and write-only mixes); L2 2 MiB; "
-                               "Infinity Cache 128 MiB; vL1D 16 KiB; LDS 64 KiB/WG; FP32 FMA 4096; "
+                               "Infinity Cache 128 MiB; vL1D 16 KiB; LDS 64 KiB/WG (L2 and LDS "
+                               "also at 32 waves/CU); FP32 FMA 4096; "
                                "MFMA FP32/BF16/FP8; uint32 chase over 2^24 cycle; 10^6 empty "
                                "64-thread WGs; plus colocated triad pair N=2^22",
                    "parallelism": "single GPU"},
