@@ -514,6 +514,13 @@ DUTIES = (10, 25, 50, 75, 100)
 # weights and writes one short vector, the triad writes one stream of three,
 # the GEMM writes an FP32 C as large as its BF16 A and B together.
 HBM_WRITE_FRAC = {"gemm": 0.5, "gemv": 0.0, "triad": 1.0 / 3.0}
+# Working set of each request kind at the profiled sizes (GEMM 2048^3 BF16 in,
+# FP32 out; GEMV 8192^2 BF16; triad three 2^24 FP32 arrays), against the
+# 256 MB Infinity Cache: a co-runner that fits is served from it when it
+# runs back to back, not from DRAM.
+KIND_FOOTPRINT = {"gemm": 2 * 2048 * 2048 * 2 + 2048 * 2048 * 4, "gemv": 8192 * 8192 * 2 + 8192 * 6,
+                  "triad": 3 * 4 * (1 << 24)}
+MALL_BYTES = 256 * 10 ** 6
 
 
 def serve_profiles(ctx, args, axis="cu", hbm_mix="triad", res=("hbm", "mfma_bf16", "lds")):
@@ -542,7 +549,8 @@ def serve_profiles(ctx, args, axis="cu", hbm_mix="triad", res=("hbm", "mfma_bf16
     ws = torch.empty(256 + 256 * 8 * 48, dtype=torch.uint8, device=dev)
     rates = {}
     duty_rates = {}
-    fixed = {"hbm": dict(passes=1), "mfma_bf16": dict(iters=2048, passes=2), "lds": dict(passes=4)}
+    fixed = {"hbm": dict(passes=1), "mfma_bf16": dict(iters=2048, passes=2), "lds": dict(passes=4),
+             "mall": dict(passes=60)}
     for r in res:
         extra = fixed[r]
         rep = ctx.stressor(r, 1.0, ws=ws, **ops[r], **extra).stop()
@@ -576,6 +584,8 @@ def serve_profiles(ctx, args, axis="cu", hbm_mix="triad", res=("hbm", "mfma_bf16
     gemm_lds = (g // 128) ** 2 * (g * 2 // 128) * (4 * 16384 + 32768)   # per stage: reads + writes
     use = {"gemm": {"mfma_bf16": 2.0 * g ** 3, "lds": gemm_lds, "hbm": 3.0 * 2 * g * g},
            "gemv": {"hbm": 2.0 * n * n}, "triad": {"hbm": 12.0 * t}}
+    for u in use.values():    # the same bytes, priced against the Infinity-Cache stressor
+        u["mall"] = u["hbm"]
     occ = {"gemm": min(1.0, (g // 128) ** 2 / (256 * 2)) * 8 / 32, "gemv": 1.0, "triad": 1.0}
     profiles = {}
     for kind, d in descs.items():
@@ -1033,16 +1043,20 @@ def run_queues(args):
     _emit(out, args)
 
 
-def predicted_pair_slowdown(profiles, a, b, read_profiles=None):
+def predicted_pair_slowdown(profiles, a, b, read_profiles=None, mall_profiles=None):
     """Product over resources of max(1, curve_A(pressure of B)).  With
     read_profiles (HBM curves and pressures against the read-only mix), a
     co-runner whose HBM traffic is mostly reads (write fraction below 1/6)
-    is priced on the read-only curve instead of the triad's."""
+    is priced on the read-only curve instead of the triad's.  With
+    mall_profiles, a co-runner whose working set fits the Infinity Cache is
+    priced on the curve against the Infinity-Cache stressor instead."""
     out = 1.0
     pts = np.array(INTENSITIES)
     for r, curve in profiles[a]["sens"].items():
         x = profiles[b]["press"].get(r, 0.0)
-        if r == "hbm" and read_profiles is not None and profiles[b]["hbm_write_frac"] < 1 / 6:
+        if r == "hbm" and mall_profiles is not None and KIND_FOOTPRINT[b] <= MALL_BYTES:
+            curve, x = mall_profiles[a]["sens"]["mall"], mall_profiles[b]["press"]["mall"]
+        elif r == "hbm" and read_profiles is not None and profiles[b]["hbm_write_frac"] < 1 / 6:
             curve, x = read_profiles[a]["sens"]["hbm"], read_profiles[b]["press"]["hbm"]
         x = min(1.0, max(0.0, x))
         out *= max(1.0, float(np.interp(x, pts, curve)))
@@ -1064,8 +1078,11 @@ def run_estimator(args):
     axes = {"cu": serve_profiles(ctx, args, axis="cu"), "duty": serve_profiles(ctx, args, axis="duty")}
     # HBM curves against the read-only mix, for read-mostly co-runners
     read_axes = {ax: serve_profiles(ctx, args, axis=ax, hbm_mix="read", res=("hbm",)) for ax in axes}
+    # curves against the Infinity-Cache stressor, for co-runners that fit it
+    mall_axes = {ax: serve_profiles(ctx, args, axis=ax, res=("mall",)) for ax in axes}
     log("profiles: " + json.dumps(axes))
     log("read-mix HBM profiles: " + json.dumps(read_axes))
+    log("Infinity-Cache profiles: " + json.dumps(mall_axes))
     # two independent instances of each kind (A's buffers and B's buffers)
     def make(kind, seed):
         if kind == "gemm":
@@ -1137,8 +1154,9 @@ def run_estimator(args):
             row = {"victim": a, "corunner": b, "measured": round(meas, 3),
                    "measured_trials": [round(t, 3) for t in trials], "stream_attempts": attempts}
             for ax, prof in axes.items():
-                for name, rp in ((ax, None), (ax + "_mix", read_axes[ax])):
-                    pred = predicted_pair_slowdown(prof, a, b, rp)
+                for name, rp, mp in ((ax, None, None), (ax + "_mix", read_axes[ax], None),
+                                     (ax + "_fit", read_axes[ax], mall_axes[ax])):
+                    pred = predicted_pair_slowdown(prof, a, b, rp, mp)
                     row[f"predicted_{name}"] = round(pred, 3)
                     row[f"rel_err_{name}"] = round(abs(pred - meas) / meas, 3)
             rows.append(row)
@@ -1146,7 +1164,7 @@ def run_estimator(args):
     rank = lambda v: np.argsort(np.argsort(v))
     m = np.array([r["measured"] for r in rows])
     summary = {}
-    for ax in [a for x in axes for a in (x, x + "_mix")]:
+    for ax in [a for x in axes for a in (x, x + "_mix", x + "_fit")]:
         err = np.array([r[f"rel_err_{ax}"] for r in rows])
         p = np.array([r[f"predicted_{ax}"] for r in rows])
         summary[ax] = {"mean_rel_err": round(float(err.mean()), 3), "max_rel_err": round(float(err.max()), 3),
@@ -1157,8 +1175,11 @@ def run_estimator(args):
                       "model": "product over HBM / BF16-MFMA / LDS of max(1, sensitivity curve at the "
                                "co-runner's standalone pressure); curves on two intensity axes: CU "
                                "fraction at full rate ('cu') and duty cycle on every CU ('duty'); "
-                               "'_mix': read-mostly co-runners priced on the read-only HBM curve"},
-           "pairs": rows, "axes": summary, "profiles": axes, "read_mix_profiles": read_axes}
+                               "'_mix': read-mostly co-runners priced on the read-only HBM curve; "
+                               "'_fit': also, co-runners whose working set fits the 256 MB Infinity "
+                               "Cache priced on the Infinity-Cache stressor's curve"},
+           "pairs": rows, "axes": summary, "profiles": axes, "read_mix_profiles": read_axes,
+           "mall_profiles": mall_axes}
     ctx.close()
     _emit(out, args)
 
