@@ -352,6 +352,8 @@ def run_sweep(args):
                 nan = lambda v: v != v
                 tab[r] = {"slowdown": [None if nan(c["slowdown"]) else round(c["slowdown"], 3) for c in row],
                           "p90": [None if nan(c["slowdown_p90"]) else round(c["slowdown_p90"], 3) for c in row],
+                          "ci95": [None if nan(c["slowdown_ci_lo"]) else
+                                   [round(c["slowdown_ci_lo"], 3), round(c["slowdown_ci_hi"], 3)] for c in row],
                           "stressor_pct_peak": [round(c["stressor_pct_peak"], 1) for c in row],
                           # a stressor that hit its deadline outlived the victim's
                           # starvation: the slowdown is then a lower bound

@@ -375,7 +375,26 @@ typedef struct ci_cell {
   int output_equal;           /* every colocated output checksum == alone      */
   int timed_out;
   int reps;
+  double slowdown_ci_lo;      /* percentile-bootstrap 95 % interval of the    */
+  double slowdown_ci_hi;      /* slowdown (ci_bootstrap_slowdown, 1000
+                                 resamples, seed 16909 + cell index)         */
 } ci_cell_t;
+
+/* Percentile-bootstrap confidence interval of the slowdown statistic
+ * median(col) / median(alone) (the sensitivity measure of Section 4.3; the
+ * paper reports no interval, so this is the reading used here).  Resample r
+ * (0 <= r < resamples) draws na alone times and then nc colocated times with
+ * replacement; draw j of resample r uses the counter-form SplitMix64 word
+ *   w_k = mix(seed + (k + 1) * 0x9E3779B97F4A7C15),  k = r * (na + nc) + j,
+ * (mix = the SplitMix64 output function) and picks index w_k mod na (alone,
+ * j < na) or w_k mod nc (colocated, j >= na, index j - na of that draw).
+ * Medians of even counts are the mean of the middle two.  *lo and *hi are
+ * the 2.5 % and 97.5 % quantiles of the resampled ratios, linearly
+ * interpolated between order statistics (position q * (resamples - 1)).
+ * Host arrays, caller-owned; pure host computation, no device needed.
+ * CI_ERR_INVALID_ARG on NULL pointers or zero counts. */
+ci_status_t ci_bootstrap_slowdown(const double* alone, uint32_t na, const double* col, uint32_t nc,
+                                  uint32_t resamples, uint64_t seed, double* lo, double* hi);
 
 /* For every resource rs[i] (operands in sopts[i]) and intensity xs[j]:
  * warm the victim up, then `reps` times run it alone and colocated with the

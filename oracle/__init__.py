@@ -21,6 +21,7 @@ Parity status per function (pins are in tests/test_oracle_pins.py):
   f32_to_bf16, f32_to_e4m3, quantize_fp8 ........ pinned
   gemm_f64, gemv_f64, mfma_tile_expected ........ pinned
   slowdown, pct_of_peak ......................... pinned (paper Table 1 values)
+  bootstrap_slowdown_ci ......................... pinned (closed-form resampling law)
   admit / simulate_admission .................... pinned
   decode (submodule: synthetic decode step) ..... pinned
 """
@@ -384,6 +385,26 @@ def slowdown(t_alone, t_coloc) -> float:
     """median(T_colocated) / median(T_alone)."""
     return float(np.median(np.asarray(t_coloc, np.float64)) /
                  np.median(np.asarray(t_alone, np.float64)))
+
+
+def bootstrap_slowdown_ci(alone, col, resamples: int = 1000, seed: int = 0) -> tuple:
+    """Percentile-bootstrap 95 % interval of median(col) / median(alone), the
+    slowdown of Section 4.3 (the paper gives no interval; this is the
+    reading the library implements).  Resample r draws len(alone) alone
+    times, then len(col) colocated times, with replacement; draw j of
+    resample r takes SplitMix64 word r*(na+nc) + j of stream `seed`, modulo
+    the sample size.  Quantiles 2.5 % / 97.5 %, linear between order
+    statistics."""
+    import synth
+    a = np.asarray(alone, dtype=np.float64)
+    c = np.asarray(col, dtype=np.float64)
+    na, nc = a.size, c.size
+    k = np.arange(resamples * (na + nc), dtype=np.uint64).reshape(resamples, na + nc)
+    w = synth.words_at(seed, k)
+    ia = (w[:, :na] % np.uint64(na)).astype(np.int64)
+    ic = (w[:, na:] % np.uint64(nc)).astype(np.int64)
+    ratios = np.median(c[ic], axis=1) / np.median(a[ia], axis=1)
+    return float(np.quantile(ratios, 0.025)), float(np.quantile(ratios, 0.975))
 
 
 def pct_of_peak(achieved: float, peak: float) -> float:

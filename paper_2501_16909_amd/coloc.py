@@ -92,7 +92,8 @@ class Cell(C.Structure):
                 ("slowdown_p90", C.c_double), ("t_alone_ns", C.c_double),
                 ("t_col_ns", C.c_double), ("stressor_achieved", C.c_double),
                 ("stressor_pct_peak", C.c_double), ("window_covered", C.c_int),
-                ("output_equal", C.c_int), ("timed_out", C.c_int), ("reps", C.c_int)]
+                ("output_equal", C.c_int), ("timed_out", C.c_int), ("reps", C.c_int),
+                ("slowdown_ci_lo", C.c_double), ("slowdown_ci_hi", C.c_double)]
 
 
 class Profile(C.Structure):
@@ -179,6 +180,9 @@ EXPORTS = {
     "ci_probe_placement": ([C.c_void_p, C.POINTER(C.c_uint32), C.c_uint32, C.c_void_p], C.c_int),
     "ci_queue_stats": ([C.c_void_p, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)],
                        C.c_int),
+    "ci_bootstrap_slowdown": ([C.POINTER(C.c_double), C.c_uint32, C.POINTER(C.c_double), C.c_uint32,
+                               C.c_uint32, C.c_uint64, C.POINTER(C.c_double), C.POINTER(C.c_double)],
+                              C.c_int),
     "ci_workspace_size": ([C.c_int, C.POINTER(StressorOpts), C.c_int, C.POINTER(C.c_size_t)], C.c_int),
     "stressor_launch": ([C.c_void_p, C.c_int, C.c_float, C.c_void_p, C.POINTER(StressorOpts),
                          C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)], C.c_int),
@@ -288,6 +292,18 @@ def _report(r: StressorReport, st: int) -> Report:
                   r.t_last_start, r.t_first_end, r.t_last_end, r.window_ns, r.kernel_ns, r.work,
                   r.units, r.achieved, r.pct_of_peak, r.checksum, bool(r.timed_out), r.distinct_cus,
                   st)
+
+
+def bootstrap_slowdown(alone, col, resamples: int = 1000, seed: int = 0) -> tuple:
+    """(lo, hi): the library's percentile-bootstrap 95 % interval of
+    median(col) / median(alone) (host computation)."""
+    a = np.ascontiguousarray(alone, dtype=np.float64)
+    c = np.ascontiguousarray(col, dtype=np.float64)
+    lo, hi = C.c_double(), C.c_double()
+    _check(load_library().ci_bootstrap_slowdown(a.ctypes.data_as(C.POINTER(C.c_double)), a.size,
+                                                c.ctypes.data_as(C.POINTER(C.c_double)), c.size,
+                                                int(resamples), int(seed), C.byref(lo), C.byref(hi)))
+    return lo.value, hi.value
 
 
 def make_opts(**kw) -> StressorOpts:

@@ -1194,6 +1194,32 @@ double ci::quantile(std::vector<double> v, double q) {
 
 
 namespace {
+uint64_t sm64_word(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+}  // namespace
+
+extern "C" ci_status_t ci_bootstrap_slowdown(const double* alone, uint32_t na, const double* col,
+                                             uint32_t nc, uint32_t resamples, uint64_t seed,
+                                             double* lo, double* hi) {
+  if (!alone || !col || !lo || !hi || na == 0 || nc == 0 || resamples == 0)
+    return set_err(CI_ERR_INVALID_ARG, "ci_bootstrap_slowdown: NULL pointer or zero count");
+  std::vector<double> ratios(resamples), ra(na), rc(nc);
+  for (uint32_t r = 0; r < resamples; ++r) {
+    const uint64_t k0 = (uint64_t)r * (na + nc);
+    for (uint32_t j = 0; j < na; ++j) ra[j] = alone[sm64_word(seed, k0 + j) % na];
+    for (uint32_t j = 0; j < nc; ++j) rc[j] = col[sm64_word(seed, k0 + na + j) % nc];
+    ratios[r] = median(rc) / median(ra);
+  }
+  *lo = quantile(ratios, 0.025);
+  *hi = quantile(ratios, 0.975);
+  return CI_OK;
+}
+
+namespace {
 struct VictimRun {
   ci_ctx* ctx;
   const ci_victim_desc_t* d;
@@ -1244,6 +1270,7 @@ extern "C" ci_status_t measure_sensitivity(ci_ctx_t* ctx, const ci_victim_desc_t
       if (masked) {
         if (k >= ctx->info.num_cus) {  // no CUs left for the victim
           cell.slowdown = cell.slowdown_p10 = cell.slowdown_p90 = NAN;
+          cell.slowdown_ci_lo = cell.slowdown_ci_hi = NAN;
           continue;
         }
         mask_for(ctx, k, 1, vmask);
@@ -1314,6 +1341,11 @@ extern "C" ci_status_t measure_sensitivity(ci_ctx_t* ctx, const ci_victim_desc_t
       cell.slowdown = cell.t_col_ns / cell.t_alone_ns;
       cell.slowdown_p10 = quantile(ratio, 0.1);
       cell.slowdown_p90 = quantile(ratio, 0.9);
+      cell.slowdown_ci_lo = cell.slowdown_ci_hi = NAN;
+      if (nrep)
+        (void)ci_bootstrap_slowdown(ta.data(), (uint32_t)ta.size(), tc.data(), (uint32_t)tc.size(),
+                                    1000, 16909ull + (uint64_t)(&cell - cells), &cell.slowdown_ci_lo,
+                                    &cell.slowdown_ci_hi);
       cell.stressor_achieved = nrep ? ach / nrep : 0.0;
       cell.stressor_pct_peak = nrep ? pct / nrep : 0.0;
       cell.window_covered = covered;

@@ -139,3 +139,19 @@ def test_decode_layout_rejects_bad_configs(bad):
     with pytest.raises(coloc.CiError) as ei:
         coloc.Context.decode_layout(dict(LLAMA8B, **bad))
     assert ei.value.status == 1
+
+
+def test_bootstrap_interval_matches_oracle():
+    """The library's bootstrap interval (host code, no device) against the
+    oracle's on seeded samples of odd and even sizes."""
+    rng = np.random.default_rng(5)
+    for na, nc, seed in ((20, 20, 0), (7, 12, 16909), (1, 9, 3), (41, 41, 123456789)):
+        a = 100.0 + rng.standard_normal(na)
+        c = 150.0 + 5 * rng.standard_normal(nc)
+        got = coloc.bootstrap_slowdown(a, c, 1000, seed)
+        want = oracle.bootstrap_slowdown_ci(a, c, 1000, seed)
+        assert got == pytest.approx(want, rel=1e-12), (na, nc, seed)
+    with pytest.raises(coloc.CiError) as ei:
+        coloc.bootstrap_slowdown([], [1.0])
+    assert ei.value.status == 1
+

@@ -258,6 +258,11 @@ def test_zero_intensity_invariant(ctx, dev):
                                     reps=41, warmups=20)
     z, full = cells
     assert abs(z["slowdown"] - 1.0) <= 0.02, z
+    # bootstrap interval of each cell: ordered, and at zero intensity it
+    # reaches 1.00 within the invariant's tolerance
+    for cell in cells:
+        assert cell["slowdown_ci_lo"] <= cell["slowdown_ci_hi"], cell
+    assert z["slowdown_ci_lo"] <= 1.02 and z["slowdown_ci_hi"] >= 0.98, z
     assert z["output_equal"] and full["output_equal"]
     assert full["window_covered"], full
     assert full["slowdown"] > 1.1, full

@@ -367,6 +367,20 @@ def _job(sens1, press, nbytes=1, occ=0.1):
     return {"sens": curves, "press": press, "bytes": nbytes, "occ": occ}
 
 
+def test_bootstrap_ci_closed_forms():
+    # constant samples: every resample gives the same ratio
+    assert oracle.bootstrap_slowdown_ci([2.0] * 5, [3.0] * 4, 200, 1) == (1.5, 1.5)
+    assert oracle.bootstrap_slowdown_ci([8.0], [2.0], 50, 3) == (0.25, 0.25)
+    # alone {1, 2, 10}, colocated {4}: the median of three draws is 1 or 10
+    # with probability 7/27 each, else 2, so ratios are 4, 2 or 0.4 and the
+    # 2.5 % / 97.5 % quantiles of 1000 resamples sit on 0.4 and 4 (a mean
+    # instead of the median, or swapped samples, would move them)
+    lo, hi = oracle.bootstrap_slowdown_ci([1.0, 2.0, 10.0], [4.0], 1000, 7)
+    assert (lo, hi) == (0.4, 4.0)
+    # draws use the counter-form generator: a different seed, same law
+    assert oracle.bootstrap_slowdown_ci([1.0, 2.0, 10.0], [4.0], 1000, 8) == (0.4, 4.0)
+
+
 def test_admission_rules():
     quiet = _job([1.0, 1.0], [0.0, 0.0])
     hog = _job([1.0, 1.0], [1.0, 0.0], occ=0.6)
