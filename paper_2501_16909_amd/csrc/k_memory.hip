@@ -229,10 +229,9 @@ __global__ void __launch_bounds__(256) triad_victim(const float* __restrict__ b,
 // four loads in flight; every word of the span is read exactly once per pass.
 // record.work = passes, record.check = sum of the words read, mod 2^32.
 // Span length must be a multiple of 4 * blockDim.x words (checked on the host).
-// U loads per thread are kept in flight: 8 for the cache-resident regions
-// (L2, vL1D), where more requests in flight raise the hit bandwidth, and 4
-// for the Infinity-Cache slices, where 8 measured slower.
-template <int U>
+// Four loads per thread in flight: eight raise the L2 rate by 1-2 % of peak
+// but also fill the CU's memory pipeline, so a victim sharing the CUs loses
+// several times more to the pipeline than to the L2 itself.
 __global__ void __launch_bounds__(1024) cache_stressor(KCtrl c, const uint32_t* __restrict__ region,
                                                        uint64_t region_words, uint64_t slice_words,
                                                        uint32_t batch) {
@@ -269,12 +268,12 @@ __global__ void __launch_bounds__(1024) cache_stressor(KCtrl c, const uint32_t* 
       for (int part = 0; part < 2; ++part) {
         uint32_t r = part ? 0u : phase;
         const uint32_t end = part ? phase : rounds;
-        for (; r + U <= end; r += U) {
-          uint4 v[U];
+        for (; r + 4 <= end; r += 4) {
+          uint4 v[4];
 #pragma unroll
-          for (int u = 0; u < U; ++u) v[u] = base[(uint64_t)(r + u) * stride];
+          for (int u = 0; u < 4; ++u) v[u] = base[(uint64_t)(r + u) * stride];
 #pragma unroll
-          for (int u = 0; u < U; ++u) acc += v[u].x + v[u].y + v[u].z + v[u].w;
+          for (int u = 0; u < 4; ++u) acc += v[u].x + v[u].y + v[u].z + v[u].w;
         }
         for (; r < end; ++r) {
           const uint4 v = base[(uint64_t)r * stride];
@@ -355,11 +354,8 @@ hipError_t launch_triad_victim(const float* b, const float* c, float* a, uint64_
 hipError_t launch_cache_stressor(const KCtrl& c, const uint32_t* region, uint64_t region_words,
                                  uint64_t slice_words, uint32_t batch, uint32_t threads,
                                  hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  if (slice_words)
-    return xlaunch(cache_stressor<4>, dim3(c.grid), dim3(threads), 0, s, e0, e1, c, region,
-                   region_words, slice_words, batch);
-  return xlaunch(cache_stressor<8>, dim3(c.grid), dim3(threads), 0, s, e0, e1, c, region,
-                 region_words, slice_words, batch);
+  return xlaunch(cache_stressor, dim3(c.grid), dim3(threads), 0, s, e0, e1, c,
+                               region, region_words, slice_words, batch);
 }
 
 }  // namespace ci
