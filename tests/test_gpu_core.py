@@ -241,6 +241,31 @@ def test_hbm_read_mix_full_size_closed_form(ctx, dev):
     torch.cuda.empty_cache()
 
 
+def test_hbm_mixes_colocated(ctx, dev):
+    """Persistent read-only and write-only mixes beside a triad victim: every
+    colocated run inside the stressor window, outputs equal to the alone
+    run, and the stressor's own rate reported per cell."""
+    import torch
+    from paper_2501_16909_amd import coloc
+    n = 1 << 22
+    tb = _t(synth.uniform_f32(synth.seed_for(0, synth.BUF_B), n), dev)
+    tc = _t(synth.uniform_f32(synth.seed_for(0, synth.BUF_C), n), dev)
+    ta = torch.empty_like(tb)
+    d = ctx.triad_desc(tb, tc, ta, passes=8)
+    m = 1 << 26
+    sb, sc, sa = (torch.empty(m, dtype=torch.float32, device=dev) for _ in range(3))
+    synth.device_fill_uniform_f32(sb.data_ptr(), m, synth.seed_for(4, synth.BUF_B2))
+    synth.device_fill_uniform_f32(sc.data_ptr(), m, synth.seed_for(4, synth.BUF_C2))
+    torch.cuda.synchronize()
+    opts = [dict(src0=sb, src1=sc, n=m, knob=coloc.HBM_MIX["read"]),
+            dict(dst=sa, n=m, knob=coloc.HBM_MIX["write"])]
+    cells = ctx.measure_sensitivity(d, ["hbm", "hbm"], opts, [0.5], reps=8, warmups=2)
+    for cell in cells:
+        assert cell["output_equal"] and cell["window_covered"] and not cell["timed_out"], cell
+        assert cell["stressor_achieved"] > 1e12 and cell["slowdown"] > 1.02, cell
+    print("read / write mix at 0.5:", [round(c["slowdown"], 3) for c in cells])
+
+
 def test_zero_intensity_invariant(ctx, dev):
     """A stressor at intensity 0 launches nothing: slowdown 1.00 +- 0.02."""
     import torch
