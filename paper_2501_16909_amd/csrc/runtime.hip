@@ -1209,7 +1209,7 @@ extern "C" ci_status_t ci_bootstrap_slowdown(const double* alone, uint32_t na, c
     return set_err(CI_ERR_INVALID_ARG, "ci_bootstrap_slowdown: NULL pointer or zero count");
   std::vector<double> ratios(resamples), ra(na), rc(nc);
   for (uint32_t r = 0; r < resamples; ++r) {
-    const uint64_t k0 = (uint64_t)r * (na + nc);
+    const uint64_t k0 = (uint64_t)r * ((uint64_t)na + nc);
     for (uint32_t j = 0; j < na; ++j) ra[j] = alone[sm64_word(seed, k0 + j) % na];
     for (uint32_t j = 0; j < nc; ++j) rc[j] = col[sm64_word(seed, k0 + na + j) % nc];
     ratios[r] = median(rc) / median(ra);
