@@ -1047,6 +1047,19 @@ def run_queues(args):
     _emit(out, args)
 
 
+def median_profiles(runs):
+    """Point-wise median of several profile measurements (curves and
+    pressures); the other fields come from the first run."""
+    out = {}
+    for kind, first in runs[0].items():
+        p = dict(first)
+        p["sens"] = {r: [float(np.median([run[kind]["sens"][r][i] for run in runs])) for i in range(len(curve))]
+                     for r, curve in first["sens"].items()}
+        p["press"] = {r: float(np.median([run[kind]["press"][r] for run in runs])) for r in first["press"]}
+        out[kind] = p
+    return out
+
+
 def predicted_pair_slowdown(profiles, a, b, read_profiles=None, mall_profiles=None):
     """Product over resources of max(1, curve_A(pressure of B)).  With
     read_profiles (HBM curves and pressures against the read-only mix), a
@@ -1079,11 +1092,15 @@ def run_estimator(args):
     from paper_2501_16909_amd import coloc
     ctx = coloc.Context(0)
     dev = ctx.device
-    axes = {"cu": serve_profiles(ctx, args, axis="cu"), "duty": serve_profiles(ctx, args, axis="duty")}
+    def profiles(**kw):
+        # the point-wise median over --profile-runs independent measurements
+        runs = [serve_profiles(ctx, args, **kw) for _ in range(max(1, args.profile_runs))]
+        return median_profiles(runs)
+    axes = {"cu": profiles(axis="cu"), "duty": profiles(axis="duty")}
     # HBM curves against the read-only mix, for read-mostly co-runners
-    read_axes = {ax: serve_profiles(ctx, args, axis=ax, hbm_mix="read", res=("hbm",)) for ax in axes}
+    read_axes = {ax: profiles(axis=ax, hbm_mix="read", res=("hbm",)) for ax in axes}
     # curves against the Infinity-Cache stressor, for co-runners that fit it
-    mall_axes = {ax: serve_profiles(ctx, args, axis=ax, res=("mall",)) for ax in axes}
+    mall_axes = {ax: profiles(axis=ax, res=("mall",)) for ax in axes}
     log("profiles: " + json.dumps(axes))
     log("read-mix HBM profiles: " + json.dumps(read_axes))
     log("Infinity-Cache profiles: " + json.dumps(mall_axes))
@@ -1182,6 +1199,7 @@ def run_estimator(args):
                                "'_mix': read-mostly co-runners priced on the read-only HBM curve; "
                                "'_fit': also, co-runners whose working set fits the 256 MB Infinity "
                                "Cache priced on the Infinity-Cache stressor's curve"},
+           "profile_runs": max(1, args.profile_runs),
            "pairs": rows, "axes": summary, "profiles": axes, "read_mix_profiles": read_axes,
            "mall_profiles": mall_axes}
     ctx.close()
@@ -1255,6 +1273,8 @@ def main():
     ap.add_argument("--profiles", default=None, help="serve: sensitivity profiles (JSON)")
     ap.add_argument("--batch", type=int, default=1, help="decode: sequences per step (1..8)")
     ap.add_argument("--contexts", type=int, default=6, help="queues: fresh contexts (queue orders) to try")
+    ap.add_argument("--profile-runs", type=int, default=1,
+                    help="estimator: profile measurements per curve, combined point-wise by the median")
     ap.add_argument("--profile-axis", default="duty", choices=["cu", "duty"],
                     help="serve: intensity axis of measured profiles (CU fraction or duty cycle)")
     args = ap.parse_args()
