@@ -632,13 +632,14 @@ def run_serve(args):
         with open(args.profiles) as f:
             profiles = json.load(f)
     else:
-        profiles = serve_profiles(ctx, args, axis=args.profile_axis)
+        profiles = median_profiles([serve_profiles(ctx, args, axis=args.profile_axis)
+                                    for _ in range(max(1, args.profile_runs))])
         log("profiles: " + json.dumps(profiles))
     out = {"metric": "serving latency p50/p99 and throughput, naive vs sensitivity-aware admission",
            "config": {"workload": "Poisson arrivals, 1/3 each BF16 GEMM n~logU[512,8192], BF16 GEMV "
                                   "n~logU[4096,16384], FP32 triad N~logU[2^20,2^28]",
                       "seconds": args.seconds, "slots": 4, "hbm_budget_gib": 32,
-                      "profile_axis": args.profile_axis},
+                      "profile_axis": args.profile_axis, "profile_runs": max(1, args.profile_runs)},
            "runs": []}
     iso_cache = {}
     for lam in args.rates:
@@ -1274,7 +1275,7 @@ def main():
     ap.add_argument("--batch", type=int, default=1, help="decode: sequences per step (1..8)")
     ap.add_argument("--contexts", type=int, default=6, help="queues: fresh contexts (queue orders) to try")
     ap.add_argument("--profile-runs", type=int, default=1,
-                    help="estimator: profile measurements per curve, combined point-wise by the median")
+                    help="estimator / serve: profile measurements per curve, combined point-wise by the median")
     ap.add_argument("--profile-axis", default="duty", choices=["cu", "duty"],
                     help="serve: intensity axis of measured profiles (CU fraction or duty cycle)")
     args = ap.parse_args()
