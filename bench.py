@@ -10,7 +10,11 @@ triad pair (victim and stressor both a = b + 3c over N = 2^22).  `value` is
 the HBM stressor's bandwidth; every stressor's rate and fraction of peak and
 the pair's slowdown ride along in the same line.
 
-Other workloads (their own JSON lines): --config sweep | precision | serve.
+Other workloads, each its own JSON line(s), with --config: sweep,
+precision, serve, pollution, bandwidth, ilp, pairs, ldsstride, estimator,
+decode, queues, hbm_mix; counters and suite-counters are short runs for
+hardware-counter passes.  One GPU only: --gpus N with N > 1 exits with a
+message.
 """
 from __future__ import annotations
 

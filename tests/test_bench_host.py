@@ -1,0 +1,69 @@
+"""Host logic of the benchmark driver (no device): suite bookkeeping, the
+profile combination and the pairwise slowdown model used by the estimator
+and serving configurations, and the one-GPU guard."""
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_suite_entries_map_to_resources():
+    assert bench.suite_resource("hbm") == "hbm"
+    assert [bench.suite_resource(n) for n in ("hbm_read", "hbm_copy", "hbm_write")] == ["hbm"] * 3
+    assert bench.suite_resource("l2_32w") == "l2" and bench.suite_resource("lds_32w") == "lds"
+    assert bench.suite_resource("mfma_bf16") == "mfma_bf16"
+
+
+def _prof(hbm, press, wf=0.0):
+    return {"sens": {"hbm": list(hbm)}, "press": {"hbm": press}, "occ": 1.0, "hbm_write_frac": wf}
+
+
+def test_median_profiles_is_pointwise():
+    runs = [{"k": _prof([1, 1.2, 1.5, 1.6, 2.0], 0.9)}, {"k": _prof([1, 1.4, 1.7, 1.9, 2.4], 0.7)},
+            {"k": _prof([1, 1.3, 2.0, 1.7, 2.2], 0.8)}]
+    m = bench.median_profiles(runs)["k"]
+    assert m["sens"]["hbm"] == [1.0, 1.3, 1.7, 1.7, 2.2] and m["press"]["hbm"] == 0.8
+    assert m["hbm_write_frac"] == 0.0 and m["occ"] == 1.0
+
+
+def test_pair_model_product_and_pricing_switches():
+    x = bench.INTENSITIES                   # 0, .25, .5, .75, 1
+    base = {"v": _prof([1, 1.5, 2, 2.5, 3], 0.0, 1 / 3),
+            "reader": _prof([1, 1, 1, 1, 1], 0.5, 0.0),
+            "writer": _prof([1, 1, 1, 1, 1], 1.0, 1 / 3)}
+    # interpolated on the victim's curve at the co-runner's pressure
+    assert bench.predicted_pair_slowdown(base, "v", "reader") == 2.0
+    assert bench.predicted_pair_slowdown(base, "v", "writer") == 3.0
+    # read-mostly co-runners switch to the read-only curve and pressure
+    read = {"v": _prof([1, 1.1, 1.2, 1.3, 1.4], 0.0), "reader": _prof([1] * 5, 0.25), "writer": _prof([1] * 5, 0.9)}
+    assert np.isclose(bench.predicted_pair_slowdown(base, "v", "reader", read), 1.1)
+    assert bench.predicted_pair_slowdown(base, "v", "writer", read) == 3.0
+    # a co-runner that fits the Infinity Cache is priced on that curve
+    mall = {k: {"sens": {"mall": [1, 1.05, 1.1, 1.15, 1.2]}, "press": {"mall": 0.5}} for k in base}
+    fits = dict(bench.KIND_FOOTPRINT)
+    try:
+        bench.KIND_FOOTPRINT.update({"v": 1, "reader": 1, "writer": 1})
+        assert np.isclose(bench.predicted_pair_slowdown(base, "v", "writer", read, mall), 1.1)
+        bench.KIND_FOOTPRINT.update({"writer": 10 ** 12})
+        assert bench.predicted_pair_slowdown(base, "v", "writer", read, mall) == 3.0
+    finally:
+        bench.KIND_FOOTPRINT.clear()
+        bench.KIND_FOOTPRINT.update(fits)
+    # never below 1 on any resource
+    low = {"v": _prof([0.9] * 5, 0.0), "w": _prof([1] * 5, 1.0, 0.5)}
+    assert bench.predicted_pair_slowdown(low, "v", "w") == 1.0
+    assert len(x) == 5
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]
