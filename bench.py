@@ -113,6 +113,7 @@ class Suite:
             ("lds", dict(src0=self.win, passes=10), "TB/s", 1e12),
             ("lds_32w", dict(src0=self.win, passes=10, wg_per_cu=2), "TB/s", 1e12),
             ("valu_f32", dict(dst=self.valu_out, iters=4096, passes=4, fa=1 - 2 ** -12, fb=2 ** -12), "TFLOP/s", 1e12),
+            ("valu_f64", dict(dst=self.valu_out, iters=4096, passes=4, fa=1 - 2 ** -12), "TFLOP/s", 1e12),
             ("mfma_f32", dict(src0=self.mf["f32"][0], src1=self.mf["f32"][1], dst=self.mf_out, iters=2048, passes=2), "TFLOP/s", 1e12),
             ("mfma_bf16", dict(src0=self.mf["bf16"][0], src1=self.mf["bf16"][1], dst=self.mf_out, iters=2048, passes=2), "TFLOP/s", 1e12),
             ("mfma_fp8", dict(src0=self.mf["fp8"][0], src1=self.mf["fp8"][1], dst=self.mf_out, iters=2048, passes=2), "TFLOP/s", 1e12),
@@ -230,7 +231,7 @@ def run_suite(args):
         "config": {"workload": "stressor suite standalone: HBM triad FP32 N=2^30 (and its "
                                "read-only, copy and write-only mixes); L2 2 MiB; "
                                "Infinity Cache 128 MiB; vL1D 16 KiB; LDS 64 KiB/WG (L2 and LDS "
-                               "also at 32 waves/CU); FP32 FMA 4096; "
+                               "also at 32 waves/CU); FP32 FMA and FP64 multiply chains 4096; "
                                "MFMA FP32/BF16/FP8; uint32 chase over 2^24 cycle; 10^6 empty "
                                "64-thread WGs; plus colocated triad pair N=2^22",
                    "parallelism": "single GPU"},
