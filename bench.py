@@ -121,9 +121,11 @@ class Suite:
             ("dispatch", dict(iters=1000000, passes=1), "MWG/s", 1e6),
         ]
 
-    def step(self, acc):
+    def step(self, acc, warm: int = 0):
         for name, opts, unit, scale in self.items:
             res = suite_resource(name)
+            for _ in range(warm):   # untimed launches of the same stressor first
+                self.ctx.stressor(res, 1.0, ws=self.ws, **opts).stop()
             st = self.ctx.stressor(res, 1.0, ws=self.ws, **opts)
             rep = st.stop()
             rate = rep.units / (rep.kernel_ns * 1e-9)
@@ -185,12 +187,12 @@ def run_suite(args):
     log("setup done")
     warm = {}
     for i in range(args.warmup):
-        suite.step(warm)
+        suite.step(warm, args.stressor_warmup)
     acc = {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        suite.step(acc)
+        suite.step(acc, args.stressor_warmup)
         log(f"step {i + 1}/{args.steps} done")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -1268,6 +1270,8 @@ def main():
                              "pollution", "bandwidth", "ilp", "pairs", "ldsstride", "estimator", "decode",
                              "queues", "hbm_mix"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--stressor-warmup", type=int, default=0,
+                    help="suite: untimed launches of each stressor right before its timed one")
     ap.add_argument("--out", default=None, help="also write the JSON line(s) to this file")
     ap.add_argument("--reps", type=int, default=10, help="sweep / precision: repetitions per cell")
     ap.add_argument("--deadline-ms", type=int, default=200,
