@@ -69,6 +69,11 @@ def test_intensity_masks_are_balanced(ctx, x):
     comp, nc = ctx.cu_mask(x, complement=True)
     lc = set(ctx.probe_placement(comp, 16384).tolist())
     assert len(lc) == nc and not (lc & cus)
+    # within each XCD the CUs spread over its shader engines as evenly as
+    # the count allows, for the mask and its complement alike
+    for sel in (cus, lc):
+        per_se = np.bincount([((c >> 8) & 0xF) * 4 + ((c >> 5) & 3) for c in sel], minlength=32)
+        assert per_se.max() - per_se.min() <= 1, per_se
 
 
 def test_device_fill_matches_host_generator(ctx, dev):
