@@ -12,8 +12,8 @@ the pair's slowdown ride along in the same line.
 
 Other workloads, each its own JSON line(s), with --config: sweep,
 precision, serve, pollution, bandwidth, ilp, pairs, ldsstride, estimator,
-decode, queues, hbm_mix; counters and suite-counters are short runs for
-hardware-counter passes.  One GPU only: --gpus N with N > 1 exits with a
+decode, queues, hbm_mix; counters, suite-counters and gemm-counters are
+short runs for hardware-counter passes.  One GPU only: --gpus N with N > 1 exits with a
 message.
 """
 from __future__ import annotations
@@ -1229,6 +1229,31 @@ def run_suite_counters(args):
     print(json.dumps({"counters_run": "stressor suite, one fixed-work launch each"}), flush=True)
 
 
+def run_gemm_counters(args):
+    """Short run for hardware-counter passes on the GEMM victim: BF16
+    M = N = K = 4096 (the sweep's GEMM shape, uniform inputs), three launches."""
+    import torch
+    import synth
+    from paper_2501_16909_amd import coloc
+    dev = torch.device("cuda:0")
+    ctx = coloc.Context(0)
+    g = 4096
+    a = torch.empty(g * g, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    synth.device_fill_uniform_f32(a.data_ptr(), g * g, synth.seed_for(2, synth.BUF_GEMM_A))
+    synth.device_fill_uniform_f32(b.data_ptr(), g * g, synth.seed_for(2, synth.BUF_GEMM_B))
+    torch.cuda.synchronize()
+    qa, sa = ctx.quantize(a, "bf16")
+    qb, sb = ctx.quantize(b, "bf16")
+    c = torch.empty((g, g), dtype=torch.float32, device=dev)
+    d = ctx.gemm_desc(qa.view(g, g), qb.view(g, g), c, "bf16", g, g, g, sa, sb)
+    for _ in range(3):
+        r = ctx.victim_run(d)
+        log(f"gemm bf16 4096^3: {2.0 * g ** 3 / r.time_ns / 1e3:.1f} TF")
+    ctx.close()
+    print(json.dumps({"counters_run": "gemm bf16 4096^3 x3"}), flush=True)
+
+
 def run_counters(args):
     """Short run for hardware-counter passes: the HBM stressor over N = 2^30
     (one pass per launch) twice, its read-only, copy and write-only mixes
@@ -1268,7 +1293,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="suite", choices=["suite", "sweep", "precision", "serve", "counters", "suite-counters",
                              "pollution", "bandwidth", "ilp", "pairs", "ldsstride", "estimator", "decode",
-                             "queues", "hbm_mix"])
+                             "queues", "hbm_mix", "gemm-counters"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stressor-warmup", type=int, default=0,
                     help="suite: untimed launches of each stressor right before its timed one")
@@ -1323,6 +1348,8 @@ def main():
         run_queues(args)
     elif args.config == "hbm_mix":
         run_hbm_mix(args)
+    elif args.config == "gemm-counters":
+        run_gemm_counters(args)
 
 
 if __name__ == "__main__":
