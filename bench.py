@@ -31,6 +31,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = ("victim slowdown per resource vs intensity; stressor % of peak (HBM GB/s, TFLOPS)")
+# stressor workspace: control words and records for up to 16 work-groups per CU on 256 CUs
+WS_BYTES = 4096 + 256 * 16 * 48
 
 
 def log(*a):
@@ -56,6 +58,8 @@ def suite_resource(name: str) -> str:
     32-waves-per-CU shape instead of its colocation default."""
     if name.startswith("hbm_"):
         return "hbm"
+    if name.startswith("mall_"):
+        return "mall"
     return name[:-4] if name.endswith("_32w") else name
 
 
@@ -75,11 +79,15 @@ class Suite:
         synth.device_fill_uniform_f32(self.hb.data_ptr(), n, synth.seed_for(1, synth.BUF_B))
         synth.device_fill_uniform_f32(self.hc.data_ptr(), n, synth.seed_for(1, synth.BUF_C))
         self.l2 = torch.empty(1 << 19, dtype=torch.int32, device=dev)
-        self.mall = torch.empty(1 << 25, dtype=torch.int32, device=dev)
         self.l1 = torch.empty(1 << 12, dtype=torch.int32, device=dev)
         synth.device_fill_u32(self.l2.data_ptr(), 1 << 19, synth.seed_for(1, synth.BUF_CACHE))
-        synth.device_fill_u32(self.mall.data_ptr(), 1 << 25, synth.seed_for(1, synth.BUF_CACHE) + 1)
         synth.device_fill_u32(self.l1.data_ptr(), 1 << 12, synth.seed_for(1, synth.BUF_CACHE) + 2)
+        # Infinity Cache: two 64 MiB arrays (128 MiB, 16 MiB per XCD slot) and an output
+        self.n_mall = 1 << 24
+        self.mb = torch.empty(self.n_mall, dtype=torch.float32, device=dev)
+        self.mc, self.ma = torch.empty_like(self.mb), torch.empty_like(self.mb)
+        synth.device_fill_uniform_f32(self.mb.data_ptr(), self.n_mall, synth.seed_for(1, synth.BUF_CACHE) + 1)
+        synth.device_fill_uniform_f32(self.mc.data_ptr(), self.n_mall, synth.seed_for(1, synth.BUF_CACHE) + 3)
         self.win = T(synth.u32(synth.seed_for(1, synth.BUF_LDS), 8192).view(np.int32))
         self.valu_out = torch.empty(256 * 4 * 256 * 8, dtype=torch.float32, device=dev)
         ones = {"f32": (np.ones((32, 2), np.float32), np.ones((2, 32), np.float32)),
@@ -99,7 +107,7 @@ class Suite:
                      (self.sc, synth.BUF_C2)):
             synth.device_fill_uniform_f32(t.data_ptr(), m, synth.seed_for(0, s))
         torch.cuda.synchronize()
-        self.ws = torch.empty(256 + 256 * 8 * 48, dtype=torch.uint8, device=dev)
+        self.ws = torch.empty(WS_BYTES, dtype=torch.uint8, device=dev)
         from paper_2501_16909_amd.coloc import HBM_MIX as mix
         self.items = [
             ("hbm", dict(src0=self.hb, src1=self.hc, dst=self.ha, n=n, passes=1), "GB/s", 1e9),
@@ -108,7 +116,8 @@ class Suite:
             ("hbm_write", dict(dst=self.ha, n=n, passes=1, knob=mix["write"]), "GB/s", 1e9),
             ("l2", dict(src0=self.l2, n=1 << 19, passes=32), "TB/s", 1e12),
             ("l2_32w", dict(src0=self.l2, n=1 << 19, passes=32, wg_per_cu=2, threads=1024), "TB/s", 1e12),
-            ("mall", dict(src0=self.mall, n=1 << 25, passes=60), "TB/s", 1e12),
+            ("mall", dict(src0=self.mb, src1=self.mc, n=self.n_mall, passes=60), "TB/s", 1e12),
+            ("mall_write", dict(dst=self.ma, n=self.n_mall, passes=240, knob=mix["write"]), "TB/s", 1e12),
             ("vl1d", dict(src0=self.l1, n=1 << 12, passes=4000), "TB/s", 1e12),
             ("lds", dict(src0=self.win, passes=10), "TB/s", 1e12),
             ("lds_32w", dict(src0=self.win, passes=10, wg_per_cu=2), "TB/s", 1e12),
@@ -268,10 +277,14 @@ def stressor_operands(dev):
     synth.device_fill_uniform_f32(hb.data_ptr(), n, synth.seed_for(2, synth.BUF_B))
     synth.device_fill_uniform_f32(hc.data_ptr(), n, synth.seed_for(2, synth.BUF_C))
     l2 = torch.empty(1 << 19, dtype=torch.int32, device=dev)
-    mall = torch.empty(1 << 25, dtype=torch.int32, device=dev)
     l1 = torch.empty(1 << 12, dtype=torch.int32, device=dev)
-    for t, k in ((l2, 0), (mall, 1), (l1, 2)):
+    for t, k in ((l2, 0), (l1, 2)):
         synth.device_fill_u32(t.data_ptr(), t.numel(), synth.seed_for(2, synth.BUF_CACHE) + k)
+    nm = 1 << 24   # Infinity Cache: two 64 MiB arrays read (16 MiB per XCD slot)
+    mb = torch.empty(nm, dtype=torch.float32, device=dev)
+    mc = torch.empty_like(mb)
+    synth.device_fill_uniform_f32(mb.data_ptr(), nm, synth.seed_for(2, synth.BUF_CACHE) + 1)
+    synth.device_fill_uniform_f32(mc.data_ptr(), nm, synth.seed_for(2, synth.BUF_CACHE) + 3)
     win = T(synth.u32(synth.seed_for(2, synth.BUF_LDS), 8192).view(np.int32))
     valu = torch.empty(256 * 4 * 256 * 8, dtype=torch.float32, device=dev)
     mf = {"f32": (np.ones((32, 2), np.float32), np.ones((2, 32), np.float32)),
@@ -285,7 +298,7 @@ def stressor_operands(dev):
     return {
         "hbm": dict(src0=hb, src1=hc, dst=ha, n=n),
         "l2": dict(src0=l2, n=1 << 19),
-        "mall": dict(src0=mall, n=1 << 25),
+        "mall": dict(src0=mb, src1=mc, n=nm),
         "vl1d": dict(src0=l1, n=1 << 12),
         "lds": dict(src0=win),
         "valu_f32": dict(dst=valu, fa=1 - 2 ** -12, fb=2 ** -12),
@@ -342,7 +355,7 @@ def run_sweep(args):
     for r in ("valu_f32", "mfma_bf16"):
         rows.append((r + "_1wave", r, dict(ops[r], wg_per_cu=1, threads=256)))
     res = [r for _, r, _ in rows]
-    ws = torch.empty(256 + 256 * 8 * 48, dtype=torch.uint8, device=dev)
+    ws = torch.empty(WS_BYTES, dtype=torch.uint8, device=dev)
     out = {"metric": "victim slowdown per resource vs intensity", "config": {
         "workload": "sensitivity sweep: BF16 GEMM 4096^3 and BF16 GEMV 8192^2 (3 rotating weight "
                     "copies) x 12 stressors x CU intensity 0/25/50/75/100%", "reps": args.reps},
@@ -395,7 +408,7 @@ def run_hbm_mix(args):
              "copy": dict(src0=h["src0"], dst=h["dst"]),
              "write": dict(dst=h["dst"])}
     opts = [dict(o, n=h["n"], knob=coloc.HBM_MIX[m]) for m, o in mixes.items()]
-    ws = torch.empty(256 + 256 * 8 * 48, dtype=torch.uint8, device=dev)
+    ws = torch.empty(WS_BYTES, dtype=torch.uint8, device=dev)
     out = {"metric": "victim slowdown vs HBM traffic mix and intensity", "config": {
         "workload": "victims of the sensitivity sweep x HBM stressor over 2^28-element FP32 arrays "
                     "in four read/write mixes x CU intensity 0/25/50/75/100%", "reps": args.reps},
@@ -446,7 +459,7 @@ def run_precision(args):
     exact = oracle.gemm_entries_f64(ha, hb, rows, cols)
     absx = oracle.gemm_entries_f64(np.abs(ha), np.abs(hb), rows, cols)
     ops = stressor_operands(dev)
-    ws = torch.empty(256 + 256 * 8 * 48, dtype=torch.uint8, device=dev)
+    ws = torch.empty(WS_BYTES, dtype=torch.uint8, device=dev)
     out = {"metric": "GEMM error vs FP64 and sensitivity per dtype",
            "config": {"workload": "GEMM M=N=K=8192, inputs N(0,1), FP32 accumulate; FP8 e4m3 per-tensor scale",
                       "sample": "4096 fixed-seed entries"}, "dtypes": {}}
@@ -557,7 +570,7 @@ def serve_profiles(ctx, args, axis="cu", hbm_mix="triad", res=("hbm", "mfma_bf16
         h = ops["hbm"]
         ops["hbm"] = dict(src0=h["src0"], src1=h["src1"], n=h["n"], knob=HBM_MIX["read"])
     res = list(res)
-    ws = torch.empty(256 + 256 * 8 * 48, dtype=torch.uint8, device=dev)
+    ws = torch.empty(WS_BYTES, dtype=torch.uint8, device=dev)
     rates = {}
     duty_rates = {}
     fixed = {"hbm": dict(passes=1), "mfma_bf16": dict(iters=2048, passes=2), "lds": dict(passes=4),
@@ -730,7 +743,7 @@ def run_pollution(args):
     from paper_2501_16909_amd import coloc
     ctx = coloc.Context(0)
     dev = ctx.device
-    ws = torch.empty(256 + 256 * 8 * 48, dtype=torch.uint8, device=dev)
+    ws = torch.empty(WS_BYTES, dtype=torch.uint8, device=dev)
     rows = []
     for mib in (0.75, 1.5, 3, 6, 12, 24, 48, 96, 192, 384, 768, 1536):
         n = int(mib * (1 << 20) / 12) // 1024 * 1024
@@ -767,7 +780,7 @@ def run_bandwidth(args):
     dev = ctx.device
     ops = stressor_operands(dev)
     d = _gemv_victim(ctx, dev)
-    ws = torch.empty(256 + 256 * 8 * 48, dtype=torch.uint8, device=dev)
+    ws = torch.empty(WS_BYTES, dtype=torch.uint8, device=dev)
     rows = []
     for wg in (0, 1, 2, 3, 4):
         if wg == 0:
@@ -801,7 +814,7 @@ def run_ilp(args):
     ctx = coloc.Context(0)
     dev = ctx.device
     ops = stressor_operands(dev)
-    ws = torch.empty(256 + 256 * 8 * 48, dtype=torch.uint8, device=dev)
+    ws = torch.empty(WS_BYTES, dtype=torch.uint8, device=dev)
     victims = {"gemv_bf16_8192": _gemv_victim(ctx, dev)}
     import synth
     n = 1 << 24
@@ -838,7 +851,7 @@ def run_pairs(args):
     from paper_2501_16909_amd import coloc
     ctx1, ctx2 = coloc.Context(0), coloc.Context(0)
     dev = ctx1.device
-    ws1 = torch.empty(256 + 256 * 8 * 48, dtype=torch.uint8, device=dev)
+    ws1 = torch.empty(WS_BYTES, dtype=torch.uint8, device=dev)
     ws2 = torch.empty_like(ws1)
     out64 = [torch.empty(256 * 256 * 8, dtype=torch.float64, device=dev) for _ in range(2)]
     out = {"metric": "seq/col speedup of two identical compute kernels",
@@ -886,7 +899,7 @@ def run_ldsstride(args):
     ctx = coloc.Context(0)
     dev = ctx.device
     ops = stressor_operands(dev)
-    ws = torch.empty(256 + 256 * 8 * 48, dtype=torch.uint8, device=dev)
+    ws = torch.empty(WS_BYTES, dtype=torch.uint8, device=dev)
     out = {"metric": "GEMM slowdown vs LDS stressor bank-conflict stride",
            "config": {"workload": "BF16 GEMM n = 1024 and 2048 (own MFMA kernel); LDS stressor 64 KiB per WG, "
                                   "256 threads, one WG per CU, 32-bit accesses at stride s words"}, "rows": []}
@@ -954,7 +967,7 @@ def run_decode(args):
              "kernel_us": {k: round(v / 1e3, 1) for k, v in kern.items()}}
     log("decode alone: " + json.dumps(alone))
     ops = stressor_operands(dev)
-    ws = torch.empty(256 + 256 * 16 * 48, dtype=torch.uint8, device=dev)
+    ws = torch.empty(WS_BYTES, dtype=torch.uint8, device=dev)
     res = ["hbm", "l2", "mall", "lds", "valu_f32", "mfma_bf16", "ptrchase"]
     rows = []
     for axis, levels in (("cu", [0.25, 0.5, 1.0]), ("duty", [25, 50])):

@@ -50,7 +50,10 @@ typedef enum ci_status {
   CI_ERR_TIMEOUT = 4,      /* a stressor hit its in-kernel deadline, or did
                               not start within the start timeout           */
   CI_ERR_UNSUPPORTED = 5,  /* combination not implemented on this device   */
-  CI_ERR_BUSY = 6          /* context already has a stressor on that slot  */
+  CI_ERR_BUSY = 6,         /* context already has a stressor on that slot  */
+  CI_ERR_DRAIN = 7         /* a stressor kernel did not exit within its
+                              deadline + 5 s after the stop request; the
+                              context launches no further stressors        */
 } ci_status_t;
 
 /* Shared resources with one stressor each (paper Section 4: block scheduler
@@ -59,7 +62,8 @@ typedef enum ci_status {
 typedef enum ci_resource {
   CI_RES_HBM = 0,        /* array streaming: triad a = b + 3c, or a CI_HBM_* mix */
   CI_RES_L2 = 1,         /* every WG re-reads one region sized for each XCD's L2 */
-  CI_RES_MALL = 2,       /* ... a region that misses L2 and fits Infinity Cache */
+  CI_RES_MALL = 2,       /* array streaming over a footprint that misses L2 and
+                            fits the Infinity Cache                            */
   CI_RES_VL1D = 3,       /* ... a region that fits the per-CU vector L1        */
   CI_RES_LDS = 4,        /* LDS copy loop with a stride (bank-conflict) knob   */
   CI_RES_VALU_F32 = 5,   /* FP32 FMA chains with an ILP knob                   */
@@ -120,7 +124,12 @@ ci_status_t ci_device_info(ci_ctx_t* ctx, ci_device_info_t* out);
 /* Peak of resource r in its own unit: bytes/s for HBM, L2, MALL, VL1D and
  * LDS; flop/s for VALU and MFMA (for VALU_F64 one multiply = one flop, so its
  * peak is half the FP64 FMA rate); work-groups/s for DISPATCH; hops/s for the
- * chase (no peak: 0); OCCUPANCY has no rate (0). */
+ * chase (no peak: 0); OCCUPANCY has no rate (0).  HBM and the matrix cores
+ * take MI355X's published figures; L2, vL1D and the vector ALUs bytes or
+ * flops per clock times units times the 2.4 GHz engine clock; the Infinity
+ * Cache and the LDS, for which no figure describes CDNA4, a ceiling measured
+ * on MI355X (Infinity Cache 7.65 TB/s, the best streaming rate any launch
+ * shape reached; LDS 117 B/clk per CU, a conflict-free 16-byte copy). */
 ci_status_t ci_peak_for(ci_ctx_t* ctx, ci_resource_t r, double* peak);
 
 /* ------------------------------------------------------------ CU masks */
@@ -166,7 +175,8 @@ ci_status_t ci_queue_stats(ci_ctx_t* ctx, uint32_t* checks, uint32_t* replaced,
 
 /* ----------------------------------------------------------- stressors */
 /* Per-work-group record written by every stressor work-group at exit
- * (device memory inside the caller's workspace). */
+ * (device memory inside the caller's workspace, after the 2304 bytes of
+ * control words). */
 typedef struct ci_wg_record {
   uint64_t t_start;  /* device wall clock at WG start                      */
   uint64_t t_end;    /* device wall clock at WG exit                       */
@@ -177,11 +187,12 @@ typedef struct ci_wg_record {
   uint64_t pad;
 } ci_wg_record_t;    /* 48 bytes */
 
-/* HBM traffic mixes (the HBM stressor's knob).  The paper's bandwidth
- * stressor streams large arrays through HBM (Section 3, Pitfall 2; Section
- * 4.3, Table 1); the mix sets the read/write proportion of that stream, since
- * DRAM bandwidth and a co-runner's slowdown both depend on it.  Per element
- * i < n (4-byte words, every element once per pass):
+/* Traffic mixes of the streaming stressors (the knob of HBM and MALL).  The
+ * paper's bandwidth stressor streams large arrays through memory (Section
+ * 3, Pitfall 2; Section 4.3, Table 1); the mix sets the read/write
+ * proportion of that stream, since bandwidth and a co-runner's slowdown both
+ * depend on it.  Per element i < n (4-byte words, every element once per
+ * pass):
  *   CI_HBM_TRIAD  a[i] = b[i] + 3 c[i] in FP32, rounded after the product
  *                 and after the sum; 2 reads : 1 write, 12 B (default)
  *   CI_HBM_READ   reads b[i] and c[i]; nothing is stored; each work-group's
@@ -197,9 +208,13 @@ typedef struct ci_wg_record {
 
 typedef struct ci_stressor_opts {
   /* Resource-specific operands (device pointers, caller-owned):
-   *   HBM:        src0 = b, src1 = c, dst = a   (FP32, n elements; only the
-   *               arrays the traffic mix touches are required)
-   *   L2/MALL/VL1D: src0 = region (uint32, n words)
+   *   HBM, MALL:  src0 = b, src1 = c, dst = a   (FP32, n elements; only the
+   *               arrays the traffic mix touches are required; n <= 2^32 for
+   *               the write-only mix).  HBM: arrays far larger than the
+   *               256 MB Infinity Cache; MALL: a footprint larger than the
+   *               L2s (4 MB per XCD) that fits the Infinity Cache.  Each XCD
+   *               slot streams its own eighth of the arrays.
+   *   L2/VL1D:    src0 = region (uint32, n words)
    *   LDS:        src0 = window words (uint32, 8192 = 32 KiB)
    *   VALU_F32:   dst  = final chain values (FP32, grid*threads*knob)
    *   VALU_F64:   dst  = final chain values (FP64, grid*threads*knob); the
@@ -220,12 +235,14 @@ typedef struct ci_stressor_opts {
   uint32_t threads;      /* threads per work-group; 0 = resource default     */
   uint32_t knob;         /* VALU_F32/F64: ILP chains per lane (1,2,4,8); LDS: stride
                             in vectors; MFMA: independent accumulators (1-4);
-                            HBM: traffic mix CI_HBM_* (0 = triad);
+                            HBM, MALL: traffic mix CI_HBM_* (0 = triad for
+                            HBM, read-only for MALL);
                             PTRCHASE: chains per lane (1-8); OCCUPANCY: LDS
                             KiB held per WG; 0 = default                     */
   uint32_t vec;          /* LDS: vector width in 32-bit words (1, 2, 4);
                             HBM: 0 = streaming (non-temporal) accesses,
-                            1 = ordinary cached accesses                     */
+                            1 = ordinary cached accesses; MALL: always
+                            cached                                          */
   uint64_t passes;       /* 0 = run until stressor_stop; > 0 = exactly this
                             many passes per work-group, then exit            */
   uint64_t iters;        /* VALU: FMA steps per pass (default 4096); MFMA:
@@ -235,10 +252,14 @@ typedef struct ci_stressor_opts {
   float fa, fb;          /* VALU chain x <- fma(x, fa, fb)                   */
   uint32_t deadline_ms;  /* in-kernel safety deadline, 0 = 2000 ms           */
   uint32_t duty;         /* percent of time the stressor is active (1..100;
-                            0 = 100): after each pass (HBM: each chunk) a
-                            wave idles for (100/duty - 1) times the time the
-                            pass took, so the unit sees duty% of the load on
-                            every masked CU.  Ignored by DISPATCH / OCCUPANCY */
+                            0 = 100): after each pass (HBM, MALL: each round
+                            of chunks) a wave idles for (100/duty - 1) times
+                            the time the pass took, so the unit sees duty% of
+                            the load on every masked CU.  Ignored by DISPATCH /
+                            OCCUPANCY */
+  uint32_t chunk;        /* HBM, MALL: 16-byte accesses per lane and stream in
+                            one wave-chunk (1, 2 or 4; 0 = 4): a wave-chunk is
+                            256 * chunk elements                            */
 } ci_stressor_opts_t;
 
 typedef struct ci_stressor_report {
@@ -261,13 +282,26 @@ typedef struct ci_stressor_report {
   int distinct_cus;         /* distinct hardware CUs seen in the records     */
 } ci_stressor_report_t;
 
-/* Device bytes of workspace a stressor needs for `ncu` CUs (its records and
- * control words).  intensity-independent upper bound: pass ncu = num_cus. */
-ci_status_t ci_workspace_size(ci_resource_t r, const ci_stressor_opts_t* opts, int ncu,
+/* Device bytes of workspace stressor r needs at CU fraction `intensity`
+ * with options opts (NULL = defaults): 2304 bytes of control words (stop and
+ * start words, the dispatch counter, one ticket line per XCD slot for the
+ * streaming stressors) and one 48-byte record per work-group, the grid
+ * being (work-groups per CU) x
+ * (CUs at that intensity).  The count uses the 256-CU layout (exact on
+ * MI355X, an upper bound on parts with fewer CUs); intensity 1 bounds every
+ * intensity.  The options stay an argument because the work-groups per CU
+ * (opts->wg_per_cu) set the record count.  Pure host computation.
+ * CI_ERR_INVALID_ARG on a bad resource, NaN or out-of-range intensity, or
+ * NULL bytes. */
+ci_status_t ci_workspace_size(ci_resource_t r, float intensity, const ci_stressor_opts_t* opts,
                               size_t* bytes);
 
 /* Start stressor r at CU fraction `intensity` (0..1, rounded as in
- * ci_cu_mask).  The kernel runs on a
+ * ci_cu_mask): one microbenchmark per shared resource holding a constant
+ * level of interference for as long as the colocated workload runs
+ * (Section 4.1); the intensity is the fraction of compute units it may use,
+ * as the paper sizes its stressors by the SMs they get (Section 4.1, green
+ * contexts; Section 4.3, Table 1).  The kernel runs on a
  * library-owned CU-masked stream that first waits for work already queued on
  * `stream` (which is not blocked).  With opts->passes == 0 the call returns
  * once the stressor is observed running on the device (all its work-groups
@@ -281,10 +315,14 @@ ci_status_t stressor_launch(ci_ctx_t* ctx, ci_resource_t r, float intensity, voi
                             const ci_stressor_opts_t* opts, void* ws, size_t ws_bytes,
                             ci_stressor_t** h);
 
-/* Signal stop, wait for the kernel(s) to drain (bounded by the deadline),
+/* End the constant interference started by stressor_launch (Section 4.1):
+ * signal stop, wait for the kernel(s) to drain (bounded by the deadline),
  * make `stream` of the launch wait for completion, read the records and fill
- * *rep (may be NULL).  Frees h.  Returns CI_ERR_TIMEOUT (after filling rep)
- * if a work-group hit its deadline. */
+ * *rep (may be NULL) with the stressor's own utilisation as a fraction of
+ * the resource's peak (the paper's utilisation metrics, Section 2.2, and the
+ * stressor rows of Tables 1-3).  Frees h.  Returns CI_ERR_TIMEOUT (after
+ * filling rep) if a work-group hit its deadline, CI_ERR_DRAIN if the kernel
+ * did not exit within the deadline + 5 s. */
 ci_status_t stressor_stop(ci_stressor_t* h, ci_stressor_report_t* rep);
 
 /* Copy the stressor's records (grid entries) to host memory; valid only
@@ -313,9 +351,12 @@ typedef struct ci_victim_result {
   uint64_t t_end;
 } ci_victim_result_t;
 
-/* Run the victim once on `stream` and wait for it: one kernel launch timed
- * with HIP events, bracketed by device timestamps, followed by the output
- * checksum.  Victim constraints: TRIAD n >= 0; GEMM K a multiple of 16 / 8 /
+/* Run the victim once on `stream` and wait for it: the workload whose
+ * latency the paper compares alone and colocated (Section 4.1; its victims
+ * are a GEMM for shared memory, Section 4.4.1, and LLM decode, dominated by
+ * matrix-vector products, Sections 4.2-4.3).  One kernel launch (a triad of
+ * `passes` sweeps: `passes` launches) timed with HIP events, bracketed by
+ * device timestamps, followed by the output checksum.  Victim constraints: TRIAD n >= 0; GEMM K a multiple of 16 / 8 /
  * 4 elements for FP8 / BF16 / F32 (any M, N); GEMV k a multiple of 8. */
 ci_status_t victim_run(ci_ctx_t* ctx, const ci_victim_desc_t* d, void* stream,
                        ci_victim_result_t* out);
@@ -349,6 +390,22 @@ ci_status_t ci_checksum_f32(ci_ctx_t* ctx, const void* x, uint64_t n, void* stre
 ci_status_t ci_quantize(ci_ctx_t* ctx, const void* src, uint64_t n, int dtype, void* dst,
                         float* scale_out, void* stream);
 
+/* One matrix-core instruction per tile, D = A B + C, in FP32 accumulate:
+ * the building block of the GEMM victim and the matrix-core stressors
+ * (Section 4.4.3 stresses the compute pipelines; the precision extension
+ * asks for each dtype's error against FP64).  The instruction set leaves
+ * the accumulation inside one instruction unspecified; this call lets a
+ * test characterise it.  Per tile t (device pointers, tiles contiguous):
+ *   dtype F32:     A 32 x 2 FP32, B 2 x 32 FP32        (v_mfma_f32_32x32x2_f32)
+ *   dtype BF16:    A 32 x 16 BF16, B 16 x 32 BF16      (v_mfma_f32_32x32x16_bf16)
+ *   dtype FP8E4M3: A 32 x 64 E4M3, B 64 x 32 E4M3      (v_mfma_f32_32x32x64_f8f6f4,
+ *                  OCP E4M3 for both operands, no block scales)
+ * all row-major; C and D 32 x 32 FP32 row-major (D may alias C).
+ * Synchronous on `stream`.  CI_ERR_INVALID_ARG on NULL pointers or a bad
+ * dtype. */
+ci_status_t ci_mfma_probe(ci_ctx_t* ctx, int dtype, const void* a, const void* b, const float* c,
+                          float* d, uint32_t ntiles, void* stream);
+
 /* ------------------------------------------------------- sensitivity */
 /* ci_measure_opts_t.flags */
 #define CI_MEASURE_NO_QUEUE_CHECK 1u  /* skip the queue-pair check (raw placement) */
@@ -359,6 +416,13 @@ typedef struct ci_measure_opts {
   int placement;         /* ci_placement_t                                    */
   uint32_t deadline_ms;  /* stressor deadline per colocated run (default 2000) */
   uint32_t flags;        /* CI_MEASURE_* bits                                 */
+  /* Optional caller-owned host arrays of nr * nx * reps doubles (NULL =
+   * not wanted; reps after its default is applied): the victim's time in ns
+   * of every alone run and every colocated run, cell c = i * nx + j, rep r
+   * at index c * reps + r.  Cells that are not measured (disjoint placement
+   * at intensity 1) hold NaN. */
+  double* rep_alone_ns;
+  double* rep_col_ns;
 } ci_measure_opts_t;
 
 typedef struct ci_cell {
@@ -378,6 +442,10 @@ typedef struct ci_cell {
   double slowdown_ci_lo;      /* percentile-bootstrap 95 % interval of the    */
   double slowdown_ci_hi;      /* slowdown (ci_bootstrap_slowdown, 1000
                                  resamples, seed 16909 + cell index)         */
+  int queue_unresolved;       /* the queue-pair check could not find a pair
+                                 of queues that leave each other alone: the
+                                 cell was measured as placed and may carry
+                                 queue interference (see ci_queue_stats)     */
 } ci_cell_t;
 
 /* Percentile-bootstrap confidence interval of the slowdown statistic
@@ -396,10 +464,15 @@ typedef struct ci_cell {
 ci_status_t ci_bootstrap_slowdown(const double* alone, uint32_t na, const double* col, uint32_t nc,
                                   uint32_t resamples, uint64_t seed, double* lo, double* hi);
 
-/* For every resource rs[i] (operands in sopts[i]) and intensity xs[j]:
- * warm the victim up, then `reps` times run it alone and colocated with the
- * stressor (persistent mode), checking the window and output of each
- * colocated run; cells[i * nx + j] receives the result.  Even repetitions
+/* The victim's sensitivity profile: its slowdown colocated versus alone
+ * (Section 4.3, the slowdown of the cache-pollution experiment; Section 4.1,
+ * constant interference over the victim's lifetime) for every shared
+ * resource and intensity, the per-resource profile the paper's estimator
+ * consumes (Section 5.1).  For every resource rs[i] (operands in sopts[i])
+ * and intensity xs[j]: warm the victim up, then `reps` times run it alone
+ * and colocated with the stressor (persistent mode), checking the window and
+ * output of each colocated run; cells[i * nx + j] receives the result and,
+ * when o->rep_alone_ns / rep_col_ns are given, the per-rep times.  Even repetitions
  * run alone first, odd ones colocated first (counterbalanced order).  ws: workspace large
  * enough for every listed stressor at full intensity.  Synchronous. */
 ci_status_t measure_sensitivity(ci_ctx_t* ctx, const ci_victim_desc_t* d,
@@ -513,6 +586,7 @@ typedef struct ci_decode_cell {
   double kernel_col_ns[CI_DK_COUNT];
   double stressor_achieved, stressor_pct_peak;  /* means over the reps        */
   int window_covered, output_equal, timed_out, reps;
+  int queue_unresolved;                   /* as in ci_cell_t                 */
 } ci_decode_cell_t;
 
 /* measure_sensitivity for the decode step: for every resource rs[i] and
@@ -603,12 +677,47 @@ typedef enum ci_policy_kind {
 
 #define CI_NPOINTS 5  /* intensities 0, .25, .5, .75, 1 */
 
+/* Sensitivity profile of one workload kind: what the paper's kernel-level
+ * interference estimator consumes (Section 5.1 asks a colocation scheduler
+ * to predict each kernel's slowdown from its sensitivity to every shared
+ * resource and the pressure its co-runners put on them).
+ *   sens[r][p]: the kind's measured slowdown (as a victim) beside stressor r
+ *     at load point p = 0, .25, .5, .75, 1 of that stressor's full rate;
+ *   press[r]:   the load the kind itself puts on r when it runs alone, as a
+ *     fraction of stressor r's full rate (0..1);
+ *   occ:        fraction of the GPU's wave slots it fills (USHER policy).
+ * Read/write-aware HBM pricing (optional; all-zero sens_hbm_read = absent):
+ * the same HBM byte rate costs a victim more when it includes writes, so a
+ * co-runner whose HBM traffic is read-mostly is priced on the victim's curve
+ * against the read-only HBM mix instead of the triad's.
+ *   sens_hbm_read[p]: slowdown curve against the read-only HBM mix;
+ *   press_hbm_read:   this kind's HBM load against that mix's full rate;
+ *   hbm_write_frac:   write share of its compulsory HBM bytes (0..1). */
 typedef struct ci_profile {
   int kind;                             /* victim kind this profile covers    */
   float sens[CI_RES_COUNT][CI_NPOINTS]; /* measured slowdown curve per resource */
   float press[CI_RES_COUNT];            /* pressure it exerts (0..1)           */
   float occ;                            /* fraction of wave slots it fills     */
+  float sens_hbm_read[CI_NPOINTS];
+  float press_hbm_read;
+  float hbm_write_frac;
 } ci_profile_t;
+
+/* A co-runner counts as read-mostly below this write share of its HBM bytes. */
+#define CI_READ_MOSTLY_WRITE_FRAC (1.0f / 6.0f)
+
+/* Predicted slowdown of `victim` beside the co-runners (Section 5.1's
+ * estimator, in the reading this library takes): the co-runners' loads add
+ * per resource, each resource's factor is max(1, curve at the summed load)
+ * with the curve linear between its five points and the load clipped to
+ * [0, 1], and the factors multiply (a conservative combination).  HBM load
+ * from read-mostly co-runners (hbm_write_frac < CI_READ_MOSTLY_WRITE_FRAC) is
+ * summed separately, from their press_hbm_read, and priced on the victim's
+ * sens_hbm_read curve when the victim has one; all other HBM load is priced
+ * on sens[CI_RES_HBM].  nco == 0 gives 1.  Pure host computation; profiles
+ * are caller-owned.  CI_ERR_INVALID_ARG on NULL pointers or nco < 0. */
+ci_status_t ci_predict_slowdown(const ci_profile_t* victim, const ci_profile_t* const* corunners,
+                                int nco, double* out);
 
 typedef struct ci_request {
   double arrival_s;       /* seconds after the loop starts                   */
@@ -616,6 +725,10 @@ typedef struct ci_request {
   int dtype;              /* as in ci_victim_desc_t                           */
   uint64_t m, n, k;       /* sizes as in ci_victim_desc_t                     */
   uint64_t seed;          /* input stream seed (uniform [-1, 1) inputs)       */
+  /* Optional caller-owned device buffer (NULL = none) that receives a copy
+   * of the request's FP32 output (GEMM m x n, GEMV n, triad n) before its
+   * arena memory is released, for checking served results. */
+  void* out_copy;
 } ci_request_t;
 
 typedef struct ci_policy {
@@ -636,18 +749,37 @@ typedef struct ci_served {
   int status;                        /* ci_status_t of this request           */
 } ci_served_t;
 
-/* Continuous-batching colocation loop: requests (sorted by arrival_s)
- * arrive in real time; each is admitted FIFO (no bypass) when the policy
- * allows, its inputs are generated and its kernel launched on a free slot
- * stream, and it retires when its completion is observed.  The loop owns
+/* Inputs of served requests are drawn on the device from the request's seed:
+ * with u(s, i) the uniform [-1, 1) draw i of SplitMix64 stream s (the
+ * counter form and mapping of the input generator), a triad reads b = u(seed)
+ * and c = u(seed + 1); a GEMM reads A = u(seed) (m x k) and B = u(seed + 1)
+ * (n x k), rounded to BF16 for BF16 requests; a GEMV reads W = u(seed)
+ * (n x k) and x = u(seed + 1) (k), both rounded to BF16.
+ *
+ * Continuous-batching colocation loop: the interference-aware scheduler of
+ * Section 5.1 (decide per kernel, predict each kernel's slowdown from the
+ * co-runners' pressure on every resource, trade a bounded slowdown for
+ * utilisation), against memory-only admission and the occupancy rule the
+ * paper shows failing (Section 3, Pitfall 1).  Requests (sorted by
+ * arrival_s) arrive in real time; each is admitted FIFO (no bypass) when the
+ * policy allows (ci_admit), its inputs are generated and its kernel launched
+ * on a free slot stream, and it retires when its completion is observed.  The loop owns
  * one device arena of hbm_budget bytes for all request buffers.  out[i]
  * receives request i's record.  Synchronous; returns when all are done. */
 ci_status_t serve_run(ci_ctx_t* ctx, const ci_request_t* trace, int n, const ci_policy_t* p,
                       ci_served_t* out);
 
-/* Pure admission decision used by serve_run, exposed for testing:
- * running[0..nrun) and cand index profiles; bytes in use / free; returns 1
- * (admit) or 0 in *admit. */
+/* Pure admission decision used by serve_run (Section 5.1: admit a kernel
+ * beside others only when the predicted slowdowns stay within a bound),
+ * exposed for testing: running_kinds[0..nrun) and cand_kind name profiles
+ * in p; cand_bytes / free_bytes are the candidate's footprint and the
+ * largest free block of the loop's arena.  *admit = 0 when the candidate
+ * does not fit in memory or every slot is busy; otherwise 1 on an idle
+ * device (nrun == 0: the rules below bound colocation only); otherwise
+ * NAIVE admits, USHER admits when the summed occupancy of all jobs stays
+ * below 1 (Section 3, Pitfall 1), and SENSITIVITY admits when
+ * ci_predict_slowdown of every job, beside all the others, is <= bound.
+ * CI_ERR_INVALID_ARG on a bad policy or a kind without a profile. */
 ci_status_t ci_admit(const ci_policy_t* p, const int* running_kinds, int nrun, int cand_kind,
                      uint64_t cand_bytes, uint64_t free_bytes, int* admit);
 

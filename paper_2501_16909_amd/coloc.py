@@ -23,7 +23,7 @@ HBM_MIX = {"triad": 1, "read": 2, "copy": 3, "write": 4}
 VICTIMS = {"triad": 0, "gemm": 1, "gemv": 2}
 POLICIES = {"naive": 0, "usher": 1, "sensitivity": 2}
 STATUS = {0: "CI_OK", 1: "CI_ERR_INVALID_ARG", 2: "CI_ERR_HIP", 3: "CI_ERR_OOM",
-          4: "CI_ERR_TIMEOUT", 5: "CI_ERR_UNSUPPORTED", 6: "CI_ERR_BUSY"}
+          4: "CI_ERR_TIMEOUT", 5: "CI_ERR_UNSUPPORTED", 6: "CI_ERR_BUSY", 7: "CI_ERR_DRAIN"}
 NPOINTS = 5
 NRES = len(RESOURCES)
 
@@ -53,7 +53,7 @@ class StressorOpts(C.Structure):
                 ("n", C.c_uint64), ("wg_per_cu", C.c_uint32), ("threads", C.c_uint32),
                 ("knob", C.c_uint32), ("vec", C.c_uint32), ("passes", C.c_uint64),
                 ("iters", C.c_uint64), ("fa", C.c_float), ("fb", C.c_float),
-                ("deadline_ms", C.c_uint32), ("duty", C.c_uint32)]
+                ("deadline_ms", C.c_uint32), ("duty", C.c_uint32), ("chunk", C.c_uint32)]
 
 
 class StressorReport(C.Structure):
@@ -83,7 +83,8 @@ MEASURE_NO_QUEUE_CHECK = 1
 
 class MeasureOpts(C.Structure):
     _fields_ = [("reps", C.c_uint32), ("warmups", C.c_uint32), ("placement", C.c_int),
-                ("deadline_ms", C.c_uint32), ("flags", C.c_uint32)]
+                ("deadline_ms", C.c_uint32), ("flags", C.c_uint32),
+                ("rep_alone_ns", C.POINTER(C.c_double)), ("rep_col_ns", C.POINTER(C.c_double))]
 
 
 class Cell(C.Structure):
@@ -93,17 +94,21 @@ class Cell(C.Structure):
                 ("t_col_ns", C.c_double), ("stressor_achieved", C.c_double),
                 ("stressor_pct_peak", C.c_double), ("window_covered", C.c_int),
                 ("output_equal", C.c_int), ("timed_out", C.c_int), ("reps", C.c_int),
-                ("slowdown_ci_lo", C.c_double), ("slowdown_ci_hi", C.c_double)]
+                ("slowdown_ci_lo", C.c_double), ("slowdown_ci_hi", C.c_double),
+                ("queue_unresolved", C.c_int)]
 
 
 class Profile(C.Structure):
     _fields_ = [("kind", C.c_int), ("sens", (C.c_float * NPOINTS) * NRES),
-                ("press", C.c_float * NRES), ("occ", C.c_float)]
+                ("press", C.c_float * NRES), ("occ", C.c_float),
+                ("sens_hbm_read", C.c_float * NPOINTS), ("press_hbm_read", C.c_float),
+                ("hbm_write_frac", C.c_float)]
 
 
 class Request(C.Structure):
     _fields_ = [("arrival_s", C.c_double), ("kind", C.c_int), ("dtype", C.c_int),
-                ("m", C.c_uint64), ("n", C.c_uint64), ("k", C.c_uint64), ("seed", C.c_uint64)]
+                ("m", C.c_uint64), ("n", C.c_uint64), ("k", C.c_uint64), ("seed", C.c_uint64),
+                ("out_copy", C.c_void_p)]
 
 
 class Policy(C.Structure):
@@ -167,7 +172,7 @@ class DecodeCell(C.Structure):
                 ("kernel_alone_ns", C.c_double * NDK), ("kernel_col_ns", C.c_double * NDK),
                 ("stressor_achieved", C.c_double), ("stressor_pct_peak", C.c_double),
                 ("window_covered", C.c_int), ("output_equal", C.c_int), ("timed_out", C.c_int),
-                ("reps", C.c_int)]
+                ("reps", C.c_int), ("queue_unresolved", C.c_int)]
 
 
 EXPORTS = {
@@ -183,7 +188,7 @@ EXPORTS = {
     "ci_bootstrap_slowdown": ([C.POINTER(C.c_double), C.c_uint32, C.POINTER(C.c_double), C.c_uint32,
                                C.c_uint32, C.c_uint64, C.POINTER(C.c_double), C.POINTER(C.c_double)],
                               C.c_int),
-    "ci_workspace_size": ([C.c_int, C.POINTER(StressorOpts), C.c_int, C.POINTER(C.c_size_t)], C.c_int),
+    "ci_workspace_size": ([C.c_int, C.c_float, C.POINTER(StressorOpts), C.POINTER(C.c_size_t)], C.c_int),
     "stressor_launch": ([C.c_void_p, C.c_int, C.c_float, C.c_void_p, C.POINTER(StressorOpts),
                          C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)], C.c_int),
     "stressor_stop": ([C.c_void_p, C.POINTER(StressorReport)], C.c_int),
@@ -195,6 +200,8 @@ EXPORTS = {
                          C.POINTER(C.c_double)], C.c_int),
     "ci_quantize": ([C.c_void_p, C.c_void_p, C.c_uint64, C.c_int, C.c_void_p, C.POINTER(C.c_float),
                      C.c_void_p], C.c_int),
+    "ci_mfma_probe": ([C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32,
+                       C.c_void_p], C.c_int),
     "measure_sensitivity": ([C.c_void_p, C.POINTER(VictimDesc), C.POINTER(C.c_int),
                              C.POINTER(StressorOpts), C.c_int, C.POINTER(C.c_float), C.c_int,
                              C.POINTER(MeasureOpts), C.c_void_p, C.c_size_t, C.c_void_p,
@@ -202,6 +209,8 @@ EXPORTS = {
     "serve_run": ([C.c_void_p, C.POINTER(Request), C.c_int, C.POINTER(Policy), C.POINTER(Served)], C.c_int),
     "ci_admit": ([C.POINTER(Policy), C.POINTER(C.c_int), C.c_int, C.c_int, C.c_uint64, C.c_uint64,
                   C.POINTER(C.c_int)], C.c_int),
+    "ci_predict_slowdown": ([C.POINTER(Profile), C.POINTER(C.POINTER(Profile)), C.c_int,
+                             C.POINTER(C.c_double)], C.c_int),
     "decode_layout": ([C.POINTER(DecodeConfig), C.POINTER(DecodeLayout)], C.c_int),
     "decode_step": ([C.c_void_p, C.POINTER(DecodeDesc), C.c_void_p, C.POINTER(DecodeResult)], C.c_int),
     "measure_decode": ([C.c_void_p, C.POINTER(DecodeDesc), C.POINTER(C.c_int), C.POINTER(StressorOpts),
@@ -328,7 +337,7 @@ class Stressor:
         self._keep = keep  # tensors that must outlive the kernel
         lib = load_library()
         need = C.c_size_t()
-        _check(lib.ci_workspace_size(RES[resource], C.byref(self.opts), ctx.info.num_cus, C.byref(need)))
+        _check(lib.ci_workspace_size(RES[resource], 1.0, C.byref(self.opts), C.byref(need)))
         if ws is None:
             ws = torch.empty(max(int(need.value), 256), dtype=torch.uint8, device=ctx.device)
         self.ws = ws
@@ -519,6 +528,14 @@ class Context:
                                           C.byref(sc), _stream_handle(self.stream)))
         return out, sc.value
 
+    def mfma_probe(self, dtype: str, a, b, c, d):
+        """ci_mfma_probe: one matrix-core instruction per tile, d = a b + c (device tensors,
+        tiles contiguous; a, b as the dtype's codes)."""
+        self._sync_torch()
+        ntiles = c.numel() // 1024
+        _check(load_library().ci_mfma_probe(self.handle, DTYPES[dtype], _ptr(a), _ptr(b), _ptr(c), _ptr(d),
+                                            ntiles, _stream_handle(self.stream)))
+
     # -------------------------------------------------------- sensitivity
     def measure_sensitivity(self, desc: VictimDesc, resources, opts_list, intensities,
                             reps: int = 20, warmups: int = 3, placement: str = "shared",
@@ -529,12 +546,15 @@ class Context:
         rs = (C.c_int * nr)(*[RES[r] for r in resources])
         so = (StressorOpts * nr)(*[make_opts(**o) for o in opts_list])
         xs = (C.c_float * nx)(*[float(x) for x in intensities])
+        per_rep = nr * nx * reps
+        rep_a = (C.c_double * per_rep)()
+        rep_c = (C.c_double * per_rep)()
         mo = MeasureOpts(reps, warmups, 1 if placement == "disjoint" else 0, deadline_ms,
-                         0 if queue_check else MEASURE_NO_QUEUE_CHECK)
+                         0 if queue_check else MEASURE_NO_QUEUE_CHECK, rep_a, rep_c)
         need = 256
         for i in range(nr):
             b = C.c_size_t()
-            _check(load_library().ci_workspace_size(rs[i], C.byref(so[i]), self.info.num_cus, C.byref(b)))
+            _check(load_library().ci_workspace_size(rs[i], 1.0, C.byref(so[i]), C.byref(b)))
             need = max(need, int(b.value))
         if ws is None:
             ws = torch.empty(need, dtype=torch.uint8, device=self.device)
@@ -543,9 +563,11 @@ class Context:
                                                   C.byref(mo), _ptr(ws), ws.numel(),
                                                   _stream_handle(self.stream), cells))
         out = []
-        for c in cells:
+        for q, c in enumerate(cells):
             out.append({f: getattr(c, f) for f, _ in Cell._fields_})
             out[-1]["resource"] = RESOURCES[c.resource]
+            out[-1]["rep_alone_ns"] = list(rep_a[q * reps:(q + 1) * reps])
+            out[-1]["rep_col_ns"] = list(rep_c[q * reps:(q + 1) * reps])
         return out
 
     # ------------------------------------------------------------- decode
@@ -580,7 +602,7 @@ class Context:
             need = 256
             for i in range(nr):
                 b = C.c_size_t()
-                _check(load_library().ci_workspace_size(rs[i], C.byref(so[i]), self.info.num_cus, C.byref(b)))
+                _check(load_library().ci_workspace_size(rs[i], 1.0, C.byref(so[i]), C.byref(b)))
                 need = max(need, int(b.value))
             ws = torch.empty(need, dtype=torch.uint8, device=self.device)
         cells = (DecodeCell * (nr * nx))()
@@ -681,7 +703,8 @@ class Context:
         tr = (Request * max(n, 1))()
         for i, q in enumerate(requests):
             tr[i] = Request(q["arrival_s"], VICTIMS[q["kind"]], DTYPES[q.get("dtype", "f32")],
-                            q.get("m", 0), q.get("n", 0), q.get("k", 0), q["seed"])
+                            q.get("m", 0), q.get("n", 0), q.get("k", 0), q["seed"],
+                            _ptr(q["out_copy"]) if q.get("out_copy") is not None else None)
         profs = make_profiles(profiles or {})
         pol = Policy(POLICIES[policy], bound, hbm_budget, slots,
                      C.cast(profs, C.POINTER(Profile)) if len(profs) else None, len(profs))
@@ -759,7 +782,9 @@ class DecodeModel:
 
 
 def make_profiles(profiles: dict):
-    """profiles: {kind name: {"sens": {res: [5 slowdowns]}, "press": {res: p}, "occ": o}}."""
+    """profiles: {kind name: {"sens": {res: [5 slowdowns]}, "press": {res: p}, "occ": o}}, and
+    optionally "sens_hbm_read" (5 slowdowns against the read-only HBM mix), "press_hbm_read"
+    and "hbm_write_frac" (read/write-aware HBM pricing, see ci_predict_slowdown)."""
     arr = (Profile * max(len(profiles), 1))()
     for i, (kind, p) in enumerate(profiles.items()):
         arr[i].kind = VICTIMS[kind]
@@ -773,9 +798,25 @@ def make_profiles(profiles: dict):
         for rname, v in p.get("press", {}).items():
             arr[i].press[RES[rname]] = float(v)
         arr[i].occ = float(p.get("occ", 0.0))
+        for j, v in enumerate(p.get("sens_hbm_read") or [0.0] * NPOINTS):
+            arr[i].sens_hbm_read[j] = float(v)
+        arr[i].press_hbm_read = float(p.get("press_hbm_read", 0.0))
+        arr[i].hbm_write_frac = float(p.get("hbm_write_frac", 1.0))
     if not profiles:
         return (Profile * 0)()
     return arr
+
+
+def predict_slowdown(profiles: dict, victim: str, corunners) -> float:
+    """ci_predict_slowdown of kind `victim` beside co-runner kinds (names in profiles)."""
+    names = list(profiles)
+    arr = make_profiles(profiles)
+    co = (C.POINTER(Profile) * max(len(corunners), 1))(
+        *[C.pointer(arr[names.index(k)]) for k in corunners])
+    out = C.c_double()
+    _check(load_library().ci_predict_slowdown(C.byref(arr[names.index(victim)]), co, len(corunners),
+                                              C.byref(out)))
+    return out.value
 
 
 def admit(policy: str, profiles: dict, running_kinds, cand_kind: str, cand_bytes: int,

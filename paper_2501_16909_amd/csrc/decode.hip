@@ -430,6 +430,7 @@ extern "C" ci_status_t measure_decode(ci_ctx_t* ctx, const ci_decode_desc_t* d,
       const int k = cus_for(ctx, xs[j]);
       cell.ncu = k;
       hipStream_t vs = ctx->vstream;
+      HeldStream hold(ctx, &vs);  // the cache never evicts the victim's stream
       uint32_t vmask[8];
       const bool masked = mo.placement == CI_PLACE_DISJOINT && k > 0;  // k == 0: whole GPU, unmasked
       if (masked) {
@@ -449,7 +450,8 @@ extern "C" ci_status_t measure_decode(ci_ctx_t* ctx, const ci_decode_desc_t* d,
       DecodeRun dr{ctx, d, caller};
       if (!(mo.flags & CI_MEASURE_NO_QUEUE_CHECK)) {
         st = check_queue_pair(ctx, rs[i], sopts ? &sopts[i] : nullptr, xs[j], caller, &vs,
-                              masked ? vmask : nullptr, ws, ws_bytes, &DecodeRun::call, &dr);
+                              masked ? vmask : nullptr, ws, ws_bytes, &DecodeRun::call, &dr,
+                              &cell.queue_unresolved);
         if (st != CI_OK) return st;
       }
       for (uint32_t w = 0; w < mo.warmups; ++w) {

@@ -39,10 +39,11 @@ inline hipError_t xlaunch(void (*kernel)(KArgs...), dim3 grid, dim3 block, uint3
 // Each returns hipSuccess or the launch error.  `grid` work-groups.
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_stamp(uint64_t* slot, hipStream_t s);
-// mix: CI_HBM_TRIAD / READ / COPY / WRITE (anything else: triad)
-hipError_t launch_hbm_stressor(const KCtrl& c, uint32_t mix, const float* b, const float* cc,
-                               float* a, uint64_t n, uint32_t threads, bool streaming,
-                               hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+// mix: CI_HBM_TRIAD / READ / COPY / WRITE (anything else: triad); chunk:
+// 16-byte accesses per lane and stream in one wave-chunk (1, 2 or 4)
+hipError_t launch_stream_stressor(const KCtrl& c, uint32_t mix, uint32_t chunk, const float* b,
+                                  const float* cc, float* a, uint64_t n, uint32_t threads,
+                                  bool streaming, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_triad_victim(const float* b, const float* c, float* a, uint64_t n,
                                uint32_t passes, uint32_t grid, hipStream_t s, hipEvent_t e0,
                                hipEvent_t e1);
@@ -73,6 +74,8 @@ hipError_t launch_dispatch_announce(HostCtrl* host, hipStream_t s);
 hipError_t launch_hog(const KCtrl& c, uint32_t lds_bytes, uint32_t threads, hipStream_t s,
     hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_probe(uint32_t nwg, uint32_t* out, hipStream_t s);
+hipError_t launch_mfma_probe(int dtype, const void* a, const void* b, const float* c, float* d,
+                             uint32_t ntiles, hipStream_t s);
 hipError_t launch_checksum_f32(const float* x, uint64_t n, uint64_t* part_bits, double* part_sum,
                                uint32_t nparts, uint64_t* out_bits, double* out_sum,
                                hipStream_t s);

@@ -358,6 +358,31 @@ __global__ void __launch_bounds__(1024) mfma_stressor(KCtrl c, const void* __res
   if (threadIdx.x == 0) write_record(c, blockIdx.x, t0, passes, 0, ws.st.flags);
 }
 
+// One matrix-core instruction per tile: D = A B + C, with A, B and the
+// accumulator input C loaded in the stressor's fragment layout (A 32 x K and
+// B K x 32 row-major, K = 2 / 16 / 64 for FP32 / BF16 / E4M3; C and D 32 x 32
+// FP32 row-major).  Tile t is work-group t (one wave).
+template <int DT>
+__global__ void __launch_bounds__(64) mfma_probe_kernel(const uint8_t* __restrict__ a,
+                                                        const uint8_t* __restrict__ b,
+                                                        const float* __restrict__ c,
+                                                        float* __restrict__ d) {
+  using Op = MfmaOp<DT>;
+  constexpr uint32_t kOpBytes = 32u * Op::K * (DT == CI_DT_F32 ? 4u : DT == CI_DT_BF16 ? 2u : 1u);
+  const uint32_t lane = threadIdx.x;
+  const size_t t = blockIdx.x;
+  const typename Op::frag fa = Op::load_a(a + t * kOpBytes, lane);
+  const typename Op::frag fb = Op::load_b(b + t * kOpBytes, lane);
+  const float* ct = c + t * 1024;
+  float* dt = d + t * 1024;
+  f32x16 acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = ct[(8u * (v / 4) + 4u * (lane >> 5) + (v % 4)) * 32 + (lane & 31u)];
+  acc = Op::mma(fa, fb, acc);
+#pragma unroll
+  for (int v = 0; v < 16; ++v) dt[(8u * (v / 4) + 4u * (lane >> 5) + (v % 4)) * 32 + (lane & 31u)] = acc[v];
+}
+
 // --------------------------------------------------------- pointer chase
 // CH independent chains per lane; global chain q of Q starts at floor(q*n/Q)
 // and follows next[] `hops` times per pass; dst[q] = index reached.  Table
@@ -539,6 +564,18 @@ hipError_t launch_hog(const KCtrl& c, uint32_t lds_bytes, uint32_t threads, hipS
 
 hipError_t launch_probe(uint32_t nwg, uint32_t* out, hipStream_t s) {
   return xlaunch(probe_kernel, dim3(nwg), dim3(64), 0, s, nullptr, nullptr, out);
+}
+
+hipError_t launch_mfma_probe(int dtype, const void* a, const void* b, const float* c, float* d,
+                             uint32_t ntiles, hipStream_t s) {
+  const uint8_t* pa = (const uint8_t*)a;
+  const uint8_t* pb = (const uint8_t*)b;
+  switch (dtype) {
+    case CI_DT_F32: return xlaunch(mfma_probe_kernel<CI_DT_F32>, dim3(ntiles), dim3(64), 0, s, nullptr, nullptr, pa, pb, c, d);
+    case CI_DT_BF16: return xlaunch(mfma_probe_kernel<CI_DT_BF16>, dim3(ntiles), dim3(64), 0, s, nullptr, nullptr, pa, pb, c, d);
+    case CI_DT_FP8E4M3: return xlaunch(mfma_probe_kernel<CI_DT_FP8E4M3>, dim3(ntiles), dim3(64), 0, s, nullptr, nullptr, pa, pb, c, d);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace ci

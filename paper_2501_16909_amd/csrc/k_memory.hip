@@ -15,8 +15,6 @@
 namespace ci {
 namespace {
 
-constexpr uint32_t kChunk = 1024;  // floats per wave-chunk: 64 lanes x 4 x 4
-
 __device__ __forceinline__ float triad1(float b, float c) {
   // two roundings: fl(b + fl(3c)); contraction into a fused multiply-add is
   // switched off for this expression
@@ -42,8 +40,8 @@ __device__ __forceinline__ vf4 triad_v(vf4 b, vf4 c) {
 
 typedef uint32_t vu4 __attribute__((ext_vector_type(4)));
 
-// HBM traffic mixes (the stressor's knob; the values are the public CI_HBM_*
-// constants): bytes moved per element are 12, 8, 8 and 4.
+// Traffic mixes of the streaming stressor (the values are the public
+// CI_HBM_* constants): bytes moved per element are 12, 8, 8 and 4.
 enum HbmMix : uint32_t { kMixTriad = 1, kMixRead = 2, kMixCopy = 3, kMixWrite = 4 };
 
 // Stored by the write-only mix: element i holds the bits of lo32(i) times an
@@ -62,53 +60,53 @@ __device__ __forceinline__ void st(V* p, V v) {
   else *p = v;
 }
 
-// One wave-chunk of 1024 elements starting at `base`: four 16-byte accesses
-// per lane and stream, all loads issued before the first store.  Streaming
-// (non-temporal) hints: the stressor's data is never reused.  The read-only
-// mix adds the 32-bit words it reads into `acc` (mod 2^32).
-template <uint32_t MIX, bool NT>
-__device__ __forceinline__ void hbm_chunk(const float* __restrict__ b, const float* __restrict__ c,
-                                          float* __restrict__ a, uint64_t base, uint64_t n,
-                                          uint32_t lane, uint32_t& acc) {
-  if (base + kChunk <= n) {
+// One wave-chunk of 256 * U elements starting at `base`: U 16-byte accesses
+// per lane and stream, all loads issued before the first store.  The
+// read-only mix adds the 32-bit words it reads into `acc` (mod 2^32).
+template <uint32_t MIX, bool NT, int U>
+__device__ __forceinline__ void stream_chunk(const float* __restrict__ b, const float* __restrict__ c,
+                                             float* __restrict__ a, uint64_t base, uint64_t n,
+                                             uint32_t lane, uint32_t& acc) {
+  constexpr uint64_t kCh = 256ull * U;
+  if (base + kCh <= n) {
     if constexpr (MIX == kMixTriad) {
       const vf4* b4 = reinterpret_cast<const vf4*>(b + base);
       const vf4* c4 = reinterpret_cast<const vf4*>(c + base);
       vf4* a4 = reinterpret_cast<vf4*>(a + base);
-      vf4 vb[4], vc[4];
+      vf4 vb[U], vc[U];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < U; ++u) {
         vb[u] = ld<NT>(b4 + u * 64 + lane);
         vc[u] = ld<NT>(c4 + u * 64 + lane);
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) st<NT>(a4 + u * 64 + lane, triad_v(vb[u], vc[u]));
+      for (int u = 0; u < U; ++u) st<NT>(a4 + u * 64 + lane, triad_v(vb[u], vc[u]));
     } else if constexpr (MIX == kMixRead) {
       const vu4* b4 = reinterpret_cast<const vu4*>(b + base);
       const vu4* c4 = reinterpret_cast<const vu4*>(c + base);
-      vu4 vb[4], vc[4];
+      vu4 vb[U], vc[U];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < U; ++u) {
         vb[u] = ld<NT>(b4 + u * 64 + lane);
         vc[u] = ld<NT>(c4 + u * 64 + lane);
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < U; ++u) {
         const vu4 t = vb[u] + vc[u];
         acc += t.x + t.y + t.z + t.w;
       }
     } else if constexpr (MIX == kMixCopy) {
       const vu4* b4 = reinterpret_cast<const vu4*>(b + base);
       vu4* a4 = reinterpret_cast<vu4*>(a + base);
-      vu4 vb[4];
+      vu4 vb[U];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) vb[u] = ld<NT>(b4 + u * 64 + lane);
+      for (int u = 0; u < U; ++u) vb[u] = ld<NT>(b4 + u * 64 + lane);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) st<NT>(a4 + u * 64 + lane, vb[u]);
+      for (int u = 0; u < U; ++u) st<NT>(a4 + u * 64 + lane, vb[u]);
     } else {
       vu4* a4 = reinterpret_cast<vu4*>(a + base);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < U; ++u) {
         const uint32_t i0 = (uint32_t)base + (uint32_t)(u * 256) + lane * 4u;
         const vu4 v = {i0 * kWriteMul, (i0 + 1u) * kWriteMul, (i0 + 2u) * kWriteMul,
                        (i0 + 3u) * kWriteMul};
@@ -119,7 +117,7 @@ __device__ __forceinline__ void hbm_chunk(const float* __restrict__ b, const flo
     const uint32_t* bu = reinterpret_cast<const uint32_t*>(b);
     const uint32_t* cu = reinterpret_cast<const uint32_t*>(c);
     uint32_t* au = reinterpret_cast<uint32_t*>(a);
-    for (uint64_t i = base + lane; i < n && i < base + kChunk; i += 64) {
+    for (uint64_t i = base + lane; i < n && i < base + kCh; i += 64) {
       if constexpr (MIX == kMixTriad) a[i] = triad1(b[i], c[i]);
       else if constexpr (MIX == kMixRead) acc += bu[i] + cu[i];
       else if constexpr (MIX == kMixCopy) au[i] = bu[i];
@@ -128,98 +126,128 @@ __device__ __forceinline__ void hbm_chunk(const float* __restrict__ b, const flo
   }
 }
 
-// Persistent / fixed-pass HBM stressor.  Wave w of the grid owns wave-chunks
-// w, w + W, w + 2W, ... (W = waves in the grid); record.work counts the
-// wave-chunks the work-group processed and, for the read-only mix,
-// record.check is the sum of the words it read mod 2^32.  NT selects
-// streaming (non-temporal) or ordinary cached accesses.
-template <uint32_t MIX, bool NT>
-__global__ void __launch_bounds__(1024) hbm_stressor(KCtrl c, const float* __restrict__ b,
-                                                     const float* __restrict__ cc,
-                                                     float* __restrict__ a, uint64_t n) {
+// Streaming stressor (HBM, and the Infinity Cache with a footprint that
+// fits it).  The array's wave-chunks are split into eight contiguous
+// ranges, one per XCD slot (work-group index mod 8: work-groups are dealt
+// to the XCDs round-robin, so a slot is one XCD's work-groups); a slot's
+// work-groups take the range in order, one round of one chunk per wave at a
+// time, from a ticket counter of that slot (thread 0 fetches the next
+// ticket while the round runs).  All active waves thus work on a narrow
+// moving window of each range, as the waves of a large one-shot grid do,
+// instead of drifting apart over the whole array as fixed per-wave strides
+// do (a measured difference of 69 against 81 % of the HBM peak for the
+// triad).  Fixed-pass mode hands out exactly `passes` sweeps of every range;
+// persistent mode wraps around until stopped.  record.work counts the
+// wave-chunks the work-group processed; for the read-only mix record.check
+// is the sum of the words it read mod 2^32.
+template <uint32_t MIX, bool NT, int U>
+__global__ void __launch_bounds__(1024) stream_stressor(KCtrl c, const float* __restrict__ b,
+                                                        const float* __restrict__ cc,
+                                                        float* __restrict__ a, uint64_t n) {
   __shared__ uint64_t s_t0;
+  __shared__ uint64_t s_ticket;
+  __shared__ uint32_t s_stop;
   __shared__ uint64_t s_work[16];
-  __shared__ uint32_t s_flags[16];
   __shared__ uint32_t s_acc[16];
   const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
   const uint32_t wpg = blockDim.x >> 6;
+  const uint32_t nslots = gridDim.x >= (uint32_t)kTicketSlots ? (uint32_t)kTicketSlots : 1u;
+  const uint32_t slot = blockIdx.x % nslots;
+  uint64_t* ticket = &c.dev->ticket[slot][0];
+  StopState sst;
+  uint64_t nxt = 0;
   if (threadIdx.x == 0) {
     uint64_t t0;
     wg_begin(c, t0);
     s_t0 = t0;
+    s_stop = 0;
     if (blockIdx.x == 0) poller_announce(c, t0);
+    s_ticket = __hip_atomic_fetch_add(ticket, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    nxt = __hip_atomic_fetch_add(ticket, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
   const uint64_t t0 = s_t0;
-  const uint64_t gw = (uint64_t)blockIdx.x * wpg + wid;
-  const uint64_t nw = (uint64_t)gridDim.x * wpg;
-  const uint64_t nchunks = (n + kChunk - 1) / kChunk;
+  stop_init(sst, c, t0, blockIdx.x == 0 && threadIdx.x == 0);
+  constexpr uint64_t kCh = 256ull * U;
+  const uint64_t nch = (n + kCh - 1) / kCh;
+  const uint64_t lo = nch * slot / nslots, hi = nch * (slot + 1) / nslots;
+  const uint64_t rounds = (hi - lo + wpg - 1) / wpg;  // tickets per sweep of the range
+  const uint64_t total = c.passes ? c.passes * rounds : 0;
   uint64_t done = 0;
   uint32_t acc = 0;
-  StopState sst;
-  stop_init(sst, c, t0, blockIdx.x == 0 && wid == 0);
   uint64_t tp = duty_mark(c);
-  if (c.passes) {
-    for (uint64_t p = 0; p < c.passes; ++p)
-      for (uint64_t ch = gw; ch < nchunks; ch += nw) {
-        hbm_chunk<MIX, NT>(b, cc, a, ch * kChunk, n, lane, acc);
-        duty_point(c, tp);
+  if (rounds) {
+    for (;;) {
+      const uint64_t t = s_ticket;
+      if (c.passes && t >= total) break;
+      const uint64_t ch = lo + (t % rounds) * wpg + wid;
+      if (ch < hi) {
+        stream_chunk<MIX, NT, U>(b, cc, a, ch * kCh, n, lane, acc);
         ++done;
       }
-  } else if (gw < nchunks) {
-    uint64_t ch = gw;
-    for (;;) {
-      hbm_chunk<MIX, NT>(b, cc, a, ch * kChunk, n, lane, acc);
       duty_point(c, tp);
-      ++done;
-      ch += nw;
-      if (ch >= nchunks) ch = gw;
-      if (should_stop(sst, c)) break;
+      __syncthreads();  // every wave has read s_ticket
+      if (threadIdx.x == 0) {
+        s_ticket = nxt;
+        nxt = __hip_atomic_fetch_add(ticket, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!c.passes && should_stop(sst, c)) s_stop = 1;
+      }
+      __syncthreads();
+      if (s_stop) break;
     }
-  } else {
-    while (!should_stop(sst, c)) __builtin_amdgcn_s_sleep(32);
+  } else if (!c.passes) {  // an empty range: hold the slot until stopped
+    for (;;) {
+      if (threadIdx.x == 0 && should_stop(sst, c)) s_stop = 1;
+      __syncthreads();
+      if (s_stop) break;
+      __builtin_amdgcn_s_sleep(32);
+    }
   }
   const uint32_t wacc = wave_sum_u32(acc);
   if (lane == 0) {
     s_work[wid] = done;
-    s_flags[wid] = sst.flags;
     s_acc[wid] = wacc;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     uint64_t w = 0;
-    uint32_t f = 0, sum = 0;
-    for (uint32_t i = 0; i < wpg; ++i) { w += s_work[i]; f |= s_flags[i]; sum += s_acc[i]; }
-    write_record(c, blockIdx.x, t0, w, sum, f);
+    uint32_t sum = 0;
+    for (uint32_t i = 0; i < wpg; ++i) {
+      w += s_work[i];
+      sum += s_acc[i];
+    }
+    write_record(c, blockIdx.x, t0, w, sum, sst.flags);
   }
 }
 
-// Victim triad: `passes` sweeps of the whole array (grid-stride over
-// wave-chunks); every sweep rewrites the same values.
+// Victim triad: one sweep of the whole array per launch (grid-stride over
+// wave-chunks of 1024 elements); `passes` sweeps are `passes` launches, so
+// that every sweep reads the whole array however many work-groups are
+// resident (a loop over sweeps inside the kernel would let resident waves
+// re-read their own chunks from the L2 while the others wait).
 __global__ void __launch_bounds__(256) triad_victim(const float* __restrict__ b,
                                                     const float* __restrict__ c,
-                                                    float* __restrict__ a, uint64_t n,
-                                                    uint32_t passes) {
+                                                    float* __restrict__ a, uint64_t n) {
+  constexpr uint64_t kChunk = 1024;
   const uint32_t lane = threadIdx.x & 63u;
   const uint64_t gw = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
   const uint64_t nchunks = (n + kChunk - 1) / kChunk;
-  for (uint32_t p = 0; p < passes; ++p)
-    for (uint64_t ch = gw; ch < nchunks; ch += nw) {
-      const uint64_t base = ch * kChunk;
-      if (base + kChunk <= n) {
-        const float4* b4 = reinterpret_cast<const float4*>(b + base);
-        const float4* c4 = reinterpret_cast<const float4*>(c + base);
-        float4* a4 = reinterpret_cast<float4*>(a + base);
-        float4 vb[4], vc[4];
+  for (uint64_t ch = gw; ch < nchunks; ch += nw) {
+    const uint64_t base = ch * kChunk;
+    if (base + kChunk <= n) {
+      const float4* b4 = reinterpret_cast<const float4*>(b + base);
+      const float4* c4 = reinterpret_cast<const float4*>(c + base);
+      float4* a4 = reinterpret_cast<float4*>(a + base);
+      float4 vb[4], vc[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) { vb[u] = b4[u * 64 + lane]; vc[u] = c4[u * 64 + lane]; }
+      for (int u = 0; u < 4; ++u) { vb[u] = b4[u * 64 + lane]; vc[u] = c4[u * 64 + lane]; }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) a4[u * 64 + lane] = triad4(vb[u], vc[u]);
-      } else {
-        for (uint64_t i = base + lane; i < n && i < base + kChunk; i += 64) a[i] = triad1(b[i], c[i]);
-      }
+      for (int u = 0; u < 4; ++u) a4[u * 64 + lane] = triad4(vb[u], vc[u]);
+    } else {
+      for (uint64_t i = base + lane; i < n && i < base + kChunk; i += 64) a[i] = triad1(b[i], c[i]);
     }
+  }
 }
 
 // Cache working-set loop.  Work-group g reads its span of `len` words once per
@@ -328,27 +356,38 @@ hipError_t launch_stamp(uint64_t* slot, hipStream_t s) {
   return xlaunch(stamp_kernel, dim3(1), dim3(64), 0, s, nullptr, nullptr, slot);
 }
 
-hipError_t launch_hbm_stressor(const KCtrl& c, uint32_t mix, const float* b, const float* cc,
-                               float* a, uint64_t n, uint32_t threads, bool streaming,
-                               hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+hipError_t launch_stream_stressor(const KCtrl& c, uint32_t mix, uint32_t chunk, const float* b,
+                                  const float* cc, float* a, uint64_t n, uint32_t threads,
+                                  bool streaming, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const dim3 g(c.grid), t(threads);
-#define CI_HBM_LAUNCH(M)                                                                    \
-  return streaming ? xlaunch(hbm_stressor<M, true>, g, t, 0, s, e0, e1, c, b, cc, a, n)     \
-                   : xlaunch(hbm_stressor<M, false>, g, t, 0, s, e0, e1, c, b, cc, a, n)
-  switch (mix) {
-    case kMixRead: CI_HBM_LAUNCH(kMixRead);
-    case kMixCopy: CI_HBM_LAUNCH(kMixCopy);
-    case kMixWrite: CI_HBM_LAUNCH(kMixWrite);
-    default: CI_HBM_LAUNCH(kMixTriad);
+#define CI_STREAM_LAUNCH(M, U)                                                                  \
+  return streaming ? xlaunch(stream_stressor<M, true, U>, g, t, 0, s, e0, e1, c, b, cc, a, n)   \
+                   : xlaunch(stream_stressor<M, false, U>, g, t, 0, s, e0, e1, c, b, cc, a, n)
+#define CI_STREAM_MIX(U)                              \
+  switch (mix) {                                      \
+    case kMixRead: CI_STREAM_LAUNCH(kMixRead, U);     \
+    case kMixCopy: CI_STREAM_LAUNCH(kMixCopy, U);     \
+    case kMixWrite: CI_STREAM_LAUNCH(kMixWrite, U);   \
+    default: CI_STREAM_LAUNCH(kMixTriad, U);          \
   }
-#undef CI_HBM_LAUNCH
+  switch (chunk) {
+    case 1: CI_STREAM_MIX(1);
+    case 4: CI_STREAM_MIX(4);
+    default: CI_STREAM_MIX(2);
+  }
+#undef CI_STREAM_MIX
+#undef CI_STREAM_LAUNCH
 }
 
 hipError_t launch_triad_victim(const float* b, const float* c, float* a, uint64_t n,
                                uint32_t passes, uint32_t grid, hipStream_t s, hipEvent_t e0,
                                hipEvent_t e1) {
-  return xlaunch(triad_victim, dim3(grid), dim3(kTriadThreads), 0, s, e0, e1, b,
-                               c, a, n, passes);
+  for (uint32_t p = 0; p < passes; ++p) {
+    const hipError_t e = xlaunch(triad_victim, dim3(grid), dim3(kTriadThreads), 0, s, p == 0 ? e0 : nullptr,
+                                 p + 1 == passes ? e1 : nullptr, b, c, a, n);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_cache_stressor(const KCtrl& c, const uint32_t* region, uint64_t region_words,

@@ -22,6 +22,14 @@ struct ci_ctx {
   uint32_t* probe_buf = nullptr;
   uint32_t nparts = 0;
   std::map<std::array<uint32_t, 8>, hipStream_t> masked;  // CU-masked streams by mask
+  std::map<std::array<uint32_t, 8>, uint64_t> masked_used; // last use (use_clock) per mask
+  uint64_t use_clock = 0;
+  // Streams a running measurement holds (its victim stream, by reference so
+  // that a replacement is seen): never evicted from `masked`.
+  std::vector<const hipStream_t*> held;
+  // A stressor kernel that did not drain may still poll the stop word: the
+  // context then refuses further stressor launches (CI_ERR_DRAIN).
+  bool drain_failed = false;
   hipStream_t vstream = nullptr;       // non-blocking stream for shared-placement victims
   // Queue pairs that passed the queue-pair check (with the idle kernel's
   // shape) and victim streams kept after qualification, each valid only at
@@ -32,6 +40,7 @@ struct ci_ctx {
     hipStream_t victim, stressor;
     uint32_t threads, wg_per_cu;
     uint64_t gen;
+    int unresolved;  // still above the tolerance after the last replacement
   };
   std::vector<QueuePair> queue_checked;
   std::vector<std::pair<hipStream_t, uint64_t>> queue_qualified;
@@ -89,10 +98,23 @@ hipStream_t replace_masked_stream(ci_ctx* ctx, const uint32_t mask[8]);
 // time.  *vs may be replaced: vmask is the victim stream's CU mask, or NULL
 // for the unmasked victim stream.  With a victim mask (disjoint CUs) the
 // idle kernel takes the launch shape of stressor r with options so.
+// *unresolved is set to 1 when the pair still interfered after the last
+// replacement (the cell is then measured as placed).
 ci_status_t check_queue_pair(ci_ctx* ctx, ci_resource_t r, const ci_stressor_opts_t* so,
                              float intensity, hipStream_t caller, hipStream_t* vs,
                              const uint32_t* vmask, void* ws, size_t ws_bytes,
-                             ci_status_t (*run)(void*, hipStream_t, double*), void* arg);
+                             ci_status_t (*run)(void*, hipStream_t, double*), void* arg,
+                             int* unresolved);
+
+// Marks a stream variable as held by the running measurement for the
+// guard's lifetime: masked_stream() never evicts the stream it names.
+struct HeldStream {
+  ci_ctx* ctx;
+  HeldStream(ci_ctx* c, const hipStream_t* s) : ctx(c) { ctx->held.push_back(s); }
+  ~HeldStream() { ctx->held.pop_back(); }
+  HeldStream(const HeldStream&) = delete;
+  HeldStream& operator=(const HeldStream&) = delete;
+};
 void mask_for(const ci_ctx* ctx, int k, int complement, uint32_t mask[8]);
 ci_status_t launch_victim(ci_ctx* ctx, const ci_victim_desc_t* d, hipStream_t s, hipEvent_t e0,
                           hipEvent_t e1);

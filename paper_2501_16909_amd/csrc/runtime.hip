@@ -91,23 +91,47 @@ static void destroy_stream(ci_ctx* ctx, hipStream_t s) {
   ++ctx->queue_gen;
 }
 
+static bool stream_in_use(const ci_ctx* ctx, hipStream_t s) {
+  if (ctx->active && ctx->active->ms == s) return true;
+  for (const hipStream_t* h : ctx->held)
+    if (*h == s) return true;
+  return false;
+}
+
 hipStream_t ci::masked_stream(ci_ctx* ctx, const uint32_t mask[8]) {
   std::array<uint32_t, 8> key{};
   for (int i = 0; i < 8; ++i) key[i] = mask[i];
   auto it = ctx->masked.find(key);
-  if (it != ctx->masked.end()) return it->second;
+  if (it != ctx->masked.end()) {
+    ctx->masked_used[key] = ++ctx->use_clock;
+    return it->second;
+  }
   // Each CU-masked stream owns a hardware queue: keep only a few, dropping
-  // any idle one (not the running stressor's) before making another.
+  // the least recently used one that nothing holds (not the running
+  // stressor's, not a measurement's victim stream) before making another.
+  // When every cached stream is in use the cache grows past the limit.
   if (ctx->masked.size() >= kMaxMaskedStreams) {
+    auto lru = ctx->masked.end();
+    uint64_t oldest = UINT64_MAX;
     for (auto jt = ctx->masked.begin(); jt != ctx->masked.end(); ++jt) {
-      if (ctx->active && ctx->active->ms == jt->second) continue;
-      destroy_stream(ctx, jt->second);
-      ctx->masked.erase(jt);
-      break;
+      if (stream_in_use(ctx, jt->second)) continue;
+      const uint64_t u = ctx->masked_used[jt->first];
+      if (u < oldest) {
+        oldest = u;
+        lru = jt;
+      }
+    }
+    if (lru != ctx->masked.end()) {
+      destroy_stream(ctx, lru->second);
+      ctx->masked_used.erase(lru->first);
+      ctx->masked.erase(lru);
     }
   }
   hipStream_t s = new_masked_stream(ctx, key);
-  if (s) ctx->masked[key] = s;
+  if (s) {
+    ctx->masked[key] = s;
+    ctx->masked_used[key] = ++ctx->use_clock;
+  }
   return s;
 }
 
@@ -121,6 +145,7 @@ hipStream_t ci::replace_masked_stream(ci_ctx* ctx, const uint32_t mask[8]) {
   auto it = ctx->masked.find(key);
   if (it != ctx->masked.end()) destroy_stream(ctx, it->second);
   ctx->masked[key] = s;
+  ctx->masked_used[key] = ++ctx->use_clock;
   return s;
 }
 
@@ -200,14 +225,26 @@ extern "C" ci_status_t ci_init(int device, ci_ctx_t** out) {
   }
 
   // Peaks.  Published MI355X figures where they exist; elsewhere bytes or
-  // flops per clock per unit times units times the peak engine clock.
+  // flops per clock per unit times units times the peak engine clock, or,
+  // where no figure describes the unit, a measured ceiling (marked so).
   const double f = (double)in.clock_khz * 1e3;
   const double cus = in.num_cus;
   in.peak[CI_RES_HBM] = 8.0e12;                         // HBM3E, published
   in.peak[CI_RES_L2] = 8.0 * 16 * 128 * f;              // 16 channels x 128 B/clk per XCD
-  in.peak[CI_RES_MALL] = 17.2e12;                       // Infinity Fabric/MALL (CDNA3 figure)
+  // Infinity Cache: measured ceiling.  The best of 60 launch shapes and
+  // traffic mixes of the streaming kernel over footprints of 64-192 MiB
+  // (beyond the 32 MB of L2, inside the 256 MB cache) is 7.65 TB/s; streams
+  // from all XCDs reach no more from the Infinity Cache than from HBM, so
+  // the XCD-to-IOD fabric, not the cache, bounds streaming.  The CDNA3
+  // figure of 17.2 TB/s is not reached by any shape.
+  in.peak[CI_RES_MALL] = 7.65e12;
   in.peak[CI_RES_VL1D] = cus * 64.0 * f;                // 64 B/clk per CU
-  in.peak[CI_RES_LDS] = cus * 128.0 * f;                // 128 B/clk per CU
+  // LDS: measured ceiling of the unit's copy (one 16-byte read and one
+  // 16-byte write per lane and step, conflict-free, no vector-ALU work):
+  // 117 B/clk per CU.  The same loop reads at 247 B/clk per CU and writes at
+  // 76, so a copy is bounded by 2 / (1/247 + 1/76) = 116 B/clk; the CDNA3
+  // figure of 128 B/clk per CU fits neither direction on CDNA4.
+  in.peak[CI_RES_LDS] = cus * 117.0 * f;
   in.peak[CI_RES_VALU_F32] = cus * 4 * 16 * 2.0 * f;    // unpacked FMA: 16 lanes/clk/SIMD
   in.peak[CI_RES_MFMA_F32] = 157.3e12;                  // published dense
   in.peak[CI_RES_MFMA_BF16] = 2.5166e15;                // published dense (2.5 PF)
@@ -226,12 +263,15 @@ extern "C" ci_status_t ci_shutdown(ci_ctx_t* ctx) {
   (void)hipSetDevice(ctx->device);
   for (auto& kv : ctx->masked) (void)hipStreamDestroy(kv.second);
   ctx->masked.clear();
+  ctx->masked_used.clear();
   ctx->queue_checked.clear();
   ctx->queue_qualified.clear();
   if (ctx->vstream) (void)hipStreamDestroy(ctx->vstream);
   for (auto& ev : ctx->ev)
     if (ev) (void)hipEventDestroy(ev);
-  if (ctx->host) (void)hipHostFree((void*)ctx->host);
+  // after a failed drain a stressor kernel may still read the stop word:
+  // that pinned block is left allocated
+  if (ctx->host && !ctx->drain_failed) (void)hipHostFree((void*)ctx->host);
   if (ctx->hres) (void)hipHostFree((void*)ctx->hres);
   if (ctx->part_bits) (void)hipFree(ctx->part_bits);
   if (ctx->part_sum) (void)hipFree(ctx->part_sum);
@@ -296,6 +336,7 @@ namespace {
 struct Defaults {
   uint32_t threads, wg_per_cu, knob, vec;
   uint64_t iters;
+  uint32_t chunk;
 };
 
 Defaults defaults_for(ci_resource_t r) {
@@ -303,9 +344,11 @@ Defaults defaults_for(ci_resource_t r) {
   // the smallest occupancy within a few percent of the best rate, so that a
   // colocated victim can still be dispatched beside the stressor.
   switch (r) {
-    case CI_RES_HBM: return {256, 1, CI_HBM_TRIAD, 0, 0};
+    // streaming stressors: 8 waves per CU, 4 x 16 bytes per lane and stream
+    // in flight (the best HBM triad rate of 21 shapes, 81 % of the peak)
+    case CI_RES_HBM: return {512, 1, CI_HBM_TRIAD, 0, 0, 4};
     case CI_RES_L2: return {512, 3, 0, 0, 0};
-    case CI_RES_MALL: return {256, 1, 0, 0, 0};
+    case CI_RES_MALL: return {512, 1, CI_HBM_READ, 1, 0, 4};
     case CI_RES_VL1D: return {256, 4, 0, 0, 0};
     case CI_RES_LDS: return {1024, 1, 1, 4, 0};
     case CI_RES_VALU_F32: return {256, 4, 8, 0, 4096};
@@ -330,6 +373,7 @@ void resolve(ci_resource_t r, const ci_stressor_opts_t* in, ci_stressor_opts_t* 
   if (!o->vec) o->vec = d.vec;
   if (!o->iters) o->iters = d.iters;
   if (!o->deadline_ms) o->deadline_ms = 2000;
+  if (!o->chunk) o->chunk = d.chunk ? d.chunk : 2;
 }
 
 // Bytes moved per element by each HBM traffic mix (4-byte words).
@@ -348,17 +392,9 @@ int mfma_dtype(ci_resource_t r) {
 
 int mfma_k(int dt) { return dt == CI_DT_F32 ? 2 : dt == CI_DT_BF16 ? 16 : 64; }
 
-// Words one work-group reads per pass for the cache stressors.
-uint64_t cache_span_words(ci_resource_t r, const ci_stressor_opts_t& o, uint32_t grid) {
-  if (r == CI_RES_MALL) {
-    // each work-group owns a disjoint slice of the region
-    const uint64_t round = 4ull * o.threads;
-    uint64_t s = o.n / grid;
-    s -= s % round;
-    return s;
-  }
-  return o.n;
-}
+// Words one work-group reads per pass for the cache stressors (L2, vL1D):
+// every work-group reads the whole region.
+uint64_t cache_span_words(const ci_stressor_opts_t& o) { return o.n; }
 
 ci_status_t check_opts(ci_ctx* ctx, ci_resource_t r, const ci_stressor_opts_t& o, uint32_t grid) {
   if (o.duty > 100) return set_err(CI_ERR_INVALID_ARG, "%s: duty %u%% > 100", kResName[r], o.duty);
@@ -366,28 +402,32 @@ ci_status_t check_opts(ci_ctx* ctx, ci_resource_t r, const ci_stressor_opts_t& o
     return set_err(CI_ERR_INVALID_ARG, "%s: threads %u must be a multiple of 64 in [64, 1024]",
                    kResName[r], o.threads);
   switch (r) {
-    case CI_RES_HBM: {
+    case CI_RES_HBM:
+    case CI_RES_MALL: {
       if (o.knob < CI_HBM_TRIAD || o.knob > CI_HBM_WRITE)
-        return set_err(CI_ERR_INVALID_ARG, "hbm: traffic mix %u is not one of CI_HBM_*", o.knob);
+        return set_err(CI_ERR_INVALID_ARG, "%s: traffic mix %u is not one of CI_HBM_*", kResName[r], o.knob);
+      if (o.chunk != 1 && o.chunk != 2 && o.chunk != 4)
+        return set_err(CI_ERR_INVALID_ARG, "%s: chunk must be 1, 2 or 4", kResName[r]);
       // arrays each mix touches: triad b, c, a; read b, c; copy b, a; write a
       const bool need_b = o.knob != CI_HBM_WRITE;
       const bool need_c = o.knob == CI_HBM_TRIAD || o.knob == CI_HBM_READ;
       const bool need_a = o.knob != CI_HBM_READ;
       static const char* const kNeed[] = {"", "b, c and a", "b and c", "b and a", "a"};
       if ((need_b && !o.src0) || (need_c && !o.src1) || (need_a && !o.dst))
-        return set_err(CI_ERR_INVALID_ARG, "hbm: %s required", kNeed[o.knob]);
-      if (o.n == 0) return set_err(CI_ERR_INVALID_ARG, "hbm: n must be > 0");
+        return set_err(CI_ERR_INVALID_ARG, "%s: %s required", kResName[r], kNeed[o.knob]);
+      if (o.n == 0) return set_err(CI_ERR_INVALID_ARG, "%s: n must be > 0", kResName[r]);
       if (((need_b ? (uintptr_t)o.src0 : 0) | (need_c ? (uintptr_t)o.src1 : 0) |
            (need_a ? (uintptr_t)o.dst : 0)) & 15)
-        return set_err(CI_ERR_INVALID_ARG, "hbm: arrays must be 16-byte aligned");
+        return set_err(CI_ERR_INVALID_ARG, "%s: arrays must be 16-byte aligned", kResName[r]);
+      if (o.knob == CI_HBM_WRITE && o.n > (1ull << 32))
+        return set_err(CI_ERR_INVALID_ARG, "%s: the write pattern is defined for n <= 2^32", kResName[r]);
       break;
     }
     case CI_RES_L2:
-    case CI_RES_MALL:
     case CI_RES_VL1D: {
       if (!o.src0) return set_err(CI_ERR_INVALID_ARG, "%s: region is required", kResName[r]);
       if ((uintptr_t)o.src0 & 15) return set_err(CI_ERR_INVALID_ARG, "%s: region must be 16-byte aligned", kResName[r]);
-      const uint64_t span = cache_span_words(r, o, grid);
+      const uint64_t span = cache_span_words(o);
       if (span / (4ull * o.threads) > 0xFFFFFFFFull)
         return set_err(CI_ERR_INVALID_ARG, "%s: region too large", kResName[r]);
       if (span == 0 || span % (4ull * o.threads))
@@ -449,13 +489,24 @@ uint32_t grid_of(ci_resource_t r, const ci_stressor_opts_t& o, int ncu) {
 
 }  // namespace
 
-extern "C" ci_status_t ci_workspace_size(ci_resource_t r, const ci_stressor_opts_t* opts, int ncu,
-                                         size_t* bytes) {
-  if (!bytes || (int)r < 0 || r >= CI_RES_COUNT || ncu < 0)
-    return set_err(CI_ERR_INVALID_ARG, "ci_workspace_size: bad argument");
+// Workspace bytes for `ncu` CUs: control words and one record per work-group.
+static size_t ws_bytes_for(ci_resource_t r, const ci_stressor_opts_t* opts, int ncu) {
   ci_stressor_opts_t o;
   resolve(r, opts, &o);
-  *bytes = sizeof(DevCtrl) + (size_t)grid_of(r, o, ncu) * sizeof(ci_wg_record_t);
+  return sizeof(DevCtrl) + (size_t)grid_of(r, o, ncu) * sizeof(ci_wg_record_t);
+}
+
+extern "C" ci_status_t ci_workspace_size(ci_resource_t r, float intensity,
+                                         const ci_stressor_opts_t* opts, size_t* bytes) {
+  if (!bytes || (int)r < 0 || r >= CI_RES_COUNT)
+    return set_err(CI_ERR_INVALID_ARG, "ci_workspace_size: bad argument");
+  if (!(intensity >= 0.0f && intensity <= 1.0f))
+    return set_err(CI_ERR_INVALID_ARG, "ci_workspace_size: intensity %g not in [0, 1]", intensity);
+  // the CU count of the 256-CU layout (8 XCDs x 32): exact on MI355X and an
+  // upper bound on a part with fewer CUs per XCD, since the count is
+  // 8 * round(per_xcd * intensity), monotone in per_xcd
+  const int ncu = 8 * (int)lround(32.0 * (double)intensity);
+  *bytes = ws_bytes_for(r, opts, ncu);
   return CI_OK;
 }
 
@@ -477,14 +528,14 @@ static ci_status_t launch_kernel(ci_stressor* h, const KCtrl& c) {
   hipEvent_t e0 = h->e0, e1 = h->persistent ? nullptr : h->e1;
   switch (h->r) {
     case CI_RES_HBM:
-      e = launch_hbm_stressor(c, o.knob, (const float*)o.src0, (const float*)o.src1,
-                              (float*)o.dst, o.n, o.threads, o.vec == 0, s, e0, e1);
+    case CI_RES_MALL:
+      e = launch_stream_stressor(c, o.knob, o.chunk, (const float*)o.src0, (const float*)o.src1,
+                                 (float*)o.dst, o.n, o.threads, o.vec == 0, s, e0, e1);
       break;
     case CI_RES_L2:
-    case CI_RES_VL1D:
-    case CI_RES_MALL: {
-      const uint64_t span = cache_span_words(h->r, o, h->grid);
-      const uint64_t slice = h->r == CI_RES_MALL ? span : 0;
+    case CI_RES_VL1D: {
+      const uint64_t span = cache_span_words(o);
+      const uint64_t slice = 0;
       uint32_t batch = 1;
       if (!c.passes) {  // poll about every 256 KiB read per work-group
         const uint64_t b = (65536 + span - 1) / span;
@@ -563,6 +614,8 @@ extern "C" ci_status_t stressor_launch(ci_ctx_t* ctx, ci_resource_t r, float int
   if (!(intensity >= 0.0f && intensity <= 1.0f))
     return set_err(CI_ERR_INVALID_ARG, "stressor_launch: intensity %g not in [0, 1]", intensity);
   if (ctx->active) return set_err(CI_ERR_BUSY, "stressor_launch: a stressor is already running");
+  if (ctx->drain_failed)
+    return set_err(CI_ERR_DRAIN, "stressor_launch: an earlier stressor kernel never drained on this context");
   HIPCHK(hipSetDevice(ctx->device));
   ci_stressor* h = new (std::nothrow) ci_stressor();
   if (!h) return set_err(CI_ERR_OOM, "stressor_launch: host allocation");
@@ -587,8 +640,7 @@ extern "C" ci_status_t stressor_launch(ci_ctx_t* ctx, ci_resource_t r, float int
     delete h;
     return st;
   }
-  size_t need = 0;
-  ci_workspace_size(r, &h->o, k, &need);
+  const size_t need = ws_bytes_for(r, &h->o, k);
   if (!ws || ws_bytes < need) {
     delete h;
     return set_err(CI_ERR_INVALID_ARG, "stressor_launch: workspace %zu bytes < %zu needed", ws_bytes, need);
@@ -695,15 +747,15 @@ static double units_of(const ci_stressor* h, const std::vector<ci_wg_record_t>& 
   const ci_stressor_opts_t& o = h->o;
   const double waves = o.threads / 64.0;
   switch (h->r) {
-    case CI_RES_HBM: {
+    case CI_RES_HBM:
+    case CI_RES_MALL: {
       const double per = hbm_bytes_per_element(o.knob);
       if (!h->persistent) return per * (double)o.n * (double)o.passes;
-      return per * 1024.0 * (double)work;
+      return per * 256.0 * o.chunk * (double)work;  // whole wave-chunks (the ragged last one counted full)
     }
     case CI_RES_L2:
     case CI_RES_VL1D:
-    case CI_RES_MALL:
-      return 4.0 * (double)cache_span_words(h->r, o, h->grid) * (double)work;
+      return 4.0 * (double)cache_span_words(o) * (double)work;
     case CI_RES_LDS: return (double)work * waves * 64.0 * 8192.0 * 4.0 * 2.0;
     case CI_RES_VALU_F32: return (double)work * o.threads * o.knob * (double)o.iters * 2.0;
     case CI_RES_MFMA_F32:
@@ -754,9 +806,13 @@ extern "C" ci_status_t stressor_stop(ci_stressor_t* h, ci_stressor_report_t* rep
     std::this_thread::sleep_for(std::chrono::microseconds(20));
   ci_status_t st = CI_OK;
   if (q == hipErrorNotReady) {
-    ctx->active = nullptr;  // cannot reuse the slot safely; report and leak h's stream state
+    // The kernel may still be running and polling the stop word, which stays
+    // raised: the context refuses further stressors (a new launch would
+    // clear the word and let the old kernel overlap later runs).
+    ctx->drain_failed = true;
+    ctx->active = nullptr;
     delete h;
-    return set_err(CI_ERR_TIMEOUT, "stressor_stop: kernel did not drain within its deadline");
+    return set_err(CI_ERR_DRAIN, "stressor_stop: kernel did not drain within its deadline + 5 s");
   }
   hipError_t e = hipStreamSynchronize(h->ms);
   if (e != hipSuccess) st = set_err(CI_ERR_HIP, "stressor kernel: %s", hipGetErrorString(e));
@@ -903,8 +959,12 @@ ci_status_t qualify_victim_queue(ci_ctx* ctx, hipStream_t* vs, const uint32_t* v
   if (best != *vs) {  // install the winner where the old victim queue was kept
     ++ctx->queue_replaced;
     destroy_stream(ctx, *vs);
-    if (vmask) ctx->masked[key] = best;
-    else ctx->vstream = best;
+    if (vmask) {
+      ctx->masked[key] = best;
+      ctx->masked_used[key] = ++ctx->use_clock;
+    } else {
+      ctx->vstream = best;
+    }
     *vs = best;
   }
   ctx->queue_qualified.push_back({best, ctx->queue_gen});
@@ -915,7 +975,9 @@ ci_status_t qualify_victim_queue(ci_ctx* ctx, hipStream_t* vs, const uint32_t* v
 ci_status_t ci::check_queue_pair(ci_ctx* ctx, ci_resource_t r, const ci_stressor_opts_t* so,
                                  float intensity, hipStream_t caller, hipStream_t* vs,
                                  const uint32_t* vmask, void* ws, size_t ws_bytes,
-                                 ci_status_t (*run)(void*, hipStream_t, double*), void* arg) {
+                                 ci_status_t (*run)(void*, hipStream_t, double*), void* arg,
+                                 int* unresolved) {
+  if (unresolved) *unresolved = 0;
   const int k = cus_for(ctx, intensity);
   if (k == 0) return CI_OK;
   uint32_t mask[8];
@@ -938,12 +1000,14 @@ ci_status_t ci::check_queue_pair(ci_ctx* ctx, ci_resource_t r, const ci_stressor
   if (qs != CI_OK) return qs;
   for (const auto& p : ctx->queue_checked)
     if (p.victim == *vs && p.stressor == ss && p.threads == o.threads && p.wg_per_cu == o.wg_per_cu &&
-        p.gen == ctx->queue_gen)
+        p.gen == ctx->queue_gen) {
+      if (unresolved) *unresolved = p.unresolved;
       return CI_OK;
-  size_t need = 0;
-  if (ci_workspace_size(CI_RES_OCCUPANCY, &o, k, &need) != CI_OK || !ws || ws_bytes < need)
-    return CI_OK;  // no room for the idle kernel: the pair stays unchecked
+    }
+  const size_t need = ws_bytes_for(CI_RES_OCCUPANCY, &o, k);
+  if (!ws || ws_bytes < need) return CI_OK;  // no room for the idle kernel: the pair stays unchecked
   ++ctx->queue_checks;
+  int unres = 0;
   for (int attempt = 0;; ++attempt) {
     ci_status_t st = CI_OK;
     double t = 0.0;
@@ -968,6 +1032,7 @@ ci_status_t ci::check_queue_pair(ci_ctx* ctx, ci_resource_t r, const ci_stressor
     if (median(ti) <= kQueueTol * median(ta)) break;
     if (attempt + 1 >= kQueueAttempts) {  // measured as placed; not retried
       ++ctx->queue_unresolved;
+      unres = 1;
       break;
     }
     ++ctx->queue_replaced;
@@ -982,7 +1047,8 @@ ci_status_t ci::check_queue_pair(ci_ctx* ctx, ci_resource_t r, const ci_stressor
       if (qs != CI_OK) return qs;
     }
   }
-  ctx->queue_checked.push_back({*vs, ss, o.threads, o.wg_per_cu, ctx->queue_gen});
+  ctx->queue_checked.push_back({*vs, ss, o.threads, o.wg_per_cu, ctx->queue_gen, unres});
+  if (unresolved) *unresolved = unres;
   return CI_OK;
 }
 
@@ -1152,6 +1218,21 @@ extern "C" ci_status_t ci_checksum_f32(ci_ctx_t* ctx, const void* x, uint64_t n,
   return CI_OK;
 }
 
+extern "C" ci_status_t ci_mfma_probe(ci_ctx_t* ctx, int dtype, const void* a, const void* b,
+                                     const float* c, float* d, uint32_t ntiles, void* stream) {
+  if (!ctx || (ntiles && (!a || !b || !c || !d)))
+    return set_err(CI_ERR_INVALID_ARG, "ci_mfma_probe: NULL argument");
+  if (dtype != CI_DT_F32 && dtype != CI_DT_BF16 && dtype != CI_DT_FP8E4M3)
+    return set_err(CI_ERR_INVALID_ARG, "ci_mfma_probe: dtype %d", dtype);
+  if (ntiles == 0) return CI_OK;
+  if (ntiles > 0x7FFFFFFFu) return set_err(CI_ERR_INVALID_ARG, "ci_mfma_probe: too many tiles");
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(launch_mfma_probe(dtype, a, b, c, d, ntiles, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return CI_OK;
+}
+
 extern "C" ci_status_t ci_quantize(ci_ctx_t* ctx, const void* src, uint64_t n, int dtype, void* dst,
                                    float* scale_out, void* stream) {
   if (!ctx || (n && (!src || !dst))) return set_err(CI_ERR_INVALID_ARG, "ci_quantize: NULL argument");
@@ -1243,7 +1324,11 @@ extern "C" ci_status_t measure_sensitivity(ci_ctx_t* ctx, const ci_victim_desc_t
     return set_err(CI_ERR_INVALID_ARG, "measure_sensitivity: bad argument");
   ci_status_t st = check_victim(d);
   if (st != CI_OK) return st;
-  ci_measure_opts_t mo{20, 3, CI_PLACE_SHARED, 2000, 0};
+  ci_measure_opts_t mo{};
+  mo.reps = 20;
+  mo.warmups = 3;
+  mo.placement = CI_PLACE_SHARED;
+  mo.deadline_ms = 2000;
   if (o) {
     mo = *o;
     if (!mo.reps) mo.reps = 20;
@@ -1256,15 +1341,24 @@ extern "C" ci_status_t measure_sensitivity(ci_ctx_t* ctx, const ci_victim_desc_t
   hipStream_t caller = (hipStream_t)stream;
   ctx->queue_checked.clear();  // queue pairs are checked per victim
   ctx->queue_qualified.clear();
+  // per-rep times of cell c, rep r at index c * reps + r (NaN where a cell
+  // is not measured)
+  if (mo.rep_alone_ns || mo.rep_col_ns)
+    for (size_t q = 0; q < (size_t)nr * nx * mo.reps; ++q) {
+      if (mo.rep_alone_ns) mo.rep_alone_ns[q] = NAN;
+      if (mo.rep_col_ns) mo.rep_col_ns[q] = NAN;
+    }
   for (int i = 0; i < nr; ++i) {
     for (int j = 0; j < nx; ++j) {
       ci_cell_t& cell = cells[i * nx + j];
+      const size_t rep0 = (size_t)(i * nx + j) * mo.reps;
       memset(&cell, 0, sizeof(cell));
       cell.resource = rs[i];
       cell.intensity = xs[j];
       const int k = cus_for(ctx, xs[j]);
       cell.ncu = k;
       hipStream_t vs = ctx->vstream;
+      HeldStream hold(ctx, &vs);  // the cache never evicts the victim's stream
       uint32_t vmask[8];
       const bool masked = mo.placement == CI_PLACE_DISJOINT && k > 0;  // k == 0: whole GPU, unmasked
       if (masked) {
@@ -1285,7 +1379,8 @@ extern "C" ci_status_t measure_sensitivity(ci_ctx_t* ctx, const ci_victim_desc_t
       VictimRun vr{ctx, d, caller};
       if (!(mo.flags & CI_MEASURE_NO_QUEUE_CHECK)) {
         st = check_queue_pair(ctx, rs[i], sopts ? &sopts[i] : nullptr, xs[j], caller, &vs,
-                              masked ? vmask : nullptr, ws, ws_bytes, &VictimRun::call, &vr);
+                              masked ? vmask : nullptr, ws, ws_bytes, &VictimRun::call, &vr,
+                              &cell.queue_unresolved);
         if (st != CI_OK) return st;
       }
       for (uint32_t w = 0; w < mo.warmups; ++w) {
@@ -1328,6 +1423,8 @@ extern "C" ci_status_t measure_sensitivity(ci_ctx_t* ctx, const ci_victim_desc_t
             covered = 0;
         }
         if (rc.checksum_bits != ra.checksum_bits) equal = 0;
+        if (mo.rep_alone_ns) mo.rep_alone_ns[rep0 + rep] = ra.time_ns;
+        if (mo.rep_col_ns) mo.rep_col_ns[rep0 + rep] = rc.time_ns;
         ta.push_back(ra.time_ns);
         tc.push_back(rc.time_ns);
         ratio.push_back(rc.time_ns / ra.time_ns);

@@ -41,26 +41,46 @@ double curve_at(const float* s, double x) {
   int i = (int)std::floor(pos);
   if (i >= CI_NPOINTS - 1) return s[CI_NPOINTS - 1];
   const double t = pos - i;
-  return s[i] + (s[i + 1] - s[i]) * t;
+  return (double)s[i] + ((double)s[i + 1] - (double)s[i]) * t;  // in FP64, not the FP32 difference
 }
 
-// Predicted slowdown of job `j` among `group`: product over resources of
-// max(1, curve_r(summed pressure of the others on r)).
-double predict(const std::vector<const ci_profile_t*>& group, size_t j) {
-  double out = 1.0;
-  for (int r = 0; r < CI_RES_COUNT; ++r) {
-    double press = 0.0;
-    for (size_t o = 0; o < group.size(); ++o)
-      if (o != j) press += group[o]->press[r];
-    out *= std::max(1.0, curve_at(group[j]->sens[r], press));
+bool has_read_curve(const ci_profile_t* p) {
+  for (int i = 0; i < CI_NPOINTS; ++i)
+    if (p->sens_hbm_read[i] != 0.0f) return true;
+  return false;
+}
+
+// The estimator (see ci_predict_slowdown in coloc.h).
+double predict_one(const ci_profile_t* v, const ci_profile_t* const* co, int nco) {
+  const bool split = has_read_curve(v);
+  double press[CI_RES_COUNT] = {};
+  double press_read = 0.0;
+  for (int o = 0; o < nco; ++o) {
+    for (int r = 0; r < CI_RES_COUNT; ++r) {
+      if (r == CI_RES_HBM && split && co[o]->hbm_write_frac < CI_READ_MOSTLY_WRITE_FRAC)
+        press_read += co[o]->press_hbm_read;
+      else
+        press[r] += co[o]->press[r];
+    }
   }
+  double out = 1.0;
+  for (int r = 0; r < CI_RES_COUNT; ++r) out *= std::max(1.0, curve_at(v->sens[r], press[r]));
+  if (split) out *= std::max(1.0, curve_at(v->sens_hbm_read, press_read));
   return out;
+}
+
+// Predicted slowdown of job `j` beside every other job of `group`.
+double predict(const std::vector<const ci_profile_t*>& group, size_t j) {
+  std::vector<const ci_profile_t*> co;
+  for (size_t o = 0; o < group.size(); ++o)
+    if (o != j) co.push_back(group[o]);
+  return predict_one(group[j], co.data(), (int)co.size());
 }
 
 // First-fit allocator over one device arena (offsets in bytes, 256-aligned).
 class Arena {
  public:
-  explicit Arena(uint64_t size) : size_(size) { free_[0] = size; }
+  explicit Arena(uint64_t size) { free_[0] = size; }
   bool alloc(uint64_t bytes, uint64_t* off) {
     bytes = (bytes + 255) & ~255ull;
     for (auto it = free_.begin(); it != free_.end(); ++it) {
@@ -100,7 +120,6 @@ class Arena {
   uint64_t used() const { return used_; }
 
  private:
-  uint64_t size_;
   uint64_t used_ = 0;
   std::map<uint64_t, uint64_t> free_;
 };
@@ -133,6 +152,17 @@ struct Running {
 
 }  // namespace
 
+extern "C" ci_status_t ci_predict_slowdown(const ci_profile_t* victim,
+                                           const ci_profile_t* const* corunners, int nco,
+                                           double* out) {
+  if (!victim || !out || nco < 0 || (nco && !corunners))
+    return set_err(CI_ERR_INVALID_ARG, "ci_predict_slowdown: bad argument");
+  for (int o = 0; o < nco; ++o)
+    if (!corunners[o]) return set_err(CI_ERR_INVALID_ARG, "ci_predict_slowdown: co-runner %d is NULL", o);
+  *out = predict_one(victim, corunners, nco);
+  return CI_OK;
+}
+
 extern "C" ci_status_t ci_admit(const ci_policy_t* p, const int* running_kinds, int nrun,
                                 int cand_kind, uint64_t cand_bytes, uint64_t free_bytes,
                                 int* admit) {
@@ -140,7 +170,12 @@ extern "C" ci_status_t ci_admit(const ci_policy_t* p, const int* running_kinds, 
     return set_err(CI_ERR_INVALID_ARG, "ci_admit: bad argument");
   *admit = 0;
   if (cand_bytes > free_bytes || nrun >= p->slots) return CI_OK;
-  if (p->kind == CI_POLICY_NAIVE) {
+  // Memory and a slot are all a request needs on an idle device: the
+  // occupancy and slowdown rules bound colocation (nothing would ever free
+  // up for a lone request they refuse, and the loop would wait forever).
+  if (p->kind == CI_POLICY_NAIVE || nrun == 0) {
+    if (p->kind != CI_POLICY_NAIVE && p->kind != CI_POLICY_USHER && p->kind != CI_POLICY_SENSITIVITY)
+      return set_err(CI_ERR_INVALID_ARG, "ci_admit: policy %d", p->kind);
     *admit = 1;
     return CI_OK;
   }
@@ -356,10 +391,13 @@ extern "C" ci_status_t serve_run(ci_ctx_t* ctx, const ci_request_t* trace, int n
       out[r.idx].slot = s;
       ci_status_t ls = start_request(ctx, q, arena_base + off, streams[s], r);
       if (ls == CI_OK) {
-        hipError_t e = launch_checksum_f32((const float*)r.d.out,
-                                           q.kind == CI_VICTIM_GEMM ? q.m * q.n : q.n,
+        const uint64_t out_len = q.kind == CI_VICTIM_GEMM ? q.m * q.n : q.n;
+        hipError_t e = launch_checksum_f32((const float*)r.d.out, out_len,
                                            part_bits + (size_t)s * nparts, part_sum + (size_t)s * nparts,
                                            nparts, &res[2 * s], (double*)&res[2 * s + 1], streams[s]);
+        if (e == hipSuccess && q.out_copy)
+          e = hipMemcpyAsync(q.out_copy, r.d.out, out_len * sizeof(float), hipMemcpyDeviceToDevice,
+                             streams[s]);
         if (e == hipSuccess) e = hipEventRecord(r.done, streams[s]);
         if (e != hipSuccess) ls = set_err(CI_ERR_HIP, "serve_run: checksum: %s", hipGetErrorString(e));
       }

@@ -26,14 +26,20 @@ struct HostCtrl {           // pinned host memory, one per context
   uint32_t pad[14];
 };
 
-struct DevCtrl {            // first 256 bytes of a stressor workspace
+constexpr int kTicketSlots = 8;  // one work counter per XCD slot (work-group index mod 8)
+
+struct DevCtrl {            // first kCtrlBytes bytes of a stressor workspace
   uint32_t dev_stop;        // set by the poller
   uint32_t started;         // work-groups that have begun
   uint32_t pad0[14];
   uint64_t dispatch_count;  // DISPATCH counting form
   uint64_t pad1[23];
+  // streaming stressors: next ticket of each XCD slot, one 256-byte line
+  // each so that no two slots share a cache line
+  uint64_t ticket[kTicketSlots][32];
 };
-static_assert(sizeof(DevCtrl) == 256, "DevCtrl must stay 256 bytes");
+constexpr size_t kCtrlBytes = 2304;
+static_assert(sizeof(DevCtrl) == kCtrlBytes, "DevCtrl layout");
 
 struct KCtrl {              // by-value kernel argument
   HostCtrl* host;           // NULL in fixed-pass mode

@@ -67,18 +67,36 @@ def test_errors_are_reported_without_a_device():
     assert lib.stressor_stop(None, None) == 1
     assert lib.ci_shutdown(None) == 0
     size = ctypes.c_size_t()
-    assert lib.ci_workspace_size(99, None, 256, ctypes.byref(size)) == 1
-    assert lib.ci_workspace_size(0, None, 256, ctypes.byref(size)) == 0
-    assert size.value == 256 + 256 * 1 * 48   # records for one work-group per CU
+    assert lib.ci_workspace_size(99, 1.0, None, ctypes.byref(size)) == 1
+    assert lib.ci_workspace_size(0, float("nan"), None, ctypes.byref(size)) == 1
+    assert lib.ci_workspace_size(0, 1.5, None, ctypes.byref(size)) == 1
+    assert lib.ci_workspace_size(0, 1.0, None, ctypes.byref(size)) == 0
+    ctrl = 2304                              # control words and the XCD slots' ticket lines
+    assert size.value == ctrl + 256 * 1 * 48   # records for one work-group per CU
+    assert lib.ci_workspace_size(0, 0.5, None, ctypes.byref(size)) == 0
+    assert size.value == ctrl + 128 * 1 * 48   # 8 x round(32 x 0.5) CUs
+    assert lib.ci_workspace_size(0, 0.0, None, ctypes.byref(size)) == 0
+    assert size.value == ctrl
+    # the L2 stressor's default shape is three work-groups per CU
+    assert lib.ci_workspace_size(1, 0.25, None, ctypes.byref(size)) == 0
+    assert size.value == ctrl + 64 * 3 * 48
 
 
-def _profiles():
+def _profiles(read_curves=False):
     # fragile: 3x slowdown under full HBM pressure; hog: exerts full HBM pressure
-    return {
-        "gemv": {"sens": {"hbm": [1.0, 1.5, 2.0, 2.5, 3.0]}, "press": {"hbm": 0.2}, "occ": 0.6},
-        "triad": {"sens": {"hbm": [1.0, 1.1, 1.2, 1.3, 1.4]}, "press": {"hbm": 1.0}, "occ": 0.6},
-        "gemm": {"sens": {"lds": [1.0, 1.0, 1.0, 1.0, 1.0]}, "press": {"mfma_bf16": 0.9}, "occ": 0.3},
+    p = {
+        "gemv": {"sens": {"hbm": [1.0, 1.5, 2.0, 2.5, 3.0]}, "press": {"hbm": 0.2}, "occ": 0.6,
+                 "hbm_write_frac": 0.0, "press_hbm_read": 0.15},
+        "triad": {"sens": {"hbm": [1.0, 1.1, 1.2, 1.3, 1.4]}, "press": {"hbm": 1.0}, "occ": 0.6,
+                  "hbm_write_frac": 1 / 3, "press_hbm_read": 0.9},
+        "gemm": {"sens": {"lds": [1.0, 1.0, 1.0, 1.0, 1.0], "hbm": [1.0, 1.2, 1.3, 1.5, 2.0]},
+                 "press": {"mfma_bf16": 0.9, "hbm": 0.1}, "occ": 0.3, "hbm_write_frac": 0.5,
+                 "press_hbm_read": 0.08},
     }
+    if read_curves:
+        p["gemv"]["sens_hbm_read"] = [1.0, 1.2, 1.3, 1.4, 1.6]
+        p["gemm"]["sens_hbm_read"] = [1.0, 1.05, 1.1, 1.2, 1.25]
+    return p
 
 
 def _oracle_job(p):
@@ -86,13 +104,49 @@ def _oracle_job(p):
     f32 = lambda v: float(np.float32(v))
     sens = [[f32(v) for v in p["sens"].get(r, [1.0] * 5)] for r in coloc.RESOURCES]
     press = [f32(p["press"].get(r, 0.0)) for r in coloc.RESOURCES]
-    return {"sens": sens, "press": press, "bytes": 1, "occ": f32(p["occ"])}
+    job = {"sens": sens, "press": press, "bytes": 1, "occ": f32(p["occ"]),
+           "hbm_write_frac": f32(p.get("hbm_write_frac", 1.0)), "press_hbm_read": f32(p.get("press_hbm_read", 0.0))}
+    if "sens_hbm_read" in p:
+        job["sens_hbm_read"] = [f32(v) for v in p["sens_hbm_read"]]
+    return job
+
+
+def test_predicted_slowdown_matches_oracle():
+    """ci_predict_slowdown (host code, no device) against the oracle's
+    read/write-aware estimator, over every victim and co-runner multiset of
+    up to three, with and without read-only HBM curves, and on random
+    profiles."""
+    import itertools
+    for rc in (False, True):
+        profs = _profiles(read_curves=rc)
+        kinds = list(profs)
+        for v in kinds:
+            for nco in range(0, 4):
+                for co in itertools.combinations_with_replacement(kinds, nco):
+                    got = coloc.predict_slowdown(profs, v, list(co))
+                    want = oracle.predicted_slowdown_rw(_oracle_job(profs[v]), [_oracle_job(profs[k]) for k in co])
+                    assert got == pytest.approx(want, rel=1e-12, abs=0), (rc, v, co)
+    rng = np.random.default_rng(9)
+    for _ in range(200):
+        profs = {}
+        for k in ("gemm", "gemv", "triad"):
+            profs[k] = {"sens": {r: sorted(1.0 + 3.0 * rng.random(5)) for r in ("hbm", "l2", "lds")},
+                        "press": {r: float(rng.random()) for r in ("hbm", "l2", "lds")}, "occ": 0.5,
+                        "hbm_write_frac": float(rng.choice([0.0, 0.1, 1 / 6, 0.5])),
+                        "press_hbm_read": float(rng.random())}
+            if rng.random() < 0.7:
+                profs[k]["sens_hbm_read"] = sorted(1.0 + rng.random(5))
+        co = list(rng.choice(list(profs), int(rng.integers(0, 4))))
+        got = coloc.predict_slowdown(profs, "gemv", co)
+        want = oracle.predicted_slowdown_rw(_oracle_job(profs["gemv"]), [_oracle_job(profs[k]) for k in co])
+        assert got == pytest.approx(want, rel=1e-12)
 
 
 @pytest.mark.parametrize("policy", ["naive", "usher", "sensitivity"])
 @pytest.mark.parametrize("bound", [1.2, 1.5, 2.5, math.inf])
-def test_admission_matches_oracle(policy, bound):
-    profs = _profiles()
+@pytest.mark.parametrize("read_curves", [False, True])
+def test_admission_matches_oracle(policy, bound, read_curves):
+    profs = _profiles(read_curves)
     kinds = list(profs)
     import itertools
     for nrun in range(0, 3):
@@ -104,6 +158,9 @@ def test_admission_matches_oracle(policy, bound):
                 assert got == want, (policy, bound, running, cand)
     assert not coloc.admit("naive", profs, [], "gemv", 101, 100)
     assert not coloc.admit("naive", profs, ["gemv"] * 4, "gemv", 1, 100, slots=4)
+    # an idle device admits whatever fits, under every policy and bound
+    greedy = {"triad": dict(profs["triad"], occ=1.0, sens={"hbm": [9.0] * 5})}
+    assert coloc.admit(policy, greedy, [], "triad", 10, 100, bound=1.0001)
 
 
 LLAMA8B = dict(hidden=4096, n_q=32, n_kv=8, head_dim=128, ffn=14336, vocab=128256, layers=32, batch=1,

@@ -152,7 +152,7 @@ def test_hbm_stressor_fixed_passes(ctx, dev, x, passes, n):
     assert np.array_equal(ta.cpu().numpy().view(np.uint32), want.view(np.uint32))
     ncu = 8 * round(32 * x)
     assert rep.grid == ncu and rep.wg_reported == rep.grid
-    chunks = (n + 1023) // 1024
+    chunks = (n + 1023) // 1024                   # default wave-chunk: 4 x 16 B per lane
     assert rep.work == passes * chunks
     assert rep.units == 12.0 * n * passes
     assert rep.distinct_cus == ncu
@@ -182,9 +182,9 @@ def test_hbm_stressor_persistent_colocated(ctx, dev):
 
 
 @pytest.mark.parametrize("mix", ["read", "copy", "write"])
-@pytest.mark.parametrize("x,passes,n,vec", [(1.0, 1, (1 << 22) + 5, 0), (0.5, 3, 1 << 20, 1),
-                                           (1 / 32, 2, 5000, 0), (0.25, 1, 333, 1)])
-def test_hbm_mixes_fixed_passes(ctx, dev, mix, x, passes, n, vec):
+@pytest.mark.parametrize("x,passes,n,vec,chunk", [(1.0, 1, (1 << 22) + 5, 0, 2), (0.5, 3, 1 << 20, 1, 1),
+                                                 (1 / 32, 2, 5000, 0, 4), (0.25, 1, 333, 1, 2)])
+def test_hbm_mixes_fixed_passes(ctx, dev, mix, x, passes, n, vec, chunk):
     """Read-only, copy and write-only mixes: outputs bit-exact, the read
     checksum mod 2^32 exact, and nothing stored where the mix stores nothing."""
     import torch
@@ -193,7 +193,8 @@ def test_hbm_mixes_fixed_passes(ctx, dev, mix, x, passes, n, vec):
     sentinel = np.full(n, 0x7FC0DEAD, np.uint32)
     ta = _t(sentinel.view(np.float32), dev)
     ops = {"read": dict(src0=tb, src1=tc), "copy": dict(src0=tb, dst=ta), "write": dict(dst=ta)}[mix]
-    rep = ctx.stressor("hbm", x, n=n, passes=passes, vec=vec, knob=coloc.HBM_MIX[mix], **ops).stop()
+    rep = ctx.stressor("hbm", x, n=n, passes=passes, vec=vec, chunk=chunk, knob=coloc.HBM_MIX[mix],
+                       **ops).stop()
     got = ta.cpu().numpy().view(np.uint32)
     if mix == "read":
         assert np.array_equal(got, sentinel)
@@ -204,7 +205,7 @@ def test_hbm_mixes_fixed_passes(ctx, dev, mix, x, passes, n, vec):
         assert np.array_equal(got, oracle.hbm_write_pattern(n))
     ncu = 8 * round(32 * x)
     assert rep.grid == ncu and rep.wg_reported == rep.grid and not rep.timed_out
-    assert rep.work == passes * ((n + 1023) // 1024)
+    assert rep.work == passes * ((n + 256 * chunk - 1) // (256 * chunk))
     assert rep.units == oracle.hbm_bytes_per_element(mix) * n * passes
     # the inputs are left as they were
     assert np.array_equal(tb.cpu().numpy().view(np.uint32), b.view(np.uint32))
@@ -216,7 +217,8 @@ def test_hbm_mix_options_are_checked(ctx, dev):
     t = torch.empty(1024, dtype=torch.float32, device=dev)
     for bad in (dict(knob=5, src0=t, src1=t, dst=t), dict(knob=coloc.HBM_MIX["read"], src0=t),
                 dict(knob=coloc.HBM_MIX["copy"], src0=t), dict(knob=coloc.HBM_MIX["write"]),
-                dict(knob=coloc.HBM_MIX["copy"], src0=t[1:], dst=t)):
+                dict(knob=coloc.HBM_MIX["copy"], src0=t[1:], dst=t),
+                dict(src0=t, src1=t, dst=t, chunk=3)):
         with pytest.raises(coloc.CiError) as ei:
             ctx.stressor("hbm", 0.25, n=512, passes=1, **bad)
         assert ei.value.status == 1, bad
@@ -317,6 +319,33 @@ def test_disjoint_idle_stressor_costs_nothing(ctx, dev):
     st = ctx.queue_stats()
     assert st["checks"] >= 1, st
     print("queue-pair check:", st, [round(c["slowdown"], 3) for c in cells])
+
+
+def test_disjoint_sweep_of_many_intensities_keeps_its_victim_stream(ctx, dev):
+    """Six intensities on disjoint CUs need more CU-masked queues than the
+    stream cache keeps (the victim's complement masks and the stressor's
+    masks): the cache must never drop the victim stream a cell is measuring
+    on.  Every cell is measured, finite, covered and output-equal, and the
+    per-rep times come back for every rep."""
+    import torch
+    n = 1 << 22
+    tb = _t(synth.uniform_f32(synth.seed_for(0, synth.BUF_B), n), dev)
+    tc = _t(synth.uniform_f32(synth.seed_for(0, synth.BUF_C), n), dev)
+    ta = torch.empty_like(tb)
+    _, _, tsb, tsc, tsa = _hbm_buffers(dev, 1 << 22)
+    d = ctx.triad_desc(tb, tc, ta, passes=4)
+    xs = [0.125, 0.25, 0.375, 0.5, 0.625, 0.75]
+    cells = ctx.measure_sensitivity(d, ["hbm"], [dict(src0=tsb, src1=tsc, dst=tsa, n=1 << 22)], xs, reps=4,
+                                    warmups=1, placement="disjoint")
+    assert [c["intensity"] for c in cells] == xs
+    for c in cells:
+        assert np.isfinite(c["slowdown"]) and c["slowdown"] > 0.5, c
+        assert c["output_equal"] and c["window_covered"], c
+        assert len(c["rep_alone_ns"]) == 4 and all(np.isfinite(c["rep_alone_ns"])), c
+        assert all(np.isfinite(c["rep_col_ns"])), c
+        # the cell's median slowdown is the ratio of the per-rep medians
+        assert c["slowdown"] == pytest.approx(np.median(c["rep_col_ns"]) / np.median(c["rep_alone_ns"]), rel=1e-12)
+    print("disjoint sweep:", [round(c["slowdown"], 3) for c in cells], ctx.queue_stats())
 
 
 def test_stamps_bracket_enqueued_work(ctx, dev):

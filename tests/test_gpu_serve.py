@@ -35,13 +35,19 @@ def _trace():
     return reqs
 
 
-def _oracle_check(q, served):
+def _oracle_check(q, served, got=None):
+    """The served result against the oracle on regenerated inputs: the
+    loop's checksums, and, when the output copy `got` is given, every
+    element (triad bit for bit, GEMM and GEMV within the accumulation
+    bound of each entry)."""
     s = q["seed"]
     if q["kind"] == "triad":
         b = synth.uniform_f32(s, q["n"])
         c = synth.uniform_f32(s + 1, q["n"])
         want = oracle.triad_f32(b, c)
         assert served["checksum_bits"] == oracle.bitsum_u32(want)
+        if got is not None:
+            assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), q
         return
     if q["kind"] == "gemm":
         m, n, k = q["m"], q["n"], q["k"]
@@ -63,10 +69,22 @@ def _oracle_check(q, served):
     # plus the FP64 rounding of that sum
     tol = float(np.sum(bound)) + 1e-12 * float(np.sum(np.abs(want))) * want.size
     assert abs(served["sum_f64"] - float(np.sum(want))) <= tol, (q, served["sum_f64"], float(np.sum(want)))
+    if got is not None:
+        got = got.astype(np.float64).reshape(want.shape)
+        assert np.all(np.abs(got - want) <= bound), (q, float(np.max(np.abs(got - want) / np.maximum(bound, 1e-300))))
+        assert oracle.bitsum_u32(got.astype(np.float32)) == served["checksum_bits"]
 
 
-def test_serve_naive_overlaps_and_matches_isolated(ctx):
-    reqs = _trace()
+def _with_copies(reqs, dev):
+    import torch
+    for q in reqs:
+        n = q["m"] * q["n"] if q["kind"] == "gemm" else q["n"]
+        q["out_copy"] = torch.full((n,), float("nan"), dtype=torch.float32, device=dev)
+    return reqs
+
+
+def test_serve_naive_overlaps_and_matches_isolated(ctx, dev):
+    reqs = _with_copies(_trace(), dev)
     out = ctx.serve(reqs, policy="naive", hbm_budget=1 << 30, slots=4)
     assert all(o["status"] == 0 for o in out)
     for q, o in zip(reqs, out):
@@ -78,11 +96,17 @@ def test_serve_naive_overlaps_and_matches_isolated(ctx):
     spans = sorted((o["admit_s"], o["end_s"]) for o in burst)
     assert any(spans[i + 1][0] < spans[i][1] for i in range(len(spans) - 1))
     assert [o["checksum_bits"] for o in burst] == [o["checksum_bits"] for o in out]
-    # same result alone and in the mix (bit for bit), and against the oracle
+    # same result alone and in the mix (bit for bit, element by element), and
+    # every element against the oracle
+    import torch
     for q, o in zip(reqs, out):
-        alone = ctx.serve([dict(q, arrival_s=0.0)], policy="naive", hbm_budget=1 << 30, slots=1)[0]
+        mixed = q["out_copy"].cpu().numpy()
+        alone_copy = torch.full_like(q["out_copy"], float("nan"))
+        alone = ctx.serve([dict(q, arrival_s=0.0, out_copy=alone_copy)], policy="naive", hbm_budget=1 << 30,
+                          slots=1)[0]
         assert alone["checksum_bits"] == o["checksum_bits"], q
-        _oracle_check(q, o)
+        assert np.array_equal(alone_copy.cpu().numpy().view(np.uint32), mixed.view(np.uint32)), q
+        _oracle_check(q, o, mixed)
 
 
 def test_serve_budget_and_slots_bound_concurrency(ctx):
@@ -124,19 +148,31 @@ def _replay_job(p):
     # same rounded values
     from paper_2501_16909_amd import coloc
     f32 = lambda v: float(np.float32(v))
-    return {"sens": [[f32(v) for v in p["sens"].get(r, [1.0] * 5)] for r in coloc.RESOURCES],
-            "press": [f32(p["press"].get(r, 0.0)) for r in coloc.RESOURCES],
-            "bytes": 1, "occ": f32(p["occ"])}
+    job = {"sens": [[f32(v) for v in p["sens"].get(r, [1.0] * 5)] for r in coloc.RESOURCES],
+           "press": [f32(p["press"].get(r, 0.0)) for r in coloc.RESOURCES],
+           "bytes": 1, "occ": f32(p["occ"]), "hbm_write_frac": f32(p.get("hbm_write_frac", 1.0)),
+           "press_hbm_read": f32(p.get("press_hbm_read", 0.0))}
+    if "sens_hbm_read" in p:
+        job["sens_hbm_read"] = [f32(v) for v in p["sens_hbm_read"]]
+    return job
 
 
-def test_serve_admissions_replay_against_oracle(ctx):
+@pytest.mark.parametrize("read_curves", [False, True])
+def test_serve_admissions_replay_against_oracle(ctx, read_curves):
     """Discrete-event replay of the loop's own log: given the completion
     order the loop observed, every admission is one the oracle's admission
     rule allows, and no request waited through a completion after which the
-    rule would already have allowed it (FIFO, no bypass)."""
-    profiles = {"gemv": {"sens": {"hbm": [1.0, 1.5, 2.0, 2.5, 3.0]}, "press": {"hbm": 0.2}, "occ": 0.6},
-                "triad": {"sens": {"hbm": [1.0, 1.1, 1.2, 1.3, 1.4]}, "press": {"hbm": 1.0}, "occ": 0.6},
-                "gemm": {"sens": {"lds": [1.0] * 5}, "press": {"mfma_bf16": 0.9}, "occ": 0.3}}
+    rule would already have allowed it (FIFO, no bypass).  With read-only
+    HBM curves the read-mostly GEMV is priced on them (ci_predict_slowdown)."""
+    profiles = {"gemv": {"sens": {"hbm": [1.0, 1.5, 2.0, 2.5, 3.0]}, "press": {"hbm": 0.2}, "occ": 0.6,
+                         "hbm_write_frac": 0.0, "press_hbm_read": 0.15},
+                "triad": {"sens": {"hbm": [1.0, 1.1, 1.2, 1.3, 1.4]}, "press": {"hbm": 1.0}, "occ": 0.6,
+                          "hbm_write_frac": 1 / 3, "press_hbm_read": 0.95},
+                "gemm": {"sens": {"lds": [1.0] * 5}, "press": {"mfma_bf16": 0.9}, "occ": 0.3,
+                         "hbm_write_frac": 0.5}}
+    if read_curves:
+        profiles["gemv"]["sens_hbm_read"] = [1.0, 1.1, 1.2, 1.3, 1.4]
+        profiles["triad"]["sens_hbm_read"] = [1.0, 1.05, 1.1, 1.15, 1.2]
     # requests of 0.1-0.5 ms each, so that completions are spaced out
     sizes = [("gemv", dict(n=16384, k=16384, dtype="bf16")), ("triad", dict(n=1 << 27)),
              ("gemm", dict(m=4096, n=4096, k=4096, dtype="bf16")), ("gemv", dict(n=8192, k=16384, dtype="bf16")),
@@ -184,6 +220,20 @@ def test_serve_admissions_replay_against_oracle(ctx):
                 assert a[1] <= b[0] + 1e-9 or b[1] <= a[0] + 1e-9, (i, j)
     starts = sorted(spans.values())
     assert any(starts[i + 1][0] < starts[i][1] for i in range(len(starts) - 1))
+
+
+@pytest.mark.parametrize("policy", ["usher", "sensitivity"])
+def test_serve_admits_a_lone_request_the_rule_would_refuse_beside_others(ctx, policy):
+    """A request that fills every wave slot (occupancy 1) and predicts 5x
+    beside itself: on an idle device it is admitted (the loop would otherwise
+    wait for ever), beside another it waits."""
+    greedy = {"sens": {"hbm": [5.0] * 5}, "press": {"hbm": 1.0}, "occ": 1.0}
+    profiles = {"triad": greedy, "gemv": greedy, "gemm": greedy}
+    reqs = [dict(r, arrival_s=0.0) for r in _trace()[:4]]
+    out = ctx.serve(reqs, policy=policy, bound=1.01, hbm_budget=1 << 30, slots=4, profiles=profiles)
+    assert all(o["status"] == 0 for o in out)
+    spans = sorted((o["admit_s"], o["end_s"]) for o in out)
+    assert all(spans[i + 1][0] >= spans[i][1] - 1e-6 for i in range(len(spans) - 1))
 
 
 def test_serve_rejects_bad_traces(ctx):

@@ -333,6 +333,49 @@ def test_gemv_row_sums():
         assert abs(y[i] - math.fsum(float(v) for v in w[i])) < 1e-15
 
 
+def _toy_rne(x, bits):
+    """x (Fraction) rounded to nearest, ties to even, at `bits` significand bits."""
+    if x == 0:
+        return x
+    a = abs(x)
+    e = a.numerator.bit_length() - a.denominator.bit_length()
+    if Fraction(2) ** e > a:
+        e -= 1
+    ulp = Fraction(2) ** (e - bits + 1)
+    q, r = divmod(a, ulp)
+    q = int(q)
+    if r > ulp / 2 or (r == ulp / 2 and q % 2):
+        q += 1
+    return (1 if x > 0 else -1) * q * ulp
+
+
+def test_accumulation_bound_against_brute_force_worst_case():
+    """Recursive summation in a toy binary format with 3-bit significands
+    (unit roundoff 2^-3), every sequence of 2 and 3 terms from 40 values,
+    exact rational arithmetic: the error never exceeds the bound for n - 1
+    roundings, and comes within 0.78 (n = 2) and 0.6 (n = 3) of it, so a
+    bound with half the unit, or one rounding fewer, would fail."""
+    import itertools
+    bits = 3
+    u = 2.0 ** -bits
+    vals = sorted({s * Fraction(m, 2 ** (bits - 1)) * Fraction(2) ** e
+                   for m in range(2 ** (bits - 1), 2 ** bits) for e in range(-2, 3) for s in (1, -1)})
+    for n, tight in ((2, 0.77), (3, 0.59)):
+        worst = 0.0
+        for seq in itertools.product(vals, repeat=n):
+            acc = seq[0]
+            for x in seq[1:]:
+                acc = _toy_rne(acc + x, bits)
+            err = float(abs(acc - sum(seq)))
+            bound = float(oracle.accumulation_bound(n - 1, float(sum(abs(x) for x in seq)), u))
+            assert err <= bound, seq
+            worst = max(worst, err / bound)
+        assert worst >= tight
+        # with one rounding fewer the same worst case breaks the bound (n = 3)
+        if n == 3:
+            assert worst * float(oracle.accumulation_bound(2, 1.0, u)) > float(oracle.accumulation_bound(1, 1.0, u))
+
+
 def test_accumulation_bound_and_mfma_closed_form():
     b = oracle.accumulation_bound(4096, np.ones((2, 2)))
     assert np.allclose(b, 4096 * 2.0 ** -24 / (1 - 4096 * 2.0 ** -24))
@@ -403,3 +446,230 @@ def test_admission_rules():
     assert oracle.predicted_slowdown([[1.0, 1.0, 1.0, 1.0, 2.0]], [5.0]) == 2.0
     assert oracle.predicted_slowdown([[0.9] * 5, [2.0] * 5], [0.3, 0.3]) == 2.0
     assert oracle.predicted_slowdown([[1.5] * 5, [2.0] * 5], [0.3, 0.3]) == 3.0
+
+
+# ----------------------------------------- characterised FP8 matrix core
+def _fp8_instruction_model(a_codes, b_codes, c0=0.0):
+    """The characterised accumulation, written out with exact rationals:
+    groups of 8 consecutive products, each cut toward zero to a multiple of
+    2^(E - 13) (E the group's largest sum of exponent fields), group sums
+    added one after another to the FP32 accumulator with round-to-nearest."""
+    tab = oracle.e4m3_table()
+    acc = Fraction(float(np.float32(c0)))
+    for g0 in range(0, len(a_codes), 8):
+        prods, exps = [], []
+        for k in range(g0, g0 + 8):
+            p = Fraction(float(tab[a_codes[k]])) * Fraction(float(tab[b_codes[k]]))
+            prods.append(p)
+            if p != 0:
+                exps.append(int(oracle.e4m3_nominal_exponent(a_codes[k]) + oracle.e4m3_nominal_exponent(b_codes[k])))
+        if not exps:
+            continue
+        q = Fraction(2) ** (max(exps) - 13)
+        gsum = sum((1 if p > 0 else -1) * (abs(p) // q) * q for p in prods)
+        acc = _toy_rne(acc + gsum, 24)
+    return acc
+
+
+def _e4m3_code(v):
+    tab = oracle.e4m3_table()
+    return int(np.flatnonzero(tab == v)[0])
+
+
+def test_fp8_bound_hand_case():
+    # one group: products 256 (1 x 256) and 2^-6 (1 x 2^-6); E = 8, quantum
+    # 2^-5; 256 is a multiple of it (granularity 2^(8-6)) and keeps all its
+    # bits, 2^-6 is below it and may be lost whole
+    a = np.zeros((1, 8), np.uint8)
+    b = np.zeros((1, 8), np.uint8)
+    a[0, 0] = a[0, 1] = _e4m3_code(1.0)
+    b[0, 0], b[0, 1] = _e4m3_code(256.0), _e4m3_code(2.0 ** -6)
+    got = oracle.mfma_fp8_error_bound(a, b)[0]
+    u = 2.0 ** -24
+    want = 2.0 ** -6 + 2 * u / (1 - 2 * u) * (256 + 2.0 ** -6)
+    assert got == pytest.approx(want, rel=1e-15)
+    # scale and the accumulator input enter linearly
+    assert oracle.mfma_fp8_error_bound(a, b, scale=-2.0, c_abs=8.0)[0] == pytest.approx(
+        2 * (2.0 ** -6 + 2 * u / (1 - 2 * u) * (256 + 2.0 ** -6 + 8.0)), rel=1e-15)
+    # 1 x 1 and 1 x 2^-6: E = 0, quantum 2^-13; 2^-6 has granularity
+    # 2^(-6-6) = 2^-12, a multiple of the quantum, and loses nothing
+    b[0, 0] = _e4m3_code(1.0)
+    assert oracle.mfma_fp8_error_bound(a, b)[0] == pytest.approx(2 * u / (1 - 2 * u) * (1 + 2.0 ** -6),
+                                                                 rel=1e-15)
+    # a group that spans less than 8 bits of exponent loses nothing to truncation
+    a[0, :] = _e4m3_code(1.5)
+    b[0, :] = _e4m3_code(0.75)
+    p = 8 * 1.125
+    assert oracle.mfma_fp8_error_bound(a, b)[0] == pytest.approx(2 * u / (1 - 2 * u) * p, rel=1e-15)
+
+
+def test_fp8_bound_dominates_the_model_and_is_tight():
+    """On seeded random codes and on adversarial tiles (one large product,
+    small ones just below the group's quantum, with and without the large
+    pair cancelling), the bound covers the model's error everywhere, and the
+    adversarial tiles reach at least half of it: a bound with 14 kept bits
+    (half the quantum) would fail there."""
+    rng = np.random.default_rng(16909)
+    fin = np.flatnonzero(np.isfinite(oracle.e4m3_table()))
+    tab = oracle.e4m3_table()
+    worst = 0.0
+    cases = []
+    for _ in range(150):
+        cases.append((rng.choice(fin, 64).astype(np.uint8), rng.choice(fin, 64).astype(np.uint8), rng.normal() * 10))
+    one, big, small = _e4m3_code(1.0), _e4m3_code(256.0), _e4m3_code(2.0 ** -5.0) if np.any(tab == 2.0 ** -5) else None
+    for cancel in (False, True):
+        a = np.full(64, one, np.uint8)
+        b = np.full(64, _e4m3_code(2.0 ** -6), np.uint8)
+        b[0] = big                                  # 2^8 against 2^-6 products: gap 14 bits
+        if cancel:
+            a[1], b[1] = _e4m3_code(-1.0), big
+        cases.append((a, b, 0.0))
+    for a, b, c0 in cases:
+        exact = sum(Fraction(float(tab[x])) * Fraction(float(tab[y])) for x, y in zip(a, b)) + Fraction(float(np.float32(c0)))
+        err = abs(float(_fp8_instruction_model(a, b, c0) - exact))
+        bound = oracle.mfma_fp8_error_bound(a[None, :], b[None, :], 1.0, abs(float(np.float32(c0))))[0]
+        assert err <= bound
+        worst = max(worst, err / bound)
+    assert worst >= 0.5
+
+
+# ------------------------------------------- estimator with the HBM split
+def _prof(hbm_curve, read_curve=None, press_hbm=0.0, press_read=0.0, wfrac=1.0, extra=None):
+    sens = [list(hbm_curve), [1.0] * 5]
+    press = [press_hbm, 0.0 if extra is None else extra]
+    p = {"sens": sens, "press": press, "hbm_write_frac": wfrac, "press_hbm_read": press_read,
+         "bytes": 1, "occ": 0.1}
+    if read_curve is not None:
+        p["sens_hbm_read"] = list(read_curve)
+    return p
+
+
+def test_read_write_aware_estimator_hand_cases():
+    triad = [1.0, 2.0, 3.0, 4.0, 5.0]
+    reads = [1.0, 1.2, 1.4, 1.6, 1.8]
+    victim = _prof(triad, reads)
+    plain_victim = _prof(triad)
+    reader = _prof(triad, press_hbm=0.9, press_read=0.5, wfrac=0.0)      # read-mostly co-runner
+    writer = _prof(triad, press_hbm=0.5, press_read=0.9, wfrac=1 / 3)    # triad-like co-runner
+    # a read-mostly co-runner is priced on the read curve at its read-mix load
+    assert oracle.predicted_slowdown_rw(victim, [reader]) == pytest.approx(1.4)
+    # without a read curve the victim prices it on the ordinary curve at its HBM load
+    assert oracle.predicted_slowdown_rw(plain_victim, [reader]) == pytest.approx(4.6)
+    # a co-runner that writes is priced on the ordinary curve
+    assert oracle.predicted_slowdown_rw(victim, [writer]) == pytest.approx(3.0)
+    # both: the two HBM factors multiply
+    assert oracle.predicted_slowdown_rw(victim, [reader, writer]) == pytest.approx(1.4 * 3.0)
+    # a write share of exactly 1/6 is not read-mostly
+    edge = _prof(triad, press_hbm=0.25, press_read=0.75, wfrac=1 / 6)
+    assert oracle.predicted_slowdown_rw(victim, [edge]) == pytest.approx(2.0)
+    # loads add and clip at 1; other resources multiply in
+    two_readers = oracle.predicted_slowdown_rw(victim, [reader, reader])
+    assert two_readers == pytest.approx(1.8)
+    other = _prof(triad, press_hbm=0.0, wfrac=0.0, extra=0.5)
+    v2 = dict(victim, sens=[triad, [1.0, 1.0, 2.0, 3.0, 4.0]])
+    assert oracle.predicted_slowdown_rw(v2, [other]) == pytest.approx(2.0)
+    # no co-runner: 1; the estimator without read curves is the plain product rule
+    assert oracle.predicted_slowdown_rw(victim, []) == 1.0
+    assert oracle.predicted_slowdown_rw(plain_victim, [writer]) == oracle.predicted_slowdown(
+        plain_victim["sens"], [0.5, 0.0])
+
+
+def test_admission_lets_a_lone_request_in():
+    """On an idle device a request needs only memory and a slot: neither the
+    occupancy rule nor the slowdown bound can refuse it (nothing would ever
+    free up); beside a co-runner they apply as before."""
+    greedy = _job([5.0, 1.0], [1.0, 0.0], occ=1.0)
+    for pol in ("usher", "sensitivity"):
+        assert oracle.admit(pol, [], greedy, 10, 1.01, 4)
+        assert not oracle.admit(pol, [greedy], greedy, 10, 1.01, 4)
+        assert not oracle.admit(pol, [], _job([1, 1], [0, 0], nbytes=20), 10, 1.01, 4)
+    with pytest.raises(ValueError):
+        oracle.admit("fifo", [], greedy, 10, 1.5, 4)
+
+
+# ------------------------------------------------ discrete-event serving model
+def _sim_jobs(n, rng, nbytes=1000):
+    kinds = [_job([1.0 + 2.0 * rng.random(), 1.0], [rng.random(), 0.0], nbytes=nbytes, occ=0.4)
+             for _ in range(3)]
+    return [kinds[int(rng.integers(0, 3))] for _ in range(n)]
+
+
+def test_simulator_single_slot_is_the_fifo_queue_recursion():
+    """One slot, naive admission: the textbook single-server FIFO recursion
+    end_i = max(arrival_i, end_{i-1}) + service_i (Lindley)."""
+    rng = np.random.default_rng(3)
+    n = 400
+    arr = np.cumsum(rng.exponential(1.0, n))
+    svc = rng.exponential(0.9, n)
+    out = oracle.simulate_admission(list(arr), _sim_jobs(n, rng), list(svc), "naive", 1 << 30, 1.5, 1)
+    end = 0.0
+    for i in range(n):
+        start = max(arr[i], end)
+        end = start + svc[i]
+        assert out[i]["admit"] == pytest.approx(start) and out[i]["end"] == pytest.approx(end)
+        assert out[i]["slot"] == 0
+
+
+def test_simulator_invariants():
+    """FIFO without bypass, slots and memory never exceeded, unbounded
+    sensitivity equal to naive, and Little's law on the whole trace
+    (time-average number in the system = sum of sojourn times / horizon)."""
+    rng = np.random.default_rng(11)
+    n = 300
+    arr = list(np.cumsum(rng.exponential(0.2, n)))
+    svc = list(rng.exponential(1.0, n))
+    jobs = _sim_jobs(n, rng, nbytes=3000)
+    budget, slots = 10000, 4
+    for pol, bound in (("naive", 1.5), ("usher", 1.5), ("sensitivity", 1.6), ("sensitivity", 2.5)):
+        out = oracle.simulate_admission(arr, jobs, svc, pol, budget, bound, slots)
+        adm = [o["admit"] for o in out]
+        assert all(a2 >= a1 for a1, a2 in zip(adm, adm[1:]))            # FIFO, no bypass
+        assert all(o["admit"] >= t for o, t in zip(out, arr))
+        for i, o in enumerate(out):                                      # state at each admission
+            live = [j for j in range(n) if out[j]["admit"] <= o["admit"] < out[j]["end"]]
+            assert len(live) <= slots
+            assert sum(jobs[j]["bytes"] for j in live) <= budget
+            if pol == "sensitivity" and o["corunners"]:
+                group = [jobs[j] for j in o["corunners"]] + [jobs[i]]
+                assert all(oracle.predicted_slowdown_rw(group[g], group[:g] + group[g + 1:]) <= bound
+                           for g in range(len(group)))
+        horizon = max(o["end"] for o in out)
+        events = sorted([(t, 1) for t in arr] + [(o["end"], -1) for o in out])
+        area, level, last = 0.0, 0, 0.0
+        for t, d in events:
+            area += level * (t - last)
+            level, last = level + d, t
+        assert area / horizon == pytest.approx(sum(o["end"] - t for o, t in zip(out, arr)) / horizon)
+    big = 1 << 40
+    a = oracle.simulate_admission(arr, jobs, svc, "naive", big, 1.5, 8)
+    b = oracle.simulate_admission(arr, jobs, svc, "sensitivity", big, math.inf, 8)
+    assert a == b
+
+
+def test_simulator_hand_case_and_slowed_service():
+    """Two requests that predict 3x beside each other: sensitivity admission
+    with bound 1.5 runs them one after the other, naive runs them together
+    (and, with slowed service, the second takes 3x its time)."""
+    frag = _job([3.0, 1.0], [1.0, 0.0], nbytes=1, occ=0.4)
+    out = oracle.simulate_admission([0.0, 0.5], [frag, frag], [2.0, 2.0], "sensitivity", 1024, 1.5, 4)
+    assert [(o["admit"], o["end"]) for o in out] == [(0.0, 2.0), (2.0, 4.0)]
+    out = oracle.simulate_admission([0.0, 0.5], [frag, frag], [2.0, 2.0], "naive", 1024, 1.5, 4, slowed=True)
+    assert [(o["admit"], o["end"]) for o in out] == [(0.0, 2.0), (0.5, 6.5)]
+    assert out[1]["corunners"] == (0,)
+    with pytest.raises(ValueError):
+        oracle.simulate_admission([0.0], [_job([1, 1], [0, 0], nbytes=2000)], [1.0], "naive", 1024, 1.5, 4)
+
+
+def test_first_fit_arena():
+    ar = oracle.FirstFitArena(4096)
+    a = ar.alloc(100)
+    b = ar.alloc(1000)
+    c = ar.alloc(256)
+    assert (a, b, c) == (0, 256, 1280)                  # 256-byte granules, lowest fit
+    ar.release(b, 1000)
+    assert ar.largest_free() == 4096 - 1536
+    assert ar.alloc(512) == 256                           # reuses the hole first
+    ar.release(a, 100)
+    ar.release(c, 256)
+    ar.release(256, 512)
+    assert ar.free == [(0, 4096)] and ar.alloc(5000) is None
