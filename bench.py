@@ -165,26 +165,290 @@ def hbm_traffic():
     return c.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline():
-    """The oracle's triad on a bounded sample, on the host (one thread)."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _host_threads() -> int:
+    """Threads the CPU baseline may use: the cores this process may run on,
+    capped by OMP_NUM_THREADS when the environment sets a share."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    cap = os.environ.get("OMP_NUM_THREADS")
+    if cap and cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(1, n)
+
+
+def cpu_baseline(host=None, prec=None, serve=None):
+    """The oracle on the host CPU, beside the GPU legs of the same run.
+
+    triad: the oracle's two-rounding triad over the headline's N = 2^30
+      arrays (copied from the device, the same bits), once on one thread and
+      repeatedly on every host thread the process may use;
+    precision: the FP64 oracle on the precision legs' 4096 sampled entries,
+      timed, and the GPU outputs' errors against it (per dtype: kernel error
+      against the quantised inputs, total error against the FP32 inputs, and
+      the largest error over its bound);
+    serving: the admission rule replayed in the oracle's discrete-event
+      model on each served trace with the requests' isolated service times:
+      the latency it predicts next to the one the GPU loop measured."""
     import oracle
     import synth
-    n = 1 << 26
-    b = synth.uniform_f32(synth.seed_for(1, synth.BUF_B), n)
-    c = synth.uniform_f32(synth.seed_for(1, synth.BUF_C), n)
+    out = {"kind": "oracle", "unit": "GB/s"}
+    threads = _host_threads()
+    if host is not None:
+        b, c = host
+        n = b.size
+    else:          # no device arrays (a bounded host-only sample)
+        n = 1 << 26
+        b = synth.uniform_f32(synth.seed_for(1, synth.BUF_B), n)
+        c = synth.uniform_f32(synth.seed_for(1, synth.BUF_C), n)
+    a = np.empty_like(b)
     oracle.triad_f32(b[:1024], c[:1024])
-    reps = 0
+    t0 = time.perf_counter()
+    oracle.triad_f32_threads(b, c, 1, out=a)
+    t1 = time.perf_counter() - t0
+    reps, used = 0, threads
     t0 = time.perf_counter()
     while True:
-        oracle.triad_f32(b, c)
+        _, used = oracle.triad_f32_threads(b, c, threads, out=a)
         reps += 1
-        if time.perf_counter() - t0 > 10.0:
+        if time.perf_counter() - t0 > 5.0 and reps >= 2:
             break
-    dt = time.perf_counter() - t0
-    return {"value": round(12.0 * n * reps / dt / 1e9, 3), "unit": "GB/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"C oracle triad a=b+3c (two FP32 roundings) over N=2^26 FP32, {reps} passes "
-                      f"({dt:.1f} s), host CPU, single thread"}
+    tall = (time.perf_counter() - t0) / reps
+    out.update({"value": round(12.0 * n / tall / 1e9, 3), "cores": used,
+                "value_1t": round(12.0 * n / t1 / 1e9, 3), "nproc": os.cpu_count(),
+                "cpu_model": _cpu_model(), "n": int(n),
+                "sample": f"C oracle triad a = b + 3c (two FP32 roundings) over N = {n} FP32 elements: "
+                          f"one pass on 1 thread ({t1:.2f} s), {reps} passes on {used} threads "
+                          f"({tall:.2f} s each)"})
+    del a
+    legs = {}
+    if prec is not None:
+        legs["precision"] = _cpu_precision_leg(prec)
+    if serve is not None:
+        legs["serving"] = _cpu_serving_leg(serve)
+    if legs:
+        out["legs"] = legs
+    return out
+
+
+def _cpu_precision_leg(prec):
+    """Errors of the sampled GPU GEMM outputs against the FP64 oracle."""
+    import oracle
+    res = {"sample": f"{len(prec['rows'])} fixed-seed entries of C = A B^T, M = N = K = {prec['k']}",
+           "dtypes": {}}
+    t0 = time.perf_counter()
+    exact = oracle.gemm_entries_f64(prec["a_rows"], prec["b_cols"], prec["pair"], prec["pair"])
+    absx = oracle.gemm_entries_f64(np.abs(prec["a_rows"]), np.abs(prec["b_cols"]), prec["pair"], prec["pair"])
+    t_exact = time.perf_counter() - t0
+    for dt, d in prec["dtypes"].items():
+        if dt == "f32":
+            fa, fb = d["qa"].astype(np.float64), d["qb"].astype(np.float64)
+        elif dt == "bf16":
+            fa, fb = oracle.bf16_to_f64(d["qa"].view(np.uint16)), oracle.bf16_to_f64(d["qb"].view(np.uint16))
+        else:
+            fa, fb = oracle.e4m3_to_f64(d["qa"]), oracle.e4m3_to_f64(d["qb"])
+        s = d["sa"] * d["sb"]
+        kern = s * oracle.gemm_entries_f64(fa, fb, prec["pair"], prec["pair"])
+        kabs = s * oracle.gemm_entries_f64(np.abs(fa), np.abs(fb), prec["pair"], prec["pair"])
+        if dt == "fp8":
+            bound = oracle.mfma_fp8_error_bound(d["qa"], d["qb"], s)
+        else:
+            bound = s * oracle.accumulation_bound(prec["k"] + 1, kabs / s, 2.0 ** -23)
+        got = d["got"]
+        res["dtypes"][dt] = {
+            "kernel_err_max_rel_absprod": float(np.max(np.abs(got - kern) / kabs)),
+            "kernel_err_normwise": float(np.linalg.norm(got - kern) / np.linalg.norm(kern)),
+            "kernel_err_max_over_bound": float(np.max(np.abs(got - kern) / bound)),
+            "total_err_max_rel_absprod": float(np.max(np.abs(got - exact) / absx)),
+            "total_err_normwise": float(np.linalg.norm(got - exact) / np.linalg.norm(exact))}
+    res["oracle_entries_per_s"] = round(len(prec["rows"]) / t_exact, 1)
+    res["oracle_full_gemm_s_extrapolated"] = round(prec["k"] ** 2 / (len(prec["rows"]) / t_exact), 1)
+    return res
+
+
+def _cpu_serving_leg(serve):
+    """The admission rule in the oracle's discrete-event model, fed the
+    isolated service times the GPU measured, next to the GPU's latencies."""
+    import oracle
+    out = []
+    for run in serve["runs"]:
+        prof, reqs = serve["profiles"], run["reqs"]
+        f32 = lambda v: float(np.float32(v))
+        names = ["hbm", "l2", "mall", "vl1d", "lds", "valu_f32", "mfma_f32", "mfma_bf16", "mfma_fp8", "ptrchase",
+                 "dispatch", "occupancy", "valu_f64"]
+        jobs = []
+        for q in reqs:
+            p = prof[q["kind"]]
+            job = {"sens": [[f32(v) for v in p["sens"].get(r, [1.0] * 5)] for r in names],
+                   "press": [f32(p["press"].get(r, 0.0)) for r in names], "occ": f32(p["occ"]),
+                   "bytes": run["footprints"][len(jobs)], "hbm_write_frac": f32(p.get("hbm_write_frac", 1.0)),
+                   "press_hbm_read": f32(p.get("press_hbm_read", 0.0))}
+            if p.get("sens_hbm_read"):
+                job["sens_hbm_read"] = [f32(v) for v in p["sens_hbm_read"]]
+            jobs.append(job)
+        t0 = time.perf_counter()
+        sim = oracle.simulate_admission([q["arrival_s"] for q in reqs], jobs, run["iso_s"], run["policy"],
+                                        run["budget"], run["bound"], run["slots"], slowed=True)
+        dt = time.perf_counter() - t0
+        lat = np.array([o["end"] - q["arrival_s"] for o, q in zip(sim, reqs)])
+        out.append({"rate_per_s": run["rate"], "policy": run["policy"], "requests": len(reqs),
+                    "model_latency_ms_p50": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                    "model_latency_ms_p99": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                    "gpu_latency_ms_p50": run["latency_ms_p50"], "gpu_latency_ms_p99": run["latency_ms_p99"],
+                    "model_colocated_fraction": round(float(np.mean([bool(o["corunners"]) for o in sim])), 3),
+                    "oracle_seconds": round(dt, 2)})
+    return out
+
+
+# the compact sensitivity block of the default run: both sweep victims against
+# the resources each kind of workload loads, at CU intensity 0, 50 and 100 %
+SENS_RES = ["hbm", "l2", "mall", "lds", "valu_f32", "mfma_bf16", "ptrchase"]
+SENS_X = [0.0, 0.5, 1.0]
+
+
+def sensitivity_block(ctx, dev, reps, ws):
+    """Victim slowdown per resource and intensity (shared CUs) for the BF16
+    GEMM 4096^3 and the BF16 GEMV 8192^2 of the sensitivity sweep, each cell
+    with its bootstrap 95 % interval and the stressor's share of its peak."""
+    ops = stressor_operands(dev)
+    victims = sweep_victims(ctx, dev)
+    nan = lambda v: v != v
+    out = {"intensities": SENS_X, "reps": reps, "placement": "shared", "victims": {}}
+    for vname in ("gemm_bf16_4096", "gemv_bf16_8192"):
+        cells = ctx.measure_sensitivity(victims[vname], SENS_RES, [ops[r] for r in SENS_RES], SENS_X, reps=reps,
+                                        warmups=2, ws=ws, deadline_ms=200)
+        tab = {}
+        for i, r in enumerate(SENS_RES):
+            row = cells[i * len(SENS_X):(i + 1) * len(SENS_X)]
+            tab[r] = {"slowdown": [None if nan(c["slowdown"]) else round(c["slowdown"], 3) for c in row],
+                      "ci95": [None if nan(c["slowdown_ci_lo"]) else
+                               [round(c["slowdown_ci_lo"], 3), round(c["slowdown_ci_hi"], 3)] for c in row],
+                      "stressor_pct_peak": [round(c["stressor_pct_peak"], 1) for c in row],
+                      "starved_lower_bound": [bool(c["timed_out"]) for c in row],
+                      "valid": [bool(c["window_covered"] and c["output_equal"] and not c["queue_unresolved"])
+                                for c in row]}
+        out["victims"][vname] = {"t_alone_us": round(float(np.median([c["t_alone_ns"] for c in cells])) / 1e3, 2),
+                                 "cells": tab}
+        log(f"sensitivity {vname}: " + ", ".join(f"{r}={tab[r]['slowdown']}" for r in tab))
+    out["queue_pair_check"] = ctx.queue_stats()
+    del ops, victims
+    return out
+
+
+def precision_block(ctx, dev, keep_host):
+    """GEMM 8192^3 from N(0, 1) in FP32, BF16 and FP8 (per-tensor scale):
+    time and rate per dtype; the sampled entries (and the operands' rows
+    that produce them) go to the CPU leg for the error against FP64."""
+    import torch
+    import synth
+    m = 8192
+    ha = synth.normal_f32(synth.seed_for(3, synth.BUF_GEMM_A), m * m).reshape(m, m)
+    hb = synth.normal_f32(synth.seed_for(3, synth.BUF_GEMM_B), m * m).reshape(m, m)
+    a = torch.from_numpy(ha).to(dev)
+    b = torch.from_numpy(hb).to(dev)
+    c = torch.empty((m, m), dtype=torch.float32, device=dev)
+    idx = synth.words(4242, 4096)
+    rows = (idx % np.uint64(m)).astype(np.int64)
+    cols = ((idx >> np.uint64(32)) % np.uint64(m)).astype(np.int64)
+    host = {"k": m, "rows": rows, "cols": cols, "pair": np.arange(len(rows)),
+            "a_rows": ha[rows].copy(), "b_cols": hb[cols].copy(), "dtypes": {}}
+    summary = {}
+    rt, ct = torch.from_numpy(rows).to(dev), torch.from_numpy(cols).to(dev)
+    for dt in ("f32", "bf16", "fp8"):
+        if dt == "f32":
+            qa, qb, sa, sb = a, b, 1.0, 1.0
+        else:
+            qa, sa = ctx.quantize(a, dt)
+            qb, sb = ctx.quantize(b, dt)
+        d = ctx.gemm_desc(qa, qb, c, dt, m, m, m, sa, sb)
+        for _ in range(5):      # untimed: the rate rises over a process's first launches
+            ctx.victim_run(d)
+        times = [ctx.victim_run(d).time_ns for _ in range(10)]
+        t = float(np.median(times))
+        summary[dt] = {"time_ms": round(t / 1e6, 3), "tflops": round(2.0 * m ** 3 / t / 1e3, 1),
+                       "pct_of_peak": round(100 * 2.0 * m ** 3 / (t * 1e-9) / ctx.peak("mfma_" + dt), 1)}
+        if keep_host:
+            host["dtypes"][dt] = {"qa": qa.index_select(0, rt).cpu().numpy(), "qb": qb.index_select(0, ct).cpu().numpy(),
+                                  "sa": sa, "sb": sb, "got": c[rt, ct].cpu().numpy().astype(np.float64)}
+        log(f"precision {dt}: {summary[dt]}")
+    del a, b, c
+    torch.cuda.empty_cache()
+    return summary, host
+
+
+def serving_block(ctx, args, keep_host):
+    """The serving loop on BASELINE-shaped traffic: Poisson arrivals of BF16
+    GEMM / BF16 GEMV / FP32 triad requests, naive against sensitivity-aware
+    admission (duty-axis profiles measured here, read/write-aware HBM
+    pricing), 60 s at 200 requests/s and 10 s at 1000/s.  Every request is
+    also served alone (one slot, in arrival order) for its isolated service
+    time and result: slowdowns are over all requests, and every result must
+    equal its isolated one bit for bit."""
+    profiles = serve_profiles(ctx, args, axis="duty")
+    reads = serve_profiles(ctx, args, axis="duty", hbm_mix="read", res=("hbm",))
+    for kind, p in profiles.items():
+        p["sens_hbm_read"] = reads[kind]["sens"]["hbm"]
+        p["press_hbm_read"] = reads[kind]["press"]["hbm"]
+    budget, slots = 32 << 30, 4
+    summary = {"config": {"workload": "Poisson arrivals, 1/3 each BF16 GEMM n~logU[512,8192], BF16 GEMV "
+                                      "n~logU[4096,16384], FP32 triad N~logU[2^20,2^28]",
+                          "slots": slots, "hbm_budget_gib": budget >> 30, "bound": args.bound,
+                          "profile_axis": "duty", "hbm_pricing": "read/write-aware"},
+               "runs": []}
+    host = {"profiles": profiles, "runs": []}
+    for lam, seconds in ((200.0, args.serve_seconds), (1000.0, max(2.0, args.serve_seconds / 6))):
+        reqs = serve_trace(lam, seconds, 31337 + int(lam))
+        iso = ctx.serve([dict(r, arrival_s=0.0) for r in reqs], policy="naive", hbm_budget=budget, slots=1)
+        iso_ns = np.array([o["service_ns"] for o in iso])
+        for policy in ("naive", "sensitivity"):
+            t0 = time.perf_counter()
+            res = ctx.serve(reqs, policy=policy, bound=args.bound, hbm_budget=budget, slots=slots,
+                            profiles=profiles)
+            wall = time.perf_counter() - t0
+            lat = np.array([r["end_s"] - r["arrival_s"] for r in res])
+            slow = np.array([r["service_ns"] for r in res]) / iso_ns
+            equal = all(r["checksum_bits"] == i["checksum_bits"] for r, i in zip(res, iso))
+            run = {"rate_per_s": lam, "seconds": seconds, "policy": policy, "requests": len(reqs),
+                   "latency_ms_p50": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                   "latency_ms_p99": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                   "throughput_req_s": round(len(reqs) / max(r["end_s"] for r in res), 1),
+                   "slowdown_p50": round(float(np.percentile(slow, 50)), 3),
+                   "slowdown_p99": round(float(np.percentile(slow, 99)), 3),
+                   "slowdown_over": "every request (service in the mix / service alone)",
+                   "results_equal_isolated": bool(equal), "wall_s": round(wall, 1)}
+            summary["runs"].append(run)
+            log(f"serve {lam}/s {policy}: {run}")
+            if keep_host:
+                host["runs"].append({"rate": lam, "policy": policy, "reqs": reqs, "iso_s": list(iso_ns * 1e-9),
+                                     "footprints": [serve_footprint(q) for q in reqs], "budget": budget,
+                                     "bound": args.bound, "slots": slots,
+                                     "latency_ms_p50": run["latency_ms_p50"], "latency_ms_p99": run["latency_ms_p99"]})
+    summary["profiles"] = profiles
+    return summary, host
+
+
+def serve_footprint(q):
+    """Bytes a request holds in the loop's arena (rounded as the loop rounds)."""
+    al = lambda b: (b + 255) // 256 * 256
+    if q["kind"] == "triad":
+        return 3 * al(q["n"] * 4)
+    if q["kind"] == "gemm":
+        e = {"f32": 4, "bf16": 2}[q.get("dtype", "bf16")]
+        stage = 0 if q.get("dtype") == "f32" else max(q["m"], q["n"]) * q["k"] * 4
+        return al(q["m"] * q["k"] * e) + al(q["n"] * q["k"] * e) + al(q["m"] * q["n"] * 4) + al(stage)
+    return al(q["n"] * q["k"] * 2) + al(q["k"] * 2) + al(q["n"] * 4) + al(max(q["n"] * q["k"], q["k"]) * 4)
 
 
 def run_suite(args):
@@ -192,6 +456,7 @@ def run_suite(args):
     from paper_2501_16909_amd import coloc
     dev = torch.device("cuda:0")
     ctx = coloc.Context(0)
+    t_start = time.perf_counter()
     suite = Suite(ctx, dev)
     log("setup done")
     warm = {}
@@ -241,22 +506,41 @@ def run_suite(args):
         "data": "synthetic (SplitMix64 counter-form uniform [-1,1) / uint32 words / random cycle)",
         "config": {"workload": "stressor suite standalone: HBM triad FP32 N=2^30 (and its "
                                "read-only, copy and write-only mixes); L2 2 MiB; "
-                               "Infinity Cache 128 MiB; vL1D 16 KiB; LDS 64 KiB/WG (L2 and LDS "
-                               "also at 32 waves/CU); FP32 FMA and FP64 multiply chains 4096; "
+                               "Infinity Cache 128 MiB (read, and write-only); vL1D 16 KiB; LDS 64 KiB/WG "
+                               "(L2 and LDS also at 32 waves/CU); FP32 FMA and FP64 multiply chains 4096; "
                                "MFMA FP32/BF16/FP8; uint32 chase over 2^24 cycle; 10^6 empty "
                                "64-thread WGs; plus colocated triad pair N=2^22",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
                      "frac": round(achieved / 8000.0, 4),
                      "traffic": traffic,
-                     "kernel": "hbm_stressor, triad mix (12 B per element, N=2^30, one pass per launch)"},
+                     "kernel": "stream_stressor, triad mix (12 B per element, N=2^30, one pass per launch)"},
         "stressors": stress,
         "colocated_triad_pair": pairs,
     }
+    log(f"suite: {wall:.1f} s timed; hbm {achieved:.0f} GB/s")
+    host_arrays = None
+    if not args.no_cpu_baseline:      # the headline arrays, for the oracle's triad on the host
+        host_arrays = (suite.hb.cpu().numpy(), suite.hc.cpu().numpy())
+    prec_host = serve_host = None
+    if not args.quick:
+        ws = suite.ws
+        del suite
+        torch.cuda.empty_cache()
+        line["sensitivity"] = sensitivity_block(ctx, dev, args.suite_reps, ws)
+        log(f"sensitivity block done at {time.perf_counter() - t_start:.0f} s")
+        line["precision"], prec_host = precision_block(ctx, dev, not args.no_cpu_baseline)
+        log(f"precision block done at {time.perf_counter() - t_start:.0f} s")
+        line["serving"], serve_host = serving_block(ctx, args, not args.no_cpu_baseline)
+        log(f"serving block done at {time.perf_counter() - t_start:.0f} s")
     ctx.close()
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline()
+        line["cpu_baseline"] = cpu_baseline(host_arrays, prec_host, serve_host)
+        log(f"cpu baseline done at {time.perf_counter() - t_start:.0f} s")
     print(json.dumps(line), flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(line, f)
 
 
 
@@ -437,70 +721,45 @@ def run_hbm_mix(args):
 
 def run_precision(args):
     """GEMM M = N = K = 8192 in FP32, BF16 and FP8 (per-tensor scale) from
-    N(0,1) inputs, FP32 accumulation.  Error against FP64 on 4096 sampled
-    entries: kernel error (FP64 product of the quantised inputs) and total
-    error (FP64 product of the FP32 inputs), each normalised by |A||B|^T and
-    normwise; plus the sensitivity row per dtype."""
+    N(0,1) inputs, FP32 accumulation: time and rate per dtype, the
+    sensitivity row per dtype, and (CPU leg) the error against FP64 on 4096
+    sampled entries: kernel error (FP64 product of the quantised inputs) and
+    total error (FP64 product of the FP32 inputs), normalised by |A||B|^T,
+    normwise, and over the dtype's bound."""
     import torch
-    import oracle
-    import synth
     from paper_2501_16909_amd import coloc
     dev = torch.device("cuda:0")
     ctx = coloc.Context(0)
+    summary, host = precision_block(ctx, dev, True)
     m = 8192
-    ha = synth.normal_f32(synth.seed_for(3, synth.BUF_GEMM_A), m * m).reshape(m, m)
-    hb = synth.normal_f32(synth.seed_for(3, synth.BUF_GEMM_B), m * m).reshape(m, m)
-    a = torch.from_numpy(ha).to(dev)
-    b = torch.from_numpy(hb).to(dev)
-    c = torch.empty((m, m), dtype=torch.float32, device=dev)
-    idx = synth.words(4242, 4096)
-    rows = (idx % np.uint64(m)).astype(np.int64)
-    cols = ((idx >> np.uint64(32)) % np.uint64(m)).astype(np.int64)
-    exact = oracle.gemm_entries_f64(ha, hb, rows, cols)
-    absx = oracle.gemm_entries_f64(np.abs(ha), np.abs(hb), rows, cols)
     ops = stressor_operands(dev)
     ws = torch.empty(WS_BYTES, dtype=torch.uint8, device=dev)
     out = {"metric": "GEMM error vs FP64 and sensitivity per dtype",
            "config": {"workload": "GEMM M=N=K=8192, inputs N(0,1), FP32 accumulate; FP8 e4m3 per-tensor scale",
-                      "sample": "4096 fixed-seed entries"}, "dtypes": {}}
+                      "sample": "4096 fixed-seed entries"}, "dtypes": summary}
+    import synth
+    ha = synth.normal_f32(synth.seed_for(3, synth.BUF_GEMM_A), m * m).reshape(m, m)
+    hb = synth.normal_f32(synth.seed_for(3, synth.BUF_GEMM_B), m * m).reshape(m, m)
+    a, b = torch.from_numpy(ha).to(dev), torch.from_numpy(hb).to(dev)
+    c = torch.empty((m, m), dtype=torch.float32, device=dev)
     for dt in ("f32", "bf16", "fp8"):
         if dt == "f32":
             qa, qb, sa, sb = a, b, 1.0, 1.0
-            fa, fb = ha.astype(np.float64), hb.astype(np.float64)
         else:
             qa, sa = ctx.quantize(a, dt)
             qb, sb = ctx.quantize(b, dt)
-            if dt == "bf16":
-                fa, fb = oracle.bf16_to_f64(qa.cpu().numpy().view(np.uint16)), oracle.bf16_to_f64(qb.cpu().numpy().view(np.uint16))
-            else:
-                fa, fb = oracle.e4m3_to_f64(qa.cpu().numpy()), oracle.e4m3_to_f64(qb.cpu().numpy())
         d = ctx.gemm_desc(qa, qb, c, dt, m, m, m, sa, sb)
-        for _ in range(5):      # untimed: the rate rises over a process's first launches
-            ctx.victim_run(d)
-        times = [ctx.victim_run(d).time_ns for _ in range(10)]
-        got = c.cpu().numpy()[rows, cols].astype(np.float64)
-        kern = sa * sb * oracle.gemm_entries_f64(fa, fb, rows, cols)
-        kabs = sa * sb * oracle.gemm_entries_f64(np.abs(fa), np.abs(fb), rows, cols)
-        t = float(np.median(times))
-        entry = {"time_ms": round(t / 1e6, 3), "tflops": round(2.0 * m ** 3 / t / 1e3, 1),
-                 "pct_of_peak": round(100 * 2.0 * m ** 3 / (t * 1e-9) / ctx.peak("mfma_" + dt), 1),
-                 "kernel_err_max_rel_absprod": float(np.max(np.abs(got - kern) / kabs)),
-                 "kernel_err_normwise": float(np.linalg.norm(got - kern) / np.linalg.norm(kern)),
-                 "total_err_max_rel_absprod": float(np.max(np.abs(got - exact) / absx)),
-                 "total_err_normwise": float(np.linalg.norm(got - exact) / np.linalg.norm(exact))}
         res = list(ops)
         cells = ctx.measure_sensitivity(d, res, [ops[r] for r in res], [0.0, 0.5, 1.0], reps=args.reps,
                                         warmups=1, ws=ws, deadline_ms=args.deadline_ms)
-        entry["sensitivity"] = {r: [round(cells[i * 3 + j]["slowdown"], 3) for j in range(3)]
-                                for i, r in enumerate(res)}
-        entry["sensitivity_intensities"] = [0.0, 0.5, 1.0]
-        out["dtypes"][dt] = entry
-        log(f"{dt}: {entry['time_ms']} ms {entry['tflops']} TF, total err normwise {entry['total_err_normwise']:.3g}")
+        summary[dt]["sensitivity"] = {r: [round(cells[i * 3 + j]["slowdown"], 3) for j in range(3)]
+                                      for i, r in enumerate(res)}
+        summary[dt]["sensitivity_intensities"] = [0.0, 0.5, 1.0]
+        log(f"{dt}: sensitivity {summary[dt]['sensitivity']}")
     ctx.close()
-    print(json.dumps(out), flush=True)
-    if args.out:
-        with open(args.out, "w") as f:
-            json.dump(out, f)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = {"kind": "oracle", "precision": _cpu_precision_leg(host)}
+    _emit(out, args)
 
 
 def serve_trace(lam, seconds, seed):
@@ -1308,6 +1567,12 @@ def main():
                              "pollution", "bandwidth", "ilp", "pairs", "ldsstride", "estimator", "decode",
                              "queues", "hbm_mix", "gemm-counters"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quick", action="store_true",
+                    help="suite: the timed stressor suite only (no sensitivity, precision or serving blocks)")
+    ap.add_argument("--suite-reps", type=int, default=5,
+                    help="suite: counterbalanced pairs per cell of the sensitivity block")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="suite: length of the 200/s serving trace (the 1000/s trace is a sixth of it)")
     ap.add_argument("--stressor-warmup", type=int, default=0,
                     help="suite: untimed launches of each stressor right before its timed one")
     ap.add_argument("--out", default=None, help="also write the JSON line(s) to this file")

@@ -12,7 +12,7 @@ the passage of the paper (Elvinger et al., SoCC'25) or the workload
 definition it follows.
 
 Parity status per function (pins are in tests/test_oracle_pins.py):
-  triad_f32, bitsum_u32, sum_f32_exact .......... pinned
+  triad_f32, triad_f32_threads, bitsum_u32, sum_f32_exact  pinned
   hbm_read_checksum, hbm_copy, hbm_write_pattern  pinned
   fma_chain_f32 / valu_outputs .................. pinned
   dmul_chain_f64 / valu64_outputs ............... pinned
@@ -51,7 +51,7 @@ def build_oracle(force: bool = False) -> str:
     """Compile coloc_oracle.c with gcc (no fused multiply-add contraction)."""
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
         tmp = _SO + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-pthread",
                                "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _SO)
     return _SO
@@ -62,6 +62,8 @@ def _lib():
     if _LIB is None:
         lib = ctypes.CDLL(build_oracle())
         lib.or_triad_f32.argtypes = [_F32P, _F32P, _F32P, ctypes.c_uint64]
+        lib.or_triad_f32_mt.argtypes = [_F32P, _F32P, _F32P, ctypes.c_uint64, ctypes.c_int]
+        lib.or_triad_f32_mt.restype = ctypes.c_int
         lib.or_bitsum_u32.argtypes = [_U32P, ctypes.c_uint64]
         lib.or_bitsum_u32.restype = ctypes.c_uint64
         lib.or_sum_u32_mod32.argtypes = [_U32P, ctypes.c_uint64, ctypes.c_uint64]
@@ -106,6 +108,17 @@ def triad_f32(b, c) -> np.ndarray:
     a = np.empty_like(b)
     _lib().or_triad_f32(b.ravel(), c.ravel(), a.ravel(), b.size)
     return a
+
+
+def triad_f32_threads(b, c, threads: int, out=None) -> tuple:
+    """triad_f32 split over `threads` host threads (contiguous shares; the
+    result is the same for any count).  Returns (a, threads that ran)."""
+    b, c = _f32(b), _f32(c)
+    if b.shape != c.shape:
+        raise ValueError("b and c must have the same shape")
+    a = np.empty_like(b) if out is None else out
+    ran = _lib().or_triad_f32_mt(b.ravel(), c.ravel(), a.ravel(), b.size, int(threads))
+    return a, int(ran)
 
 
 def bitsum_u32(x) -> int:

@@ -25,6 +25,7 @@
  * notes and repeated next to the function that takes it.
  */
 #include <math.h>
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -38,6 +39,46 @@ void or_triad_f32(const float* b, const float* c, float* a, uint64_t n) {
     float t = 3.0f * c[i];
     a[i] = b[i] + t;
   }
+}
+
+/* The same triad split over `threads` host threads, each taking one
+ * contiguous share of the elements (the CPU baseline runs the oracle on
+ * every core of the host).  Element-wise, so the result does not depend on
+ * the thread count. */
+struct triad_share {
+  const float* b;
+  const float* c;
+  float* a;
+  uint64_t lo, hi;
+};
+
+static void* triad_worker(void* arg) {
+  const struct triad_share* s = (const struct triad_share*)arg;
+  or_triad_f32(s->b + s->lo, s->c + s->lo, s->a + s->lo, s->hi - s->lo);
+  return NULL;
+}
+
+int or_triad_f32_mt(const float* b, const float* c, float* a, uint64_t n, int threads) {
+  if (threads < 1) threads = 1;
+  if (threads > 1024) threads = 1024;
+  pthread_t tid[1024];
+  struct triad_share sh[1024];
+  int started = 0;
+  for (int t = 0; t < threads; ++t) {
+    sh[t].b = b;
+    sh[t].c = c;
+    sh[t].a = a;
+    sh[t].lo = n * (uint64_t)t / (uint64_t)threads;
+    sh[t].hi = n * (uint64_t)(t + 1) / (uint64_t)threads;
+    if (t == 0) continue;  /* the calling thread takes share 0 */
+    if (pthread_create(&tid[t], NULL, triad_worker, &sh[t]) != 0) break;
+    started = t;
+  }
+  triad_worker(&sh[0]);
+  for (int t = 1; t <= started; ++t) pthread_join(tid[t], NULL);
+  /* shares whose thread could not start run here */
+  for (int t = started + 1; t < threads; ++t) triad_worker(&sh[t]);
+  return started + 1;
 }
 
 /* Sum of the raw 32-bit patterns, modulo 2**64: an order-independent

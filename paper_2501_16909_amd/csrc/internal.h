@@ -41,9 +41,11 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_stamp(uint64_t* slot, hipStream_t s);
 // mix: CI_HBM_TRIAD / READ / COPY / WRITE (anything else: triad); chunk:
 // 16-byte accesses per lane and stream in one wave-chunk (1, 2 or 4)
+// strided: the read-only mix takes fixed per-wave strides instead of tickets
 hipError_t launch_stream_stressor(const KCtrl& c, uint32_t mix, uint32_t chunk, const float* b,
                                   const float* cc, float* a, uint64_t n, uint32_t threads,
-                                  bool streaming, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+                                  bool streaming, bool strided, hipStream_t s, hipEvent_t e0,
+                                  hipEvent_t e1);
 hipError_t launch_triad_victim(const float* b, const float* c, float* a, uint64_t n,
                                uint32_t passes, uint32_t grid, hipStream_t s, hipEvent_t e0,
                                hipEvent_t e1);

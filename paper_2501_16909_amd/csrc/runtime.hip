@@ -529,8 +529,11 @@ static ci_status_t launch_kernel(ci_stressor* h, const KCtrl& c) {
   switch (h->r) {
     case CI_RES_HBM:
     case CI_RES_MALL:
+      // a read-only stream to HBM keeps fixed per-wave strides (faster there);
+      // every other stream, and every Infinity-Cache stream, takes tickets
       e = launch_stream_stressor(c, o.knob, o.chunk, (const float*)o.src0, (const float*)o.src1,
-                                 (float*)o.dst, o.n, o.threads, o.vec == 0, s, e0, e1);
+                                 (float*)o.dst, o.n, o.threads, o.vec == 0, h->r == CI_RES_HBM, s, e0,
+                                 e1);
       break;
     case CI_RES_L2:
     case CI_RES_VL1D: {

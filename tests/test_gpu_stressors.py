@@ -118,6 +118,42 @@ def test_mall_stressor_persistent(ctx, dev):
     print(f"mall triad persistent: {rep.achieved / 1e12:.2f} TB/s over {rep.window_ns / 1e6:.1f} ms")
 
 
+@pytest.mark.parametrize("res,mix,n", [
+    ("hbm", "triad", (1 << 25) + 3),    # ticket form, three 128 MiB arrays
+    ("hbm", "read", 1 << 25),           # strided form
+    ("mall", "copy", 1 << 22),
+])
+def test_stream_stressor_duty_cycle(ctx, dev, res, mix, n):
+    """Duty-cycled streaming stressors do the same work with the same
+    results and only idle between stretches of work: the launch takes longer
+    as duty falls, and at a quarter duty stays within a small multiple of the
+    full-rate launch (the idle periods do not compound across the
+    work-group's barriers)."""
+    import torch
+    from paper_2501_16909_amd import coloc
+    b, c, tb, tc, ta, sentinel = _mall_buffers(dev, n)
+    ops = {"read": dict(src0=tb, src1=tc), "triad": dict(src0=tb, src1=tc, dst=ta),
+           "copy": dict(src0=tb, dst=ta)}[mix]
+    times, sums = {}, {}
+    for duty in (100, 50, 25):
+        ta.copy_(torch.from_numpy(sentinel.view(np.float32)).to(dev))
+        rep = ctx.stressor(res, 1.0, n=n, passes=2, knob=coloc.HBM_MIX[mix], duty=duty, **ops).stop()
+        assert not rep.timed_out and rep.wg_reported == rep.grid
+        assert rep.units == oracle.hbm_bytes_per_element(mix) * n * 2
+        times[duty], sums[duty] = rep.kernel_ns, rep.checksum
+        got = ta.cpu().numpy().view(np.uint32)
+        if mix == "read":
+            assert np.array_equal(got, sentinel)
+            assert rep.checksum % 2 ** 32 == oracle.hbm_read_checksum(b, c, 2)
+        elif mix == "triad":
+            assert np.array_equal(got, oracle.triad_f32(b, c).view(np.uint32))
+        else:
+            assert np.array_equal(got, oracle.hbm_copy(b))
+    assert times[100] < times[50] < times[25], times
+    assert times[25] < 12 * times[100], times
+    print(f"{res} {mix} duty 100/50/25: " + ", ".join(f"{times[d] / 1e3:.0f} us" for d in (100, 50, 25)))
+
+
 # -------------------------------------------------------------------- LDS
 @pytest.mark.parametrize("vec,stride", [(1, 1), (1, 2), (1, 32), (2, 1), (4, 1), (4, 3)])
 def test_lds_stressor_fixed(ctx, dev, vec, stride):

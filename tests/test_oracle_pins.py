@@ -98,6 +98,20 @@ def test_triad_sum_identity():
     assert lhs <= 2.0 ** -24 * float(np.sum(3 * np.abs(c.astype(np.float64)) + np.abs(a)))
 
 
+def test_triad_threads_matches_definition():
+    """The threaded form used for the host baseline computes the same
+    elements as the FP64 two-rounding definition, for thread counts that do
+    and do not divide n (ragged shares, more threads than elements)."""
+    for n in (0, 1, 7, 1000003):
+        b, c = synth.uniform_f32(6, n), synth.uniform_f32(7, n)
+        t = (3.0 * c.astype(np.float64)).astype(np.float32)
+        want = (b.astype(np.float64) + t.astype(np.float64)).astype(np.float32)
+        for threads in (1, 3, 8, 13):
+            got, ran = oracle.triad_f32_threads(b, c, threads)
+            assert 1 <= ran <= threads
+            assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), (n, threads)
+
+
 # --------------------------------------------------------------- checksums
 def test_bitsum_brute_force_and_wrap():
     x = np.array([1.0, -2.5, 0.0], np.float32)
