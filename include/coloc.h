@@ -668,6 +668,26 @@ ci_status_t ci_attention_decode(ci_ctx_t* ctx, const float* q, const uint16_t* k
 ci_status_t ci_silu_mul_bf16(ci_ctx_t* ctx, const float* gu, uint32_t batch, uint32_t ffn,
                              uint16_t* h, void* stream);
 
+/* ci_attention_decode without the `part` workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  It allocates nothing: positions and
+ * partial results live in a static device array of 256 +
+ * CI_NOALLOC_PART_BYTES bytes that each device holds for the life of the
+ * process (its address is fetched once per device in ci_init).  Same
+ * arguments, kernels and bit-identical output as ci_attention_decode.
+ * CI_ERR_INVALID_ARG when the partial results, batch x n_q x
+ * ceil(max_ctx / 64) x (head_dim + 2) x 4 bytes, exceed
+ * CI_NOALLOC_PART_BYTES (batch 8, n_q 32, head_dim 128 fits max_ctx up to
+ * 8064), and for every argument ci_attention_decode rejects.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind (nothing in it needs clearing: each call rewrites what it reads);
+ * calls that overlap on one GPU, from any context or stream, race. */
+#define CI_NOALLOC_PART_BYTES (16ull << 20)
+ci_status_t ci_attention_decode_noalloc(ci_ctx_t* ctx, const float* q, const uint16_t* k_cache,
+                                        const uint16_t* v_cache, const int32_t* pos, uint32_t batch,
+                                        uint32_t n_q, uint32_t n_kv, uint32_t head_dim,
+                                        uint32_t max_ctx, uint16_t* out, void* stream);
+
 /* ------------------------------------------------------------- serving */
 typedef enum ci_policy_kind {
   CI_POLICY_NAIVE = 0,       /* admit when memory and a slot are free          */

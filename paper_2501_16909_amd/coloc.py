@@ -126,6 +126,7 @@ DECODE_KERNELS = ["qkv", "attn", "attn_combine", "oproj", "gate_up", "down", "lm
 NDK = len(DECODE_KERNELS)
 DECODE_KERNEL_TIMES, DECODE_GRAPH = 1, 2
 GEMV_EPILOGUES = {"plain": 0, "silu": 1, "rope": 2}
+NOALLOC_PART_BYTES = 16 << 20   # CI_NOALLOC_PART_BYTES: static scratch for partial results
 
 
 class DecodeConfig(C.Structure):
@@ -226,6 +227,9 @@ EXPORTS = {
     "ci_attention_decode": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32),
                              C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_void_p,
                              C.c_size_t, C.c_void_p, C.c_void_p], C.c_int),
+    "ci_attention_decode_noalloc": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32),
+                                     C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_void_p,
+                                     C.c_void_p], C.c_int),
     "ci_silu_mul_bf16": ([C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p], C.c_int),
     "ci_fused_gemv": ([C.c_void_p, C.POINTER(GemvArgs), C.c_void_p], C.c_int),
 }
@@ -663,6 +667,18 @@ class Context:
         _check(load_library().ci_attention_decode(self.handle, _ptr(q), _ptr(k_cache), _ptr(v_cache), p, batch,
                                                   n_q, n_kv, head_dim, max_ctx, _ptr(part), part.numel(),
                                                   _ptr(out), _stream_handle(self.stream)))
+        return out
+
+    def attention_decode_noalloc(self, q, k_cache, v_cache, pos, n_q: int, n_kv: int, head_dim: int,
+                                 max_ctx: int, out):
+        """attention_decode working in the library's static device scratch:
+        the call allocates nothing; the caller passes the output."""
+        self._sync_torch()
+        batch = len(pos)
+        p = (C.c_int32 * batch)(*[int(v) for v in pos])
+        _check(load_library().ci_attention_decode_noalloc(self.handle, _ptr(q), _ptr(k_cache), _ptr(v_cache), p,
+                                                          batch, n_q, n_kv, head_dim, max_ctx, _ptr(out),
+                                                          _stream_handle(self.stream)))
         return out
 
     def fused_gemv(self, w, epilogue: str = "plain", v=None, x=None, g=None, eps: float = 0.0, res=None,

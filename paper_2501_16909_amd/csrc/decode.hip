@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -661,6 +662,95 @@ extern "C" ci_status_t ci_attention_decode(ci_ctx_t* ctx, const float* q, const 
                              max_ctx, nchunks, mp / kChunk + 1, xs, nullptr, nullptr));
   HIPCHK(launch_attn_combine((const float*)part, ctx->dec_pos_dev, out, batch, n_q, head_dim, nchunks, xs,
                              nullptr, nullptr));
+  return exec_end(ctx, caller, xs);
+}
+
+// ------------------------------------------------ no-allocation attention
+// ci_attention_decode_noalloc works in this array instead of a caller's
+// workspace and the context's lazily allocated position buffer: the first
+// 256 bytes hold the positions, the rest the partial results.  Each device
+// holds its own copy for the life of the process.  Host code never passes
+// the array's name to a kernel (on the host it is only a stand-in for the
+// symbol): it uses the address hipGetSymbolAddress gives per device.
+namespace {
+constexpr size_t kScratchPosBytes = 256;
+constexpr size_t kScratchBytes = kScratchPosBytes + CI_NOALLOC_PART_BYTES;
+static_assert(kDecodeMaxBatch * sizeof(int32_t) <= kScratchPosBytes, "positions must fit the header");
+
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+constexpr int kScratchMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchMaxDevices];
+
+struct PosArg {
+  int32_t v[kDecodeMaxBatch];
+};
+
+// Positions reach the device as a kernel argument (no staging buffer).
+__global__ void __launch_bounds__(64) store_positions_kernel(PosArg p, uint32_t batch, int32_t* dst) {
+  if (threadIdx.x < batch) dst[threadIdx.x] = p.v[threadIdx.x];
+}
+}  // namespace
+
+ci_status_t ci::static_scratch_init(int device) {
+  if (device < 0 || device >= kScratchMaxDevices)
+    return set_err(CI_ERR_UNSUPPORTED, "static scratch: device %d beyond %d", device, kScratchMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return CI_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return set_err(CI_ERR_HIP, "static scratch: hipGetSymbolAddress on device %d: %s", device,
+                   hipGetErrorString(e));
+  if ((uintptr_t)ptr & 255)
+    return set_err(CI_ERR_HIP, "static scratch: device %d address %p not 256-byte aligned", device, ptr);
+  g_scratch_ptr[device] = ptr;
+  return CI_OK;
+}
+
+extern "C" ci_status_t ci_attention_decode_noalloc(ci_ctx_t* ctx, const float* q, const uint16_t* k_cache,
+                                                   const uint16_t* v_cache, const int32_t* pos,
+                                                   uint32_t batch, uint32_t n_q, uint32_t n_kv,
+                                                   uint32_t head_dim, uint32_t max_ctx, uint16_t* out,
+                                                   void* stream) {
+  if (!ctx || !q || !k_cache || !v_cache || !pos || !out)
+    return set_err(CI_ERR_INVALID_ARG, "ci_attention_decode_noalloc: NULL argument");
+  ci_decode_config_t c{8, n_q, n_kv, head_dim, 8, 0, 1, batch, max_ctx, 0.0f, 1.0f};
+  ci_status_t st = check_cfg(&c);
+  if (st != CI_OK) return st;
+  const ci_decode_layout_t L = layout_of(c);
+  if (L.attn_part_bytes > CI_NOALLOC_PART_BYTES)
+    return set_err(CI_ERR_INVALID_ARG,
+                   "ci_attention_decode_noalloc: %llu bytes of partial results exceed the static scratch "
+                   "limit of %llu (batch x n_q x ceil(max_ctx / 64) x (head_dim + 2) x 4)",
+                   (unsigned long long)L.attn_part_bytes, (unsigned long long)CI_NOALLOC_PART_BYTES);
+  if (!aligned16(k_cache) || !aligned16(v_cache))
+    return set_err(CI_ERR_INVALID_ARG, "ci_attention_decode_noalloc: misaligned cache");
+  PosArg pa{};
+  uint32_t mp = 0;
+  for (uint32_t b = 0; b < batch; ++b) {
+    if (pos[b] < 0 || (uint32_t)pos[b] >= max_ctx)
+      return set_err(CI_ERR_INVALID_ARG, "ci_attention_decode_noalloc: position %d of sequence %u not in [0, %u)",
+                     pos[b], b, max_ctx);
+    pa.v[b] = pos[b];
+    mp = std::max(mp, (uint32_t)pos[b]);
+  }
+  void* base = (ctx->device >= 0 && ctx->device < kScratchMaxDevices) ? g_scratch_ptr[ctx->device] : nullptr;
+  if (!base) return set_err(CI_ERR_UNSUPPORTED, "ci_attention_decode_noalloc: static scratch not set up");
+  int32_t* dpos = (int32_t*)base;
+  float* part = (float*)((uint8_t*)base + kScratchPosBytes);
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t caller = (hipStream_t)stream, xs = ctx->vstream;
+  st = exec_begin(ctx, caller, xs);
+  if (st != CI_OK) return st;
+  // every partial entry the combine reads is written by the partial kernel,
+  // and the positions are rewritten here: nothing needs clearing
+  HIPCHK(xlaunch(store_positions_kernel, dim3(1), dim3(64), 0, xs, nullptr, nullptr, pa, batch, dpos));
+  const uint32_t nchunks = (max_ctx + kChunk - 1) / kChunk;
+  HIPCHK(launch_attn_partial(q, k_cache, v_cache, dpos, part, batch, n_q, n_kv, head_dim, max_ctx, nchunks,
+                             mp / kChunk + 1, xs, nullptr, nullptr));
+  HIPCHK(launch_attn_combine(part, dpos, out, batch, n_q, head_dim, nchunks, xs, nullptr, nullptr));
   return exec_end(ctx, caller, xs);
 }
 

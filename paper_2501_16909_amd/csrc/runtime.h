@@ -120,4 +120,7 @@ ci_status_t launch_victim(ci_ctx* ctx, const ci_victim_desc_t* d, hipStream_t s,
                           hipEvent_t e1);
 ci_status_t run_victim(ci_ctx* ctx, const ci_victim_desc_t* d, hipStream_t caller, hipStream_t xs,
                        ci_victim_result_t* out);
+// Fetches, once per device, the device address of the static scratch array
+// that ci_attention_decode_noalloc works in; call with `device` current.
+ci_status_t static_scratch_init(int device);
 }  // namespace ci

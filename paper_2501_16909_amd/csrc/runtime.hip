@@ -223,6 +223,10 @@ extern "C" ci_status_t ci_init(int device, ci_ctx_t** out) {
     ci_shutdown(ctx);
     return set_err(CI_ERR_HIP, "ci_init: victim stream");
   }
+  if (ci_status_t sst = static_scratch_init(device); sst != CI_OK) {
+    ci_shutdown(ctx);
+    return sst;
+  }
 
   // Peaks.  Published MI355X figures where they exist; elsewhere bytes or
   // flops per clock per unit times units times the peak engine clock, or,

@@ -48,6 +48,7 @@ def test_struct_layouts_match_header(tmp_path):
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
         for f, _ in py._fields_:
             lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append('printf("CI_NOALLOC_PART_BYTES %llu\\n", (unsigned long long)CI_NOALLOC_PART_BYTES);')
     lines.append("return 0;}")
     src.write_text("\n".join(lines))
     exe = tmp_path / "sz"
@@ -58,6 +59,7 @@ def test_struct_layouts_match_header(tmp_path):
         for f, _ in py._fields_:
             assert int(out[f"{cname}.{f}"]) == getattr(py, f).offset, f"{cname}.{f}"
     assert ctypes.sizeof(coloc.WgRecord) == 48
+    assert int(out["CI_NOALLOC_PART_BYTES"]) == coloc.NOALLOC_PART_BYTES
 
 
 def test_errors_are_reported_without_a_device():
