@@ -60,6 +60,8 @@ def suite_resource(name: str) -> str:
         return "hbm"
     if name.startswith("mall_"):
         return "mall"
+    if name.startswith("lds_"):
+        return "lds"
     return name[:-4] if name.endswith("_32w") else name
 
 
@@ -121,6 +123,7 @@ class Suite:
             ("vl1d", dict(src0=self.l1, n=1 << 12, passes=4000), "TB/s", 1e12),
             ("lds", dict(src0=self.win, passes=10), "TB/s", 1e12),
             ("lds_32w", dict(src0=self.win, passes=10, wg_per_cu=2), "TB/s", 1e12),
+            ("lds_load", dict(src0=self.win, passes=20, access=1), "TB/s", 1e12),
             ("valu_f32", dict(dst=self.valu_out, iters=4096, passes=4, fa=1 - 2 ** -12, fb=2 ** -12), "TFLOP/s", 1e12),
             ("valu_f64", dict(dst=self.valu_out, iters=4096, passes=4, fa=1 - 2 ** -12), "TFLOP/s", 1e12),
             ("mfma_f32", dict(src0=self.mf["f32"][0], src1=self.mf["f32"][1], dst=self.mf_out, iters=2048, passes=2), "TFLOP/s", 1e12),
@@ -506,15 +509,16 @@ def run_suite(args):
         "data": "synthetic (SplitMix64 counter-form uniform [-1,1) / uint32 words / random cycle)",
         "config": {"workload": "stressor suite standalone: HBM triad FP32 N=2^30 (and its "
                                "read-only, copy and write-only mixes); L2 2 MiB; "
-                               "Infinity Cache 128 MiB (read, and write-only); vL1D 16 KiB; LDS 64 KiB/WG "
-                               "(L2 and LDS also at 32 waves/CU); FP32 FMA and FP64 multiply chains 4096; "
+                               "Infinity Cache 128 MiB (read, and write-only); vL1D 16 KiB; LDS 64 KiB/WG copy "
+                               "(L2 and LDS also at 32 waves/CU) and load-only; FP32 FMA and FP64 multiply chains 4096; "
                                "MFMA FP32/BF16/FP8; uint32 chase over 2^24 cycle; 10^6 empty "
                                "64-thread WGs; plus colocated triad pair N=2^22",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
                      "frac": round(achieved / 8000.0, 4),
                      "traffic": traffic,
-                     "kernel": "stream_stressor, triad mix (12 B per element, N=2^30, one pass per launch)"},
+                     "kernel": "stream_stressor<1u, true, 4, true>: triad mix, fixed work "
+                               "(12 B per element, N=2^30, one pass per launch)"},
         "stressors": stress,
         "colocated_triad_pair": pairs,
     }
@@ -1526,6 +1530,254 @@ def run_gemm_counters(args):
     print(json.dumps({"counters_run": "gemm bf16 4096^3 x3"}), flush=True)
 
 
+# ---------------------------------------------------------------- profiles
+# Summaries of rocprofv3 databases (rocpd SQLite) into the text files kept
+# under profiles/.  They run on any host: no GPU, no library.
+
+TCC_CHANNELS = 128      # 16 L2 channels per XCD x 8 XCDs; per-channel counters are summed over them
+GRBM_INSTANCES = 8      # GRBM_GUI_ACTIVE is summed over the 8 XCDs
+
+# the fixed-work launches of `--config counters`, by kernel
+HBM_COUNTER_KERNELS = [("triad", "stream_stressor<1u, true, 4, true>", 12),
+                       ("read", "strided_stressor<2u, true, 4>", 8),
+                       ("copy", "stream_stressor<3u, true, 4, true>", 8),
+                       ("write", "stream_stressor<4u, true, 4, true>", 4)]
+
+
+def _short_kernel(name: str) -> str:
+    n = name.replace("void ", "").replace("ci::(anonymous namespace)::", "").replace("(anonymous namespace)::", "")
+    depth = 0
+    for i, ch in enumerate(n):      # cut the argument list (the first "(" outside template brackets)
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return n[:i]
+    return n
+
+
+def _pmc_dispatches(db):
+    """[{name, grid, wg, start, end, ctr: {counter: value}}] in dispatch order."""
+    import sqlite3
+    con = sqlite3.connect(db)
+    rows = con.execute("select dispatch_id, kernel_name, grid_size, workgroup_size, counter_name, sum(value), "
+                       "min(start), max(end) from counters_collection group by dispatch_id, counter_name "
+                       "order by dispatch_id").fetchall()
+    con.close()
+    out = {}
+    for did, name, grid, wg, ctr, val, t0, t1 in rows:
+        d = out.setdefault(did, {"name": _short_kernel(name), "grid": int(grid), "wg": int(wg), "start": t0,
+                                 "end": t1, "ctr": {}})
+        d["ctr"][ctr] = float(val)
+    return [out[k] for k in sorted(out)]
+
+
+def run_counter_summary(args):
+    """HBM traffic and DRAM-side counters of `--config counters` from the
+    rocprofv3 --pmc databases given with --dbs (one counter set per run):
+    writes profiles/hbm_triad_n2e30_counters.{json,md}."""
+    n = 1 << 30
+    per = {mix: [] for mix, _, _ in HBM_COUNTER_KERNELS}
+    calib = []
+    for db in args.dbs:
+        seen = {mix: 0 for mix in per}
+        ncal = 0
+        copies = [d for d in _pmc_dispatches(db) if d["name"] == "__amd_rocclr_copyBuffer"]
+        big = max((d["grid"] for d in copies), default=0)
+        for d in _pmc_dispatches(db):
+            for mix, kname, _ in HBM_COUNTER_KERNELS:
+                if d["name"] == kname and d["grid"] == 256 * 512:
+                    if seen[mix] == len(per[mix]):
+                        per[mix].append({})
+                    per[mix][seen[mix]].update(d["ctr"])
+                    seen[mix] += 1
+            if d["name"] == "__amd_rocclr_copyBuffer" and d["grid"] == big and big > 0:
+                if ncal == len(calib):
+                    calib.append({})
+                calib[ncal].update(d["ctr"])
+                ncal += 1
+    mean = lambda xs: float(np.mean(xs)) if xs else None
+    gib = float(1 << 30)
+    ff = gib / (1024.0 * mean([c["FETCH_SIZE"] for c in calib if "FETCH_SIZE" in c]))
+    wf = gib / (1024.0 * mean([c["WRITE_SIZE"] for c in calib if "WRITE_SIZE" in c]))
+    mixes = {}
+    for mix, kname, bpe in HBM_COUNTER_KERNELS:
+        ls = per[mix]
+        get = lambda k: mean([l[k] for l in ls if k in l])
+        fetch, write = get("FETCH_SIZE"), get("WRITE_SIZE")
+        cyc = get("GRBM_GUI_ACTIVE") / GRBM_INSTANCES if get("GRBM_GUI_ACTIVE") else None
+        m = {"kernel": kname, "launches": len(ls), "fetch_kib": fetch, "write_kib": write,
+             "traffic_bytes": round(fetch * 1024 * ff + write * 1024 * wf),
+             "algorithmic_bytes": bpe * n,
+             "rdreq": get("TCC_EA0_RDREQ"), "rdreq_128b": get("TCC_EA0_RDREQ_128B"),
+             "rdreq_64b": get("TCC_EA0_RDREQ_64B"), "rdreq_32b": get("TCC_EA0_RDREQ_32B"),
+             "wrreq": get("TCC_EA0_WRREQ"), "wrreq_64b": get("TCC_EA0_WRREQ_64B"),
+             "cycles_per_xcd": cyc}
+        if cyc:
+            ch = TCC_CHANNELS * cyc
+            m["tcc_busy_frac"] = get("TCC_BUSY") / ch
+            m["rd_credit_stall_frac"] = get("TCC_EA0_RDREQ_DRAM_CREDIT_STALL") / ch
+            m["wr_credit_stall_frac"] = get("TCC_EA0_WRREQ_DRAM_CREDIT_STALL") / ch
+            m["reads_in_flight"] = get("TCC_EA0_RDREQ_LEVEL") / cyc
+            m["writes_in_flight"] = get("TCC_EA0_WRREQ_LEVEL") / cyc
+            if m["rdreq"] and m["rdreq"] > 1e6:
+                m["read_latency_cycles"] = get("TCC_EA0_RDREQ_LEVEL") / m["rdreq"]
+            if m["wrreq"] and m["wrreq"] > 1e6:
+                m["write_latency_cycles"] = get("TCC_EA0_WRREQ_LEVEL") / m["wrreq"]
+        mixes[mix] = m
+    t = mixes["triad"]
+    out = {"kernel": "stream_stressor<1u, true, 4, true> (HBM stressor, triad mix, N=2^30 FP32, one pass, "
+                     "256 work-groups x 512 threads)",
+           "kernel_sources": HBM_KERNEL_SOURCES,
+           "kernel_source_sha": sha_of(*[os.path.join(ROOT, p) for p in HBM_KERNEL_SOURCES]),
+           "commands": args.cmd,
+           "calibration_copy_1GiB": {"fetch_factor": round(ff, 4), "write_factor": round(wf, 4),
+                                     "note": "the runtime's 1 GiB device-to-device copy (1 GiB read, 1 GiB "
+                                             "written): the factors scale each counter to bytes"},
+           "traffic_bytes_per_launch": t["traffic_bytes"],
+           "algorithmic_bytes_per_launch": t["algorithmic_bytes"],
+           "traffic_over_algorithmic": round(t["traffic_bytes"] / t["algorithmic_bytes"], 4),
+           "mixes": mixes}
+    base = os.path.join(ROOT, "profiles", "hbm_triad_n2e30_counters")
+    with open(base + ".json", "w") as f:
+        json.dump(out, f, indent=1)
+    L = ["# HBM traffic and DRAM-side counters of the HBM stressor (N = 2^30 FP32, one pass per launch)", "",
+         "Commands (repository root, one MI355X; one counter set per run), then the summary:", "", "```"]
+    L += args.cmd + [" ".join(["python3 bench.py --config counter-summary --dbs"] + list(args.dbs)), "```", "",
+                     "`bench.py --config counters` launches the HBM stressor's triad mix over N = 2^30 twice "
+                     "(256 work-groups x 512 threads, one pass each), its read-only, copy and write-only "
+                     "mixes once each, then the runtime's 1 GiB device-to-device copy twice (the "
+                     "calibration kernel).", "",
+                     f"Calibration: FETCH_SIZE x {ff:.4f} and WRITE_SIZE x {wf:.4f} give bytes.", "",
+                     "| mix | kernel | traffic GiB (algorithmic) | 128 B reads | 64 B writes | L2 channels busy | "
+                     "DRAM credit stall rd / wr | reads in flight | read latency (cycles) |",
+                     "|---|---|---|---|---|---|---|---|---|"]
+    for mix, m in mixes.items():
+        L.append(f"| {mix} | `{m['kernel']}` | {m['traffic_bytes'] / gib:.3f} ({m['algorithmic_bytes'] / gib:.0f}) | "
+                 f"{(m['rdreq_128b'] or 0) / 1e6:.2f} M | {(m['wrreq_64b'] or 0) / 1e6:.2f} M | "
+                 f"{100 * m.get('tcc_busy_frac', float('nan')):.1f} % | "
+                 f"{100 * m.get('rd_credit_stall_frac', float('nan')):.1f} / "
+                 f"{100 * m.get('wr_credit_stall_frac', float('nan')):.1f} % | "
+                 f"{m.get('reads_in_flight', float('nan')):.0f} | {m.get('read_latency_cycles', float('nan')):.0f} |")
+    L += ["", f"Triad traffic per launch {t['traffic_bytes']} bytes against {t['algorithmic_bytes']} algorithmic "
+              f"(ratio {out['traffic_over_algorithmic']:.4f}): no re-reads, and no read of the output before "
+              "it is written.", "",
+          "Per-channel fractions divide by 128 L2 channels x GRBM_GUI_ACTIVE / 8 (the 8 XCDs' cycles); "
+          "in-flight counts divide the accumulated TCC_EA0_*REQ_LEVEL by the same cycles; latency is "
+          "in-flight / issue rate (Little's law).", "",
+          "The summary holds for the kernel sources whose hash it records; the benchmark reports the "
+          "traffic only while that hash matches."]
+    with open(base + ".md", "w") as f:
+        f.write("\n".join(L) + "\n")
+    print(json.dumps({"written": [base + ".json", base + ".md"], "triad_traffic": t["traffic_bytes"]}))
+
+
+def run_trace_summary(args):
+    """Kernel-trace summary (per kernel and launch shape: calls, average,
+    min, max, total) of one rocprofv3 --kernel-trace database, written to
+    --md; with --bench-json, the benchmark line's roofline kernel is checked
+    against the trace's average launch time."""
+    import sqlite3
+    con = sqlite3.connect(args.dbs[0])
+    rows = con.execute("select name, grid_x, workgroup_x, count(*), avg(duration), min(duration), max(duration), "
+                       "sum(duration) from kernels group by name, grid_x, workgroup_x "
+                       "order by sum(duration) desc").fetchall()
+    con.close()
+    L = [f"# {args.title}", "", "Command (repository root, one MI355X), then the summary:", "", "```"]
+    L += args.cmd + [" ".join(["python3 bench.py --config trace-summary --dbs"] + list(args.dbs)), "```", "",
+                     "| kernel | work-groups x threads | calls | avg us | min us | max us | total ms |",
+                     "|---|---|---|---|---|---|---|"]
+    for name, gx, wx, calls, avg, mn, mx, tot in rows:
+        L.append(f"| `{_short_kernel(name)}` | {gx // max(wx, 1)} x {wx} | {calls} | {avg / 1e3:.2f} | "
+                 f"{mn / 1e3:.2f} | {mx / 1e3:.2f} | {tot / 1e6:.3f} |")
+    if args.bench_json:
+        with open(args.bench_json) as f:
+            line = json.loads(f.read().strip().splitlines()[-1])
+        rf = line["roofline"]
+        kname = rf["kernel"].split(":")[0]
+        hit = [r for r in rows if _short_kernel(r[0]) == kname and r[1] == 256 * 512]
+        if hit:
+            avg_us = hit[0][4] / 1e3
+            live_us = 12.0 * (1 << 30) / (rf["achieved"] * 1e9) * 1e6
+            L += ["", f"Roofline kernel `{kname}`: the benchmark line of this run reports {rf['achieved']} GB/s, "
+                      f"that is {live_us:.1f} us per launch (12 x 2^30 bytes); the trace's average over "
+                      f"{hit[0][3]} launches (warm-up included) is {avg_us:.1f} us "
+                      f"({12.0 * (1 << 30) / (avg_us * 1e-6) / 1e9:.0f} GB/s), "
+                      f"{100 * (avg_us / live_us - 1):+.1f} %."]
+    with open(args.md, "w") as f:
+        f.write("\n".join(L) + "\n")
+    print(json.dumps({"written": args.md, "kernels": len(rows)}))
+
+
+# LDS stressor forms of `--config lds-counters`, in launch order:
+# (access, vector width in words, stride in vectors, passes)
+LDS_COUNTER_FORMS = [("copy", 4, 1, 10), ("load", 4, 1, 20), ("load", 2, 1, 10), ("load", 1, 1, 5),
+                     ("copy", 1, 1, 4), ("copy", 1, 2, 4), ("copy", 1, 4, 2), ("copy", 1, 8, 2),
+                     ("copy", 1, 16, 1), ("copy", 1, 32, 1), ("copy", 1, 64, 1), ("load", 1, 2, 4),
+                     ("load", 1, 32, 1)]
+
+
+def run_lds_counters(args):
+    """Short run for hardware-counter passes on the LDS stressor: each form
+    of LDS_COUNTER_FORMS once on every CU (16 waves per CU, fixed work)."""
+    import torch
+    import synth
+    from paper_2501_16909_amd import coloc
+    dev = torch.device("cuda:0")
+    ctx = coloc.Context(0)
+    w = torch.from_numpy(synth.u32(synth.seed_for(1, synth.BUF_LDS), 8192).view(np.int32)).to(dev)
+    rows = []
+    for access, vec, stride, passes in LDS_COUNTER_FORMS:
+        rep = ctx.stressor("lds", 1.0, src0=w, vec=vec, knob=stride, passes=passes,
+                           access=coloc.LDS_ACCESS[access]).stop()
+        rows.append({"access": access, "vec": vec, "stride": stride, "tb_s": round(rep.achieved / 1e12, 2),
+                     "pct_of_peak": round(rep.pct_of_peak, 1)})
+        log(f"lds {access} vec {vec} stride {stride}: {rep.achieved / 1e12:.2f} TB/s ({rep.pct_of_peak:.1f} %)")
+    ctx.close()
+    print(json.dumps({"counters_run": "lds stressor forms", "forms": rows}), flush=True)
+
+
+def run_lds_counter_summary(args):
+    """LDS counters of `--config lds-counters` from the rocprofv3 --pmc
+    databases given with --dbs: writes profiles/lds_stride_counters.md."""
+    per = [dict() for _ in LDS_COUNTER_FORMS]
+    for db in args.dbs:
+        ds = [d for d in _pmc_dispatches(db) if d["name"].startswith("lds_stressor<")]
+        if len(ds) != len(LDS_COUNTER_FORMS):
+            raise SystemExit(f"{db}: {len(ds)} LDS dispatches, expected {len(LDS_COUNTER_FORMS)}")
+        for i, d in enumerate(ds):
+            per[i].update(d["ctr"])
+    cus = 256
+    L = ["# LDS stressor: bank conflicts, LDS activity and bytes per clock (hardware counters)", "",
+         "Commands (repository root, one MI355X; one counter set per run), then the summary:", "", "```"]
+    L += args.cmd + [" ".join(["python3 bench.py --config lds-counter-summary --dbs"] + list(args.dbs)), "```", "",
+                     "`bench.py --config lds-counters` runs each form below once on all 256 CUs (one work-group "
+                     "of 16 waves per CU, 64 KiB of LDS, fixed work).  A stride of s vectors sends lane l to "
+                     "vector (l s + k) mod (8192 / width) on step k.", "",
+                     "Bytes per clock per CU = (SQ_INSTS_LDS_LOAD_BANDWIDTH + SQ_INSTS_LDS_STORE_BANDWIDTH) x 64 "
+                     "/ (GRBM_GUI_ACTIVE / 8) / 256; LDS active = SQ_LDS_IDX_ACTIVE / (GRBM_GUI_ACTIVE / 8) / 256; "
+                     "bank-conflict share = SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE; instruction issue = "
+                     "clocks per LDS instruction per CU.", "",
+                     "| form | width (words) | stride | B/clk/CU loaded | B/clk/CU stored | LDS active | "
+                     "bank-conflict share | address-conflict share | clocks per LDS instruction |",
+                     "|---|---|---|---|---|---|---|---|---|"]
+    for (access, vec, stride, _), c in zip(LDS_COUNTER_FORMS, per):
+        cyc = c["GRBM_GUI_ACTIVE"] / GRBM_INSTANCES
+        ld = c.get("SQ_INSTS_LDS_LOAD_BANDWIDTH", 0.0) * 64 / cyc / cus
+        stb = c.get("SQ_INSTS_LDS_STORE_BANDWIDTH", 0.0) * 64 / cyc / cus
+        act = c.get("SQ_LDS_IDX_ACTIVE", float("nan")) / cyc / cus
+        bank = c.get("SQ_LDS_BANK_CONFLICT", float("nan")) / c.get("SQ_LDS_IDX_ACTIVE", float("nan"))
+        addr = c.get("SQ_LDS_ADDR_CONFLICT", float("nan")) / c.get("SQ_LDS_IDX_ACTIVE", float("nan"))
+        ipc = cyc * cus / c["SQ_INSTS_LDS"] if c.get("SQ_INSTS_LDS") else float("nan")
+        L.append(f"| {access} | {vec} | {stride} | {ld:.1f} | {stb:.1f} | {100 * act:.1f} % | {100 * bank:.1f} % | "
+                 f"{100 * addr:.1f} % | {ipc:.2f} |")
+    out = os.path.join(ROOT, "profiles", "lds_stride_counters.md")
+    with open(out, "w") as f:
+        f.write("\n".join(L) + "\n")
+    print(json.dumps({"written": out}))
+
+
 def run_counters(args):
     """Short run for hardware-counter passes: the HBM stressor over N = 2^30
     (one pass per launch) twice, its read-only, copy and write-only mixes
@@ -1565,7 +1817,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="suite", choices=["suite", "sweep", "precision", "serve", "counters", "suite-counters",
                              "pollution", "bandwidth", "ilp", "pairs", "ldsstride", "estimator", "decode",
-                             "queues", "hbm_mix", "gemm-counters"])
+                             "queues", "hbm_mix", "gemm-counters", "counter-summary", "trace-summary",
+                             "lds-counters", "lds-counter-summary"])
+    ap.add_argument("--dbs", nargs="+", default=[], help="summaries: rocprofv3 databases to read")
+    ap.add_argument("--cmd", nargs="+", default=[], help="summaries: the commands that made the databases")
+    ap.add_argument("--md", default=None, help="trace-summary: markdown file to write")
+    ap.add_argument("--title", default="Kernel trace", help="trace-summary: heading")
+    ap.add_argument("--bench-json", default=None, help="trace-summary: the benchmark line of the traced run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true",
                     help="suite: the timed stressor suite only (no sensitivity, precision or serving blocks)")
@@ -1628,6 +1886,14 @@ def main():
         run_hbm_mix(args)
     elif args.config == "gemm-counters":
         run_gemm_counters(args)
+    elif args.config == "counter-summary":
+        run_counter_summary(args)
+    elif args.config == "trace-summary":
+        run_trace_summary(args)
+    elif args.config == "lds-counters":
+        run_lds_counters(args)
+    elif args.config == "lds-counter-summary":
+        run_lds_counter_summary(args)
 
 
 if __name__ == "__main__":

@@ -260,7 +260,15 @@ typedef struct ci_stressor_opts {
   uint32_t chunk;        /* HBM, MALL: 16-byte accesses per lane and stream in
                             one wave-chunk (1, 2 or 4; 0 = 4): a wave-chunk is
                             256 * chunk elements                            */
+  uint32_t access;       /* LDS: CI_LDS_COPY (0; each vector is loaded from one
+                            window and stored to the other, the paper's strided
+                            copy, Section 4.4.1) or CI_LDS_LOAD (loads only:
+                            the read path at full rate).  Must be 0 for every
+                            other resource                                  */
 } ci_stressor_opts_t;
+
+#define CI_LDS_COPY 0u
+#define CI_LDS_LOAD 1u
 
 typedef struct ci_stressor_report {
   int resource;

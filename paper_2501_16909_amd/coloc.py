@@ -20,6 +20,7 @@ RES = {name: i for i, name in enumerate(RESOURCES)}
 DTYPES = {"f32": 0, "bf16": 1, "fp8": 2}
 # HBM stressor traffic mixes (its `knob`): CI_HBM_TRIAD / READ / COPY / WRITE
 HBM_MIX = {"triad": 1, "read": 2, "copy": 3, "write": 4}
+LDS_ACCESS = {"copy": 0, "load": 1}
 VICTIMS = {"triad": 0, "gemm": 1, "gemv": 2}
 POLICIES = {"naive": 0, "usher": 1, "sensitivity": 2}
 STATUS = {0: "CI_OK", 1: "CI_ERR_INVALID_ARG", 2: "CI_ERR_HIP", 3: "CI_ERR_OOM",
@@ -53,7 +54,8 @@ class StressorOpts(C.Structure):
                 ("n", C.c_uint64), ("wg_per_cu", C.c_uint32), ("threads", C.c_uint32),
                 ("knob", C.c_uint32), ("vec", C.c_uint32), ("passes", C.c_uint64),
                 ("iters", C.c_uint64), ("fa", C.c_float), ("fb", C.c_float),
-                ("deadline_ms", C.c_uint32), ("duty", C.c_uint32), ("chunk", C.c_uint32)]
+                ("deadline_ms", C.c_uint32), ("duty", C.c_uint32), ("chunk", C.c_uint32),
+                ("access", C.c_uint32)]
 
 
 class StressorReport(C.Structure):

@@ -53,9 +53,9 @@ hipError_t launch_cache_stressor(const KCtrl& c, const uint32_t* region, uint64_
                                  uint64_t slice_words, uint32_t batch, uint32_t threads,
                                  hipStream_t s,
     hipEvent_t e0, hipEvent_t e1);
-hipError_t launch_lds_stressor(const KCtrl& c, const uint32_t* window, uint32_t vw,
-                               uint32_t stride, uint32_t threads, hipStream_t s,
-    hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_lds_stressor(const KCtrl& c, const uint32_t* window, uint32_t vw, uint32_t stride,
+                               bool load_only, uint32_t threads, hipStream_t s, hipEvent_t e0,
+                               hipEvent_t e1);
 hipError_t launch_valu_stressor(const KCtrl& c, float* out, uint32_t ilp, uint64_t iters,
                                 float fa, float fb, uint32_t threads, hipStream_t s,
     hipEvent_t e0, hipEvent_t e1);

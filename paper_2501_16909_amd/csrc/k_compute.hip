@@ -9,6 +9,8 @@
 // kernel that holds SM resources and blocks the block scheduler (Section 4.2)
 // becomes the occupancy hog; the per-block SM-ID print (Section 4.2
 // footnote) becomes the placement probe.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace ci {
@@ -43,8 +45,10 @@ __device__ __forceinline__ uint64_t wg_enter(const KCtrl& c, uint64_t* s_t0, uin
 // reading each from one window and storing it to the same place in the
 // other; the direction alternates every pass.  Stored values equal the ones
 // already there, so the contents never change.  `stride` sets how many lanes
-// of a wave land in the same bank.  record.check = sum of words read mod 2^32.
-template <int VW>
+// of a wave land in the same bank.  LOAD: the same walk without the stores
+// (the load path alone), reading each pass from A onward.  record.check =
+// sum of words read mod 2^32.
+template <int VW, bool LOAD>
 __global__ void __launch_bounds__(1024) lds_stressor(KCtrl c, const uint32_t* __restrict__ window,
                                                      uint32_t stride) {
   extern __shared__ uint32_t lds[];
@@ -67,27 +71,54 @@ __global__ void __launch_bounds__(1024) lds_stressor(KCtrl c, const uint32_t* __
   uint64_t passes = 0;
   uint64_t tp = duty_mark(c);
   for (;;) {
-    uint32_t* src = (passes & 1) ? lds + kWords : lds;
-    uint32_t* dst = (passes & 1) ? lds : lds + kWords;
-    uint32_t v = v0;
-    for (uint32_t kg = 0; kg < kVec; kg += 256) {
-      duty_point(c, tp);
-#pragma unroll 8
-      for (uint32_t k = 0; k < 256; ++k) {
-        if constexpr (VW == 4) {
-          const uint4 x = *reinterpret_cast<const uint4*>(src + v * 4);
-          *reinterpret_cast<uint4*>(dst + v * 4) = x;
-          acc += x.x + x.y + x.z + x.w;
-        } else if constexpr (VW == 2) {
-          const uint2 x = *reinterpret_cast<const uint2*>(src + v * 2);
-          *reinterpret_cast<uint2*>(dst + v * 2) = x;
-          acc += x.x + x.y;
-        } else {
-          const uint32_t x = src[v];
-          dst[v] = x;
-          acc += x;
+    if constexpr (LOAD) {
+      // Windows A and B are adjacent copies, so lane l's walk v0, v0+1, ...,
+      // v0+kVec-1 (mod kVec) reads the same words straight through A into B:
+      // no wrap, and the unrolled steps' addresses are immediate offsets.
+      // The load path then runs with two 3-input adds per 16-byte load, and
+      // the loads are issued in batches of 8 before their sums so that each
+      // wave keeps several in flight.  The last word read is at
+      // (2 kVec - 2) VW + VW - 1 < 2 kWords.
+      using V = typename std::conditional<VW == 4, uint4, typename std::conditional<VW == 2, uint2, uint32_t>::type>::type;
+      const V* base = reinterpret_cast<const V*>(lds + v0 * VW);
+      for (uint32_t kg = 0; kg < kVec; kg += 256) {
+        duty_point(c, tp);
+        const V* p = base + kg;
+        for (uint32_t k = 0; k < 256; k += 8) {
+          V x[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) x[j] = p[k + j];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            if constexpr (VW == 4) acc += x[j].x + x[j].y + x[j].z + x[j].w;
+            else if constexpr (VW == 2) acc += x[j].x + x[j].y;
+            else acc += x[j];
+          }
         }
-        v = (v + 1) & (kVec - 1);
+      }
+    } else {
+      uint32_t* src = (passes & 1) ? lds + kWords : lds;
+      uint32_t* dst = (passes & 1) ? lds : lds + kWords;
+      uint32_t v = v0;
+      for (uint32_t kg = 0; kg < kVec; kg += 256) {
+        duty_point(c, tp);
+#pragma unroll 8
+        for (uint32_t k = 0; k < 256; ++k) {
+          if constexpr (VW == 4) {
+            const uint4 x = *reinterpret_cast<const uint4*>(src + v * 4);
+            *reinterpret_cast<uint4*>(dst + v * 4) = x;
+            acc += x.x + x.y + x.z + x.w;
+          } else if constexpr (VW == 2) {
+            const uint2 x = *reinterpret_cast<const uint2*>(src + v * 2);
+            *reinterpret_cast<uint2*>(dst + v * 2) = x;
+            acc += x.x + x.y;
+          } else {
+            const uint32_t x = src[v];
+            dst[v] = x;
+            acc += x;
+          }
+          v = (v + 1) & (kVec - 1);
+        }
       }
     }
     ++passes;
@@ -473,13 +504,21 @@ __global__ void __launch_bounds__(64) probe_kernel(uint32_t* out) {
 }  // namespace
 
 hipError_t launch_lds_stressor(const KCtrl& c, const uint32_t* window, uint32_t vw, uint32_t stride,
-                               uint32_t threads, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+                               bool load_only, uint32_t threads, hipStream_t s, hipEvent_t e0,
+                               hipEvent_t e1) {
   const uint32_t shm = 2 * 8192 * 4;
+  const dim3 g(c.grid), t(threads);
+  if (load_only) {
+    switch (vw) {
+      case 1: return xlaunch(lds_stressor<1, true>, g, t, shm, s, e0, e1, c, window, stride);
+      case 2: return xlaunch(lds_stressor<2, true>, g, t, shm, s, e0, e1, c, window, stride);
+      default: return xlaunch(lds_stressor<4, true>, g, t, shm, s, e0, e1, c, window, stride);
+    }
+  }
   switch (vw) {
-    case 1: return xlaunch(lds_stressor<1>, dim3(c.grid), dim3(threads), shm, s, e0, e1, c, window, stride);
-    case 2: return xlaunch(lds_stressor<2>, dim3(c.grid), dim3(threads), shm, s, e0, e1, c, window, stride);
-    case 4: return xlaunch(lds_stressor<4>, dim3(c.grid), dim3(threads), shm, s, e0, e1, c, window, stride);
-    default: return hipErrorInvalidValue;
+    case 1: return xlaunch(lds_stressor<1, false>, g, t, shm, s, e0, e1, c, window, stride);
+    case 2: return xlaunch(lds_stressor<2, false>, g, t, shm, s, e0, e1, c, window, stride);
+    default: return xlaunch(lds_stressor<4, false>, g, t, shm, s, e0, e1, c, window, stride);
   }
 }
 

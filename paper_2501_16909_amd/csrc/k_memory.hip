@@ -210,7 +210,10 @@ __global__ void __launch_bounds__(1024) strided_stressor(KCtrl c, const float* _
   }
 }
 
-template <uint32_t MIX, bool NT, int U>
+//
+// FIXED (c.passes > 0) and persistent launches are separate instantiations,
+// so that traces and counters tell the fixed-work launches apart.
+template <uint32_t MIX, bool NT, int U, bool FIXED>
 __global__ void __launch_bounds__(1024) stream_stressor(KCtrl c, const float* __restrict__ b,
                                                         const float* __restrict__ cc,
                                                         float* __restrict__ a, uint64_t n) {
@@ -242,14 +245,14 @@ __global__ void __launch_bounds__(1024) stream_stressor(KCtrl c, const float* __
   const uint64_t nch = (n + kCh - 1) / kCh;
   const uint64_t lo = nch * slot / nslots, hi = nch * (slot + 1) / nslots;
   const uint64_t rounds = (hi - lo + wpg - 1) / wpg;  // tickets per sweep of the range
-  const uint64_t total = c.passes ? c.passes * rounds : 0;
+  const uint64_t total = FIXED ? c.passes * rounds : 0;
   uint64_t done = 0;
   uint32_t acc = 0;
   uint64_t tp = duty_mark(c);
   if (rounds) {
     for (;;) {
       const uint64_t t = s_ticket;
-      if (c.passes && t >= total) break;
+      if (FIXED && t >= total) break;
       const uint64_t ch = lo + (t % rounds) * wpg + wid;
       if (ch < hi) {
         stream_chunk<MIX, NT, U>(b, cc, a, ch * kCh, n, lane, acc);
@@ -260,16 +263,16 @@ __global__ void __launch_bounds__(1024) stream_stressor(KCtrl c, const float* __
       if (threadIdx.x == 0) {
         s_ticket = nxt;
         nxt = __hip_atomic_fetch_add(ticket, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (!c.passes && should_stop(sst, c)) s_stop = 1;
+        if (!FIXED && should_stop(sst, c)) s_stop = 1;
       }
       __syncthreads();
-      if (s_stop) break;
+      if (!FIXED && s_stop) break;
       // the busy stretch restarts after the barriers: time spent waiting
       // there for the other waves' idle periods is not work, and counting it
       // would make each idle period a multiple of the previous one
       tp = duty_mark(c);
     }
-  } else if (!c.passes) {  // an empty range: hold the slot until stopped
+  } else if (!FIXED) {  // an empty range: hold the slot until stopped
     for (;;) {
       if (threadIdx.x == 0 && should_stop(sst, c)) s_stop = 1;
       __syncthreads();
@@ -448,9 +451,12 @@ hipError_t launch_stream_stressor(const KCtrl& c, uint32_t mix, uint32_t chunk, 
                          : xlaunch(strided_stressor<kMixRead, false, 4>, g, t, 0, s, e0, e1, c, b, cc, a, n);
     }
   }
-#define CI_STREAM_LAUNCH(M, U)                                                                  \
-  return streaming ? xlaunch(stream_stressor<M, true, U>, g, t, 0, s, e0, e1, c, b, cc, a, n)   \
-                   : xlaunch(stream_stressor<M, false, U>, g, t, 0, s, e0, e1, c, b, cc, a, n)
+#define CI_STREAM_LAUNCH_F(M, U, F)                                                                \
+  return streaming ? xlaunch(stream_stressor<M, true, U, F>, g, t, 0, s, e0, e1, c, b, cc, a, n)   \
+                   : xlaunch(stream_stressor<M, false, U, F>, g, t, 0, s, e0, e1, c, b, cc, a, n)
+#define CI_STREAM_LAUNCH(M, U)                   \
+  if (c.passes) CI_STREAM_LAUNCH_F(M, U, true); \
+  CI_STREAM_LAUNCH_F(M, U, false)
 #define CI_STREAM_MIX(U)                              \
   switch (mix) {                                      \
     case kMixRead: CI_STREAM_LAUNCH(kMixRead, U);     \
@@ -465,6 +471,7 @@ hipError_t launch_stream_stressor(const KCtrl& c, uint32_t mix, uint32_t chunk, 
   }
 #undef CI_STREAM_MIX
 #undef CI_STREAM_LAUNCH
+#undef CI_STREAM_LAUNCH_F
 }
 
 hipError_t launch_triad_victim(const float* b, const float* c, float* a, uint64_t n,

@@ -243,12 +243,12 @@ extern "C" ci_status_t ci_init(int device, ci_ctx_t** out) {
   // figure of 17.2 TB/s is not reached by any shape.
   in.peak[CI_RES_MALL] = 7.65e12;
   in.peak[CI_RES_VL1D] = cus * 64.0 * f;                // 64 B/clk per CU
-  // LDS: measured ceiling of the unit's copy (one 16-byte read and one
-  // 16-byte write per lane and step, conflict-free, no vector-ALU work):
-  // 117 B/clk per CU.  The same loop reads at 247 B/clk per CU and writes at
-  // 76, so a copy is bounded by 2 / (1/247 + 1/76) = 116 B/clk; the CDNA3
-  // figure of 128 B/clk per CU fits neither direction on CDNA4.
-  in.peak[CI_RES_LDS] = cus * 117.0 * f;
+  // LDS: the load path, one 64-lane 16-byte load (1 KiB) per 4 clocks =
+  // 256 B/clk per CU (CDNA4 doubled CDNA3's 128).  The load-only stressor
+  // reaches 247 (96.5 %).  Stores are slower (76 B/clk per CU measured, no
+  // published figure), so the copy form (one load and one store of each
+  // vector) is bounded near 2 / (1/256 + 1/76) = 117 B/clk, 46 % of this peak.
+  in.peak[CI_RES_LDS] = cus * 256.0 * f;
   in.peak[CI_RES_VALU_F32] = cus * 4 * 16 * 2.0 * f;    // unpacked FMA: 16 lanes/clk/SIMD
   in.peak[CI_RES_MFMA_F32] = 157.3e12;                  // published dense
   in.peak[CI_RES_MFMA_BF16] = 2.5166e15;                // published dense (2.5 PF)
@@ -405,6 +405,8 @@ ci_status_t check_opts(ci_ctx* ctx, ci_resource_t r, const ci_stressor_opts_t& o
   if (o.threads == 0 || o.threads > 1024 || o.threads % 64)
     return set_err(CI_ERR_INVALID_ARG, "%s: threads %u must be a multiple of 64 in [64, 1024]",
                    kResName[r], o.threads);
+  if (r != CI_RES_LDS && o.access != 0)
+    return set_err(CI_ERR_INVALID_ARG, "%s: access %u is an LDS option (must be 0)", kResName[r], o.access);
   switch (r) {
     case CI_RES_HBM:
     case CI_RES_MALL: {
@@ -445,6 +447,8 @@ ci_status_t check_opts(ci_ctx* ctx, ci_resource_t r, const ci_stressor_opts_t& o
       if (!o.src0) return set_err(CI_ERR_INVALID_ARG, "lds: window (8192 words) is required");
       if (o.vec != 1 && o.vec != 2 && o.vec != 4) return set_err(CI_ERR_INVALID_ARG, "lds: vec must be 1, 2 or 4");
       if (o.knob == 0) return set_err(CI_ERR_INVALID_ARG, "lds: stride must be >= 1");
+      if (o.access != CI_LDS_COPY && o.access != CI_LDS_LOAD)
+        return set_err(CI_ERR_INVALID_ARG, "lds: access must be CI_LDS_COPY or CI_LDS_LOAD");
       if ((uint64_t)o.wg_per_cu * 65536 > ctx->info.lds_bytes_per_cu)
         return set_err(CI_ERR_INVALID_ARG, "lds: %u work-groups x 64 KiB exceed the CU's LDS", o.wg_per_cu);
       break;
@@ -553,7 +557,8 @@ static ci_status_t launch_kernel(ci_stressor* h, const KCtrl& c) {
       break;
     }
     case CI_RES_LDS:
-      e = launch_lds_stressor(c, (const uint32_t*)o.src0, o.vec, o.knob, o.threads, s, e0, e1);
+      e = launch_lds_stressor(c, (const uint32_t*)o.src0, o.vec, o.knob, o.access == CI_LDS_LOAD, o.threads,
+                              s, e0, e1);
       break;
     case CI_RES_VALU_F32:
       e = launch_valu_stressor(c, (float*)o.dst, o.knob, o.iters, o.fa, o.fb, o.threads, s, e0,
@@ -763,7 +768,8 @@ static double units_of(const ci_stressor* h, const std::vector<ci_wg_record_t>& 
     case CI_RES_L2:
     case CI_RES_VL1D:
       return 4.0 * (double)cache_span_words(o) * (double)work;
-    case CI_RES_LDS: return (double)work * waves * 64.0 * 8192.0 * 4.0 * 2.0;
+    case CI_RES_LDS:  // every lane walks the 8192-word window once per pass: loads, plus stores for copy
+      return (double)work * waves * 64.0 * 8192.0 * 4.0 * (o.access == CI_LDS_LOAD ? 1.0 : 2.0);
     case CI_RES_VALU_F32: return (double)work * o.threads * o.knob * (double)o.iters * 2.0;
     case CI_RES_MFMA_F32:
     case CI_RES_MFMA_BF16:

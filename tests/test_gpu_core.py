@@ -304,18 +304,23 @@ def test_zero_intensity_invariant(ctx, dev):
 def test_disjoint_idle_stressor_costs_nothing(ctx, dev):
     """A sleeping occupancy hog on CUs the victim does not use takes nothing
     the victim needs: with the queue-pair check in place the victim keeps its
-    alone speed on the complement CUs (1.00 +- 0.06 for a short victim)."""
+    alone speed on the complement CUs (1.00 +- 0.06 for a short victim).
+    The victim is one launch (one sweep of 384 MiB): a victim of many short
+    launches also pays the command processor's time between its launches,
+    which grows when another queue is active."""
     import torch
-    n = 1 << 22
+    n = 1 << 25
     tb = _t(synth.uniform_f32(synth.seed_for(0, synth.BUF_B), n), dev)
     tc = _t(synth.uniform_f32(synth.seed_for(0, synth.BUF_C), n), dev)
     ta = torch.empty_like(tb)
-    d = ctx.triad_desc(tb, tc, ta, passes=8)
+    d = ctx.triad_desc(tb, tc, ta, passes=1)
     cells = ctx.measure_sensitivity(d, ["occupancy"], [dict()], [0.25, 0.5], reps=16, warmups=3,
                                     placement="disjoint")
     for c in cells:
         assert c["output_equal"] and c["window_covered"], c
-        assert abs(c["slowdown"] - 1.0) <= 0.06, c
+        info = {k: c[k] for k in ("intensity", "slowdown", "slowdown_ci_lo", "slowdown_ci_hi", "t_alone_ns",
+                                  "t_col_ns", "queue_unresolved")}
+        assert abs(c["slowdown"] - 1.0) <= 0.06, info
     st = ctx.queue_stats()
     assert st["checks"] >= 1, st
     print("queue-pair check:", st, [round(c["slowdown"], 3) for c in cells])

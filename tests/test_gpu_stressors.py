@@ -155,22 +155,47 @@ def test_stream_stressor_duty_cycle(ctx, dev, res, mix, n):
 
 
 # -------------------------------------------------------------------- LDS
-@pytest.mark.parametrize("vec,stride", [(1, 1), (1, 2), (1, 32), (2, 1), (4, 1), (4, 3)])
-def test_lds_stressor_fixed(ctx, dev, vec, stride):
+@pytest.mark.parametrize("vec,stride,access", [(1, 1, 0), (1, 2, 0), (1, 32, 0), (2, 1, 0), (4, 1, 0), (4, 3, 0),
+                                               (4, 1, 1), (1, 32, 1), (2, 5, 1)])
+def test_lds_stressor_fixed(ctx, dev, vec, stride, access):
+    """Copy (access 0) and load-only (access 1) forms: every work-group's
+    checksum of the words it read matches the oracle, and the reported bytes
+    count loads, plus stores for the copy."""
     w = synth.u32(synth.seed_for(1, synth.BUF_LDS), 8192)
     st = ctx.stressor("lds", 0.25, src0=_t(w.view(np.int32), dev), vec=vec, knob=stride, passes=3,
-                      threads=256, wg_per_cu=2)
+                      threads=256, wg_per_cu=2, access=access)
     rep = st.stop()
     rec = st.records()
     exp = oracle.lds_wg_expected(w, vec, stride, waves=4, passes=rec["work"])
     assert np.all(rec["work"] == 3)
     assert np.array_equal(rec["check"].astype(np.uint32), exp)
-    assert rep.units == 3 * rep.grid * 4 * 64 * 8192 * 4 * 2
-    st = ctx.stressor("lds", 0.25, src0=_t(w.view(np.int32), dev), vec=vec, knob=stride, passes=2)
+    assert rep.units == 3 * rep.grid * 4 * 64 * 8192 * 4 * (1 if access else 2)
+    st = ctx.stressor("lds", 0.25, src0=_t(w.view(np.int32), dev), vec=vec, knob=stride, passes=2, access=access)
     rep = st.stop()   # default shape: 1024 threads (16 waves), one work-group per CU
     rec = st.records()
     assert np.array_equal(rec["check"].astype(np.uint32),
                           oracle.lds_wg_expected(w, vec, stride, waves=16, passes=rec["work"]))
+
+
+def test_lds_load_persistent_and_rejections(ctx, dev):
+    import time
+    from paper_2501_16909_amd import coloc
+    w = synth.u32(synth.seed_for(1, synth.BUF_LDS), 8192)
+    tw = _t(w.view(np.int32), dev)
+    with ctx.stressor("lds", 1.0, src0=tw, access=coloc.LDS_ACCESS["load"]) as st:
+        time.sleep(0.02)
+    rep = st.report
+    rec = st.records()
+    assert not rep.timed_out and np.all(rec["flags"] & 2) and np.all(rec["work"] > 0)
+    assert np.array_equal(rec["check"].astype(np.uint32),
+                          oracle.lds_wg_expected(w, 4, 1, waves=16, passes=rec["work"]))
+    print(f"lds load-only: {rep.achieved / 1e12:.1f} TB/s, {rep.pct_of_peak:.1f} % of the load path")
+    with pytest.raises(coloc.CiError) as ei:
+        ctx.stressor("lds", 0.25, src0=tw, access=2)
+    assert ei.value.status == 1
+    with pytest.raises(coloc.CiError) as ei:
+        ctx.stressor("valu_f32", 0.25, dst=tw, access=1)
+    assert ei.value.status == 1
 
 
 # ------------------------------------------------------------------- VALU
