@@ -65,6 +65,18 @@ def suite_resource(name: str) -> str:
     return name[:-4] if name.endswith("_32w") else name
 
 
+# The suite's entries in launch order, with the label the counter summary uses.
+SUITE_LABELS = [
+    ("hbm", "HBM triad N=2^30"), ("hbm_read", "HBM read-only N=2^30"), ("hbm_copy", "HBM copy N=2^30"),
+    ("hbm_write", "HBM write-only N=2^30"), ("l2", "L2 2 MiB (3 x 512 per CU)"),
+    ("l2_32w", "L2 2 MiB (2 x 1024 per CU)"), ("mall", "Infinity Cache 128 MiB read"),
+    ("mall_write", "Infinity Cache 128 MiB write-only"), ("vl1d", "vL1D 16 KiB"),
+    ("lds", "LDS copy vec4 stride 1 (1 WG of 16 waves per CU)"), ("lds_32w", "LDS copy, 2 WGs per CU"),
+    ("lds_load", "LDS load-only vec4 stride 1"), ("valu_f32", "VALU FMA ILP 8"),
+    ("valu_f64", "VALU FP64 multiply ILP 4"), ("mfma_f32", "MFMA FP32"), ("mfma_bf16", "MFMA BF16"),
+    ("mfma_fp8", "MFMA FP8"), ("ptrchase", "pointer chase 2^24"), ("dispatch", "dispatch 10^6 WGs")]
+
+
 class Suite:
     """Device buffers and the fixed-work form of every stressor."""
 
@@ -132,6 +144,7 @@ class Suite:
             ("ptrchase", dict(src0=self.chase, n=1 << 24, dst=self.chase_end, iters=512, passes=1), "Ghop/s", 1e9),
             ("dispatch", dict(iters=1000000, passes=1), "MWG/s", 1e6),
         ]
+        assert [it[0] for it in self.items] == [n for n, _ in SUITE_LABELS]
 
     def step(self, acc, warm: int = 0):
         for name, opts, unit, scale in self.items:
@@ -1710,6 +1723,62 @@ def run_trace_summary(args):
     print(json.dumps({"written": args.md, "kernels": len(rows)}))
 
 
+STRESSOR_KERNELS = ("stream_stressor<", "strided_stressor<", "cache_stressor", "lds_stressor<", "valu_stressor<",
+                    "valu64_stressor<", "mfma_stressor<", "chase_stressor<", "empty_wg")
+
+
+def run_suite_counter_summary(args):
+    """Per-stressor counters of `--config suite-counters` from four
+    rocprofv3 --pmc databases (--dbs A B F W: caches and GRBM, SQ, FETCH_SIZE,
+    WRITE_SIZE): writes profiles/stressor_counters.md."""
+    dbs = dict(zip("ABFW", args.dbs))
+    per = None
+    for key, db in dbs.items():
+        ds = [d for d in _pmc_dispatches(db) if d["name"].startswith(STRESSOR_KERNELS)]
+        if len(ds) != len(SUITE_LABELS):
+            raise SystemExit(f"{db}: {len(ds)} stressor dispatches, expected {len(SUITE_LABELS)}")
+        if per is None:
+            per = [{"kernel": d["name"], "grid": d["grid"], "wg": d["wg"]} for d in ds]
+        for i, d in enumerate(ds):
+            per[i].update(d["ctr"])
+    with open(os.path.join(ROOT, "profiles", "hbm_triad_n2e30_counters.json")) as f:
+        cal = json.load(f)["calibration_copy_1GiB"]
+    ff, wf = cal["fetch_factor"], cal["write_factor"]
+    g = lambda c, *names: next((c[n] for n in names if n in c), float("nan"))
+    L = ["# Hardware counters per stressor (one fixed-work launch each, MI355X)", "",
+         "Commands (repository root; one counter set per run), then the summary:", "", "```"]
+    L += args.cmd + [" ".join(["python3 bench.py --config suite-counter-summary --dbs"] + list(args.dbs)), "```", "",
+                     "Derived columns: active us = GRBM_GUI_ACTIVE / 8 XCDs / 2.4 GHz; L2 hit = TCC_HIT / (TCC_HIT "
+                     "+ TCC_MISS); vL1D hit = 1 - TCP_TCC_READ_REQ / TCP_TOTAL_CACHE_ACCESSES; VALU busy = 4 x "
+                     "SQ_INSTS_VALU / SIMD-cycles; MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / SIMD-cycles (SIMD-cycles "
+                     "= active cycles x 1024 SIMDs); LDS instr/CU/clk = SQ_INSTS_LDS / (active cycles x 256 CUs); "
+                     f"read / written past L2 = FETCH_SIZE x {ff:.4f} / WRITE_SIZE x {wf:.4f} KiB (the 1 GiB copy "
+                     "calibration of hbm_triad_n2e30_counters.md): traffic between the L2s and the memory side, "
+                     "served by the Infinity Cache or HBM; TB/s over the active time.", "",
+                     "| stressor | kernel | active us | L2 hit | L2 requests | vL1D hit | vL1D accesses | LDS instr | "
+                     "LDS bank conflicts | VALU busy | MFMA busy | waves | LDS instr/CU/clk | read past L2 GB | "
+                     "written past L2 GB | past L2 TB/s |",
+                     "|---|---|---|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    for (name, label), c in zip(SUITE_LABELS, per):
+        cyc = g(c, "GRBM_GUI_ACTIVE") / GRBM_INSTANCES
+        us = cyc / 2.4e3
+        hit, miss = g(c, "TCC_HIT_sum", "TCC_HIT"), g(c, "TCC_MISS_sum", "TCC_MISS")
+        tcp = g(c, "TCP_TOTAL_CACHE_ACCESSES_sum", "TCP_TOTAL_CACHE_ACCESSES")
+        tcp_miss = g(c, "TCP_TCC_READ_REQ_sum", "TCP_TCC_READ_REQ")
+        simd = cyc * 1024
+        rd = g(c, "FETCH_SIZE") * 1024 * ff / 1e9
+        wr = g(c, "WRITE_SIZE") * 1024 * wf / 1e9
+        L.append(f"| {label} | `{c['kernel']}` | {us:.1f} | {hit / (hit + miss):.3f} | {hit + miss:.3g} | "
+                 f"{1 - tcp_miss / tcp if tcp else float('nan'):.4f} | {tcp:.3g} | {g(c, 'SQ_INSTS_LDS'):.3g} | "
+                 f"{g(c, 'SQ_LDS_BANK_CONFLICT'):.0f} | {4 * g(c, 'SQ_INSTS_VALU') / simd:.2f} | "
+                 f"{g(c, 'SQ_VALU_MFMA_BUSY_CYCLES') / simd:.2f} | {g(c, 'SQ_WAVES'):.0f} | "
+                 f"{g(c, 'SQ_INSTS_LDS') / (cyc * 256):.3f} | {rd:.3f} | {wr:.3f} | {(rd + wr) / (us * 1e-6) / 1e3:.2f} |")
+    out = os.path.join(ROOT, "profiles", "stressor_counters.md")
+    with open(out, "w") as f:
+        f.write("\n".join(L) + "\n")
+    print(json.dumps({"written": out}))
+
+
 # LDS stressor forms of `--config lds-counters`, in launch order:
 # (access, vector width in words, stride in vectors, passes)
 LDS_COUNTER_FORMS = [("copy", 4, 1, 10), ("load", 4, 1, 20), ("load", 2, 1, 10), ("load", 1, 1, 5),
@@ -1818,7 +1887,7 @@ def main():
     ap.add_argument("--config", default="suite", choices=["suite", "sweep", "precision", "serve", "counters", "suite-counters",
                              "pollution", "bandwidth", "ilp", "pairs", "ldsstride", "estimator", "decode",
                              "queues", "hbm_mix", "gemm-counters", "counter-summary", "trace-summary",
-                             "lds-counters", "lds-counter-summary"])
+                             "lds-counters", "lds-counter-summary", "suite-counter-summary"])
     ap.add_argument("--dbs", nargs="+", default=[], help="summaries: rocprofv3 databases to read")
     ap.add_argument("--cmd", nargs="+", default=[], help="summaries: the commands that made the databases")
     ap.add_argument("--md", default=None, help="trace-summary: markdown file to write")
@@ -1894,6 +1963,8 @@ def main():
         run_lds_counters(args)
     elif args.config == "lds-counter-summary":
         run_lds_counter_summary(args)
+    elif args.config == "suite-counter-summary":
+        run_suite_counter_summary(args)
 
 
 if __name__ == "__main__":
