@@ -1028,7 +1028,7 @@ def run_pollution(args):
             synth.device_fill_uniform_f32(t.data_ptr(), n, synth.seed_for(5, i))
         torch.cuda.synchronize()
         passes = max(1, int(300e-6 * 4e12 / (12 * n)))    # >= ~0.3 ms per victim run
-        d = ctx.triad_desc(bufs[0], bufs[1], bufs[2], passes=passes)
+        d = ctx.triad_desc(bufs[0], bufs[1], bufs[2], passes=passes, in_kernel=True)   # re-reads hit the caches
         so = [dict(src0=bufs[3], src1=bufs[4], dst=bufs[5], n=n, vec=1)]   # cached accesses, as the victim
         cell = ctx.measure_sensitivity(d, ["hbm"], so, [0.5], reps=args.reps, warmups=2, placement="disjoint",
                                        ws=ws, deadline_ms=args.deadline_ms)[0]

@@ -347,9 +347,20 @@ typedef struct ci_victim_desc {
   const void* b;         /* TRIAD: c; GEMM: B (N x K row-major); GEMV: x (k)  */
   void* out;             /* TRIAD: a (n FP32); GEMM: C (M x N FP32); GEMV: y (n FP32) */
   float scale_a, scale_b;/* FP8 dequantisation scales (ignored otherwise)     */
-  uint32_t passes;       /* TRIAD sweeps per launch (>= 1)                     */
+  uint32_t passes;       /* TRIAD sweeps per run (>= 1)                        */
   uint32_t copies;       /* GEMV weight copies rotated over runs (>= 1)        */
+  uint32_t flags;        /* TRIAD: CI_VICTIM_TRIAD_IN_KERNEL or 0; 0 otherwise */
+  uint32_t reserved;     /* must be 0                                         */
 } ci_victim_desc_t;
+
+/* TRIAD victim flag.  Without it the run is `passes` launches of one sweep
+ * each, so every sweep reads the arrays from where a fresh launch finds
+ * them.  With it the passes run inside one launch: every wave sweeps its
+ * own chunks (w, w + W, ... for wave w of W) `passes` times, so a working
+ * set that fits a cache level is re-read from that level -- the form of the
+ * cache-pollution experiment (Section 4.3, Figure 3), whose instances keep
+ * copying their own data.  Same output either way. */
+#define CI_VICTIM_TRIAD_IN_KERNEL 1u
 
 typedef struct ci_victim_result {
   double time_ns;          /* launch time from HIP events                      */

@@ -72,7 +72,7 @@ class VictimDesc(C.Structure):
     _fields_ = [("kind", C.c_int), ("dtype", C.c_int), ("m", C.c_uint64), ("n", C.c_uint64),
                 ("k", C.c_uint64), ("a", C.c_void_p), ("b", C.c_void_p), ("out", C.c_void_p),
                 ("scale_a", C.c_float), ("scale_b", C.c_float), ("passes", C.c_uint32),
-                ("copies", C.c_uint32)]
+                ("copies", C.c_uint32), ("flags", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class VictimResult(C.Structure):
@@ -483,9 +483,11 @@ class Context:
         _check(load_library().ci_stamp(self.handle, _ptr(slot), _stream_handle(stream)))
 
     @staticmethod
-    def triad_desc(b, c, a, passes: int = 1) -> VictimDesc:
+    def triad_desc(b, c, a, passes: int = 1, in_kernel: bool = False) -> VictimDesc:
+        """in_kernel: the passes run inside one launch (CI_VICTIM_TRIAD_IN_KERNEL)."""
         d = VictimDesc()
         d.kind, d.dtype, d.n = 0, 0, b.numel()
+        d.flags = 1 if in_kernel else 0
         d.a, d.b, d.out = _ptr(b), _ptr(c), _ptr(a)
         d.passes, d.copies, d.scale_a, d.scale_b = passes, 1, 1.0, 1.0
         d._keep = (b, c, a)   # the descriptor holds raw pointers: keep the tensors alive
@@ -509,8 +511,8 @@ class Context:
         d._keep = (W, x, y)
         return d
 
-    def victim_triad(self, b, c, a, passes: int = 1, stream=None) -> VictimOutcome:
-        return self.victim_run(self.triad_desc(b, c, a, passes), stream)
+    def victim_triad(self, b, c, a, passes: int = 1, stream=None, in_kernel: bool = False) -> VictimOutcome:
+        return self.victim_run(self.triad_desc(b, c, a, passes, in_kernel), stream)
 
     def checksum(self, x) -> tuple:
         self._sync_torch()

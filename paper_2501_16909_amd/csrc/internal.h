@@ -46,9 +46,11 @@ hipError_t launch_stream_stressor(const KCtrl& c, uint32_t mix, uint32_t chunk, 
                                   const float* cc, float* a, uint64_t n, uint32_t threads,
                                   bool streaming, bool strided, hipStream_t s, hipEvent_t e0,
                                   hipEvent_t e1);
+// in_kernel: the passes loop inside one launch (each wave re-sweeps its own
+// chunks) instead of one launch per pass
 hipError_t launch_triad_victim(const float* b, const float* c, float* a, uint64_t n,
-                               uint32_t passes, uint32_t grid, hipStream_t s, hipEvent_t e0,
-                               hipEvent_t e1);
+                               uint32_t passes, bool in_kernel, uint32_t grid, hipStream_t s,
+                               hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_cache_stressor(const KCtrl& c, const uint32_t* region, uint64_t region_words,
                                  uint64_t slice_words, uint32_t batch, uint32_t threads,
                                  hipStream_t s,

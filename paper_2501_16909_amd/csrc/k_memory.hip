@@ -302,14 +302,18 @@ __global__ void __launch_bounds__(1024) stream_stressor(KCtrl c, const float* __
 // that every sweep reads the whole array however many work-groups are
 // resident (a loop over sweeps inside the kernel would let resident waves
 // re-read their own chunks from the L2 while the others wait).
+// With `passes` > 1 (the in-kernel form) every wave sweeps its own chunks
+// that many times.
 __global__ void __launch_bounds__(256) triad_victim(const float* __restrict__ b,
                                                     const float* __restrict__ c,
-                                                    float* __restrict__ a, uint64_t n) {
+                                                    float* __restrict__ a, uint64_t n,
+                                                    uint32_t passes) {
   constexpr uint64_t kChunk = 1024;
   const uint32_t lane = threadIdx.x & 63u;
   const uint64_t gw = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
   const uint64_t nchunks = (n + kChunk - 1) / kChunk;
+  for (uint32_t p = 0; p < passes; ++p)
   for (uint64_t ch = gw; ch < nchunks; ch += nw) {
     const uint64_t base = ch * kChunk;
     if (base + kChunk <= n) {
@@ -475,11 +479,13 @@ hipError_t launch_stream_stressor(const KCtrl& c, uint32_t mix, uint32_t chunk, 
 }
 
 hipError_t launch_triad_victim(const float* b, const float* c, float* a, uint64_t n,
-                               uint32_t passes, uint32_t grid, hipStream_t s, hipEvent_t e0,
-                               hipEvent_t e1) {
+                               uint32_t passes, bool in_kernel, uint32_t grid, hipStream_t s,
+                               hipEvent_t e0, hipEvent_t e1) {
+  if (in_kernel)
+    return xlaunch(triad_victim, dim3(grid), dim3(kTriadThreads), 0, s, e0, e1, b, c, a, n, passes);
   for (uint32_t p = 0; p < passes; ++p) {
     const hipError_t e = xlaunch(triad_victim, dim3(grid), dim3(kTriadThreads), 0, s, p == 0 ? e0 : nullptr,
-                                 p + 1 == passes ? e1 : nullptr, b, c, a, n);
+                                 p + 1 == passes ? e1 : nullptr, b, c, a, n, 1u);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

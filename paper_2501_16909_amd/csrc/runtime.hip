@@ -1080,6 +1080,9 @@ namespace {
 
 ci_status_t check_victim(const ci_victim_desc_t* d) {
   if (!d) return set_err(CI_ERR_INVALID_ARG, "victim: NULL descriptor");
+  if (d->reserved) return set_err(CI_ERR_INVALID_ARG, "victim: reserved field must be 0");
+  if (d->flags & ~(d->kind == CI_VICTIM_TRIAD_F32 ? CI_VICTIM_TRIAD_IN_KERNEL : 0u))
+    return set_err(CI_ERR_INVALID_ARG, "victim: flags 0x%x not valid for kind %d", d->flags, d->kind);
   switch (d->kind) {
     case CI_VICTIM_TRIAD_F32:
       if (d->n && (!d->a || !d->b || !d->out)) return set_err(CI_ERR_INVALID_ARG, "triad: NULL operand");
@@ -1136,7 +1139,7 @@ ci_status_t ci::launch_victim(ci_ctx* ctx, const ci_victim_desc_t* d, hipStream_
       const uint64_t cap = (uint64_t)ctx->info.num_cus * 8;
       if (g > cap) g = cap;
       e = launch_triad_victim((const float*)d->a, (const float*)d->b, (float*)d->out, d->n, d->passes,
-                              (uint32_t)g, s, e0, e1);
+                              (d->flags & CI_VICTIM_TRIAD_IN_KERNEL) != 0, (uint32_t)g, s, e0, e1);
       break;
     }
     case CI_VICTIM_GEMM: {

@@ -90,15 +90,16 @@ def test_device_fill_matches_host_generator(ctx, dev):
     assert np.array_equal(w.cpu().numpy().view(np.uint32), synth.u32(999, n))
 
 
-@pytest.mark.parametrize("n,passes", [(0, 1), (1, 1), (1023, 1), (1024, 2), ((1 << 20) + 333, 3),
-                                      (1 << 22, 1)])
-def test_triad_victim_matches_oracle(ctx, dev, n, passes):
+@pytest.mark.parametrize("n,passes,in_kernel", [(0, 1, False), (1, 1, False), (1023, 1, False), (1024, 2, False),
+                                                ((1 << 20) + 333, 3, False), (1 << 22, 1, False),
+                                                (1023, 3, True), ((1 << 20) + 333, 5, True), (1 << 22, 2, True)])
+def test_triad_victim_matches_oracle(ctx, dev, n, passes, in_kernel):
     import torch
     b = synth.uniform_f32(synth.seed_for(0, synth.BUF_B), n)
     c = synth.uniform_f32(synth.seed_for(0, synth.BUF_C), n)
     tb, tc = _t(b, dev), _t(c, dev)
     ta = torch.full((max(n, 1),), float("nan"), device=dev)[:n]
-    r = ctx.victim_triad(tb, tc, ta, passes=passes)
+    r = ctx.victim_triad(tb, tc, ta, passes=passes, in_kernel=in_kernel)
     want = oracle.triad_f32(b, c)
     got = ta.cpu().numpy()
     assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
@@ -106,6 +107,21 @@ def test_triad_victim_matches_oracle(ctx, dev, n, passes):
     assert oracle.rel_err_sum(r.sum_f64, want) <= 1e-6
     assert r.time_ns > 0 or n == 0
     assert r.t_end >= r.t_begin
+
+
+def test_victim_flags_validated(ctx, dev):
+    import torch
+    from paper_2501_16909_amd import coloc
+    t = torch.zeros(1024, dtype=torch.float32, device=dev)
+    d = ctx.triad_desc(t, t, t, passes=1)
+    d.flags = 2
+    with pytest.raises(coloc.CiError) as ei:
+        ctx.victim_run(d)
+    assert ei.value.status == 1
+    d.flags, d.reserved = 0, 1
+    with pytest.raises(coloc.CiError) as ei:
+        ctx.victim_run(d)
+    assert ei.value.status == 1
 
 
 def test_triad_sum_relative_error_full_size(ctx, dev):
