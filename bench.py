@@ -664,12 +664,12 @@ def run_sweep(args):
     t0 = time.perf_counter()
     for placement in ("shared", "disjoint"):
         for vname, d in victims.items():
-            cells = ctx.measure_sensitivity(d, res, [o for _, _, o in rows], INTENSITIES, reps=args.reps,
-                                            warmups=3, placement=placement, ws=ws,
-                                            deadline_ms=args.deadline_ms)
             tab = {}
-            for i, (r, _, _) in enumerate(rows):
-                row = cells[i * len(INTENSITIES):(i + 1) * len(INTENSITIES)]
+            for i, (r, rr, o) in enumerate(rows):
+                # one call per stressor row: each ends with a log line
+                row = ctx.measure_sensitivity(d, [rr], [o], INTENSITIES, reps=args.reps, warmups=3,
+                                              placement=placement, ws=ws, deadline_ms=args.deadline_ms)
+                log(f"{vname} {placement} {r}: {[round(c['slowdown'], 3) for c in row]}")
                 nan = lambda v: v != v
                 tab[r] = {"slowdown": [None if nan(c["slowdown"]) else round(c["slowdown"], 3) for c in row],
                           "p90": [None if nan(c["slowdown_p90"]) else round(c["slowdown_p90"], 3) for c in row],
@@ -679,7 +679,8 @@ def run_sweep(args):
                           # a stressor that hit its deadline outlived the victim's
                           # starvation: the slowdown is then a lower bound
                           "starved": [bool(c["timed_out"]) for c in row],
-                          "valid": [bool(c["window_covered"] and c["output_equal"]) and not nan(c["slowdown"])
+                          "valid": [bool(c["window_covered"] and c["output_equal"] and not c["queue_unresolved"])
+                                    and not nan(c["slowdown"])
                                     for c in row],
                           "t_alone_us": [None if nan(c["t_alone_ns"]) else round(c["t_alone_ns"] / 1e3, 2) for c in row]}
             out["tables"][f"{vname}/{placement}"] = tab
@@ -726,7 +727,8 @@ def run_hbm_mix(args):
                 nan = lambda v: v != v
                 tab[m] = {"slowdown": [None if nan(c["slowdown"]) else round(c["slowdown"], 3) for c in row],
                           "stressor_gbs": [round(c["stressor_achieved"] / 1e9, 1) for c in row],
-                          "valid": [bool(c["window_covered"] and c["output_equal"]) and not nan(c["slowdown"])
+                          "valid": [bool(c["window_covered"] and c["output_equal"] and not c["queue_unresolved"])
+                                    and not nan(c["slowdown"])
                                     for c in row]}
             out["tables"][f"{vname}/{placement}"] = tab
             log(f"{vname} {placement}: " + ", ".join(f"{m}={tab[m]['slowdown'][-1]}" for m in tab))

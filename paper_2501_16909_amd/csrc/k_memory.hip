@@ -212,9 +212,13 @@ __global__ void __launch_bounds__(1024) strided_stressor(KCtrl c, const float* _
 
 //
 // FIXED (c.passes > 0) and persistent launches are separate instantiations,
-// so that traces and counters tell the fixed-work launches apart.
+// so that traces and counters tell the fixed-work launches apart.  At most
+// 64 registers per wave: two stressor waves per SIMD (its default shape)
+// then leave 384 of the SIMD's 512 for a victim, which is what the GEMM
+// victim's two 187-register waves take.
 template <uint32_t MIX, bool NT, int U, bool FIXED>
-__global__ void __launch_bounds__(1024) stream_stressor(KCtrl c, const float* __restrict__ b,
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
+stream_stressor(KCtrl c, const float* __restrict__ b,
                                                         const float* __restrict__ cc,
                                                         float* __restrict__ a, uint64_t n) {
   __shared__ uint64_t s_t0;
