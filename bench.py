@@ -70,7 +70,8 @@ SUITE_LABELS = [
     ("hbm", "HBM triad N=2^30"), ("hbm_read", "HBM read-only N=2^30"), ("hbm_copy", "HBM copy N=2^30"),
     ("hbm_write", "HBM write-only N=2^30"), ("l2", "L2 2 MiB (3 x 512 per CU)"),
     ("l2_32w", "L2 2 MiB (2 x 1024 per CU)"), ("mall", "Infinity Cache 128 MiB read"),
-    ("mall_write", "Infinity Cache 128 MiB write-only"), ("vl1d", "vL1D 16 KiB"),
+    ("mall_write", "Infinity Cache 128 MiB write-only"), ("mall_32w", "Infinity Cache 128 MiB read, 2 x 1024 per CU"),
+    ("vl1d", "vL1D 16 KiB"),
     ("lds", "LDS copy vec4 stride 1 (1 WG of 16 waves per CU)"), ("lds_32w", "LDS copy, 2 WGs per CU"),
     ("lds_load", "LDS load-only vec4 stride 1"), ("valu_f32", "VALU FMA ILP 8"),
     ("valu_f64", "VALU FP64 multiply ILP 4"), ("mfma_f32", "MFMA FP32"), ("mfma_bf16", "MFMA BF16"),
@@ -132,6 +133,8 @@ class Suite:
             ("l2_32w", dict(src0=self.l2, n=1 << 19, passes=32, wg_per_cu=2, threads=1024), "TB/s", 1e12),
             ("mall", dict(src0=self.mb, src1=self.mc, n=self.n_mall, passes=60), "TB/s", 1e12),
             ("mall_write", dict(dst=self.ma, n=self.n_mall, passes=240, knob=mix["write"]), "TB/s", 1e12),
+            ("mall_32w", dict(src0=self.mb, src1=self.mc, n=self.n_mall, passes=60, wg_per_cu=2, threads=1024),
+             "TB/s", 1e12),
             ("vl1d", dict(src0=self.l1, n=1 << 12, passes=4000), "TB/s", 1e12),
             ("lds", dict(src0=self.win, passes=10), "TB/s", 1e12),
             ("lds_32w", dict(src0=self.win, passes=10, wg_per_cu=2), "TB/s", 1e12),
@@ -405,18 +408,15 @@ def precision_block(ctx, dev, keep_host):
 
 
 def serving_block(ctx, args, keep_host):
-    """The serving loop on BASELINE-shaped traffic: Poisson arrivals of BF16
+    """The serving loop on the serving configuration's traffic: Poisson arrivals of BF16
     GEMM / BF16 GEMV / FP32 triad requests, naive against sensitivity-aware
     admission (duty-axis profiles measured here, read/write-aware HBM
     pricing), 60 s at 200 requests/s and 10 s at 1000/s.  Every request is
     also served alone (one slot, in arrival order) for its isolated service
     time and result: slowdowns are over all requests, and every result must
     equal its isolated one bit for bit."""
-    profiles = serve_profiles(ctx, args, axis="duty")
-    reads = serve_profiles(ctx, args, axis="duty", hbm_mix="read", res=("hbm",))
-    for kind, p in profiles.items():
-        p["sens_hbm_read"] = reads[kind]["sens"]["hbm"]
-        p["press_hbm_read"] = reads[kind]["press"]["hbm"]
+    profiles = library_profiles(serve_profiles(ctx, args, axis="duty"),
+                                serve_profiles(ctx, args, axis="duty", hbm_mix="read", res=("hbm",)))
     budget, slots = 32 << 30, 4
     summary = {"config": {"workload": "Poisson arrivals, 1/3 each BF16 GEMM n~logU[512,8192], BF16 GEMV "
                                       "n~logU[4096,16384], FP32 triad N~logU[2^20,2^28]",
@@ -522,7 +522,7 @@ def run_suite(args):
         "data": "synthetic (SplitMix64 counter-form uniform [-1,1) / uint32 words / random cycle)",
         "config": {"workload": "stressor suite standalone: HBM triad FP32 N=2^30 (and its "
                                "read-only, copy and write-only mixes); L2 2 MiB; "
-                               "Infinity Cache 128 MiB (read, and write-only); vL1D 16 KiB; LDS 64 KiB/WG copy "
+                               "Infinity Cache 128 MiB (read, also at 32 waves/CU, and write-only); vL1D 16 KiB; LDS 64 KiB/WG copy "
                                "(L2 and LDS also at 32 waves/CU) and load-only; FP32 FMA and FP64 multiply chains 4096; "
                                "MFMA FP32/BF16/FP8; uint32 chase over 2^24 cycle; 10^6 empty "
                                "64-thread WGs; plus colocated triad pair N=2^22",
@@ -1359,6 +1359,19 @@ def median_profiles(runs):
     return out
 
 
+def library_profiles(profiles, reads):
+    """Profiles in the library's form (ci_profile_t through coloc.make_profiles):
+    each kind's curves and pressures plus its curve and pressure against the
+    read-only HBM mix, for read/write-aware pricing."""
+    out = {}
+    for kind, p in profiles.items():
+        q = dict(p)
+        q["sens_hbm_read"] = reads[kind]["sens"]["hbm"]
+        q["press_hbm_read"] = reads[kind]["press"]["hbm"]
+        out[kind] = q
+    return out
+
+
 def predicted_pair_slowdown(profiles, a, b, read_profiles=None, mall_profiles=None):
     """Product over resources of max(1, curve_A(pressure of B)).  With
     read_profiles (HBM curves and pressures against the read-only mix), a
@@ -1379,6 +1392,79 @@ def predicted_pair_slowdown(profiles, a, b, read_profiles=None, mall_profiles=No
     return out
 
 
+def estimator_victim(ctx, kind: str, seed: int):
+    """One instance of a request kind at the estimator's sizes: BF16 GEMM
+    2048^3, BF16 GEMV 8192^2, FP32 triad 2^24 (uniform inputs from `seed`)."""
+    import torch
+    import synth
+    dev = ctx.device
+    if kind == "gemm":
+        g = 2048
+        A = torch.from_numpy(synth.uniform_f32(seed, g * g)).to(dev)
+        B = torch.from_numpy(synth.uniform_f32(seed + 1, g * g)).to(dev)
+        qa, _ = ctx.quantize(A, "bf16")
+        qb, _ = ctx.quantize(B, "bf16")
+        return ctx.gemm_desc(qa, qb, torch.empty((g, g), dtype=torch.float32, device=dev), "bf16", g, g, g)
+    if kind == "gemv":
+        n = 8192
+        W = torch.from_numpy(synth.uniform_f32(seed, n * n)).to(dev)
+        X = torch.from_numpy(synth.uniform_f32(seed + 1, n)).to(dev)
+        qw, _ = ctx.quantize(W, "bf16")
+        qx, _ = ctx.quantize(X, "bf16")
+        return ctx.gemv_desc(qw, qx, torch.empty(n, dtype=torch.float32, device=dev), n, n)
+    t = 1 << 24
+    tb = torch.from_numpy(synth.uniform_f32(seed, t)).to(dev)
+    tc = torch.from_numpy(synth.uniform_f32(seed + 1, t)).to(dev)
+    return ctx.triad_desc(tb, tc, torch.empty_like(tb), passes=1)
+
+
+def measure_pair(ctx, da, db, reps: int, streams: int = 3, max_attempts: int = 8):
+    """Slowdown of victim A while B runs beside it.  B goes on a fresh
+    stream, bracketed by two device stamps; a colocated run counts only if
+    B's stamps cover A's whole window (A started after B's first launches,
+    ended before B's last one).  Two kernels on two queues can also slow
+    each other through the queues alone, which only adds: the pair is
+    measured on up to `streams` streams that gave covered runs and the
+    lowest ratio is kept.  Returns (lowest, per-stream ratios, streams tried)."""
+    import torch
+    dev = ctx.device
+    stamps = torch.zeros(2, dtype=torch.int64, device=dev)
+    started = torch.cuda.Event()
+    t_a = float(np.median([ctx.victim_run(da).time_ns for _ in range(5)]))
+    tb_alone = float(np.median([ctx.victim_run(db).time_ns for _ in range(3)]))
+    count = int(min(4000, max(20, 6.0 * t_a / tb_alone)))
+    trials, attempts = [], 0
+    while len(trials) < streams and attempts < max_attempts:
+        attempts += 1
+        side = torch.cuda.Stream(device=dev)
+        alone, col = [], []
+        for r in range(reps):
+            if r % 2 == 0:
+                alone.append(ctx.victim_run(da).time_ns)
+            side.synchronize()
+            # a short first batch, then the timed victim starts while the
+            # main batch runs
+            ctx.victim_enqueue(db, side, 2)
+            ctx.stamp(stamps[0:1], side)
+            started.record(side)
+            ctx.victim_enqueue(db, side, count)
+            ctx.stamp(stamps[1:2], side)
+            while not started.query():
+                pass
+            out_a = ctx.victim_run(da)
+            side.synchronize()
+            s0, s1 = (int(v) for v in stamps.cpu().tolist())
+            if s0 <= out_a.t_begin and s1 >= out_a.t_end:
+                col.append(out_a.time_ns)
+            if r % 2 == 1:
+                alone.append(ctx.victim_run(da).time_ns)
+        if len(col) * 2 > reps:
+            trials.append(float(np.median(col) / np.median(alone)))
+    if not trials:
+        raise RuntimeError("estimator pair: the co-runner never covered the victim")
+    return min(trials), trials, attempts
+
+
 def run_estimator(args):
     """Kernel-level interference estimator (Section 5.1), validated on
     workload pairs: predict the slowdown of victim A while victim B runs
@@ -1386,11 +1472,8 @@ def run_estimator(args):
     runs), from A's sensitivity curves and B's standalone pressure, and
     compare with the measured slowdown (medians of counterbalanced runs,
     lowest of three co-runner streams)."""
-    import torch
-    import synth
     from paper_2501_16909_amd import coloc
     ctx = coloc.Context(0)
-    dev = ctx.device
     def profiles(**kw):
         # the point-wise median over --profile-runs independent measurements
         runs = [serve_profiles(ctx, args, **kw) for _ in range(max(1, args.profile_runs))]
@@ -1403,74 +1486,15 @@ def run_estimator(args):
     log("profiles: " + json.dumps(axes))
     log("read-mix HBM profiles: " + json.dumps(read_axes))
     log("Infinity-Cache profiles: " + json.dumps(mall_axes))
-    # two independent instances of each kind (A's buffers and B's buffers)
-    def make(kind, seed):
-        if kind == "gemm":
-            g = 2048
-            A = torch.from_numpy(synth.uniform_f32(seed, g * g)).to(dev)
-            B = torch.from_numpy(synth.uniform_f32(seed + 1, g * g)).to(dev)
-            qa, _ = ctx.quantize(A, "bf16")
-            qb, _ = ctx.quantize(B, "bf16")
-            return ctx.gemm_desc(qa, qb, torch.empty((g, g), dtype=torch.float32, device=dev), "bf16", g, g, g)
-        if kind == "gemv":
-            n = 8192
-            W = torch.from_numpy(synth.uniform_f32(seed, n * n)).to(dev)
-            X = torch.from_numpy(synth.uniform_f32(seed + 1, n)).to(dev)
-            qw, _ = ctx.quantize(W, "bf16")
-            qx, _ = ctx.quantize(X, "bf16")
-            return ctx.gemv_desc(qw, qx, torch.empty(n, dtype=torch.float32, device=dev), n, n)
-        t = 1 << 24
-        tb = torch.from_numpy(synth.uniform_f32(seed, t)).to(dev)
-        tc = torch.from_numpy(synth.uniform_f32(seed + 1, t)).to(dev)
-        return ctx.triad_desc(tb, tc, torch.empty_like(tb), passes=1)
+    lib_profiles = library_profiles(axes["duty"], read_axes["duty"])
     kinds = ["gemm", "gemv", "triad"]
-    A = {k: make(k, 7000 + 10 * i) for i, k in enumerate(kinds)}
-    B = {k: make(k, 8000 + 10 * i) for i, k in enumerate(kinds)}
-    stamps = torch.zeros(2, dtype=torch.int64, device=dev)
-    started = torch.cuda.Event()
+    # two independent instances of each kind (A's buffers and B's buffers)
+    A = {k: estimator_victim(ctx, k, 7000 + 10 * i) for i, k in enumerate(kinds)}
+    B = {k: estimator_victim(ctx, k, 8000 + 10 * i) for i, k in enumerate(kinds)}
     rows = []
     for a in kinds:
-        t_a = float(np.median([ctx.victim_run(A[a]).time_ns for _ in range(5)]))
         for b in kinds:
-            tb_alone = float(np.median([ctx.victim_run(B[b]).time_ns for _ in range(3)]))
-            count = int(min(4000, max(20, 6.0 * t_a / tb_alone)))
-            # The co-runner goes on a fresh stream, bracketed by two device
-            # stamps; a colocated run counts only if B's stamps cover A's
-            # whole window (A started after B's first launches, ended before
-            # B's last one).  Two kernels on two queues can also slow
-            # each other through the queues alone, which only adds: each
-            # pair is measured on up to three streams that gave covered runs
-            # and the lowest ratio is kept.
-            trials, attempts = [], 0
-            while len(trials) < 3 and attempts < 8:
-                attempts += 1
-                side = torch.cuda.Stream(device=dev)
-                alone, col = [], []
-                for r in range(args.reps):
-                    if r % 2 == 0:
-                        alone.append(ctx.victim_run(A[a]).time_ns)
-                    side.synchronize()
-                    # a short first batch, then the timed victim starts while
-                    # the main batch runs
-                    ctx.victim_enqueue(B[b], side, 2)
-                    ctx.stamp(stamps[0:1], side)
-                    started.record(side)
-                    ctx.victim_enqueue(B[b], side, count)
-                    ctx.stamp(stamps[1:2], side)
-                    while not started.query():
-                        pass
-                    out_a = ctx.victim_run(A[a])
-                    side.synchronize()
-                    s0, s1 = (int(v) for v in stamps.cpu().tolist())
-                    if s0 <= out_a.t_begin and s1 >= out_a.t_end:
-                        col.append(out_a.time_ns)
-                    if r % 2 == 1:
-                        alone.append(ctx.victim_run(A[a]).time_ns)
-                if len(col) * 2 > args.reps:
-                    trials.append(float(np.median(col) / np.median(alone)))
-            if not trials:
-                raise RuntimeError(f"estimator pair {a}/{b}: the co-runner never covered the victim")
-            meas = min(trials)
+            meas, trials, attempts = measure_pair(ctx, A[a], B[b], args.reps)
             row = {"victim": a, "corunner": b, "measured": round(meas, 3),
                    "measured_trials": [round(t, 3) for t in trials], "stream_attempts": attempts}
             for ax, prof in axes.items():
@@ -1479,12 +1503,17 @@ def run_estimator(args):
                     pred = predicted_pair_slowdown(prof, a, b, rp, mp)
                     row[f"predicted_{name}"] = round(pred, 3)
                     row[f"rel_err_{name}"] = round(abs(pred - meas) / meas, 3)
+            # the library's estimator (ci_predict_slowdown, what admission
+            # uses) on the duty-axis profiles with read/write-aware pricing
+            pred = coloc.predict_slowdown(lib_profiles, a, [b])
+            row["predicted_library"] = round(pred, 3)
+            row["rel_err_library"] = round(abs(pred - meas) / meas, 3)
             rows.append(row)
             log(json.dumps(row))
     rank = lambda v: np.argsort(np.argsort(v))
     m = np.array([r["measured"] for r in rows])
     summary = {}
-    for ax in [a for x in axes for a in (x, x + "_mix", x + "_fit")]:
+    for ax in [a for x in axes for a in (x, x + "_mix", x + "_fit")] + ["library"]:
         err = np.array([r[f"rel_err_{ax}"] for r in rows])
         p = np.array([r[f"predicted_{ax}"] for r in rows])
         summary[ax] = {"mean_rel_err": round(float(err.mean()), 3), "max_rel_err": round(float(err.max()), 3),
@@ -1497,7 +1526,8 @@ def run_estimator(args):
                                "fraction at full rate ('cu') and duty cycle on every CU ('duty'); "
                                "'_mix': read-mostly co-runners priced on the read-only HBM curve; "
                                "'_fit': also, co-runners whose working set fits the 256 MB Infinity "
-                               "Cache priced on the Infinity-Cache stressor's curve"},
+                               "Cache priced on the Infinity-Cache stressor's curve; 'library': "
+                               "ci_predict_slowdown on the duty-axis profiles (read/write-aware)"},
            "profile_runs": max(1, args.profile_runs),
            "pairs": rows, "axes": summary, "profiles": axes, "read_mix_profiles": read_axes,
            "mall_profiles": mall_axes}
