@@ -208,7 +208,7 @@ def _host_threads() -> int:
     return max(1, n)
 
 
-def cpu_baseline(host=None, prec=None, serve=None):
+def cpu_baseline(host=None, prec=None, serve=None, sens=None):
     """The oracle on the host CPU, beside the GPU legs of the same run.
 
     triad: the oracle's two-rounding triad over the headline's N = 2^30
@@ -220,7 +220,9 @@ def cpu_baseline(host=None, prec=None, serve=None):
       the largest error over its bound);
     serving: the admission rule replayed in the oracle's discrete-event
       model on each served trace with the requests' isolated service times:
-      the latency it predicts next to the one the GPU loop measured."""
+      the latency it predicts next to the one the GPU loop measured;
+    sensitivity: the sensitivity block's GEMV (whole) and GEMM (sampled)
+      outputs against the FP64 oracle, timed."""
     import oracle
     import synth
     out = {"kind": "oracle", "unit": "GB/s"}
@@ -253,6 +255,8 @@ def cpu_baseline(host=None, prec=None, serve=None):
                           f"({tall:.2f} s each)"})
     del a
     legs = {}
+    if sens is not None:
+        legs["sensitivity"] = _cpu_sensitivity_leg(sens)
     if prec is not None:
         legs["precision"] = _cpu_precision_leg(prec)
     if serve is not None:
@@ -260,6 +264,35 @@ def cpu_baseline(host=None, prec=None, serve=None):
     if legs:
         out["legs"] = legs
     return out
+
+
+def _cpu_sensitivity_leg(sens):
+    """The sensitivity block's victims against the FP64 oracle: the GEMV's
+    whole output and the GEMM's sampled entries, each within its FP32
+    accumulation bound, with the oracle's time."""
+    import oracle
+    g, v = sens["gemm"], sens["gemv"]
+    t0 = time.perf_counter()
+    fa, fb = oracle.bf16_to_f64(g["a_rows"].view(np.uint16)), oracle.bf16_to_f64(g["b_cols"].view(np.uint16))
+    pair = np.arange(len(fa))
+    want = oracle.gemm_entries_f64(fa, fb, pair, pair)
+    t_gemm = time.perf_counter() - t0
+    absg = oracle.gemm_entries_f64(np.abs(fa), np.abs(fb), pair, pair)
+    bound_g = oracle.accumulation_bound(g["k"] + 1, absg, 2.0 ** -23)
+    t0 = time.perf_counter()
+    fw, fx = oracle.bf16_to_f64(v["w"].view(np.uint16)), oracle.bf16_to_f64(v["x"].view(np.uint16))
+    want_v = oracle.gemv_f64(fw, fx)
+    t_gemv = time.perf_counter() - t0
+    bound_v = oracle.accumulation_bound(fw.shape[1] + 1, np.abs(fw) @ np.abs(fx), 2.0 ** -24)
+    err_g, err_v = np.abs(g["got"] - want), np.abs(v["got"] - want_v)
+    return {"sample": f"GEMM BF16 {g['k']}^3 on {len(fa)} fixed-seed entries; GEMV BF16 "
+                      f"{fw.shape[0]} x {fw.shape[1]} whole",
+            "gemm_within_bound": bool(np.all(err_g <= bound_g)),
+            "gemm_err_max_over_bound": float((err_g / bound_g).max()),
+            "gemv_within_bound": bool(np.all(err_v <= bound_v)),
+            "gemv_err_max_over_bound": float((err_v / bound_v).max()),
+            "oracle_seconds": {"gemm_sampled": round(t_gemm, 3), "gemv_full": round(t_gemv, 3)},
+            "oracle_gemm_entries_per_s": round(len(fa) / t_gemm, 1)}
 
 
 def _cpu_precision_leg(prec):
@@ -337,10 +370,16 @@ SENS_RES = ["hbm", "l2", "mall", "lds", "valu_f32", "mfma_bf16", "ptrchase"]
 SENS_X = [0.0, 0.5, 1.0]
 
 
-def sensitivity_block(ctx, dev, reps, ws):
+def sensitivity_block(ctx, dev, reps, ws, keep_host=False):
     """Victim slowdown per resource and intensity (shared CUs) for the BF16
     GEMM 4096^3 and the BF16 GEMV 8192^2 of the sensitivity sweep, each cell
-    with its bootstrap 95 % interval and the stressor's share of its peak."""
+    with its bootstrap 95 % interval and the stressor's share of its peak.
+    With keep_host, also returns the victims' quantised inputs and outputs
+    (the GEMM on 4096 fixed-seed entries, the GEMV whole) for the CPU leg:
+    every cell's colocated output equals its alone output, so these are the
+    outputs of every run."""
+    import torch
+    import synth
     ops = stressor_operands(dev)
     victims = sweep_victims(ctx, dev)
     nan = lambda v: v != v
@@ -362,8 +401,22 @@ def sensitivity_block(ctx, dev, reps, ws):
                                  "cells": tab}
         log(f"sensitivity {vname}: " + ", ".join(f"{r}={tab[r]['slowdown']}" for r in tab))
     out["queue_pair_check"] = ctx.queue_stats()
+    host = None
+    if keep_host:
+        qa, qb, c = victims["gemm_bf16_4096"]._keep
+        m = c.shape[0]
+        idx = synth.words(4243, 4096)
+        rows = (idx % np.uint64(m)).astype(np.int64)
+        cols = ((idx >> np.uint64(32)) % np.uint64(m)).astype(np.int64)
+        rt, ct = torch.from_numpy(rows).to(dev), torch.from_numpy(cols).to(dev)
+        w3, qx, y = victims["gemv_bf16_8192"]._keep
+        n = y.numel()
+        host = {"gemm": {"k": m, "a_rows": qa.view(m, m)[rt].cpu().numpy(), "b_cols": qb.view(m, m)[ct].cpu().numpy(),
+                         "got": c[rt, ct].double().cpu().numpy()},
+                "gemv": {"w": w3[:n * n].view(n, n).cpu().numpy(), "x": qx.cpu().numpy(),
+                         "got": y.double().cpu().numpy()}}
     del ops, victims
-    return out
+    return out, host
 
 
 def precision_block(ctx, dev, keep_host):
@@ -539,12 +592,12 @@ def run_suite(args):
     host_arrays = None
     if not args.no_cpu_baseline:      # the headline arrays, for the oracle's triad on the host
         host_arrays = (suite.hb.cpu().numpy(), suite.hc.cpu().numpy())
-    prec_host = serve_host = None
+    prec_host = serve_host = sens_host = None
     if not args.quick:
         ws = suite.ws
         del suite
         torch.cuda.empty_cache()
-        line["sensitivity"] = sensitivity_block(ctx, dev, args.suite_reps, ws)
+        line["sensitivity"], sens_host = sensitivity_block(ctx, dev, args.suite_reps, ws, not args.no_cpu_baseline)
         log(f"sensitivity block done at {time.perf_counter() - t_start:.0f} s")
         line["precision"], prec_host = precision_block(ctx, dev, not args.no_cpu_baseline)
         log(f"precision block done at {time.perf_counter() - t_start:.0f} s")
@@ -552,7 +605,7 @@ def run_suite(args):
         log(f"serving block done at {time.perf_counter() - t_start:.0f} s")
     ctx.close()
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(host_arrays, prec_host, serve_host)
+        line["cpu_baseline"] = cpu_baseline(host_arrays, prec_host, serve_host, sens_host)
         log(f"cpu baseline done at {time.perf_counter() - t_start:.0f} s")
     print(json.dumps(line), flush=True)
     if args.out:
@@ -1812,11 +1865,12 @@ def run_suite_counter_summary(args):
 
 
 # LDS stressor forms of `--config lds-counters`, in launch order:
-# (access, vector width in words, stride in vectors, passes)
-LDS_COUNTER_FORMS = [("copy", 4, 1, 10), ("load", 4, 1, 20), ("load", 2, 1, 10), ("load", 1, 1, 5),
-                     ("copy", 1, 1, 4), ("copy", 1, 2, 4), ("copy", 1, 4, 2), ("copy", 1, 8, 2),
-                     ("copy", 1, 16, 1), ("copy", 1, 32, 1), ("copy", 1, 64, 1), ("load", 1, 2, 4),
-                     ("load", 1, 32, 1)]
+# (access, vector width in words, stride in vectors, passes, work-groups of 16 waves per CU)
+LDS_COUNTER_FORMS = [("copy", 4, 1, 10, 1), ("load", 4, 1, 20, 1), ("load", 4, 1, 20, 2), ("copy", 4, 1, 10, 2),
+                     ("load", 2, 1, 10, 1), ("load", 1, 1, 5, 1),
+                     ("copy", 1, 1, 4, 1), ("copy", 1, 2, 4, 1), ("copy", 1, 4, 2, 1), ("copy", 1, 8, 2, 1),
+                     ("copy", 1, 16, 1, 1), ("copy", 1, 32, 1, 1), ("copy", 1, 64, 1, 1), ("load", 1, 2, 4, 1),
+                     ("load", 1, 32, 1, 1)]
 
 
 def run_lds_counters(args):
@@ -1829,12 +1883,13 @@ def run_lds_counters(args):
     ctx = coloc.Context(0)
     w = torch.from_numpy(synth.u32(synth.seed_for(1, synth.BUF_LDS), 8192).view(np.int32)).to(dev)
     rows = []
-    for access, vec, stride, passes in LDS_COUNTER_FORMS:
-        rep = ctx.stressor("lds", 1.0, src0=w, vec=vec, knob=stride, passes=passes,
+    for access, vec, stride, passes, wgs in LDS_COUNTER_FORMS:
+        rep = ctx.stressor("lds", 1.0, src0=w, vec=vec, knob=stride, passes=passes, wg_per_cu=wgs,
                            access=coloc.LDS_ACCESS[access]).stop()
-        rows.append({"access": access, "vec": vec, "stride": stride, "tb_s": round(rep.achieved / 1e12, 2),
-                     "pct_of_peak": round(rep.pct_of_peak, 1)})
-        log(f"lds {access} vec {vec} stride {stride}: {rep.achieved / 1e12:.2f} TB/s ({rep.pct_of_peak:.1f} %)")
+        rows.append({"access": access, "vec": vec, "stride": stride, "waves_per_cu": 16 * wgs,
+                     "tb_s": round(rep.achieved / 1e12, 2), "pct_of_peak": round(rep.pct_of_peak, 1)})
+        log(f"lds {access} vec {vec} stride {stride} {16 * wgs} waves/CU: {rep.achieved / 1e12:.2f} TB/s "
+            f"({rep.pct_of_peak:.1f} %)")
     ctx.close()
     print(json.dumps({"counters_run": "lds stressor forms", "forms": rows}), flush=True)
 
@@ -1853,17 +1908,17 @@ def run_lds_counter_summary(args):
     L = ["# LDS stressor: bank conflicts, LDS activity and bytes per clock (hardware counters)", "",
          "Commands (repository root, one MI355X; one counter set per run), then the summary:", "", "```"]
     L += args.cmd + [" ".join(["python3 bench.py --config lds-counter-summary --dbs"] + list(args.dbs)), "```", "",
-                     "`bench.py --config lds-counters` runs each form below once on all 256 CUs (one work-group "
-                     "of 16 waves per CU, 64 KiB of LDS, fixed work).  A stride of s vectors sends lane l to "
-                     "vector (l s + k) mod (8192 / width) on step k.", "",
+                     "`bench.py --config lds-counters` runs each form below once on all 256 CUs (one or two "
+                     "work-groups of 16 waves per CU, 64 KiB of LDS each, fixed work).  A stride of s vectors "
+                     "sends lane l to vector (l s + k) mod (8192 / width) on step k.", "",
                      "Bytes per clock per CU = (SQ_INSTS_LDS_LOAD_BANDWIDTH + SQ_INSTS_LDS_STORE_BANDWIDTH) x 64 "
                      "/ (GRBM_GUI_ACTIVE / 8) / 256; LDS active = SQ_LDS_IDX_ACTIVE / (GRBM_GUI_ACTIVE / 8) / 256; "
                      "bank-conflict share = SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE; instruction issue = "
                      "clocks per LDS instruction per CU.", "",
-                     "| form | width (words) | stride | B/clk/CU loaded | B/clk/CU stored | LDS active | "
+                     "| form | width (words) | stride | waves/CU | B/clk/CU loaded | B/clk/CU stored | LDS active | "
                      "bank-conflict share | address-conflict share | clocks per LDS instruction |",
-                     "|---|---|---|---|---|---|---|---|---|"]
-    for (access, vec, stride, _), c in zip(LDS_COUNTER_FORMS, per):
+                     "|---|---|---|---|---|---|---|---|---|---|"]
+    for (access, vec, stride, _, wgs), c in zip(LDS_COUNTER_FORMS, per):
         cyc = c["GRBM_GUI_ACTIVE"] / GRBM_INSTANCES
         ld = c.get("SQ_INSTS_LDS_LOAD_BANDWIDTH", 0.0) * 64 / cyc / cus
         stb = c.get("SQ_INSTS_LDS_STORE_BANDWIDTH", 0.0) * 64 / cyc / cus
@@ -1871,7 +1926,7 @@ def run_lds_counter_summary(args):
         bank = c.get("SQ_LDS_BANK_CONFLICT", float("nan")) / c.get("SQ_LDS_IDX_ACTIVE", float("nan"))
         addr = c.get("SQ_LDS_ADDR_CONFLICT", float("nan")) / c.get("SQ_LDS_IDX_ACTIVE", float("nan"))
         ipc = cyc * cus / c["SQ_INSTS_LDS"] if c.get("SQ_INSTS_LDS") else float("nan")
-        L.append(f"| {access} | {vec} | {stride} | {ld:.1f} | {stb:.1f} | {100 * act:.1f} % | {100 * bank:.1f} % | "
+        L.append(f"| {access} | {vec} | {stride} | {16 * wgs} | {ld:.1f} | {stb:.1f} | {100 * act:.1f} % | {100 * bank:.1f} % | "
                  f"{100 * addr:.1f} % | {ipc:.2f} |")
     out = os.path.join(ROOT, "profiles", "lds_stride_counters.md")
     with open(out, "w") as f:

@@ -18,6 +18,8 @@ def test_suite_entries_map_to_resources():
     assert [bench.suite_resource(n) for n in ("hbm_read", "hbm_copy", "hbm_write")] == ["hbm"] * 3
     assert bench.suite_resource("l2_32w") == "l2" and bench.suite_resource("lds_32w") == "lds"
     assert bench.suite_resource("mfma_bf16") == "mfma_bf16"
+    assert bench.suite_resource("lds_load") == "lds" and bench.suite_resource("mall_32w") == "mall"
+    assert len({n for n, _ in bench.SUITE_LABELS}) == len(bench.SUITE_LABELS)
 
 
 def _prof(hbm, press, wf=0.0):
@@ -67,3 +69,27 @@ def test_more_than_one_gpu_exits_with_a_message():
     assert r.returncode == 2
     line = json.loads(r.stdout.strip().splitlines()[-1])
     assert line["n_gpus"] == 2 and "one GPU" in line["error"]
+
+
+def test_cpu_sensitivity_leg_flags_outputs_outside_the_bound():
+    """The host leg checks the sensitivity block's victims against the FP64
+    oracle: the exact products pass, an entry moved by ten times its bound
+    fails."""
+    import oracle
+    rng = np.random.default_rng(5)
+    k, n = 64, 32
+    a = oracle.f32_to_bf16(rng.standard_normal((16, k)).astype(np.float32)).view(np.int16)
+    b = oracle.f32_to_bf16(rng.standard_normal((16, k)).astype(np.float32)).view(np.int16)
+    fa, fb = oracle.bf16_to_f64(a.view(np.uint16)), oracle.bf16_to_f64(b.view(np.uint16))
+    exact = np.einsum("ik,ik->i", fa, fb)
+    w = oracle.f32_to_bf16(rng.standard_normal((n, k)).astype(np.float32)).view(np.int16)
+    x = oracle.f32_to_bf16(rng.standard_normal(k).astype(np.float32)).view(np.int16)
+    y = oracle.bf16_to_f64(w.view(np.uint16)) @ oracle.bf16_to_f64(x.view(np.uint16))
+    sens = {"gemm": {"k": k, "a_rows": a, "b_cols": b, "got": exact.copy()},
+            "gemv": {"w": w, "x": x, "got": y.copy()}}
+    leg = bench._cpu_sensitivity_leg(sens)
+    assert leg["gemm_within_bound"] and leg["gemv_within_bound"]
+    bound = oracle.accumulation_bound(k + 1, np.abs(fa * fb).sum(axis=1), 2.0 ** -23)
+    sens["gemm"]["got"][3] += 10 * bound[3]
+    leg = bench._cpu_sensitivity_leg(sens)
+    assert not leg["gemm_within_bound"] and leg["gemv_within_bound"]
