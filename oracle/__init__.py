@@ -22,8 +22,10 @@ Parity status per function (pins are in tests/test_oracle_pins.py):
   gemm_f64, gemv_f64, mfma_tile_expected ........ pinned
   slowdown, pct_of_peak ......................... pinned (paper Table 1 values)
   bootstrap_slowdown_ci ......................... pinned (closed-form resampling law)
+  accumulation_bound ............................ pinned (brute force, toy format)
+  e4m3_nominal_exponent, mfma_fp8_error_bound ... pinned (hand case, exact model)
   predicted_slowdown, predicted_slowdown_rw, admit  pinned
-  simulate_admission (discrete-event replay) .... pinned
+  simulate_admission, FirstFitArena ............. pinned
   decode (submodule: synthetic decode step) ..... pinned
 """
 from __future__ import annotations
@@ -538,7 +540,15 @@ def admit(policy: str, running: list, cand: dict, free_bytes: int, bound: float,
     'press' (per-resource pressure it exerts), 'bytes' and 'occ' (fraction of wave
     slots).  Policies: 'naive' (memory and slot only), 'usher' (summed
     occupancy below 1, Section 3 Pitfall 1), 'sensitivity' (predicted
-    slowdown of every job within `bound`)."""
+    slowdown of every job within `bound`).
+
+    Section 5.1 asks the scheduler to predict each job's slowdown per
+    resource but gives no formula; the reading taken here: each curve is
+    piecewise linear through its five measured points, co-runner pressures
+    on a resource add and clip at 1, the per-resource factors max(1, curve)
+    multiply (predicted_slowdown_rw, with read/write-aware HBM pricing), and
+    a request is admitted first in first out, without bypass, only if every
+    job, itself included, stays within the bound."""
     if policy not in ("naive", "usher", "sensitivity"):
         raise ValueError(policy)
     if cand["bytes"] > free_bytes or len(running) >= slots:

@@ -154,6 +154,25 @@ def test_stream_stressor_duty_cycle(ctx, dev, res, mix, n):
     print(f"{res} {mix} duty 100/50/25: " + ", ".join(f"{times[d] / 1e3:.0f} us" for d in (100, 50, 25)))
 
 
+@pytest.mark.parametrize("res", ["hbm", "mall"])
+def test_stream_stressor_persistent_fewer_chunks_than_slots(ctx, dev, res):
+    """A persistent stream over 3 wave-chunks (ragged last one) leaves five
+    of the eight XCD slots without a range: their work-groups hold until
+    stopped, every work-group reports and saw the stop flag, and the output
+    is the oracle's."""
+    import time
+    from paper_2501_16909_amd import coloc
+    n = 2 * 256 + 100                       # wave-chunks of 256 elements (chunk = 1)
+    b, c, tb, tc, ta, sentinel = _mall_buffers(dev, n)
+    with ctx.stressor(res, 1.0, src0=tb, src1=tc, dst=ta, n=n, chunk=1, knob=coloc.HBM_MIX["triad"]) as st:
+        time.sleep(0.02)
+    rep = st.report
+    rec = st.records()
+    assert not rep.timed_out and rep.wg_reported == rep.grid and np.all(rec["flags"] & 2)
+    assert rep.work >= 3 and rep.units == 12.0 * 256 * rep.work
+    assert np.array_equal(ta.cpu().numpy().view(np.uint32), oracle.triad_f32(b, c).view(np.uint32))
+
+
 # -------------------------------------------------------------------- LDS
 @pytest.mark.parametrize("vec,stride,access", [(1, 1, 0), (1, 2, 0), (1, 32, 0), (2, 1, 0), (4, 1, 0), (4, 3, 0),
                                                (4, 1, 1), (1, 32, 1), (2, 5, 1)])
