@@ -73,7 +73,8 @@ SUITE_LABELS = [
     ("mall_write", "Infinity Cache 128 MiB write-only"), ("mall_32w", "Infinity Cache 128 MiB read, 2 x 1024 per CU"),
     ("vl1d", "vL1D 16 KiB"),
     ("lds", "LDS copy vec4 stride 1 (1 WG of 16 waves per CU)"), ("lds_32w", "LDS copy, 2 WGs per CU"),
-    ("lds_load", "LDS load-only vec4 stride 1"), ("valu_f32", "VALU FMA ILP 8"),
+    ("lds_load", "LDS load-only vec4 stride 1"), ("lds_load_32w", "LDS load-only, 2 WGs per CU"),
+    ("valu_f32", "VALU FMA ILP 8"),
     ("valu_f64", "VALU FP64 multiply ILP 4"), ("mfma_f32", "MFMA FP32"), ("mfma_bf16", "MFMA BF16"),
     ("mfma_fp8", "MFMA FP8"), ("ptrchase", "pointer chase 2^24"), ("dispatch", "dispatch 10^6 WGs")]
 
@@ -139,6 +140,7 @@ class Suite:
             ("lds", dict(src0=self.win, passes=10), "TB/s", 1e12),
             ("lds_32w", dict(src0=self.win, passes=10, wg_per_cu=2), "TB/s", 1e12),
             ("lds_load", dict(src0=self.win, passes=20, access=1), "TB/s", 1e12),
+            ("lds_load_32w", dict(src0=self.win, passes=20, access=1, wg_per_cu=2), "TB/s", 1e12),
             ("valu_f32", dict(dst=self.valu_out, iters=4096, passes=4, fa=1 - 2 ** -12, fb=2 ** -12), "TFLOP/s", 1e12),
             ("valu_f64", dict(dst=self.valu_out, iters=4096, passes=4, fa=1 - 2 ** -12), "TFLOP/s", 1e12),
             ("mfma_f32", dict(src0=self.mf["f32"][0], src1=self.mf["f32"][1], dst=self.mf_out, iters=2048, passes=2), "TFLOP/s", 1e12),
@@ -576,7 +578,7 @@ def run_suite(args):
         "config": {"workload": "stressor suite standalone: HBM triad FP32 N=2^30 (and its "
                                "read-only, copy and write-only mixes); L2 2 MiB; "
                                "Infinity Cache 128 MiB (read, also at 32 waves/CU, and write-only); vL1D 16 KiB; LDS 64 KiB/WG copy "
-                               "(L2 and LDS also at 32 waves/CU) and load-only; FP32 FMA and FP64 multiply chains 4096; "
+                               "(L2 and LDS also at 32 waves/CU) and load-only (also at 32 waves/CU); FP32 FMA and FP64 multiply chains 4096; "
                                "MFMA FP32/BF16/FP8; uint32 chase over 2^24 cycle; 10^6 empty "
                                "64-thread WGs; plus colocated triad pair N=2^22",
                    "parallelism": "single GPU"},
