@@ -7,7 +7,7 @@
 // M x N FP32 row-major.  Three kernels, one summation order (each output is
 // the MFMA chain over K in increasing order, so they agree bit for bit):
 //   gemm256d_kernel  256 x 256 tiles, direct global -> LDS loads into a
-//                    4-stage ring; shapes with >= 256 tiles and K * element
+//                    5-stage ring; shapes with >= 256 tiles and K * element
 //                    size a multiple of 64 bytes;
 //   gemm256_kernel   256 x 256 tiles staged through registers, other
 //                    shapes with >= 256 tiles;
@@ -84,12 +84,12 @@ struct Gemm<CI_DT_FP8E4M3> {
 // a band), so the tiles an XCD computes at one time form a 4 x 8 block that
 // shares 4 A panels and 8 B panels in that XCD's L2 (a 2 x 16 row-major
 // block would need 18).
+template <uint32_t kBand = 4>
 __device__ __forceinline__ void tile_of(uint32_t bid, uint32_t nbm, uint32_t nbn, uint32_t& tm,
                                         uint32_t& tn) {
   const uint32_t nb = nbm * nbn;
   uint32_t t = bid;
   if ((nb & 7u) == 0) t = (bid & 7u) * (nb >> 3) + (bid >> 3);
-  constexpr uint32_t kBand = 4;
   const uint32_t band = kBand * nbn, group = t / band;
   const uint32_t first = group * kBand, rows = min(nbm - first, kBand), r = t - group * band;
   tm = first + r % rows;
@@ -289,7 +289,10 @@ __global__ void __launch_bounds__(64 * WAVES, 1) gemm256_kernel(const uint8_t* _
 // so after the barrier the whole stage is in LDS; a fence there would also
 // wait for the later stages' loads.  Needs K * element size to be a
 // multiple of 64 bytes; the register-staged kernel above takes the rest.
-constexpr int kRingStages = 4;
+// Five slots of 32 KiB fill the CU's 160 KiB of LDS and let loads run three
+// stages ahead; four slots (two ahead) measured 3-10 % slower at 4096-12288
+// cubed (BF16), with bit-identical results.
+constexpr int kRingStages = 5;
 constexpr int kDStage = 64;                         // K bytes per stage per row
 constexpr int kDOperand = kBig * kDStage;           // one operand, one stage (16 KiB)
 constexpr int kDSlot = 2 * kDOperand;               // A and B of one stage
@@ -326,7 +329,8 @@ template <> struct Frag<CI_DT_FP8E4M3> {
   }
 };
 
-template <int DT>
+// BAND: tile rows per band of the tile order (tile_of).
+template <int DT, uint32_t BAND>
 __global__ void __launch_bounds__(512, 1) gemm256d_kernel(const uint8_t* __restrict__ A,
                                                           const uint8_t* __restrict__ B,
                                                           float* __restrict__ C, uint32_t M,
@@ -336,7 +340,7 @@ __global__ void __launch_bounds__(512, 1) gemm256d_kernel(const uint8_t* __restr
   extern __shared__ __attribute__((aligned(1024))) uint8_t smem[];
   const uint32_t nbm = (M + kBig - 1) / kBig, nbn = (N + kBig - 1) / kBig;
   uint32_t tm, tn;
-  tile_of(blockIdx.x, nbm, nbn, tm, tn);
+  tile_of<BAND>(blockIdx.x, nbm, nbn, tm, tn);
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wid = tid >> 6;
   const uint32_t wm = wid / WN, wn = wid % WN;
   const uint64_t rowBytes = (uint64_t)K * G::kElem;
@@ -380,7 +384,8 @@ __global__ void __launch_bounds__(512, 1) gemm256d_kernel(const uint8_t* __restr
   // wait for the later stages' loads.
   auto wait_stage = [&](uint32_t t, uint32_t ahead) {
     const uint32_t after = min(nstages - 1, t + ahead) - t;
-    if (after >= 2) __builtin_amdgcn_s_waitcnt(0x0F78);        // vmcnt(8)
+    if (after >= 3) __builtin_amdgcn_s_waitcnt(0x0F7C);        // vmcnt(12)
+    else if (after == 2) __builtin_amdgcn_s_waitcnt(0x0F78);   // vmcnt(8)
     else if (after == 1) __builtin_amdgcn_s_waitcnt(0x0F74);   // vmcnt(4)
     else __builtin_amdgcn_s_waitcnt(0x0F70);                   // vmcnt(0)
     __builtin_amdgcn_s_barrier();
@@ -531,18 +536,22 @@ hipError_t launch_gemm(int dtype, const void* a, const void* b, float* c, uint64
     const uint32_t shm = kRingStages * kDSlot;
     const uint8_t* A = (const uint8_t*)a;
     const uint8_t* B = (const uint8_t*)b;
+    // Tile order: bands of 8 tile rows when every tile runs at once (one
+    // tile per CU), of 4 otherwise -- the faster of the two in each case
+    // (4096^3: 1068 against 882-954 TF; 6144-12288^3: 3-10 % the other way).
+    const bool one_wave = nbig <= 256;
+#define CI_GEMM_RING(DT)                                                                                  \
+  return one_wave ? xlaunch(gemm256d_kernel<DT, 8>, dim3((uint32_t)nbig), dim3(512), shm, s, e0, e1, A, B, c, \
+                            (uint32_t)m, (uint32_t)n, (uint32_t)k, scale)                                 \
+                  : xlaunch(gemm256d_kernel<DT, 4>, dim3((uint32_t)nbig), dim3(512), shm, s, e0, e1, A, B, c, \
+                            (uint32_t)m, (uint32_t)n, (uint32_t)k, scale)
     switch (dtype) {
-      case CI_DT_F32:
-        return xlaunch(gemm256d_kernel<CI_DT_F32>, dim3((uint32_t)nbig), dim3(512), shm, s, e0, e1, A, B, c,
-                       (uint32_t)m, (uint32_t)n, (uint32_t)k, scale);
-      case CI_DT_BF16:
-        return xlaunch(gemm256d_kernel<CI_DT_BF16>, dim3((uint32_t)nbig), dim3(512), shm, s, e0, e1, A, B, c,
-                       (uint32_t)m, (uint32_t)n, (uint32_t)k, scale);
-      case CI_DT_FP8E4M3:
-        return xlaunch(gemm256d_kernel<CI_DT_FP8E4M3>, dim3((uint32_t)nbig), dim3(512), shm, s, e0, e1, A, B,
-                       c, (uint32_t)m, (uint32_t)n, (uint32_t)k, scale);
+      case CI_DT_F32: CI_GEMM_RING(CI_DT_F32);
+      case CI_DT_BF16: CI_GEMM_RING(CI_DT_BF16);
+      case CI_DT_FP8E4M3: CI_GEMM_RING(CI_DT_FP8E4M3);
       default: return hipErrorInvalidValue;
     }
+#undef CI_GEMM_RING
   }
   if (nbig >= 256) {
     const uint32_t shm = 4 * kBigTileLds;
