@@ -168,14 +168,14 @@ extern "C" ci_status_t ci_admit(const ci_policy_t* p, const int* running_kinds, 
                                 int* admit) {
   if (!p || !admit || nrun < 0 || (nrun && !running_kinds))
     return set_err(CI_ERR_INVALID_ARG, "ci_admit: bad argument");
+  if (p->kind != CI_POLICY_NAIVE && p->kind != CI_POLICY_USHER && p->kind != CI_POLICY_SENSITIVITY)
+    return set_err(CI_ERR_INVALID_ARG, "ci_admit: policy %d", p->kind);
   *admit = 0;
   if (cand_bytes > free_bytes || nrun >= p->slots) return CI_OK;
   // Memory and a slot are all a request needs on an idle device: the
   // occupancy and slowdown rules bound colocation (nothing would ever free
   // up for a lone request they refuse, and the loop would wait forever).
   if (p->kind == CI_POLICY_NAIVE || nrun == 0) {
-    if (p->kind != CI_POLICY_NAIVE && p->kind != CI_POLICY_USHER && p->kind != CI_POLICY_SENSITIVITY)
-      return set_err(CI_ERR_INVALID_ARG, "ci_admit: policy %d", p->kind);
     *admit = 1;
     return CI_OK;
   }

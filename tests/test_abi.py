@@ -2,6 +2,7 @@
 point include/coloc.h declares, its structs have the layout the binding
 assumes, and the pure admission rule agrees with the oracle's."""
 import ctypes
+import ctypes as C
 import math
 import os
 import re
@@ -163,6 +164,19 @@ def test_admission_matches_oracle(policy, bound, read_curves):
     # an idle device admits whatever fits, under every policy and bound
     greedy = {"triad": dict(profs["triad"], occ=1.0, sens={"hbm": [9.0] * 5})}
     assert coloc.admit(policy, greedy, [], "triad", 10, 100, bound=1.0001)
+
+
+def test_admission_rejects_an_unknown_policy_first():
+    """An unknown policy is an argument error whatever the request, also one
+    that would not fit."""
+    profs = _profiles(False)
+    arr = coloc.make_profiles(profs)
+    for cand_bytes in (10, 10 ** 6):
+        pol = coloc.Policy(7, 1.5, 1 << 40, 4, C.cast(arr, C.POINTER(coloc.Profile)), len(profs))
+        out = C.c_int(5)
+        st = coloc.load_library().ci_admit(C.byref(pol), None, 0, coloc.VICTIMS["gemv"], cand_bytes, 100,
+                                           C.byref(out))
+        assert st == 1, cand_bytes
 
 
 LLAMA8B = dict(hidden=4096, n_q=32, n_kv=8, head_dim=128, ffn=14336, vocab=128256, layers=32, batch=1,
