@@ -7,7 +7,7 @@
 // M x N FP32 row-major.  Three kernels, one summation order (each output is
 // the MFMA chain over K in increasing order, so they agree bit for bit):
 //   gemm256d_kernel  256 x 256 tiles, direct global -> LDS loads into a
-//                    5-stage ring; shapes with >= 256 tiles and K * element
+//                    4-stage ring; shapes with >= 256 tiles and K * element
 //                    size a multiple of 64 bytes;
 //   gemm256_kernel   256 x 256 tiles staged through registers, other
 //                    shapes with >= 256 tiles;
@@ -289,13 +289,15 @@ __global__ void __launch_bounds__(64 * WAVES, 1) gemm256_kernel(const uint8_t* _
 // so after the barrier the whole stage is in LDS; a fence there would also
 // wait for the later stages' loads.  Needs K * element size to be a
 // multiple of 64 bytes; the register-staged kernel above takes the rest.
-// Five slots of 32 KiB fill the CU's 160 KiB of LDS and let loads run three
-// stages ahead; four slots (two ahead) measured 3-10 % slower at 4096-12288
-// cubed (BF16), with bit-identical results.
-constexpr int kRingStages = 5;
+// Four slots of 32 KiB: 128 KiB of the CU's 160 KiB, leaving 32 KiB for a
+// co-resident stressor work-group.  Five slots (loads three stages ahead)
+// ran at the same rate within run-to-run spread, but fill the whole LDS, so
+// no work-group holding any LDS could share a CU with the victim.
+constexpr int kRingStages = 4;
 constexpr int kDStage = 64;                         // K bytes per stage per row
 constexpr int kDOperand = kBig * kDStage;           // one operand, one stage (16 KiB)
 constexpr int kDSlot = 2 * kDOperand;               // A and B of one stage
+static_assert(kRingStages * kDSlot <= 128 * 1024, "the ring must leave LDS for a co-resident work-group");
 
 __device__ __forceinline__ uint32_t dswz(uint32_t row, uint32_t byte) {
   return row * kDStage + ((((byte >> 4) ^ (row >> 2)) & 3u) << 4) + (byte & 15u);
@@ -538,7 +540,8 @@ hipError_t launch_gemm(int dtype, const void* a, const void* b, float* c, uint64
     const uint8_t* B = (const uint8_t*)b;
     // Tile order: bands of 8 tile rows when every tile runs at once (one
     // tile per CU), of 4 otherwise -- the faster of the two in each case
-    // (4096^3: 1068 against 882-954 TF; 6144-12288^3: 3-10 % the other way).
+    // (BF16 4096^3: 1042-1048 against 847-989 TF; 8192^3: 1108-1130
+    // against 1074-1079 TF).
     const bool one_wave = nbig <= 256;
 #define CI_GEMM_RING(DT)                                                                                  \
   return one_wave ? xlaunch(gemm256d_kernel<DT, 8>, dim3((uint32_t)nbig), dim3(512), shm, s, e0, e1, A, B, c, \
