@@ -12,8 +12,10 @@ the pair's slowdown ride along in the same line.
 
 Other workloads, each its own JSON line(s), with --config: sweep,
 precision, serve, pollution, bandwidth, ilp, pairs, ldsstride, estimator,
-decode, queues, hbm_mix; counters, suite-counters and gemm-counters are
-short runs for hardware-counter passes.  One GPU only: --gpus N with N > 1 exits with a
+decode, queues, hbm_mix; counters, suite-counters, lds-counters and
+gemm-counters are short runs for hardware-counter passes, and the
+*-summary configurations turn their rocprofv3 databases into the files
+under profiles/ (no GPU).  One GPU only: --gpus N with N > 1 exits with a
 message.
 """
 from __future__ import annotations
@@ -1810,6 +1812,42 @@ def run_trace_summary(args):
     print(json.dumps({"written": args.md, "kernels": len(rows)}))
 
 
+def run_gemm_counter_summary(args):
+    """Counters of `--config gemm-counters` (three BF16 4096^3 launches of
+    the ring kernel) from one rocprofv3 --pmc database (--dbs): writes
+    profiles/gemm_bf16_4096_counters.md."""
+    ds = [d for d in _pmc_dispatches(args.dbs[0]) if d["name"].startswith("gemm256d_kernel<")]
+    if not ds:
+        raise SystemExit(f"{args.dbs[0]}: no gemm256d_kernel dispatch")
+    cmd = " ".join(args.cmd) if args.cmd else "(not given)"
+    L = ["# Hardware counters of the GEMM victim (BF16, M = N = K = 4096, ring kernel)", "",
+         "Command (repository root, one MI355X; one counter group), then the summary:", "", "```", cmd,
+         f"python3 bench.py --config gemm-counter-summary --dbs {args.dbs[0]}", "```", "",
+         f"`bench.py --config gemm-counters` launches the BF16 4096³ GEMM three times (`{ds[0]['name']}`, "
+         f"{ds[0]['grid'] // ds[0]['wg']} work-groups of {ds[0]['wg']} threads). Derived: active time = "
+         "GRBM_GUI_ACTIVE / 8 XCDs / 2.4 GHz; MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES over active cycles x 1024 "
+         "SIMDs; LDS B/clk/CU = SQ_INSTS_LDS x 1 KiB (each a 64-lane `ds_read_b128`) over active cycles x 256 "
+         "CUs (ring fills by `global_load_lds` come on top, about 15 B/clk/CU); waits as fractions of "
+         "SQ_WAVE_CYCLES.", "",
+         "| launch | duration us (profiled) | active us | MFMA busy | LDS read B/clk/CU | waiting | "
+         "waiting on LDS | LDS bank conflicts | LDS instructions | waves |",
+         "|---|---|---|---|---|---|---|---|---|---|"]
+    for i, d in enumerate(ds):
+        c = d["ctr"]
+        active = c["GRBM_GUI_ACTIVE"] / GRBM_INSTANCES
+        L.append(f"| {i + 1} | {(d['end'] - d['start']) / 1e3:.1f} | {active / 2.4e3:.1f} | "
+                 f"{c['SQ_VALU_MFMA_BUSY_CYCLES'] / (active * 1024):.3f} | "
+                 f"{c['SQ_INSTS_LDS'] * 1024 / (active * 256):.1f} | "
+                 f"{c['SQ_WAIT_ANY'] / c['SQ_WAVE_CYCLES']:.3f} | {c['SQ_WAIT_INST_LDS'] / c['SQ_WAVE_CYCLES']:.3f} | "
+                 f"{c['SQ_LDS_BANK_CONFLICT']:.0f} | {c['SQ_INSTS_LDS']:.0f} | {c['SQ_WAVES']:.0f} |")
+    L += ["", "Profiling slows the launches; the fractions are what matter: the matrix cores' busy share, the "
+              "LDS fragment-load rate against the 256 B/clk/CU of the load path (`lds_stride_counters.md`), "
+              "and the share of wave cycles spent waiting (on anything, and on LDS)."]
+    with open(args.md or os.path.join(ROOT, "profiles", "gemm_bf16_4096_counters.md"), "w") as f:
+        f.write("\n".join(L) + "\n")
+    print(json.dumps({"written": args.md or "profiles/gemm_bf16_4096_counters.md", "launches": len(ds)}))
+
+
 STRESSOR_KERNELS = ("stream_stressor<", "strided_stressor<", "cache_stressor", "lds_stressor<", "valu_stressor<",
                     "valu64_stressor<", "mfma_stressor<", "chase_stressor<", "empty_wg")
 
@@ -1976,7 +2014,8 @@ def main():
     ap.add_argument("--config", default="suite", choices=["suite", "sweep", "precision", "serve", "counters", "suite-counters",
                              "pollution", "bandwidth", "ilp", "pairs", "ldsstride", "estimator", "decode",
                              "queues", "hbm_mix", "gemm-counters", "counter-summary", "trace-summary",
-                             "lds-counters", "lds-counter-summary", "suite-counter-summary"])
+                             "lds-counters", "lds-counter-summary", "suite-counter-summary",
+                             "gemm-counter-summary"])
     ap.add_argument("--dbs", nargs="+", default=[], help="summaries: rocprofv3 databases to read")
     ap.add_argument("--cmd", nargs="+", default=[], help="summaries: the commands that made the databases")
     ap.add_argument("--md", default=None, help="trace-summary: markdown file to write")
@@ -2054,6 +2093,8 @@ def main():
         run_lds_counter_summary(args)
     elif args.config == "suite-counter-summary":
         run_suite_counter_summary(args)
+    elif args.config == "gemm-counter-summary":
+        run_gemm_counter_summary(args)
 
 
 if __name__ == "__main__":

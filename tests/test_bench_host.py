@@ -93,3 +93,34 @@ def test_cpu_sensitivity_leg_flags_outputs_outside_the_bound():
     sens["gemm"]["got"][3] += 10 * bound[3]
     leg = bench._cpu_sensitivity_leg(sens)
     assert not leg["gemm_within_bound"] and leg["gemv_within_bound"]
+
+
+def test_gemm_counter_summary_derives_rates(tmp_path):
+    """The counter summariser's arithmetic on a hand-made database with the
+    columns of rocprofv3's counters_collection view."""
+    import sqlite3
+    db = tmp_path / "g.db"
+    con = sqlite3.connect(db)
+    con.execute("create table counters_collection (dispatch_id int, kernel_name text, grid_size int, "
+                "workgroup_size int, counter_name text, value real, start int, end int)")
+    active = 240_000.0                       # cycles per XCD: 100 us at 2.4 GHz
+    ctr = {"GRBM_GUI_ACTIVE": active * 8, "SQ_VALU_MFMA_BUSY_CYCLES": 0.5 * active * 1024,
+           "SQ_INSTS_LDS": 48.0 * active * 256 / 1024, "SQ_WAVE_CYCLES": 1000.0, "SQ_WAIT_ANY": 250.0,
+           "SQ_WAIT_INST_LDS": 20.0, "SQ_LDS_BANK_CONFLICT": 0.0, "SQ_WAVES": 2048.0, "SQ_BUSY_CYCLES": 1.0}
+    for name, v in ctr.items():               # each counter split over two rows, as per-instance values are
+        for half in (0.5, 0.5):
+            con.execute("insert into counters_collection values (7, ?, ?, ?, ?, ?, ?, ?)",
+                        ("void ci::(anonymous namespace)::gemm256d_kernel<1, 8u>(unsigned char const*)",
+                         256 * 512, 512, name, v * half, 1_000, 121_000))
+    con.commit()
+    con.close()
+    md = tmp_path / "out.md"
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--config", "gemm-counter-summary",
+                        "--dbs", str(db), "--md", str(md), "--cmd", "rocprofv3 --pmc X -- python3 bench.py"],
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stderr
+    row = [l for l in md.read_text().splitlines() if l.startswith("| 1 |")][0].split("|")[1:-1]
+    cells = [c.strip() for c in row]
+    assert cells[:6] == ["1", "120.0", "100.0", "0.500", "48.0", "0.250"]
+    assert cells[6:] == ["0.020", "0", "2880000", "2048"]
+    assert "`gemm256d_kernel<1, 8u>`, 256 work-groups of 512 threads" in md.read_text()
