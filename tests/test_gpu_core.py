@@ -174,6 +174,40 @@ def test_hbm_stressor_fixed_passes(ctx, dev, x, passes, n):
     assert rep.distinct_cus == ncu
 
 
+def test_hbm_stressor_triad_full_size_benchmark_shape(ctx, dev):
+    """The benchmark's roofline launch itself: the HBM triad over N = 2^30
+    (4 GiB per array) at full intensity with default options (256
+    work-groups of 512 threads, one pass, fixed work).  Outputs on sampled
+    indices against the oracle on inputs regenerated from the counter-form
+    generator; every wave-chunk done once; the FP64 sum of the output
+    against the triad identity of the input sums."""
+    import torch
+    n = 1 << 30
+    sb, sc = synth.seed_for(1, synth.BUF_B), synth.seed_for(1, synth.BUF_C)
+    tb = torch.empty(n, dtype=torch.float32, device=dev)
+    tc = torch.empty_like(tb)
+    ta = torch.empty_like(tb)
+    synth.device_fill_uniform_f32(tb.data_ptr(), n, sb)
+    synth.device_fill_uniform_f32(tc.data_ptr(), n, sc)
+    torch.cuda.synchronize()
+    rep = ctx.stressor("hbm", 1.0, src0=tb, src1=tc, dst=ta, n=n, passes=1).stop()
+    assert rep.grid == 256 and rep.wg_reported == 256 and not rep.timed_out
+    assert rep.work == n // 1024 and rep.units == 12.0 * n
+    idx = np.unique(np.concatenate([np.arange(64), n - 1 - np.arange(64),
+                                    (synth.words(91, 4096) % np.uint64(n)).astype(np.int64)]))
+    want = oracle.triad_f32(synth.uniform_f32_at(sb, idx), synth.uniform_f32_at(sc, idx))
+    got = ta[torch.from_numpy(idx).to(dev)].cpu().numpy()
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+    _, sum_a = ctx.checksum(ta)
+    _, sum_b = ctx.checksum(tb)
+    _, sum_c = ctx.checksum(tc)
+    absum = float((3 * tc.abs().double().sum() + ta.abs().double().sum()).item())
+    assert abs(sum_a - (sum_b + 3 * sum_c)) <= 2.0 ** -24 * absum * 1.01 + 1e-6 * abs(sum_a)
+    print(f"hbm triad 2^30: {rep.achieved / 1e9:.0f} GB/s ({rep.pct_of_peak:.1f} % of peak)")
+    del tb, tc, ta
+    torch.cuda.empty_cache()
+
+
 def test_hbm_stressor_persistent_colocated(ctx, dev):
     n_v = 1 << 22
     b = synth.uniform_f32(synth.seed_for(0, synth.BUF_B), n_v)
