@@ -1632,6 +1632,48 @@ def run_gemm_counters(args):
     print(json.dumps({"counters_run": "gemm bf16 4096^3 x3"}), flush=True)
 
 
+def run_hbm_references(args):
+    """Short run for a kernel trace: the HBM stressor's four traffic mixes
+    over N = 2^30 FP32 (fixed work, one pass per launch) and, over the same
+    arrays as independent references, the framework's own elementwise
+    triad (torch.add(b, c, alpha=3)), tensor copy and fill, six launches
+    each.  `--config reference-summary` turns the trace into
+    profiles/hbm_references_n2e30_kernel_trace.md."""
+    import torch
+    import synth
+    from paper_2501_16909_amd import coloc
+    dev = torch.device("cuda:0")
+    ctx = coloc.Context(0)
+    n = 1 << 30
+    hb = torch.empty(n, dtype=torch.float32, device=dev)
+    hc, ha = torch.empty_like(hb), torch.empty_like(hb)
+    synth.device_fill_uniform_f32(hb.data_ptr(), n, synth.seed_for(1, synth.BUF_B))
+    synth.device_fill_uniform_f32(hc.data_ptr(), n, synth.seed_for(1, synth.BUF_C))
+    torch.cuda.synchronize()
+    ws = torch.empty(WS_BYTES, dtype=torch.uint8, device=dev)
+    mixes = [("triad", dict(src0=hb, src1=hc, dst=ha)), ("read", dict(src0=hb, src1=hc)),
+             ("copy", dict(src0=hb, dst=ha)), ("write", dict(dst=ha))]
+    for mix, ops in mixes:
+        for _ in range(6):
+            rep = ctx.stressor("hbm", 1.0, ws=ws, n=n, passes=1, knob=coloc.HBM_MIX[mix], **ops).stop()
+        log(f"hbm {mix}: {rep.achieved / 1e9:.0f} GB/s")
+    ctx.close()
+    # each pass over the arrays as two launches of 2^29 elements: the
+    # framework splits a launch whose offsets pass 2^31 bytes anyway, and
+    # this way every traced launch covers a known half
+    h = n // 2
+    for name, fn in (("torch.add triad", lambda lo, hi: torch.add(hb[lo:hi], hc[lo:hi], alpha=3.0, out=ha[lo:hi])),
+                     ("copy_", lambda lo, hi: ha[lo:hi].copy_(hb[lo:hi])),
+                     ("fill_", lambda lo, hi: ha[lo:hi].fill_(1.0))):
+        for _ in range(6):
+            fn(0, h)
+            fn(h, n)
+        torch.cuda.synchronize()
+        log(f"{name} done")
+    print(json.dumps({"references_run": "hbm mixes and framework kernels over 2^30 FP32, 6 launches each"}),
+          flush=True)
+
+
 # ---------------------------------------------------------------- profiles
 # Summaries of rocprofv3 databases (rocpd SQLite) into the text files kept
 # under profiles/.  They run on any host: no GPU, no library.
@@ -1810,6 +1852,71 @@ def run_trace_summary(args):
     with open(args.md, "w") as f:
         f.write("\n".join(L) + "\n")
     print(json.dumps({"written": args.md, "kernels": len(rows)}))
+
+
+# the kernels of `--config hbm-references`: bytes moved per element and what
+# each is (the framework's kernels are recognised by their names)
+HBM_REFERENCE_KERNELS = [("stream_stressor<1u, true, 4, true>", 12, "HBM stressor, triad mix (the roofline kernel)"),
+                         ("strided_stressor<2u, true, 4>", 8, "HBM stressor, read-only mix"),
+                         ("stream_stressor<3u, true, 4, true>", 8, "HBM stressor, copy mix"),
+                         ("stream_stressor<4u, true, 4, true>", 4, "HBM stressor, write-only mix")]
+
+
+def _reference_kind(short: str):
+    """(bytes per element, elements per launch as a fraction of 2^30, what)."""
+    for kname, per, what in HBM_REFERENCE_KERNELS:
+        if short == kname:
+            return per, 1.0, what
+    if "Functor_add" in short:
+        return 12, 0.5, "framework elementwise triad, torch.add(b, c, alpha=3, out=a)"
+    if "copyBuffer" in short:
+        return 8, 0.5, "framework tensor copy, a.copy_(b) (the runtime's device copy)"
+    if "FillFunctor" in short:
+        return 4, 0.5, "framework fill, a.fill_(1.0)"
+    return None
+
+
+def run_reference_summary(args):
+    """HBM rates of `--config hbm-references` from one rocprofv3
+    --kernel-trace database (--dbs): per reference kernel the median launch
+    duration and the rate of its algorithmic bytes (the stressor's launches
+    cover the 2^30 elements, the framework's a half each).  Writes
+    profiles/hbm_references_n2e30_kernel_trace.md."""
+    import sqlite3
+    n = 1 << 30
+    con = sqlite3.connect(args.dbs[0])
+    rows = con.execute("select name, grid_x, workgroup_x, duration from kernels order by start").fetchall()
+    con.close()
+    groups = {}
+    for name, gx, wx, dur in rows:
+        short = _short_kernel(name)
+        kind = _reference_kind(short)
+        if kind is None or (kind[1] < 1 and dur < 100e3):   # the runtime's small copies are not references
+            continue
+        g = groups.setdefault((short, gx // max(wx, 1), wx), {"kind": kind, "durs": []})
+        g["durs"].append(dur)
+    cmd = " ".join(args.cmd) if args.cmd else "(not given)"
+    md = args.md or os.path.join(ROOT, "profiles", "hbm_references_n2e30_kernel_trace.md")
+    L = ["# HBM streaming over N = 2^30 FP32: the stressor's mixes and independent references", "",
+         "Command (repository root, one MI355X), then the summary:", "", "```", cmd,
+         f"python3 bench.py --config reference-summary --dbs {args.dbs[0]}", "```", "",
+         "The launches of `bench.py --config hbm-references` over the 2^30-element arrays, by kernel: the "
+         "median traced duration and the rate of the kernel's algorithmic bytes (triad 12, read-only and copy "
+         "8, write-only and fill 4 bytes per element) against the 8 TB/s HBM peak. The stressor's launches "
+         "each cover all 2^30 elements; the framework's kernels run each pass as two launches of 2^29 "
+         "elements (it splits launches whose offsets pass 2^31 bytes).", "",
+         "| kernel | what | work-groups x threads | elements per launch | launches | median us | GB/s | "
+         "% of 8 TB/s |",
+         "|---|---|---|---|---|---|---|---|"]
+    for (short, wgs, wx), g in sorted(groups.items(), key=lambda kv: -kv[1]["kind"][0] * kv[1]["kind"][1]):
+        per, frac, what = g["kind"]
+        med = float(np.median(g["durs"]))
+        rate = per * n * frac / med     # bytes per ns = GB/s
+        L.append(f"| `{short}` | {what} | {wgs} x {wx} | 2^{29 if frac < 1 else 30} | {len(g['durs'])} | "
+                 f"{med / 1e3:.1f} | {rate:.0f} | {rate / 80.0:.1f} |")
+    with open(md, "w") as f:
+        f.write("\n".join(L) + "\n")
+    print(json.dumps({"written": md, "kernels": len(groups)}))
 
 
 def run_gemm_counter_summary(args):
@@ -2015,7 +2122,7 @@ def main():
                              "pollution", "bandwidth", "ilp", "pairs", "ldsstride", "estimator", "decode",
                              "queues", "hbm_mix", "gemm-counters", "counter-summary", "trace-summary",
                              "lds-counters", "lds-counter-summary", "suite-counter-summary",
-                             "gemm-counter-summary"])
+                             "gemm-counter-summary", "hbm-references", "reference-summary"])
     ap.add_argument("--dbs", nargs="+", default=[], help="summaries: rocprofv3 databases to read")
     ap.add_argument("--cmd", nargs="+", default=[], help="summaries: the commands that made the databases")
     ap.add_argument("--md", default=None, help="trace-summary: markdown file to write")
@@ -2095,6 +2202,10 @@ def main():
         run_suite_counter_summary(args)
     elif args.config == "gemm-counter-summary":
         run_gemm_counter_summary(args)
+    elif args.config == "hbm-references":
+        run_hbm_references(args)
+    elif args.config == "reference-summary":
+        run_reference_summary(args)
 
 
 if __name__ == "__main__":

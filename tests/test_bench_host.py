@@ -124,3 +124,43 @@ def test_gemm_counter_summary_derives_rates(tmp_path):
     assert cells[:6] == ["1", "120.0", "100.0", "0.500", "48.0", "0.250"]
     assert cells[6:] == ["0.020", "0", "2880000", "2048"]
     assert "`gemm256d_kernel<1, 8u>`, 256 work-groups of 512 threads" in md.read_text()
+
+
+def test_reference_summary_rates(tmp_path):
+    """The HBM reference summariser on a hand-made kernel table with the
+    columns of rocprofv3's kernels view: unknown kernels are left out;
+    rates are algorithmic bytes over the median duration, the framework's
+    launches covering half the elements."""
+    import sqlite3
+    db = tmp_path / "t.db"
+    con = sqlite3.connect(db)
+    con.execute("create table kernels (name text, grid_x int, workgroup_x int, duration int, start int)")
+    n = 1 << 30
+    rows = [("void ci::(anonymous namespace)::stream_stressor<1u, true, 4, true>(ci::KCtrl, float const*)",
+             256 * 512, 512, d) for d in (2_000_000, 2_100_000, 1_900_000)]
+    rows += [("void at::native::vectorized_elementwise_kernel<4, at::native::CUDAFunctor_add<float> >(int)",
+              1 << 20, 256, d) for d in (2_400_000, 2_400_000)]
+    rows += [("void at::native::vectorized_elementwise_kernel<4, at::native::FillFunctor<float> >(int)",
+              1 << 20, 256, 700_000)]
+    rows += [("stamp_kernel(unsigned long*)", 64, 64, 900_000),            # not a reference kernel
+             ("void ci::(anonymous namespace)::fill_uniform_f32(float*)", 65536 * 256, 256, 900_000),
+             ("__amd_rocclr_copyBuffer", 2 * 512, 512, 3_000)]                # a small runtime copy
+    for i, r in enumerate(rows):
+        con.execute("insert into kernels values (?, ?, ?, ?, ?)", (*r, i))
+    con.commit()
+    con.close()
+    md = tmp_path / "ref.md"
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--config", "reference-summary",
+                        "--dbs", str(db), "--md", str(md)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stderr
+    lines = [l for l in md.read_text().splitlines() if l.startswith("| `")]
+    assert len(lines) == 3
+    cells = {l.split("|")[1].strip(): [c.strip() for c in l.split("|")[2:-1]] for l in lines}
+    tri = cells["`stream_stressor<1u, true, 4, true>`"]
+    assert tri[1:] == ["256 x 512", "2^30", "3", "2000.0", f"{12 * n / 2_000_000:.0f}",
+                       f"{12 * n / 2_000_000 / 80:.1f}"]
+    add = [v for k, v in cells.items() if "add" in k][0]
+    assert add[0].startswith("framework elementwise triad") and add[2:5] == ["2^29", "2", "2400.0"]
+    assert add[5] == f"{12 * n / 2 / 2_400_000:.0f}"
+    fill = [v for k, v in cells.items() if "Fill" in k][0]
+    assert fill[5] == f"{4 * n / 2 / 700_000:.0f}"
