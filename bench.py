@@ -12,8 +12,9 @@ the pair's slowdown ride along in the same line.
 
 Other workloads, each its own JSON line(s), with --config: sweep,
 precision, serve, pollution, bandwidth, ilp, pairs, ldsstride, estimator,
-decode, queues, hbm_mix; counters, suite-counters, lds-counters and
-gemm-counters are short runs for hardware-counter passes, and the
+decode, queues, hbm_mix; counters, suite-counters, lds-counters,
+gemm-counters and hbm-references are short runs for hardware-counter
+passes or a kernel trace, and the
 *-summary configurations turn their rocprofv3 databases into the files
 under profiles/ (no GPU).  One GPU only: --gpus N with N > 1 exits with a
 message.
