@@ -1927,10 +1927,13 @@ def run_gemm_counter_summary(args):
     ds = [d for d in _pmc_dispatches(args.dbs[0]) if d["name"].startswith("gemm256d_kernel<")]
     if not ds:
         raise SystemExit(f"{args.dbs[0]}: no gemm256d_kernel dispatch")
-    cmd = " ".join(args.cmd) if args.cmd else "(not given)"
+    # further databases (--dbs A B C): the stall-breakdown counters of the same
+    # launches, matched by launch order
+    extra = [[d for d in _pmc_dispatches(db) if d["name"].startswith("gemm256d_kernel<")] for db in args.dbs[1:]]
+    cmd = "\n".join(c.strip() for c in args.cmd) if args.cmd else "(not given)"
     L = ["# Hardware counters of the GEMM victim (BF16, M = N = K = 4096, ring kernel)", "",
-         "Command (repository root, one MI355X; one counter group), then the summary:", "", "```", cmd,
-         f"python3 bench.py --config gemm-counter-summary --dbs {args.dbs[0]}", "```", "",
+         "Commands (repository root, one MI355X; one counter group per run), then the summary:", "", "```", cmd,
+         f"python3 bench.py --config gemm-counter-summary --dbs {' '.join(args.dbs)}", "```", "",
          f"`bench.py --config gemm-counters` launches the BF16 4096³ GEMM three times (`{ds[0]['name']}`, "
          f"{ds[0]['grid'] // ds[0]['wg']} work-groups of {ds[0]['wg']} threads). Derived: active time = "
          "GRBM_GUI_ACTIVE / 8 XCDs / 2.4 GHz; MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES over active cycles x 1024 "
@@ -1951,6 +1954,28 @@ def run_gemm_counter_summary(args):
     L += ["", "Profiling slows the launches; the fractions are what matter: the matrix cores' busy share, the "
               "LDS fragment-load rate against the 256 B/clk/CU of the load path (`lds_stride_counters.md`), "
               "and the share of wave cycles spent waiting (on anything, and on LDS)."]
+    if extra and all(len(e) == len(ds) for e in extra):
+        L += ["", "Where a wave's cycles go (further counter runs of the same command; the SQ wave-cycle counters "
+                  "share one unit, so the three shares add up to the whole): issuing = SQ_ACTIVE_INST_ANY, "
+                  "waiting on a dependency or the barrier = SQ_WAIT_ANY, ready but not issued = SQ_WAIT_INST_ANY, "
+                  "each over SQ_WAVE_CYCLES; MFMA co-issue = SQ_VALU_MFMA_COEXEC_CYCLES over "
+                  "SQ_VALU_MFMA_BUSY_CYCLES.", "",
+              "| launch | issuing | waiting (dependency, barrier) | ready, not issued | MFMA co-issue with other VALU | "
+              "LDS command FIFO full (cycles per active cycle per CU) |",
+              "|---|---|---|---|---|---|"]
+        for i, d in enumerate(ds):
+            c = dict(d["ctr"])
+            for e in extra:
+                for k, v in e[i]["ctr"].items():
+                    c.setdefault(k, v)
+            wc = c.get("SQ_WAVE_CYCLES")
+            if not wc or "SQ_ACTIVE_INST_ANY" not in c or "SQ_WAIT_INST_ANY" not in c:
+                continue
+            active = c["GRBM_GUI_ACTIVE"] / GRBM_INSTANCES
+            co = c.get("SQ_VALU_MFMA_COEXEC_CYCLES", float("nan")) / c["SQ_VALU_MFMA_BUSY_CYCLES"]
+            ff = c.get("SQ_LDS_CMD_FIFO_FULL", float("nan")) / (active * 256)
+            L.append(f"| {i + 1} | {c['SQ_ACTIVE_INST_ANY'] / wc:.3f} | {c['SQ_WAIT_ANY'] / wc:.3f} | "
+                     f"{c['SQ_WAIT_INST_ANY'] / wc:.3f} | {co:.3f} | {ff:.4f} |")
     with open(args.md or os.path.join(ROOT, "profiles", "gemm_bf16_4096_counters.md"), "w") as f:
         f.write("\n".join(L) + "\n")
     print(json.dumps({"written": args.md or "profiles/gemm_bf16_4096_counters.md", "launches": len(ds)}))
