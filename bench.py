@@ -89,7 +89,7 @@ class Suite:
         import torch
         import synth
         self.ctx, self.dev = ctx, dev
-        T = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+        T = lambda x: torch.from_numpy(np.require(x, requirements=["C", "W"])).to(dev)
         n = 1 << 30
         self.n_hbm = n
         self.hb = torch.empty(n, dtype=torch.float32, device=dev)
@@ -629,7 +629,7 @@ def stressor_operands(dev):
     """Operands for every stressor at the sweep's sizes."""
     import torch
     import synth
-    T = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    T = lambda x: torch.from_numpy(np.require(x, requirements=["C", "W"])).to(dev)
     n = 1 << 28
     hb = torch.empty(n, dtype=torch.float32, device=dev)
     hc, ha = torch.empty_like(hb), torch.empty_like(hb)

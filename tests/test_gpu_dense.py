@@ -21,7 +21,7 @@ def ctx(dev):
 
 def _t(x, dev):
     import torch
-    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    return torch.from_numpy(np.require(x, requirements=["C", "W"])).to(dev)
 
 
 # ------------------------------------------------------------- quantizers
