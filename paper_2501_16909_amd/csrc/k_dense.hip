@@ -410,12 +410,24 @@ __global__ void __launch_bounds__(512, 1) gemm256d_kernel(const uint8_t* __restr
 #pragma unroll
       for (int j = 0; j < JN; ++j) fb[b][j] = F::ld(slot + kDOperand, wn * 64 + j * 32 + frow, kb);
     };
-    auto mma_ks = [&](auto buf) {
+    // MFMAs of one k-step: the first (first = true), the others (rest = true)
+    auto mma_part = [&](auto buf, bool first, bool rest) {
       constexpr int b = decltype(buf)::value;
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < JN; ++j) acc[i][j] = F::mma(fa[b][i], fb[b][j], acc[i][j]);
+        for (int j = 0; j < JN; ++j)
+          if ((i == 0 && j == 0) ? first : rest) acc[i][j] = F::mma(fa[b][i], fb[b][j], acc[i][j]);
+    };
+    // FP32 (eight k-steps per stage): each k-step's block is its first MFMA,
+    // then the next k-step's reads, then its other MFMAs, fenced in that
+    // order, so that the reads have seven MFMAs to land; left to itself the
+    // compiler issues them after the block and waits for them at once.
+    // Measured 4 % faster for FP32, 1-2 % slower for BF16, which keeps the
+    // compiler's order.  Results are bit-identical either way.
+    constexpr bool kPinReads = DT == CI_DT_F32;
+    auto fence = [] {
+      if constexpr (kPinReads) __builtin_amdgcn_sched_barrier(0);
     };
     using B0 = std::integral_constant<int, 0>;
     using B1 = std::integral_constant<int, 1>;
@@ -424,8 +436,18 @@ __global__ void __launch_bounds__(512, 1) gemm256d_kernel(const uint8_t* __restr
     auto stage_body = [&](uint32_t t, bool more) {
 #pragma unroll
       for (int s = 0; s < NS; s += 2) {
+        if constexpr (kPinReads) {
+          mma_part(B0{}, true, false);
+          fence();
+        }
         read_ks(t, s + 1, B1{});
-        mma_ks(B0{});
+        fence();
+        mma_part(B0{}, !kPinReads, true);
+        fence();
+        if constexpr (kPinReads) {
+          mma_part(B1{}, true, false);
+          fence();
+        }
         if (s + 2 < NS) {
           read_ks(t, s + 2, B0{});
         } else if (more) {
@@ -433,7 +455,9 @@ __global__ void __launch_bounds__(512, 1) gemm256d_kernel(const uint8_t* __restr
           if (t + 1 + P < nstages) issue(t + 1 + P);
           read_ks(t + 1, 0, B0{});
         }
-        mma_ks(B1{});
+        fence();
+        mma_part(B1{}, !kPinReads, true);
+        fence();
       }
     };
     wait_stage(0, P - 1);
