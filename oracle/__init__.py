@@ -11,7 +11,8 @@ dense products use numpy in FP64 as a library step.  Each function names
 the passage of the paper (Elvinger et al., SoCC'25) or the workload
 definition it follows.
 
-Parity status per function (pins are in tests/test_oracle_pins.py):
+Parity status per function (pins are in tests/test_oracle_pins.py; the decode
+submodule's in tests/test_oracle_decode.py):
   triad_f32, triad_f32_threads, bitsum_u32, sum_f32_exact  pinned
   hbm_read_checksum, hbm_copy, hbm_write_pattern  pinned
   fma_chain_f32 / valu_outputs .................. pinned
