@@ -289,6 +289,11 @@ __global__ void __launch_bounds__(64 * WAVES, 1) gemm256_kernel(const uint8_t* _
 // so after the barrier the whole stage is in LDS; a fence there would also
 // wait for the later stages' loads.  Needs K * element size to be a
 // multiple of 64 bytes; the register-staged kernel above takes the rest.
+// What bounds it: while MFMAs run, a SIMD takes in about one 1 KiB fragment
+// load from LDS per 64 cycles, and a 128 x 64 wave tile issues six per eight
+// 32 x 32 MFMAs, which caps the matrix core near two thirds of its rate even
+// with no memory traffic or barriers (measured); larger wave tiles need more
+// registers than two waves per SIMD have.
 // Four slots of 32 KiB: 128 KiB of the CU's 160 KiB, leaving 32 KiB for a
 // co-resident stressor work-group.  Five slots (loads three stages ahead)
 // ran at the same rate within run-to-run spread, but fill the whole LDS, so
