@@ -12,7 +12,7 @@ the pair's slowdown ride along in the same line.
 
 Other workloads, each its own JSON line(s), with --config: sweep,
 precision, serve, pollution, bandwidth, ilp, pairs, ldsstride, estimator,
-decode, queues, hbm_mix; counters, suite-counters, lds-counters,
+decode, queues, hbm_mix, chase-latency; counters, suite-counters, lds-counters,
 gemm-counters and hbm-references are short runs for hardware-counter
 passes or a kernel trace, and the
 *-summary configurations turn their rocprofv3 databases into the files
@@ -1633,6 +1633,49 @@ def run_gemm_counters(args):
     print(json.dumps({"counters_run": "gemm bf16 4096^3 x3"}), flush=True)
 
 
+def run_chase_latency(args):
+    """Pointer-chase latency with few chains in flight: one 64-lane wave on
+    one CU of each XCD (512 chains, one per lane), each following a uniformly
+    random single cycle (Sattolo-equivalent table, seeded) for 8192 hops;
+    ns per hop = the launch's window over the hops one chain makes.  Tables
+    of 2^20, 2^24 and 2^27 entries (4 MiB: L2-sized; 64 MiB: inside the
+    Infinity Cache; 512 MiB: beyond it, from HBM).  The end indices are
+    checked against a host walk of the same table for 8 chains."""
+    import torch
+    import synth
+    from paper_2501_16909_amd import coloc
+    dev = torch.device("cuda:0")
+    ctx = coloc.Context(0)
+    ws = torch.empty(WS_BYTES, dtype=torch.uint8, device=dev)
+    hops = 8192
+    rows = []
+    for lg in (20, 24, 27):
+        n = 1 << lg
+        nxt = synth.random_cycle_u32(synth.seed_for(6, synth.BUF_CHASE) + lg, n)
+        t_next = torch.from_numpy(nxt.view(np.int32)).to(dev)
+        end = torch.empty(8 * 64, dtype=torch.int32, device=dev)
+        o = dict(src0=t_next, n=n, dst=end, threads=64, wg_per_cu=1, knob=1, iters=hops, passes=1)
+        ctx.stressor("ptrchase", 1 / 32, ws=ws, **o).stop()           # untimed: fills the caches and TLBs
+        rep = ctx.stressor("ptrchase", 1 / 32, ws=ws, **o).stop()
+        got = end.cpu().numpy().view(np.uint32)
+        chains = rep.grid * 64
+        ok = True
+        for c in range(0, chains, chains // 8):                       # host walk of 8 chains
+            i = np.uint32(c * (n // chains))
+            for _ in range(hops):
+                i = nxt[i]
+            ok &= bool(got[c] == i)
+        row = {"entries": n, "mib": n * 4 >> 20, "chains": chains, "hops_per_chain": hops,
+               "ns_per_hop": round(rep.window_ns / hops, 1), "ghops_per_s": round(rep.units / rep.window_ns, 2),
+               "end_indices_match_host_walk": ok}
+        rows.append(row)
+        log(json.dumps(row))
+        del t_next
+        torch.cuda.empty_cache()
+    ctx.close()
+    _emit({"metric": "pointer-chase latency, one wave per XCD", "rows": rows}, args)
+
+
 def run_hbm_references(args):
     """Short run for a kernel trace: the HBM stressor's four traffic mixes
     over N = 2^30 FP32 (fixed work, one pass per launch) and, over the same
@@ -2148,7 +2191,8 @@ def main():
                              "pollution", "bandwidth", "ilp", "pairs", "ldsstride", "estimator", "decode",
                              "queues", "hbm_mix", "gemm-counters", "counter-summary", "trace-summary",
                              "lds-counters", "lds-counter-summary", "suite-counter-summary",
-                             "gemm-counter-summary", "hbm-references", "reference-summary"])
+                             "gemm-counter-summary", "hbm-references", "reference-summary",
+                             "chase-latency"])
     ap.add_argument("--dbs", nargs="+", default=[], help="summaries: rocprofv3 databases to read")
     ap.add_argument("--cmd", nargs="+", default=[], help="summaries: the commands that made the databases")
     ap.add_argument("--md", default=None, help="trace-summary: markdown file to write")
@@ -2230,6 +2274,8 @@ def main():
         run_gemm_counter_summary(args)
     elif args.config == "hbm-references":
         run_hbm_references(args)
+    elif args.config == "chase-latency":
+        run_chase_latency(args)
     elif args.config == "reference-summary":
         run_reference_summary(args)
 
