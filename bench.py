@@ -1035,6 +1035,92 @@ def run_serve(args):
 
 
 
+def _serving_stats(res, reqs, iso_ns, bound):
+    lat = np.array([r["end_s"] - r["arrival_s"] for r in res])
+    slow = np.array([r["service_ns"] for r in res]) / iso_ns
+    horizon = max(r["end_s"] for r in res)
+    kinds = np.array([q["kind"] for q in reqs])
+    return {"slowdown_p50_by_kind": {k: round(float(np.median(slow[kinds == k])), 3)
+                                     for k in ("gemm", "gemv", "triad") if np.any(kinds == k)},"latency_ms_p50": round(float(np.percentile(lat, 50)) * 1e3, 3),
+            "latency_ms_p99": round(float(np.percentile(lat, 99)) * 1e3, 3),
+            "throughput_req_s": round(len(reqs) / horizon, 1),
+            "slowdown_p50": round(float(np.percentile(slow, 50)), 3),
+            "slowdown_p99": round(float(np.percentile(slow, 99)), 3),
+            "over_bound_frac": round(float(np.mean(slow > bound)), 4),
+            "mean_in_service": round(float(sum(r["end_s"] - r["admit_s"] for r in res)) / horizon, 3)}
+
+
+def run_serve_background(args):
+    """Serving on a loaded device: an HBM triad stressor on every CU at duty
+    --duty runs through each serving run (serve_run_background), so that the
+    admission rule has to decide against a constant background load; naive
+    against sensitivity-aware admission (duty-axis profiles with
+    read/write-aware HBM pricing, the stressor's own measured load as the
+    rule's background), and the same traces without the stressor.
+    Slowdowns are over every request, against the request served alone on
+    an idle device; every result must equal its isolated one bit for bit."""
+    import torch
+    from paper_2501_16909_amd import coloc
+    ctx = coloc.Context(0)
+    dev = ctx.device
+    profiles = library_profiles(serve_profiles(ctx, args, axis="duty"),
+                                serve_profiles(ctx, args, axis="duty", hbm_mix="read", res=("hbm",)))
+    ops = stressor_operands(dev)["hbm"]
+    ws = torch.empty(WS_BYTES, dtype=torch.uint8, device=dev)
+    # the background's load: its standalone rate at this duty over the full rate
+    full = ctx.stressor("hbm", 1.0, ws=ws, passes=1, **ops).stop()
+    part = ctx.stressor("hbm", 1.0, ws=ws, passes=1, duty=args.duty, **ops).stop()
+    press = min(1.0, (part.units / part.kernel_ns) / (full.units / full.kernel_ns))
+    bg = {"press": {"hbm": press}, "occ": 0.25, "hbm_write_frac": HBM_WRITE_FRAC["triad"]}
+    alone_bg = {k: round(coloc.predict_slowdown(profiles, k, [bg]), 3) for k in profiles}
+    log(f"background: HBM triad stressor, duty {args.duty} %: load {press:.3f} of the full rate; "
+        f"predicted slowdown beside it alone: {alone_bg}")
+    budget, slots = 32 << 30, 4
+    out = {"metric": "serving latency p50/p99, throughput and slowdown under a background HBM stressor, "
+                     "naive vs sensitivity-aware admission",
+           "config": {"workload": "Poisson arrivals, 1/3 each BF16 GEMM n~logU[512,8192], BF16 GEMV "
+                                  "n~logU[4096,16384], FP32 triad N~logU[2^20,2^28]",
+                      "seconds": args.seconds, "slots": slots, "hbm_budget_gib": budget >> 30,
+                      "bound": args.bound, "profile_axis": "duty", "hbm_pricing": "read/write-aware",
+                      "background": {"resource": "hbm", "mix": "triad", "intensity": 1.0, "duty_pct": args.duty,
+                                     "load": round(press, 4), "occ": 0.25,
+                                     "predicted_slowdown_beside_it_alone": alone_bg}},
+           "runs": [], "profiles": profiles}
+    for lam in args.rates:
+        reqs = serve_trace(lam, args.seconds, 31337 + int(lam))
+        iso = ctx.serve([dict(r, arrival_s=0.0) for r in reqs], policy="naive", hbm_budget=budget, slots=1)
+        iso_ns = np.array([o["service_ns"] for o in iso])
+        for loaded in (False, True):
+            for policy in ("naive", "sensitivity"):
+                log(f"serve {lam}/s {policy}, background {'on' if loaded else 'off'}: {len(reqs)} requests")
+                t0 = time.perf_counter()
+                rep = None
+                if loaded:
+                    res, rep = ctx.serve_loaded(reqs, "hbm", 1.0, ws=ws, policy=policy, bound=args.bound,
+                                                hbm_budget=budget, slots=slots, profiles=profiles, background=bg,
+                                                duty=args.duty, deadline_ms=int(1000 * (60 + 20 * args.seconds)),
+                                                **ops)
+                else:
+                    res = ctx.serve(reqs, policy=policy, bound=args.bound, hbm_budget=budget, slots=slots,
+                                    profiles=profiles)
+                wall = time.perf_counter() - t0
+                run = {"rate_per_s": lam, "policy": policy, "background": loaded, "requests": len(reqs)}
+                run.update(_serving_stats(res, reqs, iso_ns, args.bound))
+                run["results_equal_isolated"] = all(r["checksum_bits"] == i["checksum_bits"]
+                                                    for r, i in zip(res, iso))
+                if rep is not None:
+                    run["stressor_gb_s"] = round(rep.achieved / 1e9, 1)
+                    run["stressor_window_s"] = round(rep.window_ns * 1e-9, 3)
+                run["wall_s"] = round(wall, 2)
+                out["runs"].append(run)
+                log(json.dumps(run))
+                assert run["results_equal_isolated"], "a served result differs from its isolated run"
+    ctx.close()
+    print(json.dumps(out), flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(out, f)
+
 # --------------------------------------------------------------------------
 # The paper's individual experiments, on MI355X
 # --------------------------------------------------------------------------
@@ -2192,7 +2278,7 @@ def main():
                              "queues", "hbm_mix", "gemm-counters", "counter-summary", "trace-summary",
                              "lds-counters", "lds-counter-summary", "suite-counter-summary",
                              "gemm-counter-summary", "hbm-references", "reference-summary",
-                             "chase-latency"])
+                             "chase-latency", "serve-background"])
     ap.add_argument("--dbs", nargs="+", default=[], help="summaries: rocprofv3 databases to read")
     ap.add_argument("--cmd", nargs="+", default=[], help="summaries: the commands that made the databases")
     ap.add_argument("--md", default=None, help="trace-summary: markdown file to write")
@@ -2215,6 +2301,8 @@ def main():
                     help="serve: arrival rates per second")
     ap.add_argument("--seconds", type=float, default=2.0, help="serve: trace length")
     ap.add_argument("--bound", type=float, default=1.5, help="serve: p99 slowdown bound")
+    ap.add_argument("--duty", type=int, default=50,
+                    help="serve-background: duty cycle (percent) of the background HBM stressor")
     ap.add_argument("--profiles", default=None, help="serve: sensitivity profiles (JSON)")
     ap.add_argument("--batch", type=int, default=1, help="decode: sequences per step (1..8)")
     ap.add_argument("--contexts", type=int, default=6, help="queues: fresh contexts (queue orders) to try")
@@ -2278,6 +2366,8 @@ def main():
         run_chase_latency(args)
     elif args.config == "reference-summary":
         run_reference_summary(args)
+    elif args.config == "serve-background":
+        run_serve_background(args)
 
 
 if __name__ == "__main__":

@@ -777,6 +777,10 @@ typedef struct ci_policy {
   int slots;              /* max requests on the device at once (1..8)        */
   const ci_profile_t* profiles;
   int nprofiles;
+  /* Optional (NULL = none): the load of a co-runner present for the whole
+   * run, such as the stressor serve_run_background holds (its press, occ
+   * and read/write fields are read; kind and sens are not). */
+  const ci_profile_t* background;
 } ci_policy_t;
 
 typedef struct ci_served {
@@ -818,9 +822,34 @@ ci_status_t serve_run(ci_ctx_t* ctx, const ci_request_t* trace, int n, const ci_
  * NAIVE admits, USHER admits when the summed occupancy of all jobs stays
  * below 1 (Section 3, Pitfall 1), and SENSITIVITY admits when
  * ci_predict_slowdown of every job, beside all the others, is <= bound.
+ * A background load (p->background) is one more co-runner of every job
+ * and adds its occ to the USHER sum; its own slowdown is not bounded (it is
+ * not a request), and it does not change the idle-device rule.
  * CI_ERR_INVALID_ARG on a bad policy or a kind without a profile. */
 ci_status_t ci_admit(const ci_policy_t* p, const int* running_kinds, int nrun, int cand_kind,
                      uint64_t cand_bytes, uint64_t free_bytes, int* admit);
+
+/* serve_run on a device under constant background load (Section 4.1 holds a
+ * stressor's interference constant for a victim's whole lifetime; here it
+ * is held for the whole serving run, so that admission decides on a loaded
+ * device).  After its own set-up the loop launches stressor `resource` at
+ * CU fraction `intensity` with `opts` and the caller-owned workspace ws
+ * (ws_bytes >= ci_workspace_size), as stressor_launch does; opts->passes
+ * must be 0 (the stressor runs until stopped) and opts->deadline_ms should
+ * exceed the run.  The trace's clock starts once the stressor is running;
+ * requests are served exactly as by serve_run; after the last one retires
+ * the stressor is stopped and its report written to *rep (caller-owned).
+ * Admission sees the stressor only through p->background.  A stressor that
+ * holds, on every CU, the LDS, registers or wave slots a request's
+ * work-groups need keeps that request from starting until the stressor's
+ * in-kernel deadline (the resource-fit effect of Section 4.2).  Errors as
+ * serve_run and stressor_launch; CI_ERR_INVALID_ARG also for NULL opts or
+ * rep, or opts->passes != 0; CI_ERR_TIMEOUT when the stressor stopped on
+ * its deadline (out and *rep are still written). */
+ci_status_t serve_run_background(ci_ctx_t* ctx, const ci_request_t* trace, int n,
+                                 const ci_policy_t* p, ci_resource_t resource, float intensity,
+                                 const ci_stressor_opts_t* opts, void* ws, size_t ws_bytes,
+                                 ci_served_t* out, ci_stressor_report_t* rep);
 
 #ifdef __cplusplus
 }

@@ -536,7 +536,7 @@ def predicted_slowdown_rw(victim: dict, corunners: list, hbm: int = 0) -> float:
 
 
 def admit(policy: str, running: list, cand: dict, free_bytes: int, bound: float,
-          slots: int) -> bool:
+          slots: int, background: dict | None = None) -> bool:
     """running / cand: dicts with 'sens' (per-resource five-point curves),
     'press' (per-resource pressure it exerts), 'bytes' and 'occ' (fraction of wave
     slots).  Policies: 'naive' (memory and slot only), 'usher' (summed
@@ -549,7 +549,13 @@ def admit(policy: str, running: list, cand: dict, free_bytes: int, bound: float,
     on a resource add and clip at 1, the per-resource factors max(1, curve)
     multiply (predicted_slowdown_rw, with read/write-aware HBM pricing), and
     a request is admitted first in first out, without bypass, only if every
-    job, itself included, stays within the bound."""
+    job, itself included, stays within the bound.
+
+    background: the load of a co-runner present all along (Section 4.1 holds
+    a stressor's interference constant for a victim's lifetime), a dict with
+    'press', 'occ' and the optional read/write fields.  It is one more
+    co-runner of every job and adds its occupancy to the 'usher' sum; it is
+    not itself bounded, since no request waits on it."""
     if policy not in ("naive", "usher", "sensitivity"):
         raise ValueError(policy)
     if cand["bytes"] > free_bytes or len(running) >= slots:
@@ -559,13 +565,14 @@ def admit(policy: str, running: list, cand: dict, free_bytes: int, bound: float,
     # ever, since nothing running could free up.
     if policy == "naive" or not running:
         return True
+    bg = [background] if background is not None else []
     if policy == "usher":
-        return sum(j["occ"] for j in running) + cand["occ"] < 1.0
+        return sum(j["occ"] for j in running + bg) + cand["occ"] < 1.0
     if policy != "sensitivity":
         raise ValueError(policy)
     group = running + [cand]
     for j in range(len(group)):
-        others = group[:j] + group[j + 1:]
+        others = group[:j] + group[j + 1:] + bg
         if predicted_slowdown_rw(group[j], others) > bound:
             return False
     return True
@@ -607,7 +614,7 @@ class FirstFitArena:
 
 
 def simulate_admission(arrivals, jobs, service_s, policy: str, budget: int, bound: float,
-                       slots: int, slowed: bool = False):
+                       slots: int, slowed: bool = False, background: dict | None = None):
     """Discrete-event model of the continuous-batching loop (Section 5.1's
     scheduler, in this library's reading): requests arrive at arrivals[i]
     (sorted); at every arrival and completion the queue head is admitted,
@@ -617,7 +624,9 @@ def simulate_admission(arrivals, jobs, service_s, policy: str, budget: int, boun
     service_s[i] (times its predicted slowdown beside the jobs running when
     it was admitted if `slowed`) and then frees its slot and memory.
     jobs[i]: the request's admit() dict ('sens', 'press', 'occ', 'bytes', and
-    the optional read/write-aware fields).  Returns a list of dicts with
+    the optional read/write-aware fields); background: a load present all
+    along, as in admit() (with `slowed` it also slows every request, a lone
+    one included).  Returns a list of dicts with
     'admit', 'end', 'slot', 'corunners' (indices running at admission) per
     request, in request order."""
     n = len(arrivals)
@@ -648,7 +657,8 @@ def simulate_admission(arrivals, jobs, service_s, policy: str, budget: int, boun
         while queue:
             q = queue[0]
             cur = sorted(running)
-            ok = admit(policy, [jobs[r] for r in cur], jobs[q], arena.largest_free(), bound, slots)
+            ok = admit(policy, [jobs[r] for r in cur], jobs[q], arena.largest_free(), bound, slots,
+                       background)
             if not ok:
                 break
             off = arena.alloc(jobs[q]["bytes"])
@@ -657,8 +667,9 @@ def simulate_admission(arrivals, jobs, service_s, policy: str, budget: int, boun
             queue.pop(0)
             sl = free_slots.pop(0)
             svc = service_s[q]
-            if slowed and cur:
-                svc *= predicted_slowdown_rw(jobs[q], [jobs[r] for r in cur])
+            co = [jobs[r] for r in cur] + ([background] if background is not None else [])
+            if slowed and co:
+                svc *= predicted_slowdown_rw(jobs[q], co)
             running[q] = (t + svc, off, sl)
             out[q].update(admit=t, end=t + svc, slot=sl, corunners=tuple(cur))
     return out

@@ -115,7 +115,8 @@ class Request(C.Structure):
 
 class Policy(C.Structure):
     _fields_ = [("kind", C.c_int), ("bound", C.c_double), ("hbm_budget", C.c_uint64),
-                ("slots", C.c_int), ("profiles", C.POINTER(Profile)), ("nprofiles", C.c_int)]
+                ("slots", C.c_int), ("profiles", C.POINTER(Profile)), ("nprofiles", C.c_int),
+                ("background", C.POINTER(Profile))]
 
 
 class Served(C.Structure):
@@ -210,6 +211,9 @@ EXPORTS = {
                              C.POINTER(MeasureOpts), C.c_void_p, C.c_size_t, C.c_void_p,
                              C.POINTER(Cell)], C.c_int),
     "serve_run": ([C.c_void_p, C.POINTER(Request), C.c_int, C.POINTER(Policy), C.POINTER(Served)], C.c_int),
+    "serve_run_background": ([C.c_void_p, C.POINTER(Request), C.c_int, C.POINTER(Policy), C.c_int, C.c_float,
+                              C.POINTER(StressorOpts), C.c_void_p, C.c_size_t, C.POINTER(Served),
+                              C.POINTER(StressorReport)], C.c_int),
     "ci_admit": ([C.POINTER(Policy), C.POINTER(C.c_int), C.c_int, C.c_int, C.c_uint64, C.c_uint64,
                   C.POINTER(C.c_int)], C.c_int),
     "ci_predict_slowdown": ([C.POINTER(Profile), C.POINTER(C.POINTER(Profile)), C.c_int,
@@ -716,9 +720,8 @@ class Context:
         return h
 
     # ------------------------------------------------------------ serving
-    def serve(self, requests, policy: str = "naive", bound: float = 1.5, hbm_budget: int = 8 << 30,
-              slots: int = 4, profiles=None):
-        self._sync_torch()
+    @staticmethod
+    def _serve_args(requests, policy, bound, hbm_budget, slots, profiles, background):
         n = len(requests)
         tr = (Request * max(n, 1))()
         for i, q in enumerate(requests):
@@ -726,11 +729,46 @@ class Context:
                             q.get("m", 0), q.get("n", 0), q.get("k", 0), q["seed"],
                             _ptr(q["out_copy"]) if q.get("out_copy") is not None else None)
         profs = make_profiles(profiles or {})
+        bg = make_load_profile(background) if background is not None else None
         pol = Policy(POLICIES[policy], bound, hbm_budget, slots,
-                     C.cast(profs, C.POINTER(Profile)) if len(profs) else None, len(profs))
-        out = (Served * max(n, 1))()
+                     C.cast(profs, C.POINTER(Profile)) if len(profs) else None, len(profs),
+                     C.pointer(bg) if bg is not None else None)
+        pol._keep = (profs, bg)   # the policy holds raw pointers into these
+        return tr, n, pol, (Served * max(n, 1))()
+
+    def serve(self, requests, policy: str = "naive", bound: float = 1.5, hbm_budget: int = 8 << 30,
+              slots: int = 4, profiles=None, background=None):
+        """serve_run.  background: the load of a co-runner present throughout,
+        as a profile dict ("press", "occ", read/write fields), for the
+        admission rules (serve_loaded also runs one)."""
+        self._sync_torch()
+        tr, n, pol, out = self._serve_args(requests, policy, bound, hbm_budget, slots, profiles, background)
         _check(load_library().serve_run(self.handle, tr, n, C.byref(pol), out))
         return [{f: getattr(out[i], f) for f, _ in Served._fields_} for i in range(n)]
+
+    def serve_loaded(self, requests, resource: str, intensity: float, ws=None, policy: str = "naive",
+                     bound: float = 1.5, hbm_budget: int = 8 << 30, slots: int = 4, profiles=None,
+                     background=None, **opts):
+        """serve_run_background: serve `requests` while stressor `resource`
+        runs at CU fraction `intensity` with stressor options `opts` (its
+        operands and knobs, passes 0).  background: the stressor's load
+        profile for the admission rules (None: admission does not see it).
+        Returns (served records, the stressor's Report); raises CiError on
+        any error, also when the stressor stopped on its deadline."""
+        import torch
+        self._sync_torch()
+        tr, n, pol, out = self._serve_args(requests, policy, bound, hbm_budget, slots, profiles, background)
+        o = make_opts(**opts)
+        if ws is None:
+            need = C.c_size_t()
+            _check(load_library().ci_workspace_size(RES[resource], 1.0, C.byref(o), C.byref(need)))
+            ws = torch.empty(max(int(need.value), 256), dtype=torch.uint8, device=self.device)
+        rep = StressorReport()
+        st = load_library().serve_run_background(self.handle, tr, n, C.byref(pol), RES[resource],
+                                                 float(intensity), C.byref(o), _ptr(ws), ws.numel(), out,
+                                                 C.byref(rep))
+        _check(st)
+        return [{f: getattr(out[i], f) for f, _ in Served._fields_} for i in range(n)], _report(rep, st)
 
 
 class DecodeModel:
@@ -801,6 +839,23 @@ class DecodeModel:
         return self.weights[int(off):int(off) + spec[name]]
 
 
+def _fill_profile(dst: Profile, p: dict):
+    for r in range(NRES):
+        for j in range(NPOINTS):
+            dst.sens[r][j] = 1.0
+        dst.press[r] = 0.0
+    for rname, curve in p.get("sens", {}).items():
+        for j, v in enumerate(curve):
+            dst.sens[RES[rname]][j] = float(v)
+    for rname, v in p.get("press", {}).items():
+        dst.press[RES[rname]] = float(v)
+    dst.occ = float(p.get("occ", 0.0))
+    for j, v in enumerate(p.get("sens_hbm_read") or [0.0] * NPOINTS):
+        dst.sens_hbm_read[j] = float(v)
+    dst.press_hbm_read = float(p.get("press_hbm_read", 0.0))
+    dst.hbm_write_frac = float(p.get("hbm_write_frac", 1.0))
+
+
 def make_profiles(profiles: dict):
     """profiles: {kind name: {"sens": {res: [5 slowdowns]}, "press": {res: p}, "occ": o}}, and
     optionally "sens_hbm_read" (5 slowdowns against the read-only HBM mix), "press_hbm_read"
@@ -808,31 +863,31 @@ def make_profiles(profiles: dict):
     arr = (Profile * max(len(profiles), 1))()
     for i, (kind, p) in enumerate(profiles.items()):
         arr[i].kind = VICTIMS[kind]
-        for r in range(NRES):
-            for j in range(NPOINTS):
-                arr[i].sens[r][j] = 1.0
-            arr[i].press[r] = 0.0
-        for rname, curve in p.get("sens", {}).items():
-            for j, v in enumerate(curve):
-                arr[i].sens[RES[rname]][j] = float(v)
-        for rname, v in p.get("press", {}).items():
-            arr[i].press[RES[rname]] = float(v)
-        arr[i].occ = float(p.get("occ", 0.0))
-        for j, v in enumerate(p.get("sens_hbm_read") or [0.0] * NPOINTS):
-            arr[i].sens_hbm_read[j] = float(v)
-        arr[i].press_hbm_read = float(p.get("press_hbm_read", 0.0))
-        arr[i].hbm_write_frac = float(p.get("hbm_write_frac", 1.0))
+        _fill_profile(arr[i], p)
     if not profiles:
         return (Profile * 0)()
     return arr
 
 
+def make_load_profile(p: dict) -> Profile:
+    """A background load for ci_policy_t.background: "press" per resource,
+    "occ", and the optional read/write fields, as in make_profiles (its kind
+    and curves are not read)."""
+    out = Profile()
+    out.kind = -1
+    _fill_profile(out, p)
+    return out
+
+
 def predict_slowdown(profiles: dict, victim: str, corunners) -> float:
-    """ci_predict_slowdown of kind `victim` beside co-runner kinds (names in profiles)."""
+    """ci_predict_slowdown of kind `victim` beside co-runners: kind names in
+    profiles, or load profile dicts (make_load_profile) such as a background."""
     names = list(profiles)
     arr = make_profiles(profiles)
+    loads = [make_load_profile(k) for k in corunners if isinstance(k, dict)]
+    it = iter(loads)
     co = (C.POINTER(Profile) * max(len(corunners), 1))(
-        *[C.pointer(arr[names.index(k)]) for k in corunners])
+        *[C.pointer(next(it)) if isinstance(k, dict) else C.pointer(arr[names.index(k)]) for k in corunners])
     out = C.c_double()
     _check(load_library().ci_predict_slowdown(C.byref(arr[names.index(victim)]), co, len(corunners),
                                               C.byref(out)))
@@ -840,10 +895,13 @@ def predict_slowdown(profiles: dict, victim: str, corunners) -> float:
 
 
 def admit(policy: str, profiles: dict, running_kinds, cand_kind: str, cand_bytes: int,
-          free_bytes: int, bound: float = 1.5, slots: int = 4) -> bool:
+          free_bytes: int, bound: float = 1.5, slots: int = 4, background=None) -> bool:
+    """ci_admit; background: a load profile dict present throughout (make_load_profile)."""
     profs = make_profiles(profiles)
+    bg = make_load_profile(background) if background is not None else None
     pol = Policy(POLICIES[policy], bound, 1 << 40, slots,
-                 C.cast(profs, C.POINTER(Profile)) if len(profs) else None, len(profs))
+                 C.cast(profs, C.POINTER(Profile)) if len(profs) else None, len(profs),
+                 C.pointer(bg) if bg is not None else None)
     rk = (C.c_int * max(len(running_kinds), 1))(*[VICTIMS[k] for k in running_kinds])
     out = C.c_int()
     _check(load_library().ci_admit(C.byref(pol), rk, len(running_kinds), VICTIMS[cand_kind],

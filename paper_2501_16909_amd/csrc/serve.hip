@@ -13,6 +13,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -69,11 +70,13 @@ double predict_one(const ci_profile_t* v, const ci_profile_t* const* co, int nco
   return out;
 }
 
-// Predicted slowdown of job `j` beside every other job of `group`.
-double predict(const std::vector<const ci_profile_t*>& group, size_t j) {
+// Predicted slowdown of job `j` beside every other job of `group` and the
+// background load `bg` (if any).
+double predict(const std::vector<const ci_profile_t*>& group, size_t j, const ci_profile_t* bg) {
   std::vector<const ci_profile_t*> co;
   for (size_t o = 0; o < group.size(); ++o)
     if (o != j) co.push_back(group[o]);
+  if (bg) co.push_back(bg);
   return predict_one(group[j], co.data(), (int)co.size());
 }
 
@@ -189,13 +192,13 @@ extern "C" ci_status_t ci_admit(const ci_policy_t* p, const int* running_kinds, 
   if (!cp) return set_err(CI_ERR_INVALID_ARG, "ci_admit: no profile for kind %d", cand_kind);
   group.push_back(cp);
   if (p->kind == CI_POLICY_USHER) {
-    double occ = 0.0;
+    double occ = p->background ? p->background->occ : 0.0;
     for (auto* g : group) occ += g->occ;
     *admit = occ < 1.0;
     return CI_OK;
   }
   for (size_t j = 0; j < group.size(); ++j)  // CI_POLICY_SENSITIVITY
-    if (predict(group, j) > p->bound) return CI_OK;
+    if (predict(group, j, p->background) > p->bound) return CI_OK;
   *admit = 1;
   return CI_OK;
 }
@@ -276,8 +279,20 @@ ci_status_t start_request(ci_ctx* ctx, const ci_request_t& q, uint8_t* base, hip
 
 }  // namespace
 
-extern "C" ci_status_t serve_run(ci_ctx_t* ctx, const ci_request_t* trace, int n,
-                                 const ci_policy_t* p, ci_served_t* out) {
+namespace {
+
+// The stressor serve_run_background holds for the whole run.
+struct Background {
+  ci_resource_t r;
+  float intensity;
+  const ci_stressor_opts_t* opts;
+  void* ws;
+  size_t ws_bytes;
+  ci_stressor_report_t* rep;
+};
+
+ci_status_t serve_impl(ci_ctx_t* ctx, const ci_request_t* trace, int n, const ci_policy_t* p,
+                       const Background* bg, ci_served_t* out) {
   if (!ctx || !p || n < 0 || (n && (!trace || !out)))
     return set_err(CI_ERR_INVALID_ARG, "serve_run: bad argument");
   if (p->slots < 1 || p->slots > 8) return set_err(CI_ERR_INVALID_ARG, "serve_run: slots must be in [1, 8]");
@@ -329,6 +344,15 @@ extern "C" ci_status_t serve_run(ci_ctx_t* ctx, const ci_request_t* trace, int n
   std::deque<int> queue;
   std::vector<int> run_kinds;
   int next_arrival = 0, done = 0;
+  // The background stressor starts after every allocation above (nothing
+  // below allocates or frees device memory while it runs) and before the
+  // trace's clock.
+  ci_stressor_t* bg_h = nullptr;
+  if (bg && st == CI_OK) {
+    const ci_status_t ls = stressor_launch(ctx, bg->r, bg->intensity, streams[0], bg->opts, bg->ws,
+                                           bg->ws_bytes, &bg_h);
+    if (ls != CI_OK) fail(ls);
+  }
   const double t0 = now_s();
   for (int i = 0; i < n; ++i) {
     memset(&out[i], 0, sizeof(out[i]));
@@ -405,6 +429,14 @@ extern "C" ci_status_t serve_run(ci_ctx_t* ctx, const ci_request_t* trace, int n
     }
     if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
   }
+  if (bg_h) {  // stop it first: requests still queued may need its CUs
+    const std::string why = st == CI_OK ? std::string() : std::string(ci_last_error());
+    const ci_status_t ss = stressor_stop(bg_h, bg->rep);
+    if (st == CI_OK)
+      st = ss;
+    else
+      set_err(st, "%s", why.c_str());
+  }
   // drain whatever is still on the device before freeing
   for (int s = 0; s < S; ++s)
     if (streams[s]) (void)hipStreamSynchronize(streams[s]);
@@ -419,4 +451,24 @@ extern "C" ci_status_t serve_run(ci_ctx_t* ctx, const ci_request_t* trace, int n
   if (part_sum) (void)hipFree(part_sum);
   (void)hipFree(arena_base);
   return st;
+}
+
+}  // namespace
+
+extern "C" ci_status_t serve_run(ci_ctx_t* ctx, const ci_request_t* trace, int n,
+                                 const ci_policy_t* p, ci_served_t* out) {
+  return serve_impl(ctx, trace, n, p, nullptr, out);
+}
+
+extern "C" ci_status_t serve_run_background(ci_ctx_t* ctx, const ci_request_t* trace, int n,
+                                            const ci_policy_t* p, ci_resource_t resource,
+                                            float intensity, const ci_stressor_opts_t* opts, void* ws,
+                                            size_t ws_bytes, ci_served_t* out,
+                                            ci_stressor_report_t* rep) {
+  if (!opts || !rep) return set_err(CI_ERR_INVALID_ARG, "serve_run_background: NULL opts or report");
+  if (opts->passes != 0)
+    return set_err(CI_ERR_INVALID_ARG, "serve_run_background: the stressor must run until stopped (passes 0)");
+  memset(rep, 0, sizeof(*rep));
+  const Background bg{resource, intensity, opts, ws, ws_bytes, rep};
+  return serve_impl(ctx, trace, n, p, &bg, out);
 }

@@ -166,6 +166,70 @@ def test_admission_matches_oracle(policy, bound, read_curves):
     assert coloc.admit(policy, greedy, [], "triad", 10, 100, bound=1.0001)
 
 
+
+@pytest.mark.parametrize("policy", ["naive", "usher", "sensitivity"])
+@pytest.mark.parametrize("read_curves", [False, True])
+def test_admission_with_background_matches_oracle(policy, read_curves):
+    """ci_admit with a background load (ci_policy_t.background) against the
+    oracle's rule, over running sets of up to two, every candidate, several
+    bounds, and background loads that are write-heavy (priced on the triad
+    curve), read-mostly (priced on the read-only curve when the victim has
+    one) or occupancy-only."""
+    import itertools
+    profs = _profiles(read_curves)
+    kinds = list(profs)
+    loads = [{"press": {"hbm": 0.5}, "occ": 0.25, "hbm_write_frac": 1 / 3},
+             {"press": {"hbm": 0.75}, "occ": 0.0, "hbm_write_frac": 0.0, "press_hbm_read": 0.6},
+             {"press": {"mfma_bf16": 0.4, "lds": 0.3}, "occ": 0.45, "hbm_write_frac": 1.0}]
+    checked = refused = 0
+    for load in loads:
+        bgo = _oracle_job(dict(load, sens={}))
+        for bound in (1.2, 1.6, 2.5):
+            for nrun in range(0, 3):
+                for running in itertools.product(kinds, repeat=nrun):
+                    for cand in kinds:
+                        got = coloc.admit(policy, profs, list(running), cand, 10, 100, bound=bound, slots=4,
+                                          background=load)
+                        want = oracle.admit(policy, [_oracle_job(profs[k]) for k in running],
+                                            _oracle_job(profs[cand]), 100, bound, 4, background=bgo)
+                        assert got == want, (policy, load, bound, running, cand)
+                        checked += 1
+                        refused += not got
+    assert checked == 3 * 3 * 13 * 3
+    for load in loads:          # a load profile as a co-runner of ci_predict_slowdown
+        bgo = _oracle_job(dict(load, sens={}))
+        for v in kinds:
+            got = coloc.predict_slowdown(profs, v, ["triad", load])
+            want = oracle.predicted_slowdown_rw(_oracle_job(profs[v]), [_oracle_job(profs["triad"]), bgo])
+            assert got == pytest.approx(want, rel=1e-12, abs=0), (v, load)
+    if policy != "naive":
+        assert 0 < refused < checked
+
+
+def test_serve_run_background_argument_checks():
+    """serve_run_background refuses, before touching any device, a missing
+    options block or report, a stressor with a fixed pass count, and a NULL
+    context."""
+    lib = coloc.load_library()
+    pol = coloc.Policy(0, 1.5, 1 << 30, 4, None, 0, None)
+    rep = coloc.StressorReport()
+    opts = coloc.StressorOpts()
+    out = (coloc.Served * 1)()
+    st = lib.serve_run_background(None, None, 0, C.byref(pol), coloc.RES["hbm"], 1.0, None, None, 0, out,
+                                  C.byref(rep))
+    assert st == 1 and b"NULL opts" in lib.ci_last_error()
+    st = lib.serve_run_background(None, None, 0, C.byref(pol), coloc.RES["hbm"], 1.0, C.byref(opts), None, 0,
+                                  out, None)
+    assert st == 1
+    opts.passes = 1
+    st = lib.serve_run_background(None, None, 0, C.byref(pol), coloc.RES["hbm"], 1.0, C.byref(opts), None, 0,
+                                  out, C.byref(rep))
+    assert st == 1 and b"passes" in lib.ci_last_error()
+    opts.passes = 0
+    st = lib.serve_run_background(None, None, 0, C.byref(pol), coloc.RES["hbm"], 1.0, C.byref(opts), None, 0,
+                                  out, C.byref(rep))
+    assert st == 1 and b"serve_run: bad argument" in lib.ci_last_error()
+
 def test_admission_rejects_an_unknown_policy_first():
     """An unknown policy is an argument error whatever the request, also one
     that would not fit."""

@@ -222,6 +222,72 @@ def test_serve_admissions_replay_against_oracle(ctx, read_curves):
     assert any(starts[i + 1][0] < starts[i][1] for i in range(len(starts) - 1))
 
 
+
+def test_serve_under_a_background_stressor(ctx, dev):
+    """serve_run_background: an HBM triad stressor on every CU at half duty
+    runs for the whole serving run.  Every served result still equals the
+    oracle's, the stressor's own output is exact and it drained on its stop
+    flag, every admission is one the oracle's rule allows with the
+    stressor's load as background, and the rule binds: the fragile GEMV,
+    predicted 2x beside the background alone, never overlaps another
+    request (without the background it may run beside a GEMM)."""
+    import torch
+    profiles = {"gemv": {"sens": {"hbm": [1.0, 1.5, 2.0, 2.5, 3.0]}, "press": {"hbm": 0.2}, "occ": 0.6,
+                         "hbm_write_frac": 0.0, "press_hbm_read": 0.15},
+                "triad": {"sens": {"hbm": [1.0, 1.1, 1.2, 1.3, 1.4]}, "press": {"hbm": 1.0}, "occ": 0.6,
+                          "hbm_write_frac": 1 / 3, "press_hbm_read": 0.95},
+                "gemm": {"sens": {"lds": [1.0] * 5}, "press": {"mfma_bf16": 0.9}, "occ": 0.3,
+                         "hbm_write_frac": 0.5}}
+    bg = {"press": {"hbm": 0.5}, "occ": 0.25, "hbm_write_frac": 1 / 3}
+    n_s = 1 << 24
+    sb = synth.uniform_f32(synth.seed_for(4, synth.BUF_B), n_s)
+    sc = synth.uniform_f32(synth.seed_for(4, synth.BUF_C), n_s)
+    tsb = torch.from_numpy(np.require(sb, requirements=["C", "W"])).to(dev)
+    tsc = torch.from_numpy(np.require(sc, requirements=["C", "W"])).to(dev)
+    tsa = torch.empty_like(tsb)
+    reqs = _with_copies([dict(q, arrival_s=0.0005 * i) for i, q in enumerate(_trace())], dev)
+    slots, bound = 4, 1.6
+    print(f"serve_run_background: {len(reqs)} requests, HBM stressor n={n_s} duty 50", flush=True)
+    out, rep = ctx.serve_loaded(reqs, "hbm", 1.0, policy="sensitivity", bound=bound, hbm_budget=1 << 30,
+                                slots=slots, profiles=profiles, background=bg, src0=tsb, src1=tsc, dst=tsa,
+                                n=n_s, duty=50, deadline_ms=30000)
+    assert all(o["status"] == 0 for o in out)
+    for q, o in zip(reqs, out):
+        _oracle_check(q, o, q["out_copy"].cpu().numpy())
+    assert not rep.timed_out and rep.wg_reported == rep.grid and rep.work > 0
+    assert np.array_equal(tsa.cpu().numpy().view(np.uint32), oracle.triad_f32(sb, sc).view(np.uint32))
+    jobs = [_replay_job(profiles[q["kind"]]) for q in reqs]
+    bgo = _replay_job(dict(bg, sens={}))
+    order = [i for i, _ in sorted(enumerate(out), key=lambda kv: kv[1]["admit_s"])]
+    assert order == sorted(order)                       # FIFO, no bypass
+    for i, o in enumerate(out):
+        now = [j for j, oj in enumerate(out) if j != i and oj["admit_s"] <= o["admit_s"] < oj["end_s"]]
+        assert oracle.admit("sensitivity", [jobs[j] for j in now], jobs[i], 1 << 40, bound, slots,
+                            background=bgo), (i, now)
+    spans = [(o["admit_s"], o["end_s"]) for o in out]
+    for i, q in enumerate(reqs):
+        if q["kind"] != "gemv":
+            continue
+        for j in range(len(reqs)):
+            if j != i:
+                assert spans[i][1] <= spans[j][0] + 1e-9 or spans[j][1] <= spans[i][0] + 1e-9, (i, j)
+    assert oracle.admit("sensitivity", [jobs[2]], jobs[1], 1 << 40, bound, slots)   # GEMM beside GEMV
+    assert not oracle.admit("sensitivity", [jobs[2]], jobs[1], 1 << 40, bound, slots, background=bgo)
+    print(f"stressor during serving: {rep.achieved / 1e9:.0f} GB/s over {rep.window_ns / 1e6:.1f} ms")
+    # the context is free again: a plain serving run follows
+    assert ctx.serve(reqs[:3], policy="naive", hbm_budget=1 << 30, slots=2)[0]["status"] == 0
+
+
+def test_serve_under_a_background_stressor_rejects_fixed_passes(ctx, dev):
+    import torch
+    from paper_2501_16909_amd import coloc
+    t = torch.zeros(1 << 16, dtype=torch.float32, device=dev)
+    with pytest.raises(coloc.CiError) as ei:
+        ctx.serve_loaded(_trace()[:2], "hbm", 1.0, src0=t, src1=t, dst=torch.empty_like(t), n=t.numel(),
+                         passes=1)
+    assert ei.value.status == 1
+    assert ctx.serve(_trace()[:2], policy="naive", hbm_budget=1 << 30, slots=2)[1]["status"] == 0
+
 @pytest.mark.parametrize("policy", ["usher", "sensitivity"])
 def test_serve_admits_a_lone_request_the_rule_would_refuse_beside_others(ctx, policy):
     """A request that fills every wave slot (occupancy 1) and predicts 5x

@@ -601,6 +601,78 @@ def test_admission_lets_a_lone_request_in():
         oracle.admit("fifo", [], greedy, 10, 1.5, 4)
 
 
+
+def test_admission_with_a_background_load():
+    """A load present all along (a stressor held for the whole run) is one
+    more co-runner of every job and adds its occupancy to the occupancy sum,
+    but is not bounded itself.  Hand cases with dyadic loads on linear
+    curves (slowdown 1 + x on the first resource), and the identity that
+    ties it to the pinned rule: admitting beside a background X is admitting
+    beside X as a running job, less X's own bound."""
+    run = _job([2.0, 1.0], [0.25, 0.0], occ=0.25)
+    cand = _job([2.0, 1.0], [0.125, 0.0], occ=0.25)
+    bg = {"press": [0.5, 0.0], "occ": 0.5}
+    # cand beside run and bg: 1 + 0.25 + 0.5 = 1.75; run beside cand and bg: 1.625
+    assert oracle.predicted_slowdown_rw(cand, [run, bg]) == 1.75
+    assert oracle.predicted_slowdown_rw(run, [cand, bg]) == 1.625
+    assert oracle.admit("sensitivity", [run], cand, 10, 1.7, 4)               # 1.25 and 1.125
+    assert not oracle.admit("sensitivity", [run], cand, 10, 1.7, 4, background=bg)
+    assert oracle.admit("sensitivity", [run], cand, 10, 1.75, 4, background=bg)
+    # occupancy: 0.25 + 0.25 + 0.5 = 1 is not below 1; 0.375 leaves room
+    assert oracle.admit("usher", [run], cand, 10, 1.5, 4)
+    assert not oracle.admit("usher", [run], cand, 10, 1.5, 4, background=bg)
+    assert oracle.admit("usher", [run], cand, 10, 1.5, 4, background=dict(bg, occ=0.375))
+    # the background's own slowdown is never bounded: a background that a
+    # running job would slow 100x changes nothing
+    assert oracle.admit("sensitivity", [run], cand, 10, 1.75, 4,
+                        background=dict(bg, sens=[[100.0] * 5, [100.0] * 5]))
+    # memory, slots and the idle-device rule are untouched
+    assert oracle.admit("sensitivity", [], cand, 10, 1.01, 4, background={"press": [1.0, 1.0], "occ": 1.0})
+    assert not oracle.admit("naive", [], _job([1, 1], [0, 0], nbytes=20), 10, 1.5, 4, background=bg)
+    assert not oracle.admit("naive", [run] * 4, cand, 10, 1.5, 4, background=bg)
+    assert oracle.admit("naive", [run], cand, 10, 1.0, 4, background={"press": [1.0, 1.0], "occ": 2.0})
+    rng = np.random.default_rng(21)
+    for _ in range(400):
+        kinds = [_job([1.0 + 3.0 * rng.random(), 1.0 + rng.random()], [rng.random(), rng.random()],
+                      occ=0.5 * rng.random()) for _ in range(4)]
+        running = [kinds[int(i)] for i in rng.integers(0, 4, int(rng.integers(1, 4)))]
+        cand = kinds[int(rng.integers(0, 4))]
+        x = kinds[int(rng.integers(0, 4))]
+        bound = 1.0 + 3.0 * rng.random()
+        zero = {"press": [0.0, 0.0], "occ": 0.0}
+        for pol in ("naive", "usher", "sensitivity"):
+            plain = oracle.admit(pol, running, cand, 10, bound, 8)
+            assert oracle.admit(pol, running, cand, 10, bound, 8, background=zero) == plain
+            beside_x = oracle.admit(pol, running + [x], cand, 10, bound, 8)
+            with_bg = oracle.admit(pol, running, cand, 10, bound, 8, background=x)
+            if pol == "sensitivity":
+                own = oracle.predicted_slowdown_rw(x, running + [cand])
+                assert beside_x == (with_bg and own <= bound)
+            else:
+                assert beside_x == with_bg
+
+
+def test_simulator_with_a_background_load():
+    """A background that alone predicts more than the bound for every
+    request serialises sensitivity admission (a lone request is still
+    admitted) and, with slowed service, stretches a lone request by its
+    predicted slowdown beside the background alone."""
+    frag = _job([3.0, 1.0], [0.0, 0.0], nbytes=1, occ=0.25)
+    bg = {"press": [0.5, 0.0], "occ": 0.5}           # 1 + 2 * 0.5 = 2x for each request
+    out = oracle.simulate_admission([0.0, 0.5], [frag, frag], [2.0, 2.0], "sensitivity", 1024, 1.5, 4)
+    assert [(o["admit"], o["end"]) for o in out] == [(0.0, 2.0), (0.5, 2.5)]   # zero press: together
+    out = oracle.simulate_admission([0.0, 0.5], [frag, frag], [2.0, 2.0], "sensitivity", 1024, 1.5, 4,
+                                    background=bg)
+    assert [(o["admit"], o["end"]) for o in out] == [(0.0, 2.0), (2.0, 4.0)]
+    out = oracle.simulate_admission([0.0, 0.5], [frag, frag], [2.0, 2.0], "sensitivity", 1024, 1.5, 4,
+                                    slowed=True, background=bg)
+    assert [(o["admit"], o["end"]) for o in out] == [(0.0, 4.0), (4.0, 8.0)]
+    assert out[1]["corunners"] == ()
+    # occupancy: 0.25 + 0.25 + 0.5 reaches 1, so the occupancy rule serialises too
+    out = oracle.simulate_admission([0.0, 0.5], [frag, frag], [2.0, 2.0], "usher", 1024, 1.5, 4,
+                                    background=bg)
+    assert [(o["admit"], o["end"]) for o in out] == [(0.0, 2.0), (2.0, 4.0)]
+
 # ------------------------------------------------ discrete-event serving model
 def _sim_jobs(n, rng, nbytes=1000):
     kinds = [_job([1.0 + 2.0 * rng.random(), 1.0], [rng.random(), 0.0], nbytes=nbytes, occ=0.4)
