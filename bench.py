@@ -1096,6 +1096,7 @@ def run_serve_background(args):
                 t0 = time.perf_counter()
                 rep = None
                 if loaded:
+                    q0 = ctx.queue_stats()
                     res, rep = ctx.serve_loaded(reqs, "hbm", 1.0, ws=ws, policy=policy, bound=args.bound,
                                                 hbm_budget=budget, slots=slots, profiles=profiles, background=bg,
                                                 duty=args.duty, deadline_ms=int(1000 * (60 + 20 * args.seconds)),
@@ -1109,6 +1110,8 @@ def run_serve_background(args):
                 run["results_equal_isolated"] = all(r["checksum_bits"] == i["checksum_bits"]
                                                     for r, i in zip(res, iso))
                 if rep is not None:
+                    q1 = ctx.queue_stats()
+                    run["slot_queue_check"] = {k: q1[k] - q0[k] for k in q1}
                     run["stressor_gb_s"] = round(rep.achieved / 1e9, 1)
                     run["stressor_window_s"] = round(rep.window_ns * 1e-9, 3)
                 run["wall_s"] = round(wall, 2)

@@ -166,7 +166,8 @@ ci_status_t ci_probe_placement(ci_ctx_t* ctx, const uint32_t* mask, uint32_t nwg
  * than 5 %, a queue is replaced (the stressor's and the victim's in turn, at
  * most 7 times).  A victim queue is first qualified: measured alone against
  * two fresh queues with the same mask, the fastest kept (a queue can also be
- * slow on its own).
+ * slow on its own).  serve_run_background checks each slot stream against
+ * its stressor's queue the same way (with a probe triad as the victim).
  *   *checks: pairs checked; *replaced: queues replaced (by either step);
  *   *unresolved: pairs
  *   still above 5 % after the last replacement (measured as placed). */
@@ -836,7 +837,14 @@ ci_status_t ci_admit(const ci_policy_t* p, const int* running_kinds, int nrun, i
  * CU fraction `intensity` with `opts` and the caller-owned workspace ws
  * (ws_bytes >= ci_workspace_size), as stressor_launch does; opts->passes
  * must be 0 (the stressor runs until stopped) and opts->deadline_ms should
- * exceed the run.  The trace's clock starts once the stressor is running;
+ * exceed the run.  Before the stressor starts, each slot stream is checked
+ * against the stressor's queue (a probe triad in the arena, alone and
+ * beside an idle kernel on the stressor's CUs and queue; a slot slowed by
+ * more than 5 % gets a new stream, and if one stays slowed the stressor's
+ * queue is replaced once; counted in ci_queue_stats), since two hardware
+ * queues can slow each other with nothing else shared; the check is skipped
+ * when the arena holds fewer than 12 MiB or ws has no room for the idle
+ * kernel.  The trace's clock starts once the stressor is running;
  * requests are served exactly as by serve_run; after the last one retires
  * the stressor is stopped and its report written to *rep (caller-owned).
  * Admission sees the stressor only through p->background.  A stressor that

@@ -291,6 +291,117 @@ struct Background {
   ci_stressor_report_t* rep;
 };
 
+// Queue check of the slot streams against the background stressor's queue.
+// Two hardware queues can slow each other's kernels although they share no
+// CU and no traffic (the pairwise effect the measurement calls check before
+// colocating, see check_queue_pair): before the stressor starts, each slot
+// runs a probe triad alone and beside an idle kernel on the stressor's CUs
+// and queue, in counterbalanced order; a slot slowed by more than
+// kSlotQueueTol gets a new stream, kSlotQueueAttempts times at most.  The
+// new stream carries a mask of every CU: the runtime deals plain streams
+// over a small pool of hardware queues (a new plain stream may land on the
+// very queue it replaces), but gives each CU-masked stream a queue of its
+// own, created while the old one exists.  If a slot stays slowed, the
+// stressor's queue is replaced once and every slot checked again.  The
+// context's queue counters (ci_queue_stats) count the checks.
+constexpr double kSlotQueueTol = 1.05;
+constexpr int kSlotQueueAttempts = 6;
+constexpr int kSlotQueuePairs = 6;
+constexpr uint64_t kProbeMaxElems = 1ull << 24;
+constexpr uint64_t kProbeMinElems = 1ull << 20;
+
+ci_status_t probe_ns(ci_ctx* ctx, const ci_victim_desc_t& d, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                     double* ns) {
+  const ci_status_t st = launch_victim(ctx, &d, s, e0, e1);
+  if (st != CI_OK) return st;
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.0f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  *ns = (double)ms * 1e6;
+  return CI_OK;
+}
+
+ci_status_t check_slot_queues(ci_ctx* ctx, const Background& bg, std::vector<hipStream_t>& streams,
+                              uint8_t* arena, uint64_t arena_bytes, hipEvent_t e0, hipEvent_t e1) {
+  const int k = cus_for(ctx, bg.intensity);
+  uint64_t n = std::min(kProbeMaxElems, arena_bytes / 12 / 64 * 64);
+  if (k == 0 || n < kProbeMinElems) return CI_OK;  // nothing to pair, or no room for a probe
+  ci_stressor_opts_t o{};
+  o.threads = 256;  // one 256-thread work-group per stressed CU, 1 KiB of LDS, sleeping
+  o.wg_per_cu = 1;
+  o.knob = 1;
+  o.deadline_ms = 1000;
+  size_t need = 0;
+  ci_status_t st = ci_workspace_size(CI_RES_OCCUPANCY, bg.intensity, &o, &need);
+  if (st != CI_OK) return st;
+  if (!bg.ws || bg.ws_bytes < need) return CI_OK;  // no room for the idle kernel
+  float* b = (float*)arena;
+  float* c = b + n;
+  float* a = c + n;
+  HIPCHK(launch_fill_uniform(b, n, 0x5EED0001ull, streams[0]));
+  HIPCHK(launch_fill_uniform(c, n, 0x5EED0002ull, streams[0]));
+  HIPCHK(hipStreamSynchronize(streams[0]));
+  ci_victim_desc_t d{};
+  d.kind = CI_VICTIM_TRIAD_F32;
+  d.dtype = CI_DT_F32;
+  d.n = n;
+  d.passes = 1;
+  d.copies = 1;
+  d.scale_a = d.scale_b = 1.0f;
+  d.a = b;
+  d.b = c;
+  d.out = a;
+  uint32_t mask[8], all[8];
+  mask_for(ctx, k, 0, mask);
+  mask_for(ctx, cus_for(ctx, 1.0), 0, all);
+  for (int round = 0; round < 2; ++round) {
+    bool all_ok = true;
+    for (size_t s = 0; s < streams.size(); ++s) {
+      ++ctx->queue_checks;
+      for (int attempt = 0;; ++attempt) {
+        double t = 0.0;
+        for (int w = 0; w < 2; ++w)
+          if ((st = probe_ns(ctx, d, streams[s], e0, e1, &t)) != CI_OK) return st;
+        std::vector<double> ta, ti;
+        for (int r = 0; r < kSlotQueuePairs; ++r) {
+          const bool idle_first = r & 1;
+          double t_alone = 0.0, t_idle = 0.0;
+          if (!idle_first && (st = probe_ns(ctx, d, streams[s], e0, e1, &t_alone)) != CI_OK) return st;
+          ci_stressor_t* h = nullptr;
+          if ((st = stressor_launch(ctx, CI_RES_OCCUPANCY, bg.intensity, streams[s], &o, bg.ws, bg.ws_bytes,
+                                    &h)) != CI_OK)
+            return st;
+          const ci_status_t vst = probe_ns(ctx, d, streams[s], e0, e1, &t_idle);
+          st = stressor_stop(h, nullptr);
+          if (vst != CI_OK) return vst;
+          if (st != CI_OK) return st;
+          if (idle_first && (st = probe_ns(ctx, d, streams[s], e0, e1, &t_alone)) != CI_OK) return st;
+          ta.push_back(t_alone);
+          ti.push_back(t_idle);
+        }
+        if (median(ti) <= kSlotQueueTol * median(ta)) break;
+        if (attempt + 1 >= kSlotQueueAttempts) {
+          all_ok = false;
+          if (round == 1) ++ctx->queue_unresolved;
+          break;
+        }
+        ++ctx->queue_replaced;
+        hipStream_t ns = nullptr;
+        HIPCHK(hipExtStreamCreateWithCUMask(&ns, 8, all));
+        (void)hipStreamSynchronize(streams[s]);
+        (void)hipStreamDestroy(streams[s]);
+        streams[s] = ns;
+      }
+    }
+    if (all_ok) break;
+    if (round == 0) {
+      ++ctx->queue_replaced;
+      if (!replace_masked_stream(ctx, mask)) return set_err(CI_ERR_HIP, "hipExtStreamCreateWithCUMask failed");
+    }
+  }
+  return CI_OK;
+}
+
 ci_status_t serve_impl(ci_ctx_t* ctx, const ci_request_t* trace, int n, const ci_policy_t* p,
                        const Background* bg, ci_served_t* out) {
   if (!ctx || !p || n < 0 || (n && (!trace || !out)))
@@ -348,6 +459,8 @@ ci_status_t serve_impl(ci_ctx_t* ctx, const ci_request_t* trace, int n, const ci
   // below allocates or frees device memory while it runs) and before the
   // trace's clock.
   ci_stressor_t* bg_h = nullptr;
+  if (bg && st == CI_OK) fail(check_slot_queues(ctx, *bg, streams, arena_base, p->hbm_budget, slot[0].ev0,
+                                                slot[0].ev1));
   if (bg && st == CI_OK) {
     const ci_status_t ls = stressor_launch(ctx, bg->r, bg->intensity, streams[0], bg->opts, bg->ws,
                                            bg->ws_bytes, &bg_h);

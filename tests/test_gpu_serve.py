@@ -248,6 +248,7 @@ def test_serve_under_a_background_stressor(ctx, dev):
     reqs = _with_copies([dict(q, arrival_s=0.0005 * i) for i, q in enumerate(_trace())], dev)
     slots, bound = 4, 1.6
     print(f"serve_run_background: {len(reqs)} requests, HBM stressor n={n_s} duty 50", flush=True)
+    q0 = ctx.queue_stats()
     out, rep = ctx.serve_loaded(reqs, "hbm", 1.0, policy="sensitivity", bound=bound, hbm_budget=1 << 30,
                                 slots=slots, profiles=profiles, background=bg, src0=tsb, src1=tsc, dst=tsa,
                                 n=n_s, duty=50, deadline_ms=30000)
@@ -255,6 +256,8 @@ def test_serve_under_a_background_stressor(ctx, dev):
     for q, o in zip(reqs, out):
         _oracle_check(q, o, q["out_copy"].cpu().numpy())
     assert not rep.timed_out and rep.wg_reported == rep.grid and rep.work > 0
+    q1 = ctx.queue_stats()
+    assert q1["checks"] - q0["checks"] >= slots          # every slot stream checked against its queue
     assert np.array_equal(tsa.cpu().numpy().view(np.uint32), oracle.triad_f32(sb, sc).view(np.uint32))
     jobs = [_replay_job(profiles[q["kind"]]) for q in reqs]
     bgo = _replay_job(dict(bg, sens={}))
