@@ -355,12 +355,19 @@ def _cpu_serving_leg(serve):
             if p.get("sens_hbm_read"):
                 job["sens_hbm_read"] = [f32(v) for v in p["sens_hbm_read"]]
             jobs.append(job)
+        bg = None
+        if run.get("background"):
+            b = run["background"]
+            bg = {"press": [f32(b["press"].get(r, 0.0)) for r in names], "occ": f32(b["occ"]),
+                  "hbm_write_frac": f32(b.get("hbm_write_frac", 1.0)),
+                  "press_hbm_read": f32(b.get("press_hbm_read", 0.0))}
         t0 = time.perf_counter()
         sim = oracle.simulate_admission([q["arrival_s"] for q in reqs], jobs, run["iso_s"], run["policy"],
-                                        run["budget"], run["bound"], run["slots"], slowed=True)
+                                        run["budget"], run["bound"], run["slots"], slowed=True, background=bg)
         dt = time.perf_counter() - t0
         lat = np.array([o["end"] - q["arrival_s"] for o, q in zip(sim, reqs)])
-        out.append({"rate_per_s": run["rate"], "policy": run["policy"], "requests": len(reqs),
+        out.append({"rate_per_s": run["rate"], "policy": run["policy"], "background": bg is not None,
+                    "requests": len(reqs),
                     "model_latency_ms_p50": round(float(np.percentile(lat, 50)) * 1e3, 3),
                     "model_latency_ms_p99": round(float(np.percentile(lat, 99)) * 1e3, 3),
                     "gpu_latency_ms_p50": run["latency_ms_p50"], "gpu_latency_ms_p99": run["latency_ms_p99"],
@@ -465,6 +472,28 @@ def precision_block(ctx, dev, keep_host):
     return summary, host
 
 
+def background_load(ctx, dev, duty):
+    """An HBM triad stressor for serve_run_background: its operands (three
+    2^28-element FP32 arrays, 3 GiB, far beyond the Infinity Cache), a
+    workspace, and its load as the admission rules see it -- its standalone
+    rate at this duty over its full rate, with the triad's write share and
+    one 512-thread work-group per CU (8 of 32 wave slots)."""
+    import torch
+    import synth
+    n = 1 << 28
+    hb = torch.empty(n, dtype=torch.float32, device=dev)
+    hc, ha = torch.empty_like(hb), torch.empty_like(hb)
+    synth.device_fill_uniform_f32(hb.data_ptr(), n, synth.seed_for(4, synth.BUF_B))
+    synth.device_fill_uniform_f32(hc.data_ptr(), n, synth.seed_for(4, synth.BUF_C))
+    torch.cuda.synchronize()
+    ops = dict(src0=hb, src1=hc, dst=ha, n=n)
+    ws = torch.empty(WS_BYTES, dtype=torch.uint8, device=dev)
+    full = ctx.stressor("hbm", 1.0, ws=ws, passes=1, **ops).stop()
+    part = ctx.stressor("hbm", 1.0, ws=ws, passes=1, duty=duty, **ops).stop()
+    load = min(1.0, (part.units / part.kernel_ns) / (full.units / full.kernel_ns))
+    return ops, ws, {"press": {"hbm": load}, "occ": 0.25, "hbm_write_frac": HBM_WRITE_FRAC["triad"]}
+
+
 def serving_block(ctx, args, keep_host):
     """The serving loop on the serving configuration's traffic: Poisson arrivals of BF16
     GEMM / BF16 GEMV / FP32 triad requests, naive against sensitivity-aware
@@ -472,7 +501,10 @@ def serving_block(ctx, args, keep_host):
     pricing), 60 s at 200 requests/s and 10 s at 1000/s.  Every request is
     also served alone (one slot, in arrival order) for its isolated service
     time and result: slowdowns are over all requests, and every result must
-    equal its isolated one bit for bit."""
+    equal its isolated one bit for bit.  The 1000/s trace is also served on
+    a loaded device: an HBM triad stressor on every CU at 25 % duty held for
+    the whole run (serve_run_background), its load in the admission rules."""
+    from paper_2501_16909_amd import coloc
     profiles = library_profiles(serve_profiles(ctx, args, axis="duty"),
                                 serve_profiles(ctx, args, axis="duty", hbm_mix="read", res=("hbm",)))
     budget, slots = 32 << 30, 4
@@ -509,6 +541,38 @@ def serving_block(ctx, args, keep_host):
                                      "footprints": [serve_footprint(q) for q in reqs], "budget": budget,
                                      "bound": args.bound, "slots": slots,
                                      "latency_ms_p50": run["latency_ms_p50"], "latency_ms_p99": run["latency_ms_p99"]})
+        if lam != 1000.0:
+            continue
+        duty = 25
+        bg_ops, bg_ws, bg = background_load(ctx, ctx.device, duty)
+        for policy in ("naive", "sensitivity"):
+            q0 = ctx.queue_stats()
+            t0 = time.perf_counter()
+            res, rep = ctx.serve_loaded(reqs, "hbm", 1.0, ws=bg_ws, policy=policy, bound=args.bound,
+                                        hbm_budget=budget, slots=slots, profiles=profiles, background=bg,
+                                        duty=duty, deadline_ms=int(1000 * (60 + 20 * seconds)), **bg_ops)
+            wall = time.perf_counter() - t0
+            q1 = ctx.queue_stats()
+            run = {"rate_per_s": lam, "seconds": seconds, "policy": policy, "requests": len(reqs)}
+            run.update(_serving_stats(res, reqs, iso_ns, args.bound))
+            run.update({"slowdown_over": "every request (service in the mix / service alone on an idle device)",
+                        "results_equal_isolated": all(r["checksum_bits"] == i["checksum_bits"]
+                                                      for r, i in zip(res, iso)),
+                        "background": {"stressor": "hbm triad, every CU", "duty_pct": duty,
+                                       "load": round(bg["press"]["hbm"], 4),
+                                       "predicted_slowdown_beside_it_alone":
+                                           {k: round(coloc.predict_slowdown(profiles, k, [bg]), 3) for k in profiles},
+                                       "stressor_gb_s": round(rep.achieved / 1e9, 1),
+                                       "slot_queue_check": {k: q1[k] - q0[k] for k in q1}},
+                        "wall_s": round(wall, 1)})
+            summary["runs"].append(run)
+            log(f"serve {lam}/s {policy} under the background: {run}")
+            if keep_host:
+                host["runs"].append({"rate": lam, "policy": policy, "reqs": reqs, "iso_s": list(iso_ns * 1e-9),
+                                     "footprints": [serve_footprint(q) for q in reqs], "budget": budget,
+                                     "bound": args.bound, "slots": slots, "background": bg,
+                                     "latency_ms_p50": run["latency_ms_p50"], "latency_ms_p99": run["latency_ms_p99"]})
+        del bg_ops, bg_ws
     summary["profiles"] = profiles
     return summary, host
 
@@ -1065,13 +1129,8 @@ def run_serve_background(args):
     dev = ctx.device
     profiles = library_profiles(serve_profiles(ctx, args, axis="duty"),
                                 serve_profiles(ctx, args, axis="duty", hbm_mix="read", res=("hbm",)))
-    ops = stressor_operands(dev)["hbm"]
-    ws = torch.empty(WS_BYTES, dtype=torch.uint8, device=dev)
-    # the background's load: its standalone rate at this duty over the full rate
-    full = ctx.stressor("hbm", 1.0, ws=ws, passes=1, **ops).stop()
-    part = ctx.stressor("hbm", 1.0, ws=ws, passes=1, duty=args.duty, **ops).stop()
-    press = min(1.0, (part.units / part.kernel_ns) / (full.units / full.kernel_ns))
-    bg = {"press": {"hbm": press}, "occ": 0.25, "hbm_write_frac": HBM_WRITE_FRAC["triad"]}
+    ops, ws, bg = background_load(ctx, dev, args.duty)
+    press = bg["press"]["hbm"]
     alone_bg = {k: round(coloc.predict_slowdown(profiles, k, [bg]), 3) for k in profiles}
     log(f"background: HBM triad stressor, duty {args.duty} %: load {press:.3f} of the full rate; "
         f"predicted slowdown beside it alone: {alone_bg}")

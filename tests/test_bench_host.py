@@ -164,3 +164,21 @@ def test_reference_summary_rates(tmp_path):
     assert add[5] == f"{12 * n / 2 / 2_400_000:.0f}"
     fill = [v for k, v in cells.items() if "Fill" in k][0]
     assert fill[5] == f"{4 * n / 2 / 700_000:.0f}"
+
+
+def test_cpu_serving_leg_replays_with_a_background_load():
+    """The CPU leg's discrete-event replay: two requests predicted 1x beside
+    each other overlap; a background load that alone predicts 2x for each
+    (above the 1.5 bound) serialises them and stretches each by 2x."""
+    import bench
+    prof = {"triad": {"sens": {"hbm": [1.0, 1.5, 2.0, 2.5, 3.0]}, "press": {"hbm": 0.0}, "occ": 0.25,
+                      "hbm_write_frac": 1 / 3}}
+    base = {"rate": 1.0, "policy": "sensitivity", "iso_s": [2.0, 2.0], "footprints": [1, 1], "budget": 1024,
+            "bound": 1.5, "slots": 4, "latency_ms_p50": 0.0, "latency_ms_p99": 0.0,
+            "reqs": [{"arrival_s": 0.0, "kind": "triad"}, {"arrival_s": 0.5, "kind": "triad"}]}
+    loaded = dict(base, background={"press": {"hbm": 0.5}, "occ": 0.25, "hbm_write_frac": 1 / 3})
+    plain, bg = bench._cpu_serving_leg({"profiles": prof, "runs": [base, loaded]})
+    assert not plain["background"] and bg["background"]
+    assert plain["model_colocated_fraction"] == 0.5 and bg["model_colocated_fraction"] == 0.0
+    assert plain["model_latency_ms_p50"] == 2000.0          # both take 2 s, side by side
+    assert bg["model_latency_ms_p50"] == 5750.0             # 4 s, then 3.5 s waiting + 4 s
