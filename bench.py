@@ -337,7 +337,11 @@ def _cpu_precision_leg(prec):
 
 def _cpu_serving_leg(serve):
     """The admission rule in the oracle's discrete-event model, fed the
-    isolated service times the GPU measured, next to the GPU's latencies."""
+    isolated service times the GPU measured, next to the GPU's latencies.
+    Two service times per request: its kernel alone (model_kernel_*), and
+    its whole stay in the loop when served alone (model_*: input
+    generation, kernel, checksum and retirement), which is what the GPU's
+    latencies include."""
     import oracle
     out = []
     for run in serve["runs"]:
@@ -362,14 +366,20 @@ def _cpu_serving_leg(serve):
                   "hbm_write_frac": f32(b.get("hbm_write_frac", 1.0)),
                   "press_hbm_read": f32(b.get("press_hbm_read", 0.0))}
         t0 = time.perf_counter()
-        sim = oracle.simulate_admission([q["arrival_s"] for q in reqs], jobs, run["iso_s"], run["policy"],
+        arrivals = [q["arrival_s"] for q in reqs]
+        sim_k = oracle.simulate_admission(arrivals, jobs, run["iso_s"], run["policy"], run["budget"],
+                                          run["bound"], run["slots"], slowed=True, background=bg)
+        sim = oracle.simulate_admission(arrivals, jobs, run.get("iso_span_s", run["iso_s"]), run["policy"],
                                         run["budget"], run["bound"], run["slots"], slowed=True, background=bg)
         dt = time.perf_counter() - t0
-        lat = np.array([o["end"] - q["arrival_s"] for o, q in zip(sim, reqs)])
+        lat_k = np.array([o["end"] - a for o, a in zip(sim_k, arrivals)])
+        lat = np.array([o["end"] - a for o, a in zip(sim, arrivals)])
         out.append({"rate_per_s": run["rate"], "policy": run["policy"], "background": bg is not None,
                     "requests": len(reqs),
                     "model_latency_ms_p50": round(float(np.percentile(lat, 50)) * 1e3, 3),
                     "model_latency_ms_p99": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                    "model_kernel_latency_ms_p50": round(float(np.percentile(lat_k, 50)) * 1e3, 3),
+                    "model_kernel_latency_ms_p99": round(float(np.percentile(lat_k, 99)) * 1e3, 3),
                     "gpu_latency_ms_p50": run["latency_ms_p50"], "gpu_latency_ms_p99": run["latency_ms_p99"],
                     "model_colocated_fraction": round(float(np.mean([bool(o["corunners"]) for o in sim])), 3),
                     "oracle_seconds": round(dt, 2)})
@@ -518,6 +528,7 @@ def serving_block(ctx, args, keep_host):
         reqs = serve_trace(lam, seconds, 31337 + int(lam))
         iso = ctx.serve([dict(r, arrival_s=0.0) for r in reqs], policy="naive", hbm_budget=budget, slots=1)
         iso_ns = np.array([o["service_ns"] for o in iso])
+        iso_span = [o["end_s"] - o["admit_s"] for o in iso]   # inputs, kernel, checksum, retirement
         for policy in ("naive", "sensitivity"):
             t0 = time.perf_counter()
             res = ctx.serve(reqs, policy=policy, bound=args.bound, hbm_budget=budget, slots=slots,
@@ -537,7 +548,7 @@ def serving_block(ctx, args, keep_host):
             summary["runs"].append(run)
             log(f"serve {lam}/s {policy}: {run}")
             if keep_host:
-                host["runs"].append({"rate": lam, "policy": policy, "reqs": reqs, "iso_s": list(iso_ns * 1e-9),
+                host["runs"].append({"rate": lam, "policy": policy, "reqs": reqs, "iso_s": list(iso_ns * 1e-9), "iso_span_s": iso_span,
                                      "footprints": [serve_footprint(q) for q in reqs], "budget": budget,
                                      "bound": args.bound, "slots": slots,
                                      "latency_ms_p50": run["latency_ms_p50"], "latency_ms_p99": run["latency_ms_p99"]})
@@ -568,7 +579,7 @@ def serving_block(ctx, args, keep_host):
             summary["runs"].append(run)
             log(f"serve {lam}/s {policy} under the background: {run}")
             if keep_host:
-                host["runs"].append({"rate": lam, "policy": policy, "reqs": reqs, "iso_s": list(iso_ns * 1e-9),
+                host["runs"].append({"rate": lam, "policy": policy, "reqs": reqs, "iso_s": list(iso_ns * 1e-9), "iso_span_s": iso_span,
                                      "footprints": [serve_footprint(q) for q in reqs], "budget": budget,
                                      "bound": args.bound, "slots": slots, "background": bg,
                                      "latency_ms_p50": run["latency_ms_p50"], "latency_ms_p99": run["latency_ms_p99"]})

@@ -182,3 +182,16 @@ def test_cpu_serving_leg_replays_with_a_background_load():
     assert plain["model_colocated_fraction"] == 0.5 and bg["model_colocated_fraction"] == 0.0
     assert plain["model_latency_ms_p50"] == 2000.0          # both take 2 s, side by side
     assert bg["model_latency_ms_p50"] == 5750.0             # 4 s, then 3.5 s waiting + 4 s
+
+
+def test_cpu_serving_leg_models_whole_stays_and_kernels():
+    """With each request's whole stay when served alone (iso_span_s), the
+    model's latencies use it; the kernel-only model uses iso_s."""
+    import bench
+    prof = {"triad": {"sens": {"hbm": [1.0] * 5}, "press": {"hbm": 0.0}, "occ": 0.25}}
+    run = {"rate": 1.0, "policy": "naive", "iso_s": [2.0, 2.0], "iso_span_s": [3.0, 3.0], "footprints": [1, 1],
+           "budget": 1024, "bound": 1.5, "slots": 1, "latency_ms_p50": 0.0, "latency_ms_p99": 0.0,
+           "reqs": [{"arrival_s": 0.0, "kind": "triad"}, {"arrival_s": 0.0, "kind": "triad"}]}
+    (r,) = bench._cpu_serving_leg({"profiles": prof, "runs": [run]})
+    assert (r["model_kernel_latency_ms_p50"], r["model_kernel_latency_ms_p99"]) == (3000.0, 3980.0)
+    assert (r["model_latency_ms_p50"], r["model_latency_ms_p99"]) == (4500.0, 5970.0)
