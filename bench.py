@@ -1066,7 +1066,7 @@ def run_serve(args):
         profiles = median_profiles([serve_profiles(ctx, args, axis=args.profile_axis)
                                     for _ in range(max(1, args.profile_runs))])
         log("profiles: " + json.dumps(profiles))
-    out = {"metric": "serving latency p50/p99 and throughput, naive vs sensitivity-aware admission",
+    out = {"metric": "serving latency p50/p99 and throughput, naive vs occupancy-based vs sensitivity-aware admission",
            "config": {"workload": "Poisson arrivals, 1/3 each BF16 GEMM n~logU[512,8192], BF16 GEMV "
                                   "n~logU[4096,16384], FP32 triad N~logU[2^20,2^28]",
                       "seconds": args.seconds, "slots": 4, "hbm_budget_gib": 32,
@@ -1075,7 +1075,7 @@ def run_serve(args):
     iso_cache = {}
     for lam in args.rates:
         reqs = serve_trace(lam, args.seconds, 31337 + int(lam))
-        for policy in (["naive", "sensitivity"] if profiles else ["naive"]):
+        for policy in (["naive", "usher", "sensitivity"] if profiles else ["naive"]):
             t0 = time.perf_counter()
             res = ctx.serve(reqs, policy=policy, bound=args.bound, hbm_budget=32 << 30, slots=4,
                             profiles=profiles)
@@ -1128,8 +1128,8 @@ def _serving_stats(res, reqs, iso_ns, bound):
 def run_serve_background(args):
     """Serving on a loaded device: an HBM triad stressor on every CU at duty
     --duty runs through each serving run (serve_run_background), so that the
-    admission rule has to decide against a constant background load; naive
-    against sensitivity-aware admission (duty-axis profiles with
+    admission rule has to decide against a constant background load; naive,
+    occupancy-based (usher) and sensitivity-aware admission (duty-axis profiles with
     read/write-aware HBM pricing, the stressor's own measured load as the
     rule's background), and the same traces without the stressor.
     Slowdowns are over every request, against the request served alone on
@@ -1147,7 +1147,7 @@ def run_serve_background(args):
         f"predicted slowdown beside it alone: {alone_bg}")
     budget, slots = 32 << 30, 4
     out = {"metric": "serving latency p50/p99, throughput and slowdown under a background HBM stressor, "
-                     "naive vs sensitivity-aware admission",
+                     "naive vs occupancy-based vs sensitivity-aware admission",
            "config": {"workload": "Poisson arrivals, 1/3 each BF16 GEMM n~logU[512,8192], BF16 GEMV "
                                   "n~logU[4096,16384], FP32 triad N~logU[2^20,2^28]",
                       "seconds": args.seconds, "slots": slots, "hbm_budget_gib": budget >> 30,
@@ -1161,7 +1161,7 @@ def run_serve_background(args):
         iso = ctx.serve([dict(r, arrival_s=0.0) for r in reqs], policy="naive", hbm_budget=budget, slots=1)
         iso_ns = np.array([o["service_ns"] for o in iso])
         for loaded in (False, True):
-            for policy in ("naive", "sensitivity"):
+            for policy in ("naive", "usher", "sensitivity"):
                 log(f"serve {lam}/s {policy}, background {'on' if loaded else 'off'}: {len(reqs)} requests")
                 t0 = time.perf_counter()
                 rep = None
