@@ -281,6 +281,33 @@ def test_serve_under_a_background_stressor(ctx, dev):
     assert ctx.serve(reqs[:3], policy="naive", hbm_budget=1 << 30, slots=2)[0]["status"] == 0
 
 
+
+def test_serve_under_a_background_stressor_occupancy_rule(ctx, dev):
+    """The occupancy rule with a background load: requests of occupancy 0.3
+    run three at a time on their own (0.9 < 1) but one at a time beside a
+    stressor of occupancy 0.5 (0.5 + 0.3 + 0.3 >= 1); every result still
+    equals the oracle's."""
+    import torch
+    prof = {"sens": {"hbm": [1.0] * 5}, "press": {"hbm": 0.1}, "occ": 0.3}
+    profiles = {"triad": prof, "gemv": prof, "gemm": prof}
+    n_s = 1 << 22
+    tsb = torch.zeros(n_s, dtype=torch.float32, device=dev)
+    tsc, tsa = torch.zeros_like(tsb), torch.empty_like(tsb)
+    reqs = _with_copies([dict(q, arrival_s=0.0) for q in _trace()[:6]], dev)
+    print(f"serve_run_background, occupancy rule: {len(reqs)} requests", flush=True)
+    out, rep = ctx.serve_loaded(reqs, "hbm", 1.0, policy="usher", hbm_budget=1 << 30, slots=4,
+                                profiles=profiles, background={"press": {"hbm": 0.5}, "occ": 0.5},
+                                src0=tsb, src1=tsc, dst=tsa, n=n_s, deadline_ms=30000)
+    assert all(o["status"] == 0 for o in out) and not rep.timed_out
+    for q, o in zip(reqs, out):
+        _oracle_check(q, o, q["out_copy"].cpu().numpy())
+    spans = sorted((o["admit_s"], o["end_s"]) for o in out)
+    assert all(spans[i + 1][0] >= spans[i][1] - 1e-6 for i in range(len(spans) - 1))
+    assert np.array_equal(tsa.cpu().numpy(), np.zeros(n_s, np.float32))   # 0 + 3 * 0
+    alone = ctx.serve([dict(q) for q in reqs], policy="usher", hbm_budget=1 << 30, slots=4, profiles=profiles)
+    spans = sorted((o["admit_s"], o["end_s"]) for o in alone)
+    assert any(spans[i + 1][0] < spans[i][1] for i in range(len(spans) - 1))
+
 def test_serve_under_a_background_stressor_rejects_fixed_passes(ctx, dev):
     import torch
     from paper_2501_16909_amd import coloc
