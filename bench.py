@@ -482,12 +482,14 @@ def precision_block(ctx, dev, keep_host):
     return summary, host
 
 
-def background_load(ctx, dev, duty):
-    """An HBM triad stressor for serve_run_background: its operands (three
-    2^28-element FP32 arrays, 3 GiB, far beyond the Infinity Cache), a
-    workspace, and its load as the admission rules see it -- its standalone
-    rate at this duty over its full rate, with the triad's write share and
-    one 512-thread work-group per CU (8 of 32 wave slots)."""
+def background_load(ctx, dev, duty, mix="triad"):
+    """An HBM stressor for serve_run_background, in the triad or the
+    read-only mix: its operands (2^28-element FP32 arrays, 1 GiB each, far
+    beyond the Infinity Cache), a workspace, and its load as the admission
+    rules see it -- its standalone byte rate at this duty over the triad's
+    full rate, its write share, one 512-thread work-group per CU (8 of 32
+    wave slots), and for the read-only mix its rate over that mix's full
+    rate (what read-mostly co-runners are priced by)."""
     import torch
     import synth
     n = 1 << 28
@@ -496,12 +498,23 @@ def background_load(ctx, dev, duty):
     synth.device_fill_uniform_f32(hb.data_ptr(), n, synth.seed_for(4, synth.BUF_B))
     synth.device_fill_uniform_f32(hc.data_ptr(), n, synth.seed_for(4, synth.BUF_C))
     torch.cuda.synchronize()
-    ops = dict(src0=hb, src1=hc, dst=ha, n=n)
+    from paper_2501_16909_amd.coloc import HBM_MIX
+    triad = dict(src0=hb, src1=hc, dst=ha, n=n)
     ws = torch.empty(WS_BYTES, dtype=torch.uint8, device=dev)
-    full = ctx.stressor("hbm", 1.0, ws=ws, passes=1, **ops).stop()
-    part = ctx.stressor("hbm", 1.0, ws=ws, passes=1, duty=duty, **ops).stop()
-    load = min(1.0, (part.units / part.kernel_ns) / (full.units / full.kernel_ns))
-    return ops, ws, {"press": {"hbm": load}, "occ": 0.25, "hbm_write_frac": HBM_WRITE_FRAC["triad"]}
+    def rate(o, **kw):   # median of three launches after an untimed one
+        run = lambda: ctx.stressor("hbm", 1.0, ws=ws, passes=1, **o, **kw).stop()
+        run()
+        return float(np.median([(lambda r: r.units / r.kernel_ns)(run()) for _ in range(3)]))
+    full = rate(triad)
+    if mix == "triad":
+        part = rate(triad, duty=duty)
+        return triad, ws, {"press": {"hbm": min(1.0, part / full)}, "occ": 0.25,
+                           "hbm_write_frac": HBM_WRITE_FRAC["triad"]}
+    ops = dict(src0=hb, src1=hc, n=n, knob=HBM_MIX["read"])
+    full_read = rate(ops)
+    part = rate(ops, duty=duty)
+    return ops, ws, {"press": {"hbm": min(1.0, part / full)}, "occ": 0.25, "hbm_write_frac": 0.0,
+                     "press_hbm_read": min(1.0, part / full_read)}
 
 
 def serving_block(ctx, args, keep_host):
@@ -986,15 +999,19 @@ def serve_profiles(ctx, args, axis="cu", hbm_mix="triad", res=("hbm", "mfma_bf16
     duty_rates = {}
     fixed = {"hbm": dict(passes=1), "mfma_bf16": dict(iters=2048, passes=2), "lds": dict(passes=4),
              "mall": dict(passes=60)}
+
+    def steady_rate(r, **kw):
+        # median of three launches after an untimed one: a stressor's first
+        # launch in a process can run 20 % slow, which would shift every
+        # load measured against it
+        run = lambda: ctx.stressor(r, 1.0, ws=ws, **ops[r], **fixed[r], **kw).stop()
+        run()
+        return float(np.median([(lambda rep: rep.units / (rep.kernel_ns * 1e-9))(run()) for _ in range(3)]))
+
     for r in res:
-        extra = fixed[r]
-        rep = ctx.stressor(r, 1.0, ws=ws, **ops[r], **extra).stop()
-        rates[r] = rep.units / (rep.kernel_ns * 1e-9)
+        rates[r] = steady_rate(r)
         if axis == "duty":
-            duty_rates[r] = {}
-            for duty in DUTIES:
-                rep = ctx.stressor(r, 1.0, ws=ws, duty=duty, **ops[r], **extra).stop()
-                duty_rates[r][duty] = rep.units / (rep.kernel_ns * 1e-9)
+            duty_rates[r] = {duty: steady_rate(r, duty=duty) for duty in DUTIES}
             log(f"{r} duty rates (fraction of full): "
                 + ", ".join(f"{k}%: {v / rates[r]:.3f}" for k, v in duty_rates[r].items()))
     g = 2048
@@ -1127,7 +1144,7 @@ def _serving_stats(res, reqs, iso_ns, bound):
 
 def run_serve_background(args):
     """Serving on a loaded device: an HBM triad stressor on every CU at duty
-    --duty runs through each serving run (serve_run_background), so that the
+    --duty (traffic mix --background-mix) runs through each serving run (serve_run_background), so that the
     admission rule has to decide against a constant background load; naive,
     occupancy-based (usher) and sensitivity-aware admission (duty-axis profiles with
     read/write-aware HBM pricing, the stressor's own measured load as the
@@ -1140,11 +1157,11 @@ def run_serve_background(args):
     dev = ctx.device
     profiles = library_profiles(serve_profiles(ctx, args, axis="duty"),
                                 serve_profiles(ctx, args, axis="duty", hbm_mix="read", res=("hbm",)))
-    ops, ws, bg = background_load(ctx, dev, args.duty)
+    ops, ws, bg = background_load(ctx, dev, args.duty, args.background_mix)
     press = bg["press"]["hbm"]
     alone_bg = {k: round(coloc.predict_slowdown(profiles, k, [bg]), 3) for k in profiles}
-    log(f"background: HBM triad stressor, duty {args.duty} %: load {press:.3f} of the full rate; "
-        f"predicted slowdown beside it alone: {alone_bg}")
+    log(f"background: HBM {args.background_mix} stressor, duty {args.duty} %: load {press:.3f} of the "
+        f"triad's full rate; predicted slowdown beside it alone: {alone_bg}")
     budget, slots = 32 << 30, 4
     out = {"metric": "serving latency p50/p99, throughput and slowdown under a background HBM stressor, "
                      "naive vs occupancy-based vs sensitivity-aware admission",
@@ -1152,8 +1169,9 @@ def run_serve_background(args):
                                   "n~logU[4096,16384], FP32 triad N~logU[2^20,2^28]",
                       "seconds": args.seconds, "slots": slots, "hbm_budget_gib": budget >> 30,
                       "bound": args.bound, "profile_axis": "duty", "hbm_pricing": "read/write-aware",
-                      "background": {"resource": "hbm", "mix": "triad", "intensity": 1.0, "duty_pct": args.duty,
-                                     "load": round(press, 4), "occ": 0.25,
+                      "background": {"resource": "hbm", "mix": args.background_mix, "intensity": 1.0,
+                                     "duty_pct": args.duty, "load": round(press, 4),
+                                     "load_read": round(bg.get("press_hbm_read", 0.0), 4), "occ": 0.25,
                                      "predicted_slowdown_beside_it_alone": alone_bg}},
            "runs": [], "profiles": profiles}
     for lam in args.rates:
@@ -2376,6 +2394,8 @@ def main():
     ap.add_argument("--bound", type=float, default=1.5, help="serve: p99 slowdown bound")
     ap.add_argument("--duty", type=int, default=50,
                     help="serve-background: duty cycle (percent) of the background HBM stressor")
+    ap.add_argument("--background-mix", default="triad", choices=["triad", "read"],
+                    help="serve-background: traffic mix of the background HBM stressor")
     ap.add_argument("--profiles", default=None, help="serve: sensitivity profiles (JSON)")
     ap.add_argument("--batch", type=int, default=1, help="decode: sequences per step (1..8)")
     ap.add_argument("--contexts", type=int, default=6, help="queues: fresh contexts (queue orders) to try")
