@@ -486,35 +486,35 @@ def background_load(ctx, dev, duty, mix="triad"):
     """An HBM stressor for serve_run_background, in the triad or the
     read-only mix: its operands (2^28-element FP32 arrays, 1 GiB each, far
     beyond the Infinity Cache), a workspace, and its load as the admission
-    rules see it -- its standalone byte rate at this duty over the triad's
-    full rate, its write share, one 512-thread work-group per CU (8 of 32
-    wave slots), and for the read-only mix its rate over that mix's full
-    rate (what read-mostly co-runners are priced by)."""
+    rules see it, in the duty-axis profiles' units: the triad at duty d is
+    the triad curves' point d; the read-only mix at duty d is the read-only
+    curves' point d and, for the triad curves, the triad duty whose
+    standalone byte rate matches its own (equivalent_duty).  Both hold one
+    512-thread work-group per CU (8 of 32 wave slots)."""
     import torch
     import synth
+    from paper_2501_16909_amd.coloc import HBM_MIX
     n = 1 << 28
     hb = torch.empty(n, dtype=torch.float32, device=dev)
     hc, ha = torch.empty_like(hb), torch.empty_like(hb)
     synth.device_fill_uniform_f32(hb.data_ptr(), n, synth.seed_for(4, synth.BUF_B))
     synth.device_fill_uniform_f32(hc.data_ptr(), n, synth.seed_for(4, synth.BUF_C))
     torch.cuda.synchronize()
-    from paper_2501_16909_amd.coloc import HBM_MIX
     triad = dict(src0=hb, src1=hc, dst=ha, n=n)
     ws = torch.empty(WS_BYTES, dtype=torch.uint8, device=dev)
+    if mix == "triad":
+        return triad, ws, {"press": {"hbm": duty / 100.0}, "occ": 0.25, "hbm_write_frac": HBM_WRITE_FRAC["triad"]}
+
     def rate(o, **kw):   # median of three launches after an untimed one
         run = lambda: ctx.stressor("hbm", 1.0, ws=ws, passes=1, **o, **kw).stop()
         run()
         return float(np.median([(lambda r: r.units / r.kernel_ns)(run()) for _ in range(3)]))
     full = rate(triad)
-    if mix == "triad":
-        part = rate(triad, duty=duty)
-        return triad, ws, {"press": {"hbm": min(1.0, part / full)}, "occ": 0.25,
-                           "hbm_write_frac": HBM_WRITE_FRAC["triad"]}
+    table = {d: rate(triad, duty=d) for d in DUTIES}
     ops = dict(src0=hb, src1=hc, n=n, knob=HBM_MIX["read"])
-    full_read = rate(ops)
     part = rate(ops, duty=duty)
-    return ops, ws, {"press": {"hbm": min(1.0, part / full)}, "occ": 0.25, "hbm_write_frac": 0.0,
-                     "press_hbm_read": min(1.0, part / full_read)}
+    return ops, ws, {"press": {"hbm": equivalent_duty(part / full, table, full)}, "occ": 0.25,
+                     "hbm_write_frac": 0.0, "press_hbm_read": duty / 100.0}
 
 
 def serving_block(ctx, args, keep_host):
@@ -958,6 +958,20 @@ def serve_trace(lam, seconds, seed):
 
 
 DUTIES = (10, 25, 50, 75, 100)
+CURVE_DUTIES = (25, 50, 75, 100)   # with duty 0, the five points of a duty-axis curve
+
+
+def equivalent_duty(frac, duty_rates, full):
+    """The stressor duty (0..1) whose standalone rate is `frac` of the full
+    rate: linear between the measured duty levels (duty_rates: percent ->
+    rate), from rate 0 at duty 0; 1 at or beyond the top level's rate.  A
+    co-runner's pressure on the duty axis is this equivalent intensity, so
+    that it reads the victim's curve where the stressor matched its use."""
+    ds = [0.0] + [d / 100.0 for d in sorted(duty_rates)]
+    xs = [0.0]
+    for d in sorted(duty_rates):       # rates rise with duty; keep the table increasing
+        xs.append(max(duty_rates[d] / full, xs[-1] + 1e-9))
+    return float(np.interp(frac, xs, ds))
 # Write share of each request kind's compulsory HBM bytes: the GEMV reads its
 # weights and writes one short vector, the triad writes one stream of three,
 # the GEMM writes an FP32 C as large as its BF16 A and B together.
@@ -976,12 +990,15 @@ def serve_profiles(ctx, args, axis="cu", hbm_mix="triad", res=("hbm", "mfma_bf16
     sizes (GEMM BF16 2048^3, GEMV BF16 8192^2, triad N = 2^24): slowdown
     curves (shared placement) on the resources the kinds themselves load --
     HBM, BF16 matrix cores, LDS -- and the pressure each kind exerts there,
-    its standalone rate over the matching stressor's standalone rate.
+    from its standalone use of the unit against the matching stressor's
+    standalone rate (as below, per axis).
 
-    axis "cu": the stressor runs at full rate on a fraction x of the CUs.
+    axis "cu": the stressor runs at full rate on a fraction x of the CUs;
+    pressure is the use over the full rate.
     axis "duty": the stressor runs on every CU, active a fraction of the
-    time; each duty level's standalone rate over the full rate is the curve's
-    abscissa, resampled onto the same five points.
+    time; the curve's points are duty 0, 25, 50, 75 and 100 %, and a kind's
+    pressure is the equivalent duty: the duty at which the stressor's
+    standalone rate matches the kind's use (equivalent_duty).
 
     hbm_mix picks the HBM stressor's traffic mix ("triad" or "read"); res
     limits the resources profiled."""
@@ -1050,20 +1067,20 @@ def serve_profiles(ctx, args, axis="cu", hbm_mix="triad", res=("hbm", "mfma_bf16
                 row = cells[i * len(INTENSITIES):(i + 1) * len(INTENSITIES)]
                 sens[r] = [float(c["slowdown"]) if c["slowdown"] == c["slowdown"] else 1.0 for c in row]
         else:
-            xs = {r: [0.0] for r in res}
-            ys = {r: [1.0] for r in res}
-            for duty in DUTIES:
+            # the curve's points: the stressor on every CU at duty 0, 25, 50,
+            # 75 and 100 %
+            sens = {r: [1.0] for r in res}
+            for duty in CURVE_DUTIES:
                 cells = ctx.measure_sensitivity(d, res, [dict(ops[r], duty=duty) for r in res], [1.0],
                                                 reps=args.reps, warmups=2, ws=ws,
                                                 deadline_ms=args.deadline_ms)
                 for i, r in enumerate(res):
-                    xs[r].append(duty_rates[r][duty] / rates[r])
-                    ys[r].append(float(cells[i]["slowdown"]))
-            for r in res:
-                order = np.argsort(xs[r], kind="stable")
-                sens[r] = [float(v) for v in np.interp(INTENSITIES, np.asarray(xs[r])[order],
-                                                       np.asarray(ys[r])[order])]
-        press = {r: min(1.0, use[kind].get(r, 0.0) / t_alone / rates[r]) for r in res}
+                    sens[r].append(float(cells[i]["slowdown"]))
+        frac = {r: use[kind].get(r, 0.0) / t_alone / rates[r] for r in res}
+        if axis == "cu":
+            press = {r: min(1.0, frac[r]) for r in res}
+        else:
+            press = {r: equivalent_duty(frac[r], duty_rates[r], rates[r]) for r in res}
         profiles[kind] = {"sens": sens, "press": press, "occ": occ[kind],
                           "hbm_write_frac": HBM_WRITE_FRAC[kind]}
     return profiles

@@ -722,16 +722,19 @@ typedef enum ci_policy_kind {
  * to predict each kernel's slowdown from its sensitivity to every shared
  * resource and the pressure its co-runners put on them).
  *   sens[r][p]: the kind's measured slowdown (as a victim) beside stressor r
- *     at load point p = 0, .25, .5, .75, 1 of that stressor's full rate;
- *   press[r]:   the load the kind itself puts on r when it runs alone, as a
- *     fraction of stressor r's full rate (0..1);
+ *     at intensity point p = 0, .25, .5, .75, 1 (the stressor's CU fraction
+ *     or its duty cycle on every CU: the caller picks the axis);
+ *   press[r]:   the load the kind itself puts on r when it runs alone, as
+ *     the equivalent intensity of stressor r on the same axis (0..1): the
+ *     intensity at which the stressor's standalone rate matches the kind's
+ *     use of r;
  *   occ:        fraction of the GPU's wave slots it fills (USHER policy).
  * Read/write-aware HBM pricing (optional; all-zero sens_hbm_read = absent):
  * the same HBM byte rate costs a victim more when it includes writes, so a
  * co-runner whose HBM traffic is read-mostly is priced on the victim's curve
  * against the read-only HBM mix instead of the triad's.
  *   sens_hbm_read[p]: slowdown curve against the read-only HBM mix;
- *   press_hbm_read:   this kind's HBM load against that mix's full rate;
+ *   press_hbm_read:   this kind's HBM load as that mix's equivalent intensity;
  *   hbm_write_frac:   write share of its compulsory HBM bytes (0..1). */
 typedef struct ci_profile {
   int kind;                             /* victim kind this profile covers    */

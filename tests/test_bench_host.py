@@ -7,6 +7,7 @@ import subprocess
 import sys
 
 import numpy as np
+import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
@@ -195,3 +196,19 @@ def test_cpu_serving_leg_models_whole_stays_and_kernels():
     (r,) = bench._cpu_serving_leg({"profiles": prof, "runs": [run]})
     assert (r["model_kernel_latency_ms_p50"], r["model_kernel_latency_ms_p99"]) == (3000.0, 3980.0)
     assert (r["model_latency_ms_p50"], r["model_latency_ms_p99"]) == (4500.0, 5970.0)
+
+
+def test_equivalent_duty():
+    """A co-runner's pressure on the duty axis: the stressor duty whose
+    standalone rate matches its use, linear between measured duty levels."""
+    import bench
+    table = {10: 0.2, 25: 0.5, 50: 0.8, 75: 0.9, 100: 1.0}
+    f = lambda x: bench.equivalent_duty(x, table, 1.0)
+    assert f(0.0) == 0.0 and f(0.2) == pytest.approx(0.1) and f(0.8) == pytest.approx(0.5)
+    assert f(0.35) == pytest.approx(0.175)          # halfway between duty 10 and 25
+    assert f(0.95) == pytest.approx(0.875)
+    assert f(1.0) == 1.0 and f(1.5) == 1.0           # at or beyond the full rate
+    assert bench.equivalent_duty(0.4, {50: 8.0, 100: 10.0}, 10.0) == pytest.approx(0.25)   # rates in any unit
+    # a non-increasing measurement does not fold the table back
+    g = bench.equivalent_duty(0.47, {25: 0.5, 50: 0.45, 100: 1.0}, 1.0)
+    assert 0.0 < g <= 0.25
