@@ -2058,21 +2058,42 @@ def run_counter_summary(args):
 def run_trace_summary(args):
     """Kernel-trace summary (per kernel and launch shape: calls, average,
     min, max, total) of one rocprofv3 --kernel-trace database, written to
-    --md; with --bench-json, the benchmark line's roofline kernel is checked
-    against the trace's average launch time."""
+    --md; --top keeps the rows with the largest totals; with --bench-json,
+    the benchmark line's roofline kernel is checked against the trace's
+    average launch time; with --window-ms, every launch longer than that
+    (a stressor held through a run) is listed with the kernels that started
+    and ended inside its window."""
     import sqlite3
     con = sqlite3.connect(args.dbs[0])
     rows = con.execute("select name, grid_x, workgroup_x, count(*), avg(duration), min(duration), max(duration), "
                        "sum(duration) from kernels group by name, grid_x, workgroup_x "
                        "order by sum(duration) desc").fetchall()
+    windows = []
+    if args.window_ms:
+        for name, t0, t1, dur in con.execute("select name, start, end, duration from kernels where duration > ? "
+                                             "order by start", (args.window_ms * 1e6,)).fetchall():
+            inside = con.execute("select name, count(*) from kernels where start >= ? and end <= ? and "
+                                 "not (start = ? and end = ?) group by name order by count(*) desc",
+                                 (t0, t1, t0, t1)).fetchall()
+            windows.append((name, dur, inside))
     con.close()
+    total_kernels = len(rows)
+    if args.top:
+        rows = rows[:args.top]
     L = [f"# {args.title}", "", "Command (repository root, one MI355X), then the summary:", "", "```"]
-    L += args.cmd + [" ".join(["python3 bench.py --config trace-summary --dbs"] + list(args.dbs)), "```", "",
+    flags = (f" --top {args.top}" if args.top else "") + (f" --window-ms {args.window_ms:g}" if args.window_ms else "")
+    L += args.cmd + [" ".join(["python3 bench.py --config trace-summary --dbs"] + list(args.dbs)) + flags, "```", "",
                      "| kernel | work-groups x threads | calls | avg us | min us | max us | total ms |",
                      "|---|---|---|---|---|---|---|"]
     for name, gx, wx, calls, avg, mn, mx, tot in rows:
         L.append(f"| `{_short_kernel(name)}` | {gx // max(wx, 1)} x {wx} | {calls} | {avg / 1e3:.2f} | "
                  f"{mn / 1e3:.2f} | {mx / 1e3:.2f} | {tot / 1e6:.3f} |")
+    if len(rows) < total_kernels:
+        L += ["", f"({len(rows)} of {total_kernels} kernel and launch-shape rows, by total time.)"]
+    for name, dur, inside in windows:
+        L += ["", f"Launch of `{_short_kernel(name)}` lasting {dur / 1e6:.1f} ms; kernels that started and ended "
+                  f"inside its window: {sum(c for _, c in inside)}"]
+        L += [f"- `{_short_kernel(n)}`: {c}" for n, c in inside]
     if args.bench_json:
         with open(args.bench_json) as f:
             line = json.loads(f.read().strip().splitlines()[-1])
@@ -2391,6 +2412,9 @@ def main():
     ap.add_argument("--cmd", nargs="+", default=[], help="summaries: the commands that made the databases")
     ap.add_argument("--md", default=None, help="trace-summary: markdown file to write")
     ap.add_argument("--title", default="Kernel trace", help="trace-summary: heading")
+    ap.add_argument("--top", type=int, default=0, help="trace-summary: rows kept (0 = all)")
+    ap.add_argument("--window-ms", type=float, default=0.0,
+                    help="trace-summary: list launches longer than this and the kernels inside them")
     ap.add_argument("--bench-json", default=None, help="trace-summary: the benchmark line of the traced run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true",

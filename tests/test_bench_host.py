@@ -212,3 +212,27 @@ def test_equivalent_duty():
     # a non-increasing measurement does not fold the table back
     g = bench.equivalent_duty(0.47, {25: 0.5, 50: 0.45, 100: 1.0}, 1.0)
     assert 0.0 < g <= 0.25
+
+
+def test_trace_summary_lists_kernels_inside_a_long_launch(tmp_path):
+    """trace-summary --window-ms: a launch longer than the threshold is
+    listed with the kernels that ran entirely inside its window."""
+    import sqlite3
+    db = tmp_path / "t.db"
+    con = sqlite3.connect(db)
+    con.execute("create table kernels (name text, grid_x int, workgroup_x int, duration int, start int, end int)")
+    rows = [("held_stressor", 256 * 512, 512, 0, 3_000_000_000),     # 3 s
+            ("request", 1024, 256, 1_000_000, 1_000_100), ("request", 1024, 256, 2_000_000, 2_000_100),
+            ("after", 64, 64, 3_100_000_000, 3_100_000_100)]
+    con.executemany("insert into kernels values (?, ?, ?, ?, ?, ?)",
+                    [(n, g, w, e - s, s, e) for n, g, w, s, e in rows])
+    con.commit()
+    con.close()
+    md = tmp_path / "s.md"
+    subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--config", "trace-summary", "--dbs", str(db),
+                    "--window-ms", "1000", "--top", "2", "--md", str(md), "--cmd", "x"], check=True,
+                   capture_output=True)
+    text = md.read_text()
+    assert "lasting 3000.0 ms; kernels that started and ended inside its window: 2" in text
+    assert "- `request`: 2" in text and "`after`" not in text.split("lasting")[1]
+    assert "(2 of 3 kernel and launch-shape rows, by total time.)" in text
