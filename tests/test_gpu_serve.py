@@ -308,6 +308,26 @@ def test_serve_under_a_background_stressor_occupancy_rule(ctx, dev):
     spans = sorted((o["admit_s"], o["end_s"]) for o in alone)
     assert any(spans[i + 1][0] < spans[i][1] for i in range(len(spans) - 1))
 
+
+def test_serve_under_a_background_stressor_on_half_the_cus(ctx, dev):
+    """A background on half the CUs (the slot check pairs each slot with
+    the stressor's own CU mask): every served result equals the oracle's and
+    the stressor reports work from exactly half the CUs."""
+    import torch
+    n_s = 1 << 22
+    tsb = torch.zeros(n_s, dtype=torch.float32, device=dev)
+    tsc, tsa = torch.zeros_like(tsb), torch.empty_like(tsb)
+    reqs = _with_copies([dict(q, arrival_s=0.0002 * i) for i, q in enumerate(_trace()[:6])], dev)
+    print(f"serve_run_background at intensity 0.5: {len(reqs)} requests", flush=True)
+    q0 = ctx.queue_stats()
+    out, rep = ctx.serve_loaded(reqs, "hbm", 0.5, policy="naive", hbm_budget=1 << 30, slots=3,
+                                src0=tsb, src1=tsc, dst=tsa, n=n_s, deadline_ms=30000)
+    assert all(o["status"] == 0 for o in out) and not rep.timed_out
+    for q, o in zip(reqs, out):
+        _oracle_check(q, o, q["out_copy"].cpu().numpy())
+    assert rep.ncu * 2 == ctx.info.num_cus and rep.distinct_cus == rep.ncu
+    assert ctx.queue_stats()["checks"] - q0["checks"] >= 3
+
 def test_serve_under_a_background_stressor_rejects_fixed_passes(ctx, dev):
     import torch
     from paper_2501_16909_amd import coloc
